@@ -1,0 +1,872 @@
+/*
+ * pdhg_oracle.c -- plain FP64 CPU reference for restarted Halpern PDHG on LPs
+ * and for the corner-push phase of "Backing PDHG into a Corner" (Rothberg,
+ * arXiv 2511.13894).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test suite, the smoke check and the CPU leg of the
+ * benchmark do.  It shares no code, header, table or constant generator with
+ * the HIP path.
+ *
+ * What it computes, in the paper's notation (section 2, "Background"):
+ *   primal  min c'x  s.t.  a_i'x (=, <=, >=) b_i,  l <= x <= u
+ *   dual    y (free for '=', y_i <= 0 for '<=', y_i >= 0 for '>='), reduced
+ *           costs z = c - A'y split into the parts that bounds can absorb.
+ * Residuals r_P = b - Ax, r_D = c - A'y - z and the relative l2 termination
+ * tests are the ones of section 2.  Inequalities and bounds are handled
+ * implicitly (section 2, last paragraph before the restated objective).
+ *
+ * The paper names its PDHG only as "closely following cuPDLP+" (section 4.1)
+ * and says nothing of scaling, step size, restarts or primal weight.  The
+ * readings used for those silent parts are:
+ *   scaling   : 10 Ruiz passes (inf-norm, rows and columns from the same
+ *               matrix), then one Pock-Chambolle pass with alpha = 1;
+ *   step size : power iteration on Ahat'Ahat from v0 = 1/sqrt(n), P steps,
+ *               eta = safety / sqrt(lambda);
+ *   iteration : PDHG step T followed by a reflected Halpern average with the
+ *               restart anchor (halpern = 0 gives vanilla PDHG);
+ *   checks    : every K iterations on the candidate T(z); termination on the
+ *               unscaled model, restart on a weighted KKT of the scaled model
+ *               (sufficient / necessary-without-progress / artificial rules);
+ *   weight    : log-smoothed primal weight update at restarts.
+ * Corner push (section 3, Algorithm 1; implicit slacks in the paragraph after
+ * it; option 1 "modify in place and continue"; termination in section 3.1):
+ *   ub_j <- x_j if z_j > eps_abs, lb_j <- x_j if z_j < -eps_abs; an inequality
+ *   row whose slack has a reduced cost beyond eps_abs becomes an equality;
+ *   objective Uniform[0,1)^n; restart from (x, 0); stop as soon as the primal
+ *   residual of the modified model is back at the original tolerance, after at
+ *   least push_min_iters push iterations.  Returns (xhat, y, z) with y and z
+ *   those of the input.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_BIG 1e20 /* |bound| >= 1e20 counts as infinite */
+
+/* status codes (numeric values documented in the test suite) */
+enum {
+    OR_OPTIMAL = 0,
+    OR_ITER_LIMIT = 1,
+    OR_NUMERICAL = 2,
+    OR_PUSH_DONE = 3,
+    OR_ERR_ARG = -1,
+    OR_ERR_STATE = -2
+};
+
+typedef struct {
+    double eps_rel, eps_abs;
+    int64_t max_iter;
+    int32_t check_every;
+    int32_t ruiz_iters;
+    double restart_suff, restart_nec, restart_art;
+    double pw_smooth;
+    double pc_alpha;
+    int32_t power_iters;
+    int32_t halpern;
+    double eta_safety;
+    double reflect_gamma;
+    int32_t push_min_iters;
+    int32_t pad_;
+    double push_obj_scale;
+    int64_t push_max_iter;
+} or_params;
+
+typedef struct {
+    double rp2, rd2, rpinf, rdinf; /* unscaled residual norms */
+    double pobj, dobj, gap;
+    double rel_p, rel_d, rel_gap;
+    int64_t p_off;       /* variables off their bounds (structural + slack)  */
+    int64_t d_zero;      /* reduced costs at zero (structural + slack)      */
+    int64_t candidates;  /* off bound and |z| < tol                         */
+    int64_t est_primal;  /* max(p - m, 0)                                    */
+    int64_t est_dual;    /* max(m - d, 0)                                    */
+} or_kkt;
+
+typedef struct {
+    int32_t status;
+    int32_t pad_;
+    int64_t iters, restarts;
+    double rel_p, rel_d, rel_gap, pobj, dobj;
+} or_result;
+
+typedef struct {
+    int32_t status;
+    int32_t pad_;
+    int64_t iters, restarts;
+    int64_t n_fix_lower, n_fix_upper, n_rows_to_eq;
+    double rel_p_push; /* relative primal residual of the push model at stop */
+    or_kkt before, after;
+} or_push_result;
+
+typedef struct {
+    int m, n;
+    int64_t nnz;
+    /* original model (unscaled), A row-compressed with sorted, summed rows */
+    int64_t *rp;
+    int32_t *ci;
+    double *av;
+    /* explicit transpose: row j of T is column j of A, entries by ascending i */
+    int64_t *tp;
+    int32_t *ti;
+    int64_t *tpos; /* index into the CSR value arrays of each transpose entry */
+    double *b, *c, *l, *u;
+    char *sense0;
+    /* scaled operator */
+    double *ahat, *ahat_t; /* Ahat values in CSR order and in transpose order */
+    double *dr, *dc;
+    double eta, sigma_est;
+    /* current (scaled) model: solve model or push model */
+    double *bh, *ch, *lh, *uh;
+    char *sense;
+    /* iterate state (scaled) */
+    double *x, *y, *xa, *ya, *xp, *yp, *xbar, *g, *hv;
+    double omega;
+    int64_t k, t, restarts, next_check;
+    double kkt_anchor_p2, kkt_anchor_d2, kkt_anchor_gap2; /* at the anchor */
+    double kkt_prev;
+    int solved;   /* a solve has produced a checked candidate */
+    int in_push;
+    /* solution of the original solve, unscaled, kept for the push */
+    double *xs_hat; /* scaled candidate accepted by the solve */
+    double *xsol, *ysol, *zsol;
+    double *xpush; /* unscaled push result */
+    or_params p;
+} or_solver;
+
+/* ------------------------------------------------------------------------ */
+static int is_inf_lo(double v) { return v <= -OR_BIG; }
+static int is_inf_up(double v) { return v >= OR_BIG; }
+
+static double clampd(double v, double lo, double hi)
+{
+    if (v < lo) v = lo;
+    if (v > hi) v = hi;
+    return v;
+}
+
+/* projection of one dual entry onto its cone: '=' free, '<' y <= 0, '>' y >= 0 */
+static double proj_dual(double v, char s)
+{
+    if (s == '<') return v < 0.0 ? v : 0.0;
+    if (s == '>') return v > 0.0 ? v : 0.0;
+    return v;
+}
+
+/* splitmix64 (Steele, Lea and Flood 2014), counter-based uniform draw */
+uint64_t or_splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Uniform[0,1) value number j of the push objective for a given seed */
+double or_push_uniform(uint64_t seed, int64_t j)
+{
+    uint64_t h = or_splitmix64(seed ^ ((uint64_t)j * 0x9E3779B97F4A7C15ULL));
+    return (double)(h >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* plain products with the unscaled and the scaled operator                 */
+static void mv_A(const or_solver *s, const double *val, const double *x, double *out)
+{
+    int i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < s->m; i++) {
+        double acc = 0.0;
+        for (int64_t e = s->rp[i]; e < s->rp[i + 1]; e++) acc += val[e] * x[s->ci[e]];
+        out[i] = acc;
+    }
+}
+
+static void mv_At(const or_solver *s, const double *tval, const double *y, double *out)
+{
+    int j;
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < s->n; j++) {
+        double acc = 0.0;
+        for (int64_t e = s->tp[j]; e < s->tp[j + 1]; e++) acc += tval[e] * y[s->ti[e]];
+        out[j] = acc;
+    }
+}
+
+/* transpose values in transpose order, gathered from row order */
+static void gather_t(const or_solver *s, const double *val, double *tval)
+{
+    for (int64_t e = 0; e < s->nnz; e++) tval[e] = val[s->tpos[e]];
+}
+
+static double norm2(const double *v, int64_t n)
+{
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; i++) acc += v[i] * v[i];
+    return sqrt(acc);
+}
+
+/* ------------------------------------------------------------------------ */
+/* KKT of (x, y) on an unscaled model (section 2 residuals, relative l2 tests;
+ * bounds and inequalities handled implicitly).  sense may differ from the
+ * original model (push model).  With l = 0, u = inf and '=' rows this is
+ * exactly r_P = b - Ax, r_D = c - A'y - z, gap = c'x - b'y. */
+static void kkt_unscaled(const or_solver *s, const double *c, const double *l, const double *u,
+                         const char *sense, const double *x, const double *y, double *ax,
+                         double *aty, double *zout, or_kkt *k)
+{
+    int m = s->m, n = s->n;
+    double *tv = (double *)malloc(sizeof(double) * (size_t)(s->nnz > 0 ? s->nnz : 1));
+    gather_t(s, s->av, tv);
+    mv_A(s, s->av, x, ax);
+    mv_At(s, tv, y, aty);
+    free(tv);
+    double rp2 = 0, rpinf = 0, rd2 = 0, rdinf = 0, pobj = 0, dobj = 0;
+    for (int i = 0; i < m; i++) {
+        double r = s->b[i] - ax[i];
+        if (sense[i] == '<') r = r < 0.0 ? r : 0.0;
+        else if (sense[i] == '>') r = r > 0.0 ? r : 0.0;
+        rp2 += r * r;
+        if (fabs(r) > rpinf) rpinf = fabs(r);
+        dobj += s->b[i] * y[i];
+    }
+    for (int j = 0; j < n; j++) {
+        double lam = c[j] - aty[j];
+        double zp = (!is_inf_lo(l[j]) && lam > 0.0) ? lam : 0.0;
+        double zm = (!is_inf_up(u[j]) && lam < 0.0) ? -lam : 0.0;
+        double z = zp - zm;
+        double rd = lam - z;
+        rd2 += rd * rd;
+        if (fabs(rd) > rdinf) rdinf = fabs(rd);
+        pobj += c[j] * x[j];
+        if (zp > 0.0) dobj += l[j] * zp;
+        if (zm > 0.0) dobj -= u[j] * zm;
+        if (zout) zout[j] = z;
+    }
+    double nb = norm2(s->b, m), nc = norm2(c, n);
+    k->rp2 = sqrt(rp2);
+    k->rd2 = sqrt(rd2);
+    k->rpinf = rpinf;
+    k->rdinf = rdinf;
+    k->pobj = pobj;
+    k->dobj = dobj;
+    k->gap = pobj - dobj;
+    k->rel_p = k->rp2 / (1.0 + nb);
+    k->rel_d = k->rd2 / (1.0 + nc);
+    k->rel_gap = fabs(pobj - dobj) / (1.0 + fabs(pobj) + fabs(dobj));
+}
+
+/* push-estimate counts of section 2.1 and the selection count of section 4.2,
+ * for x (unscaled) against the original bounds and z (unscaled). */
+static void corner_counts(const or_solver *s, const double *x, const double *ax, const double *y,
+                          const double *z, or_kkt *k)
+{
+    const double tol = 1e-6;
+    int64_t p = 0, d = 0, cand = 0;
+    for (int j = 0; j < s->n; j++) {
+        int off = (x[j] - s->l[j] > tol) && (s->u[j] - x[j] > tol);
+        int zz = fabs(z[j]) <= tol;
+        p += off;
+        d += zz;
+        cand += off && (fabs(z[j]) < tol);
+    }
+    for (int i = 0; i < s->m; i++) {
+        char sn = s->sense0[i];
+        if (sn == '=') continue;
+        double slack = (sn == '<') ? (s->b[i] - ax[i]) : (ax[i] - s->b[i]);
+        double zs = (sn == '<') ? -y[i] : y[i];
+        int off = slack > tol;
+        p += off;
+        d += fabs(zs) <= tol;
+        cand += off && (fabs(zs) < tol);
+    }
+    k->p_off = p;
+    k->d_zero = d;
+    k->candidates = cand;
+    k->est_primal = p > s->m ? p - s->m : 0;
+    k->est_dual = s->m > d ? s->m - d : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* weighted KKT of the scaled current model at (x, y):
+ * returns squared ||rP_hat||, ||rD_hat|| and gap^2 through the pointers. */
+static void kkt_scaled_parts(or_solver *s, const double *x, const double *y, double *p2, double *d2,
+                             double *gap2)
+{
+    int m = s->m, n = s->n;
+    double *ax = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    double *aty = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    mv_A(s, s->ahat, x, ax);
+    mv_At(s, s->ahat_t, y, aty);
+    double rp = 0, rd = 0, pobj = 0, dobj = 0;
+    for (int i = 0; i < m; i++) {
+        double r = s->bh[i] - ax[i];
+        if (s->sense[i] == '<') r = r < 0.0 ? r : 0.0;
+        else if (s->sense[i] == '>') r = r > 0.0 ? r : 0.0;
+        rp += r * r;
+        dobj += s->bh[i] * y[i];
+    }
+    for (int j = 0; j < n; j++) {
+        double lam = s->ch[j] - aty[j];
+        double zp = (!is_inf_lo(s->lh[j]) && lam > 0.0) ? lam : 0.0;
+        double zm = (!is_inf_up(s->uh[j]) && lam < 0.0) ? -lam : 0.0;
+        double rdj = lam - (zp - zm);
+        rd += rdj * rdj;
+        pobj += s->ch[j] * x[j];
+        if (zp > 0.0) dobj += s->lh[j] * zp;
+        if (zm > 0.0) dobj -= s->uh[j] * zm;
+    }
+    *p2 = rp;
+    *d2 = rd;
+    *gap2 = (pobj - dobj) * (pobj - dobj);
+    free(ax);
+    free(aty);
+}
+
+static double kkt_weighted(double omega, double p2, double d2, double gap2)
+{
+    return sqrt(omega * omega * p2 + d2 / (omega * omega) + gap2);
+}
+
+/* ------------------------------------------------------------------------ */
+static void set_defaults(or_params *p)
+{
+    p->eps_rel = 1e-6;
+    p->eps_abs = 1e-6;
+    p->max_iter = 1000000;
+    p->check_every = 64;
+    p->ruiz_iters = 10;
+    p->restart_suff = 0.2;
+    p->restart_nec = 0.8;
+    p->restart_art = 0.36;
+    p->pw_smooth = 0.5;
+    p->pc_alpha = 1.0;
+    p->power_iters = 32;
+    p->halpern = 1;
+    p->eta_safety = 0.99;
+    p->reflect_gamma = 1.0;
+    p->push_min_iters = 100;
+    p->pad_ = 0;
+    p->push_obj_scale = 1.0;
+    p->push_max_iter = 1000000;
+}
+
+void or_default_params(or_params *p) { set_defaults(p); }
+
+/* row-compress (sort each row by column, sum duplicates) */
+static int canonical_rows(int m, const int64_t *rp, const int32_t *ci, const double *v, int64_t **orp,
+                          int32_t **oci, double **ov, int64_t *onnz)
+{
+    int64_t nnz = rp[m];
+    int64_t *nrp = (int64_t *)calloc((size_t)m + 1, sizeof(int64_t));
+    int32_t *nci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    double *nv = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!nrp || !nci || !nv) return -1;
+    int64_t w = 0;
+    for (int i = 0; i < m; i++) {
+        int64_t a = rp[i], e = rp[i + 1];
+        int64_t start = w;
+        for (int64_t q = a; q < e; q++) { /* insertion into the sorted run */
+            int32_t col = ci[q];
+            double val = v[q];
+            int64_t pos = w;
+            int dup = 0;
+            for (int64_t r = start; r < w; r++) {
+                if (nci[r] == col) { nv[r] += val; dup = 1; break; }
+            }
+            if (dup) continue;
+            while (pos > start && nci[pos - 1] > col) {
+                nci[pos] = nci[pos - 1];
+                nv[pos] = nv[pos - 1];
+                pos--;
+            }
+            nci[pos] = col;
+            nv[pos] = val;
+            w++;
+        }
+        nrp[i + 1] = w;
+    }
+    *orp = nrp;
+    *oci = nci;
+    *ov = nv;
+    *onnz = w;
+    return 0;
+}
+
+void or_destroy(or_solver *s)
+{
+    if (!s) return;
+    void *ptrs[] = {s->rp, s->ci, s->av, s->tp, s->ti, s->tpos, s->b, s->c, s->l, s->u, s->sense0,
+                    s->ahat, s->ahat_t, s->dr, s->dc, s->bh, s->ch, s->lh, s->uh, s->sense, s->x,
+                    s->y, s->xa, s->ya, s->xp, s->yp, s->xbar, s->g, s->hv, s->xs_hat, s->xsol,
+                    s->ysol, s->zsol, s->xpush};
+    for (size_t q = 0; q < sizeof(ptrs) / sizeof(ptrs[0]); q++) free(ptrs[q]);
+    free(s);
+}
+
+static double *dalloc(int64_t n) { return (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double)); }
+
+/* scaling (Ruiz then Pock-Chambolle), power iteration and step size */
+static void scale_and_step(or_solver *s)
+{
+    int m = s->m, n = s->n;
+    double *r = dalloc(m), *q = dalloc(n);
+    for (int i = 0; i < m; i++) s->dr[i] = 1.0;
+    for (int j = 0; j < n; j++) s->dc[j] = 1.0;
+    memcpy(s->ahat, s->av, sizeof(double) * (size_t)s->nnz);
+
+    for (int pass = 0; pass < s->p.ruiz_iters; pass++) {
+        for (int i = 0; i < m; i++) r[i] = 0.0;
+        for (int j = 0; j < n; j++) q[j] = 0.0;
+        for (int i = 0; i < m; i++)
+            for (int64_t e = s->rp[i]; e < s->rp[i + 1]; e++) {
+                double a = fabs(s->ahat[e]);
+                if (a > r[i]) r[i] = a;
+                if (a > q[s->ci[e]]) q[s->ci[e]] = a;
+            }
+        for (int i = 0; i < m; i++) r[i] = r[i] > 0.0 ? sqrt(r[i]) : 1.0;
+        for (int j = 0; j < n; j++) q[j] = q[j] > 0.0 ? sqrt(q[j]) : 1.0;
+        for (int i = 0; i < m; i++)
+            for (int64_t e = s->rp[i]; e < s->rp[i + 1]; e++) s->ahat[e] = s->ahat[e] / (r[i] * q[s->ci[e]]);
+        for (int i = 0; i < m; i++) s->dr[i] = s->dr[i] / r[i];
+        for (int j = 0; j < n; j++) s->dc[j] = s->dc[j] / q[j];
+    }
+    if (s->p.pc_alpha >= 0.0) { /* one Pock-Chambolle pass (pc_alpha < 0 disables it) */
+        double al = s->p.pc_alpha;
+        for (int i = 0; i < m; i++) r[i] = 0.0;
+        for (int j = 0; j < n; j++) q[j] = 0.0;
+        for (int i = 0; i < m; i++)
+            for (int64_t e = s->rp[i]; e < s->rp[i + 1]; e++) {
+                double a = fabs(s->ahat[e]);
+                r[i] += pow(a, 2.0 - al);
+                q[s->ci[e]] += pow(a, al);
+            }
+        for (int i = 0; i < m; i++) r[i] = r[i] > 0.0 ? sqrt(r[i]) : 1.0;
+        for (int j = 0; j < n; j++) q[j] = q[j] > 0.0 ? sqrt(q[j]) : 1.0;
+        for (int i = 0; i < m; i++)
+            for (int64_t e = s->rp[i]; e < s->rp[i + 1]; e++) s->ahat[e] = s->ahat[e] / (r[i] * q[s->ci[e]]);
+        for (int i = 0; i < m; i++) s->dr[i] = s->dr[i] / r[i];
+        for (int j = 0; j < n; j++) s->dc[j] = s->dc[j] / q[j];
+    }
+    gather_t(s, s->ahat, s->ahat_t);
+
+    /* power iteration for the largest eigenvalue of Ahat'Ahat */
+    double *v = dalloc(n), *w = dalloc(n), *av = dalloc(m);
+    for (int j = 0; j < n; j++) v[j] = 1.0 / sqrt((double)n);
+    double lam = 0.0;
+    for (int it = 0; it < s->p.power_iters; it++) {
+        mv_A(s, s->ahat, v, av);
+        mv_At(s, s->ahat_t, av, w);
+        lam = norm2(w, n);
+        if (!(lam > 0.0)) break;
+        for (int j = 0; j < n; j++) v[j] = w[j] / lam;
+    }
+    s->sigma_est = lam > 0.0 ? sqrt(lam) : 0.0;
+    s->eta = s->sigma_est > 1e-12 ? s->p.eta_safety / s->sigma_est : s->p.eta_safety;
+    free(v);
+    free(w);
+    free(av);
+    free(r);
+    free(q);
+}
+
+/* primal weight from the norms of the scaled objective and right-hand side */
+static double initial_omega(const double *ch, int n, const double *bh, int m)
+{
+    double nc = norm2(ch, n), nb = norm2(bh, m);
+    if (nc > 1e-10 && nb > 1e-10) return nc / nb;
+    return 1.0;
+}
+
+/* start (or restart from scratch) the iteration at (x0, y0), scaled */
+static void reset_iteration(or_solver *s, int64_t first_check)
+{
+    memcpy(s->xa, s->x, sizeof(double) * (size_t)s->n);
+    memcpy(s->ya, s->y, sizeof(double) * (size_t)s->m);
+    memcpy(s->xp, s->x, sizeof(double) * (size_t)s->n);
+    memcpy(s->yp, s->y, sizeof(double) * (size_t)s->m);
+    s->k = 0;
+    s->t = 0;
+    s->restarts = 0;
+    s->next_check = first_check;
+    kkt_scaled_parts(s, s->x, s->y, &s->kkt_anchor_p2, &s->kkt_anchor_d2, &s->kkt_anchor_gap2);
+    s->kkt_prev = kkt_weighted(s->omega, s->kkt_anchor_p2, s->kkt_anchor_d2, s->kkt_anchor_gap2);
+}
+
+or_solver *or_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                     const double *val, const double *b, const double *c, const double *l,
+                     const double *u, const char *sense, const or_params *params)
+{
+    if (m < 0 || n < 0 || nnz < 0 || !row_ptr) return NULL;
+    if (row_ptr[0] != 0 || row_ptr[m] != nnz) return NULL;
+    for (int64_t e = 0; e < nnz; e++)
+        if (col[e] < 0 || col[e] >= n || !isfinite(val[e])) return NULL;
+    for (int j = 0; j < n; j++) {
+        double lo = l ? l[j] : 0.0, hi = u ? u[j] : INFINITY;
+        if (isnan(lo) || isnan(hi) || lo > hi || !isfinite(c[j])) return NULL;
+    }
+    for (int i = 0; i < m; i++) {
+        if (!isfinite(b[i])) return NULL;
+        if (sense && sense[i] != '=' && sense[i] != '<' && sense[i] != '>') return NULL;
+    }
+    or_solver *s = (or_solver *)calloc(1, sizeof(or_solver));
+    if (!s) return NULL;
+    if (params) s->p = *params;
+    else set_defaults(&s->p);
+    s->m = m;
+    s->n = n;
+    if (canonical_rows(m, row_ptr, col, val, &s->rp, &s->ci, &s->av, &s->nnz) != 0) {
+        or_destroy(s);
+        return NULL;
+    }
+    /* explicit transpose by a stable counting sort over columns */
+    s->tp = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    s->ti = (int32_t *)malloc(sizeof(int32_t) * (size_t)(s->nnz > 0 ? s->nnz : 1));
+    s->tpos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(s->nnz > 0 ? s->nnz : 1));
+    for (int64_t e = 0; e < s->nnz; e++) s->tp[s->ci[e] + 1]++;
+    for (int j = 0; j < n; j++) s->tp[j + 1] += s->tp[j];
+    int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int j = 0; j < n; j++) cur[j] = s->tp[j];
+    for (int i = 0; i < m; i++)
+        for (int64_t e = s->rp[i]; e < s->rp[i + 1]; e++) {
+            int64_t dst = cur[s->ci[e]]++;
+            s->ti[dst] = i;
+            s->tpos[dst] = e;
+        }
+    free(cur);
+
+    s->b = dalloc(m);
+    s->c = dalloc(n);
+    s->l = dalloc(n);
+    s->u = dalloc(n);
+    s->sense0 = (char *)malloc((size_t)m + 1);
+    s->sense = (char *)malloc((size_t)m + 1);
+    for (int i = 0; i < m; i++) {
+        s->b[i] = b[i];
+        s->sense0[i] = sense ? sense[i] : '=';
+    }
+    for (int j = 0; j < n; j++) {
+        s->c[j] = c[j];
+        double lo = l ? l[j] : 0.0, hi = u ? u[j] : INFINITY;
+        s->l[j] = lo <= -OR_BIG ? -INFINITY : lo;
+        s->u[j] = hi >= OR_BIG ? INFINITY : hi;
+    }
+    s->ahat = dalloc(s->nnz);
+    s->ahat_t = dalloc(s->nnz);
+    s->dr = dalloc(m);
+    s->dc = dalloc(n);
+    s->bh = dalloc(m);
+    s->ch = dalloc(n);
+    s->lh = dalloc(n);
+    s->uh = dalloc(n);
+    s->x = dalloc(n);
+    s->y = dalloc(m);
+    s->xa = dalloc(n);
+    s->ya = dalloc(m);
+    s->xp = dalloc(n);
+    s->yp = dalloc(m);
+    s->xbar = dalloc(n);
+    s->g = dalloc(n);
+    s->hv = dalloc(m);
+    s->xs_hat = dalloc(n);
+    s->xsol = dalloc(n);
+    s->ysol = dalloc(m);
+    s->zsol = dalloc(n);
+    s->xpush = dalloc(n);
+
+    scale_and_step(s);
+    for (int i = 0; i < m; i++) {
+        s->bh[i] = s->dr[i] * s->b[i];
+        s->sense[i] = s->sense0[i];
+    }
+    for (int j = 0; j < n; j++) {
+        s->ch[j] = s->dc[j] * s->c[j];
+        s->lh[j] = s->l[j] / s->dc[j];
+        s->uh[j] = s->u[j] / s->dc[j];
+    }
+    s->omega = initial_omega(s->ch, n, s->bh, m);
+    for (int j = 0; j < n; j++) s->x[j] = clampd(0.0, s->lh[j], s->uh[j]);
+    for (int i = 0; i < m; i++) s->y[i] = 0.0;
+    reset_iteration(s, s->p.check_every);
+    return s;
+}
+
+/* one PDHG step T and the Halpern average with the anchor (scaled space) */
+static void pdhg_step(or_solver *s)
+{
+    int m = s->m, n = s->n;
+    double tau = s->eta / s->omega, sig = s->eta * s->omega;
+    mv_At(s, s->ahat_t, s->y, s->g);
+    for (int j = 0; j < n; j++) {
+        s->xp[j] = clampd(s->x[j] - tau * (s->ch[j] - s->g[j]), s->lh[j], s->uh[j]);
+        s->xbar[j] = 2.0 * s->xp[j] - s->x[j];
+    }
+    mv_A(s, s->ahat, s->xbar, s->hv);
+    for (int i = 0; i < m; i++) s->yp[i] = proj_dual(s->y[i] + sig * (s->bh[i] - s->hv[i]), s->sense[i]);
+    if (s->p.halpern) {
+        double kk = (double)s->k;
+        double wgt = (kk + 1.0) / (kk + 2.0), wa = 1.0 / (kk + 2.0), gm = s->p.reflect_gamma;
+        for (int j = 0; j < n; j++)
+            s->x[j] = wgt * ((1.0 + gm) * s->xp[j] - gm * s->x[j]) + wa * s->xa[j];
+        for (int i = 0; i < m; i++)
+            s->y[i] = wgt * ((1.0 + gm) * s->yp[i] - gm * s->y[i]) + wa * s->ya[i];
+    } else {
+        memcpy(s->x, s->xp, sizeof(double) * (size_t)n);
+        memcpy(s->y, s->yp, sizeof(double) * (size_t)m);
+    }
+    s->k++;
+    s->t++;
+}
+
+/* unscaled copies of a scaled primal/dual pair */
+static void unscale(const or_solver *s, const double *xh, const double *yh, double *x, double *y)
+{
+    if (x)
+        for (int j = 0; j < s->n; j++) x[j] = s->dc[j] * xh[j];
+    if (y)
+        for (int i = 0; i < s->m; i++) y[i] = s->dr[i] * yh[i];
+}
+
+/* restart test and primal-weight update at a check; candidate = (xp, yp) */
+static void restart_check(or_solver *s)
+{
+    double p2, d2, g2;
+    kkt_scaled_parts(s, s->xp, s->yp, &p2, &d2, &g2);
+    double kc = kkt_weighted(s->omega, p2, d2, g2);
+    double ka = kkt_weighted(s->omega, s->kkt_anchor_p2, s->kkt_anchor_d2, s->kkt_anchor_gap2);
+    int do_restart = (kc <= s->p.restart_suff * ka) ||
+                     (kc <= s->p.restart_nec * ka && kc > s->kkt_prev) ||
+                     ((double)s->k >= s->p.restart_art * (double)s->t);
+    s->kkt_prev = kc;
+    if (!do_restart) return;
+    double dx = 0.0, dy = 0.0;
+    for (int j = 0; j < s->n; j++) dx += (s->xp[j] - s->xa[j]) * (s->xp[j] - s->xa[j]);
+    for (int i = 0; i < s->m; i++) dy += (s->yp[i] - s->ya[i]) * (s->yp[i] - s->ya[i]);
+    dx = sqrt(dx);
+    dy = sqrt(dy);
+    if (dx > 1e-10 && dy > 1e-10) {
+        double th = s->p.pw_smooth;
+        s->omega = exp(th * log(dy / dx) + (1.0 - th) * log(s->omega));
+    }
+    memcpy(s->x, s->xp, sizeof(double) * (size_t)s->n);
+    memcpy(s->xa, s->xp, sizeof(double) * (size_t)s->n);
+    memcpy(s->y, s->yp, sizeof(double) * (size_t)s->m);
+    memcpy(s->ya, s->yp, sizeof(double) * (size_t)s->m);
+    s->kkt_anchor_p2 = p2;
+    s->kkt_anchor_d2 = d2;
+    s->kkt_anchor_gap2 = g2;
+    s->kkt_prev = kkt_weighted(s->omega, p2, d2, g2);
+    s->k = 0;
+    s->restarts++;
+}
+
+static int all_finite(const double *v, int64_t n)
+{
+    for (int64_t i = 0; i < n; i++)
+        if (!isfinite(v[i])) return 0;
+    return 1;
+}
+
+/* run up to `iters` further iterations of the current phase; returns status.
+ * Each check evaluates the candidate T(z): termination first, then restart. */
+static int run_phase(or_solver *s, int64_t iters, double *out_relp)
+{
+    int m = s->m, n = s->n;
+    double *x = dalloc(n), *y = dalloc(m), *ax = dalloc(m), *aty = dalloc(n);
+    int status = OR_ITER_LIMIT;
+    for (int64_t it = 0; it < iters; it++) {
+        pdhg_step(s);
+        if (s->t != s->next_check) continue;
+        s->next_check += s->p.check_every;
+        if (!all_finite(s->xp, n) || !all_finite(s->yp, m)) {
+            status = OR_NUMERICAL;
+            break;
+        }
+        unscale(s, s->xp, s->yp, x, y);
+        or_kkt k;
+        if (!s->in_push) {
+            kkt_unscaled(s, s->c, s->l, s->u, s->sense, x, y, ax, aty, s->zsol, &k);
+            memcpy(s->xs_hat, s->xp, sizeof(double) * (size_t)n);
+            memcpy(s->xsol, x, sizeof(double) * (size_t)n);
+            memcpy(s->ysol, y, sizeof(double) * (size_t)m);
+            s->solved = 1;
+            if (k.rel_p <= s->p.eps_rel && k.rel_d <= s->p.eps_rel && k.rel_gap <= s->p.eps_rel) {
+                status = OR_OPTIMAL;
+                if (out_relp) *out_relp = k.rel_p;
+                break;
+            }
+        } else {
+            /* primal residual of the push model (its senses), unscaled */
+            kkt_unscaled(s, s->c, s->l, s->u, s->sense, x, y, ax, aty, NULL, &k);
+            memcpy(s->xpush, x, sizeof(double) * (size_t)n);
+            if (out_relp) *out_relp = k.rel_p;
+            if (k.rel_p <= s->p.eps_rel) {
+                status = OR_PUSH_DONE;
+                break;
+            }
+        }
+        restart_check(s);
+    }
+    free(x);
+    free(y);
+    free(ax);
+    free(aty);
+    return status;
+}
+
+static void fill_result(const or_solver *s, int status, or_result *r)
+{
+    double *ax = dalloc(s->m), *aty = dalloc(s->n);
+    or_kkt k;
+    kkt_unscaled(s, s->c, s->l, s->u, s->sense0, s->xsol, s->ysol, ax, aty, NULL, &k);
+    r->status = status;
+    r->iters = s->t;
+    r->restarts = s->restarts;
+    r->rel_p = k.rel_p;
+    r->rel_d = k.rel_d;
+    r->rel_gap = k.rel_gap;
+    r->pobj = k.pobj;
+    r->dobj = k.dobj;
+    free(ax);
+    free(aty);
+}
+
+/* exactly `iters` more iterations of the solve (fewer if it terminates) */
+int or_iterate(or_solver *s, int64_t iters, or_result *r)
+{
+    if (!s || s->in_push) return OR_ERR_STATE;
+    int st = run_phase(s, iters, NULL);
+    if (!s->solved) { /* no check yet: report the current iterate */
+        or_kkt k;
+        double *ax = dalloc(s->m), *aty = dalloc(s->n);
+        unscale(s, s->x, s->y, s->xsol, s->ysol);
+        memcpy(s->xs_hat, s->x, sizeof(double) * (size_t)s->n);
+        kkt_unscaled(s, s->c, s->l, s->u, s->sense0, s->xsol, s->ysol, ax, aty, s->zsol, &k);
+        free(ax);
+        free(aty);
+    }
+    if (r) fill_result(s, st, r);
+    return st;
+}
+
+int or_solve(or_solver *s, or_result *r)
+{
+    if (!s || s->in_push) return OR_ERR_STATE;
+    int64_t left = s->p.max_iter - s->t;
+    return or_iterate(s, left > 0 ? left : 0, r);
+}
+
+/* reduced costs z of the original model at y (unscaled), section 2 split */
+static void reduced_costs(const or_solver *s, const double *x, const double *y, double *z, double *ax,
+                          or_kkt *k)
+{
+    double *aty = dalloc(s->n);
+    kkt_unscaled(s, s->c, s->l, s->u, s->sense0, x, y, ax, aty, z, k);
+    free(aty);
+}
+
+/* Algorithm 1 with implicit slacks, modified in place, continued by PDHG */
+int or_corner_push(or_solver *s, uint64_t seed, or_push_result *r)
+{
+    if (!s || !s->solved || s->in_push) return OR_ERR_STATE;
+    int m = s->m, n = s->n;
+    double *ax = dalloc(m);
+    memset(r, 0, sizeof(*r));
+    /* CP1: (x, y, z) of the solve on M */
+    reduced_costs(s, s->xsol, s->ysol, s->zsol, ax, &r->before);
+    corner_counts(s, s->xsol, ax, s->ysol, s->zsol, &r->before);
+    double ea = s->p.eps_abs;
+    /* CP2: bounds (stored scaled: the scaled candidate itself) */
+    for (int j = 0; j < n; j++) {
+        if (s->zsol[j] > ea) { s->uh[j] = s->xs_hat[j]; r->n_fix_upper++; }
+        else if (s->zsol[j] < -ea) { s->lh[j] = s->xs_hat[j]; r->n_fix_lower++; }
+    }
+    /* CP3: inequality rows whose slack has a non-trivial reduced cost */
+    for (int i = 0; i < m; i++) {
+        if ((s->sense[i] == '<' && s->ysol[i] < -ea) || (s->sense[i] == '>' && s->ysol[i] > ea)) {
+            s->sense[i] = '=';
+            r->n_rows_to_eq++;
+        }
+    }
+    /* CP4: random objective Uniform[0,1)^n, scaled like c */
+    for (int j = 0; j < n; j++) s->ch[j] = s->dc[j] * (s->p.push_obj_scale * or_push_uniform(seed, j));
+    /* CP5: start from (x, 0); keep scaling and eta; new weight and restart state */
+    memcpy(s->x, s->xs_hat, sizeof(double) * (size_t)n);
+    for (int i = 0; i < m; i++) s->y[i] = 0.0;
+    s->omega = initial_omega(s->ch, n, s->bh, m);
+    s->in_push = 1;
+    reset_iteration(s, s->p.push_min_iters);
+    memcpy(s->xpush, s->xsol, sizeof(double) * (size_t)n);
+    /* CP6 */
+    double relp = NAN;
+    int st = run_phase(s, s->p.push_max_iter, &relp);
+    r->status = st;
+    r->iters = s->t;
+    r->restarts = s->restarts;
+    r->rel_p_push = relp;
+    /* CP7: (xhat, y, z); counts after against the original model */
+    double *z2 = dalloc(n);
+    reduced_costs(s, s->xpush, s->ysol, z2, ax, &r->after);
+    corner_counts(s, s->xpush, ax, s->ysol, s->zsol, &r->after);
+    free(z2);
+    free(ax);
+    return st;
+}
+
+/* KKT report of (x, y) on the original model M (unscaled host vectors) */
+int or_kkt_report(or_solver *s, const double *x, const double *y, or_kkt *k)
+{
+    if (!s || !k) return OR_ERR_ARG;
+    const double *xx = x ? x : (s->in_push ? s->xpush : s->xsol), *yy = y ? y : s->ysol;
+    double *ax = dalloc(s->m), *z = dalloc(s->n);
+    reduced_costs(s, xx, yy, z, ax, k);
+    corner_counts(s, xx, ax, yy, z, k);
+    free(ax);
+    free(z);
+    return 0;
+}
+
+/* ---- accessors (unscaled unless stated) ---------------------------------- */
+void or_get_iterate(const or_solver *s, double *x, double *y) { unscale(s, s->x, s->y, x, y); }
+void or_get_iterate_scaled(const or_solver *s, double *x, double *y)
+{
+    if (x) memcpy(x, s->x, sizeof(double) * (size_t)s->n);
+    if (y) memcpy(y, s->y, sizeof(double) * (size_t)s->m);
+}
+void or_get_solution(const or_solver *s, double *x, double *y, double *z)
+{
+    if (x) memcpy(x, s->in_push ? s->xpush : s->xsol, sizeof(double) * (size_t)s->n);
+    if (y) memcpy(y, s->ysol, sizeof(double) * (size_t)s->m);
+    if (z) memcpy(z, s->zsol, sizeof(double) * (size_t)s->n);
+}
+void or_get_scaling(const or_solver *s, double *dr, double *dc, double *out4)
+{
+    if (dr) memcpy(dr, s->dr, sizeof(double) * (size_t)s->m);
+    if (dc) memcpy(dc, s->dc, sizeof(double) * (size_t)s->n);
+    if (out4) {
+        out4[0] = s->eta;
+        out4[1] = s->omega;
+        out4[2] = s->sigma_est;
+        out4[3] = (double)s->t;
+    }
+}
+/* scaled model of the current phase (bounds, objective, senses) */
+void or_get_model_scaled(const or_solver *s, double *lh, double *uh, double *ch, char *sense)
+{
+    if (lh) memcpy(lh, s->lh, sizeof(double) * (size_t)s->n);
+    if (uh) memcpy(uh, s->uh, sizeof(double) * (size_t)s->n);
+    if (ch) memcpy(ch, s->ch, sizeof(double) * (size_t)s->n);
+    if (sense) memcpy(sense, s->sense, (size_t)s->m);
+}
+/* scaled matrix values in canonical row order (sorted, summed rows) */
+int64_t or_get_nnz(const or_solver *s) { return s->nnz; }
+void or_get_ahat(const or_solver *s, int64_t *rp, int32_t *ci, double *v)
+{
+    if (rp) memcpy(rp, s->rp, sizeof(int64_t) * ((size_t)s->m + 1));
+    if (ci) memcpy(ci, s->ci, sizeof(int32_t) * (size_t)s->nnz);
+    if (v) memcpy(v, s->ahat, sizeof(double) * (size_t)s->nnz);
+}
+int or_params_size(void) { return (int)sizeof(or_params); }
+int or_kkt_size(void) { return (int)sizeof(or_kkt); }
+int or_push_result_size(void) { return (int)sizeof(or_push_result); }
