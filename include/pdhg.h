@@ -1,0 +1,196 @@
+/*
+ * pdhg.h -- C ABI of the MI355X (gfx950) PDHG + corner-push library.
+ *
+ * Problem (paper, section 2, with bounds and inequalities handled implicitly):
+ *     min c'x   s.t.  a_i'x (=, <=, >=) b_i  (i < m),   l <= x <= u   (x in R^n)
+ * Dual: y_i free on '=' rows, y_i <= 0 on '<=' rows, y_i >= 0 on '>=' rows;
+ * reduced costs z = c - A'y, of which a finite lower bound absorbs the
+ * positive part and a finite upper bound the negative part.  Residuals
+ * r_P = b - Ax (only violations count on inequality rows), r_D = c - A'y - z,
+ * and the relative l2 termination tests of section 2:
+ *     ||r_P|| <= eps (1 + ||b||),  ||r_D|| <= eps (1 + ||c||),
+ *     |c'x - b'y| <= eps (1 + |c'x| + |b'y|)   (b'y including bound terms).
+ *
+ * Method: restarted PDHG with a reflected Halpern average (the paper uses a
+ * PDHG "closely following cuPDLP+", section 4.1, and describes nothing
+ * more), then the corner push of section 3, Algorithm 1: bounds fixed at the
+ * current x where |z_j| > eps_abs, inequality rows with a non-trivial slack
+ * reduced cost turned into equalities, a Uniform[0,1)^n objective, PDHG
+ * restarted from (x, 0) and stopped as soon as the primal residual of the
+ * modified model is back at the original tolerance after at least
+ * push_min_iters iterations (section 3.1).
+ *
+ * Conventions for every entry point:
+ *   - Host arrays are read-only and stay owned by the caller; the library
+ *     copies what it needs.  Output arrays are caller-allocated.
+ *   - Dense vectors are contiguous float64.  The matrix is row-compressed:
+ *     row_ptr[m+1] (int64, row_ptr[0] = 0, row_ptr[m] = nnz), col_idx[nnz]
+ *     (int32, 0 <= col < n, any order inside a row, duplicates are summed),
+ *     val[nnz] (float64, finite).  nnz must stay below 2^31.
+ *   - Infinite bounds are +-INFINITY; |bound| >= 1e20 is treated as infinite.
+ *   - sense[m] holds '=', '<' (a_i'x <= b_i) or '>' (a_i'x >= b_i); NULL
+ *     means all '='.  l == NULL means 0, u == NULL means +INFINITY.
+ *   - Every function returns PDHG_OK (0) or a negative pdhg_error; no C++
+ *     exception crosses the ABI.  pdhg_last_error() returns a thread-local
+ *     description of the last failure.
+ *   - All device work runs on params.stream (a hipStream_t passed as void*;
+ *     NULL makes the library create its own stream at default priority).
+ *     Calls on one handle must not overlap; distinct handles are independent.
+ */
+#ifndef PDHG_H
+#define PDHG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdhg_solver pdhg_solver;
+
+/* solve / push outcome */
+enum pdhg_status {
+    PDHG_OPTIMAL = 0,    /* the three relative tests hold at a check           */
+    PDHG_ITER_LIMIT = 1, /* max_iter (push: push_max_iter) reached              */
+    PDHG_NUMERICAL = 2,  /* a non-finite value appeared in the candidate        */
+    PDHG_PUSH_DONE = 3,  /* push: primal residual back at eps_rel (section 3.1) */
+    PDHG_TIME_LIMIT = 4  /* time_limit seconds elapsed (checked between cycles) */
+};
+
+/* return codes */
+enum pdhg_error {
+    PDHG_OK = 0,
+    PDHG_ERR_INVALID_ARG = -1, /* bad pointer, dimension, NaN/Inf data, l > u, bad sense */
+    PDHG_ERR_STATE = -2,       /* call out of order (e.g. push before solve)         */
+    PDHG_ERR_OOM = -3,         /* device or host allocation failed                    */
+    PDHG_ERR_HIP = -4          /* a HIP runtime call failed                           */
+};
+
+enum pdhg_precision {
+    PDHG_FP64 = 0,      /* matrix, vectors and updates in float64                         */
+    PDHG_FP32_MIXED = 1 /* matrix, vectors and updates in float32; residual norms, restart
+                           test, termination and the push fixing test in float64         */
+};
+
+/* Parameters.  Every constant the paper leaves open lives here. */
+typedef struct pdhg_params {
+    double eps_rel;        /* relative l2 tolerance (section 2); default 1e-6          */
+    double eps_abs;        /* fixing threshold of Algorithm 1; default 1e-6            */
+    int64_t max_iter;      /* iteration cap of a solve; default 1e6                     */
+    int32_t check_every;   /* iterations between checks K; default 64                   */
+    int32_t ruiz_iters;    /* Ruiz equilibration passes; default 10                     */
+    double restart_suff;   /* restart if KKT_c <= suff * KKT_anchor; default 0.2        */
+    double restart_nec;    /* ... or KKT_c <= nec * KKT_anchor and no progress; 0.8     */
+    double restart_art;    /* ... or k >= art * t (artificial); default 0.36            */
+    double pw_smooth;      /* primal-weight log-smoothing; default 0.5                  */
+    double pc_alpha;       /* Pock-Chambolle exponent; default 1; < 0 disables the pass */
+    int32_t power_iters;   /* power-iteration steps for ||Ahat||_2; default 32          */
+    int32_t halpern;       /* 1: reflected Halpern average (default), 0: plain PDHG     */
+    double eta_safety;     /* step = eta_safety / ||Ahat||_2 estimate; default 0.99     */
+    double reflect_gamma;  /* reflection gamma in [0,1]; default 1                      */
+    int32_t push_min_iters;/* push iterations before the first push check; default 100  */
+    int32_t precision;     /* enum pdhg_precision; default PDHG_FP64                    */
+    double push_obj_scale; /* push objective = scale * Uniform[0,1); default 1          */
+    int64_t push_max_iter; /* iteration cap of a push; default 1e6                      */
+    double time_limit;     /* seconds per solve / push call; <= 0: none (default)       */
+    void *stream;          /* hipStream_t; NULL: library-owned stream                   */
+    int32_t verbosity;     /* 0 silent (default)                                        */
+    int32_t lanes_at;      /* lanes per row for A'y (1..64, power of 2); 0 = automatic  */
+    int32_t lanes_a;       /* lanes per row for A x; 0 = automatic                      */
+    int32_t use_graph;     /* 1: replay check cycles from a captured hipGraph (default) */
+} pdhg_params;
+
+/* outcome of pdhg_solve / pdhg_iterate, evaluated on the original model */
+typedef struct pdhg_result {
+    int32_t status;       /* enum pdhg_status                                          */
+    int32_t pad_;
+    int64_t iters;        /* iterations done in this phase (the passing check's count) */
+    int64_t restarts;
+    double rel_p, rel_d, rel_gap;
+    double pobj, dobj;
+    double seconds;       /* wall time of the call                                     */
+} pdhg_result;
+
+/* KKT and corner statistics of a primal/dual pair on the original model */
+typedef struct pdhg_kkt_report {
+    double rp2, rd2;      /* ||r_P||_2, ||r_D||_2 (unscaled)                           */
+    double rpinf, rdinf;  /* ||r_P||_inf, ||r_D||_inf (absolute test of section 2.1)   */
+    double pobj, dobj, gap;
+    double rel_p, rel_d, rel_gap;
+    int64_t p_off;        /* columns and implicit slacks off their bounds by > 1e-6   */
+    int64_t d_zero;       /* reduced costs (columns, slacks) with |z| <= 1e-6          */
+    int64_t candidates;   /* off bound and |z| < 1e-6 (section 4.2 selection count)    */
+    int64_t est_primal;   /* max(p_off - m, 0): primal push estimate (section 2.1)     */
+    int64_t est_dual;     /* max(m - d_zero, 0): dual push estimate                    */
+} pdhg_kkt_report;
+
+typedef struct pdhg_push_result {
+    int32_t status;       /* PDHG_PUSH_DONE, ITER_LIMIT, TIME_LIMIT or NUMERICAL       */
+    int32_t pad_;
+    int64_t iters;        /* push iterations                                          */
+    int64_t restarts;
+    int64_t n_fix_lower;  /* columns with lb <- x (z_j < -eps_abs)                    */
+    int64_t n_fix_upper;  /* columns with ub <- x (z_j >  eps_abs)                    */
+    int64_t n_rows_to_eq; /* inequality rows turned into equalities                   */
+    double rel_p_push;    /* relative primal residual of the push model at the stop   */
+    double seconds;
+    pdhg_kkt_report before; /* (x, y, z) of the solve, original model                 */
+    pdhg_kkt_report after;  /* (xhat, y, z): pushed x with the solve's y and z         */
+} pdhg_push_result;
+
+/* Fill *p with the defaults listed above. */
+void pdhg_default_params(pdhg_params *p);
+
+/* Copy the LP to the device, build the explicit transpose, scale it (Ruiz,
+ * then Pock-Chambolle), estimate ||Ahat||_2 by power iteration and set up the
+ * iteration at x = clamp(0, l, u), y = 0.  p == NULL uses the defaults.  On
+ * success *out owns all device memory of the solver.  Errors: INVALID_ARG
+ * (NULL pointers, m or n < 0, nnz mismatch, column out of range, non-finite
+ * val/b/c, NaN bound, l > u, unknown sense), OOM, HIP. */
+int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                const double *val, const double *b, const double *c, const double *l, const double *u,
+                const char *sense, const pdhg_params *p, pdhg_solver **out);
+
+/* Iterate until the relative tests hold (PDHG_OPTIMAL), max_iter, the time
+ * limit or a non-finite value.  Re-callable: continues from the current
+ * state.  *r may be NULL.  Errors: INVALID_ARG, STATE (after a push), HIP. */
+int pdhg_solve(pdhg_solver *s, pdhg_result *r);
+
+/* Exactly `iters` further iterations of the solve (fewer only if it
+ * terminates), with checks every check_every iterations as in pdhg_solve. */
+int pdhg_iterate(pdhg_solver *s, int64_t iters, pdhg_result *r);
+
+/* Algorithm 1 of section 3 on the solve's (x, y, z), in place, continued by
+ * PDHG; seed selects the Uniform[0,1) objective (splitmix64 of seed xor
+ * j * 0x9E3779B97F4A7C15, top 53 bits).  Requires a prior solve (STATE). */
+int pdhg_corner_push(pdhg_solver *s, uint64_t seed, pdhg_push_result *r);
+
+/* KKT report of (x, y) on the original model, in float64.  x (n) and y (m)
+ * are host arrays; NULL selects the current solution.  Errors: INVALID_ARG. */
+int pdhg_kkt(pdhg_solver *s, const double *x, const double *y, pdhg_kkt_report *k);
+
+/* Current solution, unscaled: after a solve the last checked candidate
+ * (x, y) and z = reduced costs; after a push (xhat, y, z) with the solve's y
+ * and z (Algorithm 1 returns them unchanged).  Any pointer may be NULL. */
+int pdhg_get_solution(pdhg_solver *s, double *x, double *y, double *z);
+
+/* Current PDHG iterate (x, y) of the running phase, unscaled. */
+int pdhg_get_iterate(pdhg_solver *s, double *x, double *y);
+
+/* Scaling vectors Dr (m), Dc (n) (Ahat = diag(Dr) A diag(Dc)) and
+ * scalars4 = {eta, omega, sigma_estimate, iterations of the phase}. */
+int pdhg_get_scaling(pdhg_solver *s, double *dr, double *dc, double *scalars4);
+
+/* Release all device memory of the handle (NULL is a no-op). */
+void pdhg_destroy(pdhg_solver *s);
+
+/* Thread-local text of the last error ("" if none). */
+const char *pdhg_last_error(void);
+
+/* Size checks for bindings: sizeof of each public struct. */
+int32_t pdhg_struct_size(int32_t which); /* 0 params, 1 result, 2 kkt, 3 push result */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDHG_H */

@@ -1,0 +1,545 @@
+// C ABI of the library: argument checks, ingest, the host loop that replays
+// iteration cycles, and the corner-push orchestration.  All arithmetic of the
+// method runs in the kernels of pdhg_setup.hip and pdhg_iter.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "pdhg.h"
+#include "pdhg_internal.hpp"
+
+namespace pdhg {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg)
+{
+    set_error(msg);
+    return code;
+}
+
+hipError_t init_norms(pdhg_solver *s);
+
+} // namespace pdhg
+
+using namespace pdhg;
+
+namespace {
+
+struct HipFailure {
+    hipError_t err;
+    const char *what;
+};
+
+inline void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) throw HipFailure{e, what};
+}
+
+#define HIPCHK(expr) hip_check((expr), #expr)
+
+template <typename T>
+void dalloc(T **p, size_t count)
+{
+    hip_check(hipMalloc((void **)p, sizeof(T) * (count > 0 ? count : 1)), "hipMalloc");
+}
+
+void free_all(pdhg_solver *s)
+{
+    void *ptrs[] = {s->rp,   s->ci, s->av,  s->tp,   s->ti,     s->tperm, s->atv,  s->b,   s->c,       s->l,
+                    s->u,    s->sense0, s->dr, s->dc, s->ahat, s->ahat_t, s->x,   s->y,     s->xa,   s->ya,
+                    s->xbar, s->xp, s->yp,  s->ch,   s->bh,     s->lh,    s->uh,   s->xs,  s->ys,      s->sense,
+                    s->ax,   s->aty, s->xu, s->yu,   s->zsol,   s->xpush, s->partials, s->redout, s->st};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (s->st_host) (void)hipHostFree(s->st_host);
+    if (s->rep_host) (void)hipHostFree(s->rep_host);
+    if (s->cnt_host) (void)hipHostFree(s->cnt_host);
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+}
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// iteration loop of one phase (mode 1 solve, mode 2 push) for at most
+// `iters` iterations; returns the status
+int run_phase(pdhg_solver *s, int64_t iters, int mode, double t0)
+{
+    const int K = s->p.check_every;
+    const int64_t target = s->t_host + std::max<int64_t>(iters, 0);
+    const int depth = 4; // cycles enqueued before the host looks at the state
+    bool time_out = false;
+    if (s->st_host->done) return s->st_host->status;
+    while (s->t_host < target) {
+        int enq = 0;
+        bool any_check = false;
+        while (s->t_host < target && enq < depth) {
+            const int64_t to_check = s->next_check - s->t_host;
+            const int64_t left = target - s->t_host;
+            const bool check = to_check <= left;
+            const int len = (int)(check ? to_check : left);
+            if (check && len == K && s->p.use_graph) {
+                HIPCHK(capture_cycle(s, K, mode));
+                HIPCHK(hipGraphLaunch(s->graph_exec, s->stream));
+            } else {
+                HIPCHK(launch_iterations(s, len, check, mode));
+            }
+            s->t_host += len;
+            if (check) {
+                s->next_check += K;
+                any_check = true;
+            }
+            enq++;
+        }
+        HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        s->has_candidate = s->st_host->checks > 0;
+        (void)any_check;
+        if (s->st_host->done) {
+            s->t_host = s->st_host->t; // cycles enqueued after the stop did nothing
+            break;
+        }
+        if (s->p.time_limit > 0.0 && now_s() - t0 > s->p.time_limit) {
+            time_out = true;
+            break;
+        }
+    }
+    if (s->st_host->done) return s->st_host->status;
+    return time_out ? PDHG_TIME_LIMIT : PDHG_ITER_LIMIT;
+}
+
+// unscaled solution (xu, yu) and its z / KKT report, for the current phase
+void solution_report(pdhg_solver *s, pdhg_kkt_report *k)
+{
+    if (!s->has_candidate) HIPCHK(candidate_from_iterate(s));
+    HIPCHK(unscale(s, s->xp, s->yp, s->xu, s->yu));
+    HIPCHK(report(s, s->xu, s->yu, s->zsol, k));
+}
+
+int solve_iters(pdhg_solver *s, int64_t iters, pdhg_result *r)
+{
+    const double t0 = now_s();
+    int st = run_phase(s, iters, 1, t0);
+    pdhg_kkt_report k{};
+    solution_report(s, &k);
+    s->solved = s->has_candidate;
+    if (r) {
+        std::memset(r, 0, sizeof(*r));
+        r->status = st;
+        r->iters = s->t_host;
+        r->restarts = s->st_host->restarts;
+        r->rel_p = k.rel_p;
+        r->rel_d = k.rel_d;
+        r->rel_gap = k.rel_gap;
+        r->pobj = k.pobj;
+        r->dobj = k.dobj;
+        r->seconds = now_s() - t0;
+    }
+    return PDHG_OK;
+}
+
+bool row_sorted_unique(const int64_t *rp, const int32_t *ci, int m)
+{
+    for (int i = 0; i < m; i++)
+        for (int64_t e = rp[i] + 1; e < rp[i + 1]; e++)
+            if (ci[e] <= ci[e - 1]) return false;
+    return true;
+}
+
+} // namespace
+
+extern "C" {
+
+void pdhg_default_params(pdhg_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->eps_rel = 1e-6;
+    p->eps_abs = 1e-6;
+    p->max_iter = 1000000;
+    p->check_every = 64;
+    p->ruiz_iters = 10;
+    p->restart_suff = 0.2;
+    p->restart_nec = 0.8;
+    p->restart_art = 0.36;
+    p->pw_smooth = 0.5;
+    p->pc_alpha = 1.0;
+    p->power_iters = 32;
+    p->halpern = 1;
+    p->eta_safety = 0.99;
+    p->reflect_gamma = 1.0;
+    p->push_min_iters = 100;
+    p->precision = PDHG_FP64;
+    p->push_obj_scale = 1.0;
+    p->push_max_iter = 1000000;
+    p->time_limit = 0.0;
+    p->stream = nullptr;
+    p->verbosity = 0;
+    p->lanes_at = 0;
+    p->lanes_a = 0;
+    p->use_graph = 1;
+}
+
+const char *pdhg_last_error(void) { return g_last_error.c_str(); }
+
+int32_t pdhg_struct_size(int32_t which)
+{
+    switch (which) {
+    case 0: return (int32_t)sizeof(pdhg_params);
+    case 1: return (int32_t)sizeof(pdhg_result);
+    case 2: return (int32_t)sizeof(pdhg_kkt_report);
+    case 3: return (int32_t)sizeof(pdhg_push_result);
+    default: return -1;
+    }
+}
+
+int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx, const double *val,
+                const double *b, const double *c, const double *l, const double *u, const char *sense,
+                const pdhg_params *params, pdhg_solver **out)
+{
+    if (!out) return fail(PDHG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (m < 0 || n < 0 || nnz < 0) return fail(PDHG_ERR_INVALID_ARG, "negative dimension");
+    if (!row_ptr || (nnz > 0 && (!col_idx || !val)) || (m > 0 && !b) || (n > 0 && !c))
+        return fail(PDHG_ERR_INVALID_ARG, "NULL array");
+    if (nnz >= (int64_t)1 << 31) return fail(PDHG_ERR_INVALID_ARG, "nnz must stay below 2^31");
+    if (row_ptr[0] != 0 || row_ptr[m] != nnz) return fail(PDHG_ERR_INVALID_ARG, "row_ptr[0] != 0 or row_ptr[m] != nnz");
+    for (int i = 0; i < m; i++)
+        if (row_ptr[i + 1] < row_ptr[i]) return fail(PDHG_ERR_INVALID_ARG, "row_ptr not non-decreasing");
+    for (int64_t e = 0; e < nnz; e++) {
+        if (col_idx[e] < 0 || col_idx[e] >= n) return fail(PDHG_ERR_INVALID_ARG, "column index out of range");
+        if (!std::isfinite(val[e])) return fail(PDHG_ERR_INVALID_ARG, "non-finite matrix value");
+    }
+    for (int i = 0; i < m; i++) {
+        if (!std::isfinite(b[i])) return fail(PDHG_ERR_INVALID_ARG, "non-finite b");
+        if (sense && sense[i] != '=' && sense[i] != '<' && sense[i] != '>')
+            return fail(PDHG_ERR_INVALID_ARG, "sense must be '=', '<' or '>'");
+    }
+    for (int j = 0; j < n; j++) {
+        const double lo = l ? l[j] : 0.0, hi = u ? u[j] : INFINITY;
+        if (!std::isfinite(c[j])) return fail(PDHG_ERR_INVALID_ARG, "non-finite c");
+        if (std::isnan(lo) || std::isnan(hi) || lo > hi) return fail(PDHG_ERR_INVALID_ARG, "bad bounds (NaN or l > u)");
+    }
+    pdhg_params p;
+    if (params) p = *params;
+    else pdhg_default_params(&p);
+    if (p.check_every < 1 || p.ruiz_iters < 0 || p.power_iters < 0 || p.push_min_iters < 1 ||
+        (p.precision != PDHG_FP64 && p.precision != PDHG_FP32_MIXED) || !(p.eps_rel > 0.0) || !(p.eta_safety > 0.0))
+        return fail(PDHG_ERR_INVALID_ARG, "invalid parameter");
+    for (int32_t lanes : {p.lanes_a, p.lanes_at})
+        if (lanes != 0 && (lanes < 1 || lanes > 64 || (lanes & (lanes - 1))))
+            return fail(PDHG_ERR_INVALID_ARG, "lanes must be 0 or a power of two in 1..64");
+
+    // canonical rows (ascending columns, duplicates summed), host side ingest
+    std::vector<int> rp((size_t)m + 1);
+    std::vector<int> ci;
+    std::vector<double> av;
+    if (row_sorted_unique(row_ptr, col_idx, m)) {
+        for (int i = 0; i <= m; i++) rp[i] = (int)row_ptr[i];
+        ci.assign(col_idx, col_idx + nnz);
+        av.assign(val, val + nnz);
+    } else {
+        ci.reserve((size_t)nnz);
+        av.reserve((size_t)nnz);
+        std::vector<std::pair<int, double>> row;
+        rp[0] = 0;
+        for (int i = 0; i < m; i++) {
+            row.clear();
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) row.emplace_back(col_idx[e], val[e]);
+            std::stable_sort(row.begin(), row.end(), [](auto &a, auto &b2) { return a.first < b2.first; });
+            for (size_t q = 0; q < row.size(); q++) {
+                if (!ci.empty() && (int)ci.size() > rp[i] && ci.back() == row[q].first) av.back() += row[q].second;
+                else {
+                    ci.push_back(row[q].first);
+                    av.push_back(row[q].second);
+                }
+            }
+            rp[i + 1] = (int)ci.size();
+        }
+    }
+    const int nz = rp[m];
+    std::vector<double> lv((size_t)n), uv((size_t)n);
+    std::vector<int8_t> sv((size_t)m);
+    for (int j = 0; j < n; j++) {
+        const double lo = l ? l[j] : 0.0, hi = u ? u[j] : INFINITY;
+        lv[j] = lo <= -1e20 ? -INFINITY : lo;
+        uv[j] = hi >= 1e20 ? INFINITY : hi;
+    }
+    for (int i = 0; i < m; i++) sv[i] = (int8_t)(sense ? sense[i] : '=');
+
+    pdhg_solver *s = new (std::nothrow) pdhg_solver();
+    if (!s) return fail(PDHG_ERR_OOM, "host allocation failed");
+    try {
+        s->m = m;
+        s->n = n;
+        s->nnz = nz;
+        s->p = p;
+        s->fp32 = p.precision == PDHG_FP32_MIXED;
+        if (p.stream) s->stream = (hipStream_t)p.stream;
+        else {
+            HIPCHK(hipStreamCreate(&s->stream));
+            s->own_stream = true;
+        }
+        s->lanes_a = p.lanes_a ? p.lanes_a : lanes_for_mean(m > 0 ? (double)nz / m : 1.0);
+        s->lanes_at = p.lanes_at ? p.lanes_at : lanes_for_mean(n > 0 ? (double)nz / n : 1.0);
+        s->red_blocks_m = grid_for(m, kBlock, kMaxRedBlocks);
+        s->red_blocks_n = grid_for(n, kBlock, kMaxRedBlocks);
+        const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
+        const size_t M = (size_t)m, N = (size_t)n, NZ = (size_t)nz;
+        dalloc(&s->rp, M + 1);
+        dalloc(&s->ci, NZ);
+        dalloc(&s->av, NZ);
+        dalloc(&s->tp, N + 1);
+        dalloc(&s->ti, NZ);
+        dalloc(&s->tperm, NZ);
+        dalloc(&s->atv, NZ);
+        dalloc(&s->b, M);
+        dalloc(&s->c, N);
+        dalloc(&s->l, N);
+        dalloc(&s->u, N);
+        dalloc(&s->sense0, M);
+        dalloc(&s->sense, M);
+        dalloc(&s->dr, M);
+        dalloc(&s->dc, N);
+        auto vall = [&](void **ptr, size_t cnt) { hip_check(hipMalloc(ptr, vb * (cnt > 0 ? cnt : 1)), "hipMalloc"); };
+        vall(&s->ahat, NZ);
+        vall(&s->ahat_t, NZ);
+        for (void **q : {&s->x, &s->xa, &s->xbar, &s->xp, &s->ch, &s->lh, &s->uh, &s->xs}) vall(q, N);
+        for (void **q : {&s->y, &s->ya, &s->yp, &s->bh, &s->ys}) vall(q, M);
+        dalloc(&s->ax, M);
+        dalloc(&s->aty, N);
+        dalloc(&s->xu, N);
+        dalloc(&s->yu, M);
+        dalloc(&s->zsol, N);
+        dalloc(&s->xpush, N);
+        const size_t nparts = (size_t)(Q_COUNT + 1) * (s->red_blocks_m + s->red_blocks_n) * 3 + 4 * kMaxRedBlocks;
+        dalloc(&s->partials, nparts);
+        dalloc(&s->redout, 64);
+        dalloc(&s->st, 1);
+        HIPCHK(hipHostMalloc((void **)&s->st_host, sizeof(DevState), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&s->rep_host, sizeof(double) * 64, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&s->cnt_host, sizeof(int64_t) * 16, hipHostMallocDefault));
+
+        hipStream_t st = s->stream;
+        HIPCHK(hipMemcpyAsync(s->rp, rp.data(), sizeof(int) * (M + 1), hipMemcpyHostToDevice, st));
+        if (nz > 0) {
+            HIPCHK(hipMemcpyAsync(s->ci, ci.data(), sizeof(int) * NZ, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(s->av, av.data(), sizeof(double) * NZ, hipMemcpyHostToDevice, st));
+        }
+        if (m > 0) {
+            HIPCHK(hipMemcpyAsync(s->b, b, sizeof(double) * M, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(s->sense0, sv.data(), M, hipMemcpyHostToDevice, st));
+        }
+        if (n > 0) {
+            HIPCHK(hipMemcpyAsync(s->c, c, sizeof(double) * N, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(s->l, lv.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(s->u, uv.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+        }
+        DevState hs{};
+        hs.gamma = p.reflect_gamma;
+        hs.eps_rel = p.eps_rel;
+        hs.r_suff = p.restart_suff;
+        hs.r_nec = p.restart_nec;
+        hs.r_art = p.restart_art;
+        hs.pw_smooth = p.pw_smooth;
+        hs.halpern = p.halpern;
+        hs.status = PDHG_ITER_LIMIT;
+        *s->st_host = hs;
+        HIPCHK(hipMemcpyAsync(s->st, s->st_host, sizeof(DevState), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(build_transpose(s));
+        HIPCHK(scale_problem(s));
+        HIPCHK(power_iteration(s));
+        HIPCHK(init_norms(s));
+        HIPCHK(init_iteration(s));
+        HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        s->t_host = 0;
+        s->next_check = p.check_every;
+    } catch (const HipFailure &f) {
+        std::string msg = std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err);
+        int code = (f.err == hipErrorOutOfMemory) ? PDHG_ERR_OOM : PDHG_ERR_HIP;
+        free_all(s);
+        delete s;
+        return fail(code, msg);
+    }
+    *out = s;
+    set_error("");
+    return PDHG_OK;
+}
+
+int pdhg_iterate(pdhg_solver *s, int64_t iters, pdhg_result *r)
+{
+    if (!s) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
+    if (iters < 0) return fail(PDHG_ERR_INVALID_ARG, "negative iteration count");
+    if (s->in_push) return fail(PDHG_ERR_STATE, "the handle is in its push phase");
+    try {
+        return solve_iters(s, iters, r);
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+}
+
+int pdhg_solve(pdhg_solver *s, pdhg_result *r)
+{
+    if (!s) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
+    if (s->in_push) return fail(PDHG_ERR_STATE, "the handle is in its push phase");
+    const int64_t left = s->p.max_iter - s->t_host;
+    return pdhg_iterate(s, left > 0 ? left : 0, r);
+}
+
+int pdhg_corner_push(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
+{
+    if (!s || !r) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    if (!s->solved || s->in_push) return fail(PDHG_ERR_STATE, "corner push needs a solve first (and runs once)");
+    std::memset(r, 0, sizeof(*r));
+    const double t0 = now_s();
+    try {
+        hipStream_t st = s->stream;
+        const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
+        // CP1: the solve's candidate (x, y) and z on the original model
+        HIPCHK(hipMemcpyAsync(s->xs, s->xp, vb * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(s->ys, s->yp, vb * (size_t)s->m, hipMemcpyDeviceToDevice, st));
+        HIPCHK(unscale(s, s->xs, s->ys, s->xu, s->yu));
+        HIPCHK(report(s, s->xu, s->yu, s->zsol, &r->before));
+        // CP2-CP5: bounds, senses, objective, start (x, 0), new weight and restart state
+        HIPCHK(push_setup(s, seed, r));
+        HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        s->in_push = true;
+        s->has_candidate = false;
+        s->t_host = 0;
+        s->next_check = s->p.push_min_iters;
+        // CP6
+        int status = run_phase(s, s->p.push_max_iter, 2, t0);
+        // CP7: (xhat, y, z)
+        if (s->has_candidate) HIPCHK(unscale(s, s->xp, nullptr, s->xpush, nullptr));
+        else HIPCHK(hipMemcpyAsync(s->xpush, s->xu, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(report(s, s->xpush, s->yu, nullptr, &r->after));
+        r->status = status;
+        r->iters = s->t_host;
+        r->restarts = s->st_host->restarts;
+        r->rel_p_push = s->st_host->checks > 0 ? s->st_host->rel_p : NAN;
+        r->seconds = now_s() - t0;
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_kkt(pdhg_solver *s, const double *x, const double *y, pdhg_kkt_report *k)
+{
+    if (!s || !k) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    try {
+        hipStream_t st = s->stream;
+        double *dx = nullptr, *dy = nullptr;
+        if (!s->in_push && (!x || !y)) {
+            pdhg_kkt_report tmp;
+            solution_report(s, &tmp);
+        }
+        const double *cx = s->in_push ? s->xpush : s->xu;
+        const double *cy = s->yu;
+        if (x) {
+            dalloc(&dx, (size_t)s->n);
+            HIPCHK(hipMemcpyAsync(dx, x, sizeof(double) * (size_t)s->n, hipMemcpyHostToDevice, st));
+            cx = dx;
+        }
+        if (y) {
+            dalloc(&dy, (size_t)s->m);
+            HIPCHK(hipMemcpyAsync(dy, y, sizeof(double) * (size_t)s->m, hipMemcpyHostToDevice, st));
+            cy = dy;
+        }
+        hipError_t e = report(s, cx, cy, nullptr, k);
+        if (dx) (void)hipFree(dx);
+        if (dy) (void)hipFree(dy);
+        HIPCHK(e);
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_get_solution(pdhg_solver *s, double *x, double *y, double *z)
+{
+    if (!s) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
+    try {
+        hipStream_t st = s->stream;
+        if (!s->in_push) {
+            pdhg_kkt_report tmp;
+            solution_report(s, &tmp);
+        }
+        const double *cx = s->in_push ? s->xpush : s->xu;
+        if (x) HIPCHK(hipMemcpyAsync(x, cx, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
+        if (y) HIPCHK(hipMemcpyAsync(y, s->yu, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToHost, st));
+        if (z) HIPCHK(hipMemcpyAsync(z, s->zsol, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_get_iterate(pdhg_solver *s, double *x, double *y)
+{
+    if (!s) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
+    try {
+        hipStream_t st = s->stream;
+        double *dx = nullptr, *dy = nullptr;
+        dalloc(&dx, (size_t)s->n);
+        dalloc(&dy, (size_t)s->m);
+        HIPCHK(unscale(s, s->x, s->y, dx, dy));
+        if (x) HIPCHK(hipMemcpyAsync(x, dx, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
+        if (y) HIPCHK(hipMemcpyAsync(y, dy, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToHost, st));
+        hipError_t e = hipStreamSynchronize(st);
+        (void)hipFree(dx);
+        (void)hipFree(dy);
+        HIPCHK(e);
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_get_scaling(pdhg_solver *s, double *dr, double *dc, double *scalars4)
+{
+    if (!s) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
+    try {
+        hipStream_t st = s->stream;
+        if (dr) HIPCHK(hipMemcpyAsync(dr, s->dr, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToHost, st));
+        if (dc) HIPCHK(hipMemcpyAsync(dc, s->dc, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (scalars4) {
+            scalars4[0] = s->st_host->eta;
+            scalars4[1] = s->st_host->omega;
+            scalars4[2] = s->st_host->sigma_est;
+            scalars4[3] = (double)s->t_host;
+        }
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+void pdhg_destroy(pdhg_solver *s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    free_all(s);
+    delete s;
+}
+
+} // extern "C"

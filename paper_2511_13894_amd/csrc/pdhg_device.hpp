@@ -1,0 +1,111 @@
+// Device-side building blocks: wave64 / workgroup reductions and the
+// row-compressed sparse product with L lanes per row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pdhg_internal.hpp"
+
+namespace pdhg {
+
+// Sum over a group of L consecutive lanes (L a power of two <= 64); every lane
+// of the group ends with the group's sum.  Butterfly order is fixed, so the
+// result is deterministic.
+template <int L, typename T>
+__device__ __forceinline__ T group_sum(T v)
+{
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Workgroup reduction of NQ values (sum, or max where is_max bit q is set);
+// thread 0 receives the results.  Uses kBlock/64 LDS slots per quantity.
+template <int NQ>
+__device__ __forceinline__ void block_reduce(double (&v)[NQ], unsigned is_max_mask)
+{
+    __shared__ double lds[NQ][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+        v[q] = ((is_max_mask >> q) & 1u) ? wave_max(v[q]) : wave_sum(v[q]);
+        if (lane == 0) lds[q][wid] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            double acc = lds[q][0];
+            for (int w = 1; w < kBlock / 64; w++)
+                acc = ((is_max_mask >> q) & 1u) ? fmax(acc, lds[q][w]) : acc + lds[q][w];
+            v[q] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// Row-compressed product out[r] = sum_e val[e] * x[idx[e]] over rows r < rows,
+// L lanes per row, accumulation in ACC.  One group of L lanes walks a row with
+// stride L (coalesced for L >= 2 on long rows, one lane per row when L = 1).
+template <int L, typename VM, typename VX, typename ACC, typename VO>
+__global__ __launch_bounds__(kBlock) void k_spmv(int rows, const int *__restrict__ ptr,
+                                                 const int *__restrict__ idx, const VM *__restrict__ val,
+                                                 const VX *__restrict__ x, VO *__restrict__ out)
+{
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t row = g / L;
+    const int lane = (int)(g % L);
+    if (row >= rows) return;
+    const int beg = ptr[row], end = ptr[row + 1];
+    ACC acc = 0;
+    for (int e = beg + lane; e < end; e += L) acc += (ACC)val[e] * (ACC)x[idx[e]];
+    acc = group_sum<L>(acc);
+    if (lane == 0) out[row] = (VO)acc;
+}
+
+// Launch k_spmv with the lane count chosen at run time.
+template <typename VM, typename VX, typename ACC, typename VO>
+inline void spmv(hipStream_t st, int lanes, int rows, const int *ptr, const int *idx, const VM *val,
+                 const VX *x, VO *out)
+{
+    if (rows <= 0) return;
+    const int64_t threads = (int64_t)rows * lanes;
+    const int grid = (int)((threads + kBlock - 1) / kBlock);
+#define PDHG_SPMV_CASE(LL)                                                                       \
+    case LL:                                                                                     \
+        hipLaunchKernelGGL((k_spmv<LL, VM, VX, ACC, VO>), dim3(grid), dim3(kBlock), 0, st, rows, \
+                           ptr, idx, val, x, out);                                               \
+        break;
+    switch (lanes) {
+        PDHG_SPMV_CASE(1)
+        PDHG_SPMV_CASE(2)
+        PDHG_SPMV_CASE(4)
+        PDHG_SPMV_CASE(8)
+        PDHG_SPMV_CASE(16)
+        PDHG_SPMV_CASE(32)
+    default:
+        PDHG_SPMV_CASE(64)
+    }
+#undef PDHG_SPMV_CASE
+}
+
+__device__ __forceinline__ bool is_inf_lo(double v) { return v <= -1e20; }
+__device__ __forceinline__ bool is_inf_up(double v) { return v >= 1e20; }
+
+} // namespace pdhg

@@ -1,0 +1,162 @@
+// Internal declarations of the gfx950 PDHG library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "pdhg.h"
+
+namespace pdhg {
+
+constexpr int kBlock = 256;         // threads per workgroup (4 wave64)
+constexpr int kMaxRedBlocks = 1024; // cap on per-block partials of a reduction
+
+// Quantities reduced at a check (block partials, then one fixed-order pass).
+enum CheckQ {
+    Q_PH2 = 0, // sum rP_hat^2           (scaled, current senses)
+    Q_P2,      // sum rP^2               (unscaled)
+    Q_PINF,    // max |rP|               (unscaled)
+    Q_BTY,     // sum bhat_i yhat_i
+    Q_DY2,     // sum (yp - ya)^2        (scaled)
+    Q_DH2,     // sum rD_hat^2
+    Q_D2,      // sum rD^2               (unscaled)
+    Q_DINF,    // max |rD|
+    Q_CTX,     // sum chat_j xhat_j
+    Q_BND,     // sum lhat zhat+ - uhat zhat-
+    Q_DX2,     // sum (xp - xa)^2
+    Q_NAN,     // count of non-finite candidate entries
+    Q_COUNT
+};
+
+// Quantities of a KKT report (original model, float64).
+enum ReportQ {
+    R_P2 = 0, R_PINF, R_BTY, R_D2, R_DINF, R_CTX, R_BND, R_POFF, R_DZERO, R_CAND, R_COUNT
+};
+
+// Scalar solver state kept in device memory so that every kernel reads its
+// step sizes, Halpern counter and flags without host round trips.
+struct DevState {
+    double eta, omega, tau, sigma;
+    double gamma;                  // reflection
+    double eps_rel;
+    double r_suff, r_nec, r_art, pw_smooth;
+    double nb1, nc1;               // 1 + ||b||_2, 1 + ||c||_2 (original model)
+    double sigma_est;              // power-iteration estimate of ||Ahat||_2
+    int64_t k0;                    // Halpern counter at the last state update
+    int64_t t;                     // iterations of this phase at the last update
+    int64_t restarts;
+    double anc_p2, anc_d2, anc_g2; // weighted-KKT parts at the anchor
+    double kkt_prev;
+    // values of the last check (unscaled relative tests, objectives)
+    double rel_p, rel_d, rel_gap, pobj, dobj, kkt_c;
+    int32_t halpern;
+    int32_t restart_flag;
+    int32_t done;
+    int32_t status;
+    int32_t checks;
+    int32_t pad_;
+};
+
+// Host-side report values read back from the device.
+struct ReportOut {
+    double v[R_COUNT];
+};
+
+} // namespace pdhg
+
+// The opaque handle of the ABI.
+struct pdhg_solver {
+    int m = 0, n = 0;
+    int nnz = 0;
+    pdhg_params p{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool fp32 = false;
+
+    // original model, float64, row-compressed A and its explicit transpose
+    int *rp = nullptr, *ci = nullptr;
+    double *av = nullptr;
+    int *tp = nullptr, *ti = nullptr, *tperm = nullptr;
+    double *atv = nullptr;
+    double *b = nullptr, *c = nullptr, *l = nullptr, *u = nullptr;
+    int8_t *sense0 = nullptr;
+
+    // scaling
+    double *dr = nullptr, *dc = nullptr;
+
+    // iteration arrays in the working precision (float or double)
+    void *ahat = nullptr, *ahat_t = nullptr;
+    void *x = nullptr, *y = nullptr, *xa = nullptr, *ya = nullptr, *xbar = nullptr;
+    void *xp = nullptr, *yp = nullptr;
+    void *ch = nullptr, *bh = nullptr, *lh = nullptr, *uh = nullptr;
+    void *xs = nullptr, *ys = nullptr; // scaled solution of the solve (kept for the push)
+    int8_t *sense = nullptr;
+
+    // float64 work: products, unscaled copies, reduced costs, partial sums
+    double *ax = nullptr, *aty = nullptr;
+    double *xu = nullptr, *yu = nullptr, *zsol = nullptr, *xpush = nullptr;
+    double *partials = nullptr;
+    double *redout = nullptr; // small reduction results
+    int red_blocks_m = 1, red_blocks_n = 1;
+    pdhg::DevState *st = nullptr;
+    pdhg::DevState *st_host = nullptr; // pinned mirror
+    double *rep_host = nullptr;        // pinned report values
+    int64_t *cnt_host = nullptr;       // pinned integer counts
+
+    int lanes_at = 1, lanes_a = 1;
+    int64_t t_host = 0;      // iterations of the current phase (mirror of st->t)
+    int64_t next_check = 0;  // phase iteration count of the next check
+    bool in_push = false;
+    bool has_candidate = false;   // a check has produced (xp, yp) in this phase
+    bool solved = false;          // the solve has a candidate (push allowed)
+    bool has_push_candidate = false;
+
+    // captured cycle graphs (K iterations + check) keyed by length
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_len = 0;
+    int graph_mode = -1;
+};
+
+namespace pdhg {
+
+// error helpers (capi.cpp)
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+// setup kernels (pdhg_setup.hip)
+hipError_t build_transpose(pdhg_solver *s);
+hipError_t scale_problem(pdhg_solver *s);
+hipError_t power_iteration(pdhg_solver *s);
+
+// iteration, checks, push and reports (pdhg_iter.hip)
+hipError_t init_iteration(pdhg_solver *s);
+hipError_t launch_iterations(pdhg_solver *s, int count, bool check_at_end, int mode);
+hipError_t launch_check(pdhg_solver *s, int mode, int len);
+hipError_t launch_advance(pdhg_solver *s, int len);
+hipError_t candidate_from_iterate(pdhg_solver *s);
+hipError_t unscale(pdhg_solver *s, const void *xh, const void *yh, double *xo, double *yo);
+hipError_t report(pdhg_solver *s, const double *x, const double *y, double *z, pdhg_kkt_report *k);
+hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r);
+hipError_t capture_cycle(pdhg_solver *s, int len, int mode);
+
+// launch-shape helpers
+// Lane count for a given mean row length: the power of two at or above the
+// mean, between 1 and 64.
+inline int lanes_for_mean(double mean)
+{
+    int l = 1;
+    while (l < 64 && l < mean) l <<= 1;
+    return l;
+}
+
+inline int grid_for(int64_t items, int per_block, int cap)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+} // namespace pdhg

@@ -1,0 +1,839 @@
+// The PDHG iteration (primal and dual halves with fused projections,
+// extrapolation and Halpern averaging), the periodic check (residuals, gap,
+// weighted KKT, restart and primal-weight update, termination), the corner
+// push setup of Algorithm 1, and float64 KKT reports on the original model.
+#include <cmath>
+
+#include "pdhg_device.hpp"
+#include "pdhg_internal.hpp"
+
+namespace pdhg {
+
+// ------------------------------------------------------------ iteration ---
+// Halpern weights for iteration number k (0-based since the last restart).
+__device__ __forceinline__ void halpern_weights(const DevState *st, int i, double &w, double &wa, double &g)
+{
+    const double k = (double)(st->k0 + i);
+    w = (k + 1.0) / (k + 2.0);
+    wa = 1.0 / (k + 2.0);
+    g = st->gamma;
+}
+
+// Primal half, one row of the transpose (= one column j of A) per group of L
+// lanes:  g = Ahat' y;  x+ = clamp(x - tau (chat - g), lhat, uhat);
+// xbar = 2 x+ - x;  x <- w ((1+gamma) x+ - gamma x) + wa x_anchor.
+// At the last iteration before a check the candidate x+ is stored as well.
+template <typename V, int L>
+__global__ __launch_bounds__(kBlock) void k_primal(int n, const int *__restrict__ tp, const int *__restrict__ ti,
+                                                  const V *__restrict__ atv, const V *__restrict__ y,
+                                                  const V *__restrict__ ch, const V *__restrict__ lh,
+                                                  const V *__restrict__ uh, V *__restrict__ x,
+                                                  const V *__restrict__ xa, V *__restrict__ xbar, V *__restrict__ xp,
+                                                  const DevState *__restrict__ st, int i, int store_cand)
+{
+    if (st->done) return;
+    const int64_t gi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t j = gi / L;
+    const int lane = (int)(gi % L);
+    if (j >= n) return;
+    V acc = 0;
+    const int beg = tp[j], end = tp[j + 1];
+    for (int e = beg + lane; e < end; e += L) acc += atv[e] * y[ti[e]];
+    acc = group_sum<L>(acc);
+    if (lane != 0) return;
+    const V tau = (V)st->tau;
+    const V xj = x[j];
+    V xn = xj - tau * (ch[j] - acc);
+    xn = xn < lh[j] ? lh[j] : xn;
+    xn = xn > uh[j] ? uh[j] : xn;
+    xbar[j] = (V)2 * xn - xj;
+    if (store_cand) xp[j] = xn;
+    if (st->halpern) {
+        double w, wa, g;
+        halpern_weights(st, i, w, wa, g);
+        x[j] = (V)w * (((V)1 + (V)g) * xn - (V)g * xj) + (V)wa * xa[j];
+    } else {
+        x[j] = xn;
+    }
+}
+
+// Dual half, one row of A per group of L lanes:  h = Ahat xbar;
+// y+ = proj_Y(y + sigma (bhat - h));  y <- w ((1+gamma) y+ - gamma y) + wa y_anchor.
+template <typename V, int L>
+__global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                const V *__restrict__ av, const V *__restrict__ xbar,
+                                                const V *__restrict__ bh, const int8_t *__restrict__ sense,
+                                                V *__restrict__ y, const V *__restrict__ ya, V *__restrict__ yp,
+                                                const DevState *__restrict__ st, int i, int store_cand)
+{
+    if (st->done) return;
+    const int64_t gi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t r = gi / L;
+    const int lane = (int)(gi % L);
+    if (r >= m) return;
+    V acc = 0;
+    const int beg = rp[r], end = rp[r + 1];
+    for (int e = beg + lane; e < end; e += L) acc += av[e] * xbar[ci[e]];
+    acc = group_sum<L>(acc);
+    if (lane != 0) return;
+    const V sig = (V)st->sigma;
+    const V yr = y[r];
+    V yn = yr + sig * (bh[r] - acc);
+    const int8_t s = sense[r];
+    if (s == '<') yn = yn < (V)0 ? yn : (V)0;
+    else if (s == '>') yn = yn > (V)0 ? yn : (V)0;
+    if (store_cand) yp[r] = yn;
+    if (st->halpern) {
+        double w, wa, g;
+        halpern_weights(st, i, w, wa, g);
+        y[r] = (V)w * (((V)1 + (V)g) * yn - (V)g * yr) + (V)wa * ya[r];
+    } else {
+        y[r] = yn;
+    }
+}
+
+template <typename V>
+static void launch_primal(pdhg_solver *s, int i, int store)
+{
+    const int L = s->lanes_at;
+    const int grid = (int)(((int64_t)s->n * L + kBlock - 1) / kBlock);
+    if (s->n <= 0) return;
+#define PDHG_PRIMAL_CASE(LL)                                                                                    \
+    case LL:                                                                                                    \
+        hipLaunchKernelGGL((k_primal<V, LL>), dim3(grid), dim3(kBlock), 0, s->stream, s->n, s->tp, s->ti,      \
+                           (const V *)s->ahat_t, (const V *)s->y, (const V *)s->ch, (const V *)s->lh,          \
+                           (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i,  \
+                           store);                                                                              \
+        break;
+    switch (L) {
+        PDHG_PRIMAL_CASE(1)
+        PDHG_PRIMAL_CASE(2)
+        PDHG_PRIMAL_CASE(4)
+        PDHG_PRIMAL_CASE(8)
+        PDHG_PRIMAL_CASE(16)
+        PDHG_PRIMAL_CASE(32)
+    default:
+        PDHG_PRIMAL_CASE(64)
+    }
+#undef PDHG_PRIMAL_CASE
+}
+
+template <typename V>
+static void launch_dual(pdhg_solver *s, int i, int store)
+{
+    const int L = s->lanes_a;
+    const int grid = (int)(((int64_t)s->m * L + kBlock - 1) / kBlock);
+    if (s->m <= 0) return;
+#define PDHG_DUAL_CASE(LL)                                                                                      \
+    case LL:                                                                                                    \
+        hipLaunchKernelGGL((k_dual<V, LL>), dim3(grid), dim3(kBlock), 0, s->stream, s->m, s->rp, s->ci,        \
+                           (const V *)s->ahat, (const V *)s->xbar, (const V *)s->bh, s->sense, (V *)s->y,      \
+                           (const V *)s->ya, (V *)s->yp, s->st, i, store);                                      \
+        break;
+    switch (L) {
+        PDHG_DUAL_CASE(1)
+        PDHG_DUAL_CASE(2)
+        PDHG_DUAL_CASE(4)
+        PDHG_DUAL_CASE(8)
+        PDHG_DUAL_CASE(16)
+        PDHG_DUAL_CASE(32)
+    default:
+        PDHG_DUAL_CASE(64)
+    }
+#undef PDHG_DUAL_CASE
+}
+
+// ---------------------------------------------------------------- checks ---
+// Row part of a check on the candidate (xc, yc) of the scaled current model:
+// rP_hat (current senses), unscaled rP = rP_hat / Dr, b'y, ||yc - ya||^2.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_check_rows(int m, const double *__restrict__ ax, const V *__restrict__ bh,
+                                                      const int8_t *__restrict__ sense, const double *__restrict__ dr,
+                                                      const V *__restrict__ yc, const V *__restrict__ ya,
+                                                      double *__restrict__ part, int nblk, const DevState *st)
+{
+    if (st->done) return;
+    double v[6] = {0, 0, 0, 0, 0, 0}; // PH2, P2, PINF, BTY, DY2, NAN
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+        double r = (double)bh[i] - ax[i];
+        const int8_t s = sense[i];
+        if (s == '<') r = r < 0.0 ? r : 0.0;
+        else if (s == '>') r = r > 0.0 ? r : 0.0;
+        const double ru = r / dr[i];
+        const double yi = (double)yc[i];
+        const double dy = yi - (double)ya[i];
+        v[0] += r * r;
+        v[1] += ru * ru;
+        v[2] = fmax(v[2], fabs(ru));
+        v[3] += (double)bh[i] * yi;
+        v[4] += dy * dy;
+        v[5] += isfinite(yi) ? 0.0 : 1.0;
+    }
+    block_reduce<6>(v, 1u << 2);
+    if (threadIdx.x == 0) {
+        part[Q_PH2 * nblk + blockIdx.x] = v[0];
+        part[Q_P2 * nblk + blockIdx.x] = v[1];
+        part[Q_PINF * nblk + blockIdx.x] = v[2];
+        part[Q_BTY * nblk + blockIdx.x] = v[3];
+        part[Q_DY2 * nblk + blockIdx.x] = v[4];
+        part[Q_NAN * nblk + blockIdx.x] = v[5];
+    }
+}
+
+// Column part: lambda_hat = chat - Ahat'yc, zhat split by the finite bounds,
+// rD_hat = lambda_hat - zhat, unscaled rD = rD_hat / Dc, chat'xc, bound terms
+// of the dual objective, ||xc - xa||^2.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_check_cols(int n, const double *__restrict__ aty, const V *__restrict__ ch,
+                                                      const V *__restrict__ lh, const V *__restrict__ uh,
+                                                      const double *__restrict__ dc, const V *__restrict__ xc,
+                                                      const V *__restrict__ xa, double *__restrict__ part, int nblk,
+                                                      const DevState *st)
+{
+    if (st->done) return;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0}; // DH2, D2, DINF, CTX, BND, DX2, NAN
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        const double lam = (double)ch[j] - aty[j];
+        const double lo = (double)lh[j], hi = (double)uh[j];
+        const double zp = (!is_inf_lo(lo) && lam > 0.0) ? lam : 0.0;
+        const double zm = (!is_inf_up(hi) && lam < 0.0) ? -lam : 0.0;
+        const double rd = lam - (zp - zm);
+        const double rdu = rd / dc[j];
+        const double xj = (double)xc[j];
+        const double dx = xj - (double)xa[j];
+        v[0] += rd * rd;
+        v[1] += rdu * rdu;
+        v[2] = fmax(v[2], fabs(rdu));
+        v[3] += (double)ch[j] * xj;
+        if (zp > 0.0) v[4] += lo * zp;
+        if (zm > 0.0) v[4] -= hi * zm;
+        v[5] += dx * dx;
+        v[6] += isfinite(xj) ? 0.0 : 1.0;
+    }
+    block_reduce<7>(v, 1u << 2);
+    if (threadIdx.x == 0) {
+        part[Q_DH2 * nblk + blockIdx.x] = v[0];
+        part[Q_D2 * nblk + blockIdx.x] = v[1];
+        part[Q_DINF * nblk + blockIdx.x] = v[2];
+        part[Q_CTX * nblk + blockIdx.x] = v[3];
+        part[Q_BND * nblk + blockIdx.x] = v[4];
+        part[Q_DX2 * nblk + blockIdx.x] = v[5];
+        part[(Q_COUNT)*nblk + blockIdx.x] = v[6];
+    }
+}
+
+__device__ __forceinline__ double kkt_weighted(double om, double p2, double d2, double g2)
+{
+    return sqrt(om * om * p2 + d2 / (om * om) + g2);
+}
+
+// One workgroup: reduce the partials in a fixed order, then
+//   mode 0: record the anchor's weighted-KKT parts (start of a phase);
+//   mode 1: solve check (termination on all three relative tests, restart);
+//   mode 2: push check (termination on the primal test only, restart).
+// `len` is the number of iterations since the last state update.
+__global__ __launch_bounds__(kBlock) void k_check_final(DevState *st, const double *__restrict__ pm, int gm,
+                                                       const double *__restrict__ pn, int gn, int mode, int len)
+{
+    if (st->done) return;
+    // slot q of the row partials lives at pm[q * gm + b], of the column
+    // partials at pn[q * gn + b]; slot Q_COUNT holds the column NaN count
+    double v[Q_COUNT + 1];
+#pragma unroll
+    for (int q = 0; q < Q_COUNT + 1; q++) {
+        const bool is_row = (q == Q_PH2 || q == Q_P2 || q == Q_PINF || q == Q_BTY || q == Q_DY2 || q == Q_NAN);
+        const bool is_max = (q == Q_PINF || q == Q_DINF);
+        const double *src = is_row ? pm + (size_t)q * gm : pn + (size_t)q * gn;
+        const int nb = is_row ? gm : gn;
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nb; b += kBlock) acc = is_max ? fmax(acc, src[b]) : acc + src[b];
+        v[q] = acc;
+    }
+    block_reduce<Q_COUNT + 1>(v, (1u << Q_PINF) | (1u << Q_DINF));
+    if (threadIdx.x != 0) return;
+    const double ph2 = v[Q_PH2], p2 = v[Q_P2], bty = v[Q_BTY], dy2 = v[Q_DY2];
+    const double dh2 = v[Q_DH2], d2 = v[Q_D2], ctx = v[Q_CTX], bnd = v[Q_BND], dx2 = v[Q_DX2];
+    const double nans = v[Q_NAN] + v[Q_COUNT];
+    const double pobj = ctx, dobj = bty + bnd, gap = pobj - dobj;
+    if (mode == 0) {
+        st->anc_p2 = ph2;
+        st->anc_d2 = dh2;
+        st->anc_g2 = gap * gap;
+        st->kkt_prev = kkt_weighted(st->omega, ph2, dh2, gap * gap);
+        return;
+    }
+    const int64_t t_now = st->t + len, k_now = st->k0 + len;
+    st->t = t_now;
+    st->checks += 1;
+    st->rel_p = sqrt(p2) / st->nb1;
+    st->rel_d = sqrt(d2) / st->nc1;
+    st->rel_gap = fabs(gap) / (1.0 + fabs(pobj) + fabs(dobj));
+    st->pobj = pobj;
+    st->dobj = dobj;
+    st->restart_flag = 0;
+    if (nans > 0.0) {
+        st->done = 1;
+        st->status = PDHG_NUMERICAL;
+        st->k0 = k_now;
+        return;
+    }
+    const double eps = st->eps_rel;
+    if (mode == 1 && st->rel_p <= eps && st->rel_d <= eps && st->rel_gap <= eps) {
+        st->done = 1;
+        st->status = PDHG_OPTIMAL;
+        st->k0 = k_now;
+        return;
+    }
+    if (mode == 2 && st->rel_p <= eps) {
+        st->done = 1;
+        st->status = PDHG_PUSH_DONE;
+        st->k0 = k_now;
+        return;
+    }
+    const double om = st->omega;
+    const double kc = kkt_weighted(om, ph2, dh2, gap * gap);
+    const double ka = kkt_weighted(om, st->anc_p2, st->anc_d2, st->anc_g2);
+    st->kkt_c = kc;
+    const bool restart = (kc <= st->r_suff * ka) || (kc <= st->r_nec * ka && kc > st->kkt_prev) ||
+                         ((double)k_now >= st->r_art * (double)t_now);
+    st->kkt_prev = kc;
+    if (!restart) {
+        st->k0 = k_now;
+        return;
+    }
+    const double dx = sqrt(dx2), dy = sqrt(dy2);
+    double om2 = om;
+    if (dx > 1e-10 && dy > 1e-10) {
+        const double th = st->pw_smooth;
+        om2 = exp(th * log(dy / dx) + (1.0 - th) * log(om));
+    }
+    st->omega = om2;
+    st->tau = st->eta / om2;
+    st->sigma = st->eta * om2;
+    st->anc_p2 = ph2;
+    st->anc_d2 = dh2;
+    st->anc_g2 = gap * gap;
+    st->kkt_prev = kkt_weighted(om2, ph2, dh2, gap * gap);
+    st->k0 = 0;
+    st->restarts += 1;
+    st->restart_flag = 1;
+}
+
+// On restart: x = x_anchor = x+, y = y_anchor = y+ (candidate of the check).
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_restart_apply(int n, int m, const DevState *st, V *__restrict__ x,
+                                                         V *__restrict__ xa, const V *__restrict__ xp,
+                                                         V *__restrict__ y, V *__restrict__ ya,
+                                                         const V *__restrict__ yp)
+{
+    if (!st->restart_flag || st->done) return;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
+        if (i < n) {
+            const V v = xp[i];
+            x[i] = v;
+            xa[i] = v;
+        } else {
+            const int64_t r = i - n;
+            const V v = yp[r];
+            y[r] = v;
+            ya[r] = v;
+        }
+    }
+}
+
+__global__ void k_advance(DevState *st, int len)
+{
+    if (st->done) return;
+    st->t += len;
+    st->k0 += len;
+}
+
+template <typename V>
+static void check_impl(pdhg_solver *s, const V *xc, const V *yc, double *pm, double *pn)
+{
+    hipStream_t st = s->stream;
+    spmv<V, V, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
+    spmv<V, V, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, (const V *)s->ahat_t, yc, s->aty);
+    const int gm = s->red_blocks_m, gn = s->red_blocks_n;
+    hipLaunchKernelGGL((k_check_rows<V>), dim3(gm), dim3(kBlock), 0, st, s->m, s->ax, (const V *)s->bh, s->sense, s->dr,
+                       yc, (const V *)s->ya, pm, gm, s->st);
+    hipLaunchKernelGGL((k_check_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->aty, (const V *)s->ch,
+                       (const V *)s->lh, (const V *)s->uh, s->dc, xc, (const V *)s->xa, pn, gn, s->st);
+}
+
+hipError_t launch_check(pdhg_solver *s, int mode, int len)
+{
+    const bool use_cand = mode != 0;
+    const int gm = s->red_blocks_m, gn = s->red_blocks_n;
+    double *pm = s->partials;
+    double *pn = s->partials + (size_t)(Q_COUNT + 1) * gm;
+    if (s->fp32)
+        check_impl<float>(s, (const float *)(use_cand ? s->xp : s->x), (const float *)(use_cand ? s->yp : s->y), pm, pn);
+    else
+        check_impl<double>(s, (const double *)(use_cand ? s->xp : s->x), (const double *)(use_cand ? s->yp : s->y), pm,
+                           pn);
+    hipLaunchKernelGGL(k_check_final, dim3(1), dim3(kBlock), 0, s->stream, s->st, pm, gm, pn, gn, mode, len);
+    if (mode != 0) {
+        const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
+        if (s->fp32)
+            hipLaunchKernelGGL((k_restart_apply<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->st,
+                               (float *)s->x, (float *)s->xa, (const float *)s->xp, (float *)s->y, (float *)s->ya,
+                               (const float *)s->yp);
+        else
+            hipLaunchKernelGGL((k_restart_apply<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->st,
+                               (double *)s->x, (double *)s->xa, (const double *)s->xp, (double *)s->y, (double *)s->ya,
+                               (const double *)s->yp);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(pdhg_solver *s, int len)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s->stream, s->st, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_iterations(pdhg_solver *s, int count, bool check_at_end, int mode)
+{
+    for (int i = 0; i < count; i++) {
+        const int store = (check_at_end && i == count - 1) ? 1 : 0;
+        if (s->fp32) {
+            launch_primal<float>(s, i, store);
+            launch_dual<float>(s, i, store);
+        } else {
+            launch_primal<double>(s, i, store);
+            launch_dual<double>(s, i, store);
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (check_at_end) return launch_check(s, mode, count);
+    return launch_advance(s, count);
+}
+
+// capture `len` iterations + the check into a graph (replayed per cycle)
+hipError_t capture_cycle(pdhg_solver *s, int len, int mode)
+{
+    if (s->graph_exec && s->graph_len == len && s->graph_mode == mode) return hipSuccess;
+    if (s->graph_exec) {
+        hipGraphExecDestroy(s->graph_exec);
+        s->graph_exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t el = launch_iterations(s, len, true, mode);
+    e = hipStreamEndCapture(s->stream, &g);
+    if (el != hipSuccess) return el;
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    s->graph_len = len;
+    s->graph_mode = mode;
+    return hipSuccess;
+}
+
+// ----------------------------------------------------------- phase start ---
+// partial sums of chat^2 (cols) and bhat^2 (rows) for the initial weight
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_sumsq2(int n, const V *__restrict__ a, int m, const V *__restrict__ bvec,
+                                                  double *__restrict__ part, int nblk)
+{
+    double v[2] = {0.0, 0.0};
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        const double q = (double)a[j];
+        v[0] += q * q;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+        const double q = (double)bvec[i];
+        v[1] += q * q;
+    }
+    block_reduce<2>(v, 0u);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v[0];
+        part[nblk + blockIdx.x] = v[1];
+    }
+}
+
+// omega = ||chat|| / ||bhat|| (both > 1e-10, else 1); tau, sigma; counters reset
+__global__ __launch_bounds__(kBlock) void k_phase_start(DevState *st, const double *__restrict__ part, int nblk)
+{
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+        v[0] += part[b];
+        v[1] += part[nblk + b];
+    }
+    block_reduce<2>(v, 0u);
+    if (threadIdx.x != 0) return;
+    const double nc = sqrt(v[0]), nb = sqrt(v[1]);
+    const double om = (nc > 1e-10 && nb > 1e-10) ? nc / nb : 1.0;
+    st->omega = om;
+    st->tau = st->eta / om;
+    st->sigma = st->eta * om;
+    st->k0 = 0;
+    st->t = 0;
+    st->restarts = 0;
+    st->done = 0;
+    st->status = PDHG_ITER_LIMIT;
+    st->restart_flag = 0;
+    st->checks = 0;
+}
+
+// x = clamp(0, lhat, uhat), y = 0, anchors = (x, y)
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_start_point(int n, int m, const V *__restrict__ lh, const V *__restrict__ uh,
+                                                       V *__restrict__ x, V *__restrict__ xa, V *__restrict__ y,
+                                                       V *__restrict__ ya)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
+        if (i < n) {
+            V v = (V)0;
+            v = v < lh[i] ? lh[i] : v;
+            v = v > uh[i] ? uh[i] : v;
+            x[i] = v;
+            xa[i] = v;
+        } else {
+            y[i - n] = (V)0;
+            ya[i - n] = (V)0;
+        }
+    }
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_copy_anchor(int n, int m, const V *__restrict__ x, V *__restrict__ xa,
+                                                       const V *__restrict__ y, V *__restrict__ ya)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
+        if (i < n) xa[i] = x[i];
+        else ya[i - n] = y[i - n];
+    }
+}
+
+template <typename V>
+static hipError_t phase_start(pdhg_solver *s, bool fresh_start)
+{
+    hipStream_t st = s->stream;
+    const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
+    if (fresh_start)
+        hipLaunchKernelGGL((k_start_point<V>), dim3(g), dim3(kBlock), 0, st, s->n, s->m, (const V *)s->lh,
+                           (const V *)s->uh, (V *)s->x, (V *)s->xa, (V *)s->y, (V *)s->ya);
+    else
+        hipLaunchKernelGGL((k_copy_anchor<V>), dim3(g), dim3(kBlock), 0, st, s->n, s->m, (const V *)s->x, (V *)s->xa,
+                           (const V *)s->y, (V *)s->ya);
+    const int nb = grid_for(s->n > s->m ? s->n : s->m, kBlock, kMaxRedBlocks);
+    hipLaunchKernelGGL((k_sumsq2<V>), dim3(nb), dim3(kBlock), 0, st, s->n, (const V *)s->ch, s->m, (const V *)s->bh,
+                       s->partials, nb);
+    hipLaunchKernelGGL(k_phase_start, dim3(1), dim3(kBlock), 0, st, s->st, s->partials, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_check(s, 0, 0); // anchor KKT parts of the start point
+}
+
+// 1 + ||b||_2 and 1 + ||c||_2 of the original model (relative tests)
+__global__ __launch_bounds__(kBlock) void k_set_norms(DevState *st, const double *__restrict__ part, int nblk)
+{
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+        v[0] += part[b];
+        v[1] += part[nblk + b];
+    }
+    block_reduce<2>(v, 0u);
+    if (threadIdx.x != 0) return;
+    st->nc1 = 1.0 + sqrt(v[0]);
+    st->nb1 = 1.0 + sqrt(v[1]);
+}
+
+hipError_t init_norms(pdhg_solver *s)
+{
+    const int nb = grid_for(s->n > s->m ? s->n : s->m, kBlock, kMaxRedBlocks);
+    hipLaunchKernelGGL((k_sumsq2<double>), dim3(nb), dim3(kBlock), 0, s->stream, s->n, s->c, s->m, s->b, s->partials, nb);
+    hipLaunchKernelGGL(k_set_norms, dim3(1), dim3(kBlock), 0, s->stream, s->st, s->partials, nb);
+    return hipGetLastError();
+}
+
+hipError_t init_iteration(pdhg_solver *s)
+{
+    return s->fp32 ? phase_start<float>(s, true) : phase_start<double>(s, true);
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_copy2(int n, int m, const V *__restrict__ a, V *__restrict__ ac,
+                                                 const V *__restrict__ b, V *__restrict__ bc)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
+        if (i < n) ac[i] = a[i];
+        else bc[i - n] = b[i - n];
+    }
+}
+
+// (xp, yp) <- (x, y): the candidate of a phase that has not reached a check
+hipError_t candidate_from_iterate(pdhg_solver *s)
+{
+    const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
+    if (s->fp32)
+        hipLaunchKernelGGL((k_copy2<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, (const float *)s->x,
+                           (float *)s->xp, (const float *)s->y, (float *)s->yp);
+    else
+        hipLaunchKernelGGL((k_copy2<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, (const double *)s->x,
+                           (double *)s->xp, (const double *)s->y, (double *)s->yp);
+    return hipGetLastError();
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_unscale(int n, int m, const double *__restrict__ dc,
+                                                   const double *__restrict__ dr, const V *__restrict__ xh,
+                                                   const V *__restrict__ yh, double *__restrict__ xo,
+                                                   double *__restrict__ yo)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
+        if (i < n) {
+            if (xo) xo[i] = dc[i] * (double)xh[i];
+        } else {
+            if (yo) yo[i - n] = dr[i - n] * (double)yh[i - n];
+        }
+    }
+}
+
+hipError_t unscale(pdhg_solver *s, const void *xh, const void *yh, double *xo, double *yo)
+{
+    const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
+    if (s->fp32)
+        hipLaunchKernelGGL((k_unscale<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->dc, s->dr,
+                           (const float *)xh, (const float *)yh, xo, yo);
+    else
+        hipLaunchKernelGGL((k_unscale<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->dc, s->dr,
+                           (const double *)xh, (const double *)yh, xo, yo);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- KKT report ---
+// rows: rP (original senses), its inf-norm, b'y, slack counts
+__global__ __launch_bounds__(kBlock) void k_report_rows(int m, const double *__restrict__ b, const int8_t *__restrict__ s0,
+                                                       const double *__restrict__ ax, const double *__restrict__ y,
+                                                       double *__restrict__ part, int nblk)
+{
+    const double tol = 1e-6;
+    double v[6] = {0, 0, 0, 0, 0, 0}; // P2, PINF, BTY, POFF, DZERO, CAND
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+        double r = b[i] - ax[i];
+        const int8_t sn = s0[i];
+        if (sn == '<') r = r < 0.0 ? r : 0.0;
+        else if (sn == '>') r = r > 0.0 ? r : 0.0;
+        v[0] += r * r;
+        v[1] = fmax(v[1], fabs(r));
+        v[2] += b[i] * y[i];
+        if (sn != '=') {
+            const double slack = (sn == '<') ? (b[i] - ax[i]) : (ax[i] - b[i]);
+            const double zs = (sn == '<') ? -y[i] : y[i];
+            const bool off = slack > tol;
+            v[3] += off ? 1.0 : 0.0;
+            v[4] += fabs(zs) <= tol ? 1.0 : 0.0;
+            v[5] += (off && fabs(zs) < tol) ? 1.0 : 0.0;
+        }
+    }
+    block_reduce<6>(v, 1u << 1);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 6; q++) part[q * nblk + blockIdx.x] = v[q];
+}
+
+// columns: z split, rD, c'x, bound terms of the dual objective, counts
+__global__ __launch_bounds__(kBlock) void k_report_cols(int n, const double *__restrict__ c, const double *__restrict__ l,
+                                                       const double *__restrict__ u, const double *__restrict__ aty,
+                                                       const double *__restrict__ x, double *__restrict__ zout,
+                                                       double *__restrict__ part, int nblk)
+{
+    const double tol = 1e-6;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // D2, DINF, CTX, BND, POFF, DZERO, CAND, unused
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        const double lam = c[j] - aty[j];
+        const double zp = (!is_inf_lo(l[j]) && lam > 0.0) ? lam : 0.0;
+        const double zm = (!is_inf_up(u[j]) && lam < 0.0) ? -lam : 0.0;
+        const double z = zp - zm;
+        const double rd = lam - z;
+        v[0] += rd * rd;
+        v[1] = fmax(v[1], fabs(rd));
+        v[2] += c[j] * x[j];
+        if (zp > 0.0) v[3] += l[j] * zp;
+        if (zm > 0.0) v[3] -= u[j] * zm;
+        const double zc = z;
+        const bool off = (x[j] - l[j] > tol) && (u[j] - x[j] > tol);
+        v[4] += off ? 1.0 : 0.0;
+        v[5] += fabs(zc) <= tol ? 1.0 : 0.0;
+        v[6] += (off && fabs(zc) < tol) ? 1.0 : 0.0;
+        if (zout) zout[j] = z;
+    }
+    block_reduce<8>(v, 1u << 1);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 8; q++) part[q * nblk + blockIdx.x] = v[q];
+}
+
+__global__ __launch_bounds__(kBlock) void k_report_final(const double *__restrict__ pr, int gm, const double *__restrict__ pc,
+                                                        int gn, double *__restrict__ out)
+{
+    double v[13];
+#pragma unroll
+    for (int q = 0; q < 6; q++) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < gm; b += kBlock) acc = (q == 1) ? fmax(acc, pr[q * gm + b]) : acc + pr[q * gm + b];
+        v[q] = acc;
+    }
+#pragma unroll
+    for (int q = 0; q < 7; q++) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < gn; b += kBlock) acc = (q == 1) ? fmax(acc, pc[q * gn + b]) : acc + pc[q * gn + b];
+        v[6 + q] = acc;
+    }
+    block_reduce<13>(v, (1u << 1) | (1u << 7));
+    if (threadIdx.x != 0) return;
+    // rows: P2 PINF BTY POFF DZERO CAND | cols: D2 DINF CTX BND POFF DZERO CAND
+    out[R_P2] = v[0];
+    out[R_PINF] = v[1];
+    out[R_BTY] = v[2];
+    out[R_D2] = v[6];
+    out[R_DINF] = v[7];
+    out[R_CTX] = v[8];
+    out[R_BND] = v[9];
+    out[R_POFF] = v[3] + v[10];
+    out[R_DZERO] = v[4] + v[11];
+    out[R_CAND] = v[5] + v[12];
+}
+
+hipError_t report(pdhg_solver *s, const double *x, const double *y, double *z, pdhg_kkt_report *k)
+{
+    hipStream_t st = s->stream;
+    spmv<double, double, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, s->av, x, s->ax);
+    spmv<double, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, s->atv, y, s->aty);
+    const int gm = s->red_blocks_m, gn = s->red_blocks_n;
+    double *pr = s->partials;
+    double *pc = s->partials + (size_t)6 * gm;
+    hipLaunchKernelGGL(k_report_rows, dim3(gm), dim3(kBlock), 0, st, s->m, s->b, s->sense0, s->ax, y, pr, gm);
+    hipLaunchKernelGGL(k_report_cols, dim3(gn), dim3(kBlock), 0, st, s->n, s->c, s->l, s->u, s->aty, x, z, pc, gn);
+    hipLaunchKernelGGL(k_report_final, dim3(1), dim3(kBlock), 0, st, pr, gm, pc, gn, s->redout);
+    hipMemcpyAsync(s->rep_host, s->redout, sizeof(double) * R_COUNT, hipMemcpyDeviceToHost, st);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    const double *v = s->rep_host;
+    const double nb1 = s->st_host->nb1, nc1 = s->st_host->nc1;
+    k->rp2 = sqrt(v[R_P2]);
+    k->rd2 = sqrt(v[R_D2]);
+    k->rpinf = v[R_PINF];
+    k->rdinf = v[R_DINF];
+    k->pobj = v[R_CTX];
+    k->dobj = v[R_BTY] + v[R_BND];
+    k->gap = k->pobj - k->dobj;
+    k->rel_p = k->rp2 / nb1;
+    k->rel_d = k->rd2 / nc1;
+    k->rel_gap = fabs(k->gap) / (1.0 + fabs(k->pobj) + fabs(k->dobj));
+    k->p_off = (int64_t)v[R_POFF];
+    k->d_zero = (int64_t)v[R_DZERO];
+    k->candidates = (int64_t)v[R_CAND];
+    k->est_primal = k->p_off > s->m ? k->p_off - s->m : 0;
+    k->est_dual = s->m > k->d_zero ? s->m - k->d_zero : 0;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- corner push ---
+// splitmix64 (Steele, Lea and Flood 2014)
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// Algorithm 1 on the columns: ub_j <- x_j if z_j > eps_abs, lb_j <- x_j if
+// z_j < -eps_abs (bounds stored scaled: the scaled solve candidate itself),
+// objective Uniform[0,1) scaled like c, start x at the solve's x.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_push_cols(int n, const double *__restrict__ z, const V *__restrict__ xs,
+                                                     const double *__restrict__ dc, double eps_abs, uint64_t seed,
+                                                     double scale, V *__restrict__ lh, V *__restrict__ uh,
+                                                     V *__restrict__ ch, V *__restrict__ x, double *__restrict__ part,
+                                                     int nblk)
+{
+    double v[2] = {0.0, 0.0}; // fixes at the lower, upper side
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        const V xv = xs[j];
+        if (z[j] > eps_abs) {
+            uh[j] = xv;
+            v[1] += 1.0;
+        } else if (z[j] < -eps_abs) {
+            lh[j] = xv;
+            v[0] += 1.0;
+        }
+        const uint64_t h = splitmix64(seed ^ ((uint64_t)j * 0x9E3779B97F4A7C15ULL));
+        const double uni = (double)(h >> 11) * (1.0 / 9007199254740992.0);
+        ch[j] = (V)(dc[j] * (scale * uni));
+        x[j] = xv;
+    }
+    block_reduce<2>(v, 0u);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v[0];
+        part[nblk + blockIdx.x] = v[1];
+    }
+}
+
+// inequality rows whose slack reduced cost is non-trivial become equalities; y = 0
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_push_rows(int m, const double *__restrict__ yu, double eps_abs,
+                                                     int8_t *__restrict__ sense, V *__restrict__ y,
+                                                     double *__restrict__ part)
+{
+    double v[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+        const int8_t sn = sense[i];
+        if ((sn == '<' && yu[i] < -eps_abs) || (sn == '>' && yu[i] > eps_abs)) {
+            sense[i] = '=';
+            v[0] += 1.0;
+        }
+        y[i] = (V)0;
+    }
+    block_reduce<1>(v, 0u);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum3(const double *__restrict__ p, int n0, int n1, double *__restrict__ out)
+{
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < n0; b += kBlock) {
+        v[0] += p[b];
+        v[1] += p[n0 + b];
+    }
+    for (int b = threadIdx.x; b < n1; b += kBlock) v[2] += p[2 * n0 + b];
+    block_reduce<3>(v, 0u);
+    if (threadIdx.x == 0) {
+        out[0] = v[0];
+        out[1] = v[1];
+        out[2] = v[2];
+    }
+}
+
+template <typename V>
+static hipError_t push_setup_impl(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
+{
+    hipStream_t st = s->stream;
+    const int gn = s->red_blocks_n, gm = s->red_blocks_m;
+    double *pcnt = s->partials + (size_t)(Q_COUNT + 1) * (gm + gn); // past the check slots
+    hipLaunchKernelGGL((k_push_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->zsol, (const V *)s->xs, s->dc,
+                       s->p.eps_abs, seed, s->p.push_obj_scale, (V *)s->lh, (V *)s->uh, (V *)s->ch, (V *)s->x, pcnt,
+                       gn);
+    hipLaunchKernelGGL((k_push_rows<V>), dim3(gm), dim3(kBlock), 0, st, s->m, s->yu, s->p.eps_abs, s->sense, (V *)s->y,
+                       pcnt + 2 * gn);
+    hipLaunchKernelGGL(k_sum3, dim3(1), dim3(kBlock), 0, st, pcnt, gn, gm, s->redout);
+    hipMemcpyAsync(s->rep_host, s->redout, 3 * sizeof(double), hipMemcpyDeviceToHost, st);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    r->n_fix_lower = (int64_t)s->rep_host[0];
+    r->n_fix_upper = (int64_t)s->rep_host[1];
+    r->n_rows_to_eq = (int64_t)s->rep_host[2];
+    return phase_start<V>(s, false);
+}
+
+hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
+{
+    return s->fp32 ? push_setup_impl<float>(s, seed, r) : push_setup_impl<double>(s, seed, r);
+}
+
+} // namespace pdhg

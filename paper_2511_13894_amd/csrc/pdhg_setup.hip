@@ -1,0 +1,420 @@
+// Setup on the device: explicit transpose of A, Ruiz + Pock-Chambolle
+// scaling, and the power iteration that sets the step size.
+#include "pdhg_device.hpp"
+#include "pdhg_internal.hpp"
+
+namespace pdhg {
+
+// ---------------------------------------------------------------- transpose
+// row id of every entry (one wave per row, lanes stride the row)
+__global__ __launch_bounds__(kBlock) void k_rowid(int m, const int *__restrict__ rp, int *__restrict__ rowid)
+{
+    const int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w >= m) return;
+    for (int e = rp[w] + lane; e < rp[w + 1]; e += 64) rowid[e] = (int)w;
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_cols(int nnz, const int *__restrict__ ci, int *__restrict__ cnt)
+{
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kBlock)
+        atomicAdd(&cnt[ci[e]], 1);
+}
+
+// exclusive scan of cnt[0..len) into out[0..len] in three passes:
+// per-block scans with block totals, a scan of the totals, and the offsets.
+constexpr int kScanItems = 4; // items per thread
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ int block_exclusive_scan(int v, int *total)
+{
+    __shared__ int wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int w = 0; w < kBlock / 64; w++) {
+        if (w < wid) base += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(int len, const int *__restrict__ in, int *__restrict__ out,
+                                                      int *__restrict__ tile_sums)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int vals[kScanItems];
+    int local = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; q++) {
+        vals[q] = (base + q < len) ? in[base + q] : 0;
+        local += vals[q];
+    }
+    int total;
+    int excl = block_exclusive_scan(local, &total);
+#pragma unroll
+    for (int q = 0; q < kScanItems; q++) {
+        if (base + q < len) out[base + q] = excl;
+        excl += vals[q];
+    }
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// one workgroup scans the tile totals sequentially in chunks of kBlock
+__global__ __launch_bounds__(kBlock) void k_scan_totals(int tiles, int *__restrict__ tile_sums, int *__restrict__ grand)
+{
+    int carry = 0;
+    for (int base = 0; base < tiles; base += kBlock) {
+        int i = base + threadIdx.x;
+        int v = i < tiles ? tile_sums[i] : 0;
+        int total;
+        int excl = block_exclusive_scan(v, &total);
+        if (i < tiles) tile_sums[i] = carry + excl;
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *grand = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(int len, int *__restrict__ out, const int *__restrict__ tile_sums)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) out[i] += tile_sums[i / kScanTile];
+}
+
+__global__ void k_set_last(int *out, int len, const int *grand) { out[len] = *grand; }
+
+// place every entry of A into its transpose row (order inside a row is
+// arbitrary here; k_rank_sort makes it ascending by row index)
+__global__ __launch_bounds__(kBlock) void k_scatter(int nnz, const int *__restrict__ ci, const int *__restrict__ rowid,
+                                                   int *__restrict__ cursor, int *__restrict__ ti_u,
+                                                   int *__restrict__ perm_u)
+{
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kBlock) {
+        int pos = atomicAdd(&cursor[ci[e]], 1);
+        ti_u[pos] = rowid[e];
+        perm_u[pos] = (int)e;
+    }
+}
+
+// rows inside a transpose row are distinct, so an entry's sorted position is
+// the number of smaller row indices in its segment: a deterministic order
+__global__ __launch_bounds__(kBlock) void k_rank_sort(int nnz, const int *__restrict__ ci, const int *__restrict__ tp,
+                                                     const int *__restrict__ ti_u, const int *__restrict__ perm_u,
+                                                     int *__restrict__ ti, int *__restrict__ tperm)
+{
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * kBlock) {
+        const int e = perm_u[p];
+        const int j = ci[e];
+        const int beg = tp[j], end = tp[j + 1];
+        const int key = ti_u[p];
+        int rank = 0;
+        for (int q = beg; q < end; q++) rank += ti_u[q] < key;
+        ti[beg + rank] = key;
+        tperm[beg + rank] = e;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather(int nnz, const int *__restrict__ perm, const double *__restrict__ src,
+                                                  T *__restrict__ dst)
+{
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * kBlock)
+        dst[p] = (T)src[perm[p]];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_convert(int64_t len, const double *__restrict__ src, T *__restrict__ dst)
+{
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < len; p += (int64_t)gridDim.x * kBlock)
+        dst[p] = (T)src[p];
+}
+
+static hipError_t exclusive_scan(hipStream_t st, int len, const int *in, int *out, int *work)
+{
+    // out has len+1 entries; work holds ceil(len/kScanTile) + 1 ints
+    const int tiles = (len + kScanTile - 1) / kScanTile;
+    if (len > 0) {
+        hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kBlock), 0, st, len, in, out, work);
+        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, st, tiles, work, work + tiles);
+        hipLaunchKernelGGL(k_scan_add, dim3((len + kBlock - 1) / kBlock), dim3(kBlock), 0, st, len, out, work);
+        hipLaunchKernelGGL(k_set_last, dim3(1), dim3(1), 0, st, out, len, work + tiles);
+    } else {
+        hipMemsetAsync(out, 0, sizeof(int), st);
+    }
+    return hipGetLastError();
+}
+
+hipError_t build_transpose(pdhg_solver *s)
+{
+    hipStream_t st = s->stream;
+    const int m = s->m, n = s->n, nnz = s->nnz;
+    const int tiles = (n + kScanTile - 1) / kScanTile;
+    int *rowid = nullptr, *cnt = nullptr, *ti_u = nullptr, *perm_u = nullptr, *work = nullptr;
+    hipError_t e = hipSuccess;
+    size_t nz = (size_t)(nnz > 0 ? nnz : 1);
+    if ((e = hipMalloc(&rowid, nz * sizeof(int))) != hipSuccess) return e;
+    if ((e = hipMalloc(&cnt, (size_t)(n + 1) * sizeof(int))) != hipSuccess) return e;
+    if ((e = hipMalloc(&ti_u, nz * sizeof(int))) != hipSuccess) return e;
+    if ((e = hipMalloc(&perm_u, nz * sizeof(int))) != hipSuccess) return e;
+    if ((e = hipMalloc(&work, (size_t)(tiles + 2) * sizeof(int))) != hipSuccess) return e;
+    hipMemsetAsync(cnt, 0, (size_t)(n + 1) * sizeof(int), st);
+    const int big = grid_for(nnz, kBlock, 65536);
+    if (m > 0) hipLaunchKernelGGL(k_rowid, dim3(grid_for((int64_t)m * 64, kBlock, 1 << 30)), dim3(kBlock), 0, st, m, s->rp, rowid);
+    if (nnz > 0) hipLaunchKernelGGL(k_count_cols, dim3(big), dim3(kBlock), 0, st, nnz, s->ci, cnt);
+    exclusive_scan(st, n, cnt, s->tp, work);
+    // cursor = copy of the row starts
+    hipMemcpyAsync(cnt, s->tp, (size_t)(n + 1) * sizeof(int), hipMemcpyDeviceToDevice, st);
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(big), dim3(kBlock), 0, st, nnz, s->ci, rowid, cnt, ti_u, perm_u);
+        hipLaunchKernelGGL(k_rank_sort, dim3(big), dim3(kBlock), 0, st, nnz, s->ci, s->tp, ti_u, perm_u, s->ti, s->tperm);
+        hipLaunchKernelGGL((k_gather<double>), dim3(big), dim3(kBlock), 0, st, nnz, s->tperm, s->av, s->atv);
+    }
+    e = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(st);
+    hipFree(rowid);
+    hipFree(cnt);
+    hipFree(ti_u);
+    hipFree(perm_u);
+    hipFree(work);
+    return e != hipSuccess ? e : e2;
+}
+
+// ----------------------------------------------------------------- scaling
+// per-row reduction over L lanes: MODE 0 max|a|, MODE 1 sum |a|^p
+template <int L, int MODE>
+__global__ __launch_bounds__(kBlock) void k_row_norm(int rows, const int *__restrict__ ptr,
+                                                    const double *__restrict__ val, double p,
+                                                    double *__restrict__ out)
+{
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t row = g / L;
+    const int lane = (int)(g % L);
+    if (row >= rows) return;
+    double acc = 0.0;
+    for (int e = ptr[row] + lane; e < ptr[row + 1]; e += L) {
+        double a = fabs(val[e]);
+        if (MODE == 0) acc = fmax(acc, a);
+        else acc += (p == 1.0) ? a : pow(a, p);
+    }
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) {
+        double o = __shfl_xor(acc, off, L);
+        acc = (MODE == 0) ? fmax(acc, o) : acc + o;
+    }
+    if (lane == 0) out[row] = acc > 0.0 ? sqrt(acc) : 1.0;
+}
+
+template <int MODE>
+static void row_norm(hipStream_t st, int lanes, int rows, const int *ptr, const double *val, double p, double *out)
+{
+    if (rows <= 0) return;
+    const int grid = (int)(((int64_t)rows * lanes + kBlock - 1) / kBlock);
+#define PDHG_RN_CASE(LL)                                                                                    \
+    case LL:                                                                                                \
+        hipLaunchKernelGGL((k_row_norm<LL, MODE>), dim3(grid), dim3(kBlock), 0, st, rows, ptr, val, p, out); \
+        break;
+    switch (lanes) {
+        PDHG_RN_CASE(1)
+        PDHG_RN_CASE(2)
+        PDHG_RN_CASE(4)
+        PDHG_RN_CASE(8)
+        PDHG_RN_CASE(16)
+        PDHG_RN_CASE(32)
+    default:
+        PDHG_RN_CASE(64)
+    }
+#undef PDHG_RN_CASE
+}
+
+// Ahat_e <- Ahat_e / (r_i q_j) for entry e = (i, j)
+__global__ __launch_bounds__(kBlock) void k_apply_scale(int nnz, const int *__restrict__ rowid,
+                                                       const int *__restrict__ ci, double *__restrict__ val,
+                                                       const double *__restrict__ r, const double *__restrict__ q)
+{
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kBlock)
+        val[e] = val[e] / (r[rowid[e]] * q[ci[e]]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_div_vec(int len, double *__restrict__ d, const double *__restrict__ r)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) d[i] = d[i] / r[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(int64_t len, double *__restrict__ d, double v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += (int64_t)gridDim.x * kBlock) d[i] = v;
+}
+
+// scaled data: chat = Dc c, bhat = Dr b, lhat = l / Dc, uhat = u / Dc
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_scaled_cols(int n, const double *__restrict__ dc, const double *__restrict__ c,
+                                                       const double *__restrict__ l, const double *__restrict__ u,
+                                                       V *__restrict__ ch, V *__restrict__ lh, V *__restrict__ uh)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    ch[j] = (V)(dc[j] * c[j]);
+    lh[j] = (V)(l[j] / dc[j]);
+    uh[j] = (V)(u[j] / dc[j]);
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_scaled_rows(int m, const double *__restrict__ dr, const double *__restrict__ b,
+                                                       const int8_t *__restrict__ s0, V *__restrict__ bh,
+                                                       int8_t *__restrict__ sense)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    bh[i] = (V)(dr[i] * b[i]);
+    sense[i] = s0[i];
+}
+
+template <typename V>
+static void make_scaled(pdhg_solver *s, const double *ahat64)
+{
+    hipStream_t st = s->stream;
+    const int big = grid_for(s->nnz, kBlock, 65536);
+    if (s->nnz > 0) {
+        hipLaunchKernelGGL((k_convert<V>), dim3(big), dim3(kBlock), 0, st, (int64_t)s->nnz, ahat64, (V *)s->ahat);
+        hipLaunchKernelGGL((k_gather<V>), dim3(big), dim3(kBlock), 0, st, s->nnz, s->tperm, ahat64, (V *)s->ahat_t);
+    }
+    if (s->n > 0)
+        hipLaunchKernelGGL((k_scaled_cols<V>), dim3(grid_for(s->n, kBlock, 1 << 30)), dim3(kBlock), 0, st, s->n, s->dc,
+                           s->c, s->l, s->u, (V *)s->ch, (V *)s->lh, (V *)s->uh);
+    if (s->m > 0)
+        hipLaunchKernelGGL((k_scaled_rows<V>), dim3(grid_for(s->m, kBlock, 1 << 30)), dim3(kBlock), 0, st, s->m, s->dr,
+                           s->b, s->sense0, (V *)s->bh, s->sense);
+}
+
+hipError_t scale_problem(pdhg_solver *s)
+{
+    hipStream_t st = s->stream;
+    const int m = s->m, n = s->n, nnz = s->nnz;
+    double *ah = nullptr, *aht = nullptr, *r = nullptr, *q = nullptr;
+    int *rowid = nullptr;
+    hipError_t e;
+    size_t nz = (size_t)(nnz > 0 ? nnz : 1);
+    if ((e = hipMalloc(&ah, nz * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(&aht, nz * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(&r, (size_t)(m > 0 ? m : 1) * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(&q, (size_t)(n > 0 ? n : 1) * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(&rowid, nz * sizeof(int))) != hipSuccess) return e;
+    hipMemcpyAsync(ah, s->av, (size_t)nnz * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (m > 0) hipLaunchKernelGGL(k_rowid, dim3(grid_for((int64_t)m * 64, kBlock, 1 << 30)), dim3(kBlock), 0, st, m, s->rp, rowid);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(m, kBlock, 4096)), dim3(kBlock), 0, st, (int64_t)m, s->dr, 1.0);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, st, (int64_t)n, s->dc, 1.0);
+    const int big = grid_for(nnz, kBlock, 65536);
+    const int gm = grid_for(m, kBlock, 1 << 30), gn = grid_for(n, kBlock, 1 << 30);
+    auto pass = [&](int mode, double alpha) {
+        // row statistics over A's rows, column statistics over the transpose's rows
+        if (nnz > 0) hipLaunchKernelGGL((k_gather<double>), dim3(big), dim3(kBlock), 0, st, nnz, s->tperm, ah, aht);
+        if (mode == 0) {
+            row_norm<0>(st, s->lanes_a, m, s->rp, ah, 1.0, r);
+            row_norm<0>(st, s->lanes_at, n, s->tp, aht, 1.0, q);
+        } else {
+            row_norm<1>(st, s->lanes_a, m, s->rp, ah, 2.0 - alpha, r);
+            row_norm<1>(st, s->lanes_at, n, s->tp, aht, alpha, q);
+        }
+        if (nnz > 0) hipLaunchKernelGGL(k_apply_scale, dim3(big), dim3(kBlock), 0, st, nnz, rowid, s->ci, ah, r, q);
+        if (m > 0) hipLaunchKernelGGL(k_div_vec, dim3(gm), dim3(kBlock), 0, st, m, s->dr, r);
+        if (n > 0) hipLaunchKernelGGL(k_div_vec, dim3(gn), dim3(kBlock), 0, st, n, s->dc, q);
+    };
+    for (int it = 0; it < s->p.ruiz_iters; it++) pass(0, 0.0);
+    if (s->p.pc_alpha >= 0.0) pass(1, s->p.pc_alpha);
+    if (s->fp32) make_scaled<float>(s, ah);
+    else make_scaled<double>(s, ah);
+    e = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(st);
+    hipFree(ah);
+    hipFree(aht);
+    hipFree(r);
+    hipFree(q);
+    hipFree(rowid);
+    return e != hipSuccess ? e : e2;
+}
+
+// --------------------------------------------------------- power iteration
+// partial sums of w_j^2 per block
+__global__ __launch_bounds__(kBlock) void k_sumsq_partials(int len, const double *__restrict__ w, double *__restrict__ part)
+{
+    double v[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += (int64_t)gridDim.x * kBlock)
+        v[0] += w[i] * w[i];
+    block_reduce<1>(v, 0u);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// lambda = sqrt(sum of partials), fixed order; out[0] = lambda
+__global__ __launch_bounds__(kBlock) void k_finish_norm(int nparts, const double *__restrict__ part, double *__restrict__ out)
+{
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < nparts; i += kBlock) v[0] += part[i];
+    block_reduce<1>(v, 0u);
+    if (threadIdx.x == 0) out[0] = sqrt(v[0]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_normalize(int len, const double *__restrict__ w, const double *__restrict__ lam,
+                                                     double *__restrict__ v)
+{
+    const double l = lam[0];
+    if (!(l > 0.0)) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) v[i] = w[i] / l;
+}
+
+__global__ void k_set_step(pdhg::DevState *st, const double *lam, int iters_done, double safety)
+{
+    double l = lam[0];
+    double sig = (iters_done > 0 && l > 0.0) ? sqrt(l) : 0.0;
+    st->sigma_est = sig;
+    st->eta = sig > 1e-12 ? safety / sig : safety;
+}
+
+hipError_t power_iteration(pdhg_solver *s)
+{
+    hipStream_t st = s->stream;
+    const int m = s->m, n = s->n;
+    double *v = nullptr, *w = nullptr, *u = nullptr, *lam = nullptr;
+    hipError_t e;
+    if ((e = hipMalloc(&v, (size_t)(n > 0 ? n : 1) * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(&w, (size_t)(n > 0 ? n : 1) * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(&u, (size_t)(m > 0 ? m : 1) * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(&lam, 2 * sizeof(double))) != hipSuccess) return e;
+    hipMemsetAsync(lam, 0, 2 * sizeof(double), st);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, st, (int64_t)n, v,
+                       n > 0 ? 1.0 / sqrt((double)n) : 0.0);
+    const int gn = grid_for(n, kBlock, kMaxRedBlocks);
+    for (int it = 0; it < s->p.power_iters && n > 0; it++) {
+        if (s->fp32) {
+            spmv<float, double, double, double>(st, s->lanes_a, m, s->rp, s->ci, (const float *)s->ahat, v, u);
+            spmv<float, double, double, double>(st, s->lanes_at, n, s->tp, s->ti, (const float *)s->ahat_t, u, w);
+        } else {
+            spmv<double, double, double, double>(st, s->lanes_a, m, s->rp, s->ci, (const double *)s->ahat, v, u);
+            spmv<double, double, double, double>(st, s->lanes_at, n, s->tp, s->ti, (const double *)s->ahat_t, u, w);
+        }
+        hipLaunchKernelGGL(k_sumsq_partials, dim3(gn), dim3(kBlock), 0, st, n, w, s->partials);
+        hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(kBlock), 0, st, gn, s->partials, lam);
+        hipLaunchKernelGGL(k_normalize, dim3(grid_for(n, kBlock, 1 << 30)), dim3(kBlock), 0, st, n, w, lam, v);
+    }
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, st, s->st, lam, s->p.power_iters, s->p.eta_safety);
+    e = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(st);
+    hipFree(v);
+    hipFree(w);
+    hipFree(u);
+    hipFree(lam);
+    return e != hipSuccess ? e : e2;
+}
+
+} // namespace pdhg

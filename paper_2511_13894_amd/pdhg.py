@@ -1,0 +1,226 @@
+"""Python binding of libpdhg.so (ctypes; argument marshalling only).
+
+Every entry point of include/pdhg.h is reachable under the same name; all
+arithmetic runs in the library's HIP kernels.  The binding refuses to fall
+back to anything else: if the library is missing it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+from typing import Optional
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().parent / "libpdhg.so"
+
+STATUS = {0: "OPTIMAL", 1: "ITER_LIMIT", 2: "NUMERICAL", 3: "PUSH_DONE", 4: "TIME_LIMIT"}
+PDHG_OPTIMAL, PDHG_ITER_LIMIT, PDHG_NUMERICAL, PDHG_PUSH_DONE, PDHG_TIME_LIMIT = range(5)
+PDHG_FP64, PDHG_FP32_MIXED = 0, 1
+ERRORS = {-1: "INVALID_ARG", -2: "STATE", -3: "OOM", -4: "HIP"}
+
+
+class PdhgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("eps_rel", C.c_double), ("eps_abs", C.c_double), ("max_iter", C.c_int64),
+        ("check_every", C.c_int32), ("ruiz_iters", C.c_int32),
+        ("restart_suff", C.c_double), ("restart_nec", C.c_double), ("restart_art", C.c_double),
+        ("pw_smooth", C.c_double), ("pc_alpha", C.c_double),
+        ("power_iters", C.c_int32), ("halpern", C.c_int32),
+        ("eta_safety", C.c_double), ("reflect_gamma", C.c_double),
+        ("push_min_iters", C.c_int32), ("precision", C.c_int32),
+        ("push_obj_scale", C.c_double), ("push_max_iter", C.c_int64), ("time_limit", C.c_double),
+        ("stream", C.c_void_p), ("verbosity", C.c_int32), ("lanes_at", C.c_int32), ("lanes_a", C.c_int32),
+        ("use_graph", C.c_int32),
+    ]
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("pad_", C.c_int32), ("iters", C.c_int64), ("restarts", C.c_int64),
+        ("rel_p", C.c_double), ("rel_d", C.c_double), ("rel_gap", C.c_double),
+        ("pobj", C.c_double), ("dobj", C.c_double), ("seconds", C.c_double),
+    ]
+
+
+class KKTReport(C.Structure):
+    _fields_ = [
+        ("rp2", C.c_double), ("rd2", C.c_double), ("rpinf", C.c_double), ("rdinf", C.c_double),
+        ("pobj", C.c_double), ("dobj", C.c_double), ("gap", C.c_double),
+        ("rel_p", C.c_double), ("rel_d", C.c_double), ("rel_gap", C.c_double),
+        ("p_off", C.c_int64), ("d_zero", C.c_int64), ("candidates", C.c_int64),
+        ("est_primal", C.c_int64), ("est_dual", C.c_int64),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class PushResult(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("pad_", C.c_int32), ("iters", C.c_int64), ("restarts", C.c_int64),
+        ("n_fix_lower", C.c_int64), ("n_fix_upper", C.c_int64), ("n_rows_to_eq", C.c_int64),
+        ("rel_p_push", C.c_double), ("seconds", C.c_double), ("before", KKTReport), ("after", KKTReport),
+    ]
+
+
+EXPORTS = ["pdhg_default_params", "pdhg_create", "pdhg_solve", "pdhg_iterate", "pdhg_corner_push", "pdhg_kkt",
+           "pdhg_get_solution", "pdhg_get_iterate", "pdhg_get_scaling", "pdhg_destroy", "pdhg_last_error",
+           "pdhg_struct_size"]
+
+_lib = None
+
+
+def load(path: Optional[Path] = None):
+    """Load libpdhg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = Path(path) if path else LIB_PATH
+    if not p.exists():
+        raise RuntimeError(f"{p} is not built; run __graft_entry__.build() (hipcc for gfx950) first")
+    lib = C.CDLL(str(p))
+    P = C.POINTER
+    dp = P(C.c_double)
+    lib.pdhg_default_params.argtypes = [P(Params)]
+    lib.pdhg_default_params.restype = None
+    lib.pdhg_create.argtypes = [C.c_int32, C.c_int32, C.c_int64, P(C.c_int64), P(C.c_int32), dp, dp, dp, dp, dp,
+                                C.c_char_p, P(Params), P(C.c_void_p)]
+    lib.pdhg_solve.argtypes = [C.c_void_p, P(Result)]
+    lib.pdhg_iterate.argtypes = [C.c_void_p, C.c_int64, P(Result)]
+    lib.pdhg_corner_push.argtypes = [C.c_void_p, C.c_uint64, P(PushResult)]
+    lib.pdhg_kkt.argtypes = [C.c_void_p, dp, dp, P(KKTReport)]
+    lib.pdhg_get_solution.argtypes = [C.c_void_p, dp, dp, dp]
+    lib.pdhg_get_iterate.argtypes = [C.c_void_p, dp, dp]
+    lib.pdhg_get_scaling.argtypes = [C.c_void_p, dp, dp, dp]
+    lib.pdhg_destroy.argtypes = [C.c_void_p]
+    lib.pdhg_destroy.restype = None
+    lib.pdhg_last_error.restype = C.c_char_p
+    lib.pdhg_struct_size.restype = C.c_int32
+    lib.pdhg_struct_size.argtypes = [C.c_int32]
+    for fn in ("pdhg_create", "pdhg_solve", "pdhg_iterate", "pdhg_corner_push", "pdhg_kkt", "pdhg_get_solution",
+               "pdhg_get_iterate", "pdhg_get_scaling"):
+        getattr(lib, fn).restype = C.c_int
+    sizes = [C.sizeof(Params), C.sizeof(Result), C.sizeof(KKTReport), C.sizeof(PushResult)]
+    for which, want in enumerate(sizes):
+        got = lib.pdhg_struct_size(which)
+        if got != want:
+            raise RuntimeError(f"struct {which} size mismatch: library {got}, binding {want}")
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    load().pdhg_default_params(C.byref(p))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": PDHG_FP64, "fp32": PDHG_FP32_MIXED, "fp32_mixed": PDHG_FP32_MIXED}[v]
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _refuse_second_runtime():
+    """libpdhg.so runs on the system ROCm HIP runtime.  torch wheels bundle a
+    second copy of the HIP/HSA runtime; once torch has initialised it, the
+    device is not visible to another runtime in the same process."""
+    import sys
+
+    t = sys.modules.get("torch")
+    if t is not None:
+        try:
+            if t.cuda.is_initialized():
+                raise RuntimeError("torch has initialised its bundled HIP runtime in this process; "
+                                   "libpdhg.so needs the GPU through the system ROCm runtime "
+                                   "(use a process without torch GPU calls)")
+        except AttributeError:
+            pass
+
+
+class Solver:
+    """One LP on the GPU (pdhg_create ... pdhg_destroy)."""
+
+    def __init__(self, lp, stream=None, **params):
+        _refuse_second_runtime()
+        self.lib = load()
+        self.m, self.n = int(lp.m), int(lp.n)
+        self.params = default_params(**params)
+        self.params.stream = stream.value if isinstance(stream, C.c_void_p) else stream
+        rp = np.ascontiguousarray(lp.row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(lp.col, dtype=np.int32)
+        va = np.ascontiguousarray(lp.val, dtype=np.float64)
+        b = np.ascontiguousarray(lp.b, dtype=np.float64)
+        c = np.ascontiguousarray(lp.c, dtype=np.float64)
+        l = np.ascontiguousarray(lp.l, dtype=np.float64)
+        u = np.ascontiguousarray(lp.u, dtype=np.float64)
+        sense = bytes(np.asarray(lp.sense, dtype=np.uint8))
+        h = C.c_void_p()
+        rc = self.lib.pdhg_create(self.m, self.n, int(rp[-1]) if rp.size else 0,
+                                  rp.ctypes.data_as(C.POINTER(C.c_int64)), ci.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  _dp(va), _dp(b), _dp(c), _dp(l), _dp(u), sense, C.byref(self.params), C.byref(h))
+        self._check(rc)
+        self.h = h
+
+    def _check(self, rc):
+        if rc != 0:
+            raise PdhgError(rc, self.lib.pdhg_last_error().decode())
+
+    def __del__(self):
+        self.destroy()
+
+    def destroy(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.pdhg_destroy(h)
+        self.h = None
+
+    def solve(self) -> Result:
+        r = Result()
+        self._check(self.lib.pdhg_solve(self.h, C.byref(r)))
+        return r
+
+    def iterate(self, iters: int) -> Result:
+        r = Result()
+        self._check(self.lib.pdhg_iterate(self.h, int(iters), C.byref(r)))
+        return r
+
+    def corner_push(self, seed: int) -> PushResult:
+        r = PushResult()
+        self._check(self.lib.pdhg_corner_push(self.h, C.c_uint64(seed), C.byref(r)))
+        return r
+
+    def kkt(self, x=None, y=None) -> KKTReport:
+        k = KKTReport()
+        xa = None if x is None else np.ascontiguousarray(x, dtype=np.float64)
+        ya = None if y is None else np.ascontiguousarray(y, dtype=np.float64)
+        self._check(self.lib.pdhg_kkt(self.h, None if xa is None else _dp(xa), None if ya is None else _dp(ya),
+                                      C.byref(k)))
+        return k
+
+    def get_solution(self):
+        x, y, z = np.zeros(self.n), np.zeros(self.m), np.zeros(self.n)
+        self._check(self.lib.pdhg_get_solution(self.h, _dp(x), _dp(y), _dp(z)))
+        return x, y, z
+
+    def get_iterate(self):
+        x, y = np.zeros(self.n), np.zeros(self.m)
+        self._check(self.lib.pdhg_get_iterate(self.h, _dp(x), _dp(y)))
+        return x, y
+
+    def get_scaling(self):
+        dr, dc, s4 = np.zeros(self.m), np.zeros(self.n), np.zeros(4)
+        self._check(self.lib.pdhg_get_scaling(self.h, _dp(dr), _dp(dc), _dp(s4)))
+        return {"dr": dr, "dc": dc, "eta": s4[0], "omega": s4[1], "sigma_est": s4[2], "t": int(s4[3])}

@@ -1,0 +1,71 @@
+"""The C-ABI library loads and exports every symbol the header declares
+(no compute calls: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2511_13894_amd import pdhg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(pdhg_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for need in ("pdhg_create", "pdhg_solve", "pdhg_corner_push", "pdhg_kkt", "pdhg_destroy", "pdhg_last_error"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not pdhg.LIB_PATH.exists():
+        pytest.fail("libpdhg.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(str(pdhg.LIB_PATH))
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(pdhg.EXPORTS) <= set(_declared())
+
+
+def test_struct_layouts_match_binding():
+    lib = pdhg.load()
+    assert lib.pdhg_struct_size(0) == ctypes.sizeof(pdhg.Params)
+    assert lib.pdhg_struct_size(1) == ctypes.sizeof(pdhg.Result)
+    assert lib.pdhg_struct_size(2) == ctypes.sizeof(pdhg.KKTReport)
+    assert lib.pdhg_struct_size(3) == ctypes.sizeof(pdhg.PushResult)
+    assert lib.pdhg_struct_size(99) == -1
+
+
+def test_default_params_and_argument_errors_without_gpu():
+    """Defaults, and argument checks that fail before any device call."""
+    lib = pdhg.load()
+    p = pdhg.default_params()
+    assert p.eps_rel == 1e-6 and p.check_every == 64 and p.ruiz_iters == 10 and p.power_iters == 32
+    assert p.halpern == 1 and p.reflect_gamma == 1.0 and p.push_min_iters == 100
+    h = ctypes.c_void_p()
+    rp = (ctypes.c_int64 * 2)(0, 1)
+    ci = (ctypes.c_int32 * 1)(5)  # column out of range for n = 2
+    va = (ctypes.c_double * 1)(1.0)
+    b = (ctypes.c_double * 1)(1.0)
+    c = (ctypes.c_double * 2)(1.0, 1.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = lib.pdhg_create(1, 2, 1, rp, ci, ctypes.cast(va, dp), ctypes.cast(b, dp), ctypes.cast(c, dp), None, None,
+                         None, ctypes.byref(p), ctypes.byref(h))
+    assert rc == -1 and b"column" in lib.pdhg_last_error()
+    ci[0] = 0
+    c[1] = float("nan")
+    rc = lib.pdhg_create(1, 2, 1, rp, ci, ctypes.cast(va, dp), ctypes.cast(b, dp), ctypes.cast(c, dp), None, None,
+                         None, ctypes.byref(p), ctypes.byref(h))
+    assert rc == -1 and b"c" in lib.pdhg_last_error()
+    assert lib.pdhg_solve(None, None) == -1
+    assert lib.pdhg_kkt(None, None, None, None) == -1
+    lib.pdhg_destroy(None)
