@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Benchmark: one step = the whole hot path on one synthetic LP, on one GPU:
+pdhg_create (transpose, scaling, step size), pdhg_solve to the relative KKT
+tolerance, pdhg_corner_push (Algorithm 1 and its early stop).
+
+Prints ONE JSON line.  `value` is PDHG iterations per second over the timed
+steps (solve + push iterations / wall time, inputs already on the device side
+of pdhg_create's copies is NOT assumed: pdhg_create's host-to-device copy is
+inside the step).  The roofline object covers the dominant iteration kernel:
+algorithmic bytes per launch / mean launch duration measured live with HIP
+events on the solver's stream during the timed steps.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PDHG iter/s + HBM GB/s; time to 1e-6 KKT corner, learned vs plain"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "c1": ("random sparse LP m=100000 n=400000 (power-law column degree 1..200, alpha 1.75; half the rows '<' "
+           "with implicit slacks; 30% of columns with u~U(1,10); planted degenerate optimum, 15% dual-degenerate "
+           "zeros; seed 1)"),
+    "c2": "transportation LP 2000 sources x 5000 sinks (n=10M arcs, m=7000 rows, integer data; seed 2)",
+    "c0": "random sparse LP m=200 n=500 (5 nnz per column, planted degenerate optimum; seed 0)",
+}
+
+
+def make_lp(cfg):
+    from paper_2511_13894_amd import lpgen
+
+    if cfg == "c1":
+        return lpgen.config1(1)
+    if cfg == "c2":
+        return lpgen.config2(2)
+    return lpgen.config0(0)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("pdhg_iter.hip", "pdhg_device.hpp", "pdhg_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2511_13894_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(cfg, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{cfg}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_source_hash:\s*(\w+)", txt)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    return float(t.group(1))
+
+
+def cpu_baseline(lp, iters, cfg):
+    """The CPU oracle as it stands, timed on this host: setup excluded,
+    `iters` PDHG iterations of the same LP in float64."""
+    from oracle import OracleSolver, num_threads
+
+    o = OracleSolver(lp, eps_rel=1e-30)
+    t0 = time.perf_counter()
+    o.iterate(iters)
+    dt = time.perf_counter() - t0
+    return {"value": iters / dt, "unit": "iter/s", "cores": num_threads(), "kind": "oracle",
+            "sample": f"{cfg} at full size, {iters} float64 PDHG iterations after setup ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-iters", type=int, default=2000)
+    ap.add_argument("--iters-only", type=int, default=0,
+                    help="profiling runs: create + this many iterations per step, no push, no JSON roofline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note, "
+              "not a built path", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2511_13894_amd import pdhg
+
+    t0 = time.perf_counter()
+    lp = make_lp(args.config)
+    gen_s = time.perf_counter() - t0
+    print(f"[bench] {args.config} m={lp.m} n={lp.n} nnz={lp.nnz} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    copy_gbs = pdhg.copy_probe(1 << 30, 20)
+    print(f"[bench] copy probe 1 GiB: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+
+    if args.iters_only:
+        for k in range(args.steps):
+            s = pdhg.Solver(lp, precision=args.precision)
+            r = s.iterate(args.iters_only)
+            s.destroy()
+            print(f"[bench] profiling step {k}: {r.iters} iterations", file=sys.stderr, flush=True)
+        return
+
+    def step(timing):
+        s = pdhg.Solver(lp, precision=args.precision, timing=timing)
+        r = s.solve()
+        p = s.corner_push(args.seed)
+        t = s.get_timing() if timing else None
+        s.destroy()
+        return r, p, t
+
+    for w in range(args.warmup):
+        r, p, _ = step(0)
+        print(f"[bench] warmup {w}: solve {r.iters} it ({pdhg.STATUS[r.status]}), push {p.iters} it "
+              f"({pdhg.STATUS[p.status]})", file=sys.stderr, flush=True)
+    iters = 0
+    prim_ms = dual_ms = 0.0
+    samples = 0
+    tim = None
+    details = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        r, p, tim = step(1)
+        te = time.perf_counter()
+        iters += r.iters + p.iters
+        prim_ms += tim.primal_ms * tim.samples
+        dual_ms += tim.dual_ms * tim.samples
+        samples += tim.samples
+        details.append({"solve_iters": r.iters, "solve_status": pdhg.STATUS[r.status], "push_iters": p.iters,
+                        "push_status": pdhg.STATUS[p.status], "step_s": te - ts,
+                        "rel_kkt": [r.rel_p, r.rel_d, r.rel_gap], "pobj": r.pobj,
+                        "off_bound_before": p.before.p_off, "off_bound_after": p.after.p_off,
+                        "candidates_before": p.before.candidates, "candidates_after": p.after.candidates,
+                        "est_primal_before": p.before.est_primal, "est_primal_after": p.after.est_primal,
+                        "fixed": p.n_fix_lower + p.n_fix_upper, "rows_to_eq": p.n_rows_to_eq})
+        print(f"[bench] step {k}: {te - ts:.3f}s solve {r.iters} push {p.iters}", file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t_start
+    value = iters / elapsed
+    prim_ms /= max(samples, 1)
+    dual_ms /= max(samples, 1)
+    # dominant kernel: larger share of the iteration time
+    if prim_ms >= dual_ms:
+        kname, ms, nbytes = "k_primal", prim_ms, tim.bytes_primal
+    else:
+        kname, ms, nbytes = "k_dual", dual_ms, tim.bytes_dual
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(args.config, kname),
+            "kernel": kname, "launch_us": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": int(nbytes),
+            "other_kernel": {"name": "k_dual" if kname == "k_primal" else "k_primal",
+                             "launch_us": round((dual_ms if kname == "k_primal" else prim_ms) * 1e3, 2),
+                             "algorithmic_bytes_per_launch": int(tim.bytes_dual if kname == "k_primal"
+                                                                 else tim.bytes_primal)},
+            "timed_launches": int(samples), "copy_probe_gbs": round(copy_gbs, 1)}
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64norms", "data": "synthetic",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}; step = create + solve to 1e-6 relative "
+                               f"KKT + corner push", "m": lp.m, "n": lp.n, "nnz": lp.nnz,
+                   "precision": args.precision, "eps_rel": 1e-6, "push_seed": args.seed},
+        "roofline": roof,
+        "detail": {"steps": details, "time_to_corner_s": round(elapsed / args.steps, 4),
+                   "lanes_at": tim.lanes_at, "lanes_a": tim.lanes_a},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(lp, args.cpu_iters, args.config)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -98,6 +98,8 @@ typedef struct pdhg_params {
     int32_t lanes_at;      /* lanes per row for A'y (1..64, power of 2); 0 = automatic  */
     int32_t lanes_a;       /* lanes per row for A x; 0 = automatic                      */
     int32_t use_graph;     /* 1: replay check cycles from a captured hipGraph (default) */
+    int32_t timing;        /* 1: time one primal and one dual launch per cycle with HIP
+                              events on the solver's stream (read by pdhg_get_timing)  */
 } pdhg_params;
 
 /* outcome of pdhg_solve / pdhg_iterate, evaluated on the original model */
@@ -137,6 +139,21 @@ typedef struct pdhg_push_result {
     pdhg_kkt_report before; /* (x, y, z) of the solve, original model                 */
     pdhg_kkt_report after;  /* (xhat, y, z): pushed x with the solve's y and z         */
 } pdhg_push_result;
+
+/* Live kernel timing (params.timing = 1): average durations of the two
+ * iteration kernels over the sampled launches of every solve and push call
+ * since pdhg_create, and their algorithmic bytes per launch (matrix values,
+ * indices and row pointers, one read of every vector the kernel reads, one
+ * write of every vector it writes; gathers counted once). */
+typedef struct pdhg_timing {
+    double primal_ms;      /* mean duration of one primal-half launch (A'y + update) */
+    double dual_ms;        /* mean duration of one dual-half launch (A xbar + update) */
+    int64_t samples;       /* sampled launches of each kernel                          */
+    int64_t bytes_primal;  /* algorithmic bytes of one primal-half launch             */
+    int64_t bytes_dual;    /* algorithmic bytes of one dual-half launch               */
+    int32_t lanes_at;      /* lanes per row used by the primal half                   */
+    int32_t lanes_a;       /* lanes per row used by the dual half                     */
+} pdhg_timing;
 
 /* Fill *p with the defaults listed above. */
 void pdhg_default_params(pdhg_params *p);
@@ -181,6 +198,16 @@ int pdhg_get_iterate(pdhg_solver *s, double *x, double *y);
  * scalars4 = {eta, omega, sigma_estimate, iterations of the phase}. */
 int pdhg_get_scaling(pdhg_solver *s, double *dr, double *dc, double *scalars4);
 
+/* Kernel timing and byte model (see pdhg_timing).  Errors: INVALID_ARG. */
+int pdhg_get_timing(pdhg_solver *s, pdhg_timing *t);
+
+/* Device copy probe: copies `bytes` (rounded down to 16-byte units) between
+ * two device buffers `reps` times with a plain streaming kernel and returns
+ * the achieved bandwidth (read + write bytes / time) in *gbps; the HBM
+ * ceiling that the iteration kernels are measured against.  Allocates and
+ * frees its own buffers.  Errors: INVALID_ARG, OOM, HIP. */
+int pdhg_copy_probe(int64_t bytes, int32_t reps, double *gbps);
+
 /* Release all device memory of the handle (NULL is a no-op). */
 void pdhg_destroy(pdhg_solver *s);
 
@@ -188,7 +215,7 @@ void pdhg_destroy(pdhg_solver *s);
 const char *pdhg_last_error(void);
 
 /* Size checks for bindings: sizeof of each public struct. */
-int32_t pdhg_struct_size(int32_t which); /* 0 params, 1 result, 2 kkt, 3 push result */
+int32_t pdhg_struct_size(int32_t which); /* 0 params, 1 result, 2 kkt, 3 push, 4 timing */
 
 #ifdef __cplusplus
 }

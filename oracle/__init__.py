@@ -11,6 +11,7 @@ from .oracle import (  # noqa: F401
     OrPushResult,
     OrResult,
     build_oracle,
+    num_threads,
     push_uniform,
     splitmix64,
     STATUS,

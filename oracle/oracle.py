@@ -102,7 +102,7 @@ def _load():
         lib.or_splitmix64.argtypes = [C.c_uint64]
         lib.or_push_uniform.restype = C.c_double
         lib.or_push_uniform.argtypes = [C.c_uint64, C.c_int64]
-        for f in ("or_params_size", "or_kkt_size", "or_push_result_size"):
+        for f in ("or_params_size", "or_kkt_size", "or_push_result_size", "or_num_threads"):
             getattr(lib, f).restype = C.c_int
         assert lib.or_params_size() == C.sizeof(OrParams)
         assert lib.or_kkt_size() == C.sizeof(OrKKT)
@@ -117,6 +117,10 @@ def _dp(a):
 
 def splitmix64(x: int) -> int:
     return int(_load().or_splitmix64(C.c_uint64(x & 0xFFFFFFFFFFFFFFFF)))
+
+
+def num_threads() -> int:
+    return int(_load().or_num_threads())
 
 
 def push_uniform(seed: int, j: int) -> float:

@@ -867,6 +867,18 @@ void or_get_ahat(const or_solver *s, int64_t *rp, int32_t *ci, double *v)
     if (ci) memcpy(ci, s->ci, sizeof(int32_t) * (size_t)s->nnz);
     if (v) memcpy(v, s->ahat, sizeof(double) * (size_t)s->nnz);
 }
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* threads the row-parallel products use */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 int or_params_size(void) { return (int)sizeof(or_params); }
 int or_kkt_size(void) { return (int)sizeof(or_kkt); }
 int or_push_result_size(void) { return (int)sizeof(or_push_result); }

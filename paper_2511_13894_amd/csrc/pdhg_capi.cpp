@@ -65,6 +65,8 @@ void free_all(pdhg_solver *s)
     if (s->rep_host) (void)hipHostFree(s->rep_host);
     if (s->cnt_host) (void)hipHostFree(s->cnt_host);
     if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    for (hipEvent_t &e : s->ev)
+        if (e) (void)hipEventDestroy(e);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
 }
 
@@ -86,17 +88,22 @@ int run_phase(pdhg_solver *s, int64_t iters, int mode, double t0)
     while (s->t_host < target) {
         int enq = 0;
         bool any_check = false;
+        bool events = false;
         while (s->t_host < target && enq < depth) {
             const int64_t to_check = s->next_check - s->t_host;
             const int64_t left = target - s->t_host;
             const bool check = to_check <= left;
             const int len = (int)(check ? to_check : left);
-            if (check && len == K && s->p.use_graph) {
+            // with timing on, the first segment of every batch runs eagerly with
+            // events around one primal and one dual launch; the rest replay
+            const bool timed = s->p.timing && enq == 0 && len >= 2;
+            if (check && len == K && s->p.use_graph && !timed) {
                 HIPCHK(capture_cycle(s, K, mode));
                 HIPCHK(hipGraphLaunch(s->graph_exec, s->stream));
             } else {
-                HIPCHK(launch_iterations(s, len, check, mode));
+                HIPCHK(launch_iterations(s, len, check, mode, timed));
             }
+            events = events || timed;
             s->t_host += len;
             if (check) {
                 s->next_check += K;
@@ -106,6 +113,16 @@ int run_phase(pdhg_solver *s, int64_t iters, int mode, double t0)
         }
         HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
+        if (events && !s->st_host->done) {
+            float a = 0.0f, b2 = 0.0f;
+            if (hipEventElapsedTime(&a, s->ev[0], s->ev[1]) == hipSuccess &&
+                hipEventElapsedTime(&b2, s->ev[1], s->ev[2]) == hipSuccess) {
+                s->t_primal_ms += a;
+                s->t_dual_ms += b2;
+                s->t_samples += 1;
+            }
+            (void)hipGetLastError(); // a failed timing query must not leak into later checks
+        }
         s->has_candidate = s->st_host->checks > 0;
         (void)any_check;
         if (s->st_host->done) {
@@ -191,6 +208,7 @@ void pdhg_default_params(pdhg_params *p)
     p->lanes_at = 0;
     p->lanes_a = 0;
     p->use_graph = 1;
+    p->timing = 0;
 }
 
 const char *pdhg_last_error(void) { return g_last_error.c_str(); }
@@ -202,6 +220,7 @@ int32_t pdhg_struct_size(int32_t which)
     case 1: return (int32_t)sizeof(pdhg_result);
     case 2: return (int32_t)sizeof(pdhg_kkt_report);
     case 3: return (int32_t)sizeof(pdhg_push_result);
+    case 4: return (int32_t)sizeof(pdhg_timing);
     default: return -1;
     }
 }
@@ -288,6 +307,8 @@ int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const
         s->nnz = nz;
         s->p = p;
         s->fp32 = p.precision == PDHG_FP32_MIXED;
+        if (p.timing)
+            for (hipEvent_t &e : s->ev) HIPCHK(hipEventCreate(&e));
         if (p.stream) s->stream = (hipStream_t)p.stream;
         else {
             HIPCHK(hipStreamCreate(&s->stream));
@@ -531,6 +552,37 @@ int pdhg_get_scaling(pdhg_solver *s, double *dr, double *dc, double *scalars4)
     } catch (const HipFailure &f) {
         return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
     }
+    return PDHG_OK;
+}
+
+int pdhg_get_timing(pdhg_solver *s, pdhg_timing *t)
+{
+    if (!s || !t) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    std::memset(t, 0, sizeof(*t));
+    t->samples = s->t_samples;
+    if (s->t_samples > 0) {
+        t->primal_ms = s->t_primal_ms / (double)s->t_samples;
+        t->dual_ms = s->t_dual_ms / (double)s->t_samples;
+    }
+    // byte model of the two kernels (v = bytes per working value, 4 per index)
+    const int64_t v = s->fp32 ? 4 : 8, m = s->m, n = s->n, nz = s->nnz;
+    // primal: row pointers, indices + values, y gathered once, reads x, chat,
+    // x_anchor, lhat, uhat, writes x, xbar
+    t->bytes_primal = 4 * (n + 1) + (4 + v) * nz + v * m + 7 * v * n;
+    // dual: row pointers, indices + values, xbar gathered once, reads y, bhat,
+    // y_anchor, sense byte, writes y
+    t->bytes_dual = 4 * (m + 1) + (4 + v) * nz + v * n + 4 * v * m + m;
+    t->lanes_at = s->lanes_at;
+    t->lanes_a = s->lanes_a;
+    return PDHG_OK;
+}
+
+int pdhg_copy_probe(int64_t bytes, int32_t reps, double *gbps)
+{
+    if (bytes < 16 || reps < 1 || !gbps) return fail(PDHG_ERR_INVALID_ARG, "bad copy-probe arguments");
+    hipError_t e = copy_probe(bytes, reps, gbps);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? PDHG_ERR_OOM : PDHG_ERR_HIP, std::string("copy probe: ") + hipGetErrorString(e));
     return PDHG_OK;
 }
 

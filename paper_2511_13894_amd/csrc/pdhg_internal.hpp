@@ -117,6 +117,11 @@ struct pdhg_solver {
     hipGraphExec_t graph_exec = nullptr;
     int graph_len = 0;
     int graph_mode = -1;
+
+    // live kernel timing: events around one primal and one dual launch per cycle
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    double t_primal_ms = 0.0, t_dual_ms = 0.0;
+    int64_t t_samples = 0;
 };
 
 namespace pdhg {
@@ -132,7 +137,7 @@ hipError_t power_iteration(pdhg_solver *s);
 
 // iteration, checks, push and reports (pdhg_iter.hip)
 hipError_t init_iteration(pdhg_solver *s);
-hipError_t launch_iterations(pdhg_solver *s, int count, bool check_at_end, int mode);
+hipError_t launch_iterations(pdhg_solver *s, int count, bool check_at_end, int mode, bool timed_launch);
 hipError_t launch_check(pdhg_solver *s, int mode, int len);
 hipError_t launch_advance(pdhg_solver *s, int len);
 hipError_t candidate_from_iterate(pdhg_solver *s);
@@ -140,6 +145,7 @@ hipError_t unscale(pdhg_solver *s, const void *xh, const void *yh, double *xo, d
 hipError_t report(pdhg_solver *s, const double *x, const double *y, double *z, pdhg_kkt_report *k);
 hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r);
 hipError_t capture_cycle(pdhg_solver *s, int len, int mode);
+hipError_t copy_probe(int64_t bytes, int reps, double *gbps);
 
 // launch-shape helpers
 // Lane count for a given mean row length: the power of two at or above the

@@ -393,17 +393,18 @@ hipError_t launch_advance(pdhg_solver *s, int len)
     return hipGetLastError();
 }
 
-hipError_t launch_iterations(pdhg_solver *s, int count, bool check_at_end, int mode)
+hipError_t launch_iterations(pdhg_solver *s, int count, bool check_at_end, int mode, bool timed_launch)
 {
+    const int timed = (timed_launch && count >= 2) ? count / 2 : -1; // one sampled iteration
     for (int i = 0; i < count; i++) {
         const int store = (check_at_end && i == count - 1) ? 1 : 0;
-        if (s->fp32) {
-            launch_primal<float>(s, i, store);
-            launch_dual<float>(s, i, store);
-        } else {
-            launch_primal<double>(s, i, store);
-            launch_dual<double>(s, i, store);
-        }
+        if (i == timed) hipEventRecord(s->ev[0], s->stream);
+        if (s->fp32) launch_primal<float>(s, i, store);
+        else launch_primal<double>(s, i, store);
+        if (i == timed) hipEventRecord(s->ev[1], s->stream);
+        if (s->fp32) launch_dual<float>(s, i, store);
+        else launch_dual<double>(s, i, store);
+        if (i == timed) hipEventRecord(s->ev[2], s->stream);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -422,7 +423,7 @@ hipError_t capture_cycle(pdhg_solver *s, int len, int mode)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t el = launch_iterations(s, len, true, mode);
+    hipError_t el = launch_iterations(s, len, true, mode, false);
     e = hipStreamEndCapture(s->stream, &g);
     if (el != hipSuccess) return el;
     if (e != hipSuccess) return e;
@@ -834,6 +835,53 @@ static hipError_t push_setup_impl(pdhg_solver *s, uint64_t seed, pdhg_push_resul
 hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
 {
     return s->fp32 ? push_setup_impl<float>(s, seed, r) : push_setup_impl<double>(s, seed, r);
+}
+
+// ------------------------------------------------------------ copy probe ---
+// four independent 16-byte loads in flight per thread and iteration
+__global__ __launch_bounds__(kBlock) void k_copy16(int64_t n16, const uint4 *__restrict__ src, uint4 *__restrict__ dst)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += 4 * stride) {
+        uint4 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            if (i + q * stride < n16) v[q] = src[i + q * stride];
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            if (i + q * stride < n16) dst[i + q * stride] = v[q];
+    }
+}
+
+hipError_t copy_probe(int64_t bytes, int reps, double *gbps)
+{
+    const int64_t n16 = bytes / 16;
+    uint4 *a = nullptr, *b = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&a, (size_t)n16 * 16);
+    if (e == hipSuccess) e = hipMalloc(&b, (size_t)n16 * 16);
+    if (e == hipSuccess) e = hipStreamCreate(&st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMemsetAsync(a, 1, (size_t)n16 * 16, st);
+    const int grid = grid_for((n16 + 3) / 4, kBlock, 256 * 16);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(kBlock), 0, st, n16, a, b); // warm-up
+        hipEventRecord(e0, st);
+        for (int r = 0; r < reps; r++) hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(kBlock), 0, st, n16, a, b);
+        hipEventRecord(e1, st);
+        e = hipStreamSynchronize(st);
+    }
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess) *gbps = (double)(2 * n16 * 16) * reps / (ms * 1e-3) / 1e9;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    return e;
 }
 
 } // namespace pdhg

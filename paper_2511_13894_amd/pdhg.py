@@ -37,7 +37,7 @@ class Params(C.Structure):
         ("push_min_iters", C.c_int32), ("precision", C.c_int32),
         ("push_obj_scale", C.c_double), ("push_max_iter", C.c_int64), ("time_limit", C.c_double),
         ("stream", C.c_void_p), ("verbosity", C.c_int32), ("lanes_at", C.c_int32), ("lanes_a", C.c_int32),
-        ("use_graph", C.c_int32),
+        ("use_graph", C.c_int32), ("timing", C.c_int32),
     ]
 
 
@@ -70,9 +70,16 @@ class PushResult(C.Structure):
     ]
 
 
+class Timing(C.Structure):
+    _fields_ = [
+        ("primal_ms", C.c_double), ("dual_ms", C.c_double), ("samples", C.c_int64),
+        ("bytes_primal", C.c_int64), ("bytes_dual", C.c_int64), ("lanes_at", C.c_int32), ("lanes_a", C.c_int32),
+    ]
+
+
 EXPORTS = ["pdhg_default_params", "pdhg_create", "pdhg_solve", "pdhg_iterate", "pdhg_corner_push", "pdhg_kkt",
            "pdhg_get_solution", "pdhg_get_iterate", "pdhg_get_scaling", "pdhg_destroy", "pdhg_last_error",
-           "pdhg_struct_size"]
+           "pdhg_struct_size", "pdhg_get_timing", "pdhg_copy_probe"]
 
 _lib = None
 
@@ -99,15 +106,17 @@ def load(path: Optional[Path] = None):
     lib.pdhg_get_solution.argtypes = [C.c_void_p, dp, dp, dp]
     lib.pdhg_get_iterate.argtypes = [C.c_void_p, dp, dp]
     lib.pdhg_get_scaling.argtypes = [C.c_void_p, dp, dp, dp]
+    lib.pdhg_get_timing.argtypes = [C.c_void_p, P(Timing)]
+    lib.pdhg_copy_probe.argtypes = [C.c_int64, C.c_int32, dp]
     lib.pdhg_destroy.argtypes = [C.c_void_p]
     lib.pdhg_destroy.restype = None
     lib.pdhg_last_error.restype = C.c_char_p
     lib.pdhg_struct_size.restype = C.c_int32
     lib.pdhg_struct_size.argtypes = [C.c_int32]
     for fn in ("pdhg_create", "pdhg_solve", "pdhg_iterate", "pdhg_corner_push", "pdhg_kkt", "pdhg_get_solution",
-               "pdhg_get_iterate", "pdhg_get_scaling"):
+               "pdhg_get_iterate", "pdhg_get_scaling", "pdhg_get_timing", "pdhg_copy_probe"):
         getattr(lib, fn).restype = C.c_int
-    sizes = [C.sizeof(Params), C.sizeof(Result), C.sizeof(KKTReport), C.sizeof(PushResult)]
+    sizes = [C.sizeof(Params), C.sizeof(Result), C.sizeof(KKTReport), C.sizeof(PushResult), C.sizeof(Timing)]
     for which, want in enumerate(sizes):
         got = lib.pdhg_struct_size(which)
         if got != want:
@@ -131,6 +140,16 @@ def default_params(**kw) -> Params:
             raise KeyError(k)
         setattr(p, k, v)
     return p
+
+
+def copy_probe(nbytes: int, reps: int = 20) -> float:
+    """Achieved GB/s of a plain device copy of nbytes (read + write counted)."""
+    _refuse_second_runtime()
+    g = C.c_double()
+    rc = load().pdhg_copy_probe(int(nbytes), int(reps), C.byref(g))
+    if rc != 0:
+        raise PdhgError(rc, load().pdhg_last_error().decode())
+    return g.value
 
 
 def _refuse_second_runtime():
@@ -219,6 +238,11 @@ class Solver:
         x, y = np.zeros(self.n), np.zeros(self.m)
         self._check(self.lib.pdhg_get_iterate(self.h, _dp(x), _dp(y)))
         return x, y
+
+    def get_timing(self) -> Timing:
+        t = Timing()
+        self._check(self.lib.pdhg_get_timing(self.h, C.byref(t)))
+        return t
 
     def get_scaling(self):
         dr, dc, s4 = np.zeros(self.m), np.zeros(self.n), np.zeros(4)
