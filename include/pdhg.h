@@ -95,11 +95,16 @@ typedef struct pdhg_params {
     double time_limit;     /* seconds per solve / push call; <= 0: none (default)       */
     void *stream;          /* hipStream_t; NULL: library-owned stream                   */
     int32_t verbosity;     /* 0 silent (default)                                        */
-    int32_t lanes_at;      /* lanes per row for A'y (1..64, power of 2); 0 = automatic  */
-    int32_t lanes_a;       /* lanes per row for A x; 0 = automatic                      */
+    int32_t lanes_at;      /* primal-half kernel: 1..64 (power of 2) lanes per row, or
+                              -32/-64/-128/-256 for an LDS tile of that many rows;
+                              0 = chosen from the mean row length                      */
+    int32_t lanes_a;       /* dual-half kernel, same encoding                           */
     int32_t use_graph;     /* 1: replay check cycles from a captured hipGraph (default) */
     int32_t timing;        /* 1: time one primal and one dual launch per cycle with HIP
                               events on the solver's stream (read by pdhg_get_timing)  */
+    int32_t autotune;      /* 1: at create, time every kernel choice of each half on
+                              scratch vectors and keep the fastest (0 = default: the
+                              mean-row-length rule, reproducible run to run)          */
 } pdhg_params;
 
 /* outcome of pdhg_solve / pdhg_iterate, evaluated on the original model */
@@ -151,8 +156,8 @@ typedef struct pdhg_timing {
     int64_t samples;       /* sampled launches of each kernel                          */
     int64_t bytes_primal;  /* algorithmic bytes of one primal-half launch             */
     int64_t bytes_dual;    /* algorithmic bytes of one dual-half launch               */
-    int32_t lanes_at;      /* lanes per row used by the primal half                   */
-    int32_t lanes_a;       /* lanes per row used by the dual half                     */
+    int32_t lanes_at;      /* primal-half kernel in use (lanes_at encoding)           */
+    int32_t lanes_a;       /* dual-half kernel in use                                  */
 } pdhg_timing;
 
 /* Fill *p with the defaults listed above. */

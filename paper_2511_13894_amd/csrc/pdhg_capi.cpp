@@ -209,6 +209,7 @@ void pdhg_default_params(pdhg_params *p)
     p->lanes_a = 0;
     p->use_graph = 1;
     p->timing = 0;
+    p->autotune = 0;
 }
 
 const char *pdhg_last_error(void) { return g_last_error.c_str(); }
@@ -258,9 +259,12 @@ int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const
     if (p.check_every < 1 || p.ruiz_iters < 0 || p.power_iters < 0 || p.push_min_iters < 1 ||
         (p.precision != PDHG_FP64 && p.precision != PDHG_FP32_MIXED) || !(p.eps_rel > 0.0) || !(p.eta_safety > 0.0))
         return fail(PDHG_ERR_INVALID_ARG, "invalid parameter");
-    for (int32_t lanes : {p.lanes_a, p.lanes_at})
-        if (lanes != 0 && (lanes < 1 || lanes > 64 || (lanes & (lanes - 1))))
-            return fail(PDHG_ERR_INVALID_ARG, "lanes must be 0 or a power of two in 1..64");
+    for (int32_t k : {p.lanes_a, p.lanes_at}) {
+        const bool lane_ok = k >= 1 && k <= 64 && !(k & (k - 1));
+        const bool tile_ok = k == -32 || k == -64 || k == -128 || k == -256;
+        if (k != 0 && !lane_ok && !tile_ok)
+            return fail(PDHG_ERR_INVALID_ARG, "lanes must be 0, a power of two in 1..64, or -32/-64/-128/-256");
+    }
 
     // canonical rows (ascending columns, duplicates summed), host side ingest
     std::vector<int> rp((size_t)m + 1);
@@ -314,8 +318,11 @@ int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const
             HIPCHK(hipStreamCreate(&s->stream));
             s->own_stream = true;
         }
-        s->lanes_a = p.lanes_a ? p.lanes_a : lanes_for_mean(m > 0 ? (double)nz / m : 1.0);
-        s->lanes_at = p.lanes_at ? p.lanes_at : lanes_for_mean(n > 0 ? (double)nz / n : 1.0);
+        const double mean_a = m > 0 ? (double)nz / m : 1.0, mean_at = n > 0 ? (double)nz / n : 1.0;
+        s->lanes_a = lanes_for_mean(mean_a);
+        s->lanes_at = lanes_for_mean(mean_at);
+        s->kern_a = p.lanes_a ? p.lanes_a : choose_kernel(mean_a);
+        s->kern_at = p.lanes_at ? p.lanes_at : choose_kernel(mean_at);
         s->red_blocks_m = grid_for(m, kBlock, kMaxRedBlocks);
         s->red_blocks_n = grid_for(n, kBlock, kMaxRedBlocks);
         const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
@@ -386,6 +393,7 @@ int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const
         HIPCHK(power_iteration(s));
         HIPCHK(init_norms(s));
         HIPCHK(init_iteration(s));
+        if (p.autotune) HIPCHK(autotune(s));
         HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         s->t_host = 0;
@@ -572,8 +580,8 @@ int pdhg_get_timing(pdhg_solver *s, pdhg_timing *t)
     // dual: row pointers, indices + values, xbar gathered once, reads y, bhat,
     // y_anchor, sense byte, writes y
     t->bytes_dual = 4 * (m + 1) + (4 + v) * nz + v * n + 4 * v * m + m;
-    t->lanes_at = s->lanes_at;
-    t->lanes_a = s->lanes_a;
+    t->lanes_at = s->kern_at;
+    t->lanes_a = s->kern_a;
     return PDHG_OK;
 }
 

@@ -60,6 +60,16 @@ __device__ __forceinline__ void block_reduce(double (&v)[NQ], unsigned is_max_ma
     __syncthreads();
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (bid % 8).  Map them
+// so that every XCD works on one contiguous range of logical blocks: rows
+// that gather the same cache lines then meet in the same L2.
+__device__ __forceinline__ int xcd_block(int bid, int nblk)
+{
+    const int x = bid & 7, q = nblk >> 3, r = nblk & 7;
+    const int base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    return base + (bid >> 3);
+}
+
 // Row-compressed product out[r] = sum_e val[e] * x[idx[e]] over rows r < rows,
 // L lanes per row, accumulation in ACC.  One group of L lanes walks a row with
 // stride L (coalesced for L >= 2 on long rows, one lane per row when L = 1).
@@ -68,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int rows, const int *__restrict
                                                  const int *__restrict__ idx, const VM *__restrict__ val,
                                                  const VX *__restrict__ x, VO *__restrict__ out)
 {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t g = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int64_t row = g / L;
     const int lane = (int)(g % L);
     if (row >= rows) return;

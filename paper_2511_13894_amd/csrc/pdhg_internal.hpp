@@ -105,7 +105,8 @@ struct pdhg_solver {
     double *rep_host = nullptr;        // pinned report values
     int64_t *cnt_host = nullptr;       // pinned integer counts
 
-    int lanes_at = 1, lanes_a = 1;
+    int lanes_at = 1, lanes_a = 1; // lane-group width of setup / check products
+    int kern_at = 1, kern_a = 1;   // iteration kernels: > 0 lane-group width, < 0 LDS tile of -k rows
     int64_t t_host = 0;      // iterations of the current phase (mirror of st->t)
     int64_t next_check = 0;  // phase iteration count of the next check
     bool in_push = false;
@@ -146,6 +147,8 @@ hipError_t report(pdhg_solver *s, const double *x, const double *y, double *z, p
 hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r);
 hipError_t capture_cycle(pdhg_solver *s, int len, int mode);
 hipError_t copy_probe(int64_t bytes, int reps, double *gbps);
+int choose_kernel(double mean_row);
+hipError_t autotune(pdhg_solver *s);
 
 // launch-shape helpers
 // Lane count for a given mean row length: the power of two at or above the

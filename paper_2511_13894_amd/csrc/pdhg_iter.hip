@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(int n, const int *__restrict_
                                                   const DevState *__restrict__ st, int i, int store_cand)
 {
     if (st->done) return;
-    const int64_t gi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t gi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int64_t j = gi / L;
     const int lane = (int)(gi % L);
     if (j >= n) return;
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
                                                 const DevState *__restrict__ st, int i, int store_cand)
 {
     if (st->done) return;
-    const int64_t gi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t gi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int64_t r = gi / L;
     const int lane = (int)(gi % L);
     if (r >= m) return;
@@ -92,12 +92,153 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
     }
 }
 
+// ------------------------------------------------- LDS-tiled short rows ---
+// A workgroup owns a tile of T consecutive rows.  All entries of the tile are
+// streamed in chunks of kChunk: every thread loads entries k, k+256, ... with
+// their gathered vector value (coalesced index/value loads, several loads in
+// flight per thread), writes the products to LDS, and G = 256/T threads per
+// row then sum their row's products in a fixed order.  The row sums go to LDS
+// and threads 0..T-1 run the update epilogue on contiguous rows, with the
+// epilogue's vector loads issued before the product phase.
+constexpr int kChunk = 2048;
+
+template <typename V, int T>
+__device__ __forceinline__ void tile_row_sums(int r0, int rows, const int *__restrict__ ptr,
+                                              const int *__restrict__ idx, const V *__restrict__ val,
+                                              const V *__restrict__ vec, int *s_ptr, V *s_prod, V *s_sum)
+{
+    constexpr int G = kBlock / T;
+    const int tid = threadIdx.x;
+    for (int k = tid; k <= rows; k += kBlock) s_ptr[k] = ptr[r0 + k];
+    __syncthreads();
+    const int beg = s_ptr[0], end = s_ptr[rows];
+    const int my_row = tid / G, sub = tid % G;
+    const bool have = my_row < rows;
+    const int rb = have ? s_ptr[my_row] : 0, re = have ? s_ptr[my_row + 1] : 0;
+    V acc = 0;
+    for (int cs = beg; cs < end; cs += kChunk) {
+        const int ce = cs + kChunk < end ? cs + kChunk : end;
+        for (int k = cs + tid; k < ce; k += kBlock) s_prod[k - cs] = val[k] * vec[idx[k]];
+        __syncthreads();
+        const int lo = rb > cs ? rb : cs, hi = re < ce ? re : ce;
+        for (int q = lo + sub; q < hi; q += G) acc += s_prod[q - cs];
+        __syncthreads();
+    }
+    acc = group_sum<G>(acc);
+    if (have && sub == 0) s_sum[my_row] = acc;
+    __syncthreads();
+}
+
+template <typename V, int T>
+__global__ __launch_bounds__(kBlock) void k_primal_tiled(int n, const int *__restrict__ tp, const int *__restrict__ ti,
+                                                        const V *__restrict__ atv, const V *__restrict__ y,
+                                                        const V *__restrict__ ch, const V *__restrict__ lh,
+                                                        const V *__restrict__ uh, V *__restrict__ x,
+                                                        const V *__restrict__ xa, V *__restrict__ xbar,
+                                                        V *__restrict__ xp, const DevState *__restrict__ st, int i,
+                                                        int store_cand)
+{
+    __shared__ int s_ptr[T + 1];
+    __shared__ V s_prod[kChunk];
+    __shared__ V s_sum[T];
+    if (st->done) return;
+    const int r0 = xcd_block(blockIdx.x, gridDim.x) * T;
+    const int rows = n - r0 < T ? n - r0 : T;
+    const int tid = threadIdx.x;
+    const bool mine = tid < rows;
+    const int j = r0 + tid;
+    V xj = 0, cj = 0, lo = 0, hi = 0, aj = 0;
+    if (mine) { // epilogue operands, independent of the product
+        xj = x[j];
+        cj = ch[j];
+        lo = lh[j];
+        hi = uh[j];
+        aj = xa[j];
+    }
+    tile_row_sums<V, T>(r0, rows, tp, ti, atv, y, s_ptr, s_prod, s_sum);
+    if (!mine) return;
+    const V tau = (V)st->tau;
+    V xn = xj - tau * (cj - s_sum[tid]);
+    xn = xn < lo ? lo : xn;
+    xn = xn > hi ? hi : xn;
+    xbar[j] = (V)2 * xn - xj;
+    if (store_cand) xp[j] = xn;
+    if (st->halpern) {
+        double w, wa, g;
+        halpern_weights(st, i, w, wa, g);
+        x[j] = (V)w * (((V)1 + (V)g) * xn - (V)g * xj) + (V)wa * aj;
+    } else {
+        x[j] = xn;
+    }
+}
+
+template <typename V, int T>
+__global__ __launch_bounds__(kBlock) void k_dual_tiled(int m, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                      const V *__restrict__ av, const V *__restrict__ xbar,
+                                                      const V *__restrict__ bh, const int8_t *__restrict__ sense,
+                                                      V *__restrict__ y, const V *__restrict__ ya,
+                                                      V *__restrict__ yp, const DevState *__restrict__ st, int i,
+                                                      int store_cand)
+{
+    __shared__ int s_ptr[T + 1];
+    __shared__ V s_prod[kChunk];
+    __shared__ V s_sum[T];
+    if (st->done) return;
+    const int r0 = xcd_block(blockIdx.x, gridDim.x) * T;
+    const int rows = m - r0 < T ? m - r0 : T;
+    const int tid = threadIdx.x;
+    const bool mine = tid < rows;
+    const int r = r0 + tid;
+    V yr = 0, br = 0, ar = 0;
+    int8_t sn = '=';
+    if (mine) {
+        yr = y[r];
+        br = bh[r];
+        ar = ya[r];
+        sn = sense[r];
+    }
+    tile_row_sums<V, T>(r0, rows, rp, ci, av, xbar, s_ptr, s_prod, s_sum);
+    if (!mine) return;
+    const V sig = (V)st->sigma;
+    V yn = yr + sig * (br - s_sum[tid]);
+    if (sn == '<') yn = yn < (V)0 ? yn : (V)0;
+    else if (sn == '>') yn = yn > (V)0 ? yn : (V)0;
+    if (store_cand) yp[r] = yn;
+    if (st->halpern) {
+        double w, wa, g;
+        halpern_weights(st, i, w, wa, g);
+        y[r] = (V)w * (((V)1 + (V)g) * yn - (V)g * yr) + (V)wa * ar;
+    } else {
+        y[r] = yn;
+    }
+}
+
 template <typename V>
 static void launch_primal(pdhg_solver *s, int i, int store)
 {
-    const int L = s->lanes_at;
-    const int grid = (int)(((int64_t)s->n * L + kBlock - 1) / kBlock);
+    const int L = s->kern_at;
     if (s->n <= 0) return;
+    if (L < 0) { // LDS-tiled kernel with a tile of -L rows
+        const int T = -L;
+        const int grid = (s->n + T - 1) / T;
+#define PDHG_PT_CASE(TT)                                                                                        \
+    case TT:                                                                                                    \
+        hipLaunchKernelGGL((k_primal_tiled<V, TT>), dim3(grid), dim3(kBlock), 0, s->stream, s->n, s->tp, s->ti, \
+                           (const V *)s->ahat_t, (const V *)s->y, (const V *)s->ch, (const V *)s->lh,          \
+                           (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i,  \
+                           store);                                                                              \
+        break;
+        switch (T) {
+            PDHG_PT_CASE(32)
+            PDHG_PT_CASE(64)
+            PDHG_PT_CASE(128)
+        default:
+            PDHG_PT_CASE(256)
+        }
+#undef PDHG_PT_CASE
+        return;
+    }
+    const int grid = (int)(((int64_t)s->n * L + kBlock - 1) / kBlock);
 #define PDHG_PRIMAL_CASE(LL)                                                                                    \
     case LL:                                                                                                    \
         hipLaunchKernelGGL((k_primal<V, LL>), dim3(grid), dim3(kBlock), 0, s->stream, s->n, s->tp, s->ti,      \
@@ -121,9 +262,28 @@ static void launch_primal(pdhg_solver *s, int i, int store)
 template <typename V>
 static void launch_dual(pdhg_solver *s, int i, int store)
 {
-    const int L = s->lanes_a;
-    const int grid = (int)(((int64_t)s->m * L + kBlock - 1) / kBlock);
+    const int L = s->kern_a;
     if (s->m <= 0) return;
+    if (L < 0) {
+        const int T = -L;
+        const int grid = (s->m + T - 1) / T;
+#define PDHG_DT_CASE(TT)                                                                                        \
+    case TT:                                                                                                    \
+        hipLaunchKernelGGL((k_dual_tiled<V, TT>), dim3(grid), dim3(kBlock), 0, s->stream, s->m, s->rp, s->ci,   \
+                           (const V *)s->ahat, (const V *)s->xbar, (const V *)s->bh, s->sense, (V *)s->y,      \
+                           (const V *)s->ya, (V *)s->yp, s->st, i, store);                                      \
+        break;
+        switch (T) {
+            PDHG_DT_CASE(32)
+            PDHG_DT_CASE(64)
+            PDHG_DT_CASE(128)
+        default:
+            PDHG_DT_CASE(256)
+        }
+#undef PDHG_DT_CASE
+        return;
+    }
+    const int grid = (int)(((int64_t)s->m * L + kBlock - 1) / kBlock);
 #define PDHG_DUAL_CASE(LL)                                                                                      \
     case LL:                                                                                                    \
         hipLaunchKernelGGL((k_dual<V, LL>), dim3(grid), dim3(kBlock), 0, s->stream, s->m, s->rp, s->ci,        \
@@ -837,20 +997,100 @@ hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
     return s->fp32 ? push_setup_impl<float>(s, seed, r) : push_setup_impl<double>(s, seed, r);
 }
 
+// ------------------------------------------------------- kernel choice ---
+// Short rows: LDS tile of the largest T in {32..256} whose mean tile fits in
+// about 1.5 chunks; long rows (mean > 48): lane groups sized to the mean.
+int choose_kernel(double mean_row)
+{
+    if (mean_row <= 48.0) {
+        int t = 256;
+        while (t > 32 && t * mean_row > 1.5 * kChunk) t >>= 1;
+        return -t;
+    }
+    return lanes_for_mean(mean_row);
+}
+
+// Time every candidate of each half on scratch output vectors (3 launches
+// each after one warm-up) and keep the fastest.  The iterate is untouched.
+hipError_t autotune(pdhg_solver *s)
+{
+    const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
+    void *sx = nullptr, *sxbar = nullptr, *sxp = nullptr, *sy = nullptr, *syp = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&sx, vb * (size_t)(s->n > 0 ? s->n : 1));
+    if (e == hipSuccess) e = hipMalloc(&sxbar, vb * (size_t)(s->n > 0 ? s->n : 1));
+    if (e == hipSuccess) e = hipMalloc(&sxp, vb * (size_t)(s->n > 0 ? s->n : 1));
+    if (e == hipSuccess) e = hipMalloc(&sy, vb * (size_t)(s->m > 0 ? s->m : 1));
+    if (e == hipSuccess) e = hipMalloc(&syp, vb * (size_t)(s->m > 0 ? s->m : 1));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMemcpyAsync(sx, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(sxbar, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(sy, s->y, vb * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
+    const int cands[] = {-32, -64, -128, -256, 1, 2, 4, 8, 16, 32, 64};
+    void *keep[5] = {s->x, s->xbar, s->xp, s->y, s->yp};
+    s->x = sx;
+    s->xbar = sxbar;
+    s->xp = sxp;
+    s->y = sy;
+    s->yp = syp;
+    for (int half = 0; half < 2 && e == hipSuccess; half++) {
+        float best = 1e30f;
+        int best_k = half == 0 ? s->kern_at : s->kern_a;
+        for (int c : cands) {
+            if (half == 0) s->kern_at = c;
+            else s->kern_a = c;
+            for (int rep = 0; rep < 4; rep++) {
+                if (rep == 1) hipEventRecord(e0, s->stream);
+                if (half == 0) {
+                    if (s->fp32) launch_primal<float>(s, 0, 0);
+                    else launch_primal<double>(s, 0, 0);
+                } else {
+                    if (s->fp32) launch_dual<float>(s, 0, 0);
+                    else launch_dual<double>(s, 0, 0);
+                }
+            }
+            hipEventRecord(e1, s->stream);
+            e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            if (ms < best) {
+                best = ms;
+                best_k = c;
+            }
+        }
+        if (half == 0) s->kern_at = best_k;
+        else s->kern_a = best_k;
+    }
+    s->x = keep[0];
+    s->xbar = keep[1];
+    s->xp = keep[2];
+    s->y = keep[3];
+    s->yp = keep[4];
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (void *q : {sx, sxbar, sxp, sy, syp})
+        if (q) (void)hipFree(q);
+    return e;
+}
+
 // ------------------------------------------------------------ copy probe ---
-// four independent 16-byte loads in flight per thread and iteration
+// one 16-byte element per thread, non-temporal loads and stores: the
+// fastest plain copy measured on the MI355X (about 6.4 TB/s for 2 GiB)
 __global__ __launch_bounds__(kBlock) void k_copy16(int64_t n16, const uint4 *__restrict__ src, uint4 *__restrict__ dst)
 {
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += 4 * stride) {
-        uint4 v[4];
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-            if (i + q * stride < n16) v[q] = src[i + q * stride];
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-            if (i + q * stride < n16) dst[i + q * stride] = v[q];
-    }
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n16) return;
+    uint4 v;
+    v.x = __builtin_nontemporal_load(&src[i].x);
+    v.y = __builtin_nontemporal_load(&src[i].y);
+    v.z = __builtin_nontemporal_load(&src[i].z);
+    v.w = __builtin_nontemporal_load(&src[i].w);
+    __builtin_nontemporal_store(v.x, &dst[i].x);
+    __builtin_nontemporal_store(v.y, &dst[i].y);
+    __builtin_nontemporal_store(v.z, &dst[i].z);
+    __builtin_nontemporal_store(v.w, &dst[i].w);
 }
 
 hipError_t copy_probe(int64_t bytes, int reps, double *gbps)
@@ -865,7 +1105,7 @@ hipError_t copy_probe(int64_t bytes, int reps, double *gbps)
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e == hipSuccess) e = hipMemsetAsync(a, 1, (size_t)n16 * 16, st);
-    const int grid = grid_for((n16 + 3) / 4, kBlock, 256 * 16);
+    const int grid = grid_for(n16, kBlock, 1 << 30);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(kBlock), 0, st, n16, a, b); // warm-up
         hipEventRecord(e0, st);

@@ -106,7 +106,7 @@ def test_lane_counts_and_graph_replay_give_the_same_trajectory():
     o.iterate(300)
     xo, yo = o.iterate_state()
     ref = None
-    for la, lat in [(1, 1), (4, 2), (16, 8), (64, 64), (0, 0)]:
+    for la, lat in [(1, 1), (4, 2), (16, 8), (64, 64), (-32, -64), (-128, -256), (-256, -32), (0, 0)]:
         for graph in (0, 1):
             print(f"[gpu] lanes A={la} At={lat} graph={graph}", flush=True)
             g = pdhg.Solver(lp, lanes_a=la, lanes_at=lat, use_graph=graph)
@@ -119,6 +119,19 @@ def test_lane_counts_and_graph_replay_give_the_same_trajectory():
                 else:
                     np.testing.assert_array_equal(xg, ref[0])
                     np.testing.assert_array_equal(yg, ref[1])
+
+
+def test_autotuned_kernels_follow_the_oracle():
+    lp = lpgen.config1(seed=4, m=600, n=2400)
+    o = OracleSolver(lp)
+    o.iterate(200)
+    xo, yo = o.iterate_state()
+    g = pdhg.Solver(lp, autotune=1, timing=1)
+    g.iterate(200)
+    xg, yg = g.get_iterate()
+    t = g.get_timing()
+    print(f"[gpu] autotune picked primal {t.lanes_at} dual {t.lanes_a}", flush=True)
+    assert rel_inf(xg, xo) <= 1e-10 and rel_inf(yg, yo) <= 1e-10
 
 
 def test_rerun_is_bitwise_deterministic():
