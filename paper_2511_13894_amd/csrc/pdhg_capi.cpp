@@ -261,9 +261,9 @@ int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const
         return fail(PDHG_ERR_INVALID_ARG, "invalid parameter");
     for (int32_t k : {p.lanes_a, p.lanes_at}) {
         const bool lane_ok = k >= 1 && k <= 64 && !(k & (k - 1));
-        const bool tile_ok = k == -32 || k == -64 || k == -128 || k == -256;
+        const bool tile_ok = k == -32 || k == -64 || k == -128 || k == -256 || k == -1032 || k == -1064;
         if (k != 0 && !lane_ok && !tile_ok)
-            return fail(PDHG_ERR_INVALID_ARG, "lanes must be 0, a power of two in 1..64, or -32/-64/-128/-256");
+            return fail(PDHG_ERR_INVALID_ARG, "lanes must be 0, a power of two in 1..64, or one of -32/-64/-128/-256/-1032/-1064");
     }
 
     // canonical rows (ascending columns, duplicates summed), host side ingest
@@ -346,7 +346,8 @@ int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const
         vall(&s->ahat, NZ);
         vall(&s->ahat_t, NZ);
         for (void **q : {&s->x, &s->xa, &s->xbar, &s->xp, &s->ch, &s->lh, &s->uh, &s->xs}) vall(q, N);
-        for (void **q : {&s->y, &s->ya, &s->yp, &s->bh, &s->ys}) vall(q, M);
+        for (void **q : {&s->y, &s->ya, &s->yp, &s->bh, &s->ys}) // m-vectors stay float64
+            hip_check(hipMalloc(q, sizeof(double) * (M > 0 ? M : 1)), "hipMalloc");
         dalloc(&s->ax, M);
         dalloc(&s->aty, N);
         dalloc(&s->xu, N);
@@ -441,7 +442,7 @@ int pdhg_corner_push(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
         const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
         // CP1: the solve's candidate (x, y) and z on the original model
         HIPCHK(hipMemcpyAsync(s->xs, s->xp, vb * (size_t)s->n, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(s->ys, s->yp, vb * (size_t)s->m, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(s->ys, s->yp, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
         HIPCHK(unscale(s, s->xs, s->ys, s->xu, s->yu));
         HIPCHK(report(s, s->xu, s->yu, s->zsol, &r->before));
         // CP2-CP5: bounds, senses, objective, start (x, 0), new weight and restart state
@@ -572,14 +573,16 @@ int pdhg_get_timing(pdhg_solver *s, pdhg_timing *t)
         t->primal_ms = s->t_primal_ms / (double)s->t_samples;
         t->dual_ms = s->t_dual_ms / (double)s->t_samples;
     }
-    // byte model of the two kernels (v = bytes per working value, 4 per index)
+    // byte model of the two kernels: v = bytes per matrix value and n-vector
+    // entry (4 in the mixed mode, 8 otherwise), m-vectors are float64, 4 bytes
+    // per index
     const int64_t v = s->fp32 ? 4 : 8, m = s->m, n = s->n, nz = s->nnz;
     // primal: row pointers, indices + values, y gathered once, reads x, chat,
     // x_anchor, lhat, uhat, writes x, xbar
-    t->bytes_primal = 4 * (n + 1) + (4 + v) * nz + v * m + 7 * v * n;
+    t->bytes_primal = 4 * (n + 1) + (4 + v) * nz + 8 * m + 7 * v * n;
     // dual: row pointers, indices + values, xbar gathered once, reads y, bhat,
     // y_anchor, sense byte, writes y
-    t->bytes_dual = 4 * (m + 1) + (4 + v) * nz + v * n + 4 * v * m + m;
+    t->bytes_dual = 4 * (m + 1) + (4 + v) * nz + v * n + 4 * 8 * m + m;
     t->lanes_at = s->kern_at;
     t->lanes_a = s->kern_a;
     return PDHG_OK;

@@ -19,13 +19,59 @@ __device__ __forceinline__ void halpern_weights(const DevState *st, int i, doubl
     g = st->gamma;
 }
 
+// Storage: the matrix values and every n-vector (x, x_anchor, xbar, x+, chat,
+// lhat, uhat) are V (float in the mixed mode, double otherwise); every
+// m-vector (y, y_anchor, y+, bhat) is double.  All arithmetic — products,
+// sums, projections, Halpern averages — is double in registers; only the
+// stores round to V.  (With y in float the reduced cost chat - Ahat'y loses
+// its low bits and the large primal step tau = eta/omega amplifies that
+// rounding into x; keeping the short m-vectors in double removes it.)
+
 // Primal half, one row of the transpose (= one column j of A) per group of L
 // lanes:  g = Ahat' y;  x+ = clamp(x - tau (chat - g), lhat, uhat);
 // xbar = 2 x+ - x;  x <- w ((1+gamma) x+ - gamma x) + wa x_anchor.
 // At the last iteration before a check the candidate x+ is stored as well.
+template <typename V>
+__device__ __forceinline__ void primal_update(int64_t j, double g, double xj, double cj, double lo, double hi,
+                                              double aj, V *__restrict__ x, V *__restrict__ xbar,
+                                              V *__restrict__ xp, const DevState *__restrict__ st, int i,
+                                              int store_cand)
+{
+    double xn = xj - st->tau * (cj - g);
+    xn = xn < lo ? lo : xn;
+    xn = xn > hi ? hi : xn;
+    xbar[j] = (V)(2.0 * xn - xj);
+    if (store_cand) xp[j] = (V)xn;
+    if (st->halpern) {
+        double w, wa, gm;
+        halpern_weights(st, i, w, wa, gm);
+        x[j] = (V)(w * ((1.0 + gm) * xn - gm * xj) + wa * aj);
+    } else {
+        x[j] = (V)xn;
+    }
+}
+
+// Dual half:  y+ = proj_Y(y + sigma (bhat - h));  y <- w ((1+gamma) y+ - gamma y) + wa y_anchor.
+__device__ __forceinline__ void dual_update(int64_t r, double h, double yr, double br, double ar, int8_t sn,
+                                            double *__restrict__ y, double *__restrict__ yp,
+                                            const DevState *__restrict__ st, int i, int store_cand)
+{
+    double yn = yr + st->sigma * (br - h);
+    if (sn == '<') yn = yn < 0.0 ? yn : 0.0;
+    else if (sn == '>') yn = yn > 0.0 ? yn : 0.0;
+    if (store_cand) yp[r] = yn;
+    if (st->halpern) {
+        double w, wa, gm;
+        halpern_weights(st, i, w, wa, gm);
+        y[r] = w * ((1.0 + gm) * yn - gm * yr) + wa * ar;
+    } else {
+        y[r] = yn;
+    }
+}
+
 template <typename V, int L>
 __global__ __launch_bounds__(kBlock) void k_primal(int n, const int *__restrict__ tp, const int *__restrict__ ti,
-                                                  const V *__restrict__ atv, const V *__restrict__ y,
+                                                  const V *__restrict__ atv, const double *__restrict__ y,
                                                   const V *__restrict__ ch, const V *__restrict__ lh,
                                                   const V *__restrict__ uh, V *__restrict__ x,
                                                   const V *__restrict__ xa, V *__restrict__ xbar, V *__restrict__ xp,
@@ -36,89 +82,66 @@ __global__ __launch_bounds__(kBlock) void k_primal(int n, const int *__restrict_
     const int64_t j = gi / L;
     const int lane = (int)(gi % L);
     if (j >= n) return;
-    V acc = 0;
+    double acc = 0.0;
     const int beg = tp[j], end = tp[j + 1];
-    for (int e = beg + lane; e < end; e += L) acc += atv[e] * y[ti[e]];
+    for (int e = beg + lane; e < end; e += L) acc += (double)atv[e] * y[ti[e]];
     acc = group_sum<L>(acc);
     if (lane != 0) return;
-    const V tau = (V)st->tau;
-    const V xj = x[j];
-    V xn = xj - tau * (ch[j] - acc);
-    xn = xn < lh[j] ? lh[j] : xn;
-    xn = xn > uh[j] ? uh[j] : xn;
-    xbar[j] = (V)2 * xn - xj;
-    if (store_cand) xp[j] = xn;
-    if (st->halpern) {
-        double w, wa, g;
-        halpern_weights(st, i, w, wa, g);
-        x[j] = (V)w * (((V)1 + (V)g) * xn - (V)g * xj) + (V)wa * xa[j];
-    } else {
-        x[j] = xn;
-    }
+    primal_update<V>(j, acc, (double)x[j], (double)ch[j], (double)lh[j], (double)uh[j], (double)xa[j], x, xbar, xp,
+                     st, i, store_cand);
 }
 
-// Dual half, one row of A per group of L lanes:  h = Ahat xbar;
-// y+ = proj_Y(y + sigma (bhat - h));  y <- w ((1+gamma) y+ - gamma y) + wa y_anchor.
+// Dual half, one row of A per group of L lanes:  h = Ahat xbar.
 template <typename V, int L>
 __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ rp, const int *__restrict__ ci,
                                                 const V *__restrict__ av, const V *__restrict__ xbar,
-                                                const V *__restrict__ bh, const int8_t *__restrict__ sense,
-                                                V *__restrict__ y, const V *__restrict__ ya, V *__restrict__ yp,
-                                                const DevState *__restrict__ st, int i, int store_cand)
+                                                const double *__restrict__ bh, const int8_t *__restrict__ sense,
+                                                double *__restrict__ y, const double *__restrict__ ya,
+                                                double *__restrict__ yp, const DevState *__restrict__ st, int i,
+                                                int store_cand)
 {
     if (st->done) return;
     const int64_t gi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int64_t r = gi / L;
     const int lane = (int)(gi % L);
     if (r >= m) return;
-    V acc = 0;
+    double acc = 0.0;
     const int beg = rp[r], end = rp[r + 1];
-    for (int e = beg + lane; e < end; e += L) acc += av[e] * xbar[ci[e]];
+    for (int e = beg + lane; e < end; e += L) acc += (double)av[e] * (double)xbar[ci[e]];
     acc = group_sum<L>(acc);
     if (lane != 0) return;
-    const V sig = (V)st->sigma;
-    const V yr = y[r];
-    V yn = yr + sig * (bh[r] - acc);
-    const int8_t s = sense[r];
-    if (s == '<') yn = yn < (V)0 ? yn : (V)0;
-    else if (s == '>') yn = yn > (V)0 ? yn : (V)0;
-    if (store_cand) yp[r] = yn;
-    if (st->halpern) {
-        double w, wa, g;
-        halpern_weights(st, i, w, wa, g);
-        y[r] = (V)w * (((V)1 + (V)g) * yn - (V)g * yr) + (V)wa * ya[r];
-    } else {
-        y[r] = yn;
-    }
+    dual_update(r, acc, y[r], bh[r], ya[r], sense[r], y, yp, st, i, store_cand);
 }
 
 // ------------------------------------------------- LDS-tiled short rows ---
-// A workgroup owns a tile of T consecutive rows.  All entries of the tile are
-// streamed in chunks of kChunk: every thread loads entries k, k+256, ... with
-// their gathered vector value (coalesced index/value loads, several loads in
-// flight per thread), writes the products to LDS, and G = 256/T threads per
-// row then sum their row's products in a fixed order.  The row sums go to LDS
-// and threads 0..T-1 run the update epilogue on contiguous rows, with the
-// epilogue's vector loads issued before the product phase.
-constexpr int kChunk = 2048;
+// A workgroup of NT threads owns a tile of T consecutive rows.  The tile's
+// entries stream through LDS in chunks of 8 NT: every thread loads entries
+// k, k+NT, ... with their gathered vector value (coalesced index and value
+// loads), writes the products to LDS, and G = NT/T threads per row sum their
+// row's products in a fixed order.  Row sums go to LDS and threads 0..T-1 run
+// the update epilogue on contiguous rows, with the epilogue's vector loads
+// issued before the product phase.
+constexpr int kChunk = 2048; // entries per LDS chunk of a 256-thread tile (8 per thread)
 
-template <typename V, int T>
+template <typename VM, typename VV, int T, int NT>
 __device__ __forceinline__ void tile_row_sums(int r0, int rows, const int *__restrict__ ptr,
-                                              const int *__restrict__ idx, const V *__restrict__ val,
-                                              const V *__restrict__ vec, int *s_ptr, V *s_prod, V *s_sum)
+                                              const int *__restrict__ idx, const VM *__restrict__ val,
+                                              const VV *__restrict__ vec, int *s_ptr, double *s_prod,
+                                              double *s_sum)
 {
-    constexpr int G = kBlock / T;
+    constexpr int G = NT / T;
+    constexpr int C = 8 * NT;
     const int tid = threadIdx.x;
-    for (int k = tid; k <= rows; k += kBlock) s_ptr[k] = ptr[r0 + k];
+    for (int k = tid; k <= rows; k += NT) s_ptr[k] = ptr[r0 + k];
     __syncthreads();
     const int beg = s_ptr[0], end = s_ptr[rows];
     const int my_row = tid / G, sub = tid % G;
     const bool have = my_row < rows;
     const int rb = have ? s_ptr[my_row] : 0, re = have ? s_ptr[my_row + 1] : 0;
-    V acc = 0;
-    for (int cs = beg; cs < end; cs += kChunk) {
-        const int ce = cs + kChunk < end ? cs + kChunk : end;
-        for (int k = cs + tid; k < ce; k += kBlock) s_prod[k - cs] = val[k] * vec[idx[k]];
+    double acc = 0.0;
+    for (int cs = beg; cs < end; cs += C) {
+        const int ce = cs + C < end ? cs + C : end;
+        for (int k = cs + tid; k < ce; k += NT) s_prod[k - cs] = (double)val[k] * (double)vec[idx[k]];
         __syncthreads();
         const int lo = rb > cs ? rb : cs, hi = re < ce ? re : ce;
         for (int q = lo + sub; q < hi; q += G) acc += s_prod[q - cs];
@@ -129,67 +152,55 @@ __device__ __forceinline__ void tile_row_sums(int r0, int rows, const int *__res
     __syncthreads();
 }
 
-template <typename V, int T>
-__global__ __launch_bounds__(kBlock) void k_primal_tiled(int n, const int *__restrict__ tp, const int *__restrict__ ti,
-                                                        const V *__restrict__ atv, const V *__restrict__ y,
-                                                        const V *__restrict__ ch, const V *__restrict__ lh,
-                                                        const V *__restrict__ uh, V *__restrict__ x,
-                                                        const V *__restrict__ xa, V *__restrict__ xbar,
-                                                        V *__restrict__ xp, const DevState *__restrict__ st, int i,
-                                                        int store_cand)
+template <typename V, int T, int NT>
+__global__ __launch_bounds__(NT) void k_primal_tiled(int n, const int *__restrict__ tp, const int *__restrict__ ti,
+                                                    const V *__restrict__ atv, const double *__restrict__ y,
+                                                    const V *__restrict__ ch, const V *__restrict__ lh,
+                                                    const V *__restrict__ uh, V *__restrict__ x,
+                                                    const V *__restrict__ xa, V *__restrict__ xbar,
+                                                    V *__restrict__ xp, const DevState *__restrict__ st, int i,
+                                                    int store_cand)
 {
     __shared__ int s_ptr[T + 1];
-    __shared__ V s_prod[kChunk];
-    __shared__ V s_sum[T];
+    __shared__ double s_prod[8 * NT];
+    __shared__ double s_sum[T];
     if (st->done) return;
     const int r0 = xcd_block(blockIdx.x, gridDim.x) * T;
     const int rows = n - r0 < T ? n - r0 : T;
     const int tid = threadIdx.x;
     const bool mine = tid < rows;
     const int j = r0 + tid;
-    V xj = 0, cj = 0, lo = 0, hi = 0, aj = 0;
+    double xj = 0, cj = 0, lo = 0, hi = 0, aj = 0;
     if (mine) { // epilogue operands, independent of the product
-        xj = x[j];
-        cj = ch[j];
-        lo = lh[j];
-        hi = uh[j];
-        aj = xa[j];
+        xj = (double)x[j];
+        cj = (double)ch[j];
+        lo = (double)lh[j];
+        hi = (double)uh[j];
+        aj = (double)xa[j];
     }
-    tile_row_sums<V, T>(r0, rows, tp, ti, atv, y, s_ptr, s_prod, s_sum);
+    tile_row_sums<V, double, T, NT>(r0, rows, tp, ti, atv, y, s_ptr, s_prod, s_sum);
     if (!mine) return;
-    const V tau = (V)st->tau;
-    V xn = xj - tau * (cj - s_sum[tid]);
-    xn = xn < lo ? lo : xn;
-    xn = xn > hi ? hi : xn;
-    xbar[j] = (V)2 * xn - xj;
-    if (store_cand) xp[j] = xn;
-    if (st->halpern) {
-        double w, wa, g;
-        halpern_weights(st, i, w, wa, g);
-        x[j] = (V)w * (((V)1 + (V)g) * xn - (V)g * xj) + (V)wa * aj;
-    } else {
-        x[j] = xn;
-    }
+    primal_update<V>(j, s_sum[tid], xj, cj, lo, hi, aj, x, xbar, xp, st, i, store_cand);
 }
 
-template <typename V, int T>
-__global__ __launch_bounds__(kBlock) void k_dual_tiled(int m, const int *__restrict__ rp, const int *__restrict__ ci,
-                                                      const V *__restrict__ av, const V *__restrict__ xbar,
-                                                      const V *__restrict__ bh, const int8_t *__restrict__ sense,
-                                                      V *__restrict__ y, const V *__restrict__ ya,
-                                                      V *__restrict__ yp, const DevState *__restrict__ st, int i,
-                                                      int store_cand)
+template <typename V, int T, int NT>
+__global__ __launch_bounds__(NT) void k_dual_tiled(int m, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                  const V *__restrict__ av, const V *__restrict__ xbar,
+                                                  const double *__restrict__ bh, const int8_t *__restrict__ sense,
+                                                  double *__restrict__ y, const double *__restrict__ ya,
+                                                  double *__restrict__ yp, const DevState *__restrict__ st, int i,
+                                                  int store_cand)
 {
     __shared__ int s_ptr[T + 1];
-    __shared__ V s_prod[kChunk];
-    __shared__ V s_sum[T];
+    __shared__ double s_prod[8 * NT];
+    __shared__ double s_sum[T];
     if (st->done) return;
     const int r0 = xcd_block(blockIdx.x, gridDim.x) * T;
     const int rows = m - r0 < T ? m - r0 : T;
     const int tid = threadIdx.x;
     const bool mine = tid < rows;
     const int r = r0 + tid;
-    V yr = 0, br = 0, ar = 0;
+    double yr = 0, br = 0, ar = 0;
     int8_t sn = '=';
     if (mine) {
         yr = y[r];
@@ -197,20 +208,9 @@ __global__ __launch_bounds__(kBlock) void k_dual_tiled(int m, const int *__restr
         ar = ya[r];
         sn = sense[r];
     }
-    tile_row_sums<V, T>(r0, rows, rp, ci, av, xbar, s_ptr, s_prod, s_sum);
+    tile_row_sums<V, V, T, NT>(r0, rows, rp, ci, av, xbar, s_ptr, s_prod, s_sum);
     if (!mine) return;
-    const V sig = (V)st->sigma;
-    V yn = yr + sig * (br - s_sum[tid]);
-    if (sn == '<') yn = yn < (V)0 ? yn : (V)0;
-    else if (sn == '>') yn = yn > (V)0 ? yn : (V)0;
-    if (store_cand) yp[r] = yn;
-    if (st->halpern) {
-        double w, wa, g;
-        halpern_weights(st, i, w, wa, g);
-        y[r] = (V)w * (((V)1 + (V)g) * yn - (V)g * yr) + (V)wa * ar;
-    } else {
-        y[r] = yn;
-    }
+    dual_update(r, s_sum[tid], yr, br, ar, sn, y, yp, st, i, store_cand);
 }
 
 template <typename V>
@@ -218,22 +218,25 @@ static void launch_primal(pdhg_solver *s, int i, int store)
 {
     const int L = s->kern_at;
     if (s->n <= 0) return;
-    if (L < 0) { // LDS-tiled kernel with a tile of -L rows
+    if (L < 0) { // LDS-tiled kernel: -T (256 threads) or -(1000 + T) (64 threads)
         const int T = -L;
-        const int grid = (s->n + T - 1) / T;
-#define PDHG_PT_CASE(TT)                                                                                        \
+        const int rows_per = T > 1000 ? T - 1000 : T;
+        const int grid = (s->n + rows_per - 1) / rows_per;
+#define PDHG_PT_CASE(TT, RR, NT)                                                                                \
     case TT:                                                                                                    \
-        hipLaunchKernelGGL((k_primal_tiled<V, TT>), dim3(grid), dim3(kBlock), 0, s->stream, s->n, s->tp, s->ti, \
-                           (const V *)s->ahat_t, (const V *)s->y, (const V *)s->ch, (const V *)s->lh,          \
+        hipLaunchKernelGGL((k_primal_tiled<V, RR, NT>), dim3(grid), dim3(NT), 0, s->stream, s->n, s->tp, s->ti, \
+                           (const V *)s->ahat_t, (const double *)s->y, (const V *)s->ch, (const V *)s->lh,          \
                            (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i,  \
                            store);                                                                              \
         break;
         switch (T) {
-            PDHG_PT_CASE(32)
-            PDHG_PT_CASE(64)
-            PDHG_PT_CASE(128)
+            PDHG_PT_CASE(32, 32, 256)
+            PDHG_PT_CASE(64, 64, 256)
+            PDHG_PT_CASE(128, 128, 256)
+            PDHG_PT_CASE(1032, 32, 64)
+            PDHG_PT_CASE(1064, 64, 64)
         default:
-            PDHG_PT_CASE(256)
+            PDHG_PT_CASE(256, 256, 256)
         }
 #undef PDHG_PT_CASE
         return;
@@ -242,7 +245,7 @@ static void launch_primal(pdhg_solver *s, int i, int store)
 #define PDHG_PRIMAL_CASE(LL)                                                                                    \
     case LL:                                                                                                    \
         hipLaunchKernelGGL((k_primal<V, LL>), dim3(grid), dim3(kBlock), 0, s->stream, s->n, s->tp, s->ti,      \
-                           (const V *)s->ahat_t, (const V *)s->y, (const V *)s->ch, (const V *)s->lh,          \
+                           (const V *)s->ahat_t, (const double *)s->y, (const V *)s->ch, (const V *)s->lh,          \
                            (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i,  \
                            store);                                                                              \
         break;
@@ -266,19 +269,22 @@ static void launch_dual(pdhg_solver *s, int i, int store)
     if (s->m <= 0) return;
     if (L < 0) {
         const int T = -L;
-        const int grid = (s->m + T - 1) / T;
-#define PDHG_DT_CASE(TT)                                                                                        \
+        const int rows_per = T > 1000 ? T - 1000 : T;
+        const int grid = (s->m + rows_per - 1) / rows_per;
+#define PDHG_DT_CASE(TT, RR, NT)                                                                                \
     case TT:                                                                                                    \
-        hipLaunchKernelGGL((k_dual_tiled<V, TT>), dim3(grid), dim3(kBlock), 0, s->stream, s->m, s->rp, s->ci,   \
-                           (const V *)s->ahat, (const V *)s->xbar, (const V *)s->bh, s->sense, (V *)s->y,      \
-                           (const V *)s->ya, (V *)s->yp, s->st, i, store);                                      \
+        hipLaunchKernelGGL((k_dual_tiled<V, RR, NT>), dim3(grid), dim3(NT), 0, s->stream, s->m, s->rp, s->ci,   \
+                           (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bh, s->sense, (double *)s->y,\
+                           (const double *)s->ya, (double *)s->yp, s->st, i, store);                                      \
         break;
         switch (T) {
-            PDHG_DT_CASE(32)
-            PDHG_DT_CASE(64)
-            PDHG_DT_CASE(128)
+            PDHG_DT_CASE(32, 32, 256)
+            PDHG_DT_CASE(64, 64, 256)
+            PDHG_DT_CASE(128, 128, 256)
+            PDHG_DT_CASE(1032, 32, 64)
+            PDHG_DT_CASE(1064, 64, 64)
         default:
-            PDHG_DT_CASE(256)
+            PDHG_DT_CASE(256, 256, 256)
         }
 #undef PDHG_DT_CASE
         return;
@@ -287,8 +293,8 @@ static void launch_dual(pdhg_solver *s, int i, int store)
 #define PDHG_DUAL_CASE(LL)                                                                                      \
     case LL:                                                                                                    \
         hipLaunchKernelGGL((k_dual<V, LL>), dim3(grid), dim3(kBlock), 0, s->stream, s->m, s->rp, s->ci,        \
-                           (const V *)s->ahat, (const V *)s->xbar, (const V *)s->bh, s->sense, (V *)s->y,      \
-                           (const V *)s->ya, (V *)s->yp, s->st, i, store);                                      \
+                           (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bh, s->sense, (double *)s->y,\
+                           (const double *)s->ya, (double *)s->yp, s->st, i, store);                                      \
         break;
     switch (L) {
         PDHG_DUAL_CASE(1)
@@ -306,10 +312,9 @@ static void launch_dual(pdhg_solver *s, int i, int store)
 // ---------------------------------------------------------------- checks ---
 // Row part of a check on the candidate (xc, yc) of the scaled current model:
 // rP_hat (current senses), unscaled rP = rP_hat / Dr, b'y, ||yc - ya||^2.
-template <typename V>
-__global__ __launch_bounds__(kBlock) void k_check_rows(int m, const double *__restrict__ ax, const V *__restrict__ bh,
+__global__ __launch_bounds__(kBlock) void k_check_rows(int m, const double *__restrict__ ax, const double *__restrict__ bh,
                                                       const int8_t *__restrict__ sense, const double *__restrict__ dr,
-                                                      const V *__restrict__ yc, const V *__restrict__ ya,
+                                                      const double *__restrict__ yc, const double *__restrict__ ya,
                                                       double *__restrict__ part, int nblk, const DevState *st)
 {
     if (st->done) return;
@@ -483,8 +488,8 @@ __global__ __launch_bounds__(kBlock) void k_check_final(DevState *st, const doub
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_restart_apply(int n, int m, const DevState *st, V *__restrict__ x,
                                                          V *__restrict__ xa, const V *__restrict__ xp,
-                                                         V *__restrict__ y, V *__restrict__ ya,
-                                                         const V *__restrict__ yp)
+                                                         double *__restrict__ y, double *__restrict__ ya,
+                                                         const double *__restrict__ yp)
 {
     if (!st->restart_flag || st->done) return;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
@@ -494,7 +499,7 @@ __global__ __launch_bounds__(kBlock) void k_restart_apply(int n, int m, const De
             xa[i] = v;
         } else {
             const int64_t r = i - n;
-            const V v = yp[r];
+            const double v = yp[r];
             y[r] = v;
             ya[r] = v;
         }
@@ -509,14 +514,14 @@ __global__ void k_advance(DevState *st, int len)
 }
 
 template <typename V>
-static void check_impl(pdhg_solver *s, const V *xc, const V *yc, double *pm, double *pn)
+static void check_impl(pdhg_solver *s, const V *xc, const double *yc, double *pm, double *pn)
 {
     hipStream_t st = s->stream;
     spmv<V, V, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
-    spmv<V, V, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, (const V *)s->ahat_t, yc, s->aty);
+    spmv<V, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, (const V *)s->ahat_t, yc, s->aty);
     const int gm = s->red_blocks_m, gn = s->red_blocks_n;
-    hipLaunchKernelGGL((k_check_rows<V>), dim3(gm), dim3(kBlock), 0, st, s->m, s->ax, (const V *)s->bh, s->sense, s->dr,
-                       yc, (const V *)s->ya, pm, gm, s->st);
+    hipLaunchKernelGGL(k_check_rows, dim3(gm), dim3(kBlock), 0, st, s->m, s->ax, (const double *)s->bh, s->sense, s->dr,
+                       yc, (const double *)s->ya, pm, gm, s->st);
     hipLaunchKernelGGL((k_check_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->aty, (const V *)s->ch,
                        (const V *)s->lh, (const V *)s->uh, s->dc, xc, (const V *)s->xa, pn, gn, s->st);
 }
@@ -528,7 +533,7 @@ hipError_t launch_check(pdhg_solver *s, int mode, int len)
     double *pm = s->partials;
     double *pn = s->partials + (size_t)(Q_COUNT + 1) * gm;
     if (s->fp32)
-        check_impl<float>(s, (const float *)(use_cand ? s->xp : s->x), (const float *)(use_cand ? s->yp : s->y), pm, pn);
+        check_impl<float>(s, (const float *)(use_cand ? s->xp : s->x), (const double *)(use_cand ? s->yp : s->y), pm, pn);
     else
         check_impl<double>(s, (const double *)(use_cand ? s->xp : s->x), (const double *)(use_cand ? s->yp : s->y), pm,
                            pn);
@@ -537,8 +542,8 @@ hipError_t launch_check(pdhg_solver *s, int mode, int len)
         const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
         if (s->fp32)
             hipLaunchKernelGGL((k_restart_apply<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->st,
-                               (float *)s->x, (float *)s->xa, (const float *)s->xp, (float *)s->y, (float *)s->ya,
-                               (const float *)s->yp);
+                               (float *)s->x, (float *)s->xa, (const float *)s->xp, (double *)s->y, (double *)s->ya,
+                               (const double *)s->yp);
         else
             hipLaunchKernelGGL((k_restart_apply<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->st,
                                (double *)s->x, (double *)s->xa, (const double *)s->xp, (double *)s->y, (double *)s->ya,
@@ -598,7 +603,7 @@ hipError_t capture_cycle(pdhg_solver *s, int len, int mode)
 // ----------------------------------------------------------- phase start ---
 // partial sums of chat^2 (cols) and bhat^2 (rows) for the initial weight
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_sumsq2(int n, const V *__restrict__ a, int m, const V *__restrict__ bvec,
+__global__ __launch_bounds__(kBlock) void k_sumsq2(int n, const V *__restrict__ a, int m, const double *__restrict__ bvec,
                                                   double *__restrict__ part, int nblk)
 {
     double v[2] = {0.0, 0.0};
@@ -644,8 +649,8 @@ __global__ __launch_bounds__(kBlock) void k_phase_start(DevState *st, const doub
 // x = clamp(0, lhat, uhat), y = 0, anchors = (x, y)
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_start_point(int n, int m, const V *__restrict__ lh, const V *__restrict__ uh,
-                                                       V *__restrict__ x, V *__restrict__ xa, V *__restrict__ y,
-                                                       V *__restrict__ ya)
+                                                       V *__restrict__ x, V *__restrict__ xa, double *__restrict__ y,
+                                                       double *__restrict__ ya)
 {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
         if (i < n) {
@@ -655,15 +660,15 @@ __global__ __launch_bounds__(kBlock) void k_start_point(int n, int m, const V *_
             x[i] = v;
             xa[i] = v;
         } else {
-            y[i - n] = (V)0;
-            ya[i - n] = (V)0;
+            y[i - n] = 0.0;
+            ya[i - n] = 0.0;
         }
     }
 }
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_copy_anchor(int n, int m, const V *__restrict__ x, V *__restrict__ xa,
-                                                       const V *__restrict__ y, V *__restrict__ ya)
+                                                       const double *__restrict__ y, double *__restrict__ ya)
 {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
         if (i < n) xa[i] = x[i];
@@ -678,12 +683,12 @@ static hipError_t phase_start(pdhg_solver *s, bool fresh_start)
     const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
     if (fresh_start)
         hipLaunchKernelGGL((k_start_point<V>), dim3(g), dim3(kBlock), 0, st, s->n, s->m, (const V *)s->lh,
-                           (const V *)s->uh, (V *)s->x, (V *)s->xa, (V *)s->y, (V *)s->ya);
+                           (const V *)s->uh, (V *)s->x, (V *)s->xa, (double *)s->y, (double *)s->ya);
     else
         hipLaunchKernelGGL((k_copy_anchor<V>), dim3(g), dim3(kBlock), 0, st, s->n, s->m, (const V *)s->x, (V *)s->xa,
-                           (const V *)s->y, (V *)s->ya);
+                           (const double *)s->y, (double *)s->ya);
     const int nb = grid_for(s->n > s->m ? s->n : s->m, kBlock, kMaxRedBlocks);
-    hipLaunchKernelGGL((k_sumsq2<V>), dim3(nb), dim3(kBlock), 0, st, s->n, (const V *)s->ch, s->m, (const V *)s->bh,
+    hipLaunchKernelGGL((k_sumsq2<V>), dim3(nb), dim3(kBlock), 0, st, s->n, (const V *)s->ch, s->m, (const double *)s->bh,
                        s->partials, nb);
     hipLaunchKernelGGL(k_phase_start, dim3(1), dim3(kBlock), 0, st, s->st, s->partials, nb);
     hipError_t e = hipGetLastError();
@@ -720,7 +725,7 @@ hipError_t init_iteration(pdhg_solver *s)
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_copy2(int n, int m, const V *__restrict__ a, V *__restrict__ ac,
-                                                 const V *__restrict__ b, V *__restrict__ bc)
+                                                 const double *__restrict__ b, double *__restrict__ bc)
 {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
         if (i < n) ac[i] = a[i];
@@ -734,7 +739,7 @@ hipError_t candidate_from_iterate(pdhg_solver *s)
     const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
     if (s->fp32)
         hipLaunchKernelGGL((k_copy2<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, (const float *)s->x,
-                           (float *)s->xp, (const float *)s->y, (float *)s->yp);
+                           (float *)s->xp, (const double *)s->y, (double *)s->yp);
     else
         hipLaunchKernelGGL((k_copy2<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, (const double *)s->x,
                            (double *)s->xp, (const double *)s->y, (double *)s->yp);
@@ -744,7 +749,7 @@ hipError_t candidate_from_iterate(pdhg_solver *s)
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_unscale(int n, int m, const double *__restrict__ dc,
                                                    const double *__restrict__ dr, const V *__restrict__ xh,
-                                                   const V *__restrict__ yh, double *__restrict__ xo,
+                                                   const double *__restrict__ yh, double *__restrict__ xo,
                                                    double *__restrict__ yo)
 {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
@@ -761,7 +766,7 @@ hipError_t unscale(pdhg_solver *s, const void *xh, const void *yh, double *xo, d
     const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
     if (s->fp32)
         hipLaunchKernelGGL((k_unscale<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->dc, s->dr,
-                           (const float *)xh, (const float *)yh, xo, yo);
+                           (const float *)xh, (const double *)yh, xo, yo);
     else
         hipLaunchKernelGGL((k_unscale<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->dc, s->dr,
                            (const double *)xh, (const double *)yh, xo, yo);
@@ -937,9 +942,8 @@ __global__ __launch_bounds__(kBlock) void k_push_cols(int n, const double *__res
 }
 
 // inequality rows whose slack reduced cost is non-trivial become equalities; y = 0
-template <typename V>
 __global__ __launch_bounds__(kBlock) void k_push_rows(int m, const double *__restrict__ yu, double eps_abs,
-                                                     int8_t *__restrict__ sense, V *__restrict__ y,
+                                                     int8_t *__restrict__ sense, double *__restrict__ y,
                                                      double *__restrict__ part)
 {
     double v[1] = {0.0};
@@ -949,7 +953,7 @@ __global__ __launch_bounds__(kBlock) void k_push_rows(int m, const double *__res
             sense[i] = '=';
             v[0] += 1.0;
         }
-        y[i] = (V)0;
+        y[i] = 0.0;
     }
     block_reduce<1>(v, 0u);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
@@ -980,7 +984,7 @@ static hipError_t push_setup_impl(pdhg_solver *s, uint64_t seed, pdhg_push_resul
     hipLaunchKernelGGL((k_push_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->zsol, (const V *)s->xs, s->dc,
                        s->p.eps_abs, seed, s->p.push_obj_scale, (V *)s->lh, (V *)s->uh, (V *)s->ch, (V *)s->x, pcnt,
                        gn);
-    hipLaunchKernelGGL((k_push_rows<V>), dim3(gm), dim3(kBlock), 0, st, s->m, s->yu, s->p.eps_abs, s->sense, (V *)s->y,
+    hipLaunchKernelGGL(k_push_rows, dim3(gm), dim3(kBlock), 0, st, s->m, s->yu, s->p.eps_abs, s->sense, (double *)s->y,
                        pcnt + 2 * gn);
     hipLaunchKernelGGL(k_sum3, dim3(1), dim3(kBlock), 0, st, pcnt, gn, gm, s->redout);
     hipMemcpyAsync(s->rep_host, s->redout, 3 * sizeof(double), hipMemcpyDeviceToHost, st);
@@ -998,15 +1002,13 @@ hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
 }
 
 // ------------------------------------------------------- kernel choice ---
-// Short rows: LDS tile of the largest T in {32..256} whose mean tile fits in
-// about 1.5 chunks; long rows (mean > 48): lane groups sized to the mean.
+// Short rows: LDS tiles sized from measured c1 / c2 sweeps; long rows
+// (mean > 48): lane groups sized to the mean.
 int choose_kernel(double mean_row)
 {
-    if (mean_row <= 48.0) {
-        int t = 256;
-        while (t > 32 && t * mean_row > 1.5 * kChunk) t >>= 1;
-        return -t;
-    }
+    if (mean_row <= 3.0) return -256;  // very short rows: many rows per tile
+    if (mean_row <= 32.0) return -64;  // measured best for 6 to 24 entries per row
+    if (mean_row <= 48.0) return -32;
     return lanes_for_mean(mean_row);
 }
 
@@ -1020,14 +1022,14 @@ hipError_t autotune(pdhg_solver *s)
     hipError_t e = hipMalloc(&sx, vb * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sxbar, vb * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sxp, vb * (size_t)(s->n > 0 ? s->n : 1));
-    if (e == hipSuccess) e = hipMalloc(&sy, vb * (size_t)(s->m > 0 ? s->m : 1));
-    if (e == hipSuccess) e = hipMalloc(&syp, vb * (size_t)(s->m > 0 ? s->m : 1));
+    if (e == hipSuccess) e = hipMalloc(&sy, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
+    if (e == hipSuccess) e = hipMalloc(&syp, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e == hipSuccess) e = hipMemcpyAsync(sx, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sxbar, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(sy, s->y, vb * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
-    const int cands[] = {-32, -64, -128, -256, 1, 2, 4, 8, 16, 32, 64};
+    if (e == hipSuccess) e = hipMemcpyAsync(sy, s->y, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
+    const int cands[] = {-32, -64, -128, -256, -1032, -1064, 1, 2, 4, 8, 16, 32, 64};
     void *keep[5] = {s->x, s->xbar, s->xp, s->y, s->yp};
     s->x = sx;
     s->xbar = sxbar;

@@ -293,8 +293,8 @@ static void make_scaled(pdhg_solver *s, const double *ahat64)
         hipLaunchKernelGGL((k_scaled_cols<V>), dim3(grid_for(s->n, kBlock, 1 << 30)), dim3(kBlock), 0, st, s->n, s->dc,
                            s->c, s->l, s->u, (V *)s->ch, (V *)s->lh, (V *)s->uh);
     if (s->m > 0)
-        hipLaunchKernelGGL((k_scaled_rows<V>), dim3(grid_for(s->m, kBlock, 1 << 30)), dim3(kBlock), 0, st, s->m, s->dr,
-                           s->b, s->sense0, (V *)s->bh, s->sense);
+        hipLaunchKernelGGL((k_scaled_rows<double>), dim3(grid_for(s->m, kBlock, 1 << 30)), dim3(kBlock), 0, st, s->m,
+                           s->dr, s->b, s->sense0, (double *)s->bh, s->sense);
 }
 
 hipError_t scale_problem(pdhg_solver *s)

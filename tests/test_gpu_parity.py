@@ -106,7 +106,7 @@ def test_lane_counts_and_graph_replay_give_the_same_trajectory():
     o.iterate(300)
     xo, yo = o.iterate_state()
     ref = None
-    for la, lat in [(1, 1), (4, 2), (16, 8), (64, 64), (-32, -64), (-128, -256), (-256, -32), (0, 0)]:
+    for la, lat in [(1, 1), (4, 2), (16, 8), (64, 64), (-32, -64), (-128, -256), (-256, -32), (-1032, -1064), (-1064, -1032), (0, 0)]:
         for graph in (0, 1):
             print(f"[gpu] lanes A={la} At={lat} graph={graph}", flush=True)
             g = pdhg.Solver(lp, lanes_a=la, lanes_at=lat, use_graph=graph)
