@@ -214,6 +214,66 @@ int pdhg_get_timing(pdhg_solver *s, pdhg_timing *t);
  * frees its own buffers.  Errors: INVALID_ARG, OOM, HIP. */
 int pdhg_copy_probe(int64_t bytes, int32_t reps, double *gbps);
 
+/* ------------------------------------------------------------------------
+ * Batch engine: many independent LPs of uneven sizes, solved and then
+ * corner-pushed together (the same method as above for each LP).  The LPs
+ * form one block-diagonal model; every half-iteration is one launch over
+ * instance-aligned row tiles of all LPs; each LP keeps its own scaling, step
+ * size, primal weight, restart state and termination.  LPs advance in
+ * lockstep cycles of check_every iterations; an LP that terminates stops
+ * changing while the others continue.  The push phase starts for every LP
+ * whose solve reached PDHG_OPTIMAL; its checks come at push iterations
+ * push_min_iters, +check_every, ...  params as for pdhg_create (the iteration
+ * kernels are the tiled ones: lanes_* must be 0 or a tile encoding).
+ * ------------------------------------------------------------------------ */
+typedef struct pdhg_batch pdhg_batch;
+
+typedef struct pdhg_lp_desc { /* one LP, same layout and conventions as pdhg_create */
+    int32_t m, n;            /* m >= 1, n >= 1                                      */
+    int64_t nnz;
+    const int64_t *row_ptr;
+    const int32_t *col_idx;
+    const double *val;
+    const double *b, *c, *l, *u; /* l, u may be NULL (0 and +INFINITY)              */
+    const char *sense;           /* may be NULL (all '=')                          */
+} pdhg_lp_desc;
+
+typedef struct pdhg_batch_report {
+    int32_t count;
+    int32_t lanes_at, lanes_a;   /* tiled kernels in use (pdhg_params encoding)     */
+    int32_t pad_;
+    double solve_seconds, push_seconds;
+    int64_t solve_lockstep_iters; /* iterations the batch ran in the solve phase   */
+    int64_t push_lockstep_iters;
+    double primal_ms, dual_ms;   /* mean launch time of the batched halves (timing) */
+    int64_t samples;
+    int64_t bytes_primal, bytes_dual; /* mean algorithmic bytes of the timed launches,
+                                         counting only LPs still iterating          */
+    int64_t total_m, total_n, total_nnz;
+} pdhg_batch_report;
+
+/* Copy `count` LPs (host arrays, caller keeps ownership) and set each up as
+ * pdhg_create does.  Errors: INVALID_ARG (any LP invalid, or sizes beyond
+ * 32-bit indices), OOM, HIP. */
+int pdhg_batch_create(int32_t count, const pdhg_lp_desc *lps, const pdhg_params *p, pdhg_batch **out);
+
+/* Solve every LP (results[count]); STATE if called twice. */
+int pdhg_batch_solve(pdhg_batch *b, pdhg_result *results);
+
+/* Algorithm 1 for every LP whose solve is optimal, seeds[i] selecting LP i's
+ * random objective (results[count]; LPs without a push report their solve
+ * status and 0 push iterations).  Requires pdhg_batch_solve (STATE). */
+int pdhg_batch_corner_push(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *results);
+
+/* Solution of LP i, unscaled (x: n_i, y: m_i, z: n_i; any may be NULL);
+ * after the push x is the pushed x. */
+int pdhg_batch_get_solution(pdhg_batch *b, int32_t i, double *x, double *y, double *z);
+
+/* Aggregate timings and sizes of the batch. */
+int pdhg_batch_get_report(pdhg_batch *b, pdhg_batch_report *r);
+
+void pdhg_batch_destroy(pdhg_batch *b);
+
 /* Release all device memory of the handle (NULL is a no-op). */
 void pdhg_destroy(pdhg_solver *s);
 
@@ -221,7 +281,8 @@ void pdhg_destroy(pdhg_solver *s);
 const char *pdhg_last_error(void);
 
 /* Size checks for bindings: sizeof of each public struct. */
-int32_t pdhg_struct_size(int32_t which); /* 0 params, 1 result, 2 kkt, 3 push, 4 timing */
+int32_t pdhg_struct_size(int32_t which); /* 0 params, 1 result, 2 kkt, 3 push, 4 timing,
+                                             5 lp desc, 6 batch report */
 
 #ifdef __cplusplus
 }

@@ -176,6 +176,91 @@ bool row_sorted_unique(const int64_t *rp, const int32_t *ci, int m)
     return true;
 }
 
+// one batch phase (mode 1 solve, mode 2 push), lockstep cycles over all LPs;
+// returns when every LP taking part is done or `iters` iterations have run
+bool run_batch_phase(pdhg_batch *b, int64_t iters, int mode, double t0)
+{
+    pdhg_solver *s = b->s;
+    const int K = s->p.check_every;
+    const int depth = 4;
+    const int64_t target = b->t_host + std::max<int64_t>(iters, 0);
+    bool time_out = false;
+    // algorithmic bytes of one primal / dual launch over the LPs that have not
+    // stopped (tiles of stopped LPs exit at once), from the last host view
+    const int64_t vbytes = s->fp32 ? 4 : 8;
+    auto active_bytes = [&](double &bp, double &bd) {
+        bp = bd = 0.0;
+        for (int i = 0; i < b->count; i++) {
+            if (b->sts_host[i].done) continue;
+            const int64_t mi = b->roff[i + 1] - b->roff[i], ni = b->coff[i + 1] - b->coff[i];
+            const double nz = (double)b->nnz_of[i];
+            bp += 4.0 * (ni + 1) + (4.0 + vbytes) * nz + 8.0 * mi + 7.0 * vbytes * ni;
+            bd += 4.0 * (mi + 1) + (4.0 + vbytes) * nz + (double)vbytes * ni + 33.0 * mi;
+        }
+    };
+    while (b->t_host < target) {
+        int enq = 0;
+        bool events = false;
+        double bp_now = 0.0, bd_now = 0.0;
+        if (s->p.timing) active_bytes(bp_now, bd_now);
+        while (b->t_host < target && enq < depth) {
+            const int64_t to_check = b->next_check - b->t_host;
+            const int64_t left = target - b->t_host;
+            const bool check = to_check <= left;
+            const int len = (int)(check ? to_check : left);
+            const bool timed = s->p.timing && enq == 0 && len >= 2;
+            if (check && len == K && s->p.use_graph && !timed) {
+                HIPCHK(batch_capture_cycle(b, K, mode));
+                HIPCHK(hipGraphLaunch(b->graph, s->stream));
+            } else {
+                HIPCHK(batch_iterations(b, len, check, mode, timed));
+            }
+            events = events || timed;
+            b->t_host += len;
+            if (check) b->next_check += K;
+            enq++;
+        }
+        HIPCHK(hipMemcpyAsync(b->sts_host, b->sts, sizeof(DevState) * (size_t)b->count, hipMemcpyDeviceToHost,
+                              s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        if (events) {
+            float a = 0.0f, b2 = 0.0f;
+            if (hipEventElapsedTime(&a, s->ev[0], s->ev[1]) == hipSuccess &&
+                hipEventElapsedTime(&b2, s->ev[1], s->ev[2]) == hipSuccess) {
+                s->t_primal_ms += a;
+                s->t_dual_ms += b2;
+                s->t_samples += 1;
+                b->timed_bytes_primal += bp_now;
+                b->timed_bytes_dual += bd_now;
+            }
+            (void)hipGetLastError();
+        }
+        bool all_done = true;
+        for (int i = 0; i < b->count; i++) all_done = all_done && b->sts_host[i].done;
+        if (all_done) break;
+        if (s->p.time_limit > 0.0 && now_s() - t0 > s->p.time_limit) {
+            time_out = true;
+            break;
+        }
+    }
+    return time_out;
+}
+
+void free_batch(pdhg_batch *b)
+{
+    void *ptrs[] = {b->d_coff, b->ptiles, b->dtiles, b->rn, b->rm, b->rn_start, b->rm_start, b->sts,
+                    b->part, b->lp_scalar, b->rep, b->active, b->seeds};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    if (b->sts_host) (void)hipHostFree(b->sts_host);
+    if (b->rep_host) (void)hipHostFree(b->rep_host);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->s) {
+        free_all(b->s);
+        delete b->s;
+    }
+}
+
 } // namespace
 
 extern "C" {
@@ -222,13 +307,18 @@ int32_t pdhg_struct_size(int32_t which)
     case 2: return (int32_t)sizeof(pdhg_kkt_report);
     case 3: return (int32_t)sizeof(pdhg_push_result);
     case 4: return (int32_t)sizeof(pdhg_timing);
+    case 5: return (int32_t)sizeof(pdhg_lp_desc);
+    case 6: return (int32_t)sizeof(pdhg_batch_report);
     default: return -1;
     }
 }
 
-int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx, const double *val,
-                const double *b, const double *c, const double *l, const double *u, const char *sense,
-                const pdhg_params *params, pdhg_solver **out)
+// Validate, canonicalise and upload one model, build its transpose and scale
+// it.  With `single` the step size, norms and start point of a lone LP are
+// set up as well; a batch does those per LP (pdhg_batch.hip).
+static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                        const double *val, const double *b, const double *c, const double *l, const double *u,
+                        const char *sense, const pdhg_params *params, bool single, pdhg_solver **out)
 {
     if (!out) return fail(PDHG_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -391,10 +481,12 @@ int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(build_transpose(s));
         HIPCHK(scale_problem(s));
-        HIPCHK(power_iteration(s));
-        HIPCHK(init_norms(s));
-        HIPCHK(init_iteration(s));
-        if (p.autotune) HIPCHK(autotune(s));
+        if (single) {
+            HIPCHK(power_iteration(s));
+            HIPCHK(init_norms(s));
+            HIPCHK(init_iteration(s));
+            if (p.autotune) HIPCHK(autotune(s));
+        }
         HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         s->t_host = 0;
@@ -409,6 +501,13 @@ int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const
     *out = s;
     set_error("");
     return PDHG_OK;
+}
+
+int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx, const double *val,
+                const double *b, const double *c, const double *l, const double *u, const char *sense,
+                const pdhg_params *params, pdhg_solver **out)
+{
+    return create_model(m, n, nnz, row_ptr, col_idx, val, b, c, l, u, sense, params, true, out);
 }
 
 int pdhg_iterate(pdhg_solver *s, int64_t iters, pdhg_result *r)
@@ -605,4 +704,285 @@ void pdhg_destroy(pdhg_solver *s)
     delete s;
 }
 
+int pdhg_batch_create(int32_t count, const pdhg_lp_desc *lps, const pdhg_params *params, pdhg_batch **out)
+{
+    if (!out) return fail(PDHG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !lps) return fail(PDHG_ERR_INVALID_ARG, "count must be >= 1 with a descriptor array");
+    pdhg_params p;
+    if (params) p = *params;
+    else pdhg_default_params(&p);
+    for (int32_t k : {p.lanes_a, p.lanes_at})
+        if (k > 0) return fail(PDHG_ERR_INVALID_ARG, "the batch engine runs tiled kernels only (lanes <= 0)");
+    // one block-diagonal model with global column indices
+    std::vector<int> roff(1, 0), coff(1, 0);
+    int64_t nz_total = 0;
+    for (int i = 0; i < count; i++) {
+        const pdhg_lp_desc &d = lps[i];
+        if (d.m < 1 || d.n < 1 || d.nnz < 0 || !d.row_ptr || !d.b || !d.c || (d.nnz > 0 && (!d.col_idx || !d.val)))
+            return fail(PDHG_ERR_INVALID_ARG, "LP " + std::to_string(i) + ": bad dimensions or NULL arrays");
+        if (d.row_ptr[0] != 0 || d.row_ptr[d.m] != d.nnz)
+            return fail(PDHG_ERR_INVALID_ARG, "LP " + std::to_string(i) + ": row_ptr[0] != 0 or row_ptr[m] != nnz");
+        if ((int64_t)roff.back() + d.m >= (int64_t)1 << 31 || (int64_t)coff.back() + d.n >= (int64_t)1 << 31)
+            return fail(PDHG_ERR_INVALID_ARG, "batch too large for 32-bit indices");
+        roff.push_back(roff.back() + d.m);
+        coff.push_back(coff.back() + d.n);
+        nz_total += d.nnz;
+    }
+    if (nz_total >= (int64_t)1 << 31) return fail(PDHG_ERR_INVALID_ARG, "batch nnz must stay below 2^31");
+    const int M = roff.back(), N = coff.back();
+    std::vector<int64_t> rp((size_t)M + 1, 0);
+    std::vector<int32_t> ci((size_t)nz_total);
+    std::vector<double> va((size_t)nz_total), bb((size_t)M), cc((size_t)N), ll((size_t)N), uu((size_t)N);
+    std::vector<char> sn((size_t)M);
+    int64_t w = 0;
+    for (int i = 0; i < count; i++) {
+        const pdhg_lp_desc &d = lps[i];
+        for (int r = 0; r < d.m; r++) {
+            for (int64_t e = d.row_ptr[r]; e < d.row_ptr[r + 1]; e++, w++) {
+                const int32_t col = d.col_idx[e];
+                if (col < 0 || col >= d.n)
+                    return fail(PDHG_ERR_INVALID_ARG, "LP " + std::to_string(i) + ": column index out of range");
+                ci[w] = col + coff[i];
+                va[w] = d.val[e];
+            }
+            rp[roff[i] + r + 1] = w;
+            bb[roff[i] + r] = d.b[r];
+            sn[roff[i] + r] = d.sense ? d.sense[r] : '=';
+        }
+        for (int j = 0; j < d.n; j++) {
+            cc[coff[i] + j] = d.c[j];
+            ll[coff[i] + j] = d.l ? d.l[j] : 0.0;
+            uu[coff[i] + j] = d.u ? d.u[j] : INFINITY;
+        }
+    }
+    pdhg_solver *s = nullptr;
+    int rc = create_model(M, N, nz_total, rp.data(), ci.data(), va.data(), bb.data(), cc.data(), ll.data(), uu.data(),
+                          sn.data(), &p, false, &s);
+    if (rc != PDHG_OK) return rc;
+    pdhg_batch *b = new (std::nothrow) pdhg_batch();
+    if (!b) {
+        pdhg_destroy(s);
+        return fail(PDHG_ERR_OOM, "host allocation failed");
+    }
+    b->s = s;
+    b->count = count;
+    b->roff = roff;
+    b->coff = coff;
+    for (int i = 0; i < count; i++) b->nnz_of.push_back(lps[i].nnz);
+    try {
+        hipStream_t st = s->stream;
+        std::vector<int4> rn, rm;
+        std::vector<int> rn_start, rm_start;
+        auto tiles = [&](const std::vector<int> &off, std::vector<int4> &t, std::vector<int> &start) {
+            t.clear();
+            start.assign((size_t)count + 1, 0);
+            for (int i = 0; i < count; i++) {
+                start[i] = (int)t.size();
+                for (int r = off[i]; r < off[i + 1]; r += kBlock) {
+                    int4 q;
+                    q.x = i;
+                    q.y = r;
+                    q.z = std::min(kBlock, off[i + 1] - r);
+                    q.w = 0;
+                    t.push_back(q);
+                }
+            }
+            start[count] = (int)t.size();
+        };
+        tiles(coff, rn, rn_start);
+        tiles(roff, rm, rm_start);
+        b->n_rn = (int)rn.size();
+        b->n_rm = (int)rm.size();
+        dalloc(&b->rn, rn.size());
+        dalloc(&b->rm, rm.size());
+        dalloc(&b->rn_start, rn_start.size());
+        dalloc(&b->rm_start, rm_start.size());
+        dalloc(&b->d_coff, coff.size());
+        HIPCHK(hipMemcpy(b->rn, rn.data(), sizeof(int4) * rn.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->rm, rm.data(), sizeof(int4) * rm.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->rn_start, rn_start.data(), sizeof(int) * rn_start.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->rm_start, rm_start.data(), sizeof(int) * rm_start.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->d_coff, coff.data(), sizeof(int) * coff.size(), hipMemcpyHostToDevice));
+        dalloc(&b->sts, (size_t)count);
+        dalloc(&b->part, (size_t)(Q_COUNT + 1) * (b->n_rm + b->n_rn));
+        dalloc(&b->lp_scalar, (size_t)count);
+        dalloc(&b->rep, (size_t)count * R_COUNT);
+        dalloc(&b->active, (size_t)count);
+        dalloc(&b->seeds, (size_t)count);
+        HIPCHK(hipHostMalloc((void **)&b->sts_host, sizeof(DevState) * (size_t)count, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&b->rep_host, sizeof(double) * R_COUNT * (size_t)count, hipHostMallocDefault));
+        // every LP starts from the constants of the shared parameters
+        for (int i = 0; i < count; i++) b->sts_host[i] = *s->st_host;
+        HIPCHK(hipMemcpy(b->sts, b->sts_host, sizeof(DevState) * (size_t)count, hipMemcpyHostToDevice));
+        b->active_host.assign((size_t)count, 1);
+        HIPCHK(hipMemcpy(b->active, b->active_host.data(), sizeof(int) * (size_t)count, hipMemcpyHostToDevice));
+        // tiled kernels from the mean row lengths (tiles only: the batch has no lane-group path)
+        auto tiled = [](double mean) {
+            const int k = choose_kernel(mean);
+            return k < 0 ? k : -32;
+        };
+        const int ka = p.lanes_a ? p.lanes_a : tiled(M > 0 ? (double)nz_total / M : 1.0);
+        const int kat = p.lanes_at ? p.lanes_at : tiled(N > 0 ? (double)nz_total / N : 1.0);
+        HIPCHK(batch_set_kernels(b, kat, ka));
+        HIPCHK(batch_setup(b));
+        HIPCHK(batch_phase_begin(b, true));
+        if (p.autotune) HIPCHK(batch_autotune(b));
+        HIPCHK(hipStreamSynchronize(st));
+        b->t_host = 0;
+        b->next_check = p.check_every;
+    } catch (const HipFailure &f) {
+        free_batch(b);
+        delete b;
+        return fail(f.err == hipErrorOutOfMemory ? PDHG_ERR_OOM : PDHG_ERR_HIP,
+                    std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    *out = b;
+    set_error("");
+    return PDHG_OK;
+}
+
+int pdhg_batch_solve(pdhg_batch *b, pdhg_result *results)
+{
+    if (!b || !results) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    if (b->pushed || b->solved) return fail(PDHG_ERR_STATE, "the batch has already been solved");
+    const double t0 = now_s();
+    try {
+        pdhg_solver *s = b->s;
+        const bool time_out = run_batch_phase(b, s->p.max_iter, 1, t0);
+        if (b->t_host < s->p.check_every) HIPCHK(candidate_from_iterate(s));
+        HIPCHK(unscale(s, s->xp, s->yp, s->xu, s->yu));
+        std::vector<pdhg_kkt_report> k((size_t)b->count);
+        HIPCHK(batch_report(b, s->xu, s->yu, s->zsol, k.data()));
+        b->solve_seconds = now_s() - t0;
+        b->solve_iters_max = b->t_host;
+        for (int i = 0; i < b->count; i++) {
+            const DevState &d = b->sts_host[i];
+            pdhg_result &r = results[i];
+            std::memset(&r, 0, sizeof(r));
+            r.status = d.done ? d.status : (time_out ? PDHG_TIME_LIMIT : PDHG_ITER_LIMIT);
+            r.iters = d.done ? d.t : b->t_host;
+            r.restarts = d.restarts;
+            r.rel_p = k[i].rel_p;
+            r.rel_d = k[i].rel_d;
+            r.rel_gap = k[i].rel_gap;
+            r.pobj = k[i].pobj;
+            r.dobj = k[i].dobj;
+            r.seconds = b->solve_seconds;
+            b->active_host[i] = (r.status == PDHG_OPTIMAL) ? 1 : 0;
+        }
+        b->solved = true;
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_batch_corner_push(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *results)
+{
+    if (!b || !seeds || !results) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    if (!b->solved || b->pushed) return fail(PDHG_ERR_STATE, "corner push needs a batch solve first (and runs once)");
+    const double t0 = now_s();
+    try {
+        pdhg_solver *s = b->s;
+        hipStream_t st = s->stream;
+        const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
+        for (int i = 0; i < b->count; i++) std::memset(&results[i], 0, sizeof(pdhg_push_result));
+        HIPCHK(hipMemcpyAsync(s->xs, s->xp, vb * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(s->ys, s->yp, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
+        HIPCHK(unscale(s, s->xs, s->ys, s->xu, s->yu));
+        std::vector<pdhg_kkt_report> before((size_t)b->count), after((size_t)b->count);
+        HIPCHK(batch_report(b, s->xu, s->yu, s->zsol, before.data()));
+        std::vector<int> solve_status((size_t)b->count);
+        for (int i = 0; i < b->count; i++) solve_status[i] = b->sts_host[i].status;
+        HIPCHK(hipMemcpy(b->active, b->active_host.data(), sizeof(int) * (size_t)b->count, hipMemcpyHostToDevice));
+        HIPCHK(batch_push_setup(b, seeds, results));
+        b->t_host = 0;
+        b->next_check = s->p.push_min_iters;
+        const bool time_out = run_batch_phase(b, s->p.push_max_iter, 2, t0);
+        HIPCHK(unscale(s, s->xp, nullptr, s->xpush, nullptr));
+        HIPCHK(batch_keep_unpushed(b));
+        HIPCHK(batch_report(b, s->xpush, s->yu, nullptr, after.data()));
+        b->push_seconds = now_s() - t0;
+        b->push_iters_max = b->t_host;
+        for (int i = 0; i < b->count; i++) {
+            const DevState &d = b->sts_host[i];
+            pdhg_push_result &r = results[i];
+            r.before = before[i];
+            r.after = after[i];
+            r.seconds = b->push_seconds;
+            if (!b->active_host[i]) { // the solve did not reach the tolerance: no push
+                r.status = solve_status[i];
+                r.iters = 0;
+                r.rel_p_push = NAN;
+                continue;
+            }
+            r.status = d.done ? d.status : (time_out ? PDHG_TIME_LIMIT : PDHG_ITER_LIMIT);
+            r.iters = d.done ? d.t : b->t_host;
+            r.restarts = d.restarts;
+            r.rel_p_push = d.checks > 0 ? d.rel_p : NAN;
+        }
+        b->pushed = true;
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_batch_get_solution(pdhg_batch *b, int32_t i, double *x, double *y, double *z)
+{
+    if (!b || i < 0 || i >= b->count) return fail(PDHG_ERR_INVALID_ARG, "bad handle or LP index");
+    if (!b->solved) return fail(PDHG_ERR_STATE, "no batch solve yet");
+    try {
+        pdhg_solver *s = b->s;
+        const size_t n0 = (size_t)b->coff[i], nn = (size_t)(b->coff[i + 1] - b->coff[i]);
+        const size_t m0 = (size_t)b->roff[i], mm = (size_t)(b->roff[i + 1] - b->roff[i]);
+        const double *cx = b->pushed ? s->xpush : s->xu;
+        if (x) HIPCHK(hipMemcpy(x, cx + n0, sizeof(double) * nn, hipMemcpyDeviceToHost));
+        if (y) HIPCHK(hipMemcpy(y, s->yu + m0, sizeof(double) * mm, hipMemcpyDeviceToHost));
+        if (z) HIPCHK(hipMemcpy(z, s->zsol + n0, sizeof(double) * nn, hipMemcpyDeviceToHost));
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_batch_get_report(pdhg_batch *b, pdhg_batch_report *r)
+{
+    if (!b || !r) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    std::memset(r, 0, sizeof(*r));
+    pdhg_solver *s = b->s;
+    r->count = b->count;
+    r->solve_seconds = b->solve_seconds;
+    r->push_seconds = b->push_seconds;
+    r->solve_lockstep_iters = b->solve_iters_max;
+    r->push_lockstep_iters = b->push_iters_max;
+    r->lanes_at = b->kern_at;
+    r->lanes_a = b->kern_a;
+    r->samples = s->t_samples;
+    if (s->t_samples > 0) {
+        r->primal_ms = s->t_primal_ms / (double)s->t_samples;
+        r->dual_ms = s->t_dual_ms / (double)s->t_samples;
+    }
+    const int64_t m = s->m, n = s->n, nz = s->nnz;
+    // mean algorithmic bytes of the timed launches (LPs still iterating)
+    if (s->t_samples > 0) {
+        r->bytes_primal = (int64_t)(b->timed_bytes_primal / (double)s->t_samples);
+        r->bytes_dual = (int64_t)(b->timed_bytes_dual / (double)s->t_samples);
+    }
+    r->total_m = m;
+    r->total_n = n;
+    r->total_nnz = nz;
+    return PDHG_OK;
+}
+
+void pdhg_batch_destroy(pdhg_batch *b)
+{
+    if (!b) return;
+    if (b->s && b->s->stream) (void)hipStreamSynchronize(b->s->stream);
+    free_batch(b);
+    delete b;
+}
+
 } // extern "C"
+

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "pdhg.h"
 
@@ -125,6 +126,37 @@ struct pdhg_solver {
     int64_t t_samples = 0;
 };
 
+// A batch of independent LPs stored as one block-diagonal model: every
+// row-space and column-space array of `s` is the concatenation of the LPs'
+// arrays, column indices are global, and each LP keeps its own DevState.
+struct pdhg_batch {
+    pdhg_solver *s = nullptr;
+    int count = 0;
+    std::vector<int> roff, coff;           // row / column offsets of each LP (count + 1)
+    std::vector<int64_t> nnz_of;           // entries of each LP
+    int *d_coff = nullptr;                 // device copy of coff
+    int4 *ptiles = nullptr, *dtiles = nullptr; // iteration tiles {lp, first row, rows, 0}
+    int n_ptiles = 0, n_dtiles = 0;
+    int kern_at = -64, kern_a = -64;       // tiled-kernel choice, pdhg_params.lanes_* encoding
+    int4 *rn = nullptr, *rm = nullptr;     // 256-row reduction tiles of the column / row space
+    int n_rn = 0, n_rm = 0;
+    int *rn_start = nullptr, *rm_start = nullptr; // first reduction tile of each LP (count + 1)
+    pdhg::DevState *sts = nullptr, *sts_host = nullptr;
+    double *part = nullptr;                // per-tile partial sums
+    double *lp_scalar = nullptr;           // per-LP scalars (power iteration)
+    double *rep = nullptr, *rep_host = nullptr; // per-LP report values
+    int *active = nullptr;                 // per-LP flag: takes part in the current phase
+    std::vector<int> active_host;
+    uint64_t *seeds = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_len = 0, graph_mode = -1;
+    int64_t t_host = 0, next_check = 0;
+    bool solved = false, pushed = false;
+    double solve_seconds = 0.0, push_seconds = 0.0;
+    double timed_bytes_primal = 0.0, timed_bytes_dual = 0.0; // algorithmic bytes of the timed launches
+    int64_t solve_iters_max = 0, push_iters_max = 0;
+};
+
 namespace pdhg {
 
 // error helpers (capi.cpp)
@@ -142,11 +174,23 @@ hipError_t launch_iterations(pdhg_solver *s, int count, bool check_at_end, int m
 hipError_t launch_check(pdhg_solver *s, int mode, int len);
 hipError_t launch_advance(pdhg_solver *s, int len);
 hipError_t candidate_from_iterate(pdhg_solver *s);
+hipError_t launch_start_vectors(pdhg_solver *s, bool fresh_start);
 hipError_t unscale(pdhg_solver *s, const void *xh, const void *yh, double *xo, double *yo);
 hipError_t report(pdhg_solver *s, const double *x, const double *y, double *z, pdhg_kkt_report *k);
 hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r);
 hipError_t capture_cycle(pdhg_solver *s, int len, int mode);
 hipError_t copy_probe(int64_t bytes, int reps, double *gbps);
+
+// batch engine (pdhg_batch.hip)
+hipError_t batch_setup(pdhg_batch *b);
+hipError_t batch_autotune(pdhg_batch *b);
+hipError_t batch_set_kernels(pdhg_batch *b, int kern_at, int kern_a);
+hipError_t batch_phase_begin(pdhg_batch *b, bool fresh);
+hipError_t batch_iterations(pdhg_batch *b, int count, bool check_at_end, int mode, bool timed);
+hipError_t batch_capture_cycle(pdhg_batch *b, int len, int mode);
+hipError_t batch_report(pdhg_batch *b, const double *x, const double *y, double *z, pdhg_kkt_report *out);
+hipError_t batch_push_setup(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *out);
+hipError_t batch_keep_unpushed(pdhg_batch *b);
 int choose_kernel(double mean_row);
 hipError_t autotune(pdhg_solver *s);
 

@@ -6,69 +6,11 @@
 
 #include "pdhg_device.hpp"
 #include "pdhg_internal.hpp"
+#include "pdhg_kernels.hpp"
 
 namespace pdhg {
 
 // ------------------------------------------------------------ iteration ---
-// Halpern weights for iteration number k (0-based since the last restart).
-__device__ __forceinline__ void halpern_weights(const DevState *st, int i, double &w, double &wa, double &g)
-{
-    const double k = (double)(st->k0 + i);
-    w = (k + 1.0) / (k + 2.0);
-    wa = 1.0 / (k + 2.0);
-    g = st->gamma;
-}
-
-// Storage: the matrix values and every n-vector (x, x_anchor, xbar, x+, chat,
-// lhat, uhat) are V (float in the mixed mode, double otherwise); every
-// m-vector (y, y_anchor, y+, bhat) is double.  All arithmetic — products,
-// sums, projections, Halpern averages — is double in registers; only the
-// stores round to V.  (With y in float the reduced cost chat - Ahat'y loses
-// its low bits and the large primal step tau = eta/omega amplifies that
-// rounding into x; keeping the short m-vectors in double removes it.)
-
-// Primal half, one row of the transpose (= one column j of A) per group of L
-// lanes:  g = Ahat' y;  x+ = clamp(x - tau (chat - g), lhat, uhat);
-// xbar = 2 x+ - x;  x <- w ((1+gamma) x+ - gamma x) + wa x_anchor.
-// At the last iteration before a check the candidate x+ is stored as well.
-template <typename V>
-__device__ __forceinline__ void primal_update(int64_t j, double g, double xj, double cj, double lo, double hi,
-                                              double aj, V *__restrict__ x, V *__restrict__ xbar,
-                                              V *__restrict__ xp, const DevState *__restrict__ st, int i,
-                                              int store_cand)
-{
-    double xn = xj - st->tau * (cj - g);
-    xn = xn < lo ? lo : xn;
-    xn = xn > hi ? hi : xn;
-    xbar[j] = (V)(2.0 * xn - xj);
-    if (store_cand) xp[j] = (V)xn;
-    if (st->halpern) {
-        double w, wa, gm;
-        halpern_weights(st, i, w, wa, gm);
-        x[j] = (V)(w * ((1.0 + gm) * xn - gm * xj) + wa * aj);
-    } else {
-        x[j] = (V)xn;
-    }
-}
-
-// Dual half:  y+ = proj_Y(y + sigma (bhat - h));  y <- w ((1+gamma) y+ - gamma y) + wa y_anchor.
-__device__ __forceinline__ void dual_update(int64_t r, double h, double yr, double br, double ar, int8_t sn,
-                                            double *__restrict__ y, double *__restrict__ yp,
-                                            const DevState *__restrict__ st, int i, int store_cand)
-{
-    double yn = yr + st->sigma * (br - h);
-    if (sn == '<') yn = yn < 0.0 ? yn : 0.0;
-    else if (sn == '>') yn = yn > 0.0 ? yn : 0.0;
-    if (store_cand) yp[r] = yn;
-    if (st->halpern) {
-        double w, wa, gm;
-        halpern_weights(st, i, w, wa, gm);
-        y[r] = w * ((1.0 + gm) * yn - gm * yr) + wa * ar;
-    } else {
-        y[r] = yn;
-    }
-}
-
 template <typename V, int L>
 __global__ __launch_bounds__(kBlock) void k_primal(int n, const int *__restrict__ tp, const int *__restrict__ ti,
                                                   const V *__restrict__ atv, const double *__restrict__ y,
@@ -111,45 +53,6 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
     acc = group_sum<L>(acc);
     if (lane != 0) return;
     dual_update(r, acc, y[r], bh[r], ya[r], sense[r], y, yp, st, i, store_cand);
-}
-
-// ------------------------------------------------- LDS-tiled short rows ---
-// A workgroup of NT threads owns a tile of T consecutive rows.  The tile's
-// entries stream through LDS in chunks of 8 NT: every thread loads entries
-// k, k+NT, ... with their gathered vector value (coalesced index and value
-// loads), writes the products to LDS, and G = NT/T threads per row sum their
-// row's products in a fixed order.  Row sums go to LDS and threads 0..T-1 run
-// the update epilogue on contiguous rows, with the epilogue's vector loads
-// issued before the product phase.
-constexpr int kChunk = 2048; // entries per LDS chunk of a 256-thread tile (8 per thread)
-
-template <typename VM, typename VV, int T, int NT>
-__device__ __forceinline__ void tile_row_sums(int r0, int rows, const int *__restrict__ ptr,
-                                              const int *__restrict__ idx, const VM *__restrict__ val,
-                                              const VV *__restrict__ vec, int *s_ptr, double *s_prod,
-                                              double *s_sum)
-{
-    constexpr int G = NT / T;
-    constexpr int C = 8 * NT;
-    const int tid = threadIdx.x;
-    for (int k = tid; k <= rows; k += NT) s_ptr[k] = ptr[r0 + k];
-    __syncthreads();
-    const int beg = s_ptr[0], end = s_ptr[rows];
-    const int my_row = tid / G, sub = tid % G;
-    const bool have = my_row < rows;
-    const int rb = have ? s_ptr[my_row] : 0, re = have ? s_ptr[my_row + 1] : 0;
-    double acc = 0.0;
-    for (int cs = beg; cs < end; cs += C) {
-        const int ce = cs + C < end ? cs + C : end;
-        for (int k = cs + tid; k < ce; k += NT) s_prod[k - cs] = (double)val[k] * (double)vec[idx[k]];
-        __syncthreads();
-        const int lo = rb > cs ? rb : cs, hi = re < ce ? re : ce;
-        for (int q = lo + sub; q < hi; q += G) acc += s_prod[q - cs];
-        __syncthreads();
-    }
-    acc = group_sum<G>(acc);
-    if (have && sub == 0) s_sum[my_row] = acc;
-    __syncthreads();
 }
 
 template <typename V, int T, int NT>
@@ -387,16 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_check_cols(int n, const double *__re
     }
 }
 
-__device__ __forceinline__ double kkt_weighted(double om, double p2, double d2, double g2)
-{
-    return sqrt(om * om * p2 + d2 / (om * om) + g2);
-}
-
-// One workgroup: reduce the partials in a fixed order, then
-//   mode 0: record the anchor's weighted-KKT parts (start of a phase);
-//   mode 1: solve check (termination on all three relative tests, restart);
-//   mode 2: push check (termination on the primal test only, restart).
-// `len` is the number of iterations since the last state update.
+// Reduce the check partials of one LP in a fixed order, then decide.
 __global__ __launch_bounds__(kBlock) void k_check_final(DevState *st, const double *__restrict__ pm, int gm,
                                                        const double *__restrict__ pn, int gn, int mode, int len)
 {
@@ -415,73 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_check_final(DevState *st, const doub
         v[q] = acc;
     }
     block_reduce<Q_COUNT + 1>(v, (1u << Q_PINF) | (1u << Q_DINF));
-    if (threadIdx.x != 0) return;
-    const double ph2 = v[Q_PH2], p2 = v[Q_P2], bty = v[Q_BTY], dy2 = v[Q_DY2];
-    const double dh2 = v[Q_DH2], d2 = v[Q_D2], ctx = v[Q_CTX], bnd = v[Q_BND], dx2 = v[Q_DX2];
-    const double nans = v[Q_NAN] + v[Q_COUNT];
-    const double pobj = ctx, dobj = bty + bnd, gap = pobj - dobj;
-    if (mode == 0) {
-        st->anc_p2 = ph2;
-        st->anc_d2 = dh2;
-        st->anc_g2 = gap * gap;
-        st->kkt_prev = kkt_weighted(st->omega, ph2, dh2, gap * gap);
-        return;
-    }
-    const int64_t t_now = st->t + len, k_now = st->k0 + len;
-    st->t = t_now;
-    st->checks += 1;
-    st->rel_p = sqrt(p2) / st->nb1;
-    st->rel_d = sqrt(d2) / st->nc1;
-    st->rel_gap = fabs(gap) / (1.0 + fabs(pobj) + fabs(dobj));
-    st->pobj = pobj;
-    st->dobj = dobj;
-    st->restart_flag = 0;
-    if (nans > 0.0) {
-        st->done = 1;
-        st->status = PDHG_NUMERICAL;
-        st->k0 = k_now;
-        return;
-    }
-    const double eps = st->eps_rel;
-    if (mode == 1 && st->rel_p <= eps && st->rel_d <= eps && st->rel_gap <= eps) {
-        st->done = 1;
-        st->status = PDHG_OPTIMAL;
-        st->k0 = k_now;
-        return;
-    }
-    if (mode == 2 && st->rel_p <= eps) {
-        st->done = 1;
-        st->status = PDHG_PUSH_DONE;
-        st->k0 = k_now;
-        return;
-    }
-    const double om = st->omega;
-    const double kc = kkt_weighted(om, ph2, dh2, gap * gap);
-    const double ka = kkt_weighted(om, st->anc_p2, st->anc_d2, st->anc_g2);
-    st->kkt_c = kc;
-    const bool restart = (kc <= st->r_suff * ka) || (kc <= st->r_nec * ka && kc > st->kkt_prev) ||
-                         ((double)k_now >= st->r_art * (double)t_now);
-    st->kkt_prev = kc;
-    if (!restart) {
-        st->k0 = k_now;
-        return;
-    }
-    const double dx = sqrt(dx2), dy = sqrt(dy2);
-    double om2 = om;
-    if (dx > 1e-10 && dy > 1e-10) {
-        const double th = st->pw_smooth;
-        om2 = exp(th * log(dy / dx) + (1.0 - th) * log(om));
-    }
-    st->omega = om2;
-    st->tau = st->eta / om2;
-    st->sigma = st->eta * om2;
-    st->anc_p2 = ph2;
-    st->anc_d2 = dh2;
-    st->anc_g2 = gap * gap;
-    st->kkt_prev = kkt_weighted(om2, ph2, dh2, gap * gap);
-    st->k0 = 0;
-    st->restarts += 1;
-    st->restart_flag = 1;
+    if (threadIdx.x == 0) check_decide(st, v, mode, len);
 }
 
 // On restart: x = x_anchor = x+, y = y_anchor = y+ (candidate of the check).
@@ -677,7 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_copy_anchor(int n, int m, const V *_
 }
 
 template <typename V>
-static hipError_t phase_start(pdhg_solver *s, bool fresh_start)
+static void start_vectors(pdhg_solver *s, bool fresh_start)
 {
     hipStream_t st = s->stream;
     const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
@@ -687,6 +515,21 @@ static hipError_t phase_start(pdhg_solver *s, bool fresh_start)
     else
         hipLaunchKernelGGL((k_copy_anchor<V>), dim3(g), dim3(kBlock), 0, st, s->n, s->m, (const V *)s->x, (V *)s->xa,
                            (const double *)s->y, (double *)s->ya);
+}
+
+// x = clamp(0, lhat, uhat), y = 0 (fresh) or anchors = current (x, y)
+hipError_t launch_start_vectors(pdhg_solver *s, bool fresh_start)
+{
+    if (s->fp32) start_vectors<float>(s, fresh_start);
+    else start_vectors<double>(s, fresh_start);
+    return hipGetLastError();
+}
+
+template <typename V>
+static hipError_t phase_start(pdhg_solver *s, bool fresh_start)
+{
+    hipStream_t st = s->stream;
+    start_vectors<V>(s, fresh_start);
     const int nb = grid_for(s->n > s->m ? s->n : s->m, kBlock, kMaxRedBlocks);
     hipLaunchKernelGGL((k_sumsq2<V>), dim3(nb), dim3(kBlock), 0, st, s->n, (const V *)s->ch, s->m, (const double *)s->bh,
                        s->partials, nb);
@@ -900,15 +743,6 @@ hipError_t report(pdhg_solver *s, const double *x, const double *y, double *z, p
 }
 
 // ------------------------------------------------------------- corner push ---
-// splitmix64 (Steele, Lea and Flood 2014)
-__device__ __forceinline__ uint64_t splitmix64(uint64_t x)
-{
-    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    return z ^ (z >> 31);
-}
-
 // Algorithm 1 on the columns: ub_j <- x_j if z_j > eps_abs, lb_j <- x_j if
 // z_j < -eps_abs (bounds stored scaled: the scaled solve candidate itself),
 // objective Uniform[0,1) scaled like c, start x at the solve's x.

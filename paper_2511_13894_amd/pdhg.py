@@ -77,9 +77,30 @@ class Timing(C.Structure):
     ]
 
 
+class LpDesc(C.Structure):
+    _fields_ = [
+        ("m", C.c_int32), ("n", C.c_int32), ("nnz", C.c_int64),
+        ("row_ptr", C.POINTER(C.c_int64)), ("col_idx", C.POINTER(C.c_int32)), ("val", C.POINTER(C.c_double)),
+        ("b", C.POINTER(C.c_double)), ("c", C.POINTER(C.c_double)), ("l", C.POINTER(C.c_double)),
+        ("u", C.POINTER(C.c_double)), ("sense", C.c_char_p),
+    ]
+
+
+class BatchReport(C.Structure):
+    _fields_ = [
+        ("count", C.c_int32), ("lanes_at", C.c_int32), ("lanes_a", C.c_int32), ("pad_", C.c_int32),
+        ("solve_seconds", C.c_double), ("push_seconds", C.c_double),
+        ("solve_lockstep_iters", C.c_int64), ("push_lockstep_iters", C.c_int64),
+        ("primal_ms", C.c_double), ("dual_ms", C.c_double), ("samples", C.c_int64),
+        ("bytes_primal", C.c_int64), ("bytes_dual", C.c_int64),
+        ("total_m", C.c_int64), ("total_n", C.c_int64), ("total_nnz", C.c_int64),
+    ]
+
+
 EXPORTS = ["pdhg_default_params", "pdhg_create", "pdhg_solve", "pdhg_iterate", "pdhg_corner_push", "pdhg_kkt",
            "pdhg_get_solution", "pdhg_get_iterate", "pdhg_get_scaling", "pdhg_destroy", "pdhg_last_error",
-           "pdhg_struct_size", "pdhg_get_timing", "pdhg_copy_probe"]
+           "pdhg_struct_size", "pdhg_get_timing", "pdhg_copy_probe", "pdhg_batch_create", "pdhg_batch_solve",
+           "pdhg_batch_corner_push", "pdhg_batch_get_solution", "pdhg_batch_get_report", "pdhg_batch_destroy"]
 
 _lib = None
 
@@ -110,13 +131,22 @@ def load(path: Optional[Path] = None):
     lib.pdhg_copy_probe.argtypes = [C.c_int64, C.c_int32, dp]
     lib.pdhg_destroy.argtypes = [C.c_void_p]
     lib.pdhg_destroy.restype = None
+    lib.pdhg_batch_create.argtypes = [C.c_int32, P(LpDesc), P(Params), P(C.c_void_p)]
+    lib.pdhg_batch_solve.argtypes = [C.c_void_p, P(Result)]
+    lib.pdhg_batch_corner_push.argtypes = [C.c_void_p, P(C.c_uint64), P(PushResult)]
+    lib.pdhg_batch_get_solution.argtypes = [C.c_void_p, C.c_int32, dp, dp, dp]
+    lib.pdhg_batch_get_report.argtypes = [C.c_void_p, P(BatchReport)]
+    lib.pdhg_batch_destroy.argtypes = [C.c_void_p]
+    lib.pdhg_batch_destroy.restype = None
     lib.pdhg_last_error.restype = C.c_char_p
     lib.pdhg_struct_size.restype = C.c_int32
     lib.pdhg_struct_size.argtypes = [C.c_int32]
     for fn in ("pdhg_create", "pdhg_solve", "pdhg_iterate", "pdhg_corner_push", "pdhg_kkt", "pdhg_get_solution",
-               "pdhg_get_iterate", "pdhg_get_scaling", "pdhg_get_timing", "pdhg_copy_probe"):
+               "pdhg_get_iterate", "pdhg_get_scaling", "pdhg_get_timing", "pdhg_copy_probe", "pdhg_batch_create",
+               "pdhg_batch_solve", "pdhg_batch_corner_push", "pdhg_batch_get_solution", "pdhg_batch_get_report"):
         getattr(lib, fn).restype = C.c_int
-    sizes = [C.sizeof(Params), C.sizeof(Result), C.sizeof(KKTReport), C.sizeof(PushResult), C.sizeof(Timing)]
+    sizes = [C.sizeof(Params), C.sizeof(Result), C.sizeof(KKTReport), C.sizeof(PushResult), C.sizeof(Timing),
+             C.sizeof(LpDesc), C.sizeof(BatchReport)]
     for which, want in enumerate(sizes):
         got = lib.pdhg_struct_size(which)
         if got != want:
@@ -248,3 +278,70 @@ class Solver:
         dr, dc, s4 = np.zeros(self.m), np.zeros(self.n), np.zeros(4)
         self._check(self.lib.pdhg_get_scaling(self.h, _dp(dr), _dp(dc), _dp(s4)))
         return {"dr": dr, "dc": dc, "eta": s4[0], "omega": s4[1], "sigma_est": s4[2], "t": int(s4[3])}
+
+
+class Batch:
+    """Many LPs solved and corner-pushed together (pdhg_batch_*)."""
+
+    def __init__(self, lps, **params):
+        _refuse_second_runtime()
+        self.lib = load()
+        self.lps = list(lps)
+        self.count = len(self.lps)
+        self.params = default_params(**params)
+        self.params.stream = None
+        descs = (LpDesc * self.count)()
+        self._keep = []
+        for d, lp in zip(descs, self.lps):
+            arrs = [np.ascontiguousarray(lp.row_ptr, dtype=np.int64), np.ascontiguousarray(lp.col, dtype=np.int32),
+                    np.ascontiguousarray(lp.val, dtype=np.float64), np.ascontiguousarray(lp.b, dtype=np.float64),
+                    np.ascontiguousarray(lp.c, dtype=np.float64), np.ascontiguousarray(lp.l, dtype=np.float64),
+                    np.ascontiguousarray(lp.u, dtype=np.float64)]
+            sense = bytes(np.asarray(lp.sense, dtype=np.uint8))
+            self._keep += arrs + [sense]
+            rp, ci, va, b, c, l, u = arrs
+            d.m, d.n, d.nnz = int(lp.m), int(lp.n), int(rp[-1])
+            d.row_ptr = rp.ctypes.data_as(C.POINTER(C.c_int64))
+            d.col_idx = ci.ctypes.data_as(C.POINTER(C.c_int32))
+            d.val, d.b, d.c, d.l, d.u = _dp(va), _dp(b), _dp(c), _dp(l), _dp(u)
+            d.sense = sense
+        h = C.c_void_p()
+        rc = self.lib.pdhg_batch_create(self.count, descs, C.byref(self.params), C.byref(h))
+        if rc != 0:
+            raise PdhgError(rc, self.lib.pdhg_last_error().decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != 0:
+            raise PdhgError(rc, self.lib.pdhg_last_error().decode())
+
+    def __del__(self):
+        self.destroy()
+
+    def destroy(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.pdhg_batch_destroy(h)
+        self.h = None
+
+    def solve(self):
+        r = (Result * self.count)()
+        self._check(self.lib.pdhg_batch_solve(self.h, r))
+        return list(r)
+
+    def corner_push(self, seeds):
+        sd = (C.c_uint64 * self.count)(*[int(v) for v in seeds])
+        r = (PushResult * self.count)()
+        self._check(self.lib.pdhg_batch_corner_push(self.h, sd, r))
+        return list(r)
+
+    def get_solution(self, i):
+        lp = self.lps[i]
+        x, y, z = np.zeros(lp.n), np.zeros(lp.m), np.zeros(lp.n)
+        self._check(self.lib.pdhg_batch_get_solution(self.h, int(i), _dp(x), _dp(y), _dp(z)))
+        return x, y, z
+
+    def report(self) -> BatchReport:
+        r = BatchReport()
+        self._check(self.lib.pdhg_batch_get_report(self.h, C.byref(r)))
+        return r

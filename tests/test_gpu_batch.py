@@ -1,0 +1,83 @@
+"""Batch engine (many LPs of uneven sizes in one block-diagonal model) vs
+the oracle run on each LP alone."""
+import numpy as np
+import pytest
+
+from oracle import OracleSolver
+from paper_2511_13894_amd import lpgen, pdhg
+
+pytestmark = pytest.mark.gpu
+
+
+def _family(count, seed0, m_range=(40, 400)):
+    return [lpgen.config3_instance(i, base_seed=seed0, m_range=m_range) for i in range(count)]
+
+
+@pytest.mark.parametrize("kern", [0, -1064, -256])
+def test_batch_matches_single_oracle_runs_fp64(kern):
+    lps = _family(9, 5000)
+    lps.append(lpgen.tiny(3, m=3, n=6))          # general bounds and senses
+    lps.append(lpgen.transportation(6, 9, seed=4))
+    print(f"[batch] kern={kern}: sizes {[lp.m for lp in lps]}", flush=True)
+    bt = pdhg.Batch(lps, eps_rel=1e-7, lanes_at=kern, lanes_a=kern)
+    res = bt.solve()
+    seeds = [11 + i for i in range(len(lps))]
+    push = bt.corner_push(seeds)
+    for i, lp in enumerate(lps):
+        o = OracleSolver(lp, eps_rel=1e-7)
+        ro = o.solve()
+        assert res[i].status == ro.status == 0, (i, res[i].status, ro.status)
+        assert abs(res[i].iters - ro.iters) <= 64, (i, res[i].iters, ro.iters)
+        assert abs(res[i].pobj - ro.pobj) <= 1e-6 * (1 + abs(ro.pobj)), i
+        xg, yg, zg = bt.get_solution(i)
+        po = o.corner_push(seeds[i])
+        assert (push[i].n_fix_lower, push[i].n_fix_upper, push[i].n_rows_to_eq) == \
+            (po.n_fix_lower, po.n_fix_upper, po.n_rows_to_eq), i
+        assert push[i].status == po.status, (i, push[i].status, po.status)
+        assert abs(push[i].iters - po.iters) <= 128, (i, push[i].iters, po.iters)
+        assert push[i].after.rel_p <= 1.0000001e-7
+        assert push[i].before.p_off == po.before.p_off
+
+
+def test_batch_iterates_equal_single_gpu_solve_with_same_kernels():
+    """An LP inside a batch follows the same trajectory as the same LP
+    solved alone with the same tiled kernels (the block-diagonal layout does
+    not couple LPs)."""
+    lps = _family(5, 6100)
+    bt = pdhg.Batch(lps, eps_rel=1e-7, lanes_at=-1064, lanes_a=-1064)
+    res = bt.solve()
+    for i in (0, 3):
+        g = pdhg.Solver(lps[i], eps_rel=1e-7, lanes_at=-1064, lanes_a=-1064)
+        r = g.solve()
+        assert r.iters == res[i].iters and r.status == res[i].status
+        xg, yg, _ = g.get_solution()
+        xb, yb, _ = bt.get_solution(i)
+        np.testing.assert_allclose(xb, xg, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(yb, yg, rtol=1e-9, atol=1e-12)
+
+
+def test_batch_fp32_mixed_and_report():
+    lps = _family(12, 7000, m_range=(100, 2000))
+    bt = pdhg.Batch(lps, precision="fp32", eps_rel=1e-6, timing=1, autotune=1)
+    res = bt.solve()
+    push = bt.corner_push(list(range(len(lps))))
+    rep = bt.report()
+    ok = sum(r.status == pdhg.PDHG_OPTIMAL for r in res)
+    print(f"[batch] fp32: {ok}/{len(lps)} optimal, lockstep solve {rep.solve_lockstep_iters} push "
+          f"{rep.push_lockstep_iters}, kernels {rep.lanes_at}/{rep.lanes_a}, primal {rep.primal_ms * 1e3:.1f} us "
+          f"dual {rep.dual_ms * 1e3:.1f} us", flush=True)
+    assert ok == len(lps)
+    for i, lp in enumerate(lps):
+        assert max(res[i].rel_p, res[i].rel_d, res[i].rel_gap) <= 2e-5
+        opt = float(lp.c @ lp.x_star)
+        assert abs(res[i].pobj - opt) <= 1e-4 * (1 + abs(opt))
+        assert push[i].status in (pdhg.PDHG_PUSH_DONE, pdhg.PDHG_ITER_LIMIT)
+
+
+def test_batch_state_errors():
+    lps = _family(2, 8000)
+    bt = pdhg.Batch(lps)
+    with pytest.raises(pdhg.PdhgError):
+        bt.corner_push([1, 2])
+    with pytest.raises(pdhg.PdhgError):
+        pdhg.Batch(lps, lanes_at=8)
