@@ -47,6 +47,7 @@ extern "C" {
 #endif
 
 typedef struct pdhg_solver pdhg_solver;
+typedef struct pdhg_mlp pdhg_mlp;
 
 /* solve / push outcome */
 enum pdhg_status {
@@ -106,6 +107,8 @@ typedef struct pdhg_params {
     int32_t autotune;      /* 1: at create, time every kernel choice of each half on
                               scratch vectors and keep the fastest (0 = default: the
                               mean-row-length rule, reproducible run to run)          */
+    int32_t record_history;/* 1: keep x and z of the last 4 restarts of the solve (the
+                              learned push's trend features); default 0               */
 } pdhg_params;
 
 /* outcome of pdhg_solve / pdhg_iterate, evaluated on the original model */
@@ -144,6 +147,8 @@ typedef struct pdhg_push_result {
     double seconds;
     pdhg_kkt_report before; /* (x, y, z) of the solve, original model                 */
     pdhg_kkt_report after;  /* (xhat, y, z): pushed x with the solve's y and z         */
+    int64_t n_learned_fix;  /* learned push: columns fixed from the predictor          */
+    int64_t n_learned_undo; /* learned push: fixes undone at push checks               */
 } pdhg_push_result;
 
 /* Live kernel timing (params.timing = 1): average durations of the two
@@ -273,6 +278,73 @@ int pdhg_batch_get_solution(pdhg_batch *b, int32_t i, double *x, double *y, doub
 int pdhg_batch_get_report(pdhg_batch *b, pdhg_batch_report *r);
 
 void pdhg_batch_destroy(pdhg_batch *b);
+
+/* ------------------------------------------------------------------------
+ * Learned fix predictor: a per-variable network 16 -> 64 -> 64 -> 1 (12
+ * features padded to 16) on bfloat16 matrix cores with float32 accumulation
+ * and float32 master weights:  h1 = relu(W1 f + b1), h2 = relu(W2 h1 + b2),
+ * logit = w3 . h2 + b3, probability = 1 / (1 + exp(-logit)).  It predicts
+ * which variables end at a bound after the corner push (Algorithm 1 of
+ * section 3), so that the push can start with them fixed; the paper itself
+ * has no learned component.  Parameters are a flat float32 vector of
+ * PDHG_MLP_NPARAMS values in the order w1 (64 x 16, row-major), b1 (64),
+ * w2 (64 x 64), b2 (64), w3 (64), b3 (1).  Features are float32, 16 per
+ * variable, row-major, rounded to bfloat16 on the device.
+ * ------------------------------------------------------------------------ */
+#define PDHG_MLP_NPARAMS 5313
+#define PDHG_MLP_FEATURES 16
+
+typedef struct pdhg_train_params {
+    int32_t epochs;     /* passes over the data; default 4                          */
+    int32_t batch;      /* minibatch size, 1..65536; default 4096                   */
+    double lr, beta1, beta2, eps; /* Adam; defaults 1e-3, 0.9, 0.999, 1e-8          */
+    double pos_weight;  /* weight of positive samples in the loss; <= 0: N_neg/N_pos */
+    uint64_t seed;      /* shuffling seed                                           */
+} pdhg_train_params;
+
+typedef struct pdhg_train_report {
+    double loss_first, loss_last; /* mean weighted BCE of the first and last epoch    */
+    double seconds;
+    int64_t steps;      /* Adam steps                                               */
+    double samples_per_s;
+    double pos_weight;  /* the weight used                                          */
+} pdhg_train_report;
+
+/* New network with Kaiming-uniform weights (bound sqrt(6 / fan_in), drawn
+ * from splitmix64 of seed xor parameter index) and zero biases. */
+int pdhg_mlp_create(uint64_t seed, pdhg_mlp **out);
+void pdhg_mlp_destroy(pdhg_mlp *net);
+/* Copy parameters in / out (host, PDHG_MLP_NPARAMS floats); setting them
+ * resets the Adam state. */
+int pdhg_mlp_set_params(pdhg_mlp *net, const float *params);
+int pdhg_mlp_get_params(pdhg_mlp *net, float *params);
+/* logits[n] of features[n x 16] (host arrays). */
+int pdhg_mlp_forward(pdhg_mlp *net, const float *features, int64_t n, float *logits);
+/* Gradient of the mean weighted binary cross-entropy over n <= 65536
+ * samples (labels 0/1) into grad[PDHG_MLP_NPARAMS]; *loss = the mean loss. */
+int pdhg_mlp_gradient(pdhg_mlp *net, const float *features, const float *labels, int64_t n, double pos_weight,
+                      float *grad, double *loss);
+void pdhg_default_train_params(pdhg_train_params *t);
+/* Adam training over n samples (features n x 16, labels n), shuffled per
+ * epoch; t == NULL uses the defaults. */
+int pdhg_mlp_train(pdhg_mlp *net, const float *features, const float *labels, int64_t n, const pdhg_train_params *t,
+                   pdhg_train_report *r);
+
+/* The 12 predictor features of every column of a solved LP (before its
+ * push), normalised as the network sees them: out[n x 16] float32 host
+ * array (columns 12..15 are 0), or NULL to only compute them.  The trend
+ * features need params.record_history = 1 (else they are 0).  Errors:
+ * STATE before a solve or after a push. */
+int pdhg_features(pdhg_solver *s, float *out);
+
+/* Corner push with a learned warm start: the plain fixes of Algorithm 1,
+ * then every column the plain rule leaves free whose predicted probability
+ * is >= theta is fixed at its nearer finite bound if the sign of its reduced
+ * cost allows it; at each push check a learned fix whose push-model reduced
+ * cost has the wrong sign (beyond eps_abs) is undone.  r->n_learned_fix and
+ * r->n_learned_undo count them.  Errors as pdhg_corner_push, and INVALID_ARG
+ * for theta outside (0, 1). */
+int pdhg_corner_push_learned(pdhg_solver *s, pdhg_mlp *net, double theta, uint64_t seed, pdhg_push_result *r);
 
 /* Release all device memory of the handle (NULL is a no-op). */
 void pdhg_destroy(pdhg_solver *s);

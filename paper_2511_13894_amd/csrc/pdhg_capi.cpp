@@ -14,6 +14,7 @@
 
 #include "pdhg.h"
 #include "pdhg_internal.hpp"
+#include "pdhg_mlp.hpp"
 
 namespace pdhg {
 
@@ -58,7 +59,8 @@ void free_all(pdhg_solver *s)
     void *ptrs[] = {s->rp,   s->ci, s->av,  s->tp,   s->ti,     s->tperm, s->atv,  s->b,   s->c,       s->l,
                     s->u,    s->sense0, s->dr, s->dc, s->ahat, s->ahat_t, s->x,   s->y,     s->xa,   s->ya,
                     s->xbar, s->xp, s->yp,  s->ch,   s->bh,     s->lh,    s->uh,   s->xs,  s->ys,      s->sense,
-                    s->ax,   s->aty, s->xu, s->yu,   s->zsol,   s->xpush, s->partials, s->redout, s->st};
+                    s->ax,   s->aty, s->xu, s->yu,   s->zsol,   s->xpush, s->partials, s->redout, s->st,
+                    s->hx,   s->hz,  s->feat_raw, s->feat_b, s->logits, s->lfix, s->lcount};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->st_host) (void)hipHostFree(s->st_host);
@@ -295,6 +297,7 @@ void pdhg_default_params(pdhg_params *p)
     p->use_graph = 1;
     p->timing = 0;
     p->autotune = 0;
+    p->record_history = 0;
 }
 
 const char *pdhg_last_error(void) { return g_last_error.c_str(); }
@@ -446,6 +449,10 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
         dalloc(&s->xpush, N);
         const size_t nparts = (size_t)(Q_COUNT + 1) * (s->red_blocks_m + s->red_blocks_n) * 3 + 4 * kMaxRedBlocks;
         dalloc(&s->partials, nparts);
+        if (p.record_history) {
+            dalloc(&s->hx, 4 * N);
+            dalloc(&s->hz, 4 * N);
+        }
         dalloc(&s->redout, 64);
         dalloc(&s->st, 1);
         HIPCHK(hipHostMalloc((void **)&s->st_host, sizeof(DevState), hipHostMallocDefault));
@@ -530,7 +537,7 @@ int pdhg_solve(pdhg_solver *s, pdhg_result *r)
     return pdhg_iterate(s, left > 0 ? left : 0, r);
 }
 
-int pdhg_corner_push(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
+static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, pdhg_mlp *net, double theta)
 {
     if (!s || !r) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
     if (!s->solved || s->in_push) return fail(PDHG_ERR_STATE, "corner push needs a solve first (and runs once)");
@@ -544,8 +551,20 @@ int pdhg_corner_push(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
         HIPCHK(hipMemcpyAsync(s->ys, s->yp, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
         HIPCHK(unscale(s, s->xs, s->ys, s->xu, s->yu));
         HIPCHK(report(s, s->xu, s->yu, s->zsol, &r->before));
+        if (net) { // predictor on the solve's state, before the model changes
+            const size_t n = (size_t)(s->n > 0 ? s->n : 1);
+            if (!s->feat_raw) dalloc(&s->feat_raw, 16 * n);
+            if (!s->feat_b) dalloc(&s->feat_b, 16 * n);
+            if (!s->logits) dalloc(&s->logits, n);
+            if (!s->lfix) dalloc(&s->lfix, n);
+            if (!s->lcount) dalloc(&s->lcount, 2);
+            HIPCHK(hipMemsetAsync(s->lcount, 0, 2 * sizeof(unsigned), st));
+            HIPCHK(compute_features(s));
+            HIPCHK(mlp_forward(net, st, s->feat_b, s->n, s->logits));
+        }
         // CP2-CP5: bounds, senses, objective, start (x, 0), new weight and restart state
-        HIPCHK(push_setup(s, seed, r));
+        HIPCHK(push_setup(s, seed, r, net ? theta : -1.0));
+        s->learned_active = net != nullptr;
         HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         s->in_push = true;
@@ -563,6 +582,42 @@ int pdhg_corner_push(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
         r->restarts = s->st_host->restarts;
         r->rel_p_push = s->st_host->checks > 0 ? s->st_host->rel_p : NAN;
         r->seconds = now_s() - t0;
+        if (net) {
+            unsigned cnt[2] = {0, 0};
+            HIPCHK(hipMemcpy(cnt, s->lcount, sizeof(cnt), hipMemcpyDeviceToHost));
+            r->n_learned_fix = cnt[0];
+            r->n_learned_undo = cnt[1];
+        }
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_corner_push(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
+{
+    return corner_push_common(s, seed, r, nullptr, -1.0);
+}
+
+int pdhg_corner_push_learned(pdhg_solver *s, pdhg_mlp *net, double theta, uint64_t seed, pdhg_push_result *r)
+{
+    if (!net) return fail(PDHG_ERR_INVALID_ARG, "NULL network");
+    if (!(theta > 0.0 && theta < 1.0)) return fail(PDHG_ERR_INVALID_ARG, "theta must lie in (0, 1)");
+    return corner_push_common(s, seed, r, net, theta);
+}
+
+int pdhg_features(pdhg_solver *s, float *out)
+{
+    if (!s) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
+    if (!s->solved || s->in_push) return fail(PDHG_ERR_STATE, "features describe a solved LP before its push");
+    try {
+        const size_t n = (size_t)(s->n > 0 ? s->n : 1);
+        if (!s->feat_raw) dalloc(&s->feat_raw, 16 * n);
+        if (!s->feat_b) dalloc(&s->feat_b, 16 * n);
+        HIPCHK(compute_features(s));
+        if (out) HIPCHK(hipMemcpyAsync(out, s->feat_raw, sizeof(float) * 16 * (size_t)s->n, hipMemcpyDeviceToHost,
+                                       s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
     } catch (const HipFailure &f) {
         return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
     }

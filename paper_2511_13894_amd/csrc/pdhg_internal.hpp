@@ -120,6 +120,16 @@ struct pdhg_solver {
     int graph_len = 0;
     int graph_mode = -1;
 
+    // learned push: restart history (4 slots of x and z, scaled), features,
+    // per-column learned-fix flags (1 lower, 2 upper) and counters
+    float *hx = nullptr, *hz = nullptr;
+    float *feat_raw = nullptr;   // n x 12
+    short *feat_b = nullptr;     // n x 16 bfloat16
+    float *logits = nullptr;     // n
+    int8_t *lfix = nullptr;      // n
+    unsigned *lcount = nullptr;  // [fixed, undone]
+    bool learned_active = false;
+
     // live kernel timing: events around one primal and one dual launch per cycle
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     double t_primal_ms = 0.0, t_dual_ms = 0.0;
@@ -177,7 +187,7 @@ hipError_t candidate_from_iterate(pdhg_solver *s);
 hipError_t launch_start_vectors(pdhg_solver *s, bool fresh_start);
 hipError_t unscale(pdhg_solver *s, const void *xh, const void *yh, double *xo, double *yo);
 hipError_t report(pdhg_solver *s, const double *x, const double *y, double *z, pdhg_kkt_report *k);
-hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r);
+hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, double theta);
 hipError_t capture_cycle(pdhg_solver *s, int len, int mode);
 hipError_t copy_probe(int64_t bytes, int reps, double *gbps);
 
@@ -191,6 +201,12 @@ hipError_t batch_capture_cycle(pdhg_batch *b, int len, int mode);
 hipError_t batch_report(pdhg_batch *b, const double *x, const double *y, double *z, pdhg_kkt_report *out);
 hipError_t batch_push_setup(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *out);
 hipError_t batch_keep_unpushed(pdhg_batch *b);
+
+// learned push (pdhg_learned.hip)
+hipError_t launch_record_history(pdhg_solver *s);
+hipError_t launch_learned_undo(pdhg_solver *s);
+hipError_t compute_features(pdhg_solver *s);
+hipError_t launch_learned_fix(pdhg_solver *s, double theta);
 int choose_kernel(double mean_row);
 hipError_t autotune(pdhg_solver *s);
 

@@ -366,6 +366,14 @@ hipError_t launch_check(pdhg_solver *s, int mode, int len)
         check_impl<double>(s, (const double *)(use_cand ? s->xp : s->x), (const double *)(use_cand ? s->yp : s->y), pm,
                            pn);
     hipLaunchKernelGGL(k_check_final, dim3(1), dim3(kBlock), 0, s->stream, s->st, pm, gm, pn, gn, mode, len);
+    if (mode == 1 && s->hx) { // restart history for the learned push (before the restart copies)
+        hipError_t e = launch_record_history(s);
+        if (e != hipSuccess) return e;
+    }
+    if (mode == 2 && s->learned_active) { // undo learned fixes the push model's duals reject
+        hipError_t e = launch_learned_undo(s);
+        if (e != hipSuccess) return e;
+    }
     if (mode != 0) {
         const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
         if (s->fp32)
@@ -810,7 +818,7 @@ __global__ __launch_bounds__(kBlock) void k_sum3(const double *__restrict__ p, i
 }
 
 template <typename V>
-static hipError_t push_setup_impl(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
+static hipError_t push_setup_impl(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, double theta)
 {
     hipStream_t st = s->stream;
     const int gn = s->red_blocks_n, gm = s->red_blocks_m;
@@ -821,6 +829,10 @@ static hipError_t push_setup_impl(pdhg_solver *s, uint64_t seed, pdhg_push_resul
     hipLaunchKernelGGL(k_push_rows, dim3(gm), dim3(kBlock), 0, st, s->m, s->yu, s->p.eps_abs, s->sense, (double *)s->y,
                        pcnt + 2 * gn);
     hipLaunchKernelGGL(k_sum3, dim3(1), dim3(kBlock), 0, st, pcnt, gn, gm, s->redout);
+    if (theta > 0.0) { // learned warm start on the columns the plain rule leaves free
+        hipError_t e = launch_learned_fix(s, theta);
+        if (e != hipSuccess) return e;
+    }
     hipMemcpyAsync(s->rep_host, s->redout, 3 * sizeof(double), hipMemcpyDeviceToHost, st);
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return e;
@@ -830,9 +842,9 @@ static hipError_t push_setup_impl(pdhg_solver *s, uint64_t seed, pdhg_push_resul
     return phase_start<V>(s, false);
 }
 
-hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
+hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, double theta)
 {
-    return s->fp32 ? push_setup_impl<float>(s, seed, r) : push_setup_impl<double>(s, seed, r);
+    return s->fp32 ? push_setup_impl<float>(s, seed, r, theta) : push_setup_impl<double>(s, seed, r, theta);
 }
 
 // ------------------------------------------------------- kernel choice ---

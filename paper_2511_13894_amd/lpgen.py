@@ -286,3 +286,80 @@ def from_dense(a, b, c, l=None, u=None, sense=None, name="dense") -> LP:
         s = np.frombuffer(sense.encode() if isinstance(sense, str) else bytes(sense), dtype=np.uint8).copy()
     return LP(m, n, row_ptr, ci, va, np.asarray(b, dtype=np.float64), np.asarray(c, dtype=np.float64), l, u, s,
               name=name)
+
+
+def multicommodity(n_nodes: int = 50_000, n_arcs: int = 400_000, n_comm: int = 8, seed: int = 4100,
+                   walks: int = 500, max_len: int = 20) -> LP:
+    """Multicommodity flow LP with shared arc capacities.
+
+    Graph: a Hamiltonian cycle over a random node order plus random extra
+    arcs (no self-loops, no duplicates) up to n_arcs.  Per commodity, flow is
+    planted on `walks` random walks (length <= max_len along out-arcs,
+    amounts U(1,5)); b_k is the node balance of the planted flow.  Arc
+    capacities U(10,100), scaled down where needed so that the planted total
+    load is at most 0.8 of capacity (the LP is feasible); costs U(1,50) per
+    arc, shared by all commodities.  Variables x[a, k] >= 0, column index
+    k * n_arcs + a.  Rows: node balance (node v, commodity k) at
+    k * n_nodes + v ('='), then arc capacity (a) at n_comm * n_nodes + a ('<').
+    """
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(n_nodes)
+    tail = list(order)
+    head = list(np.roll(order, -1))
+    seen = set(zip(tail, head))
+    need = n_arcs - n_nodes
+    while need > 0:
+        t = rng.integers(0, n_nodes, size=2 * need)
+        h = rng.integers(0, n_nodes, size=2 * need)
+        for a, b2 in zip(t.tolist(), h.tolist()):
+            if a != b2 and (a, b2) not in seen:
+                seen.add((a, b2))
+                tail.append(a)
+                head.append(b2)
+                need -= 1
+                if need == 0:
+                    break
+    tail = np.array(tail, dtype=np.int64)
+    head = np.array(head, dtype=np.int64)
+    # out-arc lists for the walks
+    order_out = np.argsort(tail, kind="stable")
+    start = np.searchsorted(tail[order_out], np.arange(n_nodes + 1))
+    flow = np.zeros((n_comm, n_arcs))
+    for k in range(n_comm):
+        src = rng.integers(0, n_nodes, size=walks)
+        lens = rng.integers(1, max_len + 1, size=walks)
+        amt = rng.uniform(1.0, 5.0, size=walks)
+        for w in range(walks):
+            v = src[w]
+            for _ in range(lens[w]):
+                deg = start[v + 1] - start[v]
+                a = order_out[start[v] + rng.integers(0, deg)]
+                flow[k, a] += amt[w]
+                v = head[a]
+    cap = rng.uniform(10.0, 100.0, size=n_arcs)
+    load = flow.sum(axis=0)
+    cap = np.maximum(cap, load / 0.8)
+    cost = rng.uniform(1.0, 50.0, size=n_arcs)
+    m = n_comm * n_nodes + n_arcs
+    n = n_comm * n_arcs
+    cols = np.arange(n, dtype=np.int64)
+    k_of = cols // n_arcs
+    a_of = cols % n_arcs
+    rows = np.concatenate([k_of * n_nodes + tail[a_of], k_of * n_nodes + head[a_of], n_comm * n_nodes + a_of])
+    vals = np.concatenate([np.ones(n), -np.ones(n), np.ones(n)])
+    cc = np.concatenate([cols, cols, cols])
+    row_ptr, ci, va = _csr_from_coo(m, rows, cc, vals)
+    bal = np.zeros((n_comm, n_nodes))
+    for k in range(n_comm):
+        np.add.at(bal[k], tail, flow[k])
+        np.subtract.at(bal[k], head, flow[k])
+    b = np.concatenate([bal.reshape(-1), cap])
+    sense = np.concatenate([np.full(n_comm * n_nodes, ord("="), dtype=np.uint8), np.full(n_arcs, ord("<"), dtype=np.uint8)])
+    c = np.tile(cost, n_comm)
+    return LP(m, n, row_ptr, ci, va, b, c, np.zeros(n), np.full(n, np.inf), sense,
+              x_star=flow.reshape(-1), name=f"mcf_{n_nodes}n_{n_arcs}a_{n_comm}k_s{seed}")
+
+
+def config4(seed: int = 4100) -> LP:
+    """Evaluation LP of the learned part: 50k nodes, 400k arcs, 8 commodities."""
+    return multicommodity(50_000, 400_000, 8, seed)

@@ -37,7 +37,7 @@ class Params(C.Structure):
         ("push_min_iters", C.c_int32), ("precision", C.c_int32),
         ("push_obj_scale", C.c_double), ("push_max_iter", C.c_int64), ("time_limit", C.c_double),
         ("stream", C.c_void_p), ("verbosity", C.c_int32), ("lanes_at", C.c_int32), ("lanes_a", C.c_int32),
-        ("use_graph", C.c_int32), ("timing", C.c_int32), ("autotune", C.c_int32),
+        ("use_graph", C.c_int32), ("timing", C.c_int32), ("autotune", C.c_int32), ("record_history", C.c_int32),
     ]
 
 
@@ -67,6 +67,7 @@ class PushResult(C.Structure):
         ("status", C.c_int32), ("pad_", C.c_int32), ("iters", C.c_int64), ("restarts", C.c_int64),
         ("n_fix_lower", C.c_int64), ("n_fix_upper", C.c_int64), ("n_rows_to_eq", C.c_int64),
         ("rel_p_push", C.c_double), ("seconds", C.c_double), ("before", KKTReport), ("after", KKTReport),
+        ("n_learned_fix", C.c_int64), ("n_learned_undo", C.c_int64),
     ]
 
 
@@ -97,10 +98,30 @@ class BatchReport(C.Structure):
     ]
 
 
+class TrainParams(C.Structure):
+    _fields_ = [
+        ("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
+        ("beta2", C.c_double), ("eps", C.c_double), ("pos_weight", C.c_double), ("seed", C.c_uint64),
+    ]
+
+
+class TrainReport(C.Structure):
+    _fields_ = [
+        ("loss_first", C.c_double), ("loss_last", C.c_double), ("seconds", C.c_double), ("steps", C.c_int64),
+        ("samples_per_s", C.c_double), ("pos_weight", C.c_double),
+    ]
+
+
+MLP_NPARAMS = 5313
+MLP_FEATURES = 16
+
 EXPORTS = ["pdhg_default_params", "pdhg_create", "pdhg_solve", "pdhg_iterate", "pdhg_corner_push", "pdhg_kkt",
            "pdhg_get_solution", "pdhg_get_iterate", "pdhg_get_scaling", "pdhg_destroy", "pdhg_last_error",
            "pdhg_struct_size", "pdhg_get_timing", "pdhg_copy_probe", "pdhg_batch_create", "pdhg_batch_solve",
-           "pdhg_batch_corner_push", "pdhg_batch_get_solution", "pdhg_batch_get_report", "pdhg_batch_destroy"]
+           "pdhg_batch_corner_push", "pdhg_batch_get_solution", "pdhg_batch_get_report", "pdhg_batch_destroy",
+           "pdhg_mlp_create", "pdhg_mlp_destroy", "pdhg_mlp_set_params", "pdhg_mlp_get_params", "pdhg_mlp_forward",
+           "pdhg_mlp_gradient", "pdhg_default_train_params", "pdhg_mlp_train", "pdhg_features",
+           "pdhg_corner_push_learned"]
 
 _lib = None
 
@@ -138,12 +159,27 @@ def load(path: Optional[Path] = None):
     lib.pdhg_batch_get_report.argtypes = [C.c_void_p, P(BatchReport)]
     lib.pdhg_batch_destroy.argtypes = [C.c_void_p]
     lib.pdhg_batch_destroy.restype = None
+    fp = P(C.c_float)
+    lib.pdhg_mlp_create.argtypes = [C.c_uint64, P(C.c_void_p)]
+    lib.pdhg_mlp_destroy.argtypes = [C.c_void_p]
+    lib.pdhg_mlp_destroy.restype = None
+    lib.pdhg_mlp_set_params.argtypes = [C.c_void_p, fp]
+    lib.pdhg_mlp_get_params.argtypes = [C.c_void_p, fp]
+    lib.pdhg_mlp_forward.argtypes = [C.c_void_p, fp, C.c_int64, fp]
+    lib.pdhg_mlp_gradient.argtypes = [C.c_void_p, fp, fp, C.c_int64, C.c_double, fp, P(C.c_double)]
+    lib.pdhg_default_train_params.argtypes = [P(TrainParams)]
+    lib.pdhg_default_train_params.restype = None
+    lib.pdhg_mlp_train.argtypes = [C.c_void_p, fp, fp, C.c_int64, P(TrainParams), P(TrainReport)]
+    lib.pdhg_features.argtypes = [C.c_void_p, fp]
+    lib.pdhg_corner_push_learned.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_uint64, P(PushResult)]
     lib.pdhg_last_error.restype = C.c_char_p
     lib.pdhg_struct_size.restype = C.c_int32
     lib.pdhg_struct_size.argtypes = [C.c_int32]
     for fn in ("pdhg_create", "pdhg_solve", "pdhg_iterate", "pdhg_corner_push", "pdhg_kkt", "pdhg_get_solution",
                "pdhg_get_iterate", "pdhg_get_scaling", "pdhg_get_timing", "pdhg_copy_probe", "pdhg_batch_create",
-               "pdhg_batch_solve", "pdhg_batch_corner_push", "pdhg_batch_get_solution", "pdhg_batch_get_report"):
+               "pdhg_batch_solve", "pdhg_batch_corner_push", "pdhg_batch_get_solution", "pdhg_batch_get_report",
+               "pdhg_mlp_create", "pdhg_mlp_set_params", "pdhg_mlp_get_params", "pdhg_mlp_forward",
+               "pdhg_mlp_gradient", "pdhg_mlp_train", "pdhg_features", "pdhg_corner_push_learned"):
         getattr(lib, fn).restype = C.c_int
     sizes = [C.sizeof(Params), C.sizeof(Result), C.sizeof(KKTReport), C.sizeof(PushResult), C.sizeof(Timing),
              C.sizeof(LpDesc), C.sizeof(BatchReport)]
@@ -269,6 +305,16 @@ class Solver:
         self._check(self.lib.pdhg_get_iterate(self.h, _dp(x), _dp(y)))
         return x, y
 
+    def features(self):
+        f = np.zeros((self.n, 16), dtype=np.float32)
+        self._check(self.lib.pdhg_features(self.h, f.ctypes.data_as(C.POINTER(C.c_float))))
+        return f
+
+    def corner_push_learned(self, net, theta: float, seed: int) -> PushResult:
+        r = PushResult()
+        self._check(self.lib.pdhg_corner_push_learned(self.h, net.h, float(theta), C.c_uint64(seed), C.byref(r)))
+        return r
+
     def get_timing(self) -> Timing:
         t = Timing()
         self._check(self.lib.pdhg_get_timing(self.h, C.byref(t)))
@@ -344,4 +390,67 @@ class Batch:
     def report(self) -> BatchReport:
         r = BatchReport()
         self._check(self.lib.pdhg_batch_get_report(self.h, C.byref(r)))
+        return r
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Mlp:
+    """The per-variable fix predictor on the GPU (pdhg_mlp_*)."""
+
+    def __init__(self, seed: int = 1):
+        _refuse_second_runtime()
+        self.lib = load()
+        h = C.c_void_p()
+        rc = self.lib.pdhg_mlp_create(C.c_uint64(seed), C.byref(h))
+        if rc != 0:
+            raise PdhgError(rc, self.lib.pdhg_last_error().decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != 0:
+            raise PdhgError(rc, self.lib.pdhg_last_error().decode())
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.pdhg_mlp_destroy(h)
+        self.h = None
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        assert a.size == MLP_NPARAMS
+        self._check(self.lib.pdhg_mlp_set_params(self.h, _fp(a)))
+
+    def get_params(self):
+        a = np.zeros(MLP_NPARAMS, dtype=np.float32)
+        self._check(self.lib.pdhg_mlp_get_params(self.h, _fp(a)))
+        return a
+
+    def forward(self, features):
+        f = np.ascontiguousarray(features, dtype=np.float32).reshape(-1, MLP_FEATURES)
+        out = np.zeros(f.shape[0], dtype=np.float32)
+        self._check(self.lib.pdhg_mlp_forward(self.h, _fp(f), f.shape[0], _fp(out)))
+        return out
+
+    def gradient(self, features, labels, pos_weight):
+        f = np.ascontiguousarray(features, dtype=np.float32).reshape(-1, MLP_FEATURES)
+        y = np.ascontiguousarray(labels, dtype=np.float32)
+        g = np.zeros(MLP_NPARAMS, dtype=np.float32)
+        loss = C.c_double()
+        self._check(self.lib.pdhg_mlp_gradient(self.h, _fp(f), _fp(y), f.shape[0], float(pos_weight), _fp(g),
+                                               C.byref(loss)))
+        return g, loss.value
+
+    def train(self, features, labels, **kw):
+        t = TrainParams()
+        self.lib.pdhg_default_train_params(C.byref(t))
+        for k, v in kw.items():
+            setattr(t, k, v)
+        f = np.ascontiguousarray(features, dtype=np.float32).reshape(-1, MLP_FEATURES)
+        y = np.ascontiguousarray(labels, dtype=np.float32)
+        r = TrainReport()
+        self._check(self.lib.pdhg_mlp_train(self.h, _fp(f), _fp(y), f.shape[0], C.byref(t), C.byref(r)))
         return r

@@ -1,0 +1,86 @@
+"""BF16 MFMA fix-predictor kernels vs the CPU reference (same rounding
+points; the hardware's float32 accumulation order is the only difference,
+so a hidden activation can land one bfloat16 step away: tolerances below)."""
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as M
+from paper_2511_13894_amd import pdhg
+
+pytestmark = pytest.mark.gpu
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((n, 16)).astype(np.float32)
+    f[:, 12:] = 0
+    y = (f[:, 0] - 0.7 * f[:, 5] + 0.3 * rng.standard_normal(n) > 0.4).astype(np.float32)
+    return f, y
+
+
+def test_forward_matches_reference():
+    f, _ = _data(1000, 0)  # not a multiple of 16: ragged last tile
+    p = M.init_params(5)
+    p["b1"] = 0.1 * np.random.default_rng(1).standard_normal(64)
+    p["b2"] = 0.1 * np.random.default_rng(2).standard_normal(64)
+    p["b3"] = np.array([0.2])
+    net = pdhg.Mlp(3)
+    net.set_params(M.flat(p))
+    zg = net.forward(f)
+    zo, _ = M.forward(M.unflat(net.get_params()), f.astype(np.float64))
+    err = np.abs(zg - zo)
+    print(f"[mlp] forward: max |dz| {err.max():.2e}, mean {err.mean():.2e}", flush=True)
+    assert err.mean() <= 2e-3
+    assert np.all(err <= 3e-2 * (1 + np.abs(zo)))
+
+
+def test_gradient_matches_reference():
+    f, y = _data(2000, 4)
+    p = M.init_params(9)
+    net = pdhg.Mlp(3)
+    net.set_params(M.flat(p))
+    q = M.unflat(net.get_params())
+    g, loss = net.gradient(f, y, 2.0)
+    lo, go, _ = M.loss_and_grad(q, f.astype(np.float64), y.astype(np.float64), 2.0)
+    go = M.flat(go)
+    assert loss == pytest.approx(lo, rel=2e-3)
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    print(f"[mlp] gradient: relative l2 error {rel:.2e}, loss gpu {loss:.6f} ref {lo:.6f}", flush=True)
+    assert rel <= 1e-2
+    # each block of parameters separately
+    for k, sl in (("w1", slice(0, 1024)), ("w2", slice(1088, 5184)), ("w3", slice(5248, 5312))):
+        r = np.linalg.norm(g[sl] - go[sl]) / max(np.linalg.norm(go[sl]), 1e-30)
+        assert r <= 2e-2, (k, r)
+    assert np.all(g[0:1024].reshape(64, 16)[:, 12:] == 0)
+
+
+def test_training_lowers_the_loss_and_learns():
+    f, y = _data(20000, 7)
+    net = pdhg.Mlp(11)
+    rep = net.train(f, y, epochs=6, batch=2048, lr=3e-3, seed=5)
+    z = net.forward(f)
+    acc = np.mean((z > 0) == (y > 0.5))
+    print(f"[mlp] train: loss {rep.loss_first:.4f} -> {rep.loss_last:.4f}, {rep.samples_per_s:.3e} samples/s, "
+          f"accuracy {acc:.3f}", flush=True)
+    assert rep.loss_last < 0.7 * rep.loss_first
+    assert acc > 0.9
+
+
+def test_one_adam_step_matches_reference():
+    """A single training step on one minibatch: parameters move as the
+    reference Adam step with the reference gradient predicts."""
+    f, y = _data(512, 12)
+    p = M.init_params(2)
+    net = pdhg.Mlp(3)
+    net.set_params(M.flat(p))
+    q = M.unflat(net.get_params())
+    net.train(f, y, epochs=1, batch=512, lr=1e-3, pos_weight=1.0, seed=1)
+    _, go, _ = M.loss_and_grad(q, f.astype(np.float64), y.astype(np.float64), 1.0)
+    q2 = M.adam_step(q, go, {}, lr=1e-3)
+    moved_g = net.get_params() - M.flat(q)
+    moved_o = M.flat(q2) - M.flat(q)
+    mask = np.abs(moved_o) > 1e-5
+    agree = np.mean(np.sign(moved_g[mask]) == np.sign(moved_o[mask]))
+    print(f"[mlp] adam step: sign agreement {agree:.4f} over {mask.sum()} parameters", flush=True)
+    assert agree > 0.97
+    np.testing.assert_allclose(moved_g[mask], moved_o[mask], rtol=0.2, atol=2e-4)
