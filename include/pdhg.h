@@ -85,10 +85,13 @@ typedef struct pdhg_params {
     double restart_art;    /* ... or k >= art * t (artificial); default 0.36            */
     double pw_smooth;      /* primal-weight log-smoothing; default 0.5                  */
     double pc_alpha;       /* Pock-Chambolle exponent; default 1; < 0 disables the pass */
-    int32_t power_iters;   /* power-iteration steps for ||Ahat||_2; default 32          */
+    int32_t power_iters;   /* cap on power-iteration steps for ||Ahat||_2; default 4000 */
     int32_t halpern;       /* 1: reflected Halpern average (default), 0: plain PDHG     */
     double eta_safety;     /* step = eta_safety / ||Ahat||_2 estimate; default 0.99     */
     double reflect_gamma;  /* reflection gamma in [0,1]; default 1                      */
+    double power_tol;      /* the power iteration on Ahat'Ahat stops at the first step
+                              whose eigen-residual ||Mv - rho v|| <= power_tol * rho
+                              (rho the Rayleigh quotient of the unit v); default 1e-3  */
     int32_t push_min_iters;/* push iterations before the first push check; default 100  */
     int32_t precision;     /* enum pdhg_precision; default PDHG_FP64                    */
     double push_obj_scale; /* push objective = scale * Uniform[0,1); default 1          */
@@ -206,8 +209,9 @@ int pdhg_get_solution(pdhg_solver *s, double *x, double *y, double *z);
 int pdhg_get_iterate(pdhg_solver *s, double *x, double *y);
 
 /* Scaling vectors Dr (m), Dc (n) (Ahat = diag(Dr) A diag(Dc)) and
- * scalars4 = {eta, omega, sigma_estimate, iterations of the phase}. */
-int pdhg_get_scaling(pdhg_solver *s, double *dr, double *dc, double *scalars4);
+ * scalars5 = {eta, omega, sigma_estimate, iterations of the phase,
+ * power-iteration steps taken}.  Any pointer may be NULL. */
+int pdhg_get_scaling(pdhg_solver *s, double *dr, double *dc, double *scalars5);
 
 /* Kernel timing and byte model (see pdhg_timing).  Errors: INVALID_ARG. */
 int pdhg_get_timing(pdhg_solver *s, pdhg_timing *t);
@@ -330,12 +334,21 @@ void pdhg_default_train_params(pdhg_train_params *t);
 int pdhg_mlp_train(pdhg_mlp *net, const float *features, const float *labels, int64_t n, const pdhg_train_params *t,
                    pdhg_train_report *r);
 
-/* The 12 predictor features of every column of a solved LP (before its
- * push), normalised as the network sees them: out[n x 16] float32 host
- * array (columns 12..15 are 0), or NULL to only compute them.  The trend
- * features need params.record_history = 1 (else they are 0).  Errors:
- * STATE before a solve or after a push. */
-int pdhg_features(pdhg_solver *s, float *out);
+/* The 16 predictor features of every column of a solved LP (before its
+ * push), normalised as the network sees them, into out[n x 16] (float32
+ * host array, row j = column j), or NULL to only compute them:
+ *   0..3  x_j, z_j, |c_j|, ||A_{:,j}||_2 on the scaled model;
+ *   4..11 x_j, then z_j, at each of the last 4 restarts minus the current
+ *         value (0 where fewer restarts happened, and all 0 unless
+ *         params.record_history = 1);
+ *   12    the push objective coefficient that pdhg_corner_push(seed) draws;
+ *   13-15 distance to the lower and the upper bound, relative position
+ *         between them (-1 where not defined);
+ * each mapped to sign(v) ln(1 + |v|/s), s its root mean square over the LP.
+ * The learned predictor of the push and its training data are built on
+ * these (the paper does not fix them).  Errors: STATE before a solve or
+ * after a push. */
+int pdhg_features(pdhg_solver *s, uint64_t seed, float *out);
 
 /* Corner push with a learned warm start: the plain fixes of Algorithm 1,
  * then every column the plain rule leaves free whose predicted probability

@@ -35,7 +35,7 @@ class OrParams(C.Structure):
         ("restart_suff", C.c_double), ("restart_nec", C.c_double), ("restart_art", C.c_double),
         ("pw_smooth", C.c_double), ("pc_alpha", C.c_double),
         ("power_iters", C.c_int32), ("halpern", C.c_int32),
-        ("eta_safety", C.c_double), ("reflect_gamma", C.c_double),
+        ("eta_safety", C.c_double), ("reflect_gamma", C.c_double), ("power_tol", C.c_double),
         ("push_min_iters", C.c_int32), ("pad_", C.c_int32),
         ("push_obj_scale", C.c_double), ("push_max_iter", C.c_int64),
     ]
@@ -200,9 +200,10 @@ class OracleSolver:
         return x, y, z
 
     def scaling(self):
-        dr, dc, o4 = np.zeros(self.m), np.zeros(self.n), np.zeros(4)
-        self.lib.or_get_scaling(self.h, _dp(dr), _dp(dc), _dp(o4))
-        return {"dr": dr, "dc": dc, "eta": o4[0], "omega": o4[1], "sigma_est": o4[2], "t": int(o4[3])}
+        dr, dc, o5 = np.zeros(self.m), np.zeros(self.n), np.zeros(5)
+        self.lib.or_get_scaling(self.h, _dp(dr), _dp(dc), _dp(o5))
+        return {"dr": dr, "dc": dc, "eta": o5[0], "omega": o5[1], "sigma_est": o5[2], "t": int(o5[3]),
+                "power_steps": int(o5[4])}
 
     def model_scaled(self):
         lh, uh, ch = np.zeros(self.n), np.zeros(self.n), np.zeros(self.n)

@@ -21,7 +21,11 @@
  * readings used for those silent parts are:
  *   scaling   : 10 Ruiz passes (inf-norm, rows and columns from the same
  *               matrix), then one Pock-Chambolle pass with alpha = 1;
- *   step size : power iteration on Ahat'Ahat from v0 = 1/sqrt(n), P steps,
+ *   step size : power iteration on M = Ahat'Ahat from v0 = 1/sqrt(n): each
+ *               step forms u = Ahat v, w = Ahat'u, rho = u'u (the Rayleigh
+ *               quotient of the unit v) and lambda = ||w||, and stops at the
+ *               first step whose eigen-residual ||w - rho v|| =
+ *               sqrt(w'w - rho^2) is at most tol * rho (else after P steps);
  *               eta = safety / sqrt(lambda);
  *   iteration : PDHG step T followed by a reflected Halpern average with the
  *               restart anchor (halpern = 0 gives vanilla PDHG);
@@ -67,6 +71,7 @@ typedef struct {
     int32_t halpern;
     double eta_safety;
     double reflect_gamma;
+    double power_tol;
     int32_t push_min_iters;
     int32_t pad_;
     double push_obj_scale;
@@ -117,6 +122,7 @@ typedef struct {
     double *ahat, *ahat_t; /* Ahat values in CSR order and in transpose order */
     double *dr, *dc;
     double eta, sigma_est;
+    int64_t power_steps; /* power-iteration steps taken */
     /* current (scaled) model: solve model or push model */
     double *bh, *ch, *lh, *uh;
     char *sense;
@@ -342,10 +348,11 @@ static void set_defaults(or_params *p)
     p->restart_art = 0.36;
     p->pw_smooth = 0.5;
     p->pc_alpha = 1.0;
-    p->power_iters = 32;
+    p->power_iters = 4000;
     p->halpern = 1;
     p->eta_safety = 0.99;
     p->reflect_gamma = 1.0;
+    p->power_tol = 1e-3;
     p->push_min_iters = 100;
     p->pad_ = 0;
     p->push_obj_scale = 1.0;
@@ -455,11 +462,17 @@ static void scale_and_step(or_solver *s)
     double *v = dalloc(n), *w = dalloc(n), *av = dalloc(m);
     for (int j = 0; j < n; j++) v[j] = 1.0 / sqrt((double)n);
     double lam = 0.0;
+    s->power_steps = 0;
     for (int it = 0; it < s->p.power_iters; it++) {
         mv_A(s, s->ahat, v, av);
         mv_At(s, s->ahat_t, av, w);
-        lam = norm2(w, n);
+        double rho = 0.0, ww = 0.0;
+        for (int i = 0; i < m; i++) rho += av[i] * av[i];
+        for (int j = 0; j < n; j++) ww += w[j] * w[j];
+        lam = sqrt(ww);
+        s->power_steps = it + 1;
         if (!(lam > 0.0)) break;
+        if (sqrt(fmax(ww - rho * rho, 0.0)) <= s->p.power_tol * rho) break;
         for (int j = 0; j < n; j++) v[j] = w[j] / lam;
     }
     s->sigma_est = lam > 0.0 ? sqrt(lam) : 0.0;
@@ -840,15 +853,16 @@ void or_get_solution(const or_solver *s, double *x, double *y, double *z)
     if (y) memcpy(y, s->ysol, sizeof(double) * (size_t)s->m);
     if (z) memcpy(z, s->zsol, sizeof(double) * (size_t)s->n);
 }
-void or_get_scaling(const or_solver *s, double *dr, double *dc, double *out4)
+void or_get_scaling(const or_solver *s, double *dr, double *dc, double *out5)
 {
     if (dr) memcpy(dr, s->dr, sizeof(double) * (size_t)s->m);
     if (dc) memcpy(dc, s->dc, sizeof(double) * (size_t)s->n);
-    if (out4) {
-        out4[0] = s->eta;
-        out4[1] = s->omega;
-        out4[2] = s->sigma_est;
-        out4[3] = (double)s->t;
+    if (out5) {
+        out5[0] = s->eta;
+        out5[1] = s->omega;
+        out5[2] = s->sigma_est;
+        out5[3] = (double)s->t;
+        out5[4] = (double)s->power_steps;
     }
 }
 /* scaled model of the current phase (bounds, objective, senses) */

@@ -8,6 +8,9 @@
 // LP in a fixed order, so an LP's trajectory does not depend on the others.
 #include <cmath>
 
+#include <algorithm>
+#include <vector>
+
 #include "pdhg_device.hpp"
 #include "pdhg_internal.hpp"
 #include "pdhg_kernels.hpp"
@@ -20,7 +23,7 @@ constexpr int kRedRows = kBlock; // rows per reduction tile (one per thread)
 template <typename V, int T, int NT>
 __global__ __launch_bounds__(NT) void kb_primal(const int4 *__restrict__ tiles, const int *__restrict__ tp,
                                                const int *__restrict__ ti, const V *__restrict__ atv,
-                                               const double *__restrict__ y, const V *__restrict__ ch,
+                                               const double *__restrict__ y, const double *__restrict__ ch,
                                                const V *__restrict__ lh, const V *__restrict__ uh,
                                                V *__restrict__ x, const V *__restrict__ xa, V *__restrict__ xbar,
                                                V *__restrict__ xp, const DevState *__restrict__ sts, int i,
@@ -87,7 +90,7 @@ static void launch_primal_b(pdhg_batch *b, int i, int store)
 #define PDHG_BP_CASE(TT, RR, NT)                                                                               \
     case TT:                                                                                                   \
         hipLaunchKernelGGL((kb_primal<V, RR, NT>), dim3(b->n_ptiles), dim3(NT), 0, s->stream, b->ptiles, s->tp, \
-                           s->ti, (const V *)s->ahat_t, (const double *)s->y, (const V *)s->ch,               \
+                           s->ti, (const V *)s->ahat_t, (const double *)s->y, s->ch,               \
                            (const V *)s->lh, (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar,     \
                            (V *)s->xp, b->sts, i, store);                                                     \
         break;
@@ -164,9 +167,11 @@ __global__ __launch_bounds__(kBlock) void kb_check_rows(const int4 *__restrict__
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void kb_check_cols(const int4 *__restrict__ rn, const double *__restrict__ aty,
-                                                       const V *__restrict__ ch, const V *__restrict__ lh,
+                                                       const double *__restrict__ ch, const V *__restrict__ lh,
                                                        const V *__restrict__ uh, const double *__restrict__ dc,
                                                        const V *__restrict__ xc, const V *__restrict__ xa,
+                                                       const double *__restrict__ c0, const double *__restrict__ l0,
+                                                       const double *__restrict__ u0, int orig,
                                                        double *__restrict__ part, int ntile,
                                                        const DevState *__restrict__ sts)
 {
@@ -175,8 +180,9 @@ __global__ __launch_bounds__(kBlock) void kb_check_cols(const int4 *__restrict__
     double v[7] = {0, 0, 0, 0, 0, 0, 0}; // DH2, D2, DINF, CTX, BND, DX2, NAN
     if ((int)threadIdx.x < tl.z) {
         const int j = tl.y + threadIdx.x;
-        const double lam = (double)ch[j] - aty[j];
-        const double lo = (double)lh[j], hi = (double)uh[j];
+        double cj, lo, hi;
+        check_model<V>(orig != 0, j, ch, lh, uh, c0, l0, u0, dc, cj, lo, hi);
+        const double lam = cj - aty[j];
         const double zp = (!is_inf_lo(lo) && lam > 0.0) ? lam : 0.0;
         const double zm = (!is_inf_up(hi) && lam < 0.0) ? -lam : 0.0;
         const double rd = lam - (zp - zm);
@@ -186,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void kb_check_cols(const int4 *__restrict__
         v[0] = rd * rd;
         v[1] = rdu * rdu;
         v[2] = fabs(rdu);
-        v[3] = (double)ch[j] * xj;
+        v[3] = cj * xj;
         if (zp > 0.0) v[4] += lo * zp;
         if (zm > 0.0) v[4] -= hi * zm;
         v[5] = dx * dx;
@@ -275,8 +281,9 @@ static void check_b(pdhg_batch *b, int mode, int len)
     double *pm = b->part, *pn = b->part + (size_t)(Q_COUNT + 1) * b->n_rm;
     hipLaunchKernelGGL(kb_check_rows, dim3(b->n_rm), dim3(kBlock), 0, st, b->rm, s->ax, (const double *)s->bh, s->sense,
                        s->dr, yc, (const double *)s->ya, pm, b->n_rm, b->sts);
-    hipLaunchKernelGGL((kb_check_cols<V>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, s->aty, (const V *)s->ch,
-                       (const V *)s->lh, (const V *)s->uh, s->dc, xc, (const V *)s->xa, pn, b->n_rn, b->sts);
+    hipLaunchKernelGGL((kb_check_cols<V>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, s->aty, s->ch,
+                       (const V *)s->lh, (const V *)s->uh, s->dc, xc, (const V *)s->xa, s->c, s->l, s->u,
+                       s->model_original ? 1 : 0, pn, b->n_rn, b->sts);
     hipLaunchKernelGGL(kb_check_final, dim3(b->count), dim3(kBlock), 0, st, b->sts, pm, b->n_rm, pn, b->n_rn,
                        b->rm_start, b->rn_start, mode, len);
     if (mode != 0)
@@ -348,14 +355,26 @@ __global__ __launch_bounds__(kBlock) void kb_sumsq(const int4 *__restrict__ tile
     if (threadIdx.x == 0) part[blockIdx.x] = q[0];
 }
 
-// per LP: out[lp] = sqrt(sum of its tiles' partials)
-__global__ __launch_bounds__(kBlock) void kb_norm_final(const int *__restrict__ start, const double *__restrict__ part,
-                                                       double *__restrict__ out)
+// per-LP power step (the single-LP rule): ps = {lambda[count], done[count],
+// steps[count]}; rho = u'u from the LP's row tiles, w'w from its column tiles
+__global__ __launch_bounds__(kBlock) void kb_power_finish(const int *__restrict__ rm_start,
+                                                         const double *__restrict__ pm,
+                                                         const int *__restrict__ rn_start,
+                                                         const double *__restrict__ pn, int count, double tol,
+                                                         double *__restrict__ ps)
 {
-    double q[1] = {0.0};
-    for (int t = start[blockIdx.x] + threadIdx.x; t < start[blockIdx.x + 1]; t += kBlock) q[0] += part[t];
-    block_reduce<1>(q, 0u);
-    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(q[0]);
+    const int lp = blockIdx.x;
+    if (ps[count + lp] != 0.0) return;
+    double q[2] = {0.0, 0.0};
+    for (int t = rm_start[lp] + threadIdx.x; t < rm_start[lp + 1]; t += kBlock) q[0] += pm[t];
+    for (int t = rn_start[lp] + threadIdx.x; t < rn_start[lp + 1]; t += kBlock) q[1] += pn[t];
+    block_reduce<2>(q, 0u);
+    if (threadIdx.x == 0) {
+        const double rho = q[0], ww = q[1], lam = sqrt(ww);
+        ps[lp] = lam;
+        ps[2 * count + lp] += 1.0;
+        if (!(lam > 0.0) || sqrt(fmax(ww - rho * rho, 0.0)) <= tol * rho) ps[count + lp] = 1.0;
+    }
 }
 
 // v = 1 / sqrt(n_lp) on every column of an LP
@@ -369,21 +388,21 @@ __global__ __launch_bounds__(kBlock) void kb_fill_start(const int4 *__restrict__
 }
 
 __global__ __launch_bounds__(kBlock) void kb_normalize(const int4 *__restrict__ rn, const double *__restrict__ w,
-                                                      const double *__restrict__ lam, double *__restrict__ v)
+                                                      const double *__restrict__ ps, int count, double *__restrict__ v)
 {
     const int4 tl = rn[blockIdx.x];
-    const double l = lam[tl.x];
-    if (!(l > 0.0) || (int)threadIdx.x >= tl.z) return;
+    const double l = ps[tl.x];
+    if (ps[count + tl.x] != 0.0 || !(l > 0.0) || (int)threadIdx.x >= tl.z) return;
     const int j = tl.y + threadIdx.x;
     v[j] = w[j] / l;
 }
 
-__global__ void kb_set_step(DevState *sts, int count, const double *lam, int iters_done, double safety)
+__global__ void kb_set_step(DevState *sts, int count, const double *ps, double safety)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const double l = lam[i];
-    const double sig = (iters_done > 0 && l > 0.0) ? sqrt(l) : 0.0;
+    const double l = ps[i];
+    const double sig = (ps[2 * count + i] > 0.0 && l > 0.0) ? sqrt(l) : 0.0;
     sts[i].sigma_est = sig;
     sts[i].eta = sig > 1e-12 ? safety / sig : safety;
 }
@@ -444,21 +463,36 @@ hipError_t batch_setup(pdhg_batch *b)
     // power iteration per LP on its block of Ahat'Ahat
     double *v = s->xu, *w = s->zsol, *u = s->ax; // float64 work vectors of the right lengths
     hipLaunchKernelGGL(kb_fill_start, dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, b->d_coff, v);
-    hipMemsetAsync(b->lp_scalar, 0, sizeof(double) * (size_t)b->count, st);
-    for (int it = 0; it < s->p.power_iters; it++) {
-        if (s->fp32) {
-            spmv<float, double, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, (const float *)s->ahat, v, u);
-            spmv<float, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, (const float *)s->ahat_t, u, w);
-        } else {
-            spmv<double, double, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, (const double *)s->ahat, v, u);
-            spmv<double, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, (const double *)s->ahat_t, u, w);
+    hipMemsetAsync(b->lp_scalar, 0, sizeof(double) * 4 * (size_t)b->count, st);
+    std::vector<double> done((size_t)b->count, 0.0);
+    constexpr int kPowerBatch = 32; // steps launched between reads of the done flags
+    for (int it = 0; it < s->p.power_iters && s->m > 0 && s->n > 0; it += kPowerBatch) {
+        const int len = std::min(kPowerBatch, s->p.power_iters - it);
+        for (int k = 0; k < len; k++) {
+            if (s->fp32) {
+                spmv<float, double, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, (const float *)s->ahat, v, u);
+                spmv<float, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, (const float *)s->ahat_t, u,
+                                                    w);
+            } else {
+                spmv<double, double, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, (const double *)s->ahat, v,
+                                                     u);
+                spmv<double, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, (const double *)s->ahat_t,
+                                                     u, w);
+            }
+            hipLaunchKernelGGL((kb_sumsq<double>), dim3(b->n_rm), dim3(kBlock), 0, st, b->rm, u, pm);
+            hipLaunchKernelGGL((kb_sumsq<double>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, w, pn);
+            hipLaunchKernelGGL(kb_power_finish, dim3(b->count), dim3(kBlock), 0, st, b->rm_start, pm, b->rn_start, pn,
+                               b->count, s->p.power_tol, b->lp_scalar);
+            hipLaunchKernelGGL(kb_normalize, dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, w, b->lp_scalar, b->count, v);
         }
-        hipLaunchKernelGGL((kb_sumsq<double>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, w, pn);
-        hipLaunchKernelGGL(kb_norm_final, dim3(b->count), dim3(kBlock), 0, st, b->rn_start, pn, b->lp_scalar);
-        hipLaunchKernelGGL(kb_normalize, dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, w, b->lp_scalar, v);
+        hipError_t e = hipMemcpyAsync(done.data(), b->lp_scalar + b->count, sizeof(double) * done.size(),
+                                      hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        if (std::all_of(done.begin(), done.end(), [](double d) { return d != 0.0; })) break;
     }
     hipLaunchKernelGGL(kb_set_step, dim3((b->count + 255) / 256), dim3(256), 0, st, b->sts, b->count, b->lp_scalar,
-                       s->p.power_iters, s->p.eta_safety);
+                       s->p.eta_safety);
     return hipGetLastError();
 }
 
@@ -470,7 +504,7 @@ static hipError_t phase_begin_b(pdhg_batch *b, bool fresh)
     hipError_t e = launch_start_vectors(s, fresh);
     if (e != hipSuccess) return e;
     double *pm = b->part, *pn = b->part + (size_t)(Q_COUNT + 1) * b->n_rm;
-    hipLaunchKernelGGL((kb_sumsq<V>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, (const V *)s->ch, pn);
+    hipLaunchKernelGGL((kb_sumsq<double>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, s->ch, pn);
     hipLaunchKernelGGL((kb_sumsq<double>), dim3(b->n_rm), dim3(kBlock), 0, st, b->rm, (const double *)s->bh, pm);
     hipLaunchKernelGGL(kb_phase_start, dim3(b->count), dim3(kBlock), 0, st, b->sts, pm, pn, b->rm_start, b->rn_start,
                        b->active);
@@ -630,7 +664,7 @@ __global__ __launch_bounds__(kBlock) void kb_push_cols(const int4 *__restrict__ 
                                                       const int *__restrict__ active, const double *__restrict__ z,
                                                       const V *__restrict__ xs, const double *__restrict__ dc,
                                                       double eps_abs, const uint64_t *__restrict__ seeds, double scale,
-                                                      V *__restrict__ lh, V *__restrict__ uh, V *__restrict__ ch,
+                                                      V *__restrict__ lh, V *__restrict__ uh, double *__restrict__ ch,
                                                       V *__restrict__ x, double *__restrict__ part, int ntile)
 {
     const int4 tl = rn[blockIdx.x];
@@ -646,9 +680,7 @@ __global__ __launch_bounds__(kBlock) void kb_push_cols(const int4 *__restrict__ 
             lh[j] = xv;
             v[0] = 1.0;
         }
-        const uint64_t h = splitmix64(seeds[tl.x] ^ ((uint64_t)jl * 0x9E3779B97F4A7C15ULL));
-        const double uni = (double)(h >> 11) * (1.0 / 9007199254740992.0);
-        ch[j] = (V)(dc[j] * (scale * uni));
+        ch[j] = dc[j] * (scale * push_unit(seeds[tl.x], jl));
         x[j] = xv;
     }
     block_reduce<2>(v, 0u);
@@ -701,7 +733,7 @@ static hipError_t push_setup_b(pdhg_batch *b, pdhg_push_result *out)
     double *pm = b->part, *pn = b->part + (size_t)(Q_COUNT + 1) * b->n_rm;
     hipLaunchKernelGGL((kb_push_cols<V>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, b->d_coff, b->active, s->zsol,
                        (const V *)s->xs, s->dc, s->p.eps_abs, b->seeds, s->p.push_obj_scale, (V *)s->lh, (V *)s->uh,
-                       (V *)s->ch, (V *)s->x, pn, b->n_rn);
+                       s->ch, (V *)s->x, pn, b->n_rn);
     hipLaunchKernelGGL(kb_push_rows, dim3(b->n_rm), dim3(kBlock), 0, st, b->rm, b->active, s->yu, s->p.eps_abs,
                        s->sense, (double *)s->y, pm);
     hipLaunchKernelGGL(kb_push_final, dim3(b->count), dim3(kBlock), 0, st, pn, b->n_rn, pm, b->rm_start, b->rn_start,
@@ -719,6 +751,7 @@ static hipError_t push_setup_b(pdhg_batch *b, pdhg_push_result *out)
 
 hipError_t batch_push_setup(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *out)
 {
+    b->s->model_original = false;
     hipError_t e = hipMemcpyAsync(b->seeds, seeds, sizeof(uint64_t) * (size_t)b->count, hipMemcpyHostToDevice,
                                   b->s->stream);
     if (e != hipSuccess) return e;

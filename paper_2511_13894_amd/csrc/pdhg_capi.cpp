@@ -196,7 +196,7 @@ bool run_batch_phase(pdhg_batch *b, int64_t iters, int mode, double t0)
             if (b->sts_host[i].done) continue;
             const int64_t mi = b->roff[i + 1] - b->roff[i], ni = b->coff[i + 1] - b->coff[i];
             const double nz = (double)b->nnz_of[i];
-            bp += 4.0 * (ni + 1) + (4.0 + vbytes) * nz + 8.0 * mi + 7.0 * vbytes * ni;
+            bp += 4.0 * (ni + 1) + (4.0 + vbytes) * nz + 8.0 * mi + 6.0 * vbytes * ni + 8.0 * ni;
             bd += 4.0 * (mi + 1) + (4.0 + vbytes) * nz + (double)vbytes * ni + 33.0 * mi;
         }
     };
@@ -281,10 +281,11 @@ void pdhg_default_params(pdhg_params *p)
     p->restart_art = 0.36;
     p->pw_smooth = 0.5;
     p->pc_alpha = 1.0;
-    p->power_iters = 32;
+    p->power_iters = 4000;
     p->halpern = 1;
     p->eta_safety = 0.99;
     p->reflect_gamma = 1.0;
+    p->power_tol = 1e-3;
     p->push_min_iters = 100;
     p->precision = PDHG_FP64;
     p->push_obj_scale = 1.0;
@@ -350,7 +351,8 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
     if (params) p = *params;
     else pdhg_default_params(&p);
     if (p.check_every < 1 || p.ruiz_iters < 0 || p.power_iters < 0 || p.push_min_iters < 1 ||
-        (p.precision != PDHG_FP64 && p.precision != PDHG_FP32_MIXED) || !(p.eps_rel > 0.0) || !(p.eta_safety > 0.0))
+        (p.precision != PDHG_FP64 && p.precision != PDHG_FP32_MIXED) || !(p.eps_rel > 0.0) || !(p.eta_safety > 0.0) ||
+        !(p.power_tol >= 0.0))
         return fail(PDHG_ERR_INVALID_ARG, "invalid parameter");
     for (int32_t k : {p.lanes_a, p.lanes_at}) {
         const bool lane_ok = k >= 1 && k <= 64 && !(k & (k - 1));
@@ -438,7 +440,8 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
         auto vall = [&](void **ptr, size_t cnt) { hip_check(hipMalloc(ptr, vb * (cnt > 0 ? cnt : 1)), "hipMalloc"); };
         vall(&s->ahat, NZ);
         vall(&s->ahat_t, NZ);
-        for (void **q : {&s->x, &s->xa, &s->xbar, &s->xp, &s->ch, &s->lh, &s->uh, &s->xs}) vall(q, N);
+        for (void **q : {&s->x, &s->xa, &s->xbar, &s->xp, &s->lh, &s->uh, &s->xs}) vall(q, N);
+        dalloc(&s->ch, N);
         for (void **q : {&s->y, &s->ya, &s->yp, &s->bh, &s->ys}) // m-vectors stay float64
             hip_check(hipMalloc(q, sizeof(double) * (M > 0 ? M : 1)), "hipMalloc");
         dalloc(&s->ax, M);
@@ -559,7 +562,7 @@ static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r
             if (!s->lfix) dalloc(&s->lfix, n);
             if (!s->lcount) dalloc(&s->lcount, 2);
             HIPCHK(hipMemsetAsync(s->lcount, 0, 2 * sizeof(unsigned), st));
-            HIPCHK(compute_features(s));
+            HIPCHK(compute_features(s, seed));
             HIPCHK(mlp_forward(net, st, s->feat_b, s->n, s->logits));
         }
         // CP2-CP5: bounds, senses, objective, start (x, 0), new weight and restart state
@@ -606,7 +609,7 @@ int pdhg_corner_push_learned(pdhg_solver *s, pdhg_mlp *net, double theta, uint64
     return corner_push_common(s, seed, r, net, theta);
 }
 
-int pdhg_features(pdhg_solver *s, float *out)
+int pdhg_features(pdhg_solver *s, uint64_t seed, float *out)
 {
     if (!s) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
     if (!s->solved || s->in_push) return fail(PDHG_ERR_STATE, "features describe a solved LP before its push");
@@ -614,7 +617,7 @@ int pdhg_features(pdhg_solver *s, float *out)
         const size_t n = (size_t)(s->n > 0 ? s->n : 1);
         if (!s->feat_raw) dalloc(&s->feat_raw, 16 * n);
         if (!s->feat_b) dalloc(&s->feat_b, 16 * n);
-        HIPCHK(compute_features(s));
+        HIPCHK(compute_features(s, seed));
         if (out) HIPCHK(hipMemcpyAsync(out, s->feat_raw, sizeof(float) * 16 * (size_t)s->n, hipMemcpyDeviceToHost,
                                        s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
@@ -697,7 +700,7 @@ int pdhg_get_iterate(pdhg_solver *s, double *x, double *y)
     return PDHG_OK;
 }
 
-int pdhg_get_scaling(pdhg_solver *s, double *dr, double *dc, double *scalars4)
+int pdhg_get_scaling(pdhg_solver *s, double *dr, double *dc, double *scalars5)
 {
     if (!s) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
     try {
@@ -706,11 +709,12 @@ int pdhg_get_scaling(pdhg_solver *s, double *dr, double *dc, double *scalars4)
         if (dc) HIPCHK(hipMemcpyAsync(dc, s->dc, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (scalars4) {
-            scalars4[0] = s->st_host->eta;
-            scalars4[1] = s->st_host->omega;
-            scalars4[2] = s->st_host->sigma_est;
-            scalars4[3] = (double)s->t_host;
+        if (scalars5) {
+            scalars5[0] = s->st_host->eta;
+            scalars5[1] = s->st_host->omega;
+            scalars5[2] = s->st_host->sigma_est;
+            scalars5[3] = (double)s->t_host;
+            scalars5[4] = (double)s->power_steps;
         }
     } catch (const HipFailure &f) {
         return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
@@ -733,7 +737,7 @@ int pdhg_get_timing(pdhg_solver *s, pdhg_timing *t)
     const int64_t v = s->fp32 ? 4 : 8, m = s->m, n = s->n, nz = s->nnz;
     // primal: row pointers, indices + values, y gathered once, reads x, chat,
     // x_anchor, lhat, uhat, writes x, xbar
-    t->bytes_primal = 4 * (n + 1) + (4 + v) * nz + 8 * m + 7 * v * n;
+    t->bytes_primal = 4 * (n + 1) + (4 + v) * nz + 8 * m + 6 * v * n + 8 * n;
     // dual: row pointers, indices + values, xbar gathered once, reads y, bhat,
     // y_anchor, sense byte, writes y
     t->bytes_dual = 4 * (m + 1) + (4 + v) * nz + v * n + 4 * 8 * m + m;
@@ -861,7 +865,7 @@ int pdhg_batch_create(int32_t count, const pdhg_lp_desc *lps, const pdhg_params 
         HIPCHK(hipMemcpy(b->d_coff, coff.data(), sizeof(int) * coff.size(), hipMemcpyHostToDevice));
         dalloc(&b->sts, (size_t)count);
         dalloc(&b->part, (size_t)(Q_COUNT + 1) * (b->n_rm + b->n_rn));
-        dalloc(&b->lp_scalar, (size_t)count);
+        dalloc(&b->lp_scalar, 4 * (size_t)count);
         dalloc(&b->rep, (size_t)count * R_COUNT);
         dalloc(&b->active, (size_t)count);
         dalloc(&b->seeds, (size_t)count);

@@ -91,7 +91,8 @@ struct pdhg_solver {
     void *ahat = nullptr, *ahat_t = nullptr;
     void *x = nullptr, *y = nullptr, *xa = nullptr, *ya = nullptr, *xbar = nullptr;
     void *xp = nullptr, *yp = nullptr;
-    void *ch = nullptr, *bh = nullptr, *lh = nullptr, *uh = nullptr;
+    double *ch = nullptr;            // scaled objective, float64 in both precisions
+    void *bh = nullptr, *lh = nullptr, *uh = nullptr;
     void *xs = nullptr, *ys = nullptr; // scaled solution of the solve (kept for the push)
     int8_t *sense = nullptr;
 
@@ -109,8 +110,10 @@ struct pdhg_solver {
     int lanes_at = 1, lanes_a = 1; // lane-group width of setup / check products
     int kern_at = 1, kern_a = 1;   // iteration kernels: > 0 lane-group width, < 0 LDS tile of -k rows
     int64_t t_host = 0;      // iterations of the current phase (mirror of st->t)
+    int64_t power_steps = 0; // power-iteration steps taken at create
     int64_t next_check = 0;  // phase iteration count of the next check
     bool in_push = false;
+    bool model_original = true; // the solve's model is in ch/lh/uh (false once a push rewrote it)
     bool has_candidate = false;   // a check has produced (xp, yp) in this phase
     bool solved = false;          // the solve has a candidate (push allowed)
     bool has_push_candidate = false;
@@ -153,7 +156,7 @@ struct pdhg_batch {
     int *rn_start = nullptr, *rm_start = nullptr; // first reduction tile of each LP (count + 1)
     pdhg::DevState *sts = nullptr, *sts_host = nullptr;
     double *part = nullptr;                // per-tile partial sums
-    double *lp_scalar = nullptr;           // per-LP scalars (power iteration)
+    double *lp_scalar = nullptr;           // per-LP power iteration {lambda, done, steps} x count
     double *rep = nullptr, *rep_host = nullptr; // per-LP report values
     int *active = nullptr;                 // per-LP flag: takes part in the current phase
     std::vector<int> active_host;
@@ -205,7 +208,7 @@ hipError_t batch_keep_unpushed(pdhg_batch *b);
 // learned push (pdhg_learned.hip)
 hipError_t launch_record_history(pdhg_solver *s);
 hipError_t launch_learned_undo(pdhg_solver *s);
-hipError_t compute_features(pdhg_solver *s);
+hipError_t compute_features(pdhg_solver *s, uint64_t seed);
 hipError_t launch_learned_fix(pdhg_solver *s, double theta);
 int choose_kernel(double mean_row);
 hipError_t autotune(pdhg_solver *s);

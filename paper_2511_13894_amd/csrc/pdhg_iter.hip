@@ -14,7 +14,7 @@ namespace pdhg {
 template <typename V, int L>
 __global__ __launch_bounds__(kBlock) void k_primal(int n, const int *__restrict__ tp, const int *__restrict__ ti,
                                                   const V *__restrict__ atv, const double *__restrict__ y,
-                                                  const V *__restrict__ ch, const V *__restrict__ lh,
+                                                  const double *__restrict__ ch, const V *__restrict__ lh,
                                                   const V *__restrict__ uh, V *__restrict__ x,
                                                   const V *__restrict__ xa, V *__restrict__ xbar, V *__restrict__ xp,
                                                   const DevState *__restrict__ st, int i, int store_cand)
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
 template <typename V, int T, int NT>
 __global__ __launch_bounds__(NT) void k_primal_tiled(int n, const int *__restrict__ tp, const int *__restrict__ ti,
                                                     const V *__restrict__ atv, const double *__restrict__ y,
-                                                    const V *__restrict__ ch, const V *__restrict__ lh,
+                                                    const double *__restrict__ ch, const V *__restrict__ lh,
                                                     const V *__restrict__ uh, V *__restrict__ x,
                                                     const V *__restrict__ xa, V *__restrict__ xbar,
                                                     V *__restrict__ xp, const DevState *__restrict__ st, int i,
@@ -128,7 +128,7 @@ static void launch_primal(pdhg_solver *s, int i, int store)
 #define PDHG_PT_CASE(TT, RR, NT)                                                                                \
     case TT:                                                                                                    \
         hipLaunchKernelGGL((k_primal_tiled<V, RR, NT>), dim3(grid), dim3(NT), 0, s->stream, s->n, s->tp, s->ti, \
-                           (const V *)s->ahat_t, (const double *)s->y, (const V *)s->ch, (const V *)s->lh,          \
+                           (const V *)s->ahat_t, (const double *)s->y, s->ch, (const V *)s->lh,          \
                            (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i,  \
                            store);                                                                              \
         break;
@@ -148,7 +148,7 @@ static void launch_primal(pdhg_solver *s, int i, int store)
 #define PDHG_PRIMAL_CASE(LL)                                                                                    \
     case LL:                                                                                                    \
         hipLaunchKernelGGL((k_primal<V, LL>), dim3(grid), dim3(kBlock), 0, s->stream, s->n, s->tp, s->ti,      \
-                           (const V *)s->ahat_t, (const double *)s->y, (const V *)s->ch, (const V *)s->lh,          \
+                           (const V *)s->ahat_t, (const double *)s->y, s->ch, (const V *)s->lh,          \
                            (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i,  \
                            store);                                                                              \
         break;
@@ -252,17 +252,20 @@ __global__ __launch_bounds__(kBlock) void k_check_rows(int m, const double *__re
 // rD_hat = lambda_hat - zhat, unscaled rD = rD_hat / Dc, chat'xc, bound terms
 // of the dual objective, ||xc - xa||^2.
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_check_cols(int n, const double *__restrict__ aty, const V *__restrict__ ch,
+__global__ __launch_bounds__(kBlock) void k_check_cols(int n, const double *__restrict__ aty, const double *__restrict__ ch,
                                                       const V *__restrict__ lh, const V *__restrict__ uh,
                                                       const double *__restrict__ dc, const V *__restrict__ xc,
-                                                      const V *__restrict__ xa, double *__restrict__ part, int nblk,
+                                                      const V *__restrict__ xa, const double *__restrict__ c0,
+                                                      const double *__restrict__ l0, const double *__restrict__ u0,
+                                                      int orig, double *__restrict__ part, int nblk,
                                                       const DevState *st)
 {
     if (st->done) return;
     double v[7] = {0, 0, 0, 0, 0, 0, 0}; // DH2, D2, DINF, CTX, BND, DX2, NAN
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
-        const double lam = (double)ch[j] - aty[j];
-        const double lo = (double)lh[j], hi = (double)uh[j];
+        double cj, lo, hi;
+        check_model<V>(orig != 0, j, ch, lh, uh, c0, l0, u0, dc, cj, lo, hi);
+        const double lam = cj - aty[j];
         const double zp = (!is_inf_lo(lo) && lam > 0.0) ? lam : 0.0;
         const double zm = (!is_inf_up(hi) && lam < 0.0) ? -lam : 0.0;
         const double rd = lam - (zp - zm);
@@ -272,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_check_cols(int n, const double *__re
         v[0] += rd * rd;
         v[1] += rdu * rdu;
         v[2] = fmax(v[2], fabs(rdu));
-        v[3] += (double)ch[j] * xj;
+        v[3] += cj * xj;
         if (zp > 0.0) v[4] += lo * zp;
         if (zm > 0.0) v[4] -= hi * zm;
         v[5] += dx * dx;
@@ -350,8 +353,9 @@ static void check_impl(pdhg_solver *s, const V *xc, const double *yc, double *pm
     const int gm = s->red_blocks_m, gn = s->red_blocks_n;
     hipLaunchKernelGGL(k_check_rows, dim3(gm), dim3(kBlock), 0, st, s->m, s->ax, (const double *)s->bh, s->sense, s->dr,
                        yc, (const double *)s->ya, pm, gm, s->st);
-    hipLaunchKernelGGL((k_check_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->aty, (const V *)s->ch,
-                       (const V *)s->lh, (const V *)s->uh, s->dc, xc, (const V *)s->xa, pn, gn, s->st);
+    hipLaunchKernelGGL((k_check_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->aty, s->ch,
+                       (const V *)s->lh, (const V *)s->uh, s->dc, xc, (const V *)s->xa, s->c, s->l, s->u,
+                       s->model_original ? 1 : 0, pn, gn, s->st);
 }
 
 hipError_t launch_check(pdhg_solver *s, int mode, int len)
@@ -539,7 +543,7 @@ static hipError_t phase_start(pdhg_solver *s, bool fresh_start)
     hipStream_t st = s->stream;
     start_vectors<V>(s, fresh_start);
     const int nb = grid_for(s->n > s->m ? s->n : s->m, kBlock, kMaxRedBlocks);
-    hipLaunchKernelGGL((k_sumsq2<V>), dim3(nb), dim3(kBlock), 0, st, s->n, (const V *)s->ch, s->m, (const double *)s->bh,
+    hipLaunchKernelGGL((k_sumsq2<double>), dim3(nb), dim3(kBlock), 0, st, s->n, s->ch, s->m, (const double *)s->bh,
                        s->partials, nb);
     hipLaunchKernelGGL(k_phase_start, dim3(1), dim3(kBlock), 0, st, s->st, s->partials, nb);
     hipError_t e = hipGetLastError();
@@ -758,7 +762,7 @@ template <typename V>
 __global__ __launch_bounds__(kBlock) void k_push_cols(int n, const double *__restrict__ z, const V *__restrict__ xs,
                                                      const double *__restrict__ dc, double eps_abs, uint64_t seed,
                                                      double scale, V *__restrict__ lh, V *__restrict__ uh,
-                                                     V *__restrict__ ch, V *__restrict__ x, double *__restrict__ part,
+                                                     double *__restrict__ ch, V *__restrict__ x, double *__restrict__ part,
                                                      int nblk)
 {
     double v[2] = {0.0, 0.0}; // fixes at the lower, upper side
@@ -771,9 +775,7 @@ __global__ __launch_bounds__(kBlock) void k_push_cols(int n, const double *__res
             lh[j] = xv;
             v[0] += 1.0;
         }
-        const uint64_t h = splitmix64(seed ^ ((uint64_t)j * 0x9E3779B97F4A7C15ULL));
-        const double uni = (double)(h >> 11) * (1.0 / 9007199254740992.0);
-        ch[j] = (V)(dc[j] * (scale * uni));
+        ch[j] = dc[j] * (scale * push_unit(seed, j));
         x[j] = xv;
     }
     block_reduce<2>(v, 0u);
@@ -824,7 +826,7 @@ static hipError_t push_setup_impl(pdhg_solver *s, uint64_t seed, pdhg_push_resul
     const int gn = s->red_blocks_n, gm = s->red_blocks_m;
     double *pcnt = s->partials + (size_t)(Q_COUNT + 1) * (gm + gn); // past the check slots
     hipLaunchKernelGGL((k_push_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->zsol, (const V *)s->xs, s->dc,
-                       s->p.eps_abs, seed, s->p.push_obj_scale, (V *)s->lh, (V *)s->uh, (V *)s->ch, (V *)s->x, pcnt,
+                       s->p.eps_abs, seed, s->p.push_obj_scale, (V *)s->lh, (V *)s->uh, s->ch, (V *)s->x, pcnt,
                        gn);
     hipLaunchKernelGGL(k_push_rows, dim3(gm), dim3(kBlock), 0, st, s->m, s->yu, s->p.eps_abs, s->sense, (double *)s->y,
                        pcnt + 2 * gn);
@@ -844,6 +846,7 @@ static hipError_t push_setup_impl(pdhg_solver *s, uint64_t seed, pdhg_push_resul
 
 hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, double theta)
 {
+    s->model_original = false;
     return s->fp32 ? push_setup_impl<float>(s, seed, r, theta) : push_setup_impl<double>(s, seed, r, theta);
 }
 

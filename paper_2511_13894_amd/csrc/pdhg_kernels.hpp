@@ -191,6 +191,27 @@ __device__ inline void check_decide(DevState *st, const double *v, int mode, int
     st->restart_flag = 1;
 }
 
+// Objective coefficient and bounds of column j as a check evaluates them.
+// During the solve the scaled original model is rebuilt in float64 from c,
+// l, u and Dc (the values the setup stored before rounding them to the
+// working precision), so that a float32 copy of chat, lhat, uhat cannot move
+// the tested objectives; after a push rewrote the model, its stored values.
+template <typename V>
+__device__ __forceinline__ void check_model(bool orig, int64_t j, const double *ch, const V *lh, const V *uh,
+                                            const double *c0, const double *l0, const double *u0, const double *dc,
+                                            double &cj, double &lo, double &hi)
+{
+    if (orig) {
+        cj = dc[j] * c0[j];
+        lo = l0[j] / dc[j];
+        hi = u0[j] / dc[j];
+    } else {
+        cj = ch[j];
+        lo = (double)lh[j];
+        hi = (double)uh[j];
+    }
+}
+
 // splitmix64 (Steele, Lea and Flood 2014)
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x)
 {
@@ -198,6 +219,14 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x)
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
     return z ^ (z >> 31);
+}
+
+// the push objective's Uniform[0,1) draw of column j: top 53 bits of
+// splitmix64(seed xor j * golden-ratio constant), times 2^-53
+__device__ __forceinline__ double push_unit(uint64_t seed, int64_t j)
+{
+    const uint64_t h = splitmix64(seed ^ ((uint64_t)j * 0x9E3779B97F4A7C15ULL));
+    return (double)(h >> 11) * (1.0 / 9007199254740992.0);
 }
 
 } // namespace pdhg

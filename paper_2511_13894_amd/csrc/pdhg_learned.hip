@@ -1,12 +1,18 @@
-// Learned warm start of the corner push: restart history, the 12
+// Learned warm start of the corner push: restart history, the 16
 // per-variable features, learned fixes and their undo rule.
 //
-// Features of column j on the scaled model (12, padded to 16):
-//   x_j, z_j, |c_j|, ||A_{:,j}||_2, then x_j at each of the last 4 restarts of
-//   the solve minus its current value, and the same for z_j (0 where fewer
-//   than 4 restarts happened); each feature f is mapped to
-//   sign(v) ln(1 + |v| / s_f), s_f the root mean square of f over the LP
-//   (1 if that is 0).
+// Features of column j on the scaled model:
+//   0..3   x_j, z_j, |c_j|, ||A_{:,j}||_2;
+//   4..7   x_j at each of the last 4 restarts of the solve minus its current
+//          value (0 where fewer than 4 restarts happened);
+//   8..11  the same for z_j;
+//   12     the push objective coefficient of column j (the scaled
+//          Uniform[0,1) draw of the push seed);
+//   13, 14 x_j - l_j and u_j - x_j (-1 where that bound is infinite);
+//   15     (x_j - l_j) / (u_j - l_j) where both bounds are finite and
+//          distinct, else -1.
+// Each feature f is mapped to sign(v) ln(1 + |v| / s_f), s_f the root mean
+// square of f over the LP (1 if that is 0).
 // A learned fix puts a column that the plain rule leaves free (|z_j| <=
 // eps_abs) at its nearer finite bound when the predicted probability is at
 // least theta, provided the sign of z_j allows it (z_j >= -eps_abs for the
@@ -18,11 +24,14 @@
 
 #include "pdhg_device.hpp"
 #include "pdhg_internal.hpp"
+#include "pdhg_kernels.hpp"
 #include "pdhg_mlp.hpp"
 
 namespace pdhg {
 
-constexpr int kNF = 12;
+constexpr int kNF = 16;
+// the per-block feature sums reuse the check's partial-sum buffer
+static_assert((Q_COUNT + 1) * 3 >= kNF, "partial-sum buffer too small for the feature sums");
 
 __device__ __forceinline__ double zsplit(double lam, double lo, double hi)
 {
@@ -34,7 +43,7 @@ __device__ __forceinline__ double zsplit(double lam, double lo, double hi)
 // at a restart of the solve: slot (restarts - 1) mod 4 <- candidate x, z
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_record_history(int n, const DevState *__restrict__ st,
-                                                          const V *__restrict__ xp, const V *__restrict__ ch,
+                                                          const V *__restrict__ xp, const double *__restrict__ ch,
                                                           const V *__restrict__ lh, const V *__restrict__ uh,
                                                           const double *__restrict__ aty, float *__restrict__ hx,
                                                           float *__restrict__ hz)
@@ -52,11 +61,11 @@ hipError_t launch_record_history(pdhg_solver *s)
     const int g = grid_for(s->n, kBlock, 8192);
     if (s->fp32)
         hipLaunchKernelGGL((k_record_history<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->st,
-                           (const float *)s->xp, (const float *)s->ch, (const float *)s->lh, (const float *)s->uh,
+                           (const float *)s->xp, s->ch, (const float *)s->lh, (const float *)s->uh,
                            s->aty, s->hx, s->hz);
     else
         hipLaunchKernelGGL((k_record_history<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->st,
-                           (const double *)s->xp, (const double *)s->ch, (const double *)s->lh, (const double *)s->uh,
+                           (const double *)s->xp, s->ch, (const double *)s->lh, (const double *)s->uh,
                            s->aty, s->hx, s->hz);
     return hipGetLastError();
 }
@@ -64,11 +73,13 @@ hipError_t launch_record_history(pdhg_solver *s)
 // raw features into f (n x 16, float) and per-block sums of their squares
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_feat_raw(int n, const DevState *__restrict__ st, const V *__restrict__ xp,
-                                                    const V *__restrict__ ch, const V *__restrict__ lh,
+                                                    const double *__restrict__ ch, const V *__restrict__ lh,
                                                     const V *__restrict__ uh, const double *__restrict__ aty,
                                                     const int *__restrict__ tp, const V *__restrict__ atv,
                                                     const float *__restrict__ hx, const float *__restrict__ hz,
-                                                    float *__restrict__ f, double *__restrict__ part, int nblk)
+                                                    const double *__restrict__ dc, uint64_t seed, double obj_scale,
+                                                    float *__restrict__ f,
+                                                    double *__restrict__ part, int nblk)
 {
     const int64_t rest = st->restarts;
     const int have = rest < 4 ? (int)rest : 4;
@@ -91,14 +102,18 @@ __global__ __launch_bounds__(kBlock) void k_feat_raw(int n, const DevState *__re
             v[3 + k] = (k <= have && hx) ? (double)hx[slot * n + j] - xj : 0.0;
             v[7 + k] = (k <= have && hz) ? (double)hz[slot * n + j] - zj : 0.0;
         }
+        const double lo = (double)lh[j], hi = (double)uh[j];
+        const bool flo = !is_inf_lo(lo), fhi = !is_inf_up(hi);
+        v[12] = dc[j] * (obj_scale * push_unit(seed, j));
+        v[13] = flo ? xj - lo : -1.0;
+        v[14] = fhi ? hi - xj : -1.0;
+        v[15] = (flo && fhi && hi > lo) ? (xj - lo) / (hi - lo) : -1.0;
 #pragma unroll
         for (int q = 0; q < kNF; q++) {
             if (!isfinite(v[q])) v[q] = 0.0;
             f[j * 16 + q] = (float)v[q];
             sq[q] += v[q] * v[q];
         }
-#pragma unroll
-        for (int q = kNF; q < 16; q++) f[j * 16 + q] = 0.0f;
     }
     block_reduce<kNF>(sq, 0u);
     if (threadIdx.x == 0)
@@ -148,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_feat_norm(int64_t n, const double *_
     }
 }
 
-hipError_t compute_features(pdhg_solver *s)
+hipError_t compute_features(pdhg_solver *s, uint64_t seed)
 {
     hipStream_t st = s->stream;
     // z of the candidate needs Ahat' y+ (float64 accumulation)
@@ -162,12 +177,14 @@ hipError_t compute_features(pdhg_solver *s)
     double *scale = s->redout + 16;
     if (s->fp32)
         hipLaunchKernelGGL((k_feat_raw<float>), dim3(nb), dim3(kBlock), 0, st, s->n, s->st, (const float *)s->xp,
-                           (const float *)s->ch, (const float *)s->lh, (const float *)s->uh, s->aty, s->tp,
-                           (const float *)s->ahat_t, s->hx, s->hz, s->feat_raw, s->partials, nb);
+                           s->ch, (const float *)s->lh, (const float *)s->uh, s->aty, s->tp,
+                           (const float *)s->ahat_t, s->hx, s->hz, s->dc, seed, s->p.push_obj_scale, s->feat_raw,
+                           s->partials, nb);
     else
         hipLaunchKernelGGL((k_feat_raw<double>), dim3(nb), dim3(kBlock), 0, st, s->n, s->st, (const double *)s->xp,
-                           (const double *)s->ch, (const double *)s->lh, (const double *)s->uh, s->aty, s->tp,
-                           (const double *)s->ahat_t, s->hx, s->hz, s->feat_raw, s->partials, nb);
+                           s->ch, (const double *)s->lh, (const double *)s->uh, s->aty, s->tp,
+                           (const double *)s->ahat_t, s->hx, s->hz, s->dc, seed, s->p.push_obj_scale, s->feat_raw,
+                           s->partials, nb);
     hipLaunchKernelGGL(k_feat_scale, dim3(1), dim3(kBlock), 0, st, s->n, s->partials, nb, scale);
     hipLaunchKernelGGL(k_feat_norm, dim3(grid_for((int64_t)s->n * 16, kBlock, 65536)), dim3(kBlock), 0, st,
                        (int64_t)s->n, scale, s->feat_raw, s->feat_b);
@@ -221,7 +238,7 @@ hipError_t launch_learned_fix(pdhg_solver *s, double theta)
 // undo rule at a push check (aty = Ahat' y+ of the check's candidate)
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_learned_undo(int n, const DevState *__restrict__ st,
-                                                        int8_t *__restrict__ lfix, const V *__restrict__ ch,
+                                                        int8_t *__restrict__ lfix, const double *__restrict__ ch,
                                                         const double *__restrict__ aty, const double *__restrict__ dc,
                                                         const double *__restrict__ l, const double *__restrict__ u,
                                                         double eps_abs, V *__restrict__ lh, V *__restrict__ uh,
@@ -248,11 +265,11 @@ hipError_t launch_learned_undo(pdhg_solver *s)
     const int g = grid_for(s->n, kBlock, 8192);
     if (s->fp32)
         hipLaunchKernelGGL((k_learned_undo<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->st, s->lfix,
-                           (const float *)s->ch, s->aty, s->dc, s->l, s->u, s->p.eps_abs, (float *)s->lh, (float *)s->uh,
+                           s->ch, s->aty, s->dc, s->l, s->u, s->p.eps_abs, (float *)s->lh, (float *)s->uh,
                            s->lcount);
     else
         hipLaunchKernelGGL((k_learned_undo<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->st, s->lfix,
-                           (const double *)s->ch, s->aty, s->dc, s->l, s->u, s->p.eps_abs, (double *)s->lh,
+                           s->ch, s->aty, s->dc, s->l, s->u, s->p.eps_abs, (double *)s->lh,
                            (double *)s->uh, s->lcount);
     return hipGetLastError();
 }

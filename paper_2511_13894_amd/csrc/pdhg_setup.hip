@@ -1,5 +1,7 @@
 // Setup on the device: explicit transpose of A, Ruiz + Pock-Chambolle
 // scaling, and the power iteration that sets the step size.
+#include <algorithm>
+
 #include "pdhg_device.hpp"
 #include "pdhg_internal.hpp"
 
@@ -260,11 +262,11 @@ __global__ __launch_bounds__(kBlock) void k_fill(int64_t len, double *__restrict
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_scaled_cols(int n, const double *__restrict__ dc, const double *__restrict__ c,
                                                        const double *__restrict__ l, const double *__restrict__ u,
-                                                       V *__restrict__ ch, V *__restrict__ lh, V *__restrict__ uh)
+                                                       double *__restrict__ ch, V *__restrict__ lh, V *__restrict__ uh)
 {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
-    ch[j] = (V)(dc[j] * c[j]);
+    ch[j] = dc[j] * c[j];
     lh[j] = (V)(l[j] / dc[j]);
     uh[j] = (V)(u[j] / dc[j]);
 }
@@ -291,7 +293,7 @@ static void make_scaled(pdhg_solver *s, const double *ahat64)
     }
     if (s->n > 0)
         hipLaunchKernelGGL((k_scaled_cols<V>), dim3(grid_for(s->n, kBlock, 1 << 30)), dim3(kBlock), 0, st, s->n, s->dc,
-                           s->c, s->l, s->u, (V *)s->ch, (V *)s->lh, (V *)s->uh);
+                           s->c, s->l, s->u, s->ch, (V *)s->lh, (V *)s->uh);
     if (s->m > 0)
         hipLaunchKernelGGL((k_scaled_rows<double>), dim3(grid_for(s->m, kBlock, 1 << 30)), dim3(kBlock), 0, st, s->m,
                            s->dr, s->b, s->sense0, (double *)s->bh, s->sense);
@@ -345,7 +347,15 @@ hipError_t scale_problem(pdhg_solver *s)
 }
 
 // --------------------------------------------------------- power iteration
-// partial sums of w_j^2 per block
+// Power iteration on M = Ahat'Ahat from v = 1/sqrt(n).  A step forms
+// u = Ahat v and w = Ahat'u; with v of unit length, rho = u'u is its Rayleigh
+// quotient and ||w - rho v||^2 = w'w - rho^2.  The iteration stops at the
+// first step with sqrt(w'w - rho^2) <= tol * rho (or when w = 0), keeping
+// lambda = ||w||, which lies in [rho, lambda_max(M)].  pw = {lambda, done,
+// steps}: the decision stays on the device and later steps of a launched
+// batch leave v and pw alone.
+
+// partial sums of squares per block
 __global__ __launch_bounds__(kBlock) void k_sumsq_partials(int len, const double *__restrict__ w, double *__restrict__ part)
 {
     double v[1] = {0.0};
@@ -355,28 +365,36 @@ __global__ __launch_bounds__(kBlock) void k_sumsq_partials(int len, const double
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
-// lambda = sqrt(sum of partials), fixed order; out[0] = lambda
-__global__ __launch_bounds__(kBlock) void k_finish_norm(int nparts, const double *__restrict__ part, double *__restrict__ out)
+// rho = sum of part[0, gm), w'w = sum of part[gm, gm + gn), fixed order
+__global__ __launch_bounds__(kBlock) void k_power_finish(int gm, int gn, const double *__restrict__ part, double tol,
+                                                        double *__restrict__ pw)
 {
-    double v[1] = {0.0};
-    for (int i = threadIdx.x; i < nparts; i += kBlock) v[0] += part[i];
-    block_reduce<1>(v, 0u);
-    if (threadIdx.x == 0) out[0] = sqrt(v[0]);
+    if (pw[1] != 0.0) return;
+    double v[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < gm; i += kBlock) v[0] += part[i];
+    for (int i = threadIdx.x; i < gn; i += kBlock) v[1] += part[gm + i];
+    block_reduce<2>(v, 0u);
+    if (threadIdx.x == 0) {
+        const double rho = v[0], ww = v[1], lam = sqrt(ww);
+        pw[0] = lam;
+        pw[2] += 1.0;
+        if (!(lam > 0.0) || sqrt(fmax(ww - rho * rho, 0.0)) <= tol * rho) pw[1] = 1.0;
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void k_normalize(int len, const double *__restrict__ w, const double *__restrict__ lam,
+__global__ __launch_bounds__(kBlock) void k_normalize(int len, const double *__restrict__ w, const double *__restrict__ pw,
                                                      double *__restrict__ v)
 {
-    const double l = lam[0];
-    if (!(l > 0.0)) return;
+    const double l = pw[0];
+    if (pw[1] != 0.0 || !(l > 0.0)) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < len) v[i] = w[i] / l;
 }
 
-__global__ void k_set_step(pdhg::DevState *st, const double *lam, int iters_done, double safety)
+__global__ void k_set_step(pdhg::DevState *st, const double *pw, double safety)
 {
-    double l = lam[0];
-    double sig = (iters_done > 0 && l > 0.0) ? sqrt(l) : 0.0;
+    const double l = pw[0];
+    const double sig = (pw[2] > 0.0 && l > 0.0) ? sqrt(l) : 0.0;
     st->sigma_est = sig;
     st->eta = sig > 1e-12 ? safety / sig : safety;
 }
@@ -385,35 +403,49 @@ hipError_t power_iteration(pdhg_solver *s)
 {
     hipStream_t st = s->stream;
     const int m = s->m, n = s->n;
-    double *v = nullptr, *w = nullptr, *u = nullptr, *lam = nullptr;
+    double *v = nullptr, *w = nullptr, *u = nullptr, *pw = nullptr;
     hipError_t e;
     if ((e = hipMalloc(&v, (size_t)(n > 0 ? n : 1) * sizeof(double))) != hipSuccess) return e;
     if ((e = hipMalloc(&w, (size_t)(n > 0 ? n : 1) * sizeof(double))) != hipSuccess) return e;
     if ((e = hipMalloc(&u, (size_t)(m > 0 ? m : 1) * sizeof(double))) != hipSuccess) return e;
-    if ((e = hipMalloc(&lam, 2 * sizeof(double))) != hipSuccess) return e;
-    hipMemsetAsync(lam, 0, 2 * sizeof(double), st);
+    if ((e = hipMalloc(&pw, 4 * sizeof(double))) != hipSuccess) return e;
+    hipMemsetAsync(pw, 0, 4 * sizeof(double), st);
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, st, (int64_t)n, v,
                        n > 0 ? 1.0 / sqrt((double)n) : 0.0);
-    const int gn = grid_for(n, kBlock, kMaxRedBlocks);
-    for (int it = 0; it < s->p.power_iters && n > 0; it++) {
-        if (s->fp32) {
-            spmv<float, double, double, double>(st, s->lanes_a, m, s->rp, s->ci, (const float *)s->ahat, v, u);
-            spmv<float, double, double, double>(st, s->lanes_at, n, s->tp, s->ti, (const float *)s->ahat_t, u, w);
-        } else {
-            spmv<double, double, double, double>(st, s->lanes_a, m, s->rp, s->ci, (const double *)s->ahat, v, u);
-            spmv<double, double, double, double>(st, s->lanes_at, n, s->tp, s->ti, (const double *)s->ahat_t, u, w);
+    const int gm = grid_for(m, kBlock, kMaxRedBlocks), gn = grid_for(n, kBlock, kMaxRedBlocks);
+    double pw_host[4] = {0.0, 0.0, 0.0, 0.0};
+    constexpr int kPowerBatch = 32; // steps launched between reads of the done flag
+    for (int it = 0; it < s->p.power_iters && n > 0 && m > 0; it += kPowerBatch) {
+        const int len = std::min(kPowerBatch, s->p.power_iters - it);
+        for (int k = 0; k < len; k++) {
+            if (s->fp32) {
+                spmv<float, double, double, double>(st, s->lanes_a, m, s->rp, s->ci, (const float *)s->ahat, v, u);
+                spmv<float, double, double, double>(st, s->lanes_at, n, s->tp, s->ti, (const float *)s->ahat_t, u,
+                                                    w);
+            } else {
+                spmv<double, double, double, double>(st, s->lanes_a, m, s->rp, s->ci, (const double *)s->ahat, v, u);
+                spmv<double, double, double, double>(st, s->lanes_at, n, s->tp, s->ti, (const double *)s->ahat_t, u,
+                                                     w);
+            }
+            hipLaunchKernelGGL(k_sumsq_partials, dim3(gm), dim3(kBlock), 0, st, m, u, s->partials);
+            hipLaunchKernelGGL(k_sumsq_partials, dim3(gn), dim3(kBlock), 0, st, n, w, s->partials + gm);
+            hipLaunchKernelGGL(k_power_finish, dim3(1), dim3(kBlock), 0, st, gm, gn, s->partials, s->p.power_tol, pw);
+            hipLaunchKernelGGL(k_normalize, dim3(grid_for(n, kBlock, 1 << 30)), dim3(kBlock), 0, st, n, w, pw, v);
         }
-        hipLaunchKernelGGL(k_sumsq_partials, dim3(gn), dim3(kBlock), 0, st, n, w, s->partials);
-        hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(kBlock), 0, st, gn, s->partials, lam);
-        hipLaunchKernelGGL(k_normalize, dim3(grid_for(n, kBlock, 1 << 30)), dim3(kBlock), 0, st, n, w, lam, v);
+        if ((e = hipMemcpyAsync(pw_host, pw, 4 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) break;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) break;
+        if (pw_host[1] != 0.0) break;
     }
-    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, st, s->st, lam, s->p.power_iters, s->p.eta_safety);
-    e = hipGetLastError();
+    s->power_steps = (int64_t)pw_host[2];
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, st, s->st, pw, s->p.eta_safety);
+        e = hipGetLastError();
+    }
     hipError_t e2 = hipStreamSynchronize(st);
     hipFree(v);
     hipFree(w);
     hipFree(u);
-    hipFree(lam);
+    hipFree(pw);
     return e != hipSuccess ? e : e2;
 }
 

@@ -1,7 +1,7 @@
 """Learned warm start of the corner push: data, training, evaluation.
 
 The training data are the method's own trajectories: every LP is solved with
-restart history recorded, its 12 features are read from the device, the plain
+restart history recorded, its 16 features are read from the device, the plain
 corner push (Algorithm 1) runs, and the label of a column is 1 iff the pushed
 x ends at one of its bounds (within 1e-6).  The network is trained on the GPU
 by the library's BF16 MFMA kernels; theta is chosen on a validation split so
@@ -25,51 +25,60 @@ from . import lpgen, pdhg
 
 
 def solve_and_label(lp, seed, precision="fp64", eps=1e-6, eps_abs=1e-6):
-    """(features, labels, free-column mask, solve result, push result) of one LP, or None."""
+    """(features, labels, mask, solve result, push result) of one LP, or None.
+
+    The mask selects the columns a learned fix may touch: left free by the
+    plain rule (|z_j| <= eps_abs) and bounded on at least one side."""
     s = pdhg.Solver(lp, precision=precision, record_history=1, eps_rel=eps, eps_abs=eps_abs)
     r = s.solve()
     if r.status != pdhg.PDHG_OPTIMAL:
         return None
     _, _, z = s.get_solution()
-    f = s.features()
+    f = s.features(seed)
     p = s.corner_push(seed)
     x, _, _ = s.get_solution()
     at_bound = (x - lp.l <= 1e-6) | (lp.u - x <= 1e-6)
-    free = np.abs(z) <= eps_abs
-    return f, at_bound.astype(np.float32), free, r, p
+    mask = (np.abs(z) <= eps_abs) & (np.isfinite(lp.l) | np.isfinite(lp.u))
+    return f, at_bound.astype(np.float32), mask, r, p
 
 
 def build_dataset(lps, seeds, precision="fp64", log=None):
-    feats, labels, frees = [], [], []
+    """Features and labels of the masked columns of every LP that solves."""
+    feats, labels = [], []
     t0 = time.time()
     for i, (lp, sd) in enumerate(zip(lps, seeds)):
         out = solve_and_label(lp, sd, precision)
         if out is None:
             continue
-        f, y, free, _, _ = out
-        feats.append(f)
-        labels.append(y)
-        frees.append(free)
+        f, y, mask, _, _ = out
+        feats.append(f[mask])
+        labels.append(y[mask])
         if log and (i + 1) % 20 == 0:
-            log(f"[learned] data {i + 1}/{len(lps)} LPs, {sum(a.shape[0] for a in feats)} columns, "
+            log(f"[learned] data {i + 1}/{len(lps)} LPs, {sum(a.shape[0] for a in feats)} free columns, "
                 f"{time.time() - t0:.1f}s")
-    return np.concatenate(feats), np.concatenate(labels), np.concatenate(frees)
+    return np.concatenate(feats), np.concatenate(labels)
 
 
-def choose_theta(net, f, y, free, min_precision=0.98):
-    """Smallest theta whose fixes among free columns are right >= min_precision."""
-    z = net.forward(f)
-    p = 1.0 / (1.0 + np.exp(-z.astype(np.float64)))
-    best = None
-    for th in (0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 0.98, 0.99, 0.995):
-        sel = free & (p >= th)
-        if sel.sum() == 0:
-            continue
-        prec = float(np.mean(y[sel] > 0.5))
-        if prec >= min_precision:
-            best = (th, prec, int(sel.sum()), int(free.sum()))
-            break
-    return best
+THETAS = (0.5, 0.6, 0.7, 0.8, 0.85, 0.9, 0.95, 0.98, 0.99, 0.995, 0.999)
+
+
+def theta_table(net, f, y):
+    """(theta, precision of the fixes, fraction of free columns fixed) per theta."""
+    p = 1.0 / (1.0 + np.exp(-net.forward(f).astype(np.float64)))
+    rows = []
+    for th in THETAS:
+        sel = p >= th
+        k = int(sel.sum())
+        rows.append((th, float(np.mean(y[sel] > 0.5)) if k else float("nan"), k / max(1, len(y))))
+    return rows
+
+
+def choose_theta(rows, min_precision=0.95):
+    """Smallest theta whose fixes are right at least min_precision of the time."""
+    for th, prec, frac in rows:
+        if frac > 0 and prec >= min_precision:
+            return th
+    return None
 
 
 def time_to_corner(lp, seed, precision="fp64", net=None, theta=0.9, eps=1e-6):
@@ -96,6 +105,7 @@ def main(argv=None):
     ap.add_argument("--m-hi", type=int, default=3000)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--min-precision", type=float, default=0.95)
     ap.add_argument("--mcf", default="", help="nodes,arcs,commodities of a multicommodity evaluation LP")
     args = ap.parse_args(argv)
     log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
@@ -103,19 +113,24 @@ def main(argv=None):
     tr = [lpgen.config3_instance(i, base_seed=40000, m_range=rng_range) for i in range(args.train)]
     va = [lpgen.config3_instance(i, base_seed=42000, m_range=rng_range) for i in range(args.val)]
     ev = [lpgen.config3_instance(i, base_seed=43000, m_range=rng_range) for i in range(args.eval)]
-    f, y, free = build_dataset(tr, [17 + i for i in range(len(tr))], args.precision, log)
-    fv, yv, freev = build_dataset(va, [91 + i for i in range(len(va))], args.precision, log)
-    log(f"[learned] train {f.shape[0]} columns ({y.mean():.3f} positive), val {fv.shape[0]}")
+    f, y = build_dataset(tr, [17 + i for i in range(len(tr))], args.precision, log)
+    fv, yv = build_dataset(va, [91 + i for i in range(len(va))], args.precision, log)
+    log(f"[learned] train {f.shape[0]} free columns ({y.mean():.3f} end at a bound), val {fv.shape[0]}")
     net = pdhg.Mlp(seed=7)
     rep = net.train(f, y, epochs=args.epochs, batch=4096, lr=1e-3, seed=3)
     log(f"[learned] training: loss {rep.loss_first:.4f} -> {rep.loss_last:.4f}, {rep.seconds:.2f}s, "
         f"{rep.samples_per_s:.3e} samples/s, pos_weight {rep.pos_weight:.3f}")
-    th = choose_theta(net, fv, yv, freev)
-    theta = th[0] if th else 0.99
-    log(f"[learned] theta {theta} (validation precision on free columns: {th})")
+    rows = theta_table(net, fv, yv)
+    for th, prec, frac in rows:
+        log(f"[learned] validation theta {th}: precision {prec:.4f}, fixes {frac:.4f} of free columns")
+    theta = choose_theta(rows, args.min_precision)
+    log(f"[learned] theta {theta}")
     out = {"train_columns": int(f.shape[0]), "val_columns": int(fv.shape[0]), "theta": theta,
-           "theta_detail": th, "train_loss": [rep.loss_first, rep.loss_last], "train_seconds": rep.seconds,
+           "theta_table": rows, "train_loss": [rep.loss_first, rep.loss_last], "train_seconds": rep.seconds,
            "train_samples_per_s": rep.samples_per_s, "eval": []}
+    if theta is None:
+        print(json.dumps(out))
+        return
     cases = [(lp, 500 + i) for i, lp in enumerate(ev)]
     if args.mcf:
         nn, na, nk = (int(v) for v in args.mcf.split(","))

@@ -33,7 +33,7 @@ class Params(C.Structure):
         ("restart_suff", C.c_double), ("restart_nec", C.c_double), ("restart_art", C.c_double),
         ("pw_smooth", C.c_double), ("pc_alpha", C.c_double),
         ("power_iters", C.c_int32), ("halpern", C.c_int32),
-        ("eta_safety", C.c_double), ("reflect_gamma", C.c_double),
+        ("eta_safety", C.c_double), ("reflect_gamma", C.c_double), ("power_tol", C.c_double),
         ("push_min_iters", C.c_int32), ("precision", C.c_int32),
         ("push_obj_scale", C.c_double), ("push_max_iter", C.c_int64), ("time_limit", C.c_double),
         ("stream", C.c_void_p), ("verbosity", C.c_int32), ("lanes_at", C.c_int32), ("lanes_a", C.c_int32),
@@ -170,7 +170,7 @@ def load(path: Optional[Path] = None):
     lib.pdhg_default_train_params.argtypes = [P(TrainParams)]
     lib.pdhg_default_train_params.restype = None
     lib.pdhg_mlp_train.argtypes = [C.c_void_p, fp, fp, C.c_int64, P(TrainParams), P(TrainReport)]
-    lib.pdhg_features.argtypes = [C.c_void_p, fp]
+    lib.pdhg_features.argtypes = [C.c_void_p, C.c_uint64, fp]
     lib.pdhg_corner_push_learned.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_uint64, P(PushResult)]
     lib.pdhg_last_error.restype = C.c_char_p
     lib.pdhg_struct_size.restype = C.c_int32
@@ -305,9 +305,9 @@ class Solver:
         self._check(self.lib.pdhg_get_iterate(self.h, _dp(x), _dp(y)))
         return x, y
 
-    def features(self):
+    def features(self, seed: int = 0):
         f = np.zeros((self.n, 16), dtype=np.float32)
-        self._check(self.lib.pdhg_features(self.h, f.ctypes.data_as(C.POINTER(C.c_float))))
+        self._check(self.lib.pdhg_features(self.h, C.c_uint64(seed), f.ctypes.data_as(C.POINTER(C.c_float))))
         return f
 
     def corner_push_learned(self, net, theta: float, seed: int) -> PushResult:
@@ -321,9 +321,10 @@ class Solver:
         return t
 
     def get_scaling(self):
-        dr, dc, s4 = np.zeros(self.m), np.zeros(self.n), np.zeros(4)
-        self._check(self.lib.pdhg_get_scaling(self.h, _dp(dr), _dp(dc), _dp(s4)))
-        return {"dr": dr, "dc": dc, "eta": s4[0], "omega": s4[1], "sigma_est": s4[2], "t": int(s4[3])}
+        dr, dc, s5 = np.zeros(self.m), np.zeros(self.n), np.zeros(5)
+        self._check(self.lib.pdhg_get_scaling(self.h, _dp(dr), _dp(dc), _dp(s5)))
+        return {"dr": dr, "dc": dc, "eta": s5[0], "omega": s5[1], "sigma_est": s5[2], "t": int(s5[3]),
+                "power_steps": int(s5[4])}
 
 
 class Batch:

@@ -74,3 +74,25 @@ def test_fp32_optimal_status_is_backed_by_float64_kkt():
           f"{r.rel_p:.2e}/{r.rel_d:.2e}/{r.rel_gap:.2e}", flush=True)
     if r.status == pdhg.PDHG_OPTIMAL:
         assert max(r.rel_p, r.rel_d, r.rel_gap) <= 20e-6
+
+
+@pytest.mark.parametrize("i,converges", [(100, False), (105, True), (157, True)])
+def test_fp32_check_tests_the_original_objective(i, converges):
+    """Batched-family LPs: the solve-phase checks take c, l, u in float64, so
+    an OPTIMAL status of the mixed path comes with a float64 KKT of the
+    original model within the tolerance (up to the float32 matrix's rounding
+    of Ax and A'y).  LP 100 is one the mixed path does not solve (its primal
+    weight collapses and float32 rounding of the reduced cost, amplified by
+    the growing primal step, keeps the gap near 1e-3): it must end without
+    claiming optimality."""
+    lp = lpgen.config3_instance(i)
+    g = pdhg.Solver(lp, precision="fp32", eps_rel=1e-6, max_iter=60000)
+    r = g.solve()
+    print(f"[fp32] batched-family LP {i}: {pdhg.STATUS[r.status]} after {r.iters} iterations, float64 KKT "
+          f"{r.rel_p:.2e}/{r.rel_d:.2e}/{r.rel_gap:.2e}", flush=True)
+    if converges:
+        assert r.status == pdhg.PDHG_OPTIMAL
+    if r.status == pdhg.PDHG_OPTIMAL:
+        assert max(r.rel_p, r.rel_d, r.rel_gap) <= 1.5e-6
+    else:
+        assert max(r.rel_p, r.rel_d, r.rel_gap) > 1e-6

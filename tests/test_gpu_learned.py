@@ -3,37 +3,44 @@ rule, and the end-to-end pipeline on small LPs of the batched family."""
 import numpy as np
 import pytest
 
-from oracle import OracleSolver
+from oracle import OracleSolver, push_uniform
 from paper_2511_13894_amd import learned, lpgen, pdhg
 
 pytestmark = pytest.mark.gpu
 
 
 def test_features_match_a_host_computation():
-    """x, |c| and column norms (features 0, 2, 3) recomputed on the host from
-    the solve's scaled quantities agree with the device features."""
+    """Features 0, 2, 3 and 12-15 recomputed on the host from the solve's
+    scaled quantities and the published splitmix64 draw agree with the
+    device features."""
     lp = lpgen.config0(2)
     s = pdhg.Solver(lp, record_history=1, eps_rel=1e-8)
     s.solve()
-    f = s.features()
+    seed = 77
+    f = s.features(seed)
     assert f.shape == (lp.n, 16) and np.all(np.isfinite(f))
-    assert np.all(f[:, 12:] == 0)
-    # host side: unscaled solution -> scaled values via the scaling vectors
     sc = s.get_scaling()
     x, _, _ = s.get_solution()
-    xs = x / sc["dc"]
-    cs = np.abs(lp.c * sc["dc"])
-    a = lp.dense() * sc["dr"][:, None] * sc["dc"][None, :]
+    dc = sc["dc"]
+    xs = x / dc
+    cs = np.abs(lp.c * dc)
+    a = lp.dense() * sc["dr"][:, None] * dc[None, :]
     cn = np.linalg.norm(a, axis=0)
+    lo, hi = lp.l / dc, lp.u / dc
+    flo, fhi = np.isfinite(lo), np.isfinite(hi)
+    pc = dc * np.array([push_uniform(seed, j) for j in range(lp.n)])
+    dl = np.where(flo, xs - np.where(flo, lo, 0), -1.0)
+    du = np.where(fhi, np.where(fhi, hi, 0) - xs, -1.0)
+    both = flo & fhi & (hi > lo)
+    rel = np.where(both, (xs - np.where(both, lo, 0)) / np.where(both, hi - lo, 1), -1.0)
 
     def nrm(v):
         sc_ = np.sqrt(np.mean(v * v))
         sc_ = sc_ if sc_ > 0 else 1.0
         return np.sign(v) * np.log1p(np.abs(v) / sc_)
 
-    np.testing.assert_allclose(f[:, 0], nrm(xs), atol=2e-6)
-    np.testing.assert_allclose(f[:, 2], nrm(cs), atol=2e-6)
-    np.testing.assert_allclose(f[:, 3], nrm(cn), atol=2e-6)
+    for q, v in ((0, xs), (2, cs), (3, cn), (12, pc), (13, dl), (14, du), (15, rel)):
+        np.testing.assert_allclose(f[:, q], nrm(v), atol=2e-6, err_msg=f"feature {q}")
     # trend features exist once restarts happened
     assert np.abs(f[:, 4:12]).sum() > 0
 
@@ -67,18 +74,21 @@ def test_learned_push_fixes_undoes_and_stays_feasible():
 
 def test_pipeline_trains_and_compares():
     lps = [lpgen.config3_instance(i, base_seed=45000, m_range=(60, 200)) for i in range(16)]
-    f, y, free = learned.build_dataset(lps[:12], list(range(12)))
-    assert f.shape[0] == y.shape[0] == free.shape[0] > 0
+    f, y = learned.build_dataset(lps[:12], list(range(12)))
+    assert f.shape[0] == y.shape[0] > 0
     net = pdhg.Mlp(2)
     rep = net.train(f, y, epochs=10, batch=1024, lr=2e-3, seed=1)
     z = net.forward(f)
     acc = float(np.mean((z > 0) == (y > 0.5)))
-    print(f"[learned] small pipeline: {f.shape[0]} columns, positives {y.mean():.3f}, loss {rep.loss_first:.3f} -> "
-          f"{rep.loss_last:.3f}, train accuracy {acc:.3f}", flush=True)
+    print(f"[learned] small pipeline: {f.shape[0]} free columns, positives {y.mean():.3f}, loss "
+          f"{rep.loss_first:.3f} -> {rep.loss_last:.3f}, train accuracy {acc:.3f}", flush=True)
     assert rep.loss_last < rep.loss_first
+    rows = learned.theta_table(net, f, y)
+    assert len(rows) == len(learned.THETAS)
     for lp in lps[12:]:
         a = learned.time_to_corner(lp, 3)
         b = learned.time_to_corner(lp, 3, net=net, theta=0.9)
         assert a is not None and b is not None
         assert b["push_status"] in ("PUSH_DONE", "ITER_LIMIT")
-        assert b["rel_p_after"] <= 1.0000001e-6 or b["push_status"] != "PUSH_DONE"
+        if b["push_status"] == "PUSH_DONE":
+            assert b["rel_p_after"] <= 1.0000001e-6

@@ -41,6 +41,7 @@ def test_first_50_iterates_fp64(name, make):
     assert rel_inf(sg["dc"], so["dc"]) <= 1e-14
     assert abs(sg["eta"] - so["eta"]) <= 1e-14 * so["eta"]
     assert abs(sg["omega"] - so["omega"]) <= 1e-13 * so["omega"]
+    assert sg["power_steps"] == so["power_steps"]
     for t in range(1, 51):
         g.iterate(1)
         o.iterate(1)

@@ -199,7 +199,7 @@ def test_empty_row_and_column():
 def test_scaling_reconstructs_matrix_and_step_bound():
     """Ahat = diag(Dr) A diag(Dc) entrywise; Pock-Chambolle (alpha = 1) leaves
     ||Ahat||_2 <= 1; the power-iteration estimate lies below the true norm and
-    within 1% of it; the rows of Ahat approach unit inf-norm after Ruiz."""
+    within 0.5% of it; the rows of Ahat approach unit inf-norm after Ruiz."""
     lp = lpgen.config0(3)
     s = OracleSolver(lp)
     sc = s.scaling()
@@ -212,8 +212,29 @@ def test_scaling_reconstructs_matrix_and_step_bound():
     smax = np.linalg.norm(ah, 2)
     assert smax <= 1.0 + 1e-12
     assert sc["sigma_est"] <= smax * (1 + 1e-12)
-    assert sc["sigma_est"] >= 0.99 * smax
+    assert sc["sigma_est"] >= 0.995 * smax
     assert sc["eta"] == pytest.approx(0.99 / sc["sigma_est"], rel=1e-15)
+
+
+def test_power_iteration_stops_on_its_residual_and_keeps_the_step_below_one_over_the_norm():
+    """On a batched-family LP whose top singular value stands apart from a
+    dense cluster just below it, 32 fixed steps from 1/sqrt(n) stop inside
+    the cluster (about 2% low, so eta ||Ahat|| > 1 and PDHG diverges); the
+    residual rule runs until the estimate is within 0.5% of the true norm
+    (scipy's sparse SVD) and below it."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    lp = lpgen.config3_instance(157)
+    a = sp.csr_matrix((lp.val, lp.col, lp.row_ptr), shape=(lp.m, lp.n))
+    fixed = OracleSolver(lp, power_iters=32, power_tol=0.0)
+    rule = OracleSolver(lp)
+    sc_f, sc_r = fixed.scaling(), rule.scaling()
+    ah = (sp.diags(sc_r["dr"]) @ a @ sp.diags(sc_r["dc"])).tocsr()
+    smax = float(sla.svds(ah, k=1, return_singular_vectors=False, tol=1e-12)[0])
+    assert sc_f["power_steps"] == 32 and sc_f["sigma_est"] < 0.99 * smax
+    assert 32 < sc_r["power_steps"] < 4000
+    assert 0.995 * smax <= sc_r["sigma_est"] <= smax * (1 + 1e-12)
+    assert sc_r["eta"] * smax < 1.0
 
 
 def test_ruiz_only_equilibrates_inf_norms():
