@@ -45,7 +45,7 @@ def make_lp(cfg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("pdhg_iter.hip", "pdhg_device.hpp", "pdhg_internal.hpp"):
+    for f in ("pdhg_iter.hip", "pdhg_device.hpp", "pdhg_kernels.hpp", "pdhg_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2511_13894_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--iters-only", type=int, default=0,
                     help="profiling runs: create + this many iterations per step, no push, no JSON roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every cycle eagerly instead of replaying captured hipGraphs (profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note, "
@@ -107,14 +109,14 @@ def main():
 
     if args.iters_only:
         for k in range(args.steps):
-            s = pdhg.Solver(lp, precision=args.precision)
+            s = pdhg.Solver(lp, precision=args.precision, use_graph=0 if args.no_graph else 1)
             r = s.iterate(args.iters_only)
             s.destroy()
             print(f"[bench] profiling step {k}: {r.iters} iterations", file=sys.stderr, flush=True)
         return
 
     def step(timing):
-        s = pdhg.Solver(lp, precision=args.precision, timing=timing)
+        s = pdhg.Solver(lp, precision=args.precision, timing=timing, use_graph=0 if args.no_graph else 1)
         r = s.solve()
         p = s.corner_push(args.seed)
         t = s.get_timing() if timing else None
