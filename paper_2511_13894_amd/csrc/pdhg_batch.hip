@@ -84,12 +84,12 @@ __global__ __launch_bounds__(NT) void kb_dual(const int4 *__restrict__ tiles, co
 }
 
 template <typename V>
-static void launch_primal_b(pdhg_batch *b, int i, int store)
+static void launch_primal_b(pdhg_batch *b, int i, int store, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     pdhg_solver *s = b->s;
 #define PDHG_BP_CASE(TT, RR, NT)                                                                               \
     case TT:                                                                                                   \
-        hipLaunchKernelGGL((kb_primal<V, RR, NT>), dim3(b->n_ptiles), dim3(NT), 0, s->stream, b->ptiles, s->tp, \
+        PDHG_LAUNCH(e0, e1, (kb_primal<V, RR, NT>), dim3(b->n_ptiles), dim3(NT), s->stream, b->ptiles, s->tp, \
                            s->ti, (const V *)s->ahat_t, (const double *)s->y, s->ch,               \
                            (const V *)s->lh, (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar,     \
                            (V *)s->xp, b->sts, i, store);                                                     \
@@ -107,12 +107,12 @@ static void launch_primal_b(pdhg_batch *b, int i, int store)
 }
 
 template <typename V>
-static void launch_dual_b(pdhg_batch *b, int i, int store)
+static void launch_dual_b(pdhg_batch *b, int i, int store, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     pdhg_solver *s = b->s;
 #define PDHG_BD_CASE(TT, RR, NT)                                                                               \
     case TT:                                                                                                   \
-        hipLaunchKernelGGL((kb_dual<V, RR, NT>), dim3(b->n_dtiles), dim3(NT), 0, s->stream, b->dtiles, s->rp,   \
+        PDHG_LAUNCH(e0, e1, (kb_dual<V, RR, NT>), dim3(b->n_dtiles), dim3(NT), s->stream, b->dtiles, s->rp,   \
                            s->ci, (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bh, s->sense,    \
                            (double *)s->y, (const double *)s->ya, (double *)s->yp, b->sts, i, store);         \
         break;
@@ -298,13 +298,11 @@ hipError_t batch_iterations(pdhg_batch *b, int count, bool check_at_end, int mod
     const int timed = (timed_launch && count >= 2) ? count / 2 : -1;
     for (int i = 0; i < count; i++) {
         const int store = (check_at_end && i == count - 1) ? 1 : 0;
-        if (i == timed) hipEventRecord(s->ev[0], s->stream);
-        if (s->fp32) launch_primal_b<float>(b, i, store);
-        else launch_primal_b<double>(b, i, store);
-        if (i == timed) hipEventRecord(s->ev[1], s->stream);
-        if (s->fp32) launch_dual_b<float>(b, i, store);
-        else launch_dual_b<double>(b, i, store);
-        if (i == timed) hipEventRecord(s->ev[2], s->stream);
+        hipEvent_t *ev = i == timed ? s->ev : nullptr;
+        if (s->fp32) launch_primal_b<float>(b, i, store, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
+        else launch_primal_b<double>(b, i, store, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
+        if (s->fp32) launch_dual_b<float>(b, i, store, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+        else launch_dual_b<double>(b, i, store, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -837,8 +835,8 @@ hipError_t batch_autotune(pdhg_batch *b)
     if (e == hipSuccess) e = hipMalloc(&sxp, vb * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sy, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
     if (e == hipSuccess) e = hipMalloc(&syp, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
-    if (e == hipSuccess) e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
     if (e == hipSuccess) e = hipMemcpyAsync(sx, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sxbar, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sy, s->y, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);

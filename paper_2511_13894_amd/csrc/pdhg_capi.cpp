@@ -118,7 +118,7 @@ int run_phase(pdhg_solver *s, int64_t iters, int mode, double t0)
         if (events && !s->st_host->done) {
             float a = 0.0f, b2 = 0.0f;
             if (hipEventElapsedTime(&a, s->ev[0], s->ev[1]) == hipSuccess &&
-                hipEventElapsedTime(&b2, s->ev[1], s->ev[2]) == hipSuccess) {
+                hipEventElapsedTime(&b2, s->ev[2], s->ev[3]) == hipSuccess) {
                 s->t_primal_ms += a;
                 s->t_dual_ms += b2;
                 s->t_samples += 1;
@@ -228,7 +228,7 @@ bool run_batch_phase(pdhg_batch *b, int64_t iters, int mode, double t0)
         if (events) {
             float a = 0.0f, b2 = 0.0f;
             if (hipEventElapsedTime(&a, s->ev[0], s->ev[1]) == hipSuccess &&
-                hipEventElapsedTime(&b2, s->ev[1], s->ev[2]) == hipSuccess) {
+                hipEventElapsedTime(&b2, s->ev[2], s->ev[3]) == hipSuccess) {
                 s->t_primal_ms += a;
                 s->t_dual_ms += b2;
                 s->t_samples += 1;
@@ -407,7 +407,7 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
         s->p = p;
         s->fp32 = p.precision == PDHG_FP32_MIXED;
         if (p.timing)
-            for (hipEvent_t &e : s->ev) HIPCHK(hipEventCreate(&e));
+            for (hipEvent_t &e : s->ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         if (p.stream) s->stream = (hipStream_t)p.stream;
         else {
             HIPCHK(hipStreamCreate(&s->stream));

@@ -1,6 +1,7 @@
 // Internal declarations of the gfx950 PDHG library (not part of the ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -8,6 +9,16 @@
 #include <vector>
 
 #include "pdhg.h"
+
+// Launch a kernel on STREAM.  With a start/stop event pair the events are
+// bound to this one dispatch (hipExtLaunchKernel), so their elapsed time is
+// the kernel's own execution, free of the dispatch latency a separate
+// hipEventRecord would add.
+#define PDHG_LAUNCH(E0, E1, KERNEL, GRID, BLOCK, STREAM, ...)                                                    \
+    do {                                                                                                         \
+        if (E0) hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, E0, E1, 0, __VA_ARGS__);                    \
+        else hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, __VA_ARGS__);                                    \
+    } while (0)
 
 namespace pdhg {
 
@@ -134,7 +145,7 @@ struct pdhg_solver {
     bool learned_active = false;
 
     // live kernel timing: events around one primal and one dual launch per cycle
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr}; // primal start/stop, dual start/stop
     double t_primal_ms = 0.0, t_dual_ms = 0.0;
     int64_t t_samples = 0;
 };

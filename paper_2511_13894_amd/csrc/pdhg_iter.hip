@@ -117,7 +117,7 @@ __global__ __launch_bounds__(NT) void k_dual_tiled(int m, const int *__restrict_
 }
 
 template <typename V>
-static void launch_primal(pdhg_solver *s, int i, int store)
+static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     const int L = s->kern_at;
     if (s->n <= 0) return;
@@ -127,7 +127,7 @@ static void launch_primal(pdhg_solver *s, int i, int store)
         const int grid = (s->n + rows_per - 1) / rows_per;
 #define PDHG_PT_CASE(TT, RR, NT)                                                                                \
     case TT:                                                                                                    \
-        hipLaunchKernelGGL((k_primal_tiled<V, RR, NT>), dim3(grid), dim3(NT), 0, s->stream, s->n, s->tp, s->ti, \
+        PDHG_LAUNCH(e0, e1, (k_primal_tiled<V, RR, NT>), dim3(grid), dim3(NT), s->stream, s->n, s->tp, s->ti, \
                            (const V *)s->ahat_t, (const double *)s->y, s->ch, (const V *)s->lh,          \
                            (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i,  \
                            store);                                                                              \
@@ -147,7 +147,7 @@ static void launch_primal(pdhg_solver *s, int i, int store)
     const int grid = (int)(((int64_t)s->n * L + kBlock - 1) / kBlock);
 #define PDHG_PRIMAL_CASE(LL)                                                                                    \
     case LL:                                                                                                    \
-        hipLaunchKernelGGL((k_primal<V, LL>), dim3(grid), dim3(kBlock), 0, s->stream, s->n, s->tp, s->ti,      \
+        PDHG_LAUNCH(e0, e1, (k_primal<V, LL>), dim3(grid), dim3(kBlock), s->stream, s->n, s->tp, s->ti,      \
                            (const V *)s->ahat_t, (const double *)s->y, s->ch, (const V *)s->lh,          \
                            (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i,  \
                            store);                                                                              \
@@ -166,7 +166,7 @@ static void launch_primal(pdhg_solver *s, int i, int store)
 }
 
 template <typename V>
-static void launch_dual(pdhg_solver *s, int i, int store)
+static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     const int L = s->kern_a;
     if (s->m <= 0) return;
@@ -176,7 +176,7 @@ static void launch_dual(pdhg_solver *s, int i, int store)
         const int grid = (s->m + rows_per - 1) / rows_per;
 #define PDHG_DT_CASE(TT, RR, NT)                                                                                \
     case TT:                                                                                                    \
-        hipLaunchKernelGGL((k_dual_tiled<V, RR, NT>), dim3(grid), dim3(NT), 0, s->stream, s->m, s->rp, s->ci,   \
+        PDHG_LAUNCH(e0, e1, (k_dual_tiled<V, RR, NT>), dim3(grid), dim3(NT), s->stream, s->m, s->rp, s->ci,   \
                            (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bh, s->sense, (double *)s->y,\
                            (const double *)s->ya, (double *)s->yp, s->st, i, store);                                      \
         break;
@@ -195,7 +195,7 @@ static void launch_dual(pdhg_solver *s, int i, int store)
     const int grid = (int)(((int64_t)s->m * L + kBlock - 1) / kBlock);
 #define PDHG_DUAL_CASE(LL)                                                                                      \
     case LL:                                                                                                    \
-        hipLaunchKernelGGL((k_dual<V, LL>), dim3(grid), dim3(kBlock), 0, s->stream, s->m, s->rp, s->ci,        \
+        PDHG_LAUNCH(e0, e1, (k_dual<V, LL>), dim3(grid), dim3(kBlock), s->stream, s->m, s->rp, s->ci,        \
                            (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bh, s->sense, (double *)s->y,\
                            (const double *)s->ya, (double *)s->yp, s->st, i, store);                                      \
         break;
@@ -403,13 +403,11 @@ hipError_t launch_iterations(pdhg_solver *s, int count, bool check_at_end, int m
     const int timed = (timed_launch && count >= 2) ? count / 2 : -1; // one sampled iteration
     for (int i = 0; i < count; i++) {
         const int store = (check_at_end && i == count - 1) ? 1 : 0;
-        if (i == timed) hipEventRecord(s->ev[0], s->stream);
-        if (s->fp32) launch_primal<float>(s, i, store);
-        else launch_primal<double>(s, i, store);
-        if (i == timed) hipEventRecord(s->ev[1], s->stream);
-        if (s->fp32) launch_dual<float>(s, i, store);
-        else launch_dual<double>(s, i, store);
-        if (i == timed) hipEventRecord(s->ev[2], s->stream);
+        hipEvent_t *ev = i == timed ? s->ev : nullptr;
+        if (s->fp32) launch_primal<float>(s, i, store, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
+        else launch_primal<double>(s, i, store, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
+        if (s->fp32) launch_dual<float>(s, i, store, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+        else launch_dual<double>(s, i, store, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -873,8 +871,8 @@ hipError_t autotune(pdhg_solver *s)
     if (e == hipSuccess) e = hipMalloc(&sxp, vb * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sy, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
     if (e == hipSuccess) e = hipMalloc(&syp, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
-    if (e == hipSuccess) e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
     if (e == hipSuccess) e = hipMemcpyAsync(sx, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sxbar, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sy, s->y, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
@@ -953,8 +951,8 @@ hipError_t copy_probe(int64_t bytes, int reps, double *gbps)
     hipError_t e = hipMalloc(&a, (size_t)n16 * 16);
     if (e == hipSuccess) e = hipMalloc(&b, (size_t)n16 * 16);
     if (e == hipSuccess) e = hipStreamCreate(&st);
-    if (e == hipSuccess) e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
     if (e == hipSuccess) e = hipMemsetAsync(a, 1, (size_t)n16 * 16, st);
     const int grid = grid_for(n16, kBlock, 1 << 30);
     if (e == hipSuccess) {

@@ -107,6 +107,8 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--min-precision", type=float, default=0.95)
     ap.add_argument("--mcf", default="", help="nodes,arcs,commodities of a multicommodity evaluation LP")
+    ap.add_argument("--mcf-precision", default="fp32", choices=["fp64", "fp32"])
+    ap.add_argument("--mcf-seeds", type=int, default=1)
     args = ap.parse_args(argv)
     log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
     rng_range = (args.m_lo, args.m_hi)
@@ -131,19 +133,37 @@ def main(argv=None):
     if theta is None:
         print(json.dumps(out))
         return
-    cases = [(lp, 500 + i) for i, lp in enumerate(ev)]
+    cases = [(lambda lp=lp: lp, 500 + i, args.precision) for i, lp in enumerate(ev)]
     if args.mcf:
         nn, na, nk = (int(v) for v in args.mcf.split(","))
-        cases.append((lpgen.multicommodity(nn, na, nk, seed=4100), 4100))
-    for lp, sd in cases:
-        plain = time_to_corner(lp, sd, args.precision)
-        learned = time_to_corner(lp, sd, args.precision, net, theta)
-        out["eval"].append({"lp": lp.name, "m": lp.m, "n": lp.n, "plain": plain, "learned": learned})
+        for k in range(args.mcf_seeds):
+            cases.append((lambda k=k: lpgen.multicommodity(nn, na, nk, seed=4100 + k), 4100 + k, args.mcf_precision))
+    for make, sd, prec in cases:
+        lp = make()
+        plain = time_to_corner(lp, sd, prec)
+        learned = time_to_corner(lp, sd, prec, net, theta)
+        out["eval"].append({"lp": lp.name, "m": lp.m, "n": lp.n, "precision": prec, "plain": plain,
+                            "learned": learned})
         if plain and learned:
-            log(f"[learned] {lp.name}: time {plain['seconds']:.3f}s -> {learned['seconds']:.3f}s, push iters "
-                f"{plain['push_iters']} -> {learned['push_iters']}, est_primal {plain['est_primal_after']} -> "
-                f"{learned['est_primal_after']}, learned fixes {learned['learned_fix']} (undone "
+            log(f"[learned] {lp.name} ({prec}): time {plain['seconds']:.3f}s -> {learned['seconds']:.3f}s, push "
+                f"iters {plain['push_iters']} -> {learned['push_iters']}, est_primal {plain['est_primal_after']} -> "
+                f"{learned['est_primal_after']}, candidates {plain['candidates_after']} -> "
+                f"{learned['candidates_after']}, learned fixes {learned['learned_fix']} (undone "
                 f"{learned['learned_undo']})")
+        else:
+            log(f"[learned] {lp.name} ({prec}): solve did not reach optimality")
+    both = [e for e in out["eval"] if e["plain"] and e["learned"]]
+    for tag, sel in (("batched family", [e for e in both if e["lp"].startswith("c3")]),
+                     ("multicommodity", [e for e in both if e["lp"].startswith("mcf")])):
+        if not sel:
+            continue
+        ratio = np.exp(np.mean([np.log(e["learned"]["seconds"] / e["plain"]["seconds"]) for e in sel]))
+        pi = sum(e["plain"]["push_iters"] for e in sel), sum(e["learned"]["push_iters"] for e in sel)
+        ep = sum(e["plain"]["est_primal_after"] for e in sel), sum(e["learned"]["est_primal_after"] for e in sel)
+        out[f"summary_{tag.split()[0]}"] = {"lps": len(sel), "geomean_time_ratio": ratio, "push_iters": pi,
+                                             "est_primal_after": ep}
+        log(f"[learned] {tag}: {len(sel)} LPs, time-to-corner learned/plain geomean {ratio:.3f}, push iterations "
+            f"{pi[0]} -> {pi[1]}, primal push estimate {ep[0]} -> {ep[1]}")
     print(json.dumps(out))
 
 
