@@ -102,6 +102,7 @@ typedef struct pdhg_params {
     int32_t lanes_at;      /* primal-half kernel: 1..64 (power of 2) lanes per row;
                               -32/-64/-128/-256: LDS tile of that many rows, 256
                               threads; -1032/-1064: tile of 32/64 rows, 64 threads;
+                              -2256: one row per workgroup of 256 threads (long rows);
                               0 = chosen from the mean row length                      */
     int32_t lanes_a;       /* dual-half kernel, same encoding                           */
     int32_t use_graph;     /* 1: replay check cycles from a captured hipGraph (default) */

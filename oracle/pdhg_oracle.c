@@ -206,11 +206,31 @@ static void gather_t(const or_solver *s, const double *val, double *tval)
     for (int64_t e = 0; e < s->nnz; e++) tval[e] = val[s->tpos[e]];
 }
 
+/* Compensated summation (Neumaier's improvement of Kahan's method): the
+ * rounding error of a sum stays within a few units in the last place of the
+ * result whatever the number of terms.  Every reduction over all rows or all
+ * columns uses it, so that at 10^7 terms the reference is at least as exact
+ * as any summation order a parallel implementation may use (a plain
+ * left-to-right sum can drift by n*eps, 1e-9 at that size). */
+typedef struct {
+    double s, c;
+} csum;
+
+static void cadd(csum *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+static double cval(const csum *a) { return a->s + a->c; }
+
 static double norm2(const double *v, int64_t n)
 {
-    double acc = 0.0;
-    for (int64_t i = 0; i < n; i++) acc += v[i] * v[i];
-    return sqrt(acc);
+    csum acc = {0.0, 0.0};
+    for (int64_t i = 0; i < n; i++) cadd(&acc, v[i] * v[i]);
+    return sqrt(cval(&acc));
 }
 
 /* ------------------------------------------------------------------------ */
@@ -228,14 +248,15 @@ static void kkt_unscaled(const or_solver *s, const double *c, const double *l, c
     mv_A(s, s->av, x, ax);
     mv_At(s, tv, y, aty);
     free(tv);
-    double rp2 = 0, rpinf = 0, rd2 = 0, rdinf = 0, pobj = 0, dobj = 0;
+    double rpinf = 0, rdinf = 0;
+    csum rp2 = {0, 0}, rd2 = {0, 0}, cx = {0, 0}, by = {0, 0};
     for (int i = 0; i < m; i++) {
         double r = s->b[i] - ax[i];
         if (sense[i] == '<') r = r < 0.0 ? r : 0.0;
         else if (sense[i] == '>') r = r > 0.0 ? r : 0.0;
-        rp2 += r * r;
+        cadd(&rp2, r * r);
         if (fabs(r) > rpinf) rpinf = fabs(r);
-        dobj += s->b[i] * y[i];
+        cadd(&by, s->b[i] * y[i]);
     }
     for (int j = 0; j < n; j++) {
         double lam = c[j] - aty[j];
@@ -243,16 +264,17 @@ static void kkt_unscaled(const or_solver *s, const double *c, const double *l, c
         double zm = (!is_inf_up(u[j]) && lam < 0.0) ? -lam : 0.0;
         double z = zp - zm;
         double rd = lam - z;
-        rd2 += rd * rd;
+        cadd(&rd2, rd * rd);
         if (fabs(rd) > rdinf) rdinf = fabs(rd);
-        pobj += c[j] * x[j];
-        if (zp > 0.0) dobj += l[j] * zp;
-        if (zm > 0.0) dobj -= u[j] * zm;
+        cadd(&cx, c[j] * x[j]);
+        if (zp > 0.0) cadd(&by, l[j] * zp);
+        if (zm > 0.0) cadd(&by, -(u[j] * zm));
         if (zout) zout[j] = z;
     }
+    double pobj = cval(&cx), dobj = cval(&by);
     double nb = norm2(s->b, m), nc = norm2(c, n);
-    k->rp2 = sqrt(rp2);
-    k->rd2 = sqrt(rd2);
+    k->rp2 = sqrt(cval(&rp2));
+    k->rd2 = sqrt(cval(&rd2));
     k->rpinf = rpinf;
     k->rdinf = rdinf;
     k->pobj = pobj;
@@ -305,26 +327,27 @@ static void kkt_scaled_parts(or_solver *s, const double *x, const double *y, dou
     double *aty = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     mv_A(s, s->ahat, x, ax);
     mv_At(s, s->ahat_t, y, aty);
-    double rp = 0, rd = 0, pobj = 0, dobj = 0;
+    csum rp = {0, 0}, rd = {0, 0}, cx = {0, 0}, by = {0, 0};
     for (int i = 0; i < m; i++) {
         double r = s->bh[i] - ax[i];
         if (s->sense[i] == '<') r = r < 0.0 ? r : 0.0;
         else if (s->sense[i] == '>') r = r > 0.0 ? r : 0.0;
-        rp += r * r;
-        dobj += s->bh[i] * y[i];
+        cadd(&rp, r * r);
+        cadd(&by, s->bh[i] * y[i]);
     }
     for (int j = 0; j < n; j++) {
         double lam = s->ch[j] - aty[j];
         double zp = (!is_inf_lo(s->lh[j]) && lam > 0.0) ? lam : 0.0;
         double zm = (!is_inf_up(s->uh[j]) && lam < 0.0) ? -lam : 0.0;
         double rdj = lam - (zp - zm);
-        rd += rdj * rdj;
-        pobj += s->ch[j] * x[j];
-        if (zp > 0.0) dobj += s->lh[j] * zp;
-        if (zm > 0.0) dobj -= s->uh[j] * zm;
+        cadd(&rd, rdj * rdj);
+        cadd(&cx, s->ch[j] * x[j]);
+        if (zp > 0.0) cadd(&by, s->lh[j] * zp);
+        if (zm > 0.0) cadd(&by, -(s->uh[j] * zm));
     }
-    *p2 = rp;
-    *d2 = rd;
+    double pobj = cval(&cx), dobj = cval(&by);
+    *p2 = cval(&rp);
+    *d2 = cval(&rd);
     *gap2 = (pobj - dobj) * (pobj - dobj);
     free(ax);
     free(aty);
@@ -466,9 +489,10 @@ static void scale_and_step(or_solver *s)
     for (int it = 0; it < s->p.power_iters; it++) {
         mv_A(s, s->ahat, v, av);
         mv_At(s, s->ahat_t, av, w);
-        double rho = 0.0, ww = 0.0;
-        for (int i = 0; i < m; i++) rho += av[i] * av[i];
-        for (int j = 0; j < n; j++) ww += w[j] * w[j];
+        csum rs = {0, 0}, ws = {0, 0};
+        for (int i = 0; i < m; i++) cadd(&rs, av[i] * av[i]);
+        for (int j = 0; j < n; j++) cadd(&ws, w[j] * w[j]);
+        double rho = cval(&rs), ww = cval(&ws);
         lam = sqrt(ww);
         s->power_steps = it + 1;
         if (!(lam > 0.0)) break;
@@ -653,11 +677,11 @@ static void restart_check(or_solver *s)
                      ((double)s->k >= s->p.restart_art * (double)s->t);
     s->kkt_prev = kc;
     if (!do_restart) return;
-    double dx = 0.0, dy = 0.0;
-    for (int j = 0; j < s->n; j++) dx += (s->xp[j] - s->xa[j]) * (s->xp[j] - s->xa[j]);
-    for (int i = 0; i < s->m; i++) dy += (s->yp[i] - s->ya[i]) * (s->yp[i] - s->ya[i]);
-    dx = sqrt(dx);
-    dy = sqrt(dy);
+    csum sx = {0, 0}, sy = {0, 0};
+    for (int j = 0; j < s->n; j++) cadd(&sx, (s->xp[j] - s->xa[j]) * (s->xp[j] - s->xa[j]));
+    for (int i = 0; i < s->m; i++) cadd(&sy, (s->yp[i] - s->ya[i]) * (s->yp[i] - s->ya[i]));
+    double dx = sqrt(cval(&sx));
+    double dy = sqrt(cval(&sy));
     if (dx > 1e-10 && dy > 1e-10) {
         double th = s->p.pw_smooth;
         s->omega = exp(th * log(dy / dx) + (1.0 - th) * log(s->omega));

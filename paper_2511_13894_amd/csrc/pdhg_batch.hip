@@ -30,7 +30,7 @@ __global__ __launch_bounds__(NT) void kb_primal(const int4 *__restrict__ tiles, 
                                                int store_cand)
 {
     __shared__ int s_ptr[T + 1];
-    __shared__ double s_prod[8 * NT];
+    __shared__ double s_prod[kTileU * NT];
     __shared__ double s_sum[T];
     const int4 tl = tiles[xcd_block(blockIdx.x, gridDim.x)];
     const DevState *st = sts + tl.x;
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(NT) void kb_dual(const int4 *__restrict__ tiles, co
                                              const DevState *__restrict__ sts, int i, int store_cand)
 {
     __shared__ int s_ptr[T + 1];
-    __shared__ double s_prod[8 * NT];
+    __shared__ double s_prod[kTileU * NT];
     __shared__ double s_sum[T];
     const int4 tl = tiles[xcd_block(blockIdx.x, gridDim.x)];
     const DevState *st = sts + tl.x;

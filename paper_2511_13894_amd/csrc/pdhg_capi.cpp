@@ -356,9 +356,10 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
         return fail(PDHG_ERR_INVALID_ARG, "invalid parameter");
     for (int32_t k : {p.lanes_a, p.lanes_at}) {
         const bool lane_ok = k >= 1 && k <= 64 && !(k & (k - 1));
-        const bool tile_ok = k == -32 || k == -64 || k == -128 || k == -256 || k == -1032 || k == -1064;
+        const bool tile_ok = k == -32 || k == -64 || k == -128 || k == -256 || k == -1032 || k == -1064 || k == kRowBlock;
         if (k != 0 && !lane_ok && !tile_ok)
-            return fail(PDHG_ERR_INVALID_ARG, "lanes must be 0, a power of two in 1..64, or one of -32/-64/-128/-256/-1032/-1064");
+            return fail(PDHG_ERR_INVALID_ARG,
+                        "lanes must be 0, a power of two in 1..64, or one of -32/-64/-128/-256/-1032/-1064/-2256");
     }
 
     // canonical rows (ascending columns, duplicates summed), host side ingest
@@ -772,7 +773,8 @@ int pdhg_batch_create(int32_t count, const pdhg_lp_desc *lps, const pdhg_params 
     if (params) p = *params;
     else pdhg_default_params(&p);
     for (int32_t k : {p.lanes_a, p.lanes_at})
-        if (k > 0) return fail(PDHG_ERR_INVALID_ARG, "the batch engine runs tiled kernels only (lanes <= 0)");
+        if (k > 0 || k == kRowBlock)
+            return fail(PDHG_ERR_INVALID_ARG, "the batch engine runs tiled kernels only (lanes -32/-64/-128/-256/-1032/-1064)");
     // one block-diagonal model with global column indices
     std::vector<int> roff(1, 0), coff(1, 0);
     int64_t nz_total = 0;
@@ -879,7 +881,8 @@ int pdhg_batch_create(int32_t count, const pdhg_lp_desc *lps, const pdhg_params 
         // tiled kernels from the mean row lengths (tiles only: the batch has no lane-group path)
         auto tiled = [](double mean) {
             const int k = choose_kernel(mean);
-            return k < 0 ? k : -32;
+            if (k == kRowBlock || k > 0) return mean <= 3.0 ? -256 : -32;
+            return k;
         };
         const int ka = p.lanes_a ? p.lanes_a : tiled(M > 0 ? (double)nz_total / M : 1.0);
         const int kat = p.lanes_at ? p.lanes_at : tiled(N > 0 ? (double)nz_total / N : 1.0);

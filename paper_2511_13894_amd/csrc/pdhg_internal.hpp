@@ -23,6 +23,7 @@
 namespace pdhg {
 
 constexpr int kBlock = 256;         // threads per workgroup (4 wave64)
+constexpr int kRowBlock = -2256; // kernel code: one row per workgroup of kBlock threads
 constexpr int kMaxRedBlocks = 1024; // cap on per-block partials of a reduction
 
 // Quantities reduced at a check (block partials, then one fixed-order pass).

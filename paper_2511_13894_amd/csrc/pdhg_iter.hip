@@ -55,6 +55,81 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
     dual_update(r, acc, y[r], bh[r], ya[r], sense[r], y, yp, st, i, store_cand);
 }
 
+// ------------------------------------------------------- long rows ---
+// One row per workgroup of kBlock threads, for rows of hundreds of entries
+// or more: the threads stride over the row four entries at a time, with all
+// index and value loads issued before the gathers, and a block reduction in
+// a fixed order gives the row sum to thread 0, which runs the update.
+template <typename VM, typename VV>
+__device__ __forceinline__ double row_block_sum(int beg, int end, const int *__restrict__ idx,
+                                                const VM *__restrict__ val, const VV *__restrict__ vec)
+{
+    double acc = 0.0;
+    for (int e0 = beg + (int)threadIdx.x; e0 < end; e0 += 4 * kBlock) {
+        int id[4];
+        double v[4], g[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = e0 + u * kBlock;
+            id[u] = e < end ? idx[e] : 0;
+            v[u] = e < end ? (double)val[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) g[u] = e0 + u * kBlock < end ? (double)vec[id[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (e0 + u * kBlock < end) acc += v[u] * g[u];
+    }
+    double q[1] = {acc};
+    block_reduce<1>(q, 0u);
+    return q[0];
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_primal_rowblock(int n, const int *__restrict__ tp,
+                                                           const int *__restrict__ ti, const V *__restrict__ atv,
+                                                           const double *__restrict__ y, const double *__restrict__ ch,
+                                                           const V *__restrict__ lh, const V *__restrict__ uh,
+                                                           V *__restrict__ x, const V *__restrict__ xa,
+                                                           V *__restrict__ xbar, V *__restrict__ xp,
+                                                           const DevState *__restrict__ st, int i, int store_cand)
+{
+    if (st->done) return;
+    const int j = xcd_block(blockIdx.x, gridDim.x);
+    double xj = 0, cj = 0, lo = 0, hi = 0, aj = 0;
+    if (threadIdx.x == 0) {
+        xj = (double)x[j];
+        cj = ch[j];
+        lo = (double)lh[j];
+        hi = (double)uh[j];
+        aj = (double)xa[j];
+    }
+    const double g = row_block_sum<V, double>(tp[j], tp[j + 1], ti, atv, y);
+    if (threadIdx.x == 0) primal_update<V>(j, g, xj, cj, lo, hi, aj, x, xbar, xp, st, i, store_cand);
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_dual_rowblock(int m, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                         const V *__restrict__ av, const V *__restrict__ xbar,
+                                                         const double *__restrict__ bh,
+                                                         const int8_t *__restrict__ sense, double *__restrict__ y,
+                                                         const double *__restrict__ ya, double *__restrict__ yp,
+                                                         const DevState *__restrict__ st, int i, int store_cand)
+{
+    if (st->done) return;
+    const int r = xcd_block(blockIdx.x, gridDim.x);
+    double yr = 0, br = 0, ar = 0;
+    int8_t sn = 0;
+    if (threadIdx.x == 0) {
+        yr = y[r];
+        br = bh[r];
+        ar = ya[r];
+        sn = sense[r];
+    }
+    const double h = row_block_sum<V, V>(rp[r], rp[r + 1], ci, av, xbar);
+    if (threadIdx.x == 0) dual_update(r, h, yr, br, ar, sn, y, yp, st, i, store_cand);
+}
+
 template <typename V, int T, int NT>
 __global__ __launch_bounds__(NT) void k_primal_tiled(int n, const int *__restrict__ tp, const int *__restrict__ ti,
                                                     const V *__restrict__ atv, const double *__restrict__ y,
@@ -65,7 +140,7 @@ __global__ __launch_bounds__(NT) void k_primal_tiled(int n, const int *__restric
                                                     int store_cand)
 {
     __shared__ int s_ptr[T + 1];
-    __shared__ double s_prod[8 * NT];
+    __shared__ double s_prod[kTileU * NT];
     __shared__ double s_sum[T];
     if (st->done) return;
     const int r0 = xcd_block(blockIdx.x, gridDim.x) * T;
@@ -95,7 +170,7 @@ __global__ __launch_bounds__(NT) void k_dual_tiled(int m, const int *__restrict_
                                                   int store_cand)
 {
     __shared__ int s_ptr[T + 1];
-    __shared__ double s_prod[8 * NT];
+    __shared__ double s_prod[kTileU * NT];
     __shared__ double s_sum[T];
     if (st->done) return;
     const int r0 = xcd_block(blockIdx.x, gridDim.x) * T;
@@ -121,6 +196,12 @@ static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = null
 {
     const int L = s->kern_at;
     if (s->n <= 0) return;
+    if (L == kRowBlock) {
+        PDHG_LAUNCH(e0, e1, (k_primal_rowblock<V>), dim3(s->n), dim3(kBlock), s->stream, s->n, s->tp, s->ti,
+                    (const V *)s->ahat_t, (const double *)s->y, s->ch, (const V *)s->lh, (const V *)s->uh,
+                    (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i, store);
+        return;
+    }
     if (L < 0) { // LDS-tiled kernel: -T (256 threads) or -(1000 + T) (64 threads)
         const int T = -L;
         const int rows_per = T > 1000 ? T - 1000 : T;
@@ -170,6 +251,12 @@ static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullpt
 {
     const int L = s->kern_a;
     if (s->m <= 0) return;
+    if (L == kRowBlock) {
+        PDHG_LAUNCH(e0, e1, (k_dual_rowblock<V>), dim3(s->m), dim3(kBlock), s->stream, s->m, s->rp, s->ci,
+                    (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bh, s->sense, (double *)s->y,
+                    (const double *)s->ya, (double *)s->yp, s->st, i, store);
+        return;
+    }
     if (L < 0) {
         const int T = -L;
         const int rows_per = T > 1000 ? T - 1000 : T;
@@ -849,14 +936,16 @@ hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, double
 }
 
 // ------------------------------------------------------- kernel choice ---
-// Short rows: LDS tiles sized from measured c1 / c2 sweeps; long rows
-// (mean > 48): lane groups sized to the mean.
+// From measured sweeps on the 100k x 400k and 7k x 10M LPs: one lane per row
+// for rows of about 2 entries, LDS tiles for 3 to 48 entries, lane groups
+// sized to the mean up to 384 entries, one workgroup per row beyond.
 int choose_kernel(double mean_row)
 {
-    if (mean_row <= 3.0) return -256;  // very short rows: many rows per tile
-    if (mean_row <= 32.0) return -64;  // measured best for 6 to 24 entries per row
+    if (mean_row <= 3.0) return 1;
+    if (mean_row <= 32.0) return -64; // measured best for 6 to 24 entries per row
     if (mean_row <= 48.0) return -32;
-    return lanes_for_mean(mean_row);
+    if (mean_row <= 384.0) return lanes_for_mean(mean_row);
+    return kRowBlock;
 }
 
 // Time every candidate of each half on scratch output vectors (3 launches
@@ -876,7 +965,7 @@ hipError_t autotune(pdhg_solver *s)
     if (e == hipSuccess) e = hipMemcpyAsync(sx, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sxbar, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sy, s->y, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
-    const int cands[] = {-32, -64, -128, -256, -1032, -1064, 1, 2, 4, 8, 16, 32, 64};
+    const int cands[] = {-32, -64, -128, -256, -1032, -1064, 1, 2, 4, 8, 16, 32, 64, kRowBlock};
     void *keep[5] = {s->x, s->xbar, s->xp, s->y, s->yp};
     s->x = sx;
     s->xbar = sxbar;

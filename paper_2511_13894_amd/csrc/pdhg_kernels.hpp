@@ -73,13 +73,17 @@ __device__ __forceinline__ void dual_update(int64_t r, double h, double yr, doub
 
 // ------------------------------------------------- LDS-tiled short rows ---
 // A workgroup of NT threads owns a tile of T consecutive rows.  The tile's
-// entries stream through LDS in chunks of 8 NT: every thread loads entries
-// k, k+NT, ... with their gathered vector value (coalesced index and value
-// loads), writes the products to LDS, and G = NT/T threads per row sum their
-// row's products in a fixed order.  Row sums go to LDS and threads 0..T-1 run
-// the update epilogue on contiguous rows, with the epilogue's vector loads
-// issued before the product phase.
-constexpr int kChunk = 2048; // entries per LDS chunk of a 256-thread tile (8 per thread)
+// entries stream through LDS in chunks of kTileU * NT: every thread loads
+// entries k, k+NT, ..., k+(kTileU-1)NT (coalesced index and value loads), all
+// of them before their gathers and all gathers before the first product, so
+// the latencies of one thread's entries overlap instead of adding up.  The
+// tile's entry range comes from two uniform loads of the row pointers, so the
+// entry loads need not wait for the per-row pointers to reach LDS.  Products
+// go to LDS and G = NT/T threads per row sum their row's products in a fixed
+// order.  Row sums go to LDS and threads 0..T-1 run the update epilogue on
+// contiguous rows, with the epilogue's vector loads issued before the product
+// phase.
+constexpr int kTileU = 8; // entries per thread per chunk
 
 template <typename VM, typename VV, int T, int NT>
 __device__ __forceinline__ void tile_row_sums(int r0, int rows, const int *__restrict__ ptr,
@@ -88,19 +92,32 @@ __device__ __forceinline__ void tile_row_sums(int r0, int rows, const int *__res
                                               double *s_sum)
 {
     constexpr int G = NT / T;
-    constexpr int C = 8 * NT;
+    constexpr int C = kTileU * NT;
     const int tid = threadIdx.x;
+    const int beg = ptr[r0], end = ptr[r0 + rows]; // uniform across the workgroup
     for (int k = tid; k <= rows; k += NT) s_ptr[k] = ptr[r0 + k];
-    __syncthreads();
-    const int beg = s_ptr[0], end = s_ptr[rows];
     const int my_row = tid / G, sub = tid % G;
     const bool have = my_row < rows;
-    const int rb = have ? s_ptr[my_row] : 0, re = have ? s_ptr[my_row + 1] : 0;
     double acc = 0.0;
     for (int cs = beg; cs < end; cs += C) {
         const int ce = cs + C < end ? cs + C : end;
-        for (int k = cs + tid; k < ce; k += NT) s_prod[k - cs] = (double)val[k] * (double)vec[idx[k]];
-        __syncthreads();
+        int id[kTileU];
+        double v[kTileU], g[kTileU];
+#pragma unroll
+        for (int u = 0; u < kTileU; u++) {
+            const int k = cs + tid + u * NT;
+            id[u] = k < ce ? idx[k] : 0;
+            v[u] = k < ce ? (double)val[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kTileU; u++) g[u] = cs + tid + u * NT < ce ? (double)vec[id[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kTileU; u++) {
+            const int k = cs + tid + u * NT;
+            if (k < ce) s_prod[k - cs] = v[u] * g[u];
+        }
+        __syncthreads(); // products, and on the first chunk the row pointers
+        const int rb = have ? s_ptr[my_row] : 0, re = have ? s_ptr[my_row + 1] : 0;
         const int lo = rb > cs ? rb : cs, hi = re < ce ? re : ce;
         for (int q = lo + sub; q < hi; q += G) acc += s_prod[q - cs];
         __syncthreads();

@@ -1,0 +1,124 @@
+"""Parity at full size, in the launch configuration the benchmark uses (default
+parameters: kernels chosen from the mean row length, graph-replayed cycles,
+event timing on).  The oracle cannot finish these solves, so the checks are
+on what it can compute at any size: the setup (scaling, step size), the first
+iterates, the float64 KKT of the GPU's answer evaluated by the oracle's own
+code, and the push's fixing decisions recounted from that answer."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import OracleSolver
+from paper_2511_13894_amd import lpgen, pdhg
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_inf(a, b):
+    return float(np.abs(a - b).max() / max(1.0, np.abs(b).max())) if a.size else 0.0
+
+
+@pytest.fixture(scope="module")
+def c1():
+    print("[full] c1 100k x 400k: generate + oracle setup", flush=True)
+    lp = lpgen.config1()
+    return lp, OracleSolver(lp)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    print("[full] c2 7k x 10M: generate + oracle setup", flush=True)
+    lp = lpgen.config2()
+    return lp, OracleSolver(lp)
+
+
+def _setup_and_first_iterates(lp, o, iters):
+    g = pdhg.Solver(lp, timing=1)
+    sg, so = g.get_scaling(), o.scaling()
+    assert rel_inf(sg["dr"], so["dr"]) <= 1e-14
+    assert rel_inf(sg["dc"], so["dc"]) <= 1e-14
+    assert sg["power_steps"] == so["power_steps"]
+    assert abs(sg["eta"] - so["eta"]) <= 1e-13 * so["eta"]
+    for t in range(1, iters + 1):
+        g.iterate(1)
+        o.iterate(1)
+        xg, yg = g.get_iterate()
+        xo, yo = o.iterate_state()
+        print(f"[full] {lp.name} iterate {t}: x {rel_inf(xg, xo):.2e} y {rel_inf(yg, yo):.2e}", flush=True)
+        assert rel_inf(xg, xo) <= 1e-10 and rel_inf(yg, yo) <= 1e-10
+    return g
+
+
+def _z_of(lp, y):
+    """Reduced costs of the original model split by finite bounds (float64)."""
+    a = sp.csr_matrix((lp.val, lp.col, lp.row_ptr), shape=(lp.m, lp.n))
+    lam = lp.c - a.T @ y
+    lo_fin = np.isfinite(lp.l) & (np.abs(lp.l) < 1e20)
+    hi_fin = np.isfinite(lp.u) & (np.abs(lp.u) < 1e20)
+    zp = np.where(lo_fin & (lam > 0), lam, 0.0)
+    zm = np.where(hi_fin & (lam < 0), -lam, 0.0)
+    return zp - zm
+
+
+def test_c1_setup_iterates_solve_and_push(c1):
+    lp, o = c1
+    _setup_and_first_iterates(lp, o, 3)
+    g = pdhg.Solver(lp, timing=1)
+    r = g.solve()
+    x, y, z = g.get_solution()
+    k = o.kkt(x, y)
+    print(f"[full] c1 solve: {pdhg.STATUS[r.status]} {r.iters} iterations; GPU KKT {r.rel_p:.3e}/{r.rel_d:.3e}/"
+          f"{r.rel_gap:.3e}, oracle's evaluation {k.rel_p:.3e}/{k.rel_d:.3e}/{k.rel_gap:.3e}", flush=True)
+    assert r.status == pdhg.PDHG_OPTIMAL
+    assert max(k.rel_p, k.rel_d, k.rel_gap) <= 1e-6
+    # the relative measures come from sums over 400k terms (objectives near 200
+    # whose difference is the gap): equal up to 1e-12 in absolute terms
+    for a, b in ((r.rel_p, k.rel_p), (r.rel_d, k.rel_d), (r.rel_gap, k.rel_gap)):
+        assert abs(a - b) <= 1e-6 * b + 1e-12
+    assert abs(r.pobj - k.pobj) <= 1e-12 * max(1.0, abs(k.pobj))
+    # the push's fixing decisions, recounted from the solve's answer
+    zr = _z_of(lp, y)
+    np.testing.assert_allclose(z, zr, rtol=0, atol=1e-12 * max(1.0, np.abs(zr).max()))
+    p = g.corner_push(1)
+    assert p.status == pdhg.PDHG_PUSH_DONE and p.after.rel_p <= 1e-6
+    assert p.n_fix_upper == int(np.sum(zr > 1e-6)) and p.n_fix_lower == int(np.sum(zr < -1e-6))
+    ineq = np.asarray(lp.sense) != ord("=")
+    assert p.n_rows_to_eq == int(np.sum(ineq & (np.abs(y) > 1e-6)))
+    # the corner counts of the pushed point, evaluated by the oracle
+    xp, yp, _ = g.get_solution()
+    np.testing.assert_array_equal(yp, y)
+    ka = o.kkt(xp, yp)
+    print(f"[full] c1 push: {p.iters} iterations; off-bound {p.before.p_off} -> {p.after.p_off} (oracle {ka.p_off}),"
+          f" candidates {p.after.candidates} (oracle {ka.candidates}), primal push estimate {p.after.est_primal}",
+          flush=True)
+    assert (p.after.p_off, p.after.candidates, p.after.est_primal) == (ka.p_off, ka.candidates, ka.est_primal)
+    assert abs(p.after.pobj - ka.pobj) <= 1e-12 * max(1.0, abs(ka.pobj))
+
+
+def test_c2_setup_iterates_and_solve(c2):
+    lp, o = c2
+    _setup_and_first_iterates(lp, o, 2)
+    g = pdhg.Solver(lp, timing=1)
+    r = g.solve()
+    x, y, _ = g.get_solution()
+    k = o.kkt(x, y)
+    print(f"[full] c2 solve: {pdhg.STATUS[r.status]} {r.iters} iterations; GPU KKT {r.rel_p:.3e}/{r.rel_d:.3e}/"
+          f"{r.rel_gap:.3e}, oracle's evaluation {k.rel_p:.3e}/{k.rel_d:.3e}/{k.rel_gap:.3e}", flush=True)
+    assert r.status == pdhg.PDHG_OPTIMAL
+    assert max(k.rel_p, k.rel_d, k.rel_gap) <= 1e-6
+    assert abs(r.pobj - k.pobj) <= 1e-12 * max(1.0, abs(k.pobj))
+
+
+def test_batch_of_256_every_answer_checked_by_the_oracle():
+    lps = [lpgen.config3_instance(i) for i in range(256)]
+    print("[full] batch of 256 batched-family LPs, float64", flush=True)
+    b = pdhg.Batch(lps, timing=1)
+    res = b.solve()
+    worst = 0.0
+    for i in range(256):
+        assert res[i].status == pdhg.PDHG_OPTIMAL, (i, pdhg.STATUS[res[i].status])
+        x, y, _ = b.get_solution(i)
+        k = OracleSolver(lps[i], power_iters=1).kkt(x, y)  # the report needs only the original model
+        worst = max(worst, k.rel_p, k.rel_d, k.rel_gap)
+        assert max(k.rel_p, k.rel_d, k.rel_gap) <= 1e-6, i
+    print(f"[full] batch: all 256 OPTIMAL, worst float64 KKT by the oracle {worst:.3e}", flush=True)
