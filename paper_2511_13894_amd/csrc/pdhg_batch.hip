@@ -814,6 +814,8 @@ hipError_t batch_set_kernels(pdhg_batch *b, int kern_at, int kern_a)
         e = hipMemcpy(b->dtiles, dt.data(), sizeof(int4) * dt.size(), hipMemcpyHostToDevice);
     b->n_ptiles = (int)pt.size();
     b->n_dtiles = (int)dt.size();
+    b->ptiles_all = std::move(pt);
+    b->dtiles_all = std::move(dt);
     b->kern_at = kern_at;
     b->kern_a = kern_a;
     if (b->graph) {
@@ -821,6 +823,42 @@ hipError_t batch_set_kernels(pdhg_batch *b, int kern_at, int kern_a)
         b->graph = nullptr;
     }
     return e;
+}
+
+// Iteration tiles of the LPs still iterating (all = false) or of every LP
+// (all = true, at the start of a phase).  Tiles of a stopped LP exit at once,
+// but a launch over them still dispatches their workgroups: once a quarter
+// of the tiles in use belong to stopped LPs, the lists are rebuilt without
+// them (in place: the device buffers hold every tile) and the captured cycle
+// graph, whose launches carry the tile counts, is dropped.  Tile order does
+// not enter any LP's arithmetic.
+hipError_t batch_compact_tiles(pdhg_batch *b, bool all)
+{
+    std::vector<int4> pt, dt;
+    if (all) {
+        if (b->n_ptiles == (int)b->ptiles_all.size() && b->n_dtiles == (int)b->dtiles_all.size()) return hipSuccess;
+        pt = b->ptiles_all;
+        dt = b->dtiles_all;
+    } else {
+        for (const int4 &t : b->ptiles_all)
+            if (!b->sts_host[t.x].done) pt.push_back(t);
+        for (const int4 &t : b->dtiles_all)
+            if (!b->sts_host[t.x].done) dt.push_back(t);
+        if (pt.empty() || dt.empty()) return hipSuccess; // nothing left to run: the phase ends
+        if (4 * pt.size() > 3 * (size_t)b->n_ptiles && 4 * dt.size() > 3 * (size_t)b->n_dtiles) return hipSuccess;
+    }
+    hipStream_t st = b->s->stream;
+    hipError_t e = hipMemcpyAsync(b->ptiles, pt.data(), sizeof(int4) * pt.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->dtiles, dt.data(), sizeof(int4) * dt.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st); // the host vectors die on return
+    if (e != hipSuccess) return e;
+    b->n_ptiles = (int)pt.size();
+    b->n_dtiles = (int)dt.size();
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return hipSuccess;
 }
 
 // Time every tiled kernel on scratch output vectors and keep the fastest.

@@ -200,6 +200,7 @@ bool run_batch_phase(pdhg_batch *b, int64_t iters, int mode, double t0)
             bd += 4.0 * (mi + 1) + (4.0 + vbytes) * nz + (double)vbytes * ni + 33.0 * mi;
         }
     };
+    HIPCHK(batch_compact_tiles(b, true));
     while (b->t_host < target) {
         int enq = 0;
         bool events = false;
@@ -240,6 +241,7 @@ bool run_batch_phase(pdhg_batch *b, int64_t iters, int mode, double t0)
         bool all_done = true;
         for (int i = 0; i < b->count; i++) all_done = all_done && b->sts_host[i].done;
         if (all_done) break;
+        HIPCHK(batch_compact_tiles(b, false));
         if (s->p.time_limit > 0.0 && now_s() - t0 > s->p.time_limit) {
             time_out = true;
             break;

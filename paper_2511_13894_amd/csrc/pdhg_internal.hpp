@@ -161,7 +161,8 @@ struct pdhg_batch {
     std::vector<int64_t> nnz_of;           // entries of each LP
     int *d_coff = nullptr;                 // device copy of coff
     int4 *ptiles = nullptr, *dtiles = nullptr; // iteration tiles {lp, first row, rows, 0}
-    int n_ptiles = 0, n_dtiles = 0;
+    int n_ptiles = 0, n_dtiles = 0;        // tiles in use (only LPs still iterating after a compaction)
+    std::vector<int4> ptiles_all, dtiles_all; // every LP's iteration tiles (host copy)
     int kern_at = -64, kern_a = -64;       // tiled-kernel choice, pdhg_params.lanes_* encoding
     int4 *rn = nullptr, *rm = nullptr;     // 256-row reduction tiles of the column / row space
     int n_rn = 0, n_rm = 0;
@@ -209,6 +210,7 @@ hipError_t copy_probe(int64_t bytes, int reps, double *gbps);
 // batch engine (pdhg_batch.hip)
 hipError_t batch_setup(pdhg_batch *b);
 hipError_t batch_autotune(pdhg_batch *b);
+hipError_t batch_compact_tiles(pdhg_batch *b, bool all);
 hipError_t batch_set_kernels(pdhg_batch *b, int kern_at, int kern_a);
 hipError_t batch_phase_begin(pdhg_batch *b, bool fresh);
 hipError_t batch_iterations(pdhg_batch *b, int count, bool check_at_end, int mode, bool timed);
