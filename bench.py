@@ -30,6 +30,8 @@ WORKLOADS = {
            "zeros; seed 1)"),
     "c2": "transportation LP 2000 sources x 5000 sinks (n=10M arcs, m=7000 rows, integer data; seed 2)",
     "c0": "random sparse LP m=200 n=500 (5 nnz per column, planted degenerate optimum; seed 0)",
+    "c3": ("batch of 256 independent random sparse LPs, m log-uniform in [500, 20000], n = 2.5m, 4-8 nnz per "
+           "column, planted degenerate optima (seeds 3000+i)"),
 }
 
 
@@ -75,7 +77,97 @@ def cpu_baseline(lp, iters, cfg):
     o.iterate(iters)
     dt = time.perf_counter() - t0
     return {"value": iters / dt, "unit": "iter/s", "cores": num_threads(), "kind": "oracle",
-            "sample": f"{cfg} at full size, {iters} float64 PDHG iterations after setup ({dt:.1f} s)"}
+            "sample": f"{cfg}, {iters} float64 PDHG iterations after setup ({dt:.1f} s)"}
+
+
+def bench_batch(args, pdhg, copy_gbs):
+    """The batched family: one step = batch create + solve + corner push of all 256 LPs."""
+    from paper_2511_13894_amd import lpgen
+
+    lps = [lpgen.config3_instance(i) for i in range(256)]
+    seeds = [args.seed + i for i in range(len(lps))]
+    tot_m, tot_n, tot_nz = sum(l.m for l in lps), sum(l.n for l in lps), sum(l.nnz for l in lps)
+    print(f"[bench] c3: {len(lps)} LPs, {tot_m} rows, {tot_n} columns, {tot_nz} nonzeros", file=sys.stderr,
+          flush=True)
+
+    def step(timing):
+        b = pdhg.Batch(lps, precision=args.precision, timing=timing, use_graph=0 if args.no_graph else 1)
+        res = b.solve()
+        push = b.corner_push(seeds)
+        rep = b.report()
+        b.destroy()
+        return res, push, rep
+
+    for w in range(args.warmup):
+        res, push, _ = step(0)
+        print(f"[bench] warmup {w}: {sum(r.iters for r in res)} solve + {sum(p.iters for p in push)} push "
+              f"LP-iterations", file=sys.stderr, flush=True)
+    lp_iters, prim, dual, samples, bp, bd = 0, 0.0, 0.0, 0, 0.0, 0.0
+    details = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        res, push, rep = step(1)
+        te = time.perf_counter()
+        si, pi = sum(r.iters for r in res), sum(p.iters for p in push)
+        lp_iters += si + pi
+        prim += rep.primal_ms * rep.samples
+        dual += rep.dual_ms * rep.samples
+        bp += rep.bytes_primal * rep.samples
+        bd += rep.bytes_dual * rep.samples
+        samples += rep.samples
+        status = {}
+        for r in res:
+            status[pdhg.STATUS[r.status]] = status.get(pdhg.STATUS[r.status], 0) + 1
+        details.append({"step_s": te - ts, "solve_s": rep.solve_seconds, "push_s": rep.push_seconds,
+                        "solve_lp_iters": si, "push_lp_iters": pi, "solve_lockstep": rep.solve_lockstep_iters,
+                        "push_lockstep": rep.push_lockstep_iters, "solve_status": status,
+                        "off_bound_before": sum(p.before.p_off for p in push),
+                        "off_bound_after": sum(p.after.p_off for p in push),
+                        "est_primal_before": sum(p.before.est_primal for p in push),
+                        "est_primal_after": sum(p.after.est_primal for p in push),
+                        "kernels": [rep.lanes_at, rep.lanes_a]})
+        print(f"[bench] step {k}: {te - ts:.3f}s, {si} solve + {pi} push LP-iterations, status {status}",
+              file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t_start
+    n = max(samples, 1)
+    prim_ms, dual_ms, bytes_p, bytes_d = prim / n, dual / n, bp / n, bd / n
+    if prim_ms >= dual_ms:
+        kname, ms, nbytes, other = "kb_primal", prim_ms, bytes_p, ("kb_dual", dual_ms, bytes_d)
+    else:
+        kname, ms, nbytes, other = "kb_dual", dual_ms, bytes_d, ("kb_primal", prim_ms, bytes_p)
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(lp_iters / elapsed, 1), "unit": "LP-iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64norms", "data": "synthetic",
+        "config": {"workload": f"c3: {WORKLOADS['c3']}; step = batch create + solve to 1e-6 relative KKT + corner "
+                               "push of every LP", "lps": len(lps), "m": tot_m, "n": tot_n, "nnz": tot_nz,
+                   "precision": args.precision, "eps_rel": 1e-6},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+                     "launch_us": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": int(nbytes),
+                     "other_kernel": {"name": other[0], "launch_us": round(other[1] * 1e3, 2),
+                                      "algorithmic_bytes_per_launch": int(other[2])},
+                     "timed_launches": int(samples), "copy_probe_gbs": round(copy_gbs, 1)},
+        "detail": {"steps": details},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        from oracle import OracleSolver, num_threads
+
+        sample, it_each, dt = lps[:32], 2 * args.cpu_iters, 0.0
+        for lp in sample:
+            o = OracleSolver(lp, eps_rel=1e-30)
+            t0 = time.perf_counter()
+            o.iterate(it_each)
+            dt += time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": len(sample) * it_each / dt, "unit": "LP-iter/s", "cores": num_threads(),
+                               "kind": "oracle",
+                               "sample": f"the first {len(sample)} LPs of c3, {it_each} float64 PDHG iterations each "
+                                         f"after setup, one LP at a time ({dt:.1f} s)"}
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -101,11 +193,15 @@ def main():
     from paper_2511_13894_amd import pdhg
 
     t0 = time.perf_counter()
-    lp = make_lp(args.config)
+    lp = make_lp(args.config) if args.config != "c3" else None
     gen_s = time.perf_counter() - t0
-    print(f"[bench] {args.config} m={lp.m} n={lp.n} nnz={lp.nnz} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    if lp is not None:
+        print(f"[bench] {args.config} m={lp.m} n={lp.n} nnz={lp.nnz} generated in {gen_s:.1f}s", file=sys.stderr,
+              flush=True)
     copy_gbs = pdhg.copy_probe(1 << 30, 20)
     print(f"[bench] copy probe 1 GiB: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    if args.config == "c3":
+        return bench_batch(args, pdhg, copy_gbs)
 
     if args.iters_only:
         for k in range(args.steps):
@@ -181,7 +277,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(lp, args.cpu_iters, args.config)
+        out["cpu_baseline"] = cpu_baseline(lp, args.cpu_iters, f"{args.config} at full size")
     print(json.dumps(out), flush=True)
 
 

@@ -269,6 +269,46 @@ __global__ void kb_advance(DevState *sts, int count, int len)
     sts[i].k0 += len;
 }
 
+// products over the iteration tiles, skipping the LPs that have stopped:
+// by their DevState (checks) or by a per-LP flag (power iteration, skip[lp])
+template <typename VM, typename VV, int T, int NT>
+__global__ __launch_bounds__(NT) void kb_spmv(const int4 *__restrict__ tiles, const int *__restrict__ ptr,
+                                             const int *__restrict__ idx, const VM *__restrict__ val,
+                                             const VV *__restrict__ vec, double *__restrict__ out,
+                                             const DevState *__restrict__ sts, const double *__restrict__ skip)
+{
+    __shared__ int s_ptr[T + 1];
+    __shared__ double s_prod[kTileU * NT];
+    __shared__ double s_sum[T];
+    const int4 tl = tiles[xcd_block(blockIdx.x, gridDim.x)];
+    if (sts ? sts[tl.x].done != 0 : skip[tl.x] != 0.0) return; // uniform over the workgroup
+    tile_row_sums<VM, VV, T, NT>(tl.y, tl.z, ptr, idx, val, vec, s_ptr, s_prod, s_sum);
+    if ((int)threadIdx.x < tl.z) out[tl.y + threadIdx.x] = s_sum[threadIdx.x];
+}
+
+template <typename VM, typename VV>
+static void launch_spmv_b(pdhg_batch *b, int kern, const int4 *tiles, int ntiles, const int *ptr, const int *idx,
+                          const VM *val, const VV *vec, double *out, const double *skip = nullptr)
+{
+    if (ntiles <= 0) return;
+    hipStream_t st = b->s->stream;
+#define PDHG_BS_CASE(TT, RR, NT)                                                                               \
+    case TT:                                                                                                   \
+        hipLaunchKernelGGL((kb_spmv<VM, VV, RR, NT>), dim3(ntiles), dim3(NT), 0, st, tiles, ptr, idx, val, vec, \
+                           out, skip ? nullptr : b->sts, skip);                                               \
+        break;
+    switch (-kern) {
+        PDHG_BS_CASE(32, 32, 256)
+        PDHG_BS_CASE(128, 128, 256)
+        PDHG_BS_CASE(256, 256, 256)
+        PDHG_BS_CASE(1032, 32, 64)
+        PDHG_BS_CASE(1064, 64, 64)
+    default:
+        PDHG_BS_CASE(64, 64, 256)
+    }
+#undef PDHG_BS_CASE
+}
+
 template <typename V>
 static void check_b(pdhg_batch *b, int mode, int len)
 {
@@ -276,8 +316,8 @@ static void check_b(pdhg_batch *b, int mode, int len)
     hipStream_t st = s->stream;
     const V *xc = (const V *)(mode ? s->xp : s->x);
     const double *yc = (const double *)(mode ? s->yp : s->y);
-    spmv<V, V, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
-    spmv<V, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, (const V *)s->ahat_t, yc, s->aty);
+    launch_spmv_b<V, V>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
+    launch_spmv_b<V, double>(b, b->kern_at, b->ptiles, b->n_ptiles, s->tp, s->ti, (const V *)s->ahat_t, yc, s->aty);
     double *pm = b->part, *pn = b->part + (size_t)(Q_COUNT + 1) * b->n_rm;
     hipLaunchKernelGGL(kb_check_rows, dim3(b->n_rm), dim3(kBlock), 0, st, b->rm, s->ax, (const double *)s->bh, s->sense,
                        s->dr, yc, (const double *)s->ya, pm, b->n_rm, b->sts);
@@ -467,15 +507,17 @@ hipError_t batch_setup(pdhg_batch *b)
     for (int it = 0; it < s->p.power_iters && s->m > 0 && s->n > 0; it += kPowerBatch) {
         const int len = std::min(kPowerBatch, s->p.power_iters - it);
         for (int k = 0; k < len; k++) {
+            const double *pdone = b->lp_scalar + b->count; // LPs whose power iteration has stopped
             if (s->fp32) {
-                spmv<float, double, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, (const float *)s->ahat, v, u);
-                spmv<float, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, (const float *)s->ahat_t, u,
-                                                    w);
+                launch_spmv_b<float, double>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci,
+                                             (const float *)s->ahat, v, u, pdone);
+                launch_spmv_b<float, double>(b, b->kern_at, b->ptiles, b->n_ptiles, s->tp, s->ti,
+                                             (const float *)s->ahat_t, u, w, pdone);
             } else {
-                spmv<double, double, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, (const double *)s->ahat, v,
-                                                     u);
-                spmv<double, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, (const double *)s->ahat_t,
-                                                     u, w);
+                launch_spmv_b<double, double>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci,
+                                              (const double *)s->ahat, v, u, pdone);
+                launch_spmv_b<double, double>(b, b->kern_at, b->ptiles, b->n_ptiles, s->tp, s->ti,
+                                              (const double *)s->ahat_t, u, w, pdone);
             }
             hipLaunchKernelGGL((kb_sumsq<double>), dim3(b->n_rm), dim3(kBlock), 0, st, b->rm, u, pm);
             hipLaunchKernelGGL((kb_sumsq<double>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, w, pn);
@@ -750,6 +792,10 @@ static hipError_t push_setup_b(pdhg_batch *b, pdhg_push_result *out)
 hipError_t batch_push_setup(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *out)
 {
     b->s->model_original = false;
+    // every pushed LP iterates again: its tiles must be in the lists before the
+    // phase-start check below uses them
+    hipError_t ec = batch_compact_tiles(b, true);
+    if (ec != hipSuccess) return ec;
     hipError_t e = hipMemcpyAsync(b->seeds, seeds, sizeof(uint64_t) * (size_t)b->count, hipMemcpyHostToDevice,
                                   b->s->stream);
     if (e != hipSuccess) return e;

@@ -193,6 +193,9 @@ int fail(int code, const std::string &msg);
 hipError_t build_transpose(pdhg_solver *s);
 hipError_t scale_problem(pdhg_solver *s);
 hipError_t power_iteration(pdhg_solver *s);
+// out = Ahat vec (transpose = false) or Ahat' vec, float64, with the structure of
+// the iteration kernel of that half (the kernels must have been chosen)
+hipError_t solver_product(pdhg_solver *s, bool transpose, const double *vec, double *out);
 
 // iteration, checks, push and reports (pdhg_iter.hip)
 hipError_t init_iteration(pdhg_solver *s);

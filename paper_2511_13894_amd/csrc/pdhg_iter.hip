@@ -85,6 +85,81 @@ __device__ __forceinline__ double row_block_sum(int beg, int end, const int *__r
     return q[0];
 }
 
+// ---------------------------------------------------- check products ---
+// A check's products use the structure of the iteration kernel of the same
+// half (LDS tiles, one row per workgroup, or lane groups): they cost what an
+// iteration half costs, and an LP inside a batch (same tiles) gets the same
+// row sums as when it is solved alone.
+template <typename VM, typename VV, int T, int NT>
+__global__ __launch_bounds__(NT) void k_spmv_tiled(int rows_total, const int *__restrict__ ptr,
+                                                  const int *__restrict__ idx, const VM *__restrict__ val,
+                                                  const VV *__restrict__ vec, double *__restrict__ out)
+{
+    __shared__ int s_ptr[T + 1];
+    __shared__ double s_prod[kTileU * NT];
+    __shared__ double s_sum[T];
+    const int r0 = xcd_block(blockIdx.x, gridDim.x) * T;
+    const int rows = rows_total - r0 < T ? rows_total - r0 : T;
+    tile_row_sums<VM, VV, T, NT>(r0, rows, ptr, idx, val, vec, s_ptr, s_prod, s_sum);
+    if ((int)threadIdx.x < rows) out[r0 + threadIdx.x] = s_sum[threadIdx.x];
+}
+
+template <typename VM, typename VV>
+__global__ __launch_bounds__(kBlock) void k_spmv_rowblock(const int *__restrict__ ptr, const int *__restrict__ idx,
+                                                         const VM *__restrict__ val, const VV *__restrict__ vec,
+                                                         double *__restrict__ out)
+{
+    const int r = xcd_block(blockIdx.x, gridDim.x);
+    const double h = row_block_sum<VM, VV>(ptr[r], ptr[r + 1], idx, val, vec);
+    if (threadIdx.x == 0) out[r] = h;
+}
+
+// out = M vec (float64) with the kernel structure `kern` (lanes_* encoding)
+template <typename VM, typename VV>
+static void check_spmv(hipStream_t st, int kern, int rows, const int *ptr, const int *idx, const VM *val,
+                       const VV *vec, double *out)
+{
+    if (rows <= 0) return;
+    if (kern > 0) {
+        spmv<VM, VV, double, double>(st, kern, rows, ptr, idx, val, vec, out);
+        return;
+    }
+    if (kern == kRowBlock) {
+        hipLaunchKernelGGL((k_spmv_rowblock<VM, VV>), dim3(rows), dim3(kBlock), 0, st, ptr, idx, val, vec, out);
+        return;
+    }
+    const int T = -kern;
+    const int rows_per = T > 1000 ? T - 1000 : T;
+    const int grid = (rows + rows_per - 1) / rows_per;
+#define PDHG_CS_CASE(TT, RR, NT)                                                                                 \
+    case TT:                                                                                                     \
+        hipLaunchKernelGGL((k_spmv_tiled<VM, VV, RR, NT>), dim3(grid), dim3(NT), 0, st, rows, ptr, idx, val, vec, \
+                           out);                                                                                 \
+        break;
+    switch (T) {
+        PDHG_CS_CASE(32, 32, 256)
+        PDHG_CS_CASE(64, 64, 256)
+        PDHG_CS_CASE(128, 128, 256)
+        PDHG_CS_CASE(1032, 32, 64)
+        PDHG_CS_CASE(1064, 64, 64)
+    default:
+        PDHG_CS_CASE(256, 256, 256)
+    }
+#undef PDHG_CS_CASE
+}
+
+hipError_t solver_product(pdhg_solver *s, bool transpose, const double *vec, double *out)
+{
+    if (transpose) {
+        if (s->fp32) check_spmv<float, double>(s->stream, s->kern_at, s->n, s->tp, s->ti, (const float *)s->ahat_t, vec, out);
+        else check_spmv<double, double>(s->stream, s->kern_at, s->n, s->tp, s->ti, (const double *)s->ahat_t, vec, out);
+    } else {
+        if (s->fp32) check_spmv<float, double>(s->stream, s->kern_a, s->m, s->rp, s->ci, (const float *)s->ahat, vec, out);
+        else check_spmv<double, double>(s->stream, s->kern_a, s->m, s->rp, s->ci, (const double *)s->ahat, vec, out);
+    }
+    return hipGetLastError();
+}
+
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_primal_rowblock(int n, const int *__restrict__ tp,
                                                            const int *__restrict__ ti, const V *__restrict__ atv,
@@ -435,8 +510,8 @@ template <typename V>
 static void check_impl(pdhg_solver *s, const V *xc, const double *yc, double *pm, double *pn)
 {
     hipStream_t st = s->stream;
-    spmv<V, V, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
-    spmv<V, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, (const V *)s->ahat_t, yc, s->aty);
+    check_spmv<V, V>(st, s->kern_a, s->m, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
+    check_spmv<V, double>(st, s->kern_at, s->n, s->tp, s->ti, (const V *)s->ahat_t, yc, s->aty);
     const int gm = s->red_blocks_m, gn = s->red_blocks_n;
     hipLaunchKernelGGL(k_check_rows, dim3(gm), dim3(kBlock), 0, st, s->m, s->ax, (const double *)s->bh, s->sense, s->dr,
                        yc, (const double *)s->ya, pm, gm, s->st);

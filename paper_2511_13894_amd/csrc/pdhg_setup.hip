@@ -418,15 +418,8 @@ hipError_t power_iteration(pdhg_solver *s)
     for (int it = 0; it < s->p.power_iters && n > 0 && m > 0; it += kPowerBatch) {
         const int len = std::min(kPowerBatch, s->p.power_iters - it);
         for (int k = 0; k < len; k++) {
-            if (s->fp32) {
-                spmv<float, double, double, double>(st, s->lanes_a, m, s->rp, s->ci, (const float *)s->ahat, v, u);
-                spmv<float, double, double, double>(st, s->lanes_at, n, s->tp, s->ti, (const float *)s->ahat_t, u,
-                                                    w);
-            } else {
-                spmv<double, double, double, double>(st, s->lanes_a, m, s->rp, s->ci, (const double *)s->ahat, v, u);
-                spmv<double, double, double, double>(st, s->lanes_at, n, s->tp, s->ti, (const double *)s->ahat_t, u,
-                                                     w);
-            }
+            (void)solver_product(s, false, v, u);
+            (void)solver_product(s, true, u, w);
             hipLaunchKernelGGL(k_sumsq_partials, dim3(gm), dim3(kBlock), 0, st, m, u, s->partials);
             hipLaunchKernelGGL(k_sumsq_partials, dim3(gn), dim3(kBlock), 0, st, n, w, s->partials + gm);
             hipLaunchKernelGGL(k_power_finish, dim3(1), dim3(kBlock), 0, st, gm, gn, s->partials, s->p.power_tol, pw);

@@ -24,12 +24,15 @@ import numpy as np
 from . import lpgen, pdhg
 
 
+USE_GRAPH = 1  # 0: every cycle launched eagerly (profiler runs)
+
+
 def solve_and_label(lp, seed, precision="fp64", eps=1e-6, eps_abs=1e-6):
     """(features, labels, mask, solve result, push result) of one LP, or None.
 
     The mask selects the columns a learned fix may touch: left free by the
     plain rule (|z_j| <= eps_abs) and bounded on at least one side."""
-    s = pdhg.Solver(lp, precision=precision, record_history=1, eps_rel=eps, eps_abs=eps_abs)
+    s = pdhg.Solver(lp, precision=precision, record_history=1, eps_rel=eps, eps_abs=eps_abs, use_graph=USE_GRAPH)
     r = s.solve()
     if r.status != pdhg.PDHG_OPTIMAL:
         return None
@@ -84,7 +87,8 @@ def choose_theta(rows, min_precision=0.95):
 def time_to_corner(lp, seed, precision="fp64", net=None, theta=0.9, eps=1e-6):
     """create + solve + push wall time, and the corner statistics."""
     t0 = time.perf_counter()
-    s = pdhg.Solver(lp, precision=precision, record_history=1 if net is not None else 0, eps_rel=eps)
+    s = pdhg.Solver(lp, precision=precision, record_history=1 if net is not None else 0, eps_rel=eps,
+                    use_graph=USE_GRAPH)
     r = s.solve()
     if r.status != pdhg.PDHG_OPTIMAL:
         return None
@@ -109,7 +113,10 @@ def main(argv=None):
     ap.add_argument("--mcf", default="", help="nodes,arcs,commodities of a multicommodity evaluation LP")
     ap.add_argument("--mcf-precision", default="fp32", choices=["fp64", "fp32"])
     ap.add_argument("--mcf-seeds", type=int, default=1)
+    ap.add_argument("--no-graph", action="store_true", help="launch every cycle eagerly (profiler runs)")
     args = ap.parse_args(argv)
+    global USE_GRAPH
+    USE_GRAPH = 0 if args.no_graph else 1
     log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
     rng_range = (args.m_lo, args.m_hi)
     tr = [lpgen.config3_instance(i, base_seed=40000, m_range=rng_range) for i in range(args.train)]
