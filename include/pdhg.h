@@ -360,6 +360,22 @@ int pdhg_features(pdhg_solver *s, uint64_t seed, float *out);
  * for theta outside (0, 1). */
 int pdhg_corner_push_learned(pdhg_solver *s, pdhg_mlp *net, double theta, uint64_t seed, pdhg_push_result *r);
 
+/* The features of pdhg_features for every LP of a solved batch (before its
+ * push), each LP normalised over its own columns and drawing the push
+ * objective of seeds[i] (count seeds, host): out[total_n x 16] (host),
+ * LPs in batch order, or NULL to only compute them.  The trend features
+ * need params.record_history = 1 at pdhg_batch_create.  Errors: INVALID_ARG
+ * (NULL seeds), STATE before the solve or after the push. */
+int pdhg_batch_features(pdhg_batch *b, const uint64_t *seeds, float *out);
+
+/* pdhg_batch_corner_push with the learned warm start of
+ * pdhg_corner_push_learned applied to every LP of the batch (the same
+ * rules, per LP); results[i].n_learned_fix / n_learned_undo count LP i's
+ * fixes and undos.  Errors as pdhg_batch_corner_push, and INVALID_ARG for
+ * theta outside (0, 1) or a NULL network. */
+int pdhg_batch_corner_push_learned(pdhg_batch *b, pdhg_mlp *net, double theta, const uint64_t *seeds,
+                                   pdhg_push_result *results);
+
 /* Release all device memory of the handle (NULL is a no-op). */
 void pdhg_destroy(pdhg_solver *s);
 

@@ -326,6 +326,8 @@ static void check_b(pdhg_batch *b, int mode, int len)
                        s->model_original ? 1 : 0, pn, b->n_rn, b->sts);
     hipLaunchKernelGGL(kb_check_final, dim3(b->count), dim3(kBlock), 0, st, b->sts, pm, b->n_rm, pn, b->n_rn,
                        b->rm_start, b->rn_start, mode, len);
+    if (mode == 1 && s->hx) (void)batch_record_history(b); // before the restart copies
+    if (mode == 2 && s->learned_active) (void)batch_learned_undo(b);
     if (mode != 0)
         hipLaunchKernelGGL((kb_restart_apply<V>), dim3(b->n_rn + b->n_rm), dim3(kBlock), 0, st, b->rn, b->n_rn, b->rm,
                            b->sts, (V *)s->x, (V *)s->xa, (const V *)s->xp, (double *)s->y, (double *)s->ya,
@@ -766,7 +768,7 @@ __global__ __launch_bounds__(kBlock) void kb_push_final(const double *__restrict
 }
 
 template <typename V>
-static hipError_t push_setup_b(pdhg_batch *b, pdhg_push_result *out)
+static hipError_t push_setup_b(pdhg_batch *b, pdhg_push_result *out, double theta)
 {
     pdhg_solver *s = b->s;
     hipStream_t st = s->stream;
@@ -776,6 +778,10 @@ static hipError_t push_setup_b(pdhg_batch *b, pdhg_push_result *out)
                        s->ch, (V *)s->x, pn, b->n_rn);
     hipLaunchKernelGGL(kb_push_rows, dim3(b->n_rm), dim3(kBlock), 0, st, b->rm, b->active, s->yu, s->p.eps_abs,
                        s->sense, (double *)s->y, pm);
+    if (theta > 0.0) { // learned warm start on the columns the plain rule leaves free
+        hipError_t el = batch_learned_fix(b, theta);
+        if (el != hipSuccess) return el;
+    }
     hipLaunchKernelGGL(kb_push_final, dim3(b->count), dim3(kBlock), 0, st, pn, b->n_rn, pm, b->rm_start, b->rn_start,
                        b->rep);
     hipMemcpyAsync(b->rep_host, b->rep, sizeof(double) * R_COUNT * (size_t)b->count, hipMemcpyDeviceToHost, st);
@@ -789,7 +795,7 @@ static hipError_t push_setup_b(pdhg_batch *b, pdhg_push_result *out)
     return phase_begin_b<V>(b, false);
 }
 
-hipError_t batch_push_setup(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *out)
+hipError_t batch_push_setup(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *out, double theta)
 {
     b->s->model_original = false;
     // every pushed LP iterates again: its tiles must be in the lists before the
@@ -799,7 +805,7 @@ hipError_t batch_push_setup(pdhg_batch *b, const uint64_t *seeds, pdhg_push_resu
     hipError_t e = hipMemcpyAsync(b->seeds, seeds, sizeof(uint64_t) * (size_t)b->count, hipMemcpyHostToDevice,
                                   b->s->stream);
     if (e != hipSuccess) return e;
-    return b->s->fp32 ? push_setup_b<float>(b, out) : push_setup_b<double>(b, out);
+    return b->s->fp32 ? push_setup_b<float>(b, out, theta) : push_setup_b<double>(b, out, theta);
 }
 
 // LPs whose push made no check (or did not run) keep the solve's x

@@ -253,7 +253,7 @@ bool run_batch_phase(pdhg_batch *b, int64_t iters, int mode, double t0)
 void free_batch(pdhg_batch *b)
 {
     void *ptrs[] = {b->d_coff, b->ptiles, b->dtiles, b->rn, b->rm, b->rn_start, b->rm_start, b->sts,
-                    b->part, b->lp_scalar, b->rep, b->active, b->seeds};
+                    b->part, b->lp_scalar, b->rep, b->active, b->seeds, b->fpart, b->fscale};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (b->sts_host) (void)hipHostFree(b->sts_host);
@@ -942,7 +942,22 @@ int pdhg_batch_solve(pdhg_batch *b, pdhg_result *results)
     return PDHG_OK;
 }
 
-int pdhg_batch_corner_push(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *results)
+// learned-part buffers of a batch (allocated on first use)
+static void batch_learned_buffers(pdhg_batch *b)
+{
+    pdhg_solver *s = b->s;
+    const size_t n = (size_t)(s->n > 0 ? s->n : 1);
+    if (!s->feat_raw) dalloc(&s->feat_raw, 16 * n);
+    if (!s->feat_b) dalloc(&s->feat_b, 16 * n);
+    if (!s->logits) dalloc(&s->logits, n);
+    if (!s->lfix) dalloc(&s->lfix, n);
+    if (!s->lcount) dalloc(&s->lcount, 2 * (size_t)b->count);
+    if (!b->fpart) dalloc(&b->fpart, 16 * (size_t)(b->n_rn > 0 ? b->n_rn : 1));
+    if (!b->fscale) dalloc(&b->fscale, 16 * (size_t)b->count);
+}
+
+static int batch_push_common(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *results, pdhg_mlp *net,
+                             double theta)
 {
     if (!b || !seeds || !results) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
     if (!b->solved || b->pushed) return fail(PDHG_ERR_STATE, "corner push needs a batch solve first (and runs once)");
@@ -960,7 +975,15 @@ int pdhg_batch_corner_push(pdhg_batch *b, const uint64_t *seeds, pdhg_push_resul
         std::vector<int> solve_status((size_t)b->count);
         for (int i = 0; i < b->count; i++) solve_status[i] = b->sts_host[i].status;
         HIPCHK(hipMemcpy(b->active, b->active_host.data(), sizeof(int) * (size_t)b->count, hipMemcpyHostToDevice));
-        HIPCHK(batch_push_setup(b, seeds, results));
+        if (net) { // predictor on every LP's solve state, before the models change
+            batch_learned_buffers(b);
+            HIPCHK(hipMemsetAsync(s->lcount, 0, 2 * sizeof(unsigned) * (size_t)b->count, st));
+            HIPCHK(hipMemcpyAsync(b->seeds, seeds, sizeof(uint64_t) * (size_t)b->count, hipMemcpyHostToDevice, st));
+            HIPCHK(batch_compute_features(b));
+            HIPCHK(mlp_forward(net, st, s->feat_b, s->n, s->logits));
+        }
+        HIPCHK(batch_push_setup(b, seeds, results, net ? theta : -1.0));
+        s->learned_active = net != nullptr;
         b->t_host = 0;
         b->next_check = s->p.push_min_iters;
         const bool time_out = run_batch_phase(b, s->p.push_max_iter, 2, t0);
@@ -986,7 +1009,48 @@ int pdhg_batch_corner_push(pdhg_batch *b, const uint64_t *seeds, pdhg_push_resul
             r.restarts = d.restarts;
             r.rel_p_push = d.checks > 0 ? d.rel_p : NAN;
         }
+        if (net) {
+            std::vector<unsigned> cnt(2 * (size_t)b->count);
+            HIPCHK(hipMemcpy(cnt.data(), s->lcount, sizeof(unsigned) * cnt.size(), hipMemcpyDeviceToHost));
+            for (int i = 0; i < b->count; i++) {
+                results[i].n_learned_fix = cnt[2 * (size_t)i];
+                results[i].n_learned_undo = cnt[2 * (size_t)i + 1];
+            }
+        }
+        s->learned_active = false;
         b->pushed = true;
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_batch_corner_push(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *results)
+{
+    return batch_push_common(b, seeds, results, nullptr, -1.0);
+}
+
+int pdhg_batch_corner_push_learned(pdhg_batch *b, pdhg_mlp *net, double theta, const uint64_t *seeds,
+                                   pdhg_push_result *results)
+{
+    if (!net) return fail(PDHG_ERR_INVALID_ARG, "NULL network");
+    if (!(theta > 0.0 && theta < 1.0)) return fail(PDHG_ERR_INVALID_ARG, "theta must lie in (0, 1)");
+    return batch_push_common(b, seeds, results, net, theta);
+}
+
+int pdhg_batch_features(pdhg_batch *b, const uint64_t *seeds, float *out)
+{
+    if (!b || !seeds) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    if (!b->solved || b->pushed) return fail(PDHG_ERR_STATE, "features describe a solved batch before its push");
+    try {
+        pdhg_solver *s = b->s;
+        batch_learned_buffers(b);
+        HIPCHK(hipMemcpyAsync(b->seeds, seeds, sizeof(uint64_t) * (size_t)b->count, hipMemcpyHostToDevice, s->stream));
+        HIPCHK(batch_compute_features(b));
+        if (out)
+            HIPCHK(hipMemcpyAsync(out, s->feat_raw, sizeof(float) * 16 * (size_t)s->n, hipMemcpyDeviceToHost,
+                                  s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
     } catch (const HipFailure &f) {
         return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
     }

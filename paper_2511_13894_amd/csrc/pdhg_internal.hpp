@@ -138,7 +138,7 @@ struct pdhg_solver {
     // learned push: restart history (4 slots of x and z, scaled), features,
     // per-column learned-fix flags (1 lower, 2 upper) and counters
     float *hx = nullptr, *hz = nullptr;
-    float *feat_raw = nullptr;   // n x 12
+    float *feat_raw = nullptr;   // n x 16
     short *feat_b = nullptr;     // n x 16 bfloat16
     float *logits = nullptr;     // n
     int8_t *lfix = nullptr;      // n
@@ -174,6 +174,7 @@ struct pdhg_batch {
     int *active = nullptr;                 // per-LP flag: takes part in the current phase
     std::vector<int> active_host;
     uint64_t *seeds = nullptr;
+    double *fpart = nullptr, *fscale = nullptr; // feature sums per column tile (16 x n_rn), scales per LP (16 x count)
     hipGraphExec_t graph = nullptr;
     int graph_len = 0, graph_mode = -1;
     int64_t t_host = 0, next_check = 0;
@@ -219,7 +220,7 @@ hipError_t batch_phase_begin(pdhg_batch *b, bool fresh);
 hipError_t batch_iterations(pdhg_batch *b, int count, bool check_at_end, int mode, bool timed);
 hipError_t batch_capture_cycle(pdhg_batch *b, int len, int mode);
 hipError_t batch_report(pdhg_batch *b, const double *x, const double *y, double *z, pdhg_kkt_report *out);
-hipError_t batch_push_setup(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *out);
+hipError_t batch_push_setup(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *out, double theta);
 hipError_t batch_keep_unpushed(pdhg_batch *b);
 
 // learned push (pdhg_learned.hip)
@@ -227,6 +228,12 @@ hipError_t launch_record_history(pdhg_solver *s);
 hipError_t launch_learned_undo(pdhg_solver *s);
 hipError_t compute_features(pdhg_solver *s, uint64_t seed);
 hipError_t launch_learned_fix(pdhg_solver *s, double theta);
+// the learned warm start for every LP of a batch (per-LP history, features,
+// scales and counters over the column reduction tiles)
+hipError_t batch_record_history(pdhg_batch *b);
+hipError_t batch_compute_features(pdhg_batch *b);
+hipError_t batch_learned_fix(pdhg_batch *b, double theta);
+hipError_t batch_learned_undo(pdhg_batch *b);
 int choose_kernel(double mean_row);
 hipError_t autotune(pdhg_solver *s);
 

@@ -62,6 +62,50 @@ def build_dataset(lps, seeds, precision="fp64", log=None):
     return np.concatenate(feats), np.concatenate(labels)
 
 
+def build_dataset_batched(lps, seeds, precision="fp64", eps=1e-6, eps_abs=1e-6):
+    """The same data, produced by the batch engine: every LP solved, its
+    features read and its plain push run in one batch."""
+    b = pdhg.Batch(lps, precision=precision, record_history=1, eps_rel=eps, eps_abs=eps_abs, use_graph=USE_GRAPH)
+    res = b.solve()
+    feats = b.features(seeds)
+    zs = []
+    for i in range(len(lps)):
+        zs.append(b.get_solution(i)[2])
+    b.corner_push(seeds)
+    fs, ys = [], []
+    for i, lp in enumerate(lps):
+        if res[i].status != pdhg.PDHG_OPTIMAL:
+            continue
+        x = b.get_solution(i)[0]
+        at_bound = (x - lp.l <= 1e-6) | (lp.u - x <= 1e-6)
+        mask = (np.abs(zs[i]) <= eps_abs) & (np.isfinite(lp.l) | np.isfinite(lp.u))
+        fs.append(feats[i][mask])
+        ys.append(at_bound[mask].astype(np.float32))
+    b.destroy()
+    return np.concatenate(fs), np.concatenate(ys)
+
+
+def batch_time_to_corner(lps, seeds, precision="fp64", net=None, theta=0.9, eps=1e-6):
+    """create + solve + push of the whole batch, plain or learned."""
+    t0 = time.perf_counter()
+    b = pdhg.Batch(lps, precision=precision, record_history=1 if net is not None else 0, eps_rel=eps,
+                   use_graph=USE_GRAPH)
+    res = b.solve()
+    push = b.corner_push(seeds) if net is None else b.corner_push_learned(net, theta, seeds)
+    dt = time.perf_counter() - t0
+    rep = b.report()
+    b.destroy()
+    ok = [i for i, r in enumerate(res) if r.status == pdhg.PDHG_OPTIMAL]
+    return {"seconds": dt, "push_lockstep": rep.push_lockstep_iters, "solve_lockstep": rep.solve_lockstep_iters,
+            "push_lp_iters": sum(push[i].iters for i in ok), "push_done": sum(push[i].status == pdhg.PDHG_PUSH_DONE
+                                                                              for i in ok),
+            "est_primal_after": sum(push[i].after.est_primal for i in ok),
+            "candidates_after": sum(push[i].after.candidates for i in ok),
+            "off_bound_after": sum(push[i].after.p_off for i in ok),
+            "learned_fix": sum(push[i].n_learned_fix for i in ok),
+            "learned_undo": sum(push[i].n_learned_undo for i in ok), "optimal": len(ok)}
+
+
 THETAS = (0.5, 0.6, 0.7, 0.8, 0.85, 0.9, 0.95, 0.98, 0.99, 0.995, 0.999)
 
 
@@ -114,6 +158,8 @@ def main(argv=None):
     ap.add_argument("--mcf-precision", default="fp32", choices=["fp64", "fp32"])
     ap.add_argument("--mcf-seeds", type=int, default=1)
     ap.add_argument("--no-graph", action="store_true", help="launch every cycle eagerly (profiler runs)")
+    ap.add_argument("--batched", action="store_true",
+                    help="training data from the batch engine, and learned+batched vs plain batched push")
     args = ap.parse_args(argv)
     global USE_GRAPH
     USE_GRAPH = 0 if args.no_graph else 1
@@ -122,8 +168,14 @@ def main(argv=None):
     tr = [lpgen.config3_instance(i, base_seed=40000, m_range=rng_range) for i in range(args.train)]
     va = [lpgen.config3_instance(i, base_seed=42000, m_range=rng_range) for i in range(args.val)]
     ev = [lpgen.config3_instance(i, base_seed=43000, m_range=rng_range) for i in range(args.eval)]
-    f, y = build_dataset(tr, [17 + i for i in range(len(tr))], args.precision, log)
-    fv, yv = build_dataset(va, [91 + i for i in range(len(va))], args.precision, log)
+    t_data = time.time()
+    if args.batched:
+        f, y = build_dataset_batched(tr, [17 + i for i in range(len(tr))], args.precision)
+        fv, yv = build_dataset_batched(va, [91 + i for i in range(len(va))], args.precision)
+    else:
+        f, y = build_dataset(tr, [17 + i for i in range(len(tr))], args.precision, log)
+        fv, yv = build_dataset(va, [91 + i for i in range(len(va))], args.precision, log)
+    log(f"[learned] data generation {time.time() - t_data:.1f}s ({'batch engine' if args.batched else 'one LP at a time'})")
     log(f"[learned] train {f.shape[0]} free columns ({y.mean():.3f} end at a bound), val {fv.shape[0]}")
     net = pdhg.Mlp(seed=7)
     rep = net.train(f, y, epochs=args.epochs, batch=4096, lr=1e-3, seed=3)
@@ -140,6 +192,16 @@ def main(argv=None):
     if theta is None:
         print(json.dumps(out))
         return
+    if args.batched:
+        sd = [500 + i for i in range(len(ev))]
+        plain = batch_time_to_corner(ev, sd, args.precision)
+        lrn = batch_time_to_corner(ev, sd, args.precision, net, theta)
+        out["batched_eval"] = {"lps": len(ev), "plain": plain, "learned": lrn}
+        log(f"[learned] batched: {len(ev)} LPs, time to corner {plain['seconds']:.3f}s -> {lrn['seconds']:.3f}s, push "
+            f"lockstep {plain['push_lockstep']} -> {lrn['push_lockstep']}, push LP-iterations {plain['push_lp_iters']} "
+            f"-> {lrn['push_lp_iters']}, primal push estimate {plain['est_primal_after']} -> "
+            f"{lrn['est_primal_after']}, candidates {plain['candidates_after']} -> {lrn['candidates_after']}, "
+            f"learned fixes {lrn['learned_fix']} (undone {lrn['learned_undo']})")
     cases = [(lambda lp=lp: lp, 500 + i, args.precision) for i, lp in enumerate(ev)]
     if args.mcf:
         nn, na, nk = (int(v) for v in args.mcf.split(","))

@@ -121,6 +121,7 @@ EXPORTS = ["pdhg_default_params", "pdhg_create", "pdhg_solve", "pdhg_iterate", "
            "pdhg_batch_corner_push", "pdhg_batch_get_solution", "pdhg_batch_get_report", "pdhg_batch_destroy",
            "pdhg_mlp_create", "pdhg_mlp_destroy", "pdhg_mlp_set_params", "pdhg_mlp_get_params", "pdhg_mlp_forward",
            "pdhg_mlp_gradient", "pdhg_default_train_params", "pdhg_mlp_train", "pdhg_features",
+           "pdhg_batch_features", "pdhg_batch_corner_push_learned",
            "pdhg_corner_push_learned"]
 
 _lib = None
@@ -172,6 +173,8 @@ def load(path: Optional[Path] = None):
     lib.pdhg_mlp_train.argtypes = [C.c_void_p, fp, fp, C.c_int64, P(TrainParams), P(TrainReport)]
     lib.pdhg_features.argtypes = [C.c_void_p, C.c_uint64, fp]
     lib.pdhg_corner_push_learned.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_uint64, P(PushResult)]
+    lib.pdhg_batch_features.argtypes = [C.c_void_p, P(C.c_uint64), fp]
+    lib.pdhg_batch_corner_push_learned.argtypes = [C.c_void_p, C.c_void_p, C.c_double, P(C.c_uint64), P(PushResult)]
     lib.pdhg_last_error.restype = C.c_char_p
     lib.pdhg_struct_size.restype = C.c_int32
     lib.pdhg_struct_size.argtypes = [C.c_int32]
@@ -179,7 +182,8 @@ def load(path: Optional[Path] = None):
                "pdhg_get_iterate", "pdhg_get_scaling", "pdhg_get_timing", "pdhg_copy_probe", "pdhg_batch_create",
                "pdhg_batch_solve", "pdhg_batch_corner_push", "pdhg_batch_get_solution", "pdhg_batch_get_report",
                "pdhg_mlp_create", "pdhg_mlp_set_params", "pdhg_mlp_get_params", "pdhg_mlp_forward",
-               "pdhg_mlp_gradient", "pdhg_mlp_train", "pdhg_features", "pdhg_corner_push_learned"):
+               "pdhg_mlp_gradient", "pdhg_mlp_train", "pdhg_features", "pdhg_corner_push_learned",
+               "pdhg_batch_features", "pdhg_batch_corner_push_learned"):
         getattr(lib, fn).restype = C.c_int
     sizes = [C.sizeof(Params), C.sizeof(Result), C.sizeof(KKTReport), C.sizeof(PushResult), C.sizeof(Timing),
              C.sizeof(LpDesc), C.sizeof(BatchReport)]
@@ -381,6 +385,24 @@ class Batch:
         r = (PushResult * self.count)()
         self._check(self.lib.pdhg_batch_corner_push(self.h, sd, r))
         return list(r)
+
+    def corner_push_learned(self, net, theta: float, seeds):
+        sd = (C.c_uint64 * self.count)(*[int(v) for v in seeds])
+        r = (PushResult * self.count)()
+        self._check(self.lib.pdhg_batch_corner_push_learned(self.h, net.h, float(theta), sd, r))
+        return list(r)
+
+    def features(self, seeds):
+        """Per-LP feature arrays (n_i x 16) of the solved batch."""
+        sd = (C.c_uint64 * self.count)(*[int(v) for v in seeds])
+        n = sum(int(lp.n) for lp in self.lps)
+        f = np.zeros((n, 16), dtype=np.float32)
+        self._check(self.lib.pdhg_batch_features(self.h, sd, f.ctypes.data_as(C.POINTER(C.c_float))))
+        out, k = [], 0
+        for lp in self.lps:
+            out.append(f[k:k + lp.n])
+            k += lp.n
+        return out
 
     def get_solution(self, i):
         lp = self.lps[i]

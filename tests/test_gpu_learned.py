@@ -92,3 +92,30 @@ def test_pipeline_trains_and_compares():
         assert b["push_status"] in ("PUSH_DONE", "ITER_LIMIT")
         if b["push_status"] == "PUSH_DONE":
             assert b["rel_p_after"] <= 1.0000001e-6
+
+
+def test_batch_features_and_learned_push_match_single_lp_runs():
+    """Inside a batch (same kernels), an LP's features equal those of the LP
+    solved alone, and the learned push fixes the same columns; every push
+    still ends primal feasible."""
+    lps = [lpgen.config3_instance(i, base_seed=46000, m_range=(60, 200)) for i in range(4)]
+    seeds = [11 + i for i in range(4)]
+    kw = dict(record_history=1, eps_rel=1e-7, lanes_at=-1064, lanes_a=-1064)
+    b = pdhg.Batch(lps, **kw)
+    b.solve()
+    fb = b.features(seeds)
+    net = pdhg.Mlp(4)
+    push = b.corner_push_learned(net, 1e-4, seeds)
+    for i in (0, 2):
+        g = pdhg.Solver(lps[i], **kw)
+        g.solve()
+        fg = g.features(seeds[i])
+        np.testing.assert_allclose(fb[i], fg, rtol=0, atol=2e-6)
+        p = g.corner_push_learned(net, 1e-4, seeds[i])
+        print(f"[learned] batch LP {i}: fixes {push[i].n_learned_fix} (alone {p.n_learned_fix}), undone "
+              f"{push[i].n_learned_undo} (alone {p.n_learned_undo}), push iters {push[i].iters} (alone {p.iters})",
+              flush=True)
+        assert push[i].n_learned_fix == p.n_learned_fix > 0
+    for i, p in enumerate(push):
+        assert p.status == pdhg.PDHG_PUSH_DONE, (i, pdhg.STATUS[p.status])
+        assert p.after.rel_p <= 1.0000001e-7
