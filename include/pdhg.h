@@ -103,6 +103,9 @@ typedef struct pdhg_params {
                               -32/-64/-128/-256: LDS tile of that many rows, 256
                               threads; -1032/-1064: tile of 32/64 rows, 64 threads;
                               -2256: one row per workgroup of 256 threads (long rows);
+                              -3032 (lanes_a only): sliced ELLPACK, 32-row slices with
+                              interleaved entries (long rows whose columns advance
+                              together, e.g. the sinks of a transportation model);
                               0 = chosen from the mean row length                      */
     int32_t lanes_a;       /* dual-half kernel, same encoding                           */
     int32_t use_graph;     /* 1: replay check cycles from a captured hipGraph (default) */
@@ -208,6 +211,31 @@ int pdhg_get_solution(pdhg_solver *s, double *x, double *y, double *z);
 
 /* Current PDHG iterate (x, y) of the running phase, unscaled. */
 int pdhg_get_iterate(pdhg_solver *s, double *x, double *y);
+
+/* pdhg_get_solution into caller-owned device buffers (n, m, n doubles, any
+ * may be NULL), copied on the solver's stream; `stream` (a hipStream_t, or
+ * NULL for the solver's) is ordered after the copies.  No host sync. */
+int pdhg_get_solution_device(pdhg_solver *s, double *x, double *y, double *z, void *stream);
+
+/* Warm start: restart the solve phase from the caller's (x, y) (host,
+ * unscaled; x is clamped to the bounds and y projected on the signs of its
+ * rows, the projections of section 2), with the anchors at that point, the
+ * primal weight re-initialised and the restart state reset (the iteration
+ * count starts at 0).  Errors: INVALID_ARG (NULL or non-finite entries),
+ * STATE during a push. */
+int pdhg_set_start(pdhg_solver *s, const double *x, const double *y);
+
+/* Checkpoint and resume of the solve phase: pdhg_state_size gives the
+ * buffer size; pdhg_get_state writes the iteration state (iterate, anchors,
+ * candidate, step sizes, primal weight, restart state, counters) into the
+ * caller's host buffer; pdhg_set_state loads such a buffer into a handle
+ * created from the same LP and parameters, after which pdhg_iterate /
+ * pdhg_solve continue exactly as the checkpointed run would have.  Errors:
+ * INVALID_ARG (NULL, buffer too small, not a checkpoint, another size or
+ * precision), STATE during a push. */
+int pdhg_state_size(pdhg_solver *s, int64_t *bytes);
+int pdhg_get_state(pdhg_solver *s, void *buf, int64_t bytes);
+int pdhg_set_state(pdhg_solver *s, const void *buf, int64_t bytes);
 
 /* Scaling vectors Dr (m), Dc (n) (Ahat = diag(Dr) A diag(Dc)) and
  * scalars5 = {eta, omega, sigma_estimate, iterations of the phase,

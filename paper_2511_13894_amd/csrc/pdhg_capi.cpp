@@ -60,7 +60,8 @@ void free_all(pdhg_solver *s)
                     s->u,    s->sense0, s->dr, s->dc, s->ahat, s->ahat_t, s->x,   s->y,     s->xa,   s->ya,
                     s->xbar, s->xp, s->yp,  s->ch,   s->bh,     s->lh,    s->uh,   s->xs,  s->ys,      s->sense,
                     s->ax,   s->aty, s->xu, s->yu,   s->zsol,   s->xpush, s->partials, s->redout, s->st,
-                    s->hx,   s->hz,  s->feat_raw, s->feat_b, s->logits, s->lfix, s->lcount};
+                    s->hx,   s->hz,  s->feat_raw, s->feat_b, s->logits, s->lfix, s->lcount, s->sell_idx,
+                    s->sell_val, s->sell_soff, s->sell_len, s->sell_wi_start, s->sell_wi, s->sell_part};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->st_host) (void)hipHostFree(s->st_host);
@@ -356,12 +357,14 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
         (p.precision != PDHG_FP64 && p.precision != PDHG_FP32_MIXED) || !(p.eps_rel > 0.0) || !(p.eta_safety > 0.0) ||
         !(p.power_tol >= 0.0))
         return fail(PDHG_ERR_INVALID_ARG, "invalid parameter");
-    for (int32_t k : {p.lanes_a, p.lanes_at}) {
+    for (int half = 0; half < 2; half++) { // 0: primal half (lanes_at), 1: dual half (lanes_a)
+        const int32_t k = half ? p.lanes_a : p.lanes_at;
         const bool lane_ok = k >= 1 && k <= 64 && !(k & (k - 1));
-        const bool tile_ok = k == -32 || k == -64 || k == -128 || k == -256 || k == -1032 || k == -1064 || k == kRowBlock;
+        const bool tile_ok = k == -32 || k == -64 || k == -128 || k == -256 || k == -1032 || k == -1064 ||
+                             k == kRowBlock || (half == 1 && k == kSell);
         if (k != 0 && !lane_ok && !tile_ok)
-            return fail(PDHG_ERR_INVALID_ARG,
-                        "lanes must be 0, a power of two in 1..64, or one of -32/-64/-128/-256/-1032/-1064/-2256");
+            return fail(PDHG_ERR_INVALID_ARG, "lanes must be 0, a power of two in 1..64, one of "
+                                              "-32/-64/-128/-256/-1032/-1064/-2256, or -3032 (lanes_a only)");
     }
 
     // canonical rows (ascending columns, duplicates summed), host side ingest
@@ -419,8 +422,8 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
         const double mean_a = m > 0 ? (double)nz / m : 1.0, mean_at = n > 0 ? (double)nz / n : 1.0;
         s->lanes_a = lanes_for_mean(mean_a);
         s->lanes_at = lanes_for_mean(mean_at);
-        s->kern_a = p.lanes_a ? p.lanes_a : choose_kernel(mean_a);
-        s->kern_at = p.lanes_at ? p.lanes_at : choose_kernel(mean_at);
+        s->kern_a = p.lanes_a ? p.lanes_a : choose_kernel(mean_a, true);
+        s->kern_at = p.lanes_at ? p.lanes_at : choose_kernel(mean_at, false);
         s->red_blocks_m = grid_for(m, kBlock, kMaxRedBlocks);
         s->red_blocks_n = grid_for(n, kBlock, kMaxRedBlocks);
         const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
@@ -494,6 +497,7 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(build_transpose(s));
         HIPCHK(scale_problem(s));
+        if (s->kern_a == kSell) HIPCHK(sell_build(s, rp));
         if (single) {
             HIPCHK(power_iteration(s));
             HIPCHK(init_norms(s));
@@ -682,6 +686,160 @@ int pdhg_get_solution(pdhg_solver *s, double *x, double *y, double *z)
     return PDHG_OK;
 }
 
+int pdhg_get_solution_device(pdhg_solver *s, double *x, double *y, double *z, void *stream)
+{
+    if (!s) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
+    try {
+        hipStream_t st = s->stream;
+        if (!s->in_push) {
+            pdhg_kkt_report tmp;
+            solution_report(s, &tmp);
+        }
+        const double *cx = s->in_push ? s->xpush : s->xu;
+        if (x) HIPCHK(hipMemcpyAsync(x, cx, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+        if (y) HIPCHK(hipMemcpyAsync(y, s->yu, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
+        if (z) HIPCHK(hipMemcpyAsync(z, s->zsol, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+        hipStream_t cs = stream ? (hipStream_t)stream : st;
+        if (cs != st) { // order the caller's stream after the copies
+            hipEvent_t ev = nullptr;
+            HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            HIPCHK(hipEventRecord(ev, st));
+            HIPCHK(hipStreamWaitEvent(cs, ev, 0));
+            HIPCHK(hipEventDestroy(ev));
+        }
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_set_start(pdhg_solver *s, const double *x, const double *y)
+{
+    if (!s || !x || !y) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    if (s->in_push) return fail(PDHG_ERR_STATE, "the handle is in its push phase");
+    for (int j = 0; j < s->n; j++)
+        if (!std::isfinite(x[j])) return fail(PDHG_ERR_INVALID_ARG, "non-finite start x");
+    for (int i = 0; i < s->m; i++)
+        if (!std::isfinite(y[i])) return fail(PDHG_ERR_INVALID_ARG, "non-finite start y");
+    try {
+        hipStream_t st = s->stream;
+        HIPCHK(hipMemcpyAsync(s->xu, x, sizeof(double) * (size_t)s->n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(s->yu, y, sizeof(double) * (size_t)s->m, hipMemcpyHostToDevice, st));
+        HIPCHK(set_start(s));
+        HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        s->t_host = 0;
+        s->next_check = s->p.check_every;
+        s->has_candidate = false;
+        s->solved = false;
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+// checkpoint layout: header, DevState, x, x_anchor, x+ (working precision),
+// y, y_anchor, y+ (float64)
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int32_t version, m, n, fp32;
+    int64_t t_host, next_check;
+    int32_t has_candidate, solved;
+    int64_t bytes;
+};
+constexpr char kCkptMagic[8] = {'P', 'D', 'H', 'G', 'C', 'K', 'P', 'T'};
+
+int64_t ckpt_bytes(const pdhg_solver *s)
+{
+    const int64_t vb = s->fp32 ? 4 : 8;
+    return (int64_t)sizeof(CkptHeader) + (int64_t)sizeof(DevState) + 3 * vb * s->n + 3 * 8 * (int64_t)s->m;
+}
+} // namespace
+
+int pdhg_state_size(pdhg_solver *s, int64_t *bytes)
+{
+    if (!s || !bytes) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    *bytes = ckpt_bytes(s);
+    return PDHG_OK;
+}
+
+int pdhg_get_state(pdhg_solver *s, void *buf, int64_t bytes)
+{
+    if (!s || !buf) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    if (bytes < ckpt_bytes(s)) return fail(PDHG_ERR_INVALID_ARG, "state buffer smaller than pdhg_state_size");
+    if (s->in_push) return fail(PDHG_ERR_STATE, "checkpoints cover the solve phase only");
+    try {
+        hipStream_t st = s->stream;
+        char *p = (char *)buf;
+        CkptHeader h{};
+        std::memcpy(h.magic, kCkptMagic, 8);
+        h.version = 1;
+        h.m = s->m;
+        h.n = s->n;
+        h.fp32 = s->fp32 ? 1 : 0;
+        h.t_host = s->t_host;
+        h.next_check = s->next_check;
+        h.has_candidate = s->has_candidate ? 1 : 0;
+        h.solved = s->solved ? 1 : 0;
+        h.bytes = ckpt_bytes(s);
+        std::memcpy(p, &h, sizeof(h));
+        p += sizeof(h);
+        HIPCHK(hipMemcpyAsync(p, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+        p += sizeof(DevState);
+        const size_t xb = (size_t)(s->fp32 ? 4 : 8) * (size_t)s->n, yb = 8 * (size_t)s->m;
+        for (const void *src : {(const void *)s->x, (const void *)s->xa, (const void *)s->xp}) {
+            HIPCHK(hipMemcpyAsync(p, src, xb, hipMemcpyDeviceToHost, st));
+            p += xb;
+        }
+        for (const void *src : {(const void *)s->y, (const void *)s->ya, (const void *)s->yp}) {
+            HIPCHK(hipMemcpyAsync(p, src, yb, hipMemcpyDeviceToHost, st));
+            p += yb;
+        }
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_set_state(pdhg_solver *s, const void *buf, int64_t bytes)
+{
+    if (!s || !buf) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    if (s->in_push) return fail(PDHG_ERR_STATE, "checkpoints cover the solve phase only");
+    CkptHeader h;
+    if (bytes < (int64_t)sizeof(h)) return fail(PDHG_ERR_INVALID_ARG, "state buffer too small");
+    std::memcpy(&h, buf, sizeof(h));
+    if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+        return fail(PDHG_ERR_INVALID_ARG, "not a checkpoint of this library");
+    if (h.m != s->m || h.n != s->n || h.fp32 != (s->fp32 ? 1 : 0) || h.bytes != ckpt_bytes(s) || bytes < h.bytes)
+        return fail(PDHG_ERR_INVALID_ARG, "checkpoint of another LP size or precision");
+    try {
+        hipStream_t st = s->stream;
+        const char *p = (const char *)buf + sizeof(h);
+        HIPCHK(hipMemcpyAsync(s->st, p, sizeof(DevState), hipMemcpyHostToDevice, st));
+        p += sizeof(DevState);
+        const size_t xb = (size_t)(s->fp32 ? 4 : 8) * (size_t)s->n, yb = 8 * (size_t)s->m;
+        for (void *dst : {(void *)s->x, (void *)s->xa, (void *)s->xp}) {
+            HIPCHK(hipMemcpyAsync(dst, p, xb, hipMemcpyHostToDevice, st));
+            p += xb;
+        }
+        for (void *dst : {(void *)s->y, (void *)s->ya, (void *)s->yp}) {
+            HIPCHK(hipMemcpyAsync(dst, p, yb, hipMemcpyHostToDevice, st));
+            p += yb;
+        }
+        HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        s->t_host = h.t_host;
+        s->next_check = h.next_check;
+        s->has_candidate = h.has_candidate != 0;
+        s->solved = h.solved != 0;
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
 int pdhg_get_iterate(pdhg_solver *s, double *x, double *y)
 {
     if (!s) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
@@ -775,7 +933,7 @@ int pdhg_batch_create(int32_t count, const pdhg_lp_desc *lps, const pdhg_params 
     if (params) p = *params;
     else pdhg_default_params(&p);
     for (int32_t k : {p.lanes_a, p.lanes_at})
-        if (k > 0 || k == kRowBlock)
+        if (k > 0 || k == kRowBlock || k == kSell)
             return fail(PDHG_ERR_INVALID_ARG, "the batch engine runs tiled kernels only (lanes -32/-64/-128/-256/-1032/-1064)");
     // one block-diagonal model with global column indices
     std::vector<int> roff(1, 0), coff(1, 0);
@@ -882,7 +1040,7 @@ int pdhg_batch_create(int32_t count, const pdhg_lp_desc *lps, const pdhg_params 
         HIPCHK(hipMemcpy(b->active, b->active_host.data(), sizeof(int) * (size_t)count, hipMemcpyHostToDevice));
         // tiled kernels from the mean row lengths (tiles only: the batch has no lane-group path)
         auto tiled = [](double mean) {
-            const int k = choose_kernel(mean);
+            const int k = choose_kernel(mean, false);
             if (k == kRowBlock || k > 0) return mean <= 3.0 ? -256 : -32;
             return k;
         };

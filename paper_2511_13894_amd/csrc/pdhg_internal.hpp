@@ -24,6 +24,7 @@ namespace pdhg {
 
 constexpr int kBlock = 256;         // threads per workgroup (4 wave64)
 constexpr int kRowBlock = -2256; // kernel code: one row per workgroup of kBlock threads
+constexpr int kSell = -3032;     // kernel code (dual half): sliced ELLPACK, 32-row slices
 constexpr int kMaxRedBlocks = 1024; // cap on per-block partials of a reduction
 
 // Quantities reduced at a check (block partials, then one fixed-order pass).
@@ -125,6 +126,13 @@ struct pdhg_solver {
     int64_t power_steps = 0; // power-iteration steps taken at create
     int64_t next_check = 0;  // phase iteration count of the next check
     bool in_push = false;
+    // sliced ELLPACK copy of Ahat for the dual half (kernel code kSell)
+    int *sell_idx = nullptr, *sell_len = nullptr, *sell_wi_start = nullptr;
+    void *sell_val = nullptr;
+    int64_t *sell_soff = nullptr;
+    int2 *sell_wi = nullptr;
+    double *sell_part = nullptr;
+    int n_sell_wi = 0;
     bool model_original = true; // the solve's model is in ch/lh/uh (false once a push rewrote it)
     bool has_candidate = false;   // a check has produced (xp, yp) in this phase
     bool solved = false;          // the solve has a candidate (push allowed)
@@ -197,9 +205,16 @@ hipError_t power_iteration(pdhg_solver *s);
 // out = Ahat vec (transpose = false) or Ahat' vec, float64, with the structure of
 // the iteration kernel of that half (the kernels must have been chosen)
 hipError_t solver_product(pdhg_solver *s, bool transpose, const double *vec, double *out);
+// sliced ELLPACK dual half: layout (after scaling), iteration half, product Ahat vec
+hipError_t sell_build(pdhg_solver *s, const std::vector<int> &rp_host);
+void sell_dual(pdhg_solver *s, int i, int store, hipEvent_t e0, hipEvent_t e1);
+void sell_product(pdhg_solver *s, const double *vec, double *out);
+void sell_product(pdhg_solver *s, const float *vec, double *out);
 
 // iteration, checks, push and reports (pdhg_iter.hip)
 hipError_t init_iteration(pdhg_solver *s);
+// restart the solve phase from the start point staged (unscaled) in xu, yu
+hipError_t set_start(pdhg_solver *s);
 hipError_t launch_iterations(pdhg_solver *s, int count, bool check_at_end, int mode, bool timed_launch);
 hipError_t launch_check(pdhg_solver *s, int mode, int len);
 hipError_t launch_advance(pdhg_solver *s, int len);
@@ -234,7 +249,7 @@ hipError_t batch_record_history(pdhg_batch *b);
 hipError_t batch_compute_features(pdhg_batch *b);
 hipError_t batch_learned_fix(pdhg_batch *b, double theta);
 hipError_t batch_learned_undo(pdhg_batch *b);
-int choose_kernel(double mean_row);
+int choose_kernel(double mean_row, bool dual_half);
 hipError_t autotune(pdhg_solver *s);
 
 // launch-shape helpers

@@ -153,6 +153,8 @@ hipError_t solver_product(pdhg_solver *s, bool transpose, const double *vec, dou
     if (transpose) {
         if (s->fp32) check_spmv<float, double>(s->stream, s->kern_at, s->n, s->tp, s->ti, (const float *)s->ahat_t, vec, out);
         else check_spmv<double, double>(s->stream, s->kern_at, s->n, s->tp, s->ti, (const double *)s->ahat_t, vec, out);
+    } else if (s->kern_a == kSell) {
+        sell_product(s, vec, out);
     } else {
         if (s->fp32) check_spmv<float, double>(s->stream, s->kern_a, s->m, s->rp, s->ci, (const float *)s->ahat, vec, out);
         else check_spmv<double, double>(s->stream, s->kern_a, s->m, s->rp, s->ci, (const double *)s->ahat, vec, out);
@@ -326,6 +328,10 @@ static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullpt
 {
     const int L = s->kern_a;
     if (s->m <= 0) return;
+    if (L == kSell) {
+        sell_dual(s, i, store, e0, e1);
+        return;
+    }
     if (L == kRowBlock) {
         PDHG_LAUNCH(e0, e1, (k_dual_rowblock<V>), dim3(s->m), dim3(kBlock), s->stream, s->m, s->rp, s->ci,
                     (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bh, s->sense, (double *)s->y,
@@ -510,7 +516,8 @@ template <typename V>
 static void check_impl(pdhg_solver *s, const V *xc, const double *yc, double *pm, double *pn)
 {
     hipStream_t st = s->stream;
-    check_spmv<V, V>(st, s->kern_a, s->m, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
+    if (s->kern_a == kSell) sell_product(s, xc, s->ax);
+    else check_spmv<V, V>(st, s->kern_a, s->m, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
     check_spmv<V, double>(st, s->kern_at, s->n, s->tp, s->ti, (const V *)s->ahat_t, yc, s->aty);
     const int gm = s->red_blocks_m, gn = s->red_blocks_n;
     hipLaunchKernelGGL(k_check_rows, dim3(gm), dim3(kBlock), 0, st, s->m, s->ax, (const double *)s->bh, s->sense, s->dr,
@@ -736,6 +743,42 @@ hipError_t init_norms(pdhg_solver *s)
 hipError_t init_iteration(pdhg_solver *s)
 {
     return s->fp32 ? phase_start<float>(s, true) : phase_start<double>(s, true);
+}
+
+// caller's start point (xu, yu unscaled) -> x = clamp(x / Dc, lhat, uhat),
+// y = y / Dr projected on the sign of its row (the projections of the method)
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_set_start(int n, int m, const double *__restrict__ xu,
+                                                     const double *__restrict__ yu, const double *__restrict__ dc,
+                                                     const double *__restrict__ dr, const V *__restrict__ lh,
+                                                     const V *__restrict__ uh, const int8_t *__restrict__ sense,
+                                                     V *__restrict__ x, double *__restrict__ y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
+        if (i < n) {
+            const double v = fmin(fmax(xu[i] / dc[i], (double)lh[i]), (double)uh[i]);
+            x[i] = (V)v;
+        } else {
+            const int64_t r = i - n;
+            double v = yu[r] / dr[r];
+            if (sense[r] == '<') v = fmin(v, 0.0);
+            else if (sense[r] == '>') v = fmax(v, 0.0);
+            y[r] = v;
+        }
+    }
+}
+
+hipError_t set_start(pdhg_solver *s)
+{
+    const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
+    if (s->fp32) {
+        hipLaunchKernelGGL((k_set_start<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->xu, s->yu, s->dc,
+                           s->dr, (const float *)s->lh, (const float *)s->uh, s->sense, (float *)s->x, (double *)s->y);
+        return phase_start<float>(s, false);
+    }
+    hipLaunchKernelGGL((k_set_start<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->xu, s->yu, s->dc,
+                       s->dr, (const double *)s->lh, (const double *)s->uh, s->sense, (double *)s->x, (double *)s->y);
+    return phase_start<double>(s, false);
 }
 
 template <typename V>
@@ -1013,14 +1056,16 @@ hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, double
 // ------------------------------------------------------- kernel choice ---
 // From measured sweeps on the 100k x 400k and 7k x 10M LPs: one lane per row
 // for rows of about 2 entries, LDS tiles for 3 to 48 entries, lane groups
-// sized to the mean up to 384 entries, one workgroup per row beyond.
-int choose_kernel(double mean_row)
+// sized to the mean beyond (64 lanes on the dual half's 1,400 to 2,800-entry
+// rows beat one workgroup per row and the sliced ELLPACK layout, which stay
+// available as explicit or autotuned choices).
+int choose_kernel(double mean_row, bool dual_half)
 {
+    (void)dual_half;
     if (mean_row <= 3.0) return 1;
     if (mean_row <= 32.0) return -64; // measured best for 6 to 24 entries per row
     if (mean_row <= 48.0) return -32;
-    if (mean_row <= 384.0) return lanes_for_mean(mean_row);
-    return kRowBlock;
+    return lanes_for_mean(mean_row);
 }
 
 // Time every candidate of each half on scratch output vectors (3 launches
@@ -1040,7 +1085,7 @@ hipError_t autotune(pdhg_solver *s)
     if (e == hipSuccess) e = hipMemcpyAsync(sx, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sxbar, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sy, s->y, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
-    const int cands[] = {-32, -64, -128, -256, -1032, -1064, 1, 2, 4, 8, 16, 32, 64, kRowBlock};
+    const int cands[] = {-32, -64, -128, -256, -1032, -1064, 1, 2, 4, 8, 16, 32, 64, kRowBlock, kSell};
     void *keep[5] = {s->x, s->xbar, s->xp, s->y, s->yp};
     s->x = sx;
     s->xbar = sxbar;
@@ -1051,6 +1096,7 @@ hipError_t autotune(pdhg_solver *s)
         float best = 1e30f;
         int best_k = half == 0 ? s->kern_at : s->kern_a;
         for (int c : cands) {
+            if (c == kSell && (half == 0 || !s->sell_idx)) continue; // dual half, layout built
             if (half == 0) s->kern_at = c;
             else s->kern_a = c;
             for (int rep = 0; rep < 4; rep++) {

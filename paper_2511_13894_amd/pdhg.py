@@ -122,7 +122,8 @@ EXPORTS = ["pdhg_default_params", "pdhg_create", "pdhg_solve", "pdhg_iterate", "
            "pdhg_mlp_create", "pdhg_mlp_destroy", "pdhg_mlp_set_params", "pdhg_mlp_get_params", "pdhg_mlp_forward",
            "pdhg_mlp_gradient", "pdhg_default_train_params", "pdhg_mlp_train", "pdhg_features",
            "pdhg_batch_features", "pdhg_batch_corner_push_learned",
-           "pdhg_corner_push_learned"]
+           "pdhg_corner_push_learned", "pdhg_get_solution_device", "pdhg_set_start", "pdhg_state_size",
+           "pdhg_get_state", "pdhg_set_state"]
 
 _lib = None
 
@@ -174,6 +175,11 @@ def load(path: Optional[Path] = None):
     lib.pdhg_features.argtypes = [C.c_void_p, C.c_uint64, fp]
     lib.pdhg_corner_push_learned.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_uint64, P(PushResult)]
     lib.pdhg_batch_features.argtypes = [C.c_void_p, P(C.c_uint64), fp]
+    lib.pdhg_get_solution_device.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.pdhg_set_start.argtypes = [C.c_void_p, dp, dp]
+    lib.pdhg_state_size.argtypes = [C.c_void_p, P(C.c_int64)]
+    lib.pdhg_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
+    lib.pdhg_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
     lib.pdhg_batch_corner_push_learned.argtypes = [C.c_void_p, C.c_void_p, C.c_double, P(C.c_uint64), P(PushResult)]
     lib.pdhg_last_error.restype = C.c_char_p
     lib.pdhg_struct_size.restype = C.c_int32
@@ -183,7 +189,8 @@ def load(path: Optional[Path] = None):
                "pdhg_batch_solve", "pdhg_batch_corner_push", "pdhg_batch_get_solution", "pdhg_batch_get_report",
                "pdhg_mlp_create", "pdhg_mlp_set_params", "pdhg_mlp_get_params", "pdhg_mlp_forward",
                "pdhg_mlp_gradient", "pdhg_mlp_train", "pdhg_features", "pdhg_corner_push_learned",
-               "pdhg_batch_features", "pdhg_batch_corner_push_learned"):
+               "pdhg_batch_features", "pdhg_batch_corner_push_learned", "pdhg_get_solution_device",
+               "pdhg_set_start", "pdhg_state_size", "pdhg_get_state", "pdhg_set_state"):
         getattr(lib, fn).restype = C.c_int
     sizes = [C.sizeof(Params), C.sizeof(Result), C.sizeof(KKTReport), C.sizeof(PushResult), C.sizeof(Timing),
              C.sizeof(LpDesc), C.sizeof(BatchReport)]
@@ -318,6 +325,22 @@ class Solver:
         r = PushResult()
         self._check(self.lib.pdhg_corner_push_learned(self.h, net.h, float(theta), C.c_uint64(seed), C.byref(r)))
         return r
+
+    def set_start(self, x, y):
+        xa = np.ascontiguousarray(x, dtype=np.float64)
+        ya = np.ascontiguousarray(y, dtype=np.float64)
+        self._check(self.lib.pdhg_set_start(self.h, _dp(xa), _dp(ya)))
+
+    def get_state(self) -> bytes:
+        nb = C.c_int64()
+        self._check(self.lib.pdhg_state_size(self.h, C.byref(nb)))
+        buf = C.create_string_buffer(nb.value)
+        self._check(self.lib.pdhg_get_state(self.h, buf, nb.value))
+        return buf.raw
+
+    def set_state(self, state: bytes):
+        buf = C.create_string_buffer(state, len(state))
+        self._check(self.lib.pdhg_set_state(self.h, buf, len(state)))
 
     def get_timing(self) -> Timing:
         t = Timing()

@@ -1,0 +1,96 @@
+"""Warm start, checkpoint/resume and the device-pointer solution accessor."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2511_13894_amd import lpgen, pdhg
+
+pytestmark = pytest.mark.gpu
+
+
+def test_checkpoint_resume_continues_bitwise():
+    lp = lpgen.config1(seed=5, m=800, n=3200)
+    a = pdhg.Solver(lp, eps_rel=1e-7)
+    a.iterate(100)
+    state = a.get_state()
+    a.iterate(150)
+    xa, ya = a.get_iterate()
+    b = pdhg.Solver(lp, eps_rel=1e-7)
+    b.set_state(state)
+    b.iterate(150)
+    xb, yb = b.get_iterate()
+    np.testing.assert_array_equal(xa, xb)
+    np.testing.assert_array_equal(ya, yb)
+    ra, rb = a.solve(), b.solve()
+    print(f"[state] resumed solve: {rb.iters} iterations (uninterrupted {ra.iters})", flush=True)
+    assert (ra.status, ra.iters, ra.restarts) == (rb.status, rb.iters, rb.restarts)
+    assert ra.pobj == rb.pobj
+    pa, pb = a.corner_push(3), b.corner_push(3)
+    assert (pa.iters, pa.after.p_off) == (pb.iters, pb.after.p_off)
+
+
+def test_checkpoint_errors():
+    lp = lpgen.config0(1)
+    a = pdhg.Solver(lp)
+    a.iterate(10)
+    state = a.get_state()
+    with pytest.raises(pdhg.PdhgError):
+        pdhg.Solver(lpgen.tiny(3)).set_state(state)
+    with pytest.raises(pdhg.PdhgError):
+        a.set_state(b"not a checkpoint" * 8)
+    f32 = pdhg.Solver(lp, precision="fp32")
+    with pytest.raises(pdhg.PdhgError):
+        f32.set_state(state)
+    a.solve()
+    a.corner_push(1)
+    with pytest.raises(pdhg.PdhgError):
+        a.get_state()
+
+
+def test_warm_start_from_an_optimal_point_stops_at_the_first_check():
+    lp = lpgen.config0(4)
+    a = pdhg.Solver(lp, eps_rel=1e-8)
+    ra = a.solve()
+    x, y, _ = a.get_solution()
+    b = pdhg.Solver(lp, eps_rel=1e-6)
+    b.set_start(x, y)
+    rb = b.solve()
+    print(f"[state] cold solve {ra.iters} iterations; warm start from its answer {rb.iters}", flush=True)
+    assert rb.status == pdhg.PDHG_OPTIMAL and rb.iters <= 128 < ra.iters
+    bad = x.copy()
+    bad[0] = np.nan
+    with pytest.raises(pdhg.PdhgError):
+        b.set_start(bad, y)
+
+
+def test_solution_into_device_buffers():
+    lp = lpgen.config0(5)
+    s = pdhg.Solver(lp)
+    s.solve()
+    x, y, z = s.get_solution()
+    # the HIP runtime the library itself loaded (the same file, hence the same runtime instance)
+    path = next(line.split()[-1] for line in open("/proc/self/maps") if "libamdhip64.so" in line)
+    hip = C.CDLL(path)
+    hip.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+    hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    hip.hipDeviceSynchronize.argtypes = []
+    hip.hipFree.argtypes = [C.c_void_p]
+    bufs = []
+    for k in (lp.n, lp.m, lp.n):
+        p = C.c_void_p()
+        assert hip.hipMalloc(C.byref(p), 8 * k) == 0
+        bufs.append(p)
+    try:
+        assert s.lib.pdhg_get_solution_device(s.h, bufs[0], bufs[1], bufs[2], None) == 0
+        assert hip.hipDeviceSynchronize() == 0
+        got = []
+        for p, k in zip(bufs, (lp.n, lp.m, lp.n)):
+            h = np.zeros(k)
+            assert hip.hipMemcpy(h.ctypes.data_as(C.c_void_p), p, 8 * k, 2) == 0  # device to host
+            got.append(h)
+        for a, b in zip(got, (x, y, z)):
+            np.testing.assert_array_equal(a, b)
+    finally:
+        for p in bufs:
+            hip.hipFree(p)
