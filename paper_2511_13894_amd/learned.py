@@ -158,6 +158,8 @@ def main(argv=None):
     ap.add_argument("--mcf-precision", default="fp32", choices=["fp64", "fp32"])
     ap.add_argument("--mcf-seeds", type=int, default=1)
     ap.add_argument("--no-graph", action="store_true", help="launch every cycle eagerly (profiler runs)")
+    ap.add_argument("--theta-by-time", action="store_true",
+                    help="with --batched: choose theta by the validation batch's measured time to the corner")
     ap.add_argument("--batched", action="store_true",
                     help="training data from the batch engine, and learned+batched vs plain batched push")
     args = ap.parse_args(argv)
@@ -185,7 +187,18 @@ def main(argv=None):
     for th, prec, frac in rows:
         log(f"[learned] validation theta {th}: precision {prec:.4f}, fixes {frac:.4f} of free columns")
     theta = choose_theta(rows, args.min_precision)
-    log(f"[learned] theta {theta}")
+    if args.batched and args.theta_by_time:
+        sd = [91 + i for i in range(len(va))]
+        base = batch_time_to_corner(va, sd, args.precision)
+        best = (base["seconds"], None)
+        for th in (0.9, 0.95, 0.98, 0.99, 0.995):
+            r = batch_time_to_corner(va, sd, args.precision, net, th)
+            log(f"[learned] validation batch, theta {th}: {r['seconds']:.3f}s (plain {base['seconds']:.3f}s), push "
+                f"lockstep {r['push_lockstep']} (plain {base['push_lockstep']})")
+            if r["seconds"] < best[0]:
+                best = (r["seconds"], th)
+        theta = best[1]
+        log(f"[learned] theta by validation time: {theta} (None: the plain push was fastest)")
     out = {"train_columns": int(f.shape[0]), "val_columns": int(fv.shape[0]), "theta": theta,
            "theta_table": rows, "train_loss": [rep.loss_first, rep.loss_last], "train_seconds": rep.seconds,
            "train_samples_per_s": rep.samples_per_s, "eval": []}
