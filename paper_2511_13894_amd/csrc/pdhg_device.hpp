@@ -70,6 +70,29 @@ __device__ __forceinline__ int xcd_block(int bid, int nblk)
     return base + (bid >> 3);
 }
 
+// One lane's share of a row's product: the terms e = beg+lane, beg+lane+L, ...
+// below end, accumulated in that order.  Four terms' index, value and
+// gathered loads are issued before the first of them is accumulated, so a
+// lane waits for one round of loads per four terms instead of per term.
+template <int L, typename ACC, typename VM, typename VX>
+__device__ __forceinline__ ACC lane_dot(int beg, int end, int lane, const int *__restrict__ idx,
+                                        const VM *__restrict__ val, const VX *__restrict__ x)
+{
+    ACC acc = 0;
+    int e = beg + lane;
+    for (; e + 3 * L < end; e += 4 * L) {
+        const int i0 = idx[e], i1 = idx[e + L], i2 = idx[e + 2 * L], i3 = idx[e + 3 * L];
+        const ACC v0 = (ACC)val[e], v1 = (ACC)val[e + L], v2 = (ACC)val[e + 2 * L], v3 = (ACC)val[e + 3 * L];
+        const ACC g0 = (ACC)x[i0], g1 = (ACC)x[i1], g2 = (ACC)x[i2], g3 = (ACC)x[i3];
+        acc += v0 * g0;
+        acc += v1 * g1;
+        acc += v2 * g2;
+        acc += v3 * g3;
+    }
+    for (; e < end; e += L) acc += (ACC)val[e] * (ACC)x[idx[e]];
+    return acc;
+}
+
 // Row-compressed product out[r] = sum_e val[e] * x[idx[e]] over rows r < rows,
 // L lanes per row, accumulation in ACC.  One group of L lanes walks a row with
 // stride L (coalesced for L >= 2 on long rows, one lane per row when L = 1).
@@ -83,8 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int rows, const int *__restrict
     const int lane = (int)(g % L);
     if (row >= rows) return;
     const int beg = ptr[row], end = ptr[row + 1];
-    ACC acc = 0;
-    for (int e = beg + lane; e < end; e += L) acc += (ACC)val[e] * (ACC)x[idx[e]];
+    ACC acc = lane_dot<L, ACC>(beg, end, lane, idx, val, x);
     acc = group_sum<L>(acc);
     if (lane == 0) out[row] = (VO)acc;
 }

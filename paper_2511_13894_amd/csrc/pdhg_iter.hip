@@ -24,9 +24,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(int n, const int *__restrict_
     const int64_t j = gi / L;
     const int lane = (int)(gi % L);
     if (j >= n) return;
-    double acc = 0.0;
-    const int beg = tp[j], end = tp[j + 1];
-    for (int e = beg + lane; e < end; e += L) acc += (double)atv[e] * y[ti[e]];
+    double acc = lane_dot<L, double>(tp[j], tp[j + 1], lane, ti, atv, y);
     acc = group_sum<L>(acc);
     if (lane != 0) return;
     primal_update<V>(j, acc, (double)x[j], (double)ch[j], (double)lh[j], (double)uh[j], (double)xa[j], x, xbar, xp,
@@ -47,9 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
     const int64_t r = gi / L;
     const int lane = (int)(gi % L);
     if (r >= m) return;
-    double acc = 0.0;
-    const int beg = rp[r], end = rp[r + 1];
-    for (int e = beg + lane; e < end; e += L) acc += (double)av[e] * (double)xbar[ci[e]];
+    double acc = lane_dot<L, double>(rp[r], rp[r + 1], lane, ci, av, xbar);
     acc = group_sum<L>(acc);
     if (lane != 0) return;
     dual_update(r, acc, y[r], bh[r], ya[r], sense[r], y, yp, st, i, store_cand);
@@ -68,14 +64,17 @@ __device__ __forceinline__ double row_block_sum(int beg, int end, const int *__r
     for (int e0 = beg + (int)threadIdx.x; e0 < end; e0 += 4 * kBlock) {
         int id[4];
         double v[4], g[4];
+        // every lane loads: positions past the row's end reload its last
+        // entry (e0 < end here), so no load is merged with a fallback value
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int e = e0 + u * kBlock;
-            id[u] = e < end ? idx[e] : 0;
-            v[u] = e < end ? (double)val[e] : 0.0;
+            const int ec = e < end ? e : end - 1;
+            id[u] = idx[ec];
+            v[u] = (double)val[ec];
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++) g[u] = e0 + u * kBlock < end ? (double)vec[id[u]] : 0.0;
+        for (int u = 0; u < 4; u++) g[u] = (double)vec[id[u]];
 #pragma unroll
         for (int u = 0; u < 4; u++)
             if (e0 + u * kBlock < end) acc += v[u] * g[u];

@@ -103,14 +103,23 @@ __device__ __forceinline__ void tile_row_sums(int r0, int rows, const int *__res
         const int ce = cs + C < end ? cs + C : end;
         int id[kTileU];
         double v[kTileU], g[kTileU];
+        // Slice u of the chunk is tested once for the whole workgroup; inside
+        // a live slice every lane loads, lanes past the chunk's end reloading
+        // its last entry.  A per-lane conditional load would be merged with
+        // the fallback value right after it and so wait for each load in turn.
 #pragma unroll
         for (int u = 0; u < kTileU; u++) {
-            const int k = cs + tid + u * NT;
-            id[u] = k < ce ? idx[k] : 0;
-            v[u] = k < ce ? (double)val[k] : 0.0;
+            id[u] = 0;
+            v[u] = 0.0;
+            if (cs + u * NT < ce) {
+                const int k = cs + tid + u * NT;
+                const int kc = k < ce ? k : ce - 1;
+                id[u] = idx[kc];
+                v[u] = (double)val[kc];
+            }
         }
 #pragma unroll
-        for (int u = 0; u < kTileU; u++) g[u] = cs + tid + u * NT < ce ? (double)vec[id[u]] : 0.0;
+        for (int u = 0; u < kTileU; u++) g[u] = cs + u * NT < ce ? (double)vec[id[u]] : 0.0;
 #pragma unroll
         for (int u = 0; u < kTileU; u++) {
             const int k = cs + tid + u * NT;
@@ -119,7 +128,17 @@ __device__ __forceinline__ void tile_row_sums(int r0, int rows, const int *__res
         __syncthreads(); // products, and on the first chunk the row pointers
         const int rb = have ? s_ptr[my_row] : 0, re = have ? s_ptr[my_row + 1] : 0;
         const int lo = rb > cs ? rb : cs, hi = re < ce ? re : ce;
-        for (int q = lo + sub; q < hi; q += G) acc += s_prod[q - cs];
+        // the row's products in the same sequential order, read four at a time
+        int q = lo + sub;
+        for (; q + 3 * G < hi; q += 4 * G) {
+            const double p0 = s_prod[q - cs], p1 = s_prod[q + G - cs];
+            const double p2 = s_prod[q + 2 * G - cs], p3 = s_prod[q + 3 * G - cs];
+            acc += p0;
+            acc += p1;
+            acc += p2;
+            acc += p3;
+        }
+        for (; q < hi; q += G) acc += s_prod[q - cs];
         __syncthreads();
     }
     acc = group_sum<G>(acc);

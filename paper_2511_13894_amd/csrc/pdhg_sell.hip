@@ -43,15 +43,17 @@ __global__ __launch_bounds__(kBlock) void k_sell_partial(const int2 *__restrict_
     for (int kk = k0 + g; kk < k1; kk += 4 * kSellG) {
         int id[4];
         double v[4], x[4];
+        // positions past the slice's end reload its last position (kk < k1
+        // here), so every lane loads and no load is merged with a fallback
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int k = kk + u * kSellG;
-            const int64_t e = base + (int64_t)k * kSellC;
-            id[u] = k < k1 ? idx[e] : 0;
-            v[u] = k < k1 ? (double)val[e] : 0.0;
+            const int64_t e = base + (int64_t)(k < k1 ? k : k1 - 1) * kSellC;
+            id[u] = idx[e];
+            v[u] = (double)val[e];
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++) x[u] = kk + u * kSellG < k1 ? (double)vec[id[u]] : 0.0;
+        for (int u = 0; u < 4; u++) x[u] = (double)vec[id[u]];
 #pragma unroll
         for (int u = 0; u < 4; u++)
             if (kk + u * kSellG < k1) acc += v[u] * x[u];
