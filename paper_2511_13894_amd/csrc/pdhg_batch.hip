@@ -221,16 +221,7 @@ __global__ __launch_bounds__(kBlock) void kb_check_final(DevState *__restrict__ 
     const int m0 = rm_start[blockIdx.x], m1 = rm_start[blockIdx.x + 1];
     const int n0 = rn_start[blockIdx.x], n1 = rn_start[blockIdx.x + 1];
     double v[Q_COUNT + 1];
-#pragma unroll
-    for (int q = 0; q < Q_COUNT + 1; q++) {
-        const bool is_row = (q == Q_PH2 || q == Q_P2 || q == Q_PINF || q == Q_BTY || q == Q_DY2 || q == Q_NAN);
-        const bool is_max = (q == Q_PINF || q == Q_DINF);
-        const double *src = is_row ? pm + (size_t)q * ntm : pn + (size_t)q * ntn;
-        const int lo = is_row ? m0 : n0, hi = is_row ? m1 : n1;
-        double acc = 0.0;
-        for (int t = lo + threadIdx.x; t < hi; t += kBlock) acc = is_max ? fmax(acc, src[t]) : acc + src[t];
-        v[q] = acc;
-    }
+    fold_check_partials(v, pm, (size_t)ntm, m0, m1, pn, (size_t)ntn, n0, n1);
     block_reduce<Q_COUNT + 1>(v, (1u << Q_PINF) | (1u << Q_DINF));
     if (threadIdx.x == 0) check_decide(st, v, mode, len);
 }

@@ -468,16 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_check_final(DevState *st, const doub
     // slot q of the row partials lives at pm[q * gm + b], of the column
     // partials at pn[q * gn + b]; slot Q_COUNT holds the column NaN count
     double v[Q_COUNT + 1];
-#pragma unroll
-    for (int q = 0; q < Q_COUNT + 1; q++) {
-        const bool is_row = (q == Q_PH2 || q == Q_P2 || q == Q_PINF || q == Q_BTY || q == Q_DY2 || q == Q_NAN);
-        const bool is_max = (q == Q_PINF || q == Q_DINF);
-        const double *src = is_row ? pm + (size_t)q * gm : pn + (size_t)q * gn;
-        const int nb = is_row ? gm : gn;
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < nb; b += kBlock) acc = is_max ? fmax(acc, src[b]) : acc + src[b];
-        v[q] = acc;
-    }
+    fold_check_partials(v, pm, (size_t)gm, 0, gm, pn, (size_t)gn, 0, gn);
     block_reduce<Q_COUNT + 1>(v, (1u << Q_PINF) | (1u << Q_DINF));
     if (threadIdx.x == 0) check_decide(st, v, mode, len);
 }

@@ -146,6 +146,42 @@ __device__ __forceinline__ void tile_row_sums(int r0, int rows, const int *__res
     __syncthreads();
 }
 
+// The check's quantities from per-block (or per-tile) partials: slot q folds
+// its partials lo..hi-1 (row slots from pm + q*sm over [m0, m1), column slots
+// from pn + q*sn over [n0, n1)), thread t taking lo+t, lo+t+kBlock, ... in
+// that order, by sum or, for the infinity norms, by max.  Each round issues
+// every slot's load (indices clamped into the range) before combining any,
+// so a round costs one memory latency instead of one per slot.
+__device__ __forceinline__ void fold_check_partials(double (&v)[Q_COUNT + 1], const double *pm, size_t sm, int m0,
+                                                    int m1, const double *pn, size_t sn, int n0, int n1)
+{
+    constexpr unsigned row_slots =
+        (1u << Q_PH2) | (1u << Q_P2) | (1u << Q_PINF) | (1u << Q_BTY) | (1u << Q_DY2) | (1u << Q_NAN);
+    constexpr unsigned max_slots = (1u << Q_PINF) | (1u << Q_DINF);
+    const int len = m1 - m0 > n1 - n0 ? m1 - m0 : n1 - n0;
+    const int rounds = (len + kBlock - 1) / kBlock;
+#pragma unroll
+    for (int q = 0; q < Q_COUNT + 1; q++) v[q] = 0.0;
+    for (int r = 0; r < rounds; r++) {
+        const int off = (int)threadIdx.x + r * kBlock;
+        double a[Q_COUNT + 1];
+#pragma unroll
+        for (int q = 0; q < Q_COUNT + 1; q++) {
+            const bool row = (row_slots >> q) & 1u;
+            const int lo = row ? m0 : n0, hi = row ? m1 : n1;
+            const double *src = row ? pm + (size_t)q * sm : pn + (size_t)q * sn;
+            const int k = lo + off;
+            a[q] = hi > lo ? src[k < hi ? k : hi - 1] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < Q_COUNT + 1; q++) {
+            const bool row = (row_slots >> q) & 1u;
+            if ((row ? m0 : n0) + off < (row ? m1 : n1))
+                v[q] = ((max_slots >> q) & 1u) ? fmax(v[q], a[q]) : v[q] + a[q];
+        }
+    }
+}
+
 __device__ __forceinline__ double kkt_weighted(double om, double p2, double d2, double g2)
 {
     return sqrt(om * om * p2 + d2 / (om * om) + g2);
