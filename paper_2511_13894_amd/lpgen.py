@@ -240,22 +240,24 @@ def config2(seed: int = 2) -> LP:
     return transportation(2000, 5000, seed)
 
 
-def tiny(seed: int, m: int = 3, n: int = 6, with_ineq: bool = True, with_bounds: bool = True) -> LP:
+def tiny(seed: int, m: int = 3, n: int = 6, with_ineq: bool = True, with_bounds: bool = True,
+         with_free: bool = False) -> LP:
     """Small feasible, bounded LP for brute-force checks.
 
     Bounds: each column gets a finite lower bound, a finite upper bound or
-    both (never free), rows get random senses.  A primal point x0 inside the
-    box fixes b (so the LP is feasible) and a sign-consistent dual pair
-    (y0, z0) fixes c (so it is dual feasible, hence bounded)."""
+    both, and with ``with_free`` also neither (a free column); rows get random
+    senses.  A primal point x0 inside the box fixes b (so the LP is feasible)
+    and a sign-consistent dual pair (y0, z0) fixes c (so it is dual feasible,
+    hence bounded); a free column has z0 = 0."""
     rng = np.random.default_rng(seed)
     a = rng.standard_normal((m, n))
     a[rng.random((m, n)) < 0.3] = 0.0
-    kind = rng.integers(0, 3, size=n) if with_bounds else np.zeros(n, dtype=np.int64)
-    l = np.where(kind == 1, -np.inf, np.round(rng.uniform(-2, 0, size=n), 1))
-    u = np.where(kind == 0, np.inf, np.round(rng.uniform(1, 3, size=n), 1))
+    kind = rng.integers(0, 4 if with_free else 3, size=n) if with_bounds else np.zeros(n, dtype=np.int64)
+    l = np.where((kind == 1) | (kind == 3), -np.inf, np.round(rng.uniform(-2, 0, size=n), 1))
+    u = np.where((kind == 0) | (kind == 3), np.inf, np.round(rng.uniform(1, 3, size=n), 1))
     if not with_bounds:
         l = np.zeros(n)
-    x0 = np.where(np.isfinite(l), l, u - 1.0) + rng.uniform(0, 1, size=n)
+    x0 = np.where(np.isfinite(l), l, np.where(np.isfinite(u), u - 1.0, -0.5)) + rng.uniform(0, 1, size=n)
     x0 = np.minimum(x0, np.where(np.isfinite(u), u, np.inf))
     sense = np.full(m, ord("="), dtype=np.uint8)
     if with_ineq:
@@ -267,6 +269,7 @@ def tiny(seed: int, m: int = 3, n: int = 6, with_ineq: bool = True, with_bounds:
     y0 = np.where(sense == ord("<"), -np.abs(y0), np.where(sense == ord(">"), np.abs(y0), y0))
     z0 = rng.uniform(-1, 1, size=n)
     z0 = np.where(np.isinf(u), np.abs(z0), np.where(np.isinf(l), -np.abs(z0), z0))
+    z0 = np.where(np.isinf(l) & np.isinf(u), 0.0, z0)
     c = a.T @ y0 + z0
     rows, cols = np.nonzero(a)
     row_ptr, ci, va = _csr_from_coo(m, rows, cols, a[rows, cols])

@@ -18,6 +18,7 @@ def test_batch_matches_single_oracle_runs_fp64(kern):
     lps = _family(9, 5000)
     lps.append(lpgen.tiny(3, m=3, n=6))          # general bounds and senses
     lps.append(lpgen.transportation(6, 9, seed=4))
+    lps.append(lpgen.tiny(207, m=40, n=120, with_free=True))  # free columns
     print(f"[batch] kern={kern}: sizes {[lp.m for lp in lps]}", flush=True)
     bt = pdhg.Batch(lps, eps_rel=1e-7, lanes_at=kern, lanes_a=kern)
     res = bt.solve()

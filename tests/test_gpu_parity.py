@@ -27,6 +27,10 @@ def _cases():
         ("tiny_general_8", lambda: lpgen.tiny(8, m=4, n=9)),
         ("transport_12x30", lambda: lpgen.transportation(12, 30, seed=3)),
         ("ragged_deg_1_9", lambda: lpgen.planted(333, 777, seed=4, deg_range=(1, 9))),
+        ("tiny_free_201", lambda: lpgen.tiny(201, m=3, n=7, with_free=True)),
+        ("free_mixed_40x120", lambda: lpgen.tiny(207, m=40, n=120, with_free=True)),
+        ("hand_free_variable", lambda: lpgen.from_dense([[1.0, -1.0]], [0.0], [1.0, 0.0], [-np.inf, 1.0],
+                                                        [np.inf, np.inf], "=")),
     ]
 
 

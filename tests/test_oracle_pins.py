@@ -77,6 +77,24 @@ def test_tiny_lps_vs_vertex_enumeration(seed):
             assert y[i] >= 0.0
 
 
+@pytest.mark.parametrize("seed,m,n", [(200 + s, 3, 7) for s in range(6)] + [(207, 40, 120)])
+def test_free_columns_vs_highs(seed, m, n):
+    """Columns with no finite bound (section 2: z_j = 0 there, so the reduced
+    cost itself must vanish): the oracle's optimum equals HiGHS's, its free
+    columns carry z = 0 and a reduced cost within the dual tolerance."""
+    lp = lpgen.tiny(seed, m=m, n=n, with_free=True)
+    free = np.isinf(lp.l) & np.isinf(lp.u)
+    opt, _ = lp_ref.highs(lp)
+    s = OracleSolver(lp, eps_rel=1e-9, max_iter=400000)
+    r = s.solve()
+    assert r.status == 0
+    assert abs(r.pobj - opt) <= 1e-6 * (1 + abs(opt))
+    x, y, z = s.solution()
+    assert np.all(z[free] == 0.0)
+    lam = lp.c - lp.dense().T @ y
+    assert np.abs(lam[free]).max(initial=0.0) <= 1e-6 * (1 + np.abs(lp.c).max())
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_vanilla_pdhg_also_converges(seed):
     """halpern = 0 (plain PDHG with restarts) reaches the same vertex optimum."""
