@@ -21,7 +21,11 @@
  * readings used for those silent parts are:
  *   scaling   : 10 Ruiz passes (inf-norm, rows and columns from the same
  *               matrix), then one Pock-Chambolle pass with alpha = 1;
- *   step size : power iteration on M = Ahat'Ahat from v0 = 1/sqrt(n): each
+ *   step size : power iteration on M = Ahat'Ahat from v0 proportional to
+ *               1 + U_j (U_j the counter-based uniform draw of column j with
+ *               a fixed seed, OR_POWER_SEED), scaled to unit length; a
+ *               constant start lies in the null space of any matrix whose
+ *               scaled rows sum to zero, such as [1, -1].  Each
  *               step forms u = Ahat v, w = Ahat'u, rho = u'u (the Rayleigh
  *               quotient of the unit v) and lambda = ||w||, and stops at the
  *               first step whose eigen-residual ||w - rho v|| =
@@ -175,6 +179,9 @@ double or_push_uniform(uint64_t seed, int64_t j)
     uint64_t h = or_splitmix64(seed ^ ((uint64_t)j * 0x9E3779B97F4A7C15ULL));
     return (double)(h >> 11) * (1.0 / 9007199254740992.0);
 }
+
+/* seed of the power iteration's start vector (any fixed value) */
+#define OR_POWER_SEED 0x5DEECE66DULL
 
 /* ------------------------------------------------------------------------ */
 /* plain products with the unscaled and the scaled operator                 */
@@ -483,7 +490,15 @@ static void scale_and_step(or_solver *s)
 
     /* power iteration for the largest eigenvalue of Ahat'Ahat */
     double *v = dalloc(n), *w = dalloc(n), *av = dalloc(m);
-    for (int j = 0; j < n; j++) v[j] = 1.0 / sqrt((double)n);
+    {
+        csum vs = {0, 0};
+        for (int j = 0; j < n; j++) {
+            v[j] = 1.0 + or_push_uniform(OR_POWER_SEED, j);
+            cadd(&vs, v[j] * v[j]);
+        }
+        const double nv = sqrt(cval(&vs));
+        for (int j = 0; j < n; j++) v[j] = v[j] / nv;
+    }
     double lam = 0.0;
     s->power_steps = 0;
     for (int it = 0; it < s->p.power_iters; it++) {

@@ -408,14 +408,35 @@ __global__ __launch_bounds__(kBlock) void kb_power_finish(const int *__restrict_
     }
 }
 
-// v = 1 / sqrt(n_lp) on every column of an LP
+// the power iteration's start on every column of an LP, numbered from the
+// LP's first column (so an LP gets the start it gets when solved alone)
 __global__ __launch_bounds__(kBlock) void kb_fill_start(const int4 *__restrict__ rn, const int *__restrict__ coff,
                                                        double *__restrict__ v)
 {
     const int4 tl = rn[blockIdx.x];
     if ((int)threadIdx.x >= tl.z) return;
-    const double nl = (double)(coff[tl.x + 1] - coff[tl.x]);
-    v[tl.y + threadIdx.x] = 1.0 / sqrt(nl);
+    const int j = tl.y + threadIdx.x;
+    v[j] = power_start(j - coff[tl.x]);
+}
+
+// ps[3 count + lp] = the LP's ||v|| from its column tiles' partials
+__global__ __launch_bounds__(kBlock) void kb_start_norm(const int *__restrict__ rn_start, const double *__restrict__ pn,
+                                                       int count, double *__restrict__ ps)
+{
+    const int lp = blockIdx.x;
+    double q[1] = {0.0};
+    for (int t = rn_start[lp] + threadIdx.x; t < rn_start[lp + 1]; t += kBlock) q[0] += pn[t];
+    block_reduce<1>(q, 0u);
+    if (threadIdx.x == 0) ps[3 * count + lp] = sqrt(q[0]);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_div_start(const int4 *__restrict__ rn, const double *__restrict__ ps,
+                                                      int count, double *__restrict__ v)
+{
+    const int4 tl = rn[blockIdx.x];
+    if ((int)threadIdx.x >= tl.z) return;
+    const int j = tl.y + threadIdx.x;
+    v[j] = v[j] / ps[3 * count + tl.x];
 }
 
 __global__ __launch_bounds__(kBlock) void kb_normalize(const int4 *__restrict__ rn, const double *__restrict__ w,
@@ -493,8 +514,13 @@ hipError_t batch_setup(pdhg_batch *b)
     hipLaunchKernelGGL(kb_set_norms, dim3(b->count), dim3(kBlock), 0, st, b->sts, pm, pn, b->rm_start, b->rn_start);
     // power iteration per LP on its block of Ahat'Ahat
     double *v = s->xu, *w = s->zsol, *u = s->ax; // float64 work vectors of the right lengths
-    hipLaunchKernelGGL(kb_fill_start, dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, b->d_coff, v);
     hipMemsetAsync(b->lp_scalar, 0, sizeof(double) * 4 * (size_t)b->count, st);
+    if (b->n_rn > 0) { // start: v = (1 + U) / ||1 + U|| per LP, the norm in lp_scalar[3 count + lp]
+        hipLaunchKernelGGL(kb_fill_start, dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, b->d_coff, v);
+        hipLaunchKernelGGL((kb_sumsq<double>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, v, pn);
+        hipLaunchKernelGGL(kb_start_norm, dim3(b->count), dim3(kBlock), 0, st, b->rn_start, pn, b->count, b->lp_scalar);
+        hipLaunchKernelGGL(kb_div_start, dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, b->lp_scalar, b->count, v);
+    }
     std::vector<double> done((size_t)b->count, 0.0);
     constexpr int kPowerBatch = 32; // steps launched between reads of the done flags
     for (int it = 0; it < s->p.power_iters && s->m > 0 && s->n > 0; it += kPowerBatch) {

@@ -177,7 +177,7 @@ struct pdhg_batch {
     int *rn_start = nullptr, *rm_start = nullptr; // first reduction tile of each LP (count + 1)
     pdhg::DevState *sts = nullptr, *sts_host = nullptr;
     double *part = nullptr;                // per-tile partial sums
-    double *lp_scalar = nullptr;           // per-LP power iteration {lambda, done, steps} x count
+    double *lp_scalar = nullptr;           // per-LP power iteration {lambda, done, steps, ||v0||} x count
     double *rep = nullptr, *rep_host = nullptr; // per-LP report values
     int *active = nullptr;                 // per-LP flag: takes part in the current phase
     std::vector<int> active_host;

@@ -301,4 +301,12 @@ __device__ __forceinline__ double push_unit(uint64_t seed, int64_t j)
     return (double)(h >> 11) * (1.0 / 9007199254740992.0);
 }
 
+// The power iteration's start vector, before scaling to unit length:
+// v_j = 1 + U_j, U_j the same counter-based draw with a fixed seed.  Positive
+// like a constant start (a large weight on the top singular vector of a
+// nonnegative matrix), but not in the null space of matrices whose scaled
+// rows sum to zero, such as [1, -1], where a constant start gives u = 0.
+constexpr uint64_t kPowerSeed = 0x5DEECE66DULL;
+__device__ __forceinline__ double power_start(int64_t j) { return 1.0 + push_unit(kPowerSeed, j); }
+
 } // namespace pdhg

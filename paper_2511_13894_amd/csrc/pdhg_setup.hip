@@ -4,6 +4,7 @@
 
 #include "pdhg_device.hpp"
 #include "pdhg_internal.hpp"
+#include "pdhg_kernels.hpp"
 
 namespace pdhg {
 
@@ -365,6 +366,27 @@ __global__ __launch_bounds__(kBlock) void k_sumsq_partials(int len, const double
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
+__global__ __launch_bounds__(kBlock) void k_power_start(int64_t len, double *__restrict__ v)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) v[i] = power_start(i);
+}
+
+// out[0] = sqrt of the sum of part[0, g), fixed order
+__global__ __launch_bounds__(kBlock) void k_norm_finish(int g, const double *__restrict__ part, double *__restrict__ out)
+{
+    double q[1] = {0.0};
+    for (int i = threadIdx.x; i < g; i += kBlock) q[0] += part[i];
+    block_reduce<1>(q, 0u);
+    if (threadIdx.x == 0) out[0] = sqrt(q[0]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_div_scalar(int64_t len, double *__restrict__ v, const double *__restrict__ d)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) v[i] = v[i] / d[0];
+}
+
 // rho = sum of part[0, gm), w'w = sum of part[gm, gm + gn), fixed order
 __global__ __launch_bounds__(kBlock) void k_power_finish(int gm, int gn, const double *__restrict__ part, double tol,
                                                         double *__restrict__ pw)
@@ -410,9 +432,14 @@ hipError_t power_iteration(pdhg_solver *s)
     if ((e = hipMalloc(&u, (size_t)(m > 0 ? m : 1) * sizeof(double))) != hipSuccess) return e;
     if ((e = hipMalloc(&pw, 4 * sizeof(double))) != hipSuccess) return e;
     hipMemsetAsync(pw, 0, 4 * sizeof(double), st);
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, st, (int64_t)n, v,
-                       n > 0 ? 1.0 / sqrt((double)n) : 0.0);
     const int gm = grid_for(m, kBlock, kMaxRedBlocks), gn = grid_for(n, kBlock, kMaxRedBlocks);
+    if (n > 0) { // start: v = (1 + U) / ||1 + U||, the norm kept in pw[3]
+        const int gv = grid_for(n, kBlock, 1 << 30);
+        hipLaunchKernelGGL(k_power_start, dim3(gv), dim3(kBlock), 0, st, (int64_t)n, v);
+        hipLaunchKernelGGL(k_sumsq_partials, dim3(gn), dim3(kBlock), 0, st, n, v, s->partials);
+        hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(kBlock), 0, st, gn, s->partials, pw + 3);
+        hipLaunchKernelGGL(k_div_scalar, dim3(gv), dim3(kBlock), 0, st, (int64_t)n, v, pw + 3);
+    }
     double pw_host[4] = {0.0, 0.0, 0.0, 0.0};
     constexpr int kPowerBatch = 32; // steps launched between reads of the done flag
     for (int it = 0; it < s->p.power_iters && n > 0 && m > 0; it += kPowerBatch) {

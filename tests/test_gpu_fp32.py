@@ -23,6 +23,7 @@ def _rel(a, b):
     ("c0_s0", lambda: lpgen.config0(0)),
     ("c0_s3", lambda: lpgen.config0(3)),
     ("transport_40x100", lambda: lpgen.transportation(40, 100, seed=5)),
+    ("free_mixed_40x120", lambda: lpgen.tiny(207, m=40, n=120, with_free=True)),
 ], ids=lambda v: v if isinstance(v, str) else "")
 def test_fp32_mixed_error_against_fp64_oracle(name, make):
     lp = make()
