@@ -263,6 +263,11 @@ def main():
                              "algorithmic_bytes_per_launch": int(tim.bytes_dual if kname == "k_primal"
                                                                  else tim.bytes_primal)},
             "timed_launches": int(samples), "copy_probe_gbs": round(copy_gbs, 1)}
+    # the two halves of one PDHG iteration together (they take about the same time)
+    pair_bytes, pair_ms = tim.bytes_primal + tim.bytes_dual, prim_ms + dual_ms
+    roof["iteration_pair"] = {"algorithmic_bytes": int(pair_bytes), "us": round(pair_ms * 1e3, 2),
+                              "achieved": round(pair_bytes / (pair_ms * 1e-3) / 1e9, 1),
+                              "frac": round(pair_bytes / (pair_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 2), "higher_is_better": True,

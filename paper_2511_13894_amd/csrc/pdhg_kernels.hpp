@@ -95,7 +95,11 @@ __device__ __forceinline__ void tile_row_sums(int r0, int rows, const int *__res
     constexpr int C = kTileU * NT;
     const int tid = threadIdx.x;
     const int beg = ptr[r0], end = ptr[r0 + rows]; // uniform across the workgroup
-    for (int k = tid; k <= rows; k += NT) s_ptr[k] = ptr[r0 + k];
+    // The tile's row pointers (rows + 1 <= NT + 1 of them) stay in registers
+    // until the products go to LDS: storing them at once would wait for
+    // their loads, and with them for every load issued earlier.
+    const int pa = ptr[r0 + (tid < rows ? tid : rows)];
+    const int pb = T >= NT ? ptr[r0 + (tid + NT < rows ? tid + NT : rows)] : 0;
     const int my_row = tid / G, sub = tid % G;
     const bool have = my_row < rows;
     double acc = 0.0;
@@ -124,6 +128,10 @@ __device__ __forceinline__ void tile_row_sums(int r0, int rows, const int *__res
         for (int u = 0; u < kTileU; u++) {
             const int k = cs + tid + u * NT;
             if (k < ce) s_prod[k - cs] = v[u] * g[u];
+        }
+        if (cs == beg) {
+            if (tid <= rows) s_ptr[tid] = pa;
+            if (T >= NT && tid + NT <= rows) s_ptr[tid + NT] = pb;
         }
         __syncthreads(); // products, and on the first chunk the row pointers
         const int rb = have ? s_ptr[my_row] : 0, re = have ? s_ptr[my_row + 1] : 0;
