@@ -150,7 +150,12 @@ def bench_batch(args, pdhg, copy_gbs):
                      "launch_us": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": int(nbytes),
                      "other_kernel": {"name": other[0], "launch_us": round(other[1] * 1e3, 2),
                                       "algorithmic_bytes_per_launch": int(other[2])},
-                     "timed_launches": int(samples), "copy_probe_gbs": round(copy_gbs, 1)},
+                     "timed_launches": int(samples), "copy_probe_gbs": round(copy_gbs, 1),
+                     "iteration_pair": {"algorithmic_bytes": int(bytes_p + bytes_d),
+                                        "us": round((prim_ms + dual_ms) * 1e3, 2),
+                                        "achieved": round((bytes_p + bytes_d) / ((prim_ms + dual_ms) * 1e-3) / 1e9, 1),
+                                        "frac": round((bytes_p + bytes_d) / ((prim_ms + dual_ms) * 1e-3) / 1e9
+                                                      / HBM_PEAK_GBS, 4)}},
         "detail": {"steps": details},
     }
     if not args.no_cpu_baseline:
