@@ -11,7 +11,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 OUT = PKG / "libpdhg.so"
 BUILD = PKG / "_build"
-SOURCES = ["pdhg_setup.hip", "pdhg_iter.hip", "pdhg_sell.hip", "pdhg_batch.hip", "pdhg_mlp.hip", "pdhg_learned.hip",
+SOURCES = ["pdhg_setup.hip", "pdhg_iter.hip", "pdhg_sell.hip", "pdhg_compact.hip", "pdhg_batch.hip", "pdhg_mlp.hip", "pdhg_learned.hip",
            "pdhg_capi.cpp", "pdhg_mlp_capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

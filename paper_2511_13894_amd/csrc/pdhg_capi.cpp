@@ -30,6 +30,19 @@ int fail(int code, const std::string &msg)
 
 hipError_t init_norms(pdhg_solver *s);
 
+// byte model of the two kernels: v = bytes per matrix value and n-vector
+// entry (4 in the mixed mode, 8 otherwise), m-vectors are float64, 4 bytes
+// per index
+void model_bytes(const pdhg_solver *s, int64_t *bytes_primal, int64_t *bytes_dual)
+{
+    const int64_t v = s->fp32 ? 4 : 8, m = s->m, n = s->n, nz = s->nnz;
+    // primal: row pointers, indices + values, y gathered once, reads x, chat,
+    // x_anchor, lhat, uhat, writes x, xbar
+    *bytes_primal = 4 * (n + 1) + (4 + v) * nz + 8 * m + 6 * v * n + 8 * n;
+    // dual: row pointers, indices + values, xbar gathered once, reads y, bhat,
+    // y_anchor, sense byte, writes y
+    *bytes_dual = 4 * (m + 1) + (4 + v) * nz + v * n + 4 * 8 * m + m;
+}
 } // namespace pdhg
 
 using namespace pdhg;
@@ -56,6 +69,7 @@ void dalloc(T **p, size_t count)
 
 void free_all(pdhg_solver *s)
 {
+    (void)push_compact_end(s, false);
     void *ptrs[] = {s->rp,   s->ci, s->av,  s->tp,   s->ti,     s->tperm, s->atv,  s->b,   s->c,       s->l,
                     s->u,    s->sense0, s->dr, s->dc, s->ahat, s->ahat_t, s->x,   s->y,     s->xa,   s->ya,
                     s->xbar, s->xp, s->yp,  s->ch,   s->bh,     s->lh,    s->uh,   s->xs,  s->ys,      s->sense,
@@ -123,6 +137,10 @@ int run_phase(pdhg_solver *s, int64_t iters, int mode, double t0)
                 s->t_primal_ms += a;
                 s->t_dual_ms += b2;
                 s->t_samples += 1;
+                int64_t bp = 0, bd = 0;
+                model_bytes(s, &bp, &bd); // of the model iterated now (the push may run on fewer columns)
+                s->t_bytes_primal += (double)bp;
+                s->t_bytes_dual += (double)bd;
             }
             (void)hipGetLastError(); // a failed timing query must not leak into later checks
         }
@@ -302,6 +320,7 @@ void pdhg_default_params(pdhg_params *p)
     p->timing = 0;
     p->autotune = 0;
     p->record_history = 0;
+    p->push_compact = 1;
 }
 
 const char *pdhg_last_error(void) { return g_last_error.c_str(); }
@@ -581,8 +600,11 @@ static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r
         s->has_candidate = false;
         s->t_host = 0;
         s->next_check = s->p.push_min_iters;
-        // CP6
+        // CP6, on the free columns unless learned fixes may be undone or the
+        // dual half uses the sliced layout of the full matrix
+        if (s->p.push_compact && !net && s->kern_a != kSell) HIPCHK(push_compact_begin(s));
         int status = run_phase(s, s->p.push_max_iter, 2, t0);
+        HIPCHK(push_compact_end(s, true));
         // CP7: (xhat, y, z)
         if (s->has_candidate) HIPCHK(unscale(s, s->xp, nullptr, s->xpush, nullptr));
         else HIPCHK(hipMemcpyAsync(s->xpush, s->xu, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
@@ -599,6 +621,7 @@ static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r
             r->n_learned_undo = cnt[1];
         }
     } catch (const HipFailure &f) {
+        (void)push_compact_end(s, false); // the full model's arrays back in the handle
         return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
     }
     return PDHG_OK;
@@ -892,16 +915,12 @@ int pdhg_get_timing(pdhg_solver *s, pdhg_timing *t)
         t->primal_ms = s->t_primal_ms / (double)s->t_samples;
         t->dual_ms = s->t_dual_ms / (double)s->t_samples;
     }
-    // byte model of the two kernels: v = bytes per matrix value and n-vector
-    // entry (4 in the mixed mode, 8 otherwise), m-vectors are float64, 4 bytes
-    // per index
-    const int64_t v = s->fp32 ? 4 : 8, m = s->m, n = s->n, nz = s->nnz;
-    // primal: row pointers, indices + values, y gathered once, reads x, chat,
-    // x_anchor, lhat, uhat, writes x, xbar
-    t->bytes_primal = 4 * (n + 1) + (4 + v) * nz + 8 * m + 6 * v * n + 8 * n;
-    // dual: row pointers, indices + values, xbar gathered once, reads y, bhat,
-    // y_anchor, sense byte, writes y
-    t->bytes_dual = 4 * (m + 1) + (4 + v) * nz + v * n + 4 * 8 * m + m;
+    if (s->t_samples > 0) { // mean over the timed launches (solve and push models)
+        t->bytes_primal = (int64_t)(s->t_bytes_primal / (double)s->t_samples);
+        t->bytes_dual = (int64_t)(s->t_bytes_dual / (double)s->t_samples);
+    } else {
+        model_bytes(s, &t->bytes_primal, &t->bytes_dual);
+    }
     t->lanes_at = s->kern_at;
     t->lanes_a = s->kern_a;
     return PDHG_OK;

@@ -153,10 +153,29 @@ struct pdhg_solver {
     unsigned *lcount = nullptr;  // [fixed, undone]
     bool learned_active = false;
 
+    // push model without its fixed columns while the push iterates
+    // (pdhg_compact.hip): the compact arrays, and the full model's fields they
+    // replace in this struct until the push ends
+    struct PushCompact {
+        bool active = false;
+        int nf = 0, nnz = 0;
+        int *flag = nullptr, *newid = nullptr, *keep = nullptr; // free flag and index of every full column; full index of each compact one
+        int *tp = nullptr, *ti = nullptr, *rp = nullptr, *ci = nullptr;
+        void *ahat = nullptr, *ahat_t = nullptr, *lh = nullptr, *uh = nullptr;
+        void *x = nullptr, *xa = nullptr, *xbar = nullptr, *xp = nullptr;
+        double *ch = nullptr, *dc = nullptr, *bt = nullptr;
+        int n0 = 0, nnz0 = 0, red_blocks_n0 = 1;
+        int *tp0 = nullptr, *ti0 = nullptr, *rp0 = nullptr, *ci0 = nullptr;
+        void *ahat0 = nullptr, *ahat_t0 = nullptr, *lh0 = nullptr, *uh0 = nullptr, *bh0 = nullptr;
+        void *x0 = nullptr, *xa0 = nullptr, *xbar0 = nullptr, *xp0 = nullptr;
+        double *ch0 = nullptr, *dc0 = nullptr;
+    } pc;
+
     // live kernel timing: events around one primal and one dual launch per cycle
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr}; // primal start/stop, dual start/stop
     double t_primal_ms = 0.0, t_dual_ms = 0.0;
     int64_t t_samples = 0;
+    double t_bytes_primal = 0.0, t_bytes_dual = 0.0; // algorithmic bytes of the timed launches
 };
 
 // A batch of independent LPs stored as one block-diagonal model: every
@@ -223,6 +242,12 @@ hipError_t launch_start_vectors(pdhg_solver *s, bool fresh_start);
 hipError_t unscale(pdhg_solver *s, const void *xh, const void *yh, double *xo, double *yo);
 hipError_t report(pdhg_solver *s, const double *x, const double *y, double *z, pdhg_kkt_report *k);
 hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, double theta);
+// push on the free columns only: build the compact model and put it in place,
+// or (end) put x and x+ back into the full vectors and restore the full model
+hipError_t push_compact_begin(pdhg_solver *s);
+hipError_t push_compact_end(pdhg_solver *s, bool scatter);
+// algorithmic bytes of one primal and one dual launch on the current model
+void model_bytes(const pdhg_solver *s, int64_t *bytes_primal, int64_t *bytes_dual);
 hipError_t capture_cycle(pdhg_solver *s, int len, int mode);
 hipError_t copy_probe(int64_t bytes, int reps, double *gbps);
 

@@ -38,6 +38,7 @@ class Params(C.Structure):
         ("push_obj_scale", C.c_double), ("push_max_iter", C.c_int64), ("time_limit", C.c_double),
         ("stream", C.c_void_p), ("verbosity", C.c_int32), ("lanes_at", C.c_int32), ("lanes_a", C.c_int32),
         ("use_graph", C.c_int32), ("timing", C.c_int32), ("autotune", C.c_int32), ("record_history", C.c_int32),
+        ("push_compact", C.c_int32),
     ]
 
 

@@ -50,6 +50,7 @@ def test_default_params_and_argument_errors_without_gpu():
     lib = pdhg.load()
     p = pdhg.default_params()
     assert p.eps_rel == 1e-6 and p.check_every == 64 and p.ruiz_iters == 10 and p.power_iters == 4000 and p.power_tol == 1e-3
+    assert p.push_compact == 1 and p.record_history == 0
     assert p.halpern == 1 and p.reflect_gamma == 1.0 and p.push_min_iters == 100
     h = ctypes.c_void_p()
     rp = (ctypes.c_int64 * 2)(0, 1)

@@ -1,0 +1,93 @@
+"""The corner push on its free columns only (push_compact = 1, the default)
+against the push on the full model (push_compact = 0) and the oracle.
+
+Fixed columns keep their value, so dropping them and folding their constant
+part of A x into the right-hand side leaves residuals, gap, restarts and the
+stopping test unchanged up to rounding: same fixing decisions, same status,
+the same iteration count (a rounding-level difference may move one check),
+and the same pushed point."""
+import numpy as np
+import pytest
+
+from oracle import OracleSolver
+from paper_2511_13894_amd import lpgen, pdhg
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_inf(a, b):
+    return float(np.abs(a - b).max() / max(1.0, np.abs(b).max())) if a.size else 0.0
+
+
+def _cases():
+    return [
+        ("c0_s0", lambda: lpgen.config0(0)),
+        ("ineq_ub_small", lambda: lpgen.config1(seed=3, m=300, n=1200)),
+        ("free_mixed_40x120", lambda: lpgen.tiny(207, m=40, n=120, with_free=True)),
+        ("transport_12x30", lambda: lpgen.transportation(12, 30, seed=3)),
+        ("ragged_deg_1_9", lambda: lpgen.planted(333, 777, seed=4, deg_range=(1, 9))),
+    ]
+
+
+@pytest.mark.parametrize("name,make", _cases(), ids=[c[0] for c in _cases()])
+def test_compact_push_matches_full_push_and_oracle(name, make):
+    print(f"[compact] {name}", flush=True)
+    lp = make()
+    eps = 1e-8
+    out = {}
+    for compact in (0, 1):
+        g = pdhg.Solver(lp, eps_rel=eps, max_iter=400000, push_compact=compact)
+        r = g.solve()
+        assert r.status == pdhg.PDHG_OPTIMAL
+        p = g.corner_push(17)
+        x, y, _ = g.get_solution()
+        xi, yi = g.get_iterate()
+        out[compact] = (p, x, y, xi, yi)
+    o = OracleSolver(lp, eps_rel=eps, max_iter=400000)
+    o.solve()
+    po = o.corner_push(17)
+    xo = o.solution()[0]
+    (p0, x0, y0, xi0, yi0), (p1, x1, y1, xi1, yi1) = out[0], out[1]
+    print(f"[compact] {name}: fixed {p1.n_fix_lower}+{p1.n_fix_upper} of {lp.n}, rows to '=' {p1.n_rows_to_eq}; "
+          f"push iterations compact {p1.iters} / full {p0.iters} / oracle {po.iters}; "
+          f"|x_compact - x_full| {rel_inf(x1, x0):.2e}", flush=True)
+    for p in (p0, p1):
+        assert (p.n_fix_lower, p.n_fix_upper, p.n_rows_to_eq) == (po.n_fix_lower, po.n_fix_upper, po.n_rows_to_eq)
+        assert p.status == po.status
+        assert p.before.p_off == po.before.p_off
+    assert abs(p1.iters - p0.iters) <= 64 and abs(p1.iters - po.iters) <= 64
+    np.testing.assert_array_equal(y1, y0)  # the solve's y, returned by both
+    if p1.status == pdhg.PDHG_PUSH_DONE:
+        assert p1.after.rel_p <= eps * 1.0000001
+    if p1.iters == p0.iters:
+        assert rel_inf(x1, x0) <= 1e-8
+        assert (p1.after.p_off, p1.after.candidates) == (p0.after.p_off, p0.after.candidates)
+        # the last iterate too: fixed columns at their bound, free ones as in the full push
+        assert rel_inf(xi1, xi0) <= 1e-8 and rel_inf(yi1, yi0) <= 1e-8
+    if p1.iters == po.iters:
+        assert rel_inf(x1, xo) <= 1e-7
+
+
+def test_compact_push_fp32_and_timing_bytes():
+    """FP32-mixed compact push reaches the full push's answer; the timed
+    launches of the push carry the compact model's (smaller) byte counts."""
+    lp = lpgen.config1(seed=3, m=300, n=1200)
+    res = {}
+    for compact in (0, 1):
+        g = pdhg.Solver(lp, precision="fp32", eps_rel=1e-6, max_iter=400000, push_compact=compact, timing=1)
+        g.solve()
+        t_solve = g.get_timing()
+        p = g.corner_push(5)
+        t_all = g.get_timing()
+        res[compact] = (p, g.get_solution()[0], t_solve, t_all)
+    (p0, x0, ts0, ta0), (p1, x1, ts1, ta1) = res[0], res[1]
+    print(f"[compact] fp32: push iterations {p1.iters} / {p0.iters}; mean primal bytes per timed launch "
+          f"{ta1.bytes_primal} (compact) / {ta0.bytes_primal} (full)", flush=True)
+    assert p1.status == p0.status
+    assert (p1.n_fix_lower, p1.n_fix_upper) == (p0.n_fix_lower, p0.n_fix_upper)
+    assert abs(p1.iters - p0.iters) <= 64
+    assert ts1.bytes_primal == ts0.bytes_primal  # the solve is the same
+    if p1.n_fix_lower + p1.n_fix_upper > 0 and ta1.samples > ts1.samples:
+        assert ta1.bytes_primal < ta0.bytes_primal
+    if p1.iters == p0.iters:
+        assert rel_inf(x1, x0) <= 1e-5
