@@ -4,6 +4,9 @@ event timing on).  The oracle cannot finish these solves, so the checks are
 on what it can compute at any size: the setup (scaling, step size), the first
 iterates, the float64 KKT of the GPU's answer evaluated by the oracle's own
 code, and the push's fixing decisions recounted from that answer."""
+import json
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -93,6 +96,19 @@ def test_c1_setup_iterates_solve_and_push(c1):
           flush=True)
     assert (p.after.p_off, p.after.candidates, p.after.est_primal) == (ka.p_off, ka.candidates, ka.est_primal)
     assert abs(p.after.pobj - ka.pobj) <= 1e-12 * max(1.0, abs(ka.pobj))
+    # the oracle's own full solve and push of this LP (tests/golden/make_c1_oracle.py)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c1_oracle.json")))
+    gs, gp = gold["solve"], gold["push"]
+    print(f"[full] c1 vs the oracle's full run: solve {r.iters}/{gs['iters']} iterations, push {p.iters}/{gp['iters']}, "
+          f"off-bound after {p.after.p_off}/{gp['p_off_after']}", flush=True)
+    assert r.iters == gs["iters"] and r.restarts == gs["restarts"]
+    assert abs(r.pobj - gs["pobj"]) <= 1e-9 * abs(gs["pobj"])
+    assert (p.n_fix_lower, p.n_fix_upper, p.n_rows_to_eq) == (gp["n_fix_lower"], gp["n_fix_upper"], gp["n_rows_to_eq"])
+    assert (p.before.p_off, p.before.candidates) == (gp["p_off_before"], gp["candidates_before"])
+    assert p.status == gp["status"] and abs(p.iters - gp["iters"]) <= 64
+    if p.iters == gp["iters"]:
+        assert (p.after.p_off, p.after.candidates, p.after.est_primal) == \
+            (gp["p_off_after"], gp["candidates_after"], gp["est_primal_after"])
 
 
 def test_c2_setup_iterates_and_solve(c2):
