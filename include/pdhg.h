@@ -55,7 +55,8 @@ enum pdhg_status {
     PDHG_ITER_LIMIT = 1, /* max_iter (push: push_max_iter) reached              */
     PDHG_NUMERICAL = 2,  /* a non-finite value appeared in the candidate        */
     PDHG_PUSH_DONE = 3,  /* push: primal residual back at eps_rel (section 3.1) */
-    PDHG_TIME_LIMIT = 4  /* time_limit seconds elapsed (checked between cycles) */
+    PDHG_TIME_LIMIT = 4, /* time_limit seconds elapsed (checked between cycles) */
+    PDHG_PUSH_SKIPPED = 5 /* push gate closed: too few candidates (section 4.2)  */
 };
 
 /* return codes */
@@ -125,6 +126,15 @@ typedef struct pdhg_params {
                               Not used by the learned push (its undo frees fixed
                               columns again), the sliced ELLPACK dual or the batch.
                               0: iterate on the full push model                       */
+    int32_t push_gate;     /* 1: push only when the solve's answer has at least
+                              max(push_gate_rows * m, push_gate_min) candidates (off
+                              bound, |z| < 1e-6): the selection rule of section 4.2,
+                              which asks for a substantial number of primal push steps
+                              and enough freedom to reduce them.  Otherwise the push
+                              returns PDHG_PUSH_SKIPPED with the solve's point.  0
+                              (default): always push                                   */
+    double push_gate_rows; /* 2.0 */
+    int64_t push_gate_min; /* 100000 */
 } pdhg_params;
 
 /* outcome of pdhg_solve / pdhg_iterate, evaluated on the original model */
@@ -152,7 +162,8 @@ typedef struct pdhg_kkt_report {
 } pdhg_kkt_report;
 
 typedef struct pdhg_push_result {
-    int32_t status;       /* PDHG_PUSH_DONE, ITER_LIMIT, TIME_LIMIT or NUMERICAL       */
+    int32_t status;       /* PDHG_PUSH_DONE, ITER_LIMIT, TIME_LIMIT, NUMERICAL or
+                             PUSH_SKIPPED (gate closed: after = before, 0 iterations) */
     int32_t pad_;
     int64_t iters;        /* push iterations                                          */
     int64_t restarts;
@@ -217,6 +228,11 @@ int pdhg_kkt(pdhg_solver *s, const double *x, const double *y, pdhg_kkt_report *
  * (x, y) and z = reduced costs; after a push (xhat, y, z) with the solve's y
  * and z (Algorithm 1 returns them unchanged).  Any pointer may be NULL. */
 int pdhg_get_solution(pdhg_solver *s, double *x, double *y, double *z);
+
+/* The solve's own answer (x, y, z), unscaled, also after a push: the point a
+ * crossover started before the push would take, where pdhg_get_solution then
+ * gives the pushed one.  Errors: STATE before a solve has a candidate. */
+int pdhg_get_solve_solution(pdhg_solver *s, double *x, double *y, double *z);
 
 /* Current PDHG iterate (x, y) of the running phase, unscaled. */
 int pdhg_get_iterate(pdhg_solver *s, double *x, double *y);
@@ -315,6 +331,9 @@ int pdhg_batch_corner_push(pdhg_batch *b, const uint64_t *seeds, pdhg_push_resul
 /* Solution of LP i, unscaled (x: n_i, y: m_i, z: n_i; any may be NULL);
  * after the push x is the pushed x. */
 int pdhg_batch_get_solution(pdhg_batch *b, int32_t i, double *x, double *y, double *z);
+
+/* LP i's solve answer, also after the push (see pdhg_get_solve_solution). */
+int pdhg_batch_get_solve_solution(pdhg_batch *b, int32_t i, double *x, double *y, double *z);
 
 /* Aggregate timings and sizes of the batch. */
 int pdhg_batch_get_report(pdhg_batch *b, pdhg_batch_report *r);

@@ -15,7 +15,7 @@ _HERE = Path(__file__).resolve().parent
 _SRC = _HERE / "pdhg_oracle.c"
 _LIB = _HERE / "liboracle.so"
 
-STATUS = {"OPTIMAL": 0, "ITER_LIMIT": 1, "NUMERICAL": 2, "PUSH_DONE": 3}
+STATUS = {"OPTIMAL": 0, "ITER_LIMIT": 1, "NUMERICAL": 2, "PUSH_DONE": 3, "PUSH_SKIPPED": 5}
 
 
 def build_oracle(force: bool = True) -> Path:
@@ -38,6 +38,7 @@ class OrParams(C.Structure):
         ("eta_safety", C.c_double), ("reflect_gamma", C.c_double), ("power_tol", C.c_double),
         ("push_min_iters", C.c_int32), ("pad_", C.c_int32),
         ("push_obj_scale", C.c_double), ("push_max_iter", C.c_int64),
+        ("push_gate", C.c_int32), ("pad2_", C.c_int32), ("push_gate_rows", C.c_double), ("push_gate_min", C.c_int64),
     ]
 
 

@@ -59,6 +59,7 @@ enum {
     OR_ITER_LIMIT = 1,
     OR_NUMERICAL = 2,
     OR_PUSH_DONE = 3,
+    OR_PUSH_SKIPPED = 5, /* gate of section 4.2 closed: too few candidates */
     OR_ERR_ARG = -1,
     OR_ERR_STATE = -2
 };
@@ -80,6 +81,13 @@ typedef struct {
     int32_t pad_;
     double push_obj_scale;
     int64_t push_max_iter;
+    /* selection rule of section 4.2 (off by default): push only when the
+       solve's answer has at least max(push_gate_rows * m, push_gate_min)
+       candidates (off bound with |z| < tol) */
+    int32_t push_gate;
+    int32_t pad2_;
+    double push_gate_rows;
+    int64_t push_gate_min;
 } or_params;
 
 typedef struct {
@@ -386,6 +394,9 @@ static void set_defaults(or_params *p)
     p->push_min_iters = 100;
     p->pad_ = 0;
     p->push_obj_scale = 1.0;
+    p->push_gate = 0;
+    p->push_gate_rows = 2.0;
+    p->push_gate_min = 100000;
     p->push_max_iter = 1000000;
 }
 
@@ -828,6 +839,17 @@ int or_corner_push(or_solver *s, uint64_t seed, or_push_result *r)
     /* CP1: (x, y, z) of the solve on M */
     reduced_costs(s, s->xsol, s->ysol, s->zsol, ax, &r->before);
     corner_counts(s, s->xsol, ax, s->ysol, s->zsol, &r->before);
+    if (s->p.push_gate &&
+        (double)r->before.candidates < fmax(s->p.push_gate_rows * (double)m, (double)s->p.push_gate_min)) {
+        /* too few candidates: no push, the solve's point is the answer */
+        r->status = OR_PUSH_SKIPPED;
+        r->rel_p_push = NAN;
+        r->after = r->before;
+        memcpy(s->xpush, s->xsol, sizeof(double) * (size_t)n);
+        s->in_push = 1;
+        free(ax);
+        return OR_PUSH_SKIPPED;
+    }
     double ea = s->p.eps_abs;
     /* CP2: bounds (stored scaled: the scaled candidate itself) */
     for (int j = 0; j < n; j++) {

@@ -30,6 +30,13 @@ int fail(int code, const std::string &msg)
 
 hipError_t init_norms(pdhg_solver *s);
 
+// candidates a push needs with the gate on (section 4.2): max(rows * m, min)
+double gate_threshold(const pdhg_params &p, int64_t m)
+{
+    const double a = p.push_gate_rows * (double)m, b = (double)p.push_gate_min;
+    return a > b ? a : b;
+}
+
 // byte model of the two kernels: v = bytes per matrix value and n-vector
 // entry (4 in the mixed mode, 8 otherwise), m-vectors are float64, 4 bytes
 // per index
@@ -321,6 +328,9 @@ void pdhg_default_params(pdhg_params *p)
     p->autotune = 0;
     p->record_history = 0;
     p->push_compact = 1;
+    p->push_gate = 0;
+    p->push_gate_rows = 2.0;
+    p->push_gate_min = 100000;
 }
 
 const char *pdhg_last_error(void) { return g_last_error.c_str(); }
@@ -580,6 +590,17 @@ static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r
         HIPCHK(hipMemcpyAsync(s->ys, s->yp, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
         HIPCHK(unscale(s, s->xs, s->ys, s->xu, s->yu));
         HIPCHK(report(s, s->xu, s->yu, s->zsol, &r->before));
+        if (s->p.push_gate && (double)r->before.candidates < gate_threshold(s->p, s->m)) {
+            // section 4.2's selection rule: too few candidates to be worth a push
+            HIPCHK(hipMemcpyAsync(s->xpush, s->xu, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+            r->after = r->before;
+            r->status = PDHG_PUSH_SKIPPED;
+            r->rel_p_push = NAN;
+            r->seconds = now_s() - t0;
+            s->in_push = true; // the handle's one push (skipped); pdhg_get_solution gives the solve's x
+            return PDHG_OK;
+        }
         if (net) { // predictor on the solve's state, before the model changes
             const size_t n = (size_t)(s->n > 0 ? s->n : 1);
             if (!s->feat_raw) dalloc(&s->feat_raw, 16 * n);
@@ -700,6 +721,27 @@ int pdhg_get_solution(pdhg_solver *s, double *x, double *y, double *z)
         }
         const double *cx = s->in_push ? s->xpush : s->xu;
         if (x) HIPCHK(hipMemcpyAsync(x, cx, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
+        if (y) HIPCHK(hipMemcpyAsync(y, s->yu, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToHost, st));
+        if (z) HIPCHK(hipMemcpyAsync(z, s->zsol, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_get_solve_solution(pdhg_solver *s, double *x, double *y, double *z)
+{
+    if (!s) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
+    if (!s->solved) return fail(PDHG_ERR_STATE, "no solve answer yet");
+    try {
+        hipStream_t st = s->stream;
+        if (!s->in_push) {
+            pdhg_kkt_report tmp;
+            solution_report(s, &tmp);
+        }
+        // xu, yu, zsol hold the solve's answer; the push writes its x to xpush
+        if (x) HIPCHK(hipMemcpyAsync(x, s->xu, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
         if (y) HIPCHK(hipMemcpyAsync(y, s->yu, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToHost, st));
         if (z) HIPCHK(hipMemcpyAsync(z, s->zsol, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1151,7 +1193,16 @@ static int batch_push_common(pdhg_batch *b, const uint64_t *seeds, pdhg_push_res
         HIPCHK(batch_report(b, s->xu, s->yu, s->zsol, before.data()));
         std::vector<int> solve_status((size_t)b->count);
         for (int i = 0; i < b->count; i++) solve_status[i] = b->sts_host[i].status;
-        HIPCHK(hipMemcpy(b->active, b->active_host.data(), sizeof(int) * (size_t)b->count, hipMemcpyHostToDevice));
+        // per-LP gate (section 4.2): a gated LP stays at its solve's answer
+        std::vector<int> act = b->active_host;
+        std::vector<char> gated((size_t)b->count, 0);
+        if (s->p.push_gate)
+            for (int i = 0; i < b->count; i++)
+                if (act[i] && (double)before[i].candidates < gate_threshold(s->p, b->roff[i + 1] - b->roff[i])) {
+                    act[i] = 0;
+                    gated[i] = 1;
+                }
+        HIPCHK(hipMemcpy(b->active, act.data(), sizeof(int) * (size_t)b->count, hipMemcpyHostToDevice));
         if (net) { // predictor on every LP's solve state, before the models change
             batch_learned_buffers(b);
             HIPCHK(hipMemsetAsync(s->lcount, 0, 2 * sizeof(unsigned) * (size_t)b->count, st));
@@ -1175,8 +1226,8 @@ static int batch_push_common(pdhg_batch *b, const uint64_t *seeds, pdhg_push_res
             r.before = before[i];
             r.after = after[i];
             r.seconds = b->push_seconds;
-            if (!b->active_host[i]) { // the solve did not reach the tolerance: no push
-                r.status = solve_status[i];
+            if (!act[i]) { // no push: the solve did not reach the tolerance, or the gate is closed
+                r.status = gated[i] ? PDHG_PUSH_SKIPPED : solve_status[i];
                 r.iters = 0;
                 r.rel_p_push = NAN;
                 continue;
@@ -1244,6 +1295,23 @@ int pdhg_batch_get_solution(pdhg_batch *b, int32_t i, double *x, double *y, doub
         const size_t m0 = (size_t)b->roff[i], mm = (size_t)(b->roff[i + 1] - b->roff[i]);
         const double *cx = b->pushed ? s->xpush : s->xu;
         if (x) HIPCHK(hipMemcpy(x, cx + n0, sizeof(double) * nn, hipMemcpyDeviceToHost));
+        if (y) HIPCHK(hipMemcpy(y, s->yu + m0, sizeof(double) * mm, hipMemcpyDeviceToHost));
+        if (z) HIPCHK(hipMemcpy(z, s->zsol + n0, sizeof(double) * nn, hipMemcpyDeviceToHost));
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
+int pdhg_batch_get_solve_solution(pdhg_batch *b, int32_t i, double *x, double *y, double *z)
+{
+    if (!b || i < 0 || i >= b->count) return fail(PDHG_ERR_INVALID_ARG, "bad handle or LP index");
+    if (!b->solved) return fail(PDHG_ERR_STATE, "no batch solve yet");
+    try {
+        pdhg_solver *s = b->s;
+        const size_t n0 = (size_t)b->coff[i], nn = (size_t)(b->coff[i + 1] - b->coff[i]);
+        const size_t m0 = (size_t)b->roff[i], mm = (size_t)(b->roff[i + 1] - b->roff[i]);
+        if (x) HIPCHK(hipMemcpy(x, s->xu + n0, sizeof(double) * nn, hipMemcpyDeviceToHost));
         if (y) HIPCHK(hipMemcpy(y, s->yu + m0, sizeof(double) * mm, hipMemcpyDeviceToHost));
         if (z) HIPCHK(hipMemcpy(z, s->zsol + n0, sizeof(double) * nn, hipMemcpyDeviceToHost));
     } catch (const HipFailure &f) {

@@ -14,8 +14,8 @@ import numpy as np
 
 LIB_PATH = Path(__file__).resolve().parent / "libpdhg.so"
 
-STATUS = {0: "OPTIMAL", 1: "ITER_LIMIT", 2: "NUMERICAL", 3: "PUSH_DONE", 4: "TIME_LIMIT"}
-PDHG_OPTIMAL, PDHG_ITER_LIMIT, PDHG_NUMERICAL, PDHG_PUSH_DONE, PDHG_TIME_LIMIT = range(5)
+STATUS = {0: "OPTIMAL", 1: "ITER_LIMIT", 2: "NUMERICAL", 3: "PUSH_DONE", 4: "TIME_LIMIT", 5: "PUSH_SKIPPED"}
+PDHG_OPTIMAL, PDHG_ITER_LIMIT, PDHG_NUMERICAL, PDHG_PUSH_DONE, PDHG_TIME_LIMIT, PDHG_PUSH_SKIPPED = range(6)
 PDHG_FP64, PDHG_FP32_MIXED = 0, 1
 ERRORS = {-1: "INVALID_ARG", -2: "STATE", -3: "OOM", -4: "HIP"}
 
@@ -38,7 +38,8 @@ class Params(C.Structure):
         ("push_obj_scale", C.c_double), ("push_max_iter", C.c_int64), ("time_limit", C.c_double),
         ("stream", C.c_void_p), ("verbosity", C.c_int32), ("lanes_at", C.c_int32), ("lanes_a", C.c_int32),
         ("use_graph", C.c_int32), ("timing", C.c_int32), ("autotune", C.c_int32), ("record_history", C.c_int32),
-        ("push_compact", C.c_int32),
+        ("push_compact", C.c_int32), ("push_gate", C.c_int32), ("push_gate_rows", C.c_double),
+        ("push_gate_min", C.c_int64),
     ]
 
 
@@ -124,7 +125,7 @@ EXPORTS = ["pdhg_default_params", "pdhg_create", "pdhg_solve", "pdhg_iterate", "
            "pdhg_mlp_gradient", "pdhg_default_train_params", "pdhg_mlp_train", "pdhg_features",
            "pdhg_batch_features", "pdhg_batch_corner_push_learned",
            "pdhg_corner_push_learned", "pdhg_get_solution_device", "pdhg_set_start", "pdhg_state_size",
-           "pdhg_get_state", "pdhg_set_state"]
+           "pdhg_get_state", "pdhg_set_state", "pdhg_get_solve_solution", "pdhg_batch_get_solve_solution"]
 
 _lib = None
 
@@ -149,6 +150,7 @@ def load(path: Optional[Path] = None):
     lib.pdhg_corner_push.argtypes = [C.c_void_p, C.c_uint64, P(PushResult)]
     lib.pdhg_kkt.argtypes = [C.c_void_p, dp, dp, P(KKTReport)]
     lib.pdhg_get_solution.argtypes = [C.c_void_p, dp, dp, dp]
+    lib.pdhg_get_solve_solution.argtypes = [C.c_void_p, dp, dp, dp]
     lib.pdhg_get_iterate.argtypes = [C.c_void_p, dp, dp]
     lib.pdhg_get_scaling.argtypes = [C.c_void_p, dp, dp, dp]
     lib.pdhg_get_timing.argtypes = [C.c_void_p, P(Timing)]
@@ -159,6 +161,7 @@ def load(path: Optional[Path] = None):
     lib.pdhg_batch_solve.argtypes = [C.c_void_p, P(Result)]
     lib.pdhg_batch_corner_push.argtypes = [C.c_void_p, P(C.c_uint64), P(PushResult)]
     lib.pdhg_batch_get_solution.argtypes = [C.c_void_p, C.c_int32, dp, dp, dp]
+    lib.pdhg_batch_get_solve_solution.argtypes = [C.c_void_p, C.c_int32, dp, dp, dp]
     lib.pdhg_batch_get_report.argtypes = [C.c_void_p, P(BatchReport)]
     lib.pdhg_batch_destroy.argtypes = [C.c_void_p]
     lib.pdhg_batch_destroy.restype = None
@@ -191,7 +194,8 @@ def load(path: Optional[Path] = None):
                "pdhg_mlp_create", "pdhg_mlp_set_params", "pdhg_mlp_get_params", "pdhg_mlp_forward",
                "pdhg_mlp_gradient", "pdhg_mlp_train", "pdhg_features", "pdhg_corner_push_learned",
                "pdhg_batch_features", "pdhg_batch_corner_push_learned", "pdhg_get_solution_device",
-               "pdhg_set_start", "pdhg_state_size", "pdhg_get_state", "pdhg_set_state"):
+               "pdhg_set_start", "pdhg_state_size", "pdhg_get_state", "pdhg_set_state", "pdhg_get_solve_solution",
+               "pdhg_batch_get_solve_solution"):
         getattr(lib, fn).restype = C.c_int
     sizes = [C.sizeof(Params), C.sizeof(Result), C.sizeof(KKTReport), C.sizeof(PushResult), C.sizeof(Timing),
              C.sizeof(LpDesc), C.sizeof(BatchReport)]
@@ -310,6 +314,12 @@ class Solver:
     def get_solution(self):
         x, y, z = np.zeros(self.n), np.zeros(self.m), np.zeros(self.n)
         self._check(self.lib.pdhg_get_solution(self.h, _dp(x), _dp(y), _dp(z)))
+        return x, y, z
+
+    def get_solve_solution(self):
+        """The solve's own (x, y, z), also after a push."""
+        x, y, z = np.zeros(self.n), np.zeros(self.m), np.zeros(self.n)
+        self._check(self.lib.pdhg_get_solve_solution(self.h, _dp(x), _dp(y), _dp(z)))
         return x, y, z
 
     def get_iterate(self):
@@ -432,6 +442,13 @@ class Batch:
         lp = self.lps[i]
         x, y, z = np.zeros(lp.n), np.zeros(lp.m), np.zeros(lp.n)
         self._check(self.lib.pdhg_batch_get_solution(self.h, int(i), _dp(x), _dp(y), _dp(z)))
+        return x, y, z
+
+    def get_solve_solution(self, i):
+        """LP i's solve answer (x, y, z), also after the push."""
+        lp = self.lps[i]
+        x, y, z = np.zeros(lp.n), np.zeros(lp.m), np.zeros(lp.n)
+        self._check(self.lib.pdhg_batch_get_solve_solution(self.h, int(i), _dp(x), _dp(y), _dp(z)))
         return x, y, z
 
     def report(self) -> BatchReport:

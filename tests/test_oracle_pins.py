@@ -95,6 +95,34 @@ def test_free_columns_vs_highs(seed, m, n):
     assert np.abs(lam[free]).max(initial=0.0) <= 1e-6 * (1 + np.abs(lp.c).max())
 
 
+def test_push_gate_follows_the_selection_rule():
+    """Section 4.2's selection rule as a push gate: with fewer candidates than
+    max(rows * m, min) the push is skipped and the solve's point is the
+    answer; at a threshold the count meets ("at least") the push runs exactly
+    as without the gate."""
+    lp = lpgen.config0(0)
+    plain = OracleSolver(lp, eps_rel=1e-8)
+    plain.solve()
+    pp = plain.corner_push(3)
+    cand = pp.before.candidates
+    assert cand > 0 and pp.iters > 0
+    closed = OracleSolver(lp, eps_rel=1e-8, push_gate=1, push_gate_rows=0.0, push_gate_min=cand + 1)
+    closed.solve()
+    x0 = closed.solution()[0]
+    r = closed.corner_push(3)
+    assert r.status == 5 and r.iters == 0
+    assert (r.after.p_off, r.after.candidates) == (r.before.p_off, r.before.candidates)
+    np.testing.assert_array_equal(closed.solution()[0], x0)
+    opened = OracleSolver(lp, eps_rel=1e-8, push_gate=1, push_gate_rows=0.0, push_gate_min=cand)
+    opened.solve()
+    ro = opened.corner_push(3)
+    assert (ro.status, ro.iters) == (pp.status, pp.iters)
+    np.testing.assert_array_equal(opened.solution()[0], plain.solution()[0])
+    by_rows = OracleSolver(lp, eps_rel=1e-8, push_gate=1, push_gate_rows=(cand + 1) / lp.m, push_gate_min=0)
+    by_rows.solve()
+    assert by_rows.corner_push(3).status == 5
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_vanilla_pdhg_also_converges(seed):
     """halpern = 0 (plain PDHG with restarts) reaches the same vertex optimum."""
