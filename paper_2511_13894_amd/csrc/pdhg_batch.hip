@@ -866,6 +866,111 @@ static void build_tiles(const std::vector<int> &off, int count, int rows_per, st
 
 static int tile_rows(int kern) { return -kern > 1000 ? -kern - 1000 : -kern; }
 
+// ---------------------------------------------- push on the free columns ---
+// The compaction of the block-diagonal model keeps each LP's free columns
+// contiguous and in order, so the batch only needs the column-side
+// structures of the compact numbering: LP offsets, primal iteration tiles,
+// column reduction tiles.  out[i] = first compact column of LP i (i <= count),
+// out[count + 1 + i] = first compact transpose entry of LP i.
+__global__ void kb_compact_offsets(int count, const int *__restrict__ coff, const int *__restrict__ newid,
+                                   const int *__restrict__ tpc, int *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > count) return;
+    const int k = newid[coff[i]];
+    out[i] = k;
+    out[count + 1 + i] = tpc[k];
+}
+
+hipError_t batch_push_compact_begin(pdhg_batch *b)
+{
+    pdhg_solver *s = b->s;
+    hipError_t e = push_compact_begin(s);
+    if (e != hipSuccess || !s->pc.active) return e;
+    hipStream_t st = s->stream;
+    const int cnt = b->count;
+    std::vector<int> h(2 * ((size_t)cnt + 1));
+    int *dv = nullptr;
+    int4 *rn = nullptr;
+    int *rn_start = nullptr, *d_coff = nullptr;
+    e = hipMalloc(&dv, sizeof(int) * h.size());
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(kb_compact_offsets, dim3((cnt + 1 + 255) / 256), dim3(256), 0, st, cnt, b->d_coff,
+                           s->pc.newid, s->pc.tp, dv);
+        e = hipMemcpyAsync(h.data(), dv, sizeof(int) * h.size(), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(dv);
+    }
+    std::vector<int> coff(h.begin(), h.begin() + cnt + 1);
+    std::vector<int64_t> nnz((size_t)cnt);
+    for (int i = 0; i < cnt; i++) nnz[i] = (int64_t)h[cnt + 2 + i] - h[cnt + 1 + i];
+    std::vector<int4> pt, rt;
+    std::vector<int> rs;
+    build_tiles(coff, cnt, tile_rows(b->kern_at), pt, nullptr);
+    build_tiles(coff, cnt, kBlock, rt, &rs);
+    if (e == hipSuccess) e = hipMalloc(&rn, sizeof(int4) * (rt.size() > 0 ? rt.size() : 1));
+    if (e == hipSuccess) e = hipMalloc(&rn_start, sizeof(int) * rs.size());
+    if (e == hipSuccess) e = hipMalloc(&d_coff, sizeof(int) * coff.size());
+    if (e == hipSuccess && !rt.empty()) e = hipMemcpy(rn, rt.data(), sizeof(int4) * rt.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(rn_start, rs.data(), sizeof(int) * rs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_coff, coff.data(), sizeof(int) * coff.size(), hipMemcpyHostToDevice);
+    // at most as many primal tiles as the full model's: the buffer holds them
+    if (e == hipSuccess && !pt.empty()) e = hipMemcpy(b->ptiles, pt.data(), sizeof(int4) * pt.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        for (void *q : {(void *)rn, (void *)rn_start, (void *)d_coff})
+            if (q) (void)hipFree(q);
+        (void)push_compact_end(s, false);
+        return e;
+    }
+    b->full.coff = b->coff;
+    b->full.nnz_of = b->nnz_of;
+    b->full.ptiles_all = b->ptiles_all;
+    b->full.rn = b->rn;
+    b->full.n_rn = b->n_rn;
+    b->full.rn_start = b->rn_start;
+    b->full.d_coff = b->d_coff;
+    b->coff = coff;
+    b->nnz_of = nnz;
+    b->ptiles_all = pt;
+    b->n_ptiles = (int)pt.size();
+    b->rn = rn;
+    b->n_rn = (int)rt.size();
+    b->rn_start = rn_start;
+    b->d_coff = d_coff;
+    b->full.active = true;
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return hipSuccess;
+}
+
+hipError_t batch_push_compact_end(pdhg_batch *b, bool scatter)
+{
+    pdhg_solver *s = b->s;
+    hipError_t e = push_compact_end(s, scatter);
+    if (!b->full.active) return e;
+    for (void *q : {(void *)b->rn, (void *)b->rn_start, (void *)b->d_coff})
+        if (q) (void)hipFree(q);
+    b->coff = b->full.coff;
+    b->nnz_of = b->full.nnz_of;
+    b->ptiles_all = b->full.ptiles_all;
+    b->rn = b->full.rn;
+    b->n_rn = b->full.n_rn;
+    b->rn_start = b->full.rn_start;
+    b->d_coff = b->full.d_coff;
+    b->full = {};
+    const hipError_t e2 = b->ptiles_all.empty() ? hipSuccess
+                                                : hipMemcpy(b->ptiles, b->ptiles_all.data(),
+                                                            sizeof(int4) * b->ptiles_all.size(), hipMemcpyHostToDevice);
+    b->n_ptiles = (int)b->ptiles_all.size();
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return e != hipSuccess ? e : e2;
+}
+
 // (Re)build the iteration tiles for a kernel choice and upload them.
 hipError_t batch_set_kernels(pdhg_batch *b, int kern_at, int kern_a)
 {

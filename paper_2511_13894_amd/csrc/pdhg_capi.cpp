@@ -278,6 +278,7 @@ bool run_batch_phase(pdhg_batch *b, int64_t iters, int mode, double t0)
 
 void free_batch(pdhg_batch *b)
 {
+    (void)batch_push_compact_end(b, false);
     void *ptrs[] = {b->d_coff, b->ptiles, b->dtiles, b->rn, b->rm, b->rn_start, b->rm_start, b->sts,
                     b->part, b->lp_scalar, b->rep, b->active, b->seeds, b->fpart, b->fscale};
     for (void *q : ptrs)
@@ -1214,7 +1215,9 @@ static int batch_push_common(pdhg_batch *b, const uint64_t *seeds, pdhg_push_res
         s->learned_active = net != nullptr;
         b->t_host = 0;
         b->next_check = s->p.push_min_iters;
+        if (s->p.push_compact && !net) HIPCHK(batch_push_compact_begin(b)); // the push on the free columns
         const bool time_out = run_batch_phase(b, s->p.push_max_iter, 2, t0);
+        HIPCHK(batch_push_compact_end(b, true));
         HIPCHK(unscale(s, s->xp, nullptr, s->xpush, nullptr));
         HIPCHK(batch_keep_unpushed(b));
         HIPCHK(batch_report(b, s->xpush, s->yu, nullptr, after.data()));
@@ -1248,6 +1251,7 @@ static int batch_push_common(pdhg_batch *b, const uint64_t *seeds, pdhg_push_res
         s->learned_active = false;
         b->pushed = true;
     } catch (const HipFailure &f) {
+        (void)batch_push_compact_end(b, false); // the full model's structures back in the handle
         return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
     }
     return PDHG_OK;

@@ -209,6 +209,17 @@ struct pdhg_batch {
     double solve_seconds = 0.0, push_seconds = 0.0;
     double timed_bytes_primal = 0.0, timed_bytes_dual = 0.0; // algorithmic bytes of the timed launches
     int64_t solve_iters_max = 0, push_iters_max = 0;
+    // while the push runs on the free columns: the full model's column-side
+    // structures, replaced by those of the compact numbering
+    struct {
+        bool active = false;
+        std::vector<int> coff;
+        std::vector<int64_t> nnz_of;
+        std::vector<int4> ptiles_all;
+        int4 *rn = nullptr;
+        int n_rn = 0;
+        int *rn_start = nullptr, *d_coff = nullptr;
+    } full;
 };
 
 namespace pdhg {
@@ -248,6 +259,10 @@ hipError_t push_compact_begin(pdhg_solver *s);
 hipError_t push_compact_end(pdhg_solver *s, bool scatter);
 // algorithmic bytes of one primal and one dual launch on the current model
 void model_bytes(const pdhg_solver *s, int64_t *bytes_primal, int64_t *bytes_dual);
+// the batch push on its free columns (per-LP offsets and tiles of the compact
+// numbering), and back
+hipError_t batch_push_compact_begin(pdhg_batch *b);
+hipError_t batch_push_compact_end(pdhg_batch *b, bool scatter);
 hipError_t capture_cycle(pdhg_solver *s, int len, int mode);
 hipError_t copy_probe(int64_t bytes, int reps, double *gbps);
 

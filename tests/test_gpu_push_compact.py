@@ -91,3 +91,33 @@ def test_compact_push_fp32_and_timing_bytes():
         assert ta1.bytes_primal < ta0.bytes_primal
     if p1.iters == p0.iters:
         assert rel_inf(x1, x0) <= 1e-5
+
+
+def test_compact_batch_push_matches_full_batch_push_and_oracle():
+    """The batch push on each LP's free columns (compact per-LP offsets and
+    tiles) against the full batch push and the oracle, LP by LP."""
+    lps = [lpgen.config3_instance(i, base_seed=5000, m_range=(40, 400)) for i in range(8)]
+    lps.append(lpgen.tiny(207, m=40, n=120, with_free=True))
+    lps.append(lpgen.transportation(6, 9, seed=4))
+    seeds = [11 + i for i in range(len(lps))]
+    out = {}
+    for compact in (0, 1):
+        b = pdhg.Batch(lps, eps_rel=1e-7, push_compact=compact, timing=1)
+        b.solve()
+        r = b.corner_push(seeds)
+        out[compact] = (r, [b.get_solution(i)[0] for i in range(len(lps))], b.report())
+    (r0, x0, rep0), (r1, x1, rep1) = out[0], out[1]
+    print(f"[compact] batch: push lockstep {rep1.push_lockstep_iters} / {rep0.push_lockstep_iters}; mean primal "
+          f"bytes per timed launch {rep1.bytes_primal} / {rep0.bytes_primal}", flush=True)
+    assert rep1.push_lockstep_iters == rep0.push_lockstep_iters
+    for i, lp in enumerate(lps):
+        o = OracleSolver(lp, eps_rel=1e-7)
+        o.solve()
+        po = o.corner_push(seeds[i])
+        assert (r1[i].n_fix_lower, r1[i].n_fix_upper, r1[i].n_rows_to_eq) == \
+            (po.n_fix_lower, po.n_fix_upper, po.n_rows_to_eq), i
+        assert r1[i].status == r0[i].status == po.status, i
+        assert r1[i].iters == r0[i].iters, (i, r1[i].iters, r0[i].iters)
+        assert abs(r1[i].iters - po.iters) <= 128, (i, r1[i].iters, po.iters)
+        assert rel_inf(x1[i], x0[i]) <= 1e-8, i
+        assert (r1[i].after.p_off, r1[i].after.candidates) == (r0[i].after.p_off, r0[i].after.candidates), i
