@@ -117,14 +117,14 @@ typedef struct pdhg_params {
                               mean-row-length rule, reproducible run to run)          */
     int32_t record_history;/* 1: keep x and z of the last 4 restarts of the solve (the
                               learned push's trend features); default 0               */
-    int32_t push_compact;  /* 1 (default): the single-LP push iterates on its free
-                              columns only.  A column Algorithm 1 fixes (lower bound =
+    int32_t push_compact;  /* 1 (default): the push iterates on its free columns only
+                              (per LP in a batch).  A column Algorithm 1 fixes (lower bound =
                               upper bound) keeps its value, so it enters only as the
                               constant Ahat_j x_j of the dual product, folded into the
                               right-hand side; residuals, gap, restarts and the stop
                               test are those of the full push model up to rounding.
                               Not used by the learned push (its undo frees fixed
-                              columns again), the sliced ELLPACK dual or the batch.
+                              columns again) or the sliced ELLPACK dual.
                               0: iterate on the full push model                       */
     int32_t push_gate;     /* 1: push only when the solve's answer has at least
                               max(push_gate_rows * m, push_gate_min) candidates (off
