@@ -121,3 +121,26 @@ def test_compact_batch_push_matches_full_batch_push_and_oracle():
         assert abs(r1[i].iters - po.iters) <= 128, (i, r1[i].iters, po.iters)
         assert rel_inf(x1[i], x0[i]) <= 1e-8, i
         assert (r1[i].after.p_off, r1[i].after.candidates) == (r0[i].after.p_off, r0[i].after.candidates), i
+
+
+@pytest.mark.parametrize("name,make", [
+    # the only row is slack, so y = 0, z = c > 0 and the push fixes every column (no free column left)
+    ("all_fixed", lambda: lpgen.from_dense([[1.0, 1.0]], [5.0], [1.0, 1.0], [0.0, 0.0], [1.0, 1.0], "<")),
+    # zero costs: every reduced cost is 0 and the push fixes nothing (the full model is kept)
+    ("none_fixed", lambda: lpgen.from_dense([[1.0, 1.0, 1.0]], [1.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0],
+                                            [1.0, 1.0, 1.0], "=")),
+], ids=["all_fixed", "none_fixed"])
+def test_compact_push_with_no_or_every_column_fixed(name, make):
+    lp = make()
+    o = OracleSolver(lp, eps_rel=1e-8)
+    o.solve()
+    po = o.corner_push(3)
+    for compact in (0, 1):
+        g = pdhg.Solver(lp, eps_rel=1e-8, push_compact=compact)
+        assert g.solve().status == pdhg.PDHG_OPTIMAL
+        pg = g.corner_push(3)
+        print(f"[compact] {name} compact={compact}: fixed {pg.n_fix_lower}+{pg.n_fix_upper} of {lp.n}, "
+              f"push {pg.iters} iterations (oracle {po.iters})", flush=True)
+        assert (pg.status, pg.iters) == (po.status, po.iters)
+        assert (pg.n_fix_lower, pg.n_fix_upper) == (po.n_fix_lower, po.n_fix_upper)
+        assert rel_inf(g.get_solution()[0], o.solution()[0]) <= 1e-9
