@@ -91,7 +91,8 @@ def bench_batch(args, pdhg, copy_gbs):
           flush=True)
 
     def step(timing):
-        b = pdhg.Batch(lps, precision=args.precision, timing=timing, use_graph=0 if args.no_graph else 1)
+        b = pdhg.Batch(lps, precision=args.precision, timing=timing, use_graph=0 if args.no_graph else 1,
+                       push_compact=args.push_compact)
         res = b.solve()
         push = b.corner_push(seeds)
         rep = b.report()
@@ -187,6 +188,8 @@ def main():
     ap.add_argument("--iters-only", type=int, default=0,
                     help="profiling runs: create + this many iterations per step, no push, no JSON roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--push-compact", type=int, default=1, choices=[0, 1],
+                    help="1 (default): the push iterates on its free columns; 0: on the full push model")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every cycle eagerly instead of replaying captured hipGraphs (profiler runs)")
     args = ap.parse_args()
@@ -217,7 +220,8 @@ def main():
         return
 
     def step(timing):
-        s = pdhg.Solver(lp, precision=args.precision, timing=timing, use_graph=0 if args.no_graph else 1)
+        s = pdhg.Solver(lp, precision=args.precision, timing=timing, use_graph=0 if args.no_graph else 1,
+                        push_compact=args.push_compact)
         r = s.solve()
         p = s.corner_push(args.seed)
         t = s.get_timing() if timing else None
