@@ -123,8 +123,9 @@ typedef struct pdhg_params {
                               constant Ahat_j x_j of the dual product, folded into the
                               right-hand side; residuals, gap, restarts and the stop
                               test are those of the full push model up to rounding.
-                              Not used by the learned push (its undo frees fixed
-                              columns again) or the sliced ELLPACK dual.
+                              The learned push keeps its learned fixes (an undo may
+                              free them again) and drops only the plain rule's.  Not
+                              used with the sliced ELLPACK dual.
                               0: iterate on the full push model                       */
     int32_t push_gate;     /* 1: push only when the solve's answer has at least
                               max(push_gate_rows * m, push_gate_min) candidates (off

@@ -622,9 +622,9 @@ static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r
         s->has_candidate = false;
         s->t_host = 0;
         s->next_check = s->p.push_min_iters;
-        // CP6, on the free columns unless learned fixes may be undone or the
-        // dual half uses the sliced layout of the full matrix
-        if (s->p.push_compact && !net && s->kern_a != kSell) HIPCHK(push_compact_begin(s));
+        // CP6, on the free columns (learned fixes kept), unless the dual half
+        // uses the sliced layout of the full matrix
+        if (s->p.push_compact && s->kern_a != kSell) HIPCHK(push_compact_begin(s));
         int status = run_phase(s, s->p.push_max_iter, 2, t0);
         HIPCHK(push_compact_end(s, true));
         // CP7: (xhat, y, z)
@@ -1215,7 +1215,7 @@ static int batch_push_common(pdhg_batch *b, const uint64_t *seeds, pdhg_push_res
         s->learned_active = net != nullptr;
         b->t_host = 0;
         b->next_check = s->p.push_min_iters;
-        if (s->p.push_compact && !net) HIPCHK(batch_push_compact_begin(b)); // the push on the free columns
+        if (s->p.push_compact) HIPCHK(batch_push_compact_begin(b)); // the push on the free columns
         const bool time_out = run_batch_phase(b, s->p.push_max_iter, 2, t0);
         HIPCHK(batch_push_compact_end(b, true));
         HIPCHK(unscale(s, s->xp, nullptr, s->xpush, nullptr));

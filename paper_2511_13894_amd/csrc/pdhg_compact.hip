@@ -12,7 +12,9 @@
 // hence the same weighted KKT, restarts and stopping test, with the fixed
 // columns' share of the matrix and n-vectors gone from every push iteration.
 // The solver's fields point at the compact model while the push iterates and
-// at the full model again once it ends.
+// at the full model again once it ends.  In the learned push a learned fix may
+// be undone at a check, so only the plain rule's fixes are dropped: learned
+// fixes stay in the compact model with their flags and original bounds.
 #include <hipcub/hipcub.hpp>
 
 #include "pdhg_device.hpp"
@@ -20,14 +22,29 @@
 
 namespace pdhg {
 
-// flag[j] = 1 for a free column (lhat_j != uhat_j), 0 for a fixed one; flag[n] = 0
+// flag[j] = 1 for a column the compact model keeps (lhat_j != uhat_j, or a
+// learned fix, which an undo may free again), 0 for a fixed one; flag[n] = 0
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_free_flags(int n, const V *__restrict__ lh, const V *__restrict__ uh,
-                                                      int *__restrict__ flag)
+                                                      const int8_t *__restrict__ lfix, int *__restrict__ flag)
 {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j < n) flag[j] = lh[j] != uh[j] ? 1 : 0;
+    if (j < n) flag[j] = (lh[j] != uh[j] || (lfix && lfix[j])) ? 1 : 0;
     else if (j == n) flag[j] = 0;
+}
+
+// the learned push's per-column state on the kept columns
+__global__ __launch_bounds__(kBlock) void k_gather_learned(int nf, const int *__restrict__ keep,
+                                                          const int8_t *__restrict__ lfix, const double *__restrict__ l,
+                                                          const double *__restrict__ u, int8_t *__restrict__ lfixc,
+                                                          double *__restrict__ lc, double *__restrict__ uc)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= nf) return;
+    const int j = keep[k];
+    lfixc[k] = lfix[j];
+    lc[k] = l[j];
+    uc[k] = u[j];
 }
 
 // keep[newid[j]] = j for every free column j
@@ -200,7 +217,7 @@ hipError_t alloc(T **p, size_t count)
 void free_compact(pdhg_solver::PushCompact &c)
 {
     void *ptrs[] = {c.flag, c.newid, c.keep, c.tp, c.ti, c.rp, c.ci, c.ahat, c.ahat_t, c.lh, c.uh,
-                    c.x, c.xa, c.xbar, c.xp, c.ch, c.dc, c.bt};
+                    c.x, c.xa, c.xbar, c.xp, c.ch, c.dc, c.bt, c.lfix, c.l, c.u};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     c = pdhg_solver::PushCompact{};
@@ -216,7 +233,8 @@ hipError_t begin_impl(pdhg_solver *s)
     hipError_t e = alloc(&c.flag, (size_t)n + 1);
     if (e == hipSuccess) e = alloc(&c.newid, (size_t)n + 1);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_free_flags<V>), dim3(gn1), dim3(kBlock), 0, st, n, (const V *)s->lh, (const V *)s->uh,
+    const int8_t *lfix = s->learned_active ? s->lfix : nullptr;
+    hipLaunchKernelGGL((k_free_flags<V>), dim3(gn1), dim3(kBlock), 0, st, n, (const V *)s->lh, (const V *)s->uh, lfix,
                        c.flag);
     if ((e = exclusive_scan(st, c.flag, c.newid, n)) != hipSuccess) return e;
     const int nf = read_int(st, c.newid + n, e);
@@ -283,6 +301,13 @@ hipError_t begin_impl(pdhg_solver *s)
     hipLaunchKernelGGL((k_gather_free<V>), dim3(grid_for(nf, kBlock, 1 << 30)), dim3(kBlock), 0, st, nf, c.keep,
                        s->ch, s->dc, (const V *)s->lh, (const V *)s->uh, (const V *)s->x, (const V *)s->xa,
                        (const V *)s->xp, c.ch, c.dc, (V *)c.lh, (V *)c.uh, (V *)c.x, (V *)c.xa, (V *)c.xp);
+    if (lfix) {
+        if ((e = alloc(&c.lfix, (size_t)nf)) != hipSuccess) return e;
+        if ((e = alloc(&c.l, (size_t)nf)) != hipSuccess) return e;
+        if ((e = alloc(&c.u, (size_t)nf)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gather_learned, dim3(grid_for(nf, kBlock, 1 << 30)), dim3(kBlock), 0, st, nf, c.keep, lfix,
+                           s->l, s->u, c.lfix, c.l, c.u);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     // put the compact model in place
@@ -322,6 +347,14 @@ hipError_t begin_impl(pdhg_solver *s)
     s->xp = c.xp;
     s->ch = c.ch;
     s->dc = c.dc;
+    if (lfix) {
+        c.lfix0 = s->lfix;
+        c.l0 = s->l;
+        c.u0 = s->u;
+        s->lfix = c.lfix;
+        s->l = c.l;
+        s->u = c.u;
+    }
     c.active = true;
     if (s->graph_exec) { // captured on the full model's arrays
         (void)hipGraphExecDestroy(s->graph_exec);
@@ -361,6 +394,11 @@ hipError_t end_impl(pdhg_solver *s, bool scatter)
     s->xp = c.xp0;
     s->ch = c.ch0;
     s->dc = c.dc0;
+    if (c.lfix0) {
+        s->lfix = c.lfix0;
+        s->l = c.l0;
+        s->u = c.u0;
+    }
     if (s->graph_exec) {
         (void)hipGraphExecDestroy(s->graph_exec);
         s->graph_exec = nullptr;

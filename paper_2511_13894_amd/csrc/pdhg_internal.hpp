@@ -164,7 +164,11 @@ struct pdhg_solver {
         void *ahat = nullptr, *ahat_t = nullptr, *lh = nullptr, *uh = nullptr;
         void *x = nullptr, *xa = nullptr, *xbar = nullptr, *xp = nullptr;
         double *ch = nullptr, *dc = nullptr, *bt = nullptr;
+        int8_t *lfix = nullptr;             // learned push: its fixes, which an undo may free again
+        double *l = nullptr, *u = nullptr;  // learned push: the original bounds an undo restores
         int n0 = 0, nnz0 = 0, red_blocks_n0 = 1;
+        int8_t *lfix0 = nullptr;
+        double *l0 = nullptr, *u0 = nullptr;
         int *tp0 = nullptr, *ti0 = nullptr, *rp0 = nullptr, *ci0 = nullptr;
         void *ahat0 = nullptr, *ahat_t0 = nullptr, *lh0 = nullptr, *uh0 = nullptr, *bh0 = nullptr;
         void *x0 = nullptr, *xa0 = nullptr, *xbar0 = nullptr, *xp0 = nullptr;

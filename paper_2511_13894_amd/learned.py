@@ -88,10 +88,8 @@ def build_dataset_batched(lps, seeds, precision="fp64", eps=1e-6, eps_abs=1e-6):
 def batch_time_to_corner(lps, seeds, precision="fp64", net=None, theta=0.9, eps=1e-6):
     """create + solve + push of the whole batch, plain or learned."""
     t0 = time.perf_counter()
-    # both arms push on the full model: the learned push can free a fixed column
-    # again, so it keeps every column, and the plain arm does the same
     b = pdhg.Batch(lps, precision=precision, record_history=1 if net is not None else 0, eps_rel=eps,
-                   use_graph=USE_GRAPH, push_compact=0)
+                   use_graph=USE_GRAPH)
     res = b.solve()
     push = b.corner_push(seeds) if net is None else b.corner_push_learned(net, theta, seeds)
     dt = time.perf_counter() - t0
@@ -134,7 +132,7 @@ def time_to_corner(lp, seed, precision="fp64", net=None, theta=0.9, eps=1e-6):
     """create + solve + push wall time, and the corner statistics."""
     t0 = time.perf_counter()
     s = pdhg.Solver(lp, precision=precision, record_history=1 if net is not None else 0, eps_rel=eps,
-                    use_graph=USE_GRAPH, push_compact=0)  # like for like, as in batch_time_to_corner
+                    use_graph=USE_GRAPH)
     r = s.solve()
     if r.status != pdhg.PDHG_OPTIMAL:
         return None

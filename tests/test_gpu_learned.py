@@ -119,3 +119,36 @@ def test_batch_features_and_learned_push_match_single_lp_runs():
     for i, p in enumerate(push):
         assert p.status == pdhg.PDHG_PUSH_DONE, (i, pdhg.STATUS[p.status])
         assert p.after.rel_p <= 1.0000001e-7
+
+
+def test_learned_push_on_free_columns_equals_the_full_push():
+    """push_compact drops only the plain rule's fixes in the learned push:
+    learned fixes stay, so the undo rule frees the same columns and the push
+    follows the full model's, single and batched."""
+    lp = lpgen.config0(3)
+    net = pdhg.Mlp(1)
+    out = {}
+    for compact in (0, 1):
+        s = pdhg.Solver(lp, record_history=1, eps_rel=1e-7, push_compact=compact)
+        s.solve()
+        p = s.corner_push_learned(net, 1e-4, 5)
+        out[compact] = (p, s.get_solution()[0])
+    (p0, x0), (p1, x1) = out[0], out[1]
+    print(f"[learned] compact push: fixed {p1.n_learned_fix}/{p0.n_learned_fix}, undone {p1.n_learned_undo}/"
+          f"{p0.n_learned_undo}, iterations {p1.iters}/{p0.iters}", flush=True)
+    assert (p1.n_learned_fix, p1.n_learned_undo, p1.status, p1.iters) == \
+        (p0.n_learned_fix, p0.n_learned_undo, p0.status, p0.iters)
+    assert np.abs(x1 - x0).max() <= 1e-8 * max(1.0, np.abs(x0).max())
+    lps = [lpgen.config3_instance(i, base_seed=5000, m_range=(40, 300)) for i in range(6)]
+    res = {}
+    for compact in (0, 1):
+        b = pdhg.Batch(lps, record_history=1, eps_rel=1e-7, push_compact=compact)
+        b.solve()
+        r = b.corner_push_learned(net, 1e-4, [5 + i for i in range(len(lps))])
+        res[compact] = (r, [b.get_solution(i)[0] for i in range(len(lps))])
+    for i in range(len(lps)):
+        a, c = res[0][0][i], res[1][0][i]
+        assert (c.n_learned_fix, c.n_learned_undo, c.status, c.iters) == \
+            (a.n_learned_fix, a.n_learned_undo, a.status, a.iters), i
+        xa, xc = res[0][1][i], res[1][1][i]
+        assert np.abs(xc - xa).max() <= 1e-8 * max(1.0, np.abs(xa).max()), i
