@@ -144,3 +144,35 @@ def test_compact_push_with_no_or_every_column_fixed(name, make):
         assert (pg.status, pg.iters) == (po.status, po.iters)
         assert (pg.n_fix_lower, pg.n_fix_upper) == (po.n_fix_lower, po.n_fix_upper)
         assert rel_inf(g.get_solution()[0], o.solution()[0]) <= 1e-9
+
+
+def test_compact_push_graph_replay_equals_eager_launches():
+    """The cycle graph is captured again on the compact model's arrays: the
+    push with graph replays equals the push launched eagerly, bit for bit."""
+    lp = lpgen.config1(seed=3, m=300, n=1200)
+    out = []
+    for graph in (0, 1):
+        g = pdhg.Solver(lp, eps_rel=1e-8, max_iter=400000, use_graph=graph)
+        g.solve()
+        p = g.corner_push(17)
+        out.append((p.iters, g.get_solution()[0], g.get_iterate()))
+    assert out[0][0] == out[1][0]
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    np.testing.assert_array_equal(out[0][2][0], out[1][2][0])
+    np.testing.assert_array_equal(out[0][2][1], out[1][2][1])
+
+
+def test_compact_batch_push_fp32():
+    lps = [lpgen.config3_instance(i, base_seed=5000, m_range=(40, 300)) for i in range(6)]
+    seeds = [3 + i for i in range(len(lps))]
+    res = {}
+    for compact in (0, 1):
+        b = pdhg.Batch(lps, precision="fp32", eps_rel=1e-6, push_compact=compact)
+        b.solve()
+        res[compact] = (b.corner_push(seeds), [b.get_solution(i)[0] for i in range(len(lps))])
+    for i in range(len(lps)):
+        a, c = res[0][0][i], res[1][0][i]
+        assert (c.status, c.n_fix_lower, c.n_fix_upper) == (a.status, a.n_fix_lower, a.n_fix_upper), i
+        assert abs(c.iters - a.iters) <= 64, (i, c.iters, a.iters)
+        if c.iters == a.iters:
+            assert rel_inf(res[1][1][i], res[0][1][i]) <= 1e-5, i
