@@ -385,7 +385,7 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
     else pdhg_default_params(&p);
     if (p.check_every < 1 || p.ruiz_iters < 0 || p.power_iters < 0 || p.push_min_iters < 1 ||
         (p.precision != PDHG_FP64 && p.precision != PDHG_FP32_MIXED) || !(p.eps_rel > 0.0) || !(p.eta_safety > 0.0) ||
-        !(p.power_tol >= 0.0))
+        !(p.power_tol >= 0.0) || !(p.push_gate_rows >= 0.0) || p.push_gate_min < 0)
         return fail(PDHG_ERR_INVALID_ARG, "invalid parameter");
     for (int half = 0; half < 2; half++) { // 0: primal half (lanes_at), 1: dual half (lanes_a)
         const int32_t k = half ? p.lanes_a : p.lanes_at;

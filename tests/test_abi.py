@@ -51,6 +51,7 @@ def test_default_params_and_argument_errors_without_gpu():
     p = pdhg.default_params()
     assert p.eps_rel == 1e-6 and p.check_every == 64 and p.ruiz_iters == 10 and p.power_iters == 4000 and p.power_tol == 1e-3
     assert p.push_compact == 1 and p.record_history == 0
+    assert p.push_gate == 0 and p.push_gate_rows == 2.0 and p.push_gate_min == 100000
     assert p.halpern == 1 and p.reflect_gamma == 1.0 and p.push_min_iters == 100
     h = ctypes.c_void_p()
     rp = (ctypes.c_int64 * 2)(0, 1)
@@ -67,6 +68,17 @@ def test_default_params_and_argument_errors_without_gpu():
     rc = lib.pdhg_create(1, 2, 1, rp, ci, ctypes.cast(va, dp), ctypes.cast(b, dp), ctypes.cast(c, dp), None, None,
                          None, ctypes.byref(p), ctypes.byref(h))
     assert rc == -1 and b"c" in lib.pdhg_last_error()
+    c[1] = 1.0
+    # the largest model: indices are 32-bit, so nnz >= 2^31 is refused before any array is read
+    rc = lib.pdhg_create(1, 2, 1 << 31, rp, ci, ctypes.cast(va, dp), ctypes.cast(b, dp), ctypes.cast(c, dp), None,
+                         None, None, ctypes.byref(p), ctypes.byref(h))
+    assert rc == -1 and b"2^31" in lib.pdhg_last_error()
+    for field, bad in (("push_gate_rows", -1.0), ("push_gate_min", -5), ("push_gate_rows", float("nan"))):
+        q = pdhg.default_params()
+        setattr(q, field, bad)
+        rc = lib.pdhg_create(1, 2, 1, rp, ci, ctypes.cast(va, dp), ctypes.cast(b, dp), ctypes.cast(c, dp), None,
+                             None, None, ctypes.byref(q), ctypes.byref(h))
+        assert rc == -1 and b"invalid parameter" in lib.pdhg_last_error(), field
     assert lib.pdhg_solve(None, None) == -1
     assert lib.pdhg_kkt(None, None, None, None) == -1
     lib.pdhg_destroy(None)
