@@ -920,6 +920,10 @@ hipError_t batch_push_compact_begin(pdhg_batch *b)
         for (void *q : {(void *)rn, (void *)rn_start, (void *)d_coff})
             if (q) (void)hipFree(q);
         (void)push_compact_end(s, false);
+        // the device tile list may hold compact tiles by now: put the full ones back
+        if (!b->ptiles_all.empty())
+            (void)hipMemcpy(b->ptiles, b->ptiles_all.data(), sizeof(int4) * b->ptiles_all.size(), hipMemcpyHostToDevice);
+        b->n_ptiles = (int)b->ptiles_all.size();
         return e;
     }
     b->full.coff = b->coff;
