@@ -188,8 +188,11 @@ typedef struct pdhg_timing {
     double primal_ms;      /* mean duration of one primal-half launch (A'y + update) */
     double dual_ms;        /* mean duration of one dual-half launch (A xbar + update) */
     int64_t samples;       /* sampled launches of each kernel                          */
-    int64_t bytes_primal;  /* algorithmic bytes of one primal-half launch             */
-    int64_t bytes_dual;    /* algorithmic bytes of one dual-half launch               */
+    int64_t bytes_primal;  /* algorithmic bytes of one primal-half launch: the mean
+                              over the sampled launches, each counted on the model it
+                              ran on (the push may iterate on fewer columns); the
+                              current model's count when nothing was sampled           */
+    int64_t bytes_dual;    /* the same for the dual half                              */
     int32_t lanes_at;      /* primal-half kernel in use (lanes_at encoding)           */
     int32_t lanes_a;       /* dual-half kernel in use                                  */
 } pdhg_timing;
