@@ -32,6 +32,8 @@ WORKLOADS = {
     "c0": "random sparse LP m=200 n=500 (5 nnz per column, planted degenerate optimum; seed 0)",
     "c3": ("batch of 256 independent random sparse LPs, m log-uniform in [500, 20000], n = 2.5m, 4-8 nnz per "
            "column, planted degenerate optima (seeds 3000+i)"),
+    "c4": ("multicommodity flow LP: 50000 nodes, 400000 arcs, 8 commodities (m=800000 node-balance + arc-capacity "
+           "rows, n=3.2M, nnz=9.6M; seed 4100)"),
 }
 
 
@@ -42,6 +44,8 @@ def make_lp(cfg):
         return lpgen.config1(1)
     if cfg == "c2":
         return lpgen.config2(2)
+    if cfg == "c4":
+        return lpgen.config4()
     return lpgen.config0(0)
 
 
