@@ -1044,15 +1044,16 @@ hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, double
 }
 
 // ------------------------------------------------------- kernel choice ---
-// From measured sweeps on the 100k x 400k and 7k x 10M LPs: one lane per row
-// for rows of about 2 entries, LDS tiles for 3 to 48 entries, lane groups
-// sized to the mean beyond, at most 32 (on the dual half's 1,400 to
+// From measured sweeps on the 100k x 400k, 7k x 10M and 800k x 3.2M LPs:
+// LDS tiles up to 48 entries per row (256-row tiles for 2-3 entries: 56 against
+// 63 us for one lane per row on the multicommodity primal), lane groups sized
+// to the mean beyond, at most 32 (on the dual half's 1,400 to
 // 2,800-entry rows 32 lanes beat 64, one workgroup per row and the sliced
 // ELLPACK layout, which stay available as explicit or autotuned choices).
 int choose_kernel(double mean_row, bool dual_half)
 {
     (void)dual_half;
-    if (mean_row <= 3.0) return 1;
+    if (mean_row <= 3.0) return -256; // 2-3 entries per row: 256-row tiles match or beat one lane per row
     if (mean_row <= 16.0) return -64; // measured best for 6 and 15 entries per row
     if (mean_row <= 48.0) return -32; // 24 entries per row
     // long rows: a lane group per row; with four terms in flight per lane, 32
