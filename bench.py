@@ -149,7 +149,7 @@ def bench_batch(args, pdhg, copy_gbs):
         "dtype": "f64" if args.precision == "fp64" else "f32+f64norms", "data": "synthetic",
         "config": {"workload": f"c3: {WORKLOADS['c3']}; step = batch create + solve to 1e-6 relative KKT + corner "
                                "push of every LP", "lps": len(lps), "m": tot_m, "n": tot_n, "nnz": tot_nz,
-                   "precision": args.precision, "eps_rel": 1e-6},
+                   "precision": args.precision, "eps_rel": 1e-6, "push_on_free_columns": bool(args.push_compact)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
                      "launch_us": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": int(nbytes),
@@ -288,7 +288,8 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+f64norms", "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}; step = create + solve to 1e-6 relative "
                                f"KKT + corner push", "m": lp.m, "n": lp.n, "nnz": lp.nnz,
-                   "precision": args.precision, "eps_rel": 1e-6, "push_seed": args.seed},
+                   "precision": args.precision, "eps_rel": 1e-6, "push_seed": args.seed,
+                   "push_on_free_columns": bool(args.push_compact)},
         "roofline": roof,
         "detail": {"steps": details, "time_to_corner_s": round(elapsed / args.steps, 4),
                    "lanes_at": tim.lanes_at, "lanes_a": tim.lanes_a},
