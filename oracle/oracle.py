@@ -71,6 +71,14 @@ class OrPushResult(C.Structure):
     ]
 
 
+class OrDualPushResult(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("pad_", C.c_int32), ("iters", C.c_int64), ("restarts", C.c_int64),
+        ("n_rc_zero", C.c_int64), ("n_dual_zero", C.c_int64),
+        ("rel_d_push", C.c_double), ("before", OrKKT), ("after", OrKKT),
+    ]
+
+
 _lib = None
 
 
@@ -90,6 +98,8 @@ def _load():
         lib.or_iterate.argtypes = [C.c_void_p, C.c_int64, P(OrResult)]
         lib.or_solve.argtypes = [C.c_void_p, P(OrResult)]
         lib.or_corner_push.argtypes = [C.c_void_p, C.c_uint64, P(OrPushResult)]
+        lib.or_dual_push.argtypes = [C.c_void_p, C.c_uint64, P(OrDualPushResult)]
+        lib.or_get_rhs_scaled.argtypes = [C.c_void_p, dp]
         lib.or_kkt_report.argtypes = [C.c_void_p, dp, dp, P(OrKKT)]
         lib.or_get_iterate.argtypes = [C.c_void_p, dp, dp]
         lib.or_get_iterate_scaled.argtypes = [C.c_void_p, dp, dp]
@@ -103,11 +113,13 @@ def _load():
         lib.or_splitmix64.argtypes = [C.c_uint64]
         lib.or_push_uniform.restype = C.c_double
         lib.or_push_uniform.argtypes = [C.c_uint64, C.c_int64]
-        for f in ("or_params_size", "or_kkt_size", "or_push_result_size", "or_num_threads"):
+        for f in ("or_params_size", "or_kkt_size", "or_push_result_size", "or_dual_push_result_size",
+                  "or_num_threads"):
             getattr(lib, f).restype = C.c_int
         assert lib.or_params_size() == C.sizeof(OrParams)
         assert lib.or_kkt_size() == C.sizeof(OrKKT)
         assert lib.or_push_result_size() == C.sizeof(OrPushResult)
+        assert lib.or_dual_push_result_size() == C.sizeof(OrDualPushResult)
         _lib = lib
     return _lib
 
@@ -182,6 +194,14 @@ class OracleSolver:
             raise RuntimeError("corner push needs a prior solve")
         return r
 
+    def dual_push(self, seed: int) -> OrDualPushResult:
+        """Dual corner push; afterwards solution() gives (x, yhat, zhat)."""
+        r = OrDualPushResult()
+        st = self.lib.or_dual_push(self.h, C.c_uint64(seed), C.byref(r))
+        if st < 0:
+            raise RuntimeError("dual push needs a prior solve (and runs once)")
+        return r
+
     def kkt(self, x=None, y=None) -> OrKKT:
         k = OrKKT()
         xa = None if x is None else np.ascontiguousarray(x, dtype=np.float64)
@@ -211,6 +231,11 @@ class OracleSolver:
         sense = C.create_string_buffer(self.m + 1)
         self.lib.or_get_model_scaled(self.h, _dp(lh), _dp(uh), _dp(ch), sense)
         return lh, uh, ch, sense.raw[: self.m]
+
+    def rhs_scaled(self):
+        bh = np.zeros(self.m)
+        self.lib.or_get_rhs_scaled(self.h, _dp(bh))
+        return bh
 
     def ahat(self):
         nnz = int(self.lib.or_get_nnz(self.h))

@@ -45,6 +45,27 @@
  *   residual of the modified model is back at the original tolerance, after at
  *   least push_min_iters push iterations.  Returns (xhat, y, z) with y and z
  *   those of the input.
+ * Dual corner push (section 6 names the idea of cutting dual superbasics the
+ * same way, and nothing more; the construction is this library's reading,
+ * the mirror image of Algorithm 1):
+ *   keep the solve's x and restrict (y, z) to the dual optimal face that
+ *   complementary slackness with x defines: a column further than eps_abs
+ *   from both bounds gets z_j = 0, one within eps_abs of its lower bound only
+ *   z_j >= 0, of its upper bound only z_j <= 0, of both z_j free; an
+ *   inequality row whose slack exceeds eps_abs gets y_i = 0 (sense 'N'),
+ *   every other row keeps its sign rule.  That face is the dual feasible set of
+ *   the push model  min c'w  s.t.  a_i'w (sense_i) g_i,  w_j in the cone of
+ *   column j (R, R+, R-, {0}),  whose right-hand side is random but anchored:
+ *   g = scale * (A w0 - s.v), w0 a random point of the cones (w0_j = U_j on
+ *   R and R+, -U_j on R-, 0 on {0}), v_i = U_(n+i) a random slack with
+ *   s_i = +1 on '>' rows, -1 on '<' rows, 0 on '=' rows.  w0 is feasible for
+ *   the push model, so the random dual objective g'y is bounded on the face
+ *   (the mirror of the primal push, whose model keeps the solve's x
+ *   feasible); a random g alone is unbounded wherever A has dependent
+ *   equality rows.  PDHG restarts from (0, y) and stops
+ *   as soon as the dual residual of the push model is back at the original
+ *   tolerance, after at least push_min_iters iterations.  Returns (x, yhat,
+ *   zhat): the solve's x, the pushed y and its reduced costs.
  */
 #include <math.h>
 #include <stdint.h>
@@ -118,6 +139,16 @@ typedef struct {
 } or_push_result;
 
 typedef struct {
+    int32_t status;
+    int32_t pad_;
+    int64_t iters, restarts;
+    int64_t n_rc_zero;   /* columns strictly inside their bounds: z_j pinned to 0 */
+    int64_t n_dual_zero; /* inequality rows with slack: y_i pinned to 0          */
+    double rel_d_push;   /* relative dual residual of the push model at the stop */
+    or_kkt before, after;
+} or_dual_push_result;
+
+typedef struct {
     int m, n;
     int64_t nnz;
     /* original model (unscaled), A row-compressed with sorted, summed rows */
@@ -145,11 +176,12 @@ typedef struct {
     double kkt_anchor_p2, kkt_anchor_d2, kkt_anchor_gap2; /* at the anchor */
     double kkt_prev;
     int solved;   /* a solve has produced a checked candidate */
-    int in_push;
+    int in_push;  /* 0 solve, 1 corner push, 2 dual corner push */
     /* solution of the original solve, unscaled, kept for the push */
-    double *xs_hat; /* scaled candidate accepted by the solve */
+    double *xs_hat, *ys_hat; /* scaled candidate accepted by the solve */
     double *xsol, *ysol, *zsol;
-    double *xpush; /* unscaled push result */
+    double *xpush;         /* unscaled push result */
+    double *ypush, *zpush; /* unscaled dual push result and its reduced costs */
     or_params p;
 } or_solver;
 
@@ -164,11 +196,13 @@ static double clampd(double v, double lo, double hi)
     return v;
 }
 
-/* projection of one dual entry onto its cone: '=' free, '<' y <= 0, '>' y >= 0 */
+/* projection of one dual entry onto its cone: '=' free, '<' y <= 0, '>' y >= 0,
+ * 'N' (a row the dual push drops) y = 0 */
 static double proj_dual(double v, char s)
 {
     if (s == '<') return v < 0.0 ? v : 0.0;
     if (s == '>') return v > 0.0 ? v : 0.0;
+    if (s == 'N') return 0.0;
     return v;
 }
 
@@ -269,6 +303,7 @@ static void kkt_unscaled(const or_solver *s, const double *c, const double *l, c
         double r = s->b[i] - ax[i];
         if (sense[i] == '<') r = r < 0.0 ? r : 0.0;
         else if (sense[i] == '>') r = r > 0.0 ? r : 0.0;
+        else if (sense[i] == 'N') r = 0.0;
         cadd(&rp2, r * r);
         if (fabs(r) > rpinf) rpinf = fabs(r);
         cadd(&by, s->b[i] * y[i]);
@@ -347,6 +382,7 @@ static void kkt_scaled_parts(or_solver *s, const double *x, const double *y, dou
         double r = s->bh[i] - ax[i];
         if (s->sense[i] == '<') r = r < 0.0 ? r : 0.0;
         else if (s->sense[i] == '>') r = r > 0.0 ? r : 0.0;
+        else if (s->sense[i] == 'N') r = 0.0;
         cadd(&rp, r * r);
         cadd(&by, s->bh[i] * y[i]);
     }
@@ -448,7 +484,7 @@ void or_destroy(or_solver *s)
     void *ptrs[] = {s->rp, s->ci, s->av, s->tp, s->ti, s->tpos, s->b, s->c, s->l, s->u, s->sense0,
                     s->ahat, s->ahat_t, s->dr, s->dc, s->bh, s->ch, s->lh, s->uh, s->sense, s->x,
                     s->y, s->xa, s->ya, s->xp, s->yp, s->xbar, s->g, s->hv, s->xs_hat, s->xsol,
-                    s->ysol, s->zsol, s->xpush};
+                    s->ysol, s->zsol, s->xpush, s->ys_hat, s->ypush, s->zpush};
     for (size_t q = 0; q < sizeof(ptrs) / sizeof(ptrs[0]); q++) free(ptrs[q]);
     free(s);
 }
@@ -637,6 +673,9 @@ or_solver *or_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, 
     s->ysol = dalloc(m);
     s->zsol = dalloc(n);
     s->xpush = dalloc(n);
+    s->ys_hat = dalloc(m);
+    s->ypush = dalloc(m);
+    s->zpush = dalloc(n);
 
     scale_and_step(s);
     for (int i = 0; i < m; i++) {
@@ -751,12 +790,23 @@ static int run_phase(or_solver *s, int64_t iters, double *out_relp)
         if (!s->in_push) {
             kkt_unscaled(s, s->c, s->l, s->u, s->sense, x, y, ax, aty, s->zsol, &k);
             memcpy(s->xs_hat, s->xp, sizeof(double) * (size_t)n);
+            memcpy(s->ys_hat, s->yp, sizeof(double) * (size_t)m);
             memcpy(s->xsol, x, sizeof(double) * (size_t)n);
             memcpy(s->ysol, y, sizeof(double) * (size_t)m);
             s->solved = 1;
             if (k.rel_p <= s->p.eps_rel && k.rel_d <= s->p.eps_rel && k.rel_gap <= s->p.eps_rel) {
                 status = OR_OPTIMAL;
                 if (out_relp) *out_relp = k.rel_p;
+                break;
+            }
+        } else if (s->in_push == 2) {
+            /* dual residual of the dual push model: its cones (0 or infinite,
+               the same scaled and unscaled) decide what the bounds absorb */
+            kkt_unscaled(s, s->c, s->lh, s->uh, s->sense, x, y, ax, aty, NULL, &k);
+            memcpy(s->ypush, y, sizeof(double) * (size_t)m);
+            if (out_relp) *out_relp = k.rel_d;
+            if (k.rel_d <= s->p.eps_rel) {
+                status = OR_PUSH_DONE;
                 break;
             }
         } else {
@@ -805,6 +855,7 @@ int or_iterate(or_solver *s, int64_t iters, or_result *r)
         double *ax = dalloc(s->m), *aty = dalloc(s->n);
         unscale(s, s->x, s->y, s->xsol, s->ysol);
         memcpy(s->xs_hat, s->x, sizeof(double) * (size_t)s->n);
+        memcpy(s->ys_hat, s->y, sizeof(double) * (size_t)s->m);
         kkt_unscaled(s, s->c, s->l, s->u, s->sense0, s->xsol, s->ysol, ax, aty, s->zsol, &k);
         free(ax);
         free(aty);
@@ -888,11 +939,77 @@ int or_corner_push(or_solver *s, uint64_t seed, or_push_result *r)
     return st;
 }
 
+/* Dual corner push (reading in the file header); one push per solve, like
+ * or_corner_push. */
+int or_dual_push(or_solver *s, uint64_t seed, or_dual_push_result *r)
+{
+    if (!s || !r || !s->solved || s->in_push) return OR_ERR_STATE;
+    int m = s->m, n = s->n;
+    double *ax = dalloc(m);
+    memset(r, 0, sizeof(*r));
+    /* DP1: (x, y, z) of the solve on M; ax = A x */
+    reduced_costs(s, s->xsol, s->ysol, s->zsol, ax, &r->before);
+    corner_counts(s, s->xsol, ax, s->ysol, s->zsol, &r->before);
+    double ea = s->p.eps_abs, sc = s->p.push_obj_scale;
+    double *w0 = dalloc(n), *aw = dalloc(m);
+    /* DP2: the cone of each push column from where x sits against its bounds,
+       and the anchor point w0 in it */
+    for (int j = 0; j < n; j++) {
+        int at_lo = !is_inf_lo(s->l[j]) && s->xsol[j] - s->l[j] <= ea;
+        int at_up = !is_inf_up(s->u[j]) && s->u[j] - s->xsol[j] <= ea;
+        s->lh[j] = at_lo ? 0.0 : -INFINITY;
+        s->uh[j] = at_up ? 0.0 : INFINITY;
+        if (!at_lo && !at_up) r->n_rc_zero++;
+        double uj = or_push_uniform(seed, j);
+        w0[j] = (at_lo && at_up) ? 0.0 : (at_up ? -uj : uj);
+        s->x[j] = 0.0; /* DP5: w = 0 */
+    }
+    mv_A(s, s->av, w0, aw);
+    /* DP3, DP4: rows with slack dropped (y_i = 0); the anchored random
+       right-hand side (scaled like b) on the others; y starts at the solve's */
+    for (int i = 0; i < m; i++) {
+        char sn = s->sense0[i];
+        double slack = sn == '<' ? s->b[i] - ax[i] : (sn == '>' ? ax[i] - s->b[i] : 0.0);
+        if (sn != '=' && slack > ea) {
+            s->sense[i] = 'N';
+            s->bh[i] = 0.0;
+            s->y[i] = 0.0;
+            r->n_dual_zero++;
+        } else {
+            double v = or_push_uniform(seed, (int64_t)n + i);
+            double g = sn == '>' ? aw[i] - v : (sn == '<' ? aw[i] + v : aw[i]);
+            s->sense[i] = sn;
+            s->bh[i] = s->dr[i] * (sc * g);
+            s->y[i] = s->ys_hat[i];
+        }
+    }
+    free(w0);
+    free(aw);
+    /* DP5: new weight and restart state; the objective stays c */
+    s->omega = initial_omega(s->ch, n, s->bh, m);
+    s->in_push = 2;
+    reset_iteration(s, s->p.push_min_iters);
+    memcpy(s->ypush, s->ysol, sizeof(double) * (size_t)m);
+    /* DP6 */
+    double reld = NAN;
+    int st = run_phase(s, s->p.push_max_iter, &reld);
+    r->status = st;
+    r->iters = s->t;
+    r->restarts = s->restarts;
+    r->rel_d_push = reld;
+    /* DP7: (x, yhat, zhat), counts against the original model */
+    reduced_costs(s, s->xsol, s->ypush, s->zpush, ax, &r->after);
+    corner_counts(s, s->xsol, ax, s->ypush, s->zpush, &r->after);
+    free(ax);
+    return st;
+}
+
 /* KKT report of (x, y) on the original model M (unscaled host vectors) */
 int or_kkt_report(or_solver *s, const double *x, const double *y, or_kkt *k)
 {
     if (!s || !k) return OR_ERR_ARG;
-    const double *xx = x ? x : (s->in_push ? s->xpush : s->xsol), *yy = y ? y : s->ysol;
+    const double *xx = x ? x : (s->in_push == 1 ? s->xpush : s->xsol);
+    const double *yy = y ? y : (s->in_push == 2 ? s->ypush : s->ysol);
     double *ax = dalloc(s->m), *z = dalloc(s->n);
     reduced_costs(s, xx, yy, z, ax, k);
     corner_counts(s, xx, ax, yy, z, k);
@@ -910,9 +1027,11 @@ void or_get_iterate_scaled(const or_solver *s, double *x, double *y)
 }
 void or_get_solution(const or_solver *s, double *x, double *y, double *z)
 {
-    if (x) memcpy(x, s->in_push ? s->xpush : s->xsol, sizeof(double) * (size_t)s->n);
-    if (y) memcpy(y, s->ysol, sizeof(double) * (size_t)s->m);
-    if (z) memcpy(z, s->zsol, sizeof(double) * (size_t)s->n);
+    /* after a dual push: the solve's x, the pushed y and its reduced costs */
+    const int dual = s->in_push == 2;
+    if (x) memcpy(x, s->in_push == 1 ? s->xpush : s->xsol, sizeof(double) * (size_t)s->n);
+    if (y) memcpy(y, dual ? s->ypush : s->ysol, sizeof(double) * (size_t)s->m);
+    if (z) memcpy(z, dual ? s->zpush : s->zsol, sizeof(double) * (size_t)s->n);
 }
 void or_get_scaling(const or_solver *s, double *dr, double *dc, double *out5)
 {
@@ -925,6 +1044,11 @@ void or_get_scaling(const or_solver *s, double *dr, double *dc, double *out5)
         out5[3] = (double)s->t;
         out5[4] = (double)s->power_steps;
     }
+}
+/* scaled right-hand side of the current phase */
+void or_get_rhs_scaled(const or_solver *s, double *bh)
+{
+    if (bh) memcpy(bh, s->bh, sizeof(double) * (size_t)s->m);
 }
 /* scaled model of the current phase (bounds, objective, senses) */
 void or_get_model_scaled(const or_solver *s, double *lh, double *uh, double *ch, char *sense)
@@ -957,3 +1081,4 @@ int or_num_threads(void)
 int or_params_size(void) { return (int)sizeof(or_params); }
 int or_kkt_size(void) { return (int)sizeof(or_kkt); }
 int or_push_result_size(void) { return (int)sizeof(or_push_result); }
+int or_dual_push_result_size(void) { return (int)sizeof(or_dual_push_result); }
