@@ -34,6 +34,9 @@ WORKLOADS = {
            "column, planted degenerate optima (seeds 3000+i)"),
     "c4": ("multicommodity flow LP: 50000 nodes, 400000 arcs, 8 commodities (m=800000 node-balance + arc-capacity "
            "rows, n=3.2M, nnz=9.6M; seed 4100)"),
+    "c5": ("random sparse LP m=100000 n=400000 with the c1 structure and a primal-degenerate planted optimum (85% "
+           "of columns at zero, none dual-degenerate: fewer variables off their bounds than rows, a large dual "
+           "optimal face; seed 5)"),
 }
 
 
@@ -46,6 +49,8 @@ def make_lp(cfg):
         return lpgen.config2(2)
     if cfg == "c4":
         return lpgen.config4()
+    if cfg == "c5":
+        return lpgen.config5()
     return lpgen.config0(0)
 
 
@@ -194,6 +199,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--push-compact", type=int, default=1, choices=[0, 1],
                     help="1 (default): the push iterates on its free columns; 0: on the full push model")
+    ap.add_argument("--push", default="primal", choices=["primal", "dual"],
+                    help="primal (default): the corner push of Algorithm 1; dual: the dual corner push")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every cycle eagerly instead of replaying captured hipGraphs (profiler runs)")
     args = ap.parse_args()
@@ -213,6 +220,9 @@ def main():
     copy_gbs = pdhg.copy_probe(1 << 30, 20)
     print(f"[bench] copy probe 1 GiB: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     if args.config == "c3":
+        if args.push == "dual":
+            print("the dual push is a single-LP entry point; c3 is a batch", file=sys.stderr)
+            sys.exit(2)
         return bench_batch(args, pdhg, copy_gbs)
 
     if args.iters_only:
@@ -227,7 +237,7 @@ def main():
         s = pdhg.Solver(lp, precision=args.precision, timing=timing, use_graph=0 if args.no_graph else 1,
                         push_compact=args.push_compact)
         r = s.solve()
-        p = s.corner_push(args.seed)
+        p = s.corner_push(args.seed) if args.push == "primal" else s.dual_push(args.seed)
         t = s.get_timing() if timing else None
         s.destroy()
         return r, p, t
@@ -250,13 +260,20 @@ def main():
         prim_ms += tim.primal_ms * tim.samples
         dual_ms += tim.dual_ms * tim.samples
         samples += tim.samples
-        details.append({"solve_iters": r.iters, "solve_status": pdhg.STATUS[r.status], "push_iters": p.iters,
-                        "push_status": pdhg.STATUS[p.status], "step_s": te - ts,
-                        "rel_kkt": [r.rel_p, r.rel_d, r.rel_gap], "pobj": r.pobj,
-                        "off_bound_before": p.before.p_off, "off_bound_after": p.after.p_off,
-                        "candidates_before": p.before.candidates, "candidates_after": p.after.candidates,
-                        "est_primal_before": p.before.est_primal, "est_primal_after": p.after.est_primal,
-                        "fixed": p.n_fix_lower + p.n_fix_upper, "rows_to_eq": p.n_rows_to_eq})
+        d = {"solve_iters": r.iters, "solve_status": pdhg.STATUS[r.status], "push_iters": p.iters,
+             "push_status": pdhg.STATUS[p.status], "step_s": te - ts,
+             "rel_kkt": [r.rel_p, r.rel_d, r.rel_gap], "pobj": r.pobj}
+        if args.push == "primal":
+            d.update({"off_bound_before": p.before.p_off, "off_bound_after": p.after.p_off,
+                      "candidates_before": p.before.candidates, "candidates_after": p.after.candidates,
+                      "est_primal_before": p.before.est_primal, "est_primal_after": p.after.est_primal,
+                      "fixed": p.n_fix_lower + p.n_fix_upper, "rows_to_eq": p.n_rows_to_eq})
+        else:
+            d.update({"zero_rc_before": p.before.d_zero, "zero_rc_after": p.after.d_zero,
+                      "est_dual_before": p.before.est_dual, "est_dual_after": p.after.est_dual,
+                      "cols_free": p.n_cols_free, "rows_fixed": p.n_rows_fixed,
+                      "rel_d_push": p.rel_d_push, "push_s": p.seconds})
+        details.append(d)
         print(f"[bench] step {k}: {te - ts:.3f}s solve {r.iters} push {p.iters}", file=sys.stderr, flush=True)
     elapsed = time.perf_counter() - t_start
     value = iters / elapsed
@@ -287,9 +304,11 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64norms", "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}; step = create + solve to 1e-6 relative "
-                               f"KKT + corner push", "m": lp.m, "n": lp.n, "nnz": lp.nnz,
+                               f"KKT + {'corner push' if args.push == 'primal' else 'dual corner push'}",
+                   "m": lp.m, "n": lp.n, "nnz": lp.nnz,
                    "precision": args.precision, "eps_rel": 1e-6, "push_seed": args.seed,
-                   "push_on_free_columns": bool(args.push_compact)},
+                   "push_on_free_columns": bool(args.push_compact) and args.push == "primal",
+                   "push": args.push},
         "roofline": roof,
         "detail": {"steps": details, "time_to_corner_s": round(elapsed / args.steps, 4),
                    "lanes_at": tim.lanes_at, "lanes_a": tim.lanes_a},

@@ -179,6 +179,21 @@ typedef struct pdhg_push_result {
     int64_t n_learned_undo; /* learned push: fixes undone at push checks               */
 } pdhg_push_result;
 
+/* Outcome of the dual corner push (pdhg_dual_push). */
+typedef struct pdhg_dual_push_result {
+    int32_t status;       /* PDHG_PUSH_DONE, ITER_LIMIT, TIME_LIMIT or NUMERICAL       */
+    int32_t pad_;
+    int64_t iters;        /* push iterations                                          */
+    int64_t restarts;
+    int64_t n_cols_free;  /* columns off both bounds by more than eps_abs (z_j = 0)   */
+    int64_t n_rows_fixed; /* inequality rows with slack beyond eps_abs: y_i held at
+                             the solve's value (dropped from the push model)          */
+    double rel_d_push;    /* relative dual residual of the push model at the stop     */
+    double seconds;
+    pdhg_kkt_report before; /* (x, y, z) of the solve, original model                 */
+    pdhg_kkt_report after;  /* (x, yhat, zhat): the solve's x with the pushed y       */
+} pdhg_dual_push_result;
+
 /* Live kernel timing (params.timing = 1): average durations of the two
  * iteration kernels over the sampled launches of every solve and push call
  * since pdhg_create, and their algorithmic bytes per launch (matrix values,
@@ -224,13 +239,39 @@ int pdhg_iterate(pdhg_solver *s, int64_t iters, pdhg_result *r);
  * j * 0x9E3779B97F4A7C15, top 53 bits).  Requires a prior solve (STATE). */
 int pdhg_corner_push(pdhg_solver *s, uint64_t seed, pdhg_push_result *r);
 
+/* Dual corner push: the mirror image of Algorithm 1 for the dual superbasics
+ * that section 6 says the same technique could reduce (the paper gives no
+ * construction; this is the library's reading).  Keeps the solve's x and
+ * restricts (y, z) to the dual optimal face that complementary slackness with
+ * x defines: z_j = 0 for a column off both bounds by more than eps_abs,
+ * z_j >= 0 (<= 0) for one within eps_abs of its lower (upper) bound only, and
+ * an inequality row whose slack exceeds eps_abs keeps its dual.  Like
+ * Algorithm 1, which fixes bounds at the solve's x so that x stays feasible,
+ * the face is anchored at the solve's ybar: a dropped row keeps y_i = ybar_i,
+ * and each column's objective is shifted by the part of its reduced cost at
+ * ybar that its sign rule rejects.  On that face PDHG maximises g'y,
+ * g = push_obj_scale * (A w0 - s.v): w0_j = U_j inside the column's cone (-U_j
+ * for an upper-bound cone, 0 for a column at both bounds), v_i = U_(n+i) on
+ * inequality rows (s_i = +1 for '>', -1 for '<'), U_k the uniform draw of
+ * pdhg_corner_push's generator at index k; w0 keeps the push model feasible,
+ * so the push is bounded.  Starts from (0, ybar), stops as soon as the push
+ * model's dual residual over (1 + ||c||) is back at eps_rel (after at least
+ * push_min_iters iterations; checks at push_min_iters + k K).  Afterwards
+ * pdhg_get_solution gives (x, yhat, zhat), zhat the reduced costs of yhat on
+ * the original model.  One push per solve: STATE before a solve or after a
+ * push of either kind.  Single LP only; the push runs on the full model
+ * (push_compact applies to pdhg_corner_push).  Errors: INVALID_ARG, STATE,
+ * HIP. */
+int pdhg_dual_push(pdhg_solver *s, uint64_t seed, pdhg_dual_push_result *r);
+
 /* KKT report of (x, y) on the original model, in float64.  x (n) and y (m)
  * are host arrays; NULL selects the current solution.  Errors: INVALID_ARG. */
 int pdhg_kkt(pdhg_solver *s, const double *x, const double *y, pdhg_kkt_report *k);
 
 /* Current solution, unscaled: after a solve the last checked candidate
  * (x, y) and z = reduced costs; after a push (xhat, y, z) with the solve's y
- * and z (Algorithm 1 returns them unchanged).  Any pointer may be NULL. */
+ * and z (Algorithm 1 returns them unchanged); after a dual push (x, yhat,
+ * zhat) with the solve's x.  Any pointer may be NULL. */
 int pdhg_get_solution(pdhg_solver *s, double *x, double *y, double *z);
 
 /* The solve's own answer (x, y, z), unscaled, also after a push: the point a
@@ -444,7 +485,7 @@ const char *pdhg_last_error(void);
 
 /* Size checks for bindings: sizeof of each public struct. */
 int32_t pdhg_struct_size(int32_t which); /* 0 params, 1 result, 2 kkt, 3 push, 4 timing,
-                                             5 lp desc, 6 batch report */
+                                             5 lp desc, 6 batch report, 7 dual push */
 
 #ifdef __cplusplus
 }

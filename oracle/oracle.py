@@ -74,7 +74,7 @@ class OrPushResult(C.Structure):
 class OrDualPushResult(C.Structure):
     _fields_ = [
         ("status", C.c_int32), ("pad_", C.c_int32), ("iters", C.c_int64), ("restarts", C.c_int64),
-        ("n_rc_zero", C.c_int64), ("n_dual_zero", C.c_int64),
+        ("n_cols_free", C.c_int64), ("n_rows_fixed", C.c_int64),
         ("rel_d_push", C.c_double), ("before", OrKKT), ("after", OrKKT),
     ]
 

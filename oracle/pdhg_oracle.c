@@ -52,20 +52,29 @@
  *   complementary slackness with x defines: a column further than eps_abs
  *   from both bounds gets z_j = 0, one within eps_abs of its lower bound only
  *   z_j >= 0, of its upper bound only z_j <= 0, of both z_j free; an
- *   inequality row whose slack exceeds eps_abs gets y_i = 0 (sense 'N'),
- *   every other row keeps its sign rule.  That face is the dual feasible set of
- *   the push model  min c'w  s.t.  a_i'w (sense_i) g_i,  w_j in the cone of
- *   column j (R, R+, R-, {0}),  whose right-hand side is random but anchored:
+ *   inequality row whose slack exceeds eps_abs keeps its dual fixed (sense
+ *   'N'), every other row keeps its sign rule.  As Algorithm 1 fixes bounds
+ *   at the solve's x rather than at the bound, so that x stays feasible, the
+ *   dual push fixes at the solve's point ybar: a dropped row's y_i stays
+ *   ybar_i (its term moves into the objective), and each column's objective
+ *   is shifted by r_j, the part of its reduced cost at ybar that its cone
+ *   rejects (all of it off both bounds, the negative part at the lower bound
+ *   only, the positive part at the upper bound only), so that ybar is a point
+ *   of the face.  The face is then the dual feasible set of the push model
+ *     min c~'w  s.t.  a_i'w (sense_i) g_i (rows kept),  w_j in the cone of
+ *     column j (R, R+, R-, {0}),  c~ = c - A_N' ybar_N - r,
+ *   whose right-hand side is random but anchored:
  *   g = scale * (A w0 - s.v), w0 a random point of the cones (w0_j = U_j on
  *   R and R+, -U_j on R-, 0 on {0}), v_i = U_(n+i) a random slack with
  *   s_i = +1 on '>' rows, -1 on '<' rows, 0 on '=' rows.  w0 is feasible for
  *   the push model, so the random dual objective g'y is bounded on the face
  *   (the mirror of the primal push, whose model keeps the solve's x
  *   feasible); a random g alone is unbounded wherever A has dependent
- *   equality rows.  PDHG restarts from (0, y) and stops
- *   as soon as the dual residual of the push model is back at the original
- *   tolerance, after at least push_min_iters iterations.  Returns (x, yhat,
- *   zhat): the solve's x, the pushed y and its reduced costs.
+ *   equality rows.  PDHG restarts from (0, ybar) and stops
+ *   as soon as the dual residual of the push model, relative to 1 + ||c||,
+ *   is back at the original tolerance, after at least push_min_iters
+ *   iterations.  Returns (x, yhat, zhat): the solve's x, the pushed y (ybar
+ *   on the dropped rows) and its reduced costs on the original model.
  */
 #include <math.h>
 #include <stdint.h>
@@ -142,8 +151,8 @@ typedef struct {
     int32_t status;
     int32_t pad_;
     int64_t iters, restarts;
-    int64_t n_rc_zero;   /* columns strictly inside their bounds: z_j pinned to 0 */
-    int64_t n_dual_zero; /* inequality rows with slack: y_i pinned to 0          */
+    int64_t n_cols_free;  /* columns off both bounds: reduced cost held at ybar's */
+    int64_t n_rows_fixed; /* inequality rows with slack: y_i held at ybar_i        */
     double rel_d_push;   /* relative dual residual of the push model at the stop */
     or_kkt before, after;
 } or_dual_push_result;
@@ -182,6 +191,7 @@ typedef struct {
     double *xsol, *ysol, *zsol;
     double *xpush;         /* unscaled push result */
     double *ypush, *zpush; /* unscaled dual push result and its reduced costs */
+    double *cpush;         /* unscaled objective of the dual push model        */
     or_params p;
 } or_solver;
 
@@ -484,7 +494,7 @@ void or_destroy(or_solver *s)
     void *ptrs[] = {s->rp, s->ci, s->av, s->tp, s->ti, s->tpos, s->b, s->c, s->l, s->u, s->sense0,
                     s->ahat, s->ahat_t, s->dr, s->dc, s->bh, s->ch, s->lh, s->uh, s->sense, s->x,
                     s->y, s->xa, s->ya, s->xp, s->yp, s->xbar, s->g, s->hv, s->xs_hat, s->xsol,
-                    s->ysol, s->zsol, s->xpush, s->ys_hat, s->ypush, s->zpush};
+                    s->ysol, s->zsol, s->xpush, s->ys_hat, s->ypush, s->zpush, s->cpush};
     for (size_t q = 0; q < sizeof(ptrs) / sizeof(ptrs[0]); q++) free(ptrs[q]);
     free(s);
 }
@@ -676,6 +686,7 @@ or_solver *or_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, 
     s->ys_hat = dalloc(m);
     s->ypush = dalloc(m);
     s->zpush = dalloc(n);
+    s->cpush = dalloc(n);
 
     scale_and_step(s);
     for (int i = 0; i < m; i++) {
@@ -802,10 +813,11 @@ static int run_phase(or_solver *s, int64_t iters, double *out_relp)
         } else if (s->in_push == 2) {
             /* dual residual of the dual push model: its cones (0 or infinite,
                the same scaled and unscaled) decide what the bounds absorb */
-            kkt_unscaled(s, s->c, s->lh, s->uh, s->sense, x, y, ax, aty, NULL, &k);
-            memcpy(s->ypush, y, sizeof(double) * (size_t)m);
-            if (out_relp) *out_relp = k.rel_d;
-            if (k.rel_d <= s->p.eps_rel) {
+            kkt_unscaled(s, s->cpush, s->lh, s->uh, s->sense, x, y, ax, aty, NULL, &k);
+            double reld = k.rd2 / (1.0 + norm2(s->c, n));
+            for (int i = 0; i < m; i++) s->ypush[i] = s->sense[i] == 'N' ? s->ysol[i] : y[i];
+            if (out_relp) *out_relp = reld;
+            if (reld <= s->p.eps_rel) {
                 status = OR_PUSH_DONE;
                 break;
             }
@@ -951,41 +963,59 @@ int or_dual_push(or_solver *s, uint64_t seed, or_dual_push_result *r)
     reduced_costs(s, s->xsol, s->ysol, s->zsol, ax, &r->before);
     corner_counts(s, s->xsol, ax, s->ysol, s->zsol, &r->before);
     double ea = s->p.eps_abs, sc = s->p.push_obj_scale;
-    double *w0 = dalloc(n), *aw = dalloc(m);
+    double *w0 = dalloc(n), *aw = dalloc(m), *yn = dalloc(m), *atyn = dalloc(n), *aty = dalloc(n);
+    double *tv = dalloc(s->nnz);
+    gather_t(s, s->av, tv);
+    /* DP3: rows with slack beyond eps_abs leave the push model, their dual
+       fixed at the solve's value */
+    for (int i = 0; i < m; i++) {
+        char sn = s->sense0[i];
+        double slack = sn == '<' ? s->b[i] - ax[i] : (sn == '>' ? ax[i] - s->b[i] : 0.0);
+        int drop = sn != '=' && slack > ea;
+        s->sense[i] = drop ? 'N' : sn;
+        yn[i] = drop ? s->ysol[i] : 0.0;
+        r->n_rows_fixed += drop;
+    }
+    mv_At(s, tv, s->ysol, aty); /* A'ybar */
+    mv_At(s, tv, yn, atyn);     /* A_N'ybar_N */
     /* DP2: the cone of each push column from where x sits against its bounds,
-       and the anchor point w0 in it */
+       the objective c~ = c - A_N'ybar_N - r, and the anchor point w0 */
     for (int j = 0; j < n; j++) {
         int at_lo = !is_inf_lo(s->l[j]) && s->xsol[j] - s->l[j] <= ea;
         int at_up = !is_inf_up(s->u[j]) && s->u[j] - s->xsol[j] <= ea;
         s->lh[j] = at_lo ? 0.0 : -INFINITY;
         s->uh[j] = at_up ? 0.0 : INFINITY;
-        if (!at_lo && !at_up) r->n_rc_zero++;
+        if (!at_lo && !at_up) r->n_cols_free++;
+        double lam = s->c[j] - aty[j];
+        double rj = (at_lo && at_up) ? 0.0 : at_lo ? fmin(lam, 0.0) : at_up ? fmax(lam, 0.0) : lam;
+        s->cpush[j] = s->c[j] - atyn[j] - rj;
+        s->ch[j] = s->dc[j] * s->cpush[j];
         double uj = or_push_uniform(seed, j);
         w0[j] = (at_lo && at_up) ? 0.0 : (at_up ? -uj : uj);
         s->x[j] = 0.0; /* DP5: w = 0 */
     }
     mv_A(s, s->av, w0, aw);
-    /* DP3, DP4: rows with slack dropped (y_i = 0); the anchored random
-       right-hand side (scaled like b) on the others; y starts at the solve's */
+    /* DP4: the anchored random right-hand side (scaled like b) on the rows
+       kept; y starts at the solve's there (and is 0 on dropped rows) */
     for (int i = 0; i < m; i++) {
-        char sn = s->sense0[i];
-        double slack = sn == '<' ? s->b[i] - ax[i] : (sn == '>' ? ax[i] - s->b[i] : 0.0);
-        if (sn != '=' && slack > ea) {
-            s->sense[i] = 'N';
+        char sn = s->sense[i];
+        if (sn == 'N') {
             s->bh[i] = 0.0;
             s->y[i] = 0.0;
-            r->n_dual_zero++;
         } else {
             double v = or_push_uniform(seed, (int64_t)n + i);
             double g = sn == '>' ? aw[i] - v : (sn == '<' ? aw[i] + v : aw[i]);
-            s->sense[i] = sn;
             s->bh[i] = s->dr[i] * (sc * g);
             s->y[i] = s->ys_hat[i];
         }
     }
     free(w0);
     free(aw);
-    /* DP5: new weight and restart state; the objective stays c */
+    free(yn);
+    free(atyn);
+    free(aty);
+    free(tv);
+    /* DP5: new weight and restart state */
     s->omega = initial_omega(s->ch, n, s->bh, m);
     s->in_push = 2;
     reset_iteration(s, s->p.push_min_iters);

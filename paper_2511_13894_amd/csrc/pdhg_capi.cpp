@@ -74,6 +74,12 @@ void dalloc(T **p, size_t count)
     hip_check(hipMalloc((void **)p, sizeof(T) * (count > 0 ? count : 1)), "hipMalloc");
 }
 
+// The handle's current answer (unscaled, device): the solve's, the primal
+// push's (xhat, y, z) or the dual push's (x, yhat, zhat).
+const double *cur_x(const pdhg_solver *s) { return s->in_push && !s->dual_pushed ? s->xpush : s->xu; }
+const double *cur_y(const pdhg_solver *s) { return s->dual_pushed ? s->ypush : s->yu; }
+const double *cur_z(const pdhg_solver *s) { return s->dual_pushed ? s->zpush : s->zsol; }
+
 void free_all(pdhg_solver *s)
 {
     (void)push_compact_end(s, false);
@@ -82,7 +88,8 @@ void free_all(pdhg_solver *s)
                     s->xbar, s->xp, s->yp,  s->ch,   s->bh,     s->lh,    s->uh,   s->xs,  s->ys,      s->sense,
                     s->ax,   s->aty, s->xu, s->yu,   s->zsol,   s->xpush, s->partials, s->redout, s->st,
                     s->hx,   s->hz,  s->feat_raw, s->feat_b, s->logits, s->lfix, s->lcount, s->sell_idx,
-                    s->sell_val, s->sell_soff, s->sell_len, s->sell_wi_start, s->sell_wi, s->sell_part};
+                    s->sell_val, s->sell_soff, s->sell_len, s->sell_wi_start, s->sell_wi, s->sell_part,
+                    s->ypush, s->zpush};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->st_host) (void)hipHostFree(s->st_host);
@@ -346,6 +353,7 @@ int32_t pdhg_struct_size(int32_t which)
     case 4: return (int32_t)sizeof(pdhg_timing);
     case 5: return (int32_t)sizeof(pdhg_lp_desc);
     case 6: return (int32_t)sizeof(pdhg_batch_report);
+    case 7: return (int32_t)sizeof(pdhg_dual_push_result);
     default: return -1;
     }
 }
@@ -661,6 +669,57 @@ int pdhg_corner_push_learned(pdhg_solver *s, pdhg_mlp *net, double theta, uint64
     return corner_push_common(s, seed, r, net, theta);
 }
 
+// The dual corner push: DP1 the solve's answer and its report (which leaves
+// A x in s->ax and A'y in s->aty), DP2-DP5 the dual face of x as a push model
+// anchored at the solve's y, with the anchored random right-hand side, start
+// (0, y), DP6 PDHG to the dual test, DP7 (x, yhat, zhat).
+int pdhg_dual_push(pdhg_solver *s, uint64_t seed, pdhg_dual_push_result *r)
+{
+    if (!s || !r) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    if (!s->solved || s->in_push) return fail(PDHG_ERR_STATE, "dual push needs a solve first (and runs once)");
+    std::memset(r, 0, sizeof(*r));
+    const double t0 = now_s();
+    try {
+        hipStream_t st = s->stream;
+        const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
+        if (!s->ypush) dalloc(&s->ypush, (size_t)(s->m > 0 ? s->m : 1));
+        if (!s->zpush) dalloc(&s->zpush, (size_t)(s->n > 0 ? s->n : 1));
+        // DP1
+        HIPCHK(hipMemcpyAsync(s->xs, s->xp, vb * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(s->ys, s->yp, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
+        HIPCHK(unscale(s, s->xs, s->ys, s->xu, s->yu));
+        HIPCHK(report(s, s->xu, s->yu, s->zsol, &r->before));
+        // DP2-DP5; w0 lives in xpush, ybar on the dropped rows in ypush and
+        // A_N'ybar_N in zpush until the push writes them
+        HIPCHK(dual_push_setup(s, seed, s->xpush, s->ypush, s->zpush, &r->n_cols_free, &r->n_rows_fixed));
+        HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        s->in_push = true;
+        s->dual_pushed = true;
+        s->has_candidate = false;
+        s->t_host = 0;
+        s->next_check = s->p.push_min_iters;
+        // DP6
+        int status = run_phase(s, s->p.push_max_iter, 3, t0);
+        // DP7
+        if (s->has_candidate) {
+            HIPCHK(unscale(s, nullptr, s->yp, nullptr, s->ypush));
+            HIPCHK(dual_push_finish(s)); // the solve's y on the dropped rows
+        } else {
+            HIPCHK(hipMemcpyAsync(s->ypush, s->yu, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
+        }
+        HIPCHK(report(s, s->xu, s->ypush, s->zpush, &r->after));
+        r->status = status;
+        r->iters = s->t_host;
+        r->restarts = s->st_host->restarts;
+        r->rel_d_push = s->st_host->checks > 0 ? s->st_host->rel_d : NAN;
+        r->seconds = now_s() - t0;
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
 int pdhg_features(pdhg_solver *s, uint64_t seed, float *out)
 {
     if (!s) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
@@ -689,8 +748,8 @@ int pdhg_kkt(pdhg_solver *s, const double *x, const double *y, pdhg_kkt_report *
             pdhg_kkt_report tmp;
             solution_report(s, &tmp);
         }
-        const double *cx = s->in_push ? s->xpush : s->xu;
-        const double *cy = s->yu;
+        const double *cx = cur_x(s);
+        const double *cy = cur_y(s);
         if (x) {
             dalloc(&dx, (size_t)s->n);
             HIPCHK(hipMemcpyAsync(dx, x, sizeof(double) * (size_t)s->n, hipMemcpyHostToDevice, st));
@@ -720,10 +779,9 @@ int pdhg_get_solution(pdhg_solver *s, double *x, double *y, double *z)
             pdhg_kkt_report tmp;
             solution_report(s, &tmp);
         }
-        const double *cx = s->in_push ? s->xpush : s->xu;
-        if (x) HIPCHK(hipMemcpyAsync(x, cx, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
-        if (y) HIPCHK(hipMemcpyAsync(y, s->yu, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToHost, st));
-        if (z) HIPCHK(hipMemcpyAsync(z, s->zsol, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
+        if (x) HIPCHK(hipMemcpyAsync(x, cur_x(s), sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
+        if (y) HIPCHK(hipMemcpyAsync(y, cur_y(s), sizeof(double) * (size_t)s->m, hipMemcpyDeviceToHost, st));
+        if (z) HIPCHK(hipMemcpyAsync(z, cur_z(s), sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
     } catch (const HipFailure &f) {
         return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
@@ -761,10 +819,9 @@ int pdhg_get_solution_device(pdhg_solver *s, double *x, double *y, double *z, vo
             pdhg_kkt_report tmp;
             solution_report(s, &tmp);
         }
-        const double *cx = s->in_push ? s->xpush : s->xu;
-        if (x) HIPCHK(hipMemcpyAsync(x, cx, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
-        if (y) HIPCHK(hipMemcpyAsync(y, s->yu, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
-        if (z) HIPCHK(hipMemcpyAsync(z, s->zsol, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+        if (x) HIPCHK(hipMemcpyAsync(x, cur_x(s), sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+        if (y) HIPCHK(hipMemcpyAsync(y, cur_y(s), sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
+        if (z) HIPCHK(hipMemcpyAsync(z, cur_z(s), sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
         hipStream_t cs = stream ? (hipStream_t)stream : st;
         if (cs != st) { // order the caller's stream after the copies
             hipEvent_t ev = nullptr;

@@ -112,6 +112,7 @@ struct pdhg_solver {
     // float64 work: products, unscaled copies, reduced costs, partial sums
     double *ax = nullptr, *aty = nullptr;
     double *xu = nullptr, *yu = nullptr, *zsol = nullptr, *xpush = nullptr;
+    double *ypush = nullptr, *zpush = nullptr; // dual push result (allocated by the dual push)
     double *partials = nullptr;
     double *redout = nullptr; // small reduction results
     int red_blocks_m = 1, red_blocks_n = 1;
@@ -126,6 +127,7 @@ struct pdhg_solver {
     int64_t power_steps = 0; // power-iteration steps taken at create
     int64_t next_check = 0;  // phase iteration count of the next check
     bool in_push = false;
+    bool dual_pushed = false; // the handle's push was the dual push
     // sliced ELLPACK copy of Ahat for the dual half (kernel code kSell)
     int *sell_idx = nullptr, *sell_len = nullptr, *sell_wi_start = nullptr;
     void *sell_val = nullptr;
@@ -257,6 +259,9 @@ hipError_t launch_start_vectors(pdhg_solver *s, bool fresh_start);
 hipError_t unscale(pdhg_solver *s, const void *xh, const void *yh, double *xo, double *yo);
 hipError_t report(pdhg_solver *s, const double *x, const double *y, double *z, pdhg_kkt_report *k);
 hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, double theta);
+hipError_t dual_push_setup(pdhg_solver *s, uint64_t seed, double *w0, double *yn, double *atyn, int64_t *n_cols_free,
+                           int64_t *n_rows_fixed);
+hipError_t dual_push_finish(pdhg_solver *s);
 // push on the free columns only: build the compact model and put it in place,
 // or (end) put x and x+ back into the full vectors and restore the full model
 hipError_t push_compact_begin(pdhg_solver *s);

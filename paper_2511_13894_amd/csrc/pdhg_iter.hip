@@ -394,6 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_check_rows(int m, const double *__re
         const int8_t s = sense[i];
         if (s == '<') r = r < 0.0 ? r : 0.0;
         else if (s == '>') r = r > 0.0 ? r : 0.0;
+        else if (s == 'N') r = 0.0; // dropped by the dual push
         const double ru = r / dr[i];
         const double yi = (double)yc[i];
         const double dy = yi - (double)ya[i];
@@ -1041,6 +1042,142 @@ hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, double
 {
     s->model_original = false;
     return s->fp32 ? push_setup_impl<float>(s, seed, r, theta) : push_setup_impl<double>(s, seed, r, theta);
+}
+
+// -------------------------------------------------------- dual push ---
+// The mirror image of Algorithm 1 on the dual side, anchored at the solve's
+// ybar as Algorithm 1 is at its x.  Rows: an inequality row with slack beyond
+// eps_abs leaves the push model (sense 'N'), its dual held at ybar_i; yn
+// carries ybar on those rows and 0 elsewhere.  ax = A x (unscaled).
+__global__ __launch_bounds__(kBlock) void k_dpush_rows(int m, const int8_t *__restrict__ sense0,
+                                                      const double *__restrict__ b, const double *__restrict__ ax,
+                                                      const double *__restrict__ yu, double eps_abs,
+                                                      int8_t *__restrict__ sense, double *__restrict__ yn,
+                                                      double *__restrict__ part)
+{
+    double v[1] = {0.0}; // rows dropped, dual held at the solve's
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+        const int8_t sn = sense0[i];
+        const double slack = sn == '<' ? b[i] - ax[i] : (sn == '>' ? ax[i] - b[i] : 0.0);
+        const bool drop = sn != '=' && slack > eps_abs;
+        sense[i] = drop ? (int8_t)'N' : sn;
+        yn[i] = drop ? yu[i] : 0.0;
+        v[0] += drop ? 1.0 : 0.0;
+    }
+    block_reduce<1>(v, 0u);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// Columns: the cone of push variable w_j from where the solve's x sits: R off
+// both bounds (z_j = 0 on the face), R+ within eps_abs of the lower bound only
+// (z_j >= 0), R- of the upper bound only (z_j <= 0), {0} of both (z_j free);
+// bounds 0 or infinite, the same scaled and unscaled.  Objective
+// c~ = c - A_N'ybar_N - r, r_j the part of lambda_j = c_j - a_j'ybar that the
+// cone rejects, so ybar lies on the face; stored scaled.  w0 (unscaled, for
+// the anchored right-hand side A w0) is U_j in the cone; the iterate starts at 0.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_dpush_cols(int n, const double *__restrict__ xu, const double *__restrict__ l,
+                                                      const double *__restrict__ u, const double *__restrict__ c,
+                                                      const double *__restrict__ aty, const double *__restrict__ atyn,
+                                                      const double *__restrict__ dc, double eps_abs, uint64_t seed,
+                                                      V *__restrict__ lh, V *__restrict__ uh, double *__restrict__ ch,
+                                                      V *__restrict__ x, double *__restrict__ w0,
+                                                      double *__restrict__ part, int nblk)
+{
+    double v[1] = {0.0}; // columns off both bounds
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        const double xj = xu[j];
+        const bool at_lo = !is_inf_lo(l[j]) && xj - l[j] <= eps_abs;
+        const bool at_up = !is_inf_up(u[j]) && u[j] - xj <= eps_abs;
+        lh[j] = at_lo ? (V)0 : (V)-INFINITY;
+        uh[j] = at_up ? (V)0 : (V)INFINITY;
+        const double lam = c[j] - aty[j];
+        const double rj = (at_lo && at_up) ? 0.0 : at_lo ? fmin(lam, 0.0) : at_up ? fmax(lam, 0.0) : lam;
+        ch[j] = dc[j] * (c[j] - atyn[j] - rj);
+        const double uj = push_unit(seed, j);
+        w0[j] = (at_lo && at_up) ? 0.0 : (at_up ? -uj : uj);
+        x[j] = (V)0;
+        v[0] += (!at_lo && !at_up) ? 1.0 : 0.0;
+    }
+    block_reduce<1>(v, 0u);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v[0];
+        part[nblk + blockIdx.x] = 0.0;
+    }
+}
+
+// Rows kept: y starts at the solve's and the right-hand side is the anchored
+// g_i = scale (a_i'w0 - s_i v_i), scaled like b, v_i = U_(n+i), s_i = +1 on
+// '>' rows, -1 on '<', 0 on '='; bh holds a_i'w0 (unscaled) on entry.
+// Dropped rows: bh = 0, y = 0 (their dual lives in the objective).
+__global__ __launch_bounds__(kBlock) void k_dpush_rhs(int m, int n, const int8_t *__restrict__ sense,
+                                                     const double *__restrict__ dr, const double *__restrict__ ys,
+                                                     uint64_t seed, double scale, double *__restrict__ bh,
+                                                     double *__restrict__ y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+        const int8_t sn = sense[i];
+        if (sn == 'N') {
+            bh[i] = 0.0;
+            y[i] = 0.0;
+        } else {
+            const double aw = bh[i];
+            const double vi = push_unit(seed, (int64_t)n + i);
+            const double g = sn == '>' ? aw - vi : (sn == '<' ? aw + vi : aw);
+            bh[i] = dr[i] * (scale * g);
+            y[i] = ys[i];
+        }
+    }
+}
+
+// The pushed y: the push's on the rows kept, the solve's on the dropped ones.
+__global__ __launch_bounds__(kBlock) void k_dpush_final(int m, const int8_t *__restrict__ sense,
+                                                       const double *__restrict__ yu, double *__restrict__ ypush)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock)
+        if (sense[i] == 'N') ypush[i] = yu[i];
+}
+
+// Needs report() of the solve's (xu, yu) just before: s->ax holds A xu and
+// s->aty A'yu.  w0 (n) and yn (m) are float64 work buffers of the caller;
+// atyn (n) another.
+template <typename V>
+static hipError_t dual_push_setup_impl(pdhg_solver *s, uint64_t seed, double *w0, double *yn, double *atyn,
+                                       int64_t *n_cols_free, int64_t *n_rows_fixed)
+{
+    hipStream_t st = s->stream;
+    const int gn = s->red_blocks_n, gm = s->red_blocks_m;
+    double *pcnt = s->partials + (size_t)(Q_COUNT + 1) * (gm + gn); // past the check slots
+    hipLaunchKernelGGL(k_dpush_rows, dim3(gm), dim3(kBlock), 0, st, s->m, s->sense0, s->b, s->ax, s->yu, s->p.eps_abs,
+                       s->sense, yn, pcnt + 2 * gn);
+    spmv<double, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, s->atv, yn, atyn);
+    hipLaunchKernelGGL((k_dpush_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->xu, s->l, s->u, s->c, s->aty, atyn,
+                       s->dc, s->p.eps_abs, seed, (V *)s->lh, (V *)s->uh, s->ch, (V *)s->x, w0, pcnt, gn);
+    spmv<double, double, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, s->av, w0, (double *)s->bh);
+    hipLaunchKernelGGL(k_dpush_rhs, dim3(gm), dim3(kBlock), 0, st, s->m, s->n, s->sense, s->dr, (const double *)s->ys,
+                       seed, s->p.push_obj_scale, (double *)s->bh, (double *)s->y);
+    hipLaunchKernelGGL(k_sum3, dim3(1), dim3(kBlock), 0, st, pcnt, gn, gm, s->redout);
+    hipMemcpyAsync(s->rep_host, s->redout, 3 * sizeof(double), hipMemcpyDeviceToHost, st);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    *n_cols_free = (int64_t)s->rep_host[0];
+    *n_rows_fixed = (int64_t)s->rep_host[2];
+    return phase_start<V>(s, false);
+}
+
+hipError_t dual_push_setup(pdhg_solver *s, uint64_t seed, double *w0, double *yn, double *atyn, int64_t *n_cols_free,
+                           int64_t *n_rows_fixed)
+{
+    s->model_original = false;
+    return s->fp32 ? dual_push_setup_impl<float>(s, seed, w0, yn, atyn, n_cols_free, n_rows_fixed)
+                   : dual_push_setup_impl<double>(s, seed, w0, yn, atyn, n_cols_free, n_rows_fixed);
+}
+
+hipError_t dual_push_finish(pdhg_solver *s)
+{
+    const int g = grid_for(s->m, kBlock, 8192);
+    hipLaunchKernelGGL(k_dpush_final, dim3(g), dim3(kBlock), 0, s->stream, s->m, s->sense, s->yu, s->ypush);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------- kernel choice ---

@@ -61,6 +61,7 @@ __device__ __forceinline__ void dual_update(int64_t r, double h, double yr, doub
     double yn = yr + st->sigma * (br - h);
     if (sn == '<') yn = yn < 0.0 ? yn : 0.0;
     else if (sn == '>') yn = yn > 0.0 ? yn : 0.0;
+    else if (sn == 'N') yn = 0.0; // a row the dual push drops: y_i = 0
     if (store_cand) yp[r] = yn;
     if (st->halpern) {
         double w, wa, gm;
@@ -199,7 +200,8 @@ __device__ __forceinline__ double kkt_weighted(double om, double p2, double d2, 
 // v[Q_COUNT], the column NaN count):
 //   mode 0: record the anchor's weighted-KKT parts (start of a phase);
 //   mode 1: solve check (termination on all three relative tests, restart);
-//   mode 2: push check (termination on the primal test only, restart).
+//   mode 2: push check (termination on the primal test only, restart);
+//   mode 3: dual push check (termination on the dual test only, restart).
 // `len` is the number of iterations since the last state update.
 __device__ inline void check_decide(DevState *st, const double *v, int mode, int len)
 {
@@ -236,7 +238,7 @@ __device__ inline void check_decide(DevState *st, const double *v, int mode, int
         st->k0 = k_now;
         return;
     }
-    if (mode == 2 && st->rel_p <= eps) {
+    if ((mode == 2 && st->rel_p <= eps) || (mode == 3 && st->rel_d <= eps)) {
         st->done = 1;
         st->status = PDHG_PUSH_DONE;
         st->k0 = k_now;

@@ -192,6 +192,15 @@ def config1(seed: int = 1, m: int = 100_000, n: int = 400_000) -> LP:
                    power_law=(1, 200, 1.75), name=f"c1_s{seed}_m{m}_n{n}")
 
 
+def config5(seed: int = 5, m: int = 100_000, n: int = 400_000) -> LP:
+    """The c1 structure with a primal-degenerate planted optimum (dual push workload):
+    85% of columns at zero and no dual-degenerate zeros, so about 0.15 n columns and
+    0.3 m slacks sit off their bounds against m rows and the dual optimal face has
+    dimension of order m - 0.15 n - 0.3 m."""
+    return planted(m, n, seed, zero_frac=0.85, degen_frac=0.0, ineq_frac=0.5, upper_frac=0.3,
+                   power_law=(1, 200, 1.75), name=f"c5_s{seed}_m{m}_n{n}")
+
+
 def config3_instance(i: int, base_seed: int = 3000, m_range=(500, 20_000)) -> LP:
     """Instance i of the batched family: m log-uniform, n = round(2.5 m), degree U{4..8}."""
     seed = base_seed + i

@@ -73,6 +73,14 @@ class PushResult(C.Structure):
     ]
 
 
+class DualPushResult(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("pad_", C.c_int32), ("iters", C.c_int64), ("restarts", C.c_int64),
+        ("n_cols_free", C.c_int64), ("n_rows_fixed", C.c_int64),
+        ("rel_d_push", C.c_double), ("seconds", C.c_double), ("before", KKTReport), ("after", KKTReport),
+    ]
+
+
 class Timing(C.Structure):
     _fields_ = [
         ("primal_ms", C.c_double), ("dual_ms", C.c_double), ("samples", C.c_int64),
@@ -125,7 +133,8 @@ EXPORTS = ["pdhg_default_params", "pdhg_create", "pdhg_solve", "pdhg_iterate", "
            "pdhg_mlp_gradient", "pdhg_default_train_params", "pdhg_mlp_train", "pdhg_features",
            "pdhg_batch_features", "pdhg_batch_corner_push_learned",
            "pdhg_corner_push_learned", "pdhg_get_solution_device", "pdhg_set_start", "pdhg_state_size",
-           "pdhg_get_state", "pdhg_set_state", "pdhg_get_solve_solution", "pdhg_batch_get_solve_solution"]
+           "pdhg_get_state", "pdhg_set_state", "pdhg_get_solve_solution", "pdhg_batch_get_solve_solution",
+           "pdhg_dual_push"]
 
 _lib = None
 
@@ -148,6 +157,7 @@ def load(path: Optional[Path] = None):
     lib.pdhg_solve.argtypes = [C.c_void_p, P(Result)]
     lib.pdhg_iterate.argtypes = [C.c_void_p, C.c_int64, P(Result)]
     lib.pdhg_corner_push.argtypes = [C.c_void_p, C.c_uint64, P(PushResult)]
+    lib.pdhg_dual_push.argtypes = [C.c_void_p, C.c_uint64, P(DualPushResult)]
     lib.pdhg_kkt.argtypes = [C.c_void_p, dp, dp, P(KKTReport)]
     lib.pdhg_get_solution.argtypes = [C.c_void_p, dp, dp, dp]
     lib.pdhg_get_solve_solution.argtypes = [C.c_void_p, dp, dp, dp]
@@ -188,7 +198,8 @@ def load(path: Optional[Path] = None):
     lib.pdhg_last_error.restype = C.c_char_p
     lib.pdhg_struct_size.restype = C.c_int32
     lib.pdhg_struct_size.argtypes = [C.c_int32]
-    for fn in ("pdhg_create", "pdhg_solve", "pdhg_iterate", "pdhg_corner_push", "pdhg_kkt", "pdhg_get_solution",
+    for fn in ("pdhg_create", "pdhg_solve", "pdhg_iterate", "pdhg_corner_push", "pdhg_dual_push", "pdhg_kkt",
+               "pdhg_get_solution",
                "pdhg_get_iterate", "pdhg_get_scaling", "pdhg_get_timing", "pdhg_copy_probe", "pdhg_batch_create",
                "pdhg_batch_solve", "pdhg_batch_corner_push", "pdhg_batch_get_solution", "pdhg_batch_get_report",
                "pdhg_mlp_create", "pdhg_mlp_set_params", "pdhg_mlp_get_params", "pdhg_mlp_forward",
@@ -198,7 +209,7 @@ def load(path: Optional[Path] = None):
                "pdhg_batch_get_solve_solution"):
         getattr(lib, fn).restype = C.c_int
     sizes = [C.sizeof(Params), C.sizeof(Result), C.sizeof(KKTReport), C.sizeof(PushResult), C.sizeof(Timing),
-             C.sizeof(LpDesc), C.sizeof(BatchReport)]
+             C.sizeof(LpDesc), C.sizeof(BatchReport), C.sizeof(DualPushResult)]
     for which, want in enumerate(sizes):
         got = lib.pdhg_struct_size(which)
         if got != want:
@@ -301,6 +312,12 @@ class Solver:
     def corner_push(self, seed: int) -> PushResult:
         r = PushResult()
         self._check(self.lib.pdhg_corner_push(self.h, C.c_uint64(seed), C.byref(r)))
+        return r
+
+    def dual_push(self, seed: int) -> DualPushResult:
+        """Dual corner push; afterwards get_solution() gives (x, yhat, zhat)."""
+        r = DualPushResult()
+        self._check(self.lib.pdhg_dual_push(self.h, C.c_uint64(seed), C.byref(r)))
         return r
 
     def kkt(self, x=None, y=None) -> KKTReport:

@@ -42,6 +42,7 @@ def test_struct_layouts_match_binding():
     assert lib.pdhg_struct_size(1) == ctypes.sizeof(pdhg.Result)
     assert lib.pdhg_struct_size(2) == ctypes.sizeof(pdhg.KKTReport)
     assert lib.pdhg_struct_size(3) == ctypes.sizeof(pdhg.PushResult)
+    assert lib.pdhg_struct_size(7) == ctypes.sizeof(pdhg.DualPushResult)
     assert lib.pdhg_struct_size(99) == -1
 
 

@@ -1,0 +1,151 @@
+"""The dual corner push on the GPU against the oracle.
+
+Same seeded LPs, same solve (equal iteration counts), then the dual push on
+both sides: the face it builds (integer decisions) must be identical, the stop
+the same up to one check, and the pushed y within rounding of the oracle's when
+the stops agree.  The pushed y is also checked on its own against what the
+method fixes: x unchanged, the dual test met, the dual superbasic estimate cut,
+and on a degenerate 2-column LP the closed-form vertex."""
+import numpy as np
+import pytest
+
+from oracle import OracleSolver
+from paper_2511_13894_amd import lpgen, pdhg
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_inf(a, b):
+    return float(np.abs(a - b).max() / max(1.0, np.abs(b).max())) if a.size else 0.0
+
+
+def _cases():
+    return [
+        ("degenerate_200x500", lambda: lpgen.planted(200, 500, seed=1, zero_frac=0.8, degen_frac=0.0)),
+        ("degenerate_ineq_ub_300x900",
+         lambda: lpgen.planted(300, 900, seed=2, zero_frac=0.85, degen_frac=0.0, ineq_frac=0.3, upper_frac=0.2)),
+        ("degenerate_ragged_400x1000",
+         lambda: lpgen.planted(400, 1000, seed=3, zero_frac=0.8, degen_frac=0.0, deg_range=(1, 9))),
+        ("transport_12x30", lambda: lpgen.transportation(12, 30, seed=3)),
+        ("free_mixed_40x120", lambda: lpgen.tiny(207, m=40, n=120, with_free=True)),
+        ("c0_s0", lambda: lpgen.config0(0)),
+    ]
+
+
+@pytest.mark.parametrize("name,make", _cases(), ids=[c[0] for c in _cases()])
+def test_dual_push_matches_oracle(name, make):
+    print(f"[dual push] {name}", flush=True)
+    lp = make()
+    eps = 1e-8
+    g = pdhg.Solver(lp, eps_rel=eps, max_iter=400000)
+    o = OracleSolver(lp, eps_rel=eps, max_iter=400000)
+    rg, ro = g.solve(), o.solve()
+    assert rg.status == ro.status == pdhg.PDHG_OPTIMAL
+    assert rg.iters == ro.iters
+    x0, y0, _ = g.get_solution()
+    pg, po = g.dual_push(5), o.dual_push(5)
+    print(f"[dual push] {name}: pinned z {pg.n_cols_free}, pinned y {pg.n_rows_fixed}; iterations {pg.iters} "
+          f"(oracle {po.iters}); est_dual {pg.before.est_dual} -> {pg.after.est_dual} "
+          f"(oracle {po.before.est_dual} -> {po.after.est_dual})", flush=True)
+    assert (pg.n_cols_free, pg.n_rows_fixed) == (po.n_cols_free, po.n_rows_fixed)
+    assert pg.status == po.status == pdhg.PDHG_PUSH_DONE
+    assert pg.before.d_zero == po.before.d_zero and pg.before.est_dual == po.before.est_dual
+    assert abs(pg.iters - po.iters) <= 64, (pg.iters, po.iters)
+    assert pg.rel_d_push <= eps
+    x1, y1, z1 = g.get_solution()
+    np.testing.assert_array_equal(x1, x0)  # the solve's x is the answer's x
+    xs, ys, _ = g.get_solve_solution()
+    np.testing.assert_array_equal(ys, y0)  # the solve's answer is kept beside the push's
+    k = g.kkt(x1, y1)
+    assert k.rel_d <= 2 * eps and k.rel_gap <= 100 * eps
+    assert pg.after.est_dual <= pg.before.est_dual
+    if pg.iters == po.iters:
+        xo1, yo1, zo1 = o.solution()
+        assert rel_inf(y1, yo1) <= 1e-7
+        assert pg.after.est_dual == po.after.est_dual
+
+
+def test_dual_push_reaches_the_closed_form_vertex():
+    """x* = (1/3, 1/3) with three active '>' rows: the dual face is
+    y = (t, t, 1 - 3t), t in [0, 1/3]; the converged push ends on one end point,
+    the same one as the oracle's, with the estimate of dual superbasics 1 -> 0."""
+    lp = lpgen.from_dense([[1, 2], [2, 1], [1, 1]], [1, 1, 2 / 3], [1, 1], [0, 0], [np.inf, np.inf], ">>>")
+    for seed in range(4):
+        g = pdhg.Solver(lp, eps_rel=1e-10, max_iter=400000, push_min_iters=20000)
+        o = OracleSolver(lp, eps_rel=1e-10, max_iter=400000, push_min_iters=20000)
+        g.solve()
+        o.solve()
+        pg, po = g.dual_push(seed), o.dual_push(seed)
+        y = g.get_solution()[1]
+        t = y[0]
+        assert min(abs(t), abs(t - 1 / 3)) <= 1e-6, y
+        np.testing.assert_allclose(y, [t, t, 1 - 3 * t], atol=1e-6)
+        np.testing.assert_allclose(y, o.solution()[1], atol=1e-6)
+        assert pg.before.est_dual == 1 and pg.after.est_dual == 0 and pg.status == po.status
+
+
+@pytest.mark.parametrize("lanes_a", [-3032, -32, 4])
+def test_dual_push_on_every_dual_half_kernel(lanes_a):
+    """The dropped rows ('N', y = 0) go through every dual-half kernel: sliced
+    ELLPACK, LDS tiles and lane groups give the oracle's push."""
+    lp = lpgen.planted(300, 900, seed=2, zero_frac=0.85, degen_frac=0.0, ineq_frac=0.3, upper_frac=0.2)
+    g = pdhg.Solver(lp, eps_rel=1e-8, max_iter=400000, lanes_a=lanes_a)
+    o = OracleSolver(lp, eps_rel=1e-8, max_iter=400000)
+    assert g.get_timing().lanes_a == lanes_a
+    g.solve()
+    o.solve()
+    pg, po = g.dual_push(9), o.dual_push(9)
+    print(f"[dual push] lanes_a {lanes_a}: {pg.iters} iterations (oracle {po.iters}), "
+          f"{pg.n_rows_fixed} rows dropped", flush=True)
+    assert pg.n_rows_fixed == po.n_rows_fixed > 0
+    assert pg.status == po.status and abs(pg.iters - po.iters) <= 64
+    if pg.iters == po.iters:
+        assert rel_inf(g.get_solution()[1], o.solution()[1]) <= 1e-7
+
+
+def test_dual_push_graph_replay_equals_eager_launches():
+    lp = lpgen.planted(200, 500, seed=1, zero_frac=0.8, degen_frac=0.0)
+    out = []
+    for graph in (0, 1):
+        g = pdhg.Solver(lp, eps_rel=1e-8, max_iter=400000, use_graph=graph)
+        g.solve()
+        p = g.dual_push(3)
+        out.append((p.iters, g.get_solution()[1]))
+    assert out[0][0] == out[1][0]
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
+def test_dual_push_fp32_mixed():
+    """FP32 matrix and x-vectors (y and the checks stay float64): the same face,
+    and the push cuts the dual superbasic estimate as the float64 one does."""
+    lp = lpgen.planted(400, 1000, seed=3, zero_frac=0.8, degen_frac=0.0, deg_range=(1, 9))
+    res = {}
+    for prec in ("fp64", "fp32"):
+        g = pdhg.Solver(lp, precision=prec, eps_rel=1e-6, max_iter=400000)
+        assert g.solve().status == pdhg.PDHG_OPTIMAL
+        res[prec] = g.dual_push(4)
+    a, b = res["fp64"], res["fp32"]
+    print(f"[dual push] fp32: est_dual {b.before.est_dual} -> {b.after.est_dual}, {b.iters} iterations "
+          f"(fp64 {a.before.est_dual} -> {a.after.est_dual}, {a.iters})", flush=True)
+    assert b.status == pdhg.PDHG_PUSH_DONE
+    assert b.rel_d_push <= 1e-6
+    assert b.after.est_dual < b.before.est_dual
+    assert abs(b.n_cols_free - a.n_cols_free) <= 2
+
+
+def test_dual_push_state_rules():
+    lp = lpgen.config0(0)
+    g = pdhg.Solver(lp, eps_rel=1e-6)
+    with pytest.raises(pdhg.PdhgError):
+        g.dual_push(1)
+    g.solve()
+    g.dual_push(1)
+    with pytest.raises(pdhg.PdhgError):
+        g.dual_push(1)
+    with pytest.raises(pdhg.PdhgError):
+        g.corner_push(1)
+    g2 = pdhg.Solver(lp, eps_rel=1e-6)
+    g2.solve()
+    g2.corner_push(1)
+    with pytest.raises(pdhg.PdhgError):
+        g2.dual_push(1)

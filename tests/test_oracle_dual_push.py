@@ -102,7 +102,7 @@ def test_every_point_of_the_dual_push_face_is_dual_optimal(seed):
     assert np.all(np.isinf(lh[~at_lo])) and np.all(np.isinf(uh[~at_up]))
     np.testing.assert_array_equal(np.frombuffer(sense, dtype=np.uint8) == ord("N"),
                                   np.array([b == (0.0, 0.0) for b in yb]))
-    assert pr.n_rc_zero == int((~at_lo & ~at_up).sum())
+    assert pr.n_cols_free == int((~at_lo & ~at_up).sum())
     rng = np.random.default_rng(seed)
     for _ in range(6):
         y = face_argmax(lp, x, rng.standard_normal(lp.m))
@@ -165,7 +165,7 @@ def test_dual_push_removes_dual_superbasics_on_planted_degenerate_lps(eps, max_a
     np.testing.assert_array_equal(x1, x0)
     k = s.kkt(x1, y1)
     assert k.rel_d <= 2 * eps and k.rel_gap <= 10 * eps
-    assert pr.n_rc_zero == 100 and pr.n_dual_zero == 0
+    assert pr.n_cols_free == 100 and pr.n_rows_fixed == 0
     assert pr.before.est_dual >= 80
     assert pr.after.est_dual < pr.before.est_dual / 2
     if max_after is not None:
