@@ -258,10 +258,12 @@ int pdhg_corner_push(pdhg_solver *s, uint64_t seed, pdhg_push_result *r);
  * model's dual residual over (1 + ||c||) is back at eps_rel (after at least
  * push_min_iters iterations; checks at push_min_iters + k K).  Afterwards
  * pdhg_get_solution gives (x, yhat, zhat), zhat the reduced costs of yhat on
- * the original model.  One push per solve: STATE before a solve or after a
- * push of either kind.  Single LP only; the push runs on the full model
- * (push_compact applies to pdhg_corner_push).  Errors: INVALID_ARG, STATE,
- * HIP. */
+ * the original model.  Runs once per solve, right after it or after
+ * pdhg_corner_push (the primal phase first, as in crossover): then x is the
+ * pushed xhat, ybar is still the solve's y, and the answer is (xhat, yhat,
+ * zhat).  pdhg_corner_push is refused after it.  Single LP only; the push
+ * runs on the full model (push_compact applies to pdhg_corner_push).
+ * Errors: INVALID_ARG, STATE (no solve yet, or a second dual push), HIP. */
 int pdhg_dual_push(pdhg_solver *s, uint64_t seed, pdhg_dual_push_result *r);
 
 /* KKT report of (x, y) on the original model, in float64.  x (n) and y (m)
@@ -271,7 +273,8 @@ int pdhg_kkt(pdhg_solver *s, const double *x, const double *y, pdhg_kkt_report *
 /* Current solution, unscaled: after a solve the last checked candidate
  * (x, y) and z = reduced costs; after a push (xhat, y, z) with the solve's y
  * and z (Algorithm 1 returns them unchanged); after a dual push (x, yhat,
- * zhat) with the solve's x.  Any pointer may be NULL. */
+ * zhat), x the solve's or, after both pushes, the corner push's xhat.  Any
+ * pointer may be NULL. */
 int pdhg_get_solution(pdhg_solver *s, double *x, double *y, double *z);
 
 /* The solve's own answer (x, y, z), unscaled, also after a push: the point a

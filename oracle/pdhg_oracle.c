@@ -74,7 +74,9 @@
  *   as soon as the dual residual of the push model, relative to 1 + ||c||,
  *   is back at the original tolerance, after at least push_min_iters
  *   iterations.  Returns (x, yhat, zhat): the solve's x, the pushed y (ybar
- *   on the dropped rows) and its reduced costs on the original model.
+ *   on the dropped rows) and its reduced costs on the original model.  Run
+ *   after the corner push (the primal phase first, as in crossover), x is the
+ *   pushed xhat and ybar still the solve's y.
  */
 #include <math.h>
 #include <stdint.h>
@@ -185,7 +187,7 @@ typedef struct {
     double kkt_anchor_p2, kkt_anchor_d2, kkt_anchor_gap2; /* at the anchor */
     double kkt_prev;
     int solved;   /* a solve has produced a checked candidate */
-    int in_push;  /* 0 solve, 1 corner push, 2 dual corner push */
+    int in_push;  /* bits: 1 corner push done, 2 dual corner push done (0: solve) */
     /* solution of the original solve, unscaled, kept for the push */
     double *xs_hat, *ys_hat; /* scaled candidate accepted by the solve */
     double *xsol, *ysol, *zsol;
@@ -810,7 +812,7 @@ static int run_phase(or_solver *s, int64_t iters, double *out_relp)
                 if (out_relp) *out_relp = k.rel_p;
                 break;
             }
-        } else if (s->in_push == 2) {
+        } else if (s->in_push & 2) {
             /* dual residual of the dual push model: its cones (0 or infinite,
                the same scaled and unscaled) decide what the bounds absorb */
             kkt_unscaled(s, s->cpush, s->lh, s->uh, s->sense, x, y, ax, aty, NULL, &k);
@@ -951,17 +953,20 @@ int or_corner_push(or_solver *s, uint64_t seed, or_push_result *r)
     return st;
 }
 
-/* Dual corner push (reading in the file header); one push per solve, like
- * or_corner_push. */
+/* Dual corner push (reading in the file header).  Runs once, after the solve
+ * or after the corner push; in the second case its face is that of the
+ * pushed xhat, and (xhat, yhat, zhat) is returned. */
 int or_dual_push(or_solver *s, uint64_t seed, or_dual_push_result *r)
 {
-    if (!s || !r || !s->solved || s->in_push) return OR_ERR_STATE;
+    if (!s || !r || !s->solved || (s->in_push & 2)) return OR_ERR_STATE;
     int m = s->m, n = s->n;
     double *ax = dalloc(m);
+    /* x: the solve's, or the corner push's xhat when that push came first */
+    const double *xk = (s->in_push & 1) ? s->xpush : s->xsol;
     memset(r, 0, sizeof(*r));
-    /* DP1: (x, y, z) of the solve on M; ax = A x */
-    reduced_costs(s, s->xsol, s->ysol, s->zsol, ax, &r->before);
-    corner_counts(s, s->xsol, ax, s->ysol, s->zsol, &r->before);
+    /* DP1: (x, y, z) on M, y and z the solve's; ax = A x */
+    reduced_costs(s, xk, s->ysol, s->zsol, ax, &r->before);
+    corner_counts(s, xk, ax, s->ysol, s->zsol, &r->before);
     double ea = s->p.eps_abs, sc = s->p.push_obj_scale;
     double *w0 = dalloc(n), *aw = dalloc(m), *yn = dalloc(m), *atyn = dalloc(n), *aty = dalloc(n);
     double *tv = dalloc(s->nnz);
@@ -981,8 +986,8 @@ int or_dual_push(or_solver *s, uint64_t seed, or_dual_push_result *r)
     /* DP2: the cone of each push column from where x sits against its bounds,
        the objective c~ = c - A_N'ybar_N - r, and the anchor point w0 */
     for (int j = 0; j < n; j++) {
-        int at_lo = !is_inf_lo(s->l[j]) && s->xsol[j] - s->l[j] <= ea;
-        int at_up = !is_inf_up(s->u[j]) && s->u[j] - s->xsol[j] <= ea;
+        int at_lo = !is_inf_lo(s->l[j]) && xk[j] - s->l[j] <= ea;
+        int at_up = !is_inf_up(s->u[j]) && s->u[j] - xk[j] <= ea;
         s->lh[j] = at_lo ? 0.0 : -INFINITY;
         s->uh[j] = at_up ? 0.0 : INFINITY;
         if (!at_lo && !at_up) r->n_cols_free++;
@@ -1017,7 +1022,7 @@ int or_dual_push(or_solver *s, uint64_t seed, or_dual_push_result *r)
     free(tv);
     /* DP5: new weight and restart state */
     s->omega = initial_omega(s->ch, n, s->bh, m);
-    s->in_push = 2;
+    s->in_push |= 2;
     reset_iteration(s, s->p.push_min_iters);
     memcpy(s->ypush, s->ysol, sizeof(double) * (size_t)m);
     /* DP6 */
@@ -1028,8 +1033,8 @@ int or_dual_push(or_solver *s, uint64_t seed, or_dual_push_result *r)
     r->restarts = s->restarts;
     r->rel_d_push = reld;
     /* DP7: (x, yhat, zhat), counts against the original model */
-    reduced_costs(s, s->xsol, s->ypush, s->zpush, ax, &r->after);
-    corner_counts(s, s->xsol, ax, s->ypush, s->zpush, &r->after);
+    reduced_costs(s, xk, s->ypush, s->zpush, ax, &r->after);
+    corner_counts(s, xk, ax, s->ypush, s->zpush, &r->after);
     free(ax);
     return st;
 }
@@ -1038,8 +1043,8 @@ int or_dual_push(or_solver *s, uint64_t seed, or_dual_push_result *r)
 int or_kkt_report(or_solver *s, const double *x, const double *y, or_kkt *k)
 {
     if (!s || !k) return OR_ERR_ARG;
-    const double *xx = x ? x : (s->in_push == 1 ? s->xpush : s->xsol);
-    const double *yy = y ? y : (s->in_push == 2 ? s->ypush : s->ysol);
+    const double *xx = x ? x : ((s->in_push & 1) ? s->xpush : s->xsol);
+    const double *yy = y ? y : ((s->in_push & 2) ? s->ypush : s->ysol);
     double *ax = dalloc(s->m), *z = dalloc(s->n);
     reduced_costs(s, xx, yy, z, ax, k);
     corner_counts(s, xx, ax, yy, z, k);
@@ -1058,8 +1063,8 @@ void or_get_iterate_scaled(const or_solver *s, double *x, double *y)
 void or_get_solution(const or_solver *s, double *x, double *y, double *z)
 {
     /* after a dual push: the solve's x, the pushed y and its reduced costs */
-    const int dual = s->in_push == 2;
-    if (x) memcpy(x, s->in_push == 1 ? s->xpush : s->xsol, sizeof(double) * (size_t)s->n);
+    const int dual = (s->in_push & 2) != 0;
+    if (x) memcpy(x, (s->in_push & 1) ? s->xpush : s->xsol, sizeof(double) * (size_t)s->n);
     if (y) memcpy(y, dual ? s->ypush : s->ysol, sizeof(double) * (size_t)s->m);
     if (z) memcpy(z, dual ? s->zpush : s->zsol, sizeof(double) * (size_t)s->n);
 }

@@ -76,7 +76,7 @@ void dalloc(T **p, size_t count)
 
 // The handle's current answer (unscaled, device): the solve's, the primal
 // push's (xhat, y, z) or the dual push's (x, yhat, zhat).
-const double *cur_x(const pdhg_solver *s) { return s->in_push && !s->dual_pushed ? s->xpush : s->xu; }
+const double *cur_x(const pdhg_solver *s) { return s->primal_pushed ? s->xpush : s->xu; }
 const double *cur_y(const pdhg_solver *s) { return s->dual_pushed ? s->ypush : s->yu; }
 const double *cur_z(const pdhg_solver *s) { return s->dual_pushed ? s->zpush : s->zsol; }
 
@@ -89,7 +89,7 @@ void free_all(pdhg_solver *s)
                     s->ax,   s->aty, s->xu, s->yu,   s->zsol,   s->xpush, s->partials, s->redout, s->st,
                     s->hx,   s->hz,  s->feat_raw, s->feat_b, s->logits, s->lfix, s->lcount, s->sell_idx,
                     s->sell_val, s->sell_soff, s->sell_len, s->sell_wi_start, s->sell_wi, s->sell_part,
-                    s->ypush, s->zpush};
+                    s->ypush, s->zpush, s->w0};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->st_host) (void)hipHostFree(s->st_host);
@@ -608,6 +608,7 @@ static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r
             r->rel_p_push = NAN;
             r->seconds = now_s() - t0;
             s->in_push = true; // the handle's one push (skipped); pdhg_get_solution gives the solve's x
+            s->primal_pushed = true;
             return PDHG_OK;
         }
         if (net) { // predictor on the solve's state, before the model changes
@@ -627,6 +628,7 @@ static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r
         HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         s->in_push = true;
+        s->primal_pushed = true;
         s->has_candidate = false;
         s->t_host = 0;
         s->next_check = s->p.push_min_iters;
@@ -669,14 +671,16 @@ int pdhg_corner_push_learned(pdhg_solver *s, pdhg_mlp *net, double theta, uint64
     return corner_push_common(s, seed, r, net, theta);
 }
 
-// The dual corner push: DP1 the solve's answer and its report (which leaves
-// A x in s->ax and A'y in s->aty), DP2-DP5 the dual face of x as a push model
+// The dual corner push: DP1 the solve's answer, x replaced by the corner
+// push's xhat when that push came first, and its report (which leaves A x in
+// s->ax and A'y in s->aty), DP2-DP5 the dual face of x as a push model
 // anchored at the solve's y, with the anchored random right-hand side, start
 // (0, y), DP6 PDHG to the dual test, DP7 (x, yhat, zhat).
 int pdhg_dual_push(pdhg_solver *s, uint64_t seed, pdhg_dual_push_result *r)
 {
     if (!s || !r) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
-    if (!s->solved || s->in_push) return fail(PDHG_ERR_STATE, "dual push needs a solve first (and runs once)");
+    if (!s->solved || s->dual_pushed)
+        return fail(PDHG_ERR_STATE, "dual push needs a solve first (and runs once)");
     std::memset(r, 0, sizeof(*r));
     const double t0 = now_s();
     try {
@@ -684,14 +688,18 @@ int pdhg_dual_push(pdhg_solver *s, uint64_t seed, pdhg_dual_push_result *r)
         const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
         if (!s->ypush) dalloc(&s->ypush, (size_t)(s->m > 0 ? s->m : 1));
         if (!s->zpush) dalloc(&s->zpush, (size_t)(s->n > 0 ? s->n : 1));
-        // DP1
-        HIPCHK(hipMemcpyAsync(s->xs, s->xp, vb * (size_t)s->n, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(s->ys, s->yp, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
-        HIPCHK(unscale(s, s->xs, s->ys, s->xu, s->yu));
-        HIPCHK(report(s, s->xu, s->yu, s->zsol, &r->before));
-        // DP2-DP5; w0 lives in xpush, ybar on the dropped rows in ypush and
-        // A_N'ybar_N in zpush until the push writes them
-        HIPCHK(dual_push_setup(s, seed, s->xpush, s->ypush, s->zpush, &r->n_cols_free, &r->n_rows_fixed));
+        // DP1 (after the corner push, xs, ys, xu, yu already hold the solve's answer)
+        if (!s->primal_pushed) {
+            HIPCHK(hipMemcpyAsync(s->xs, s->xp, vb * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(s->ys, s->yp, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
+            HIPCHK(unscale(s, s->xs, s->ys, s->xu, s->yu));
+        }
+        const double *xk = cur_x(s);
+        HIPCHK(report(s, xk, s->yu, s->zsol, &r->before));
+        // DP2-DP5; ybar on the dropped rows lives in ypush and A_N'ybar_N in
+        // zpush until the push writes them
+        if (!s->w0) dalloc(&s->w0, (size_t)(s->n > 0 ? s->n : 1));
+        HIPCHK(dual_push_setup(s, seed, xk, s->w0, s->ypush, s->zpush, &r->n_cols_free, &r->n_rows_fixed));
         HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         s->in_push = true;
@@ -708,7 +716,7 @@ int pdhg_dual_push(pdhg_solver *s, uint64_t seed, pdhg_dual_push_result *r)
         } else {
             HIPCHK(hipMemcpyAsync(s->ypush, s->yu, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
         }
-        HIPCHK(report(s, s->xu, s->ypush, s->zpush, &r->after));
+        HIPCHK(report(s, xk, s->ypush, s->zpush, &r->after));
         r->status = status;
         r->iters = s->t_host;
         r->restarts = s->st_host->restarts;

@@ -113,6 +113,7 @@ struct pdhg_solver {
     double *ax = nullptr, *aty = nullptr;
     double *xu = nullptr, *yu = nullptr, *zsol = nullptr, *xpush = nullptr;
     double *ypush = nullptr, *zpush = nullptr; // dual push result (allocated by the dual push)
+    double *w0 = nullptr;                      // dual push: the anchor point of its right-hand side
     double *partials = nullptr;
     double *redout = nullptr; // small reduction results
     int red_blocks_m = 1, red_blocks_n = 1;
@@ -127,7 +128,8 @@ struct pdhg_solver {
     int64_t power_steps = 0; // power-iteration steps taken at create
     int64_t next_check = 0;  // phase iteration count of the next check
     bool in_push = false;
-    bool dual_pushed = false; // the handle's push was the dual push
+    bool primal_pushed = false; // pdhg_corner_push has run (its x is in xpush)
+    bool dual_pushed = false;   // pdhg_dual_push has run (its y and z in ypush, zpush)
     // sliced ELLPACK copy of Ahat for the dual half (kernel code kSell)
     int *sell_idx = nullptr, *sell_len = nullptr, *sell_wi_start = nullptr;
     void *sell_val = nullptr;
@@ -259,8 +261,8 @@ hipError_t launch_start_vectors(pdhg_solver *s, bool fresh_start);
 hipError_t unscale(pdhg_solver *s, const void *xh, const void *yh, double *xo, double *yo);
 hipError_t report(pdhg_solver *s, const double *x, const double *y, double *z, pdhg_kkt_report *k);
 hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, double theta);
-hipError_t dual_push_setup(pdhg_solver *s, uint64_t seed, double *w0, double *yn, double *atyn, int64_t *n_cols_free,
-                           int64_t *n_rows_fixed);
+hipError_t dual_push_setup(pdhg_solver *s, uint64_t seed, const double *xk, double *w0, double *yn, double *atyn,
+                           int64_t *n_cols_free, int64_t *n_rows_fixed);
 hipError_t dual_push_finish(pdhg_solver *s);
 // push on the free columns only: build the compact model and put it in place,
 // or (end) put x and x+ back into the full vectors and restore the full model

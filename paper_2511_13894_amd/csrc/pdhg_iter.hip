@@ -1138,12 +1138,12 @@ __global__ __launch_bounds__(kBlock) void k_dpush_final(int m, const int8_t *__r
         if (sense[i] == 'N') ypush[i] = yu[i];
 }
 
-// Needs report() of the solve's (xu, yu) just before: s->ax holds A xu and
-// s->aty A'yu.  w0 (n) and yn (m) are float64 work buffers of the caller;
-// atyn (n) another.
+// Needs report() of (xk, yu) just before: s->ax holds A xk and s->aty A'yu.
+// xk is the solve's x or the corner push's xhat (unscaled).  w0 (n) and yn
+// (m) are float64 work buffers of the caller; atyn (n) another.
 template <typename V>
-static hipError_t dual_push_setup_impl(pdhg_solver *s, uint64_t seed, double *w0, double *yn, double *atyn,
-                                       int64_t *n_cols_free, int64_t *n_rows_fixed)
+static hipError_t dual_push_setup_impl(pdhg_solver *s, uint64_t seed, const double *xk, double *w0, double *yn,
+                                       double *atyn, int64_t *n_cols_free, int64_t *n_rows_fixed)
 {
     hipStream_t st = s->stream;
     const int gn = s->red_blocks_n, gm = s->red_blocks_m;
@@ -1151,7 +1151,7 @@ static hipError_t dual_push_setup_impl(pdhg_solver *s, uint64_t seed, double *w0
     hipLaunchKernelGGL(k_dpush_rows, dim3(gm), dim3(kBlock), 0, st, s->m, s->sense0, s->b, s->ax, s->yu, s->p.eps_abs,
                        s->sense, yn, pcnt + 2 * gn);
     spmv<double, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, s->atv, yn, atyn);
-    hipLaunchKernelGGL((k_dpush_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->xu, s->l, s->u, s->c, s->aty, atyn,
+    hipLaunchKernelGGL((k_dpush_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, xk, s->l, s->u, s->c, s->aty, atyn,
                        s->dc, s->p.eps_abs, seed, (V *)s->lh, (V *)s->uh, s->ch, (V *)s->x, w0, pcnt, gn);
     spmv<double, double, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, s->av, w0, (double *)s->bh);
     hipLaunchKernelGGL(k_dpush_rhs, dim3(gm), dim3(kBlock), 0, st, s->m, s->n, s->sense, s->dr, (const double *)s->ys,
@@ -1165,12 +1165,12 @@ static hipError_t dual_push_setup_impl(pdhg_solver *s, uint64_t seed, double *w0
     return phase_start<V>(s, false);
 }
 
-hipError_t dual_push_setup(pdhg_solver *s, uint64_t seed, double *w0, double *yn, double *atyn, int64_t *n_cols_free,
-                           int64_t *n_rows_fixed)
+hipError_t dual_push_setup(pdhg_solver *s, uint64_t seed, const double *xk, double *w0, double *yn, double *atyn,
+                           int64_t *n_cols_free, int64_t *n_rows_fixed)
 {
     s->model_original = false;
-    return s->fp32 ? dual_push_setup_impl<float>(s, seed, w0, yn, atyn, n_cols_free, n_rows_fixed)
-                   : dual_push_setup_impl<double>(s, seed, w0, yn, atyn, n_cols_free, n_rows_fixed);
+    return s->fp32 ? dual_push_setup_impl<float>(s, seed, xk, w0, yn, atyn, n_cols_free, n_rows_fixed)
+                   : dual_push_setup_impl<double>(s, seed, xk, w0, yn, atyn, n_cols_free, n_rows_fixed);
 }
 
 hipError_t dual_push_finish(pdhg_solver *s)

@@ -133,6 +133,43 @@ def test_dual_push_fp32_mixed():
     assert abs(b.n_cols_free - a.n_cols_free) <= 2
 
 
+@pytest.mark.parametrize("name,make", [
+    ("degenerate_ineq_ub_300x900",
+     lambda: lpgen.planted(300, 900, seed=2, zero_frac=0.85, degen_frac=0.0, ineq_frac=0.3, upper_frac=0.2)),
+    ("c0_s0", lambda: lpgen.config0(0)),
+    ("ineq_ub_300x1200", lambda: lpgen.config1(seed=3, m=300, n=1200)),
+], ids=["degenerate_ineq_ub_300x900", "c0_s0", "ineq_ub_300x1200"])
+def test_dual_push_after_corner_push_matches_oracle(name, make):
+    """Crossover's order: the corner push (on its free columns, the default),
+    then the dual push from its xhat; both phases follow the oracle."""
+    print(f"[dual push] after the corner push: {name}", flush=True)
+    lp = make()
+    g = pdhg.Solver(lp, eps_rel=1e-8, max_iter=400000)
+    o = OracleSolver(lp, eps_rel=1e-8, max_iter=400000)
+    g.solve()
+    o.solve()
+    pg, po = g.corner_push(3), o.corner_push(3)
+    assert pg.status == po.status == pdhg.PDHG_PUSH_DONE
+    xh = g.get_solution()[0]
+    dg, do = g.dual_push(5), o.dual_push(5)
+    print(f"[dual push] after the corner push: {name}: primal push {pg.iters} / {po.iters}, dual push {dg.iters} / "
+          f"{do.iters}; est_primal {pg.after.est_primal}, est_dual {dg.before.est_dual} -> {dg.after.est_dual}",
+          flush=True)
+    assert (dg.n_cols_free, dg.n_rows_fixed) == (do.n_cols_free, do.n_rows_fixed) or pg.iters != po.iters
+    assert dg.status == do.status == pdhg.PDHG_PUSH_DONE and dg.rel_d_push <= 1e-8
+    x2, y2, _ = g.get_solution()
+    np.testing.assert_array_equal(x2, xh)
+    xs, ys, _ = g.get_solve_solution()
+    k = g.kkt(x2, y2)
+    assert k.rel_p <= 1e-8 * 1.0000001 and k.rel_d <= 2e-8
+    if pg.iters == po.iters:
+        assert rel_inf(xh, o.solution()[0]) <= 1e-7
+        assert abs(dg.iters - do.iters) <= 64
+        if dg.iters == do.iters:
+            assert rel_inf(y2, o.solution()[1]) <= 1e-7
+            assert dg.after.est_dual == do.after.est_dual
+
+
 def test_dual_push_state_rules():
     lp = lpgen.config0(0)
     g = pdhg.Solver(lp, eps_rel=1e-6)
@@ -147,5 +184,6 @@ def test_dual_push_state_rules():
     g2 = pdhg.Solver(lp, eps_rel=1e-6)
     g2.solve()
     g2.corner_push(1)
+    g2.dual_push(1)
     with pytest.raises(pdhg.PdhgError):
         g2.dual_push(1)

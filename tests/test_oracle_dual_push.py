@@ -190,7 +190,33 @@ def test_dual_push_is_bounded_with_dependent_equality_rows():
     assert abs(dual_objective(lp, y1) - opt) <= 1e-6 * (1 + abs(opt))
 
 
-def test_dual_and_primal_push_are_one_per_solve():
+def test_dual_push_after_the_corner_push_works_from_xhat():
+    """Crossover's order, primal phase first: after Algorithm 1 the dual push
+    takes its face from the pushed xhat (its column cones are xhat's), keeps
+    xhat, and cuts the dual superbasic estimate of (xhat, y) to zero; the
+    pair stays primal and dual feasible with a vanishing gap."""
+    lp = lpgen.planted(300, 900, seed=2, zero_frac=0.85, degen_frac=0.0, ineq_frac=0.3, upper_frac=0.2)
+    s = OracleSolver(lp, eps_rel=1e-8, max_iter=400000)
+    s.solve()
+    pp = s.corner_push(3)
+    assert pp.status == 3
+    xh, y0, _ = s.solution()
+    pd = s.dual_push(5)
+    assert pd.status == 3
+    x2, y2, z2 = s.solution()
+    np.testing.assert_array_equal(x2, xh)
+    lh, uh, _, _ = s.model_scaled()
+    _, _, at_lo, at_up = _face_bounds(lp, xh, 1e-6)
+    np.testing.assert_array_equal(lh == 0.0, at_lo)
+    np.testing.assert_array_equal(uh == 0.0, at_up)
+    assert pd.before.est_dual > 50 and pd.after.est_dual == 0
+    k = s.kkt(x2, y2)
+    assert k.rel_p <= 1e-8 and k.rel_d <= 2e-8 and k.rel_gap <= 1e-6
+
+
+def test_push_order_rules():
+    """One dual push per solve, after the solve or after the corner push; no
+    corner push after a dual push."""
     lp = lpgen.config0(0)
     s = OracleSolver(lp, eps_rel=1e-6)
     with pytest.raises(RuntimeError):
@@ -204,5 +230,6 @@ def test_dual_and_primal_push_are_one_per_solve():
     s2 = OracleSolver(lp, eps_rel=1e-6)
     s2.solve()
     s2.corner_push(1)
+    s2.dual_push(1)
     with pytest.raises(RuntimeError):
         s2.dual_push(1)
