@@ -111,6 +111,48 @@ def test_c1_setup_iterates_solve_and_push(c1):
             (gp["p_off_after"], gp["candidates_after"], gp["est_primal_after"])
 
 
+def test_c5_solve_and_dual_push_against_the_oracle_full_run():
+    """The dual push workload (100k x 400k, primal-degenerate optimum): the
+    GPU's solve and dual push against the oracle's own full run
+    (tests/golden/make_c5_oracle.py), the face's decisions recounted from the
+    GPU's solve answer, and the pushed pair evaluated by the oracle's code."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c5_oracle.json")))
+    print("[full] c5 100k x 400k: generate + oracle setup", flush=True)
+    lp = lpgen.config5()
+    o = OracleSolver(lp)
+    g = pdhg.Solver(lp, timing=1)
+    r = g.solve()
+    x, y, _ = g.get_solution()
+    gs, gd = gold["solve"], gold["dual_push"]
+    print(f"[full] c5 solve: {pdhg.STATUS[r.status]} {r.iters} iterations (oracle {gs['iters']})", flush=True)
+    assert r.status == pdhg.PDHG_OPTIMAL and r.iters == gs["iters"] and r.restarts == gs["restarts"]
+    assert abs(r.pobj - gs["pobj"]) <= 1e-9 * abs(gs["pobj"])
+    p = g.dual_push(1)
+    # the face's decisions, recounted from the solve's answer
+    a = sp.csr_matrix((lp.val, lp.col, lp.row_ptr), shape=(lp.m, lp.n))
+    ax = a @ x
+    sense = np.asarray(lp.sense)
+    slack = np.where(sense == ord("<"), lp.b - ax, np.where(sense == ord(">"), ax - lp.b, 0.0))
+    at_lo = np.isfinite(lp.l) & (x - lp.l <= 1e-6)
+    at_up = np.isfinite(lp.u) & (lp.u - x <= 1e-6)
+    assert p.n_cols_free == int(np.sum(~at_lo & ~at_up))
+    assert p.n_rows_fixed == int(np.sum((sense != ord("=")) & (slack > 1e-6)))
+    assert (p.n_cols_free, p.n_rows_fixed) == (gd["n_cols_free"], gd["n_rows_fixed"])
+    x2, y2, _ = g.get_solution()
+    np.testing.assert_array_equal(x2, x)
+    ka = o.kkt(x2, y2)
+    print(f"[full] c5 dual push: {p.iters} iterations (oracle {gd['iters']}); est_dual {p.before.est_dual} -> "
+          f"{p.after.est_dual} (oracle's evaluation {ka.est_dual}; oracle's run {gd['est_dual_before']} -> "
+          f"{gd['est_dual_after']})", flush=True)
+    assert p.status == gd["status"] == pdhg.PDHG_PUSH_DONE and p.rel_d_push <= 1e-6
+    assert (p.after.d_zero, p.after.est_dual) == (ka.d_zero, ka.est_dual)
+    assert ka.rel_d <= 2e-6
+    assert p.before.est_dual == gd["est_dual_before"]
+    assert abs(p.iters - gd["iters"]) <= 64
+    if p.iters == gd["iters"]:
+        assert p.after.est_dual == gd["est_dual_after"]
+
+
 def test_c2_setup_iterates_and_solve(c2):
     lp, o = c2
     _setup_and_first_iterates(lp, o, 2)
