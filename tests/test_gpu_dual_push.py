@@ -29,6 +29,10 @@ def _cases():
         ("transport_12x30", lambda: lpgen.transportation(12, 30, seed=3)),
         ("free_mixed_40x120", lambda: lpgen.tiny(207, m=40, n=120, with_free=True)),
         ("c0_s0", lambda: lpgen.config0(0)),
+        # a fixed column (cone {0}), an empty column, an empty '<' row and a loose '>' row (both dropped)
+        ("edge_fixed_empty", lambda: lpgen.from_dense([[1, 1, 0, 1], [0, 0, 0, 0], [1, -1, 0, 2]], [3, 5, 1],
+                                                      [1, 2, 3, 0.5], [0, 0, 0, 1], [np.inf, np.inf, np.inf, 1],
+                                                      "=<>")),
     ]
 
 

@@ -214,6 +214,26 @@ def test_dual_push_after_the_corner_push_works_from_xhat():
     assert k.rel_p <= 1e-8 and k.rel_d <= 2e-8 and k.rel_gap <= 1e-6
 
 
+def test_dual_push_edge_cases_fixed_and_empty():
+    """A fixed column (l = u: both bounds, so z free and w in {0}), an empty
+    column (at its lower bound: w >= 0), an empty '<' row and a loose '>' row
+    (both dropped, y held at 0): the push keeps HiGHS's optimal objective."""
+    lp = lpgen.from_dense([[1, 1, 0, 1], [0, 0, 0, 0], [1, -1, 0, 2]], [3, 5, 1], [1, 2, 3, 0.5], [0, 0, 0, 1],
+                          [np.inf, np.inf, np.inf, 1], "=<>")
+    opt, _ = lp_ref.highs(lp)
+    s = OracleSolver(lp, eps_rel=1e-8, max_iter=400000)
+    s.solve()
+    pd = s.dual_push(3)
+    assert pd.status == 3 and pd.n_cols_free == 1 and pd.n_rows_fixed == 2
+    lh, uh, _, sense = s.model_scaled()
+    assert sense == b"=NN"
+    np.testing.assert_array_equal(lh, [-np.inf, 0.0, 0.0, 0.0])
+    np.testing.assert_array_equal(uh, [np.inf, np.inf, np.inf, 0.0])
+    x, y, z = s.solution()
+    assert y[1] == 0.0 and y[2] == 0.0
+    assert abs(dual_objective(lp, y) - opt) <= 1e-7 * (1 + abs(opt))
+
+
 def test_push_order_rules():
     """One dual push per solve, after the solve or after the corner push; no
     corner push after a dual push."""
