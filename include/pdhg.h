@@ -376,6 +376,15 @@ int pdhg_batch_solve(pdhg_batch *b, pdhg_result *results);
  * status and 0 push iterations).  Requires pdhg_batch_solve (STATE). */
 int pdhg_batch_corner_push(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *results);
 
+/* pdhg_dual_push for every LP whose solve is optimal, seeds[i] selecting LP
+ * i's draws (U_k at LP i's own column and row numbering), in lockstep cycles
+ * over the block-diagonal model (results[count]; an LP without a push reports
+ * its solve status and 0 iterations).  After pdhg_batch_corner_push each LP's
+ * face is that of its pushed xhat; pdhg_batch_corner_push is refused after
+ * it.  Afterwards pdhg_batch_get_solution gives (x, yhat, zhat).  Errors:
+ * INVALID_ARG, STATE (no batch solve, or a second dual push), HIP. */
+int pdhg_batch_dual_push(pdhg_batch *b, const uint64_t *seeds, pdhg_dual_push_result *results);
+
 /* Solution of LP i, unscaled (x: n_i, y: m_i, z: n_i; any may be NULL);
  * after the push x is the pushed x. */
 int pdhg_batch_get_solution(pdhg_batch *b, int32_t i, double *x, double *y, double *z);

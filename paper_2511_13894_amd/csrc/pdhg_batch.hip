@@ -144,6 +144,7 @@ __global__ __launch_bounds__(kBlock) void kb_check_rows(const int4 *__restrict__
         const int8_t s = sense[i];
         if (s == '<') r = r < 0.0 ? r : 0.0;
         else if (s == '>') r = r > 0.0 ? r : 0.0;
+        else if (s == 'N') r = 0.0; // dropped by the dual push
         const double ru = r / dr[i];
         const double yi = yc[i];
         const double dy = yi - ya[i];
@@ -841,6 +842,162 @@ hipError_t batch_keep_unpushed(pdhg_batch *b)
 {
     hipLaunchKernelGGL(kb_keep_unpushed, dim3(b->n_rn), dim3(kBlock), 0, b->s->stream, b->rn, b->sts, b->active,
                        b->s->xu, b->s->xpush);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------- dual push ---
+// The single-LP dual push of pdhg_iter.hip over every LP taking part, each
+// with its own seed and its own column and row numbering for the draws.  LPs
+// not taking part keep their model; their entries of the work vectors are 0.
+__global__ __launch_bounds__(kBlock) void kb_dpush_rows(const int4 *__restrict__ rm, const int *__restrict__ active,
+                                                       const int8_t *__restrict__ sense0, const double *__restrict__ bv,
+                                                       const double *__restrict__ ax, const double *__restrict__ yu,
+                                                       double eps_abs, int8_t *__restrict__ sense,
+                                                       double *__restrict__ yn, double *__restrict__ part)
+{
+    const int4 tl = rm[blockIdx.x];
+    double v[1] = {0.0}; // rows dropped, dual held at the solve's
+    if ((int)threadIdx.x < tl.z) {
+        const int i = tl.y + threadIdx.x;
+        if (active[tl.x]) {
+            const int8_t sn = sense0[i];
+            const double slack = sn == '<' ? bv[i] - ax[i] : (sn == '>' ? ax[i] - bv[i] : 0.0);
+            const bool drop = sn != '=' && slack > eps_abs;
+            sense[i] = drop ? (int8_t)'N' : sn;
+            yn[i] = drop ? yu[i] : 0.0;
+            v[0] = drop ? 1.0 : 0.0;
+        } else {
+            yn[i] = 0.0;
+        }
+    }
+    block_reduce<1>(v, 0u);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void kb_dpush_cols(const int4 *__restrict__ rn, const int *__restrict__ coff,
+                                                       const int *__restrict__ active, const double *__restrict__ xk,
+                                                       const double *__restrict__ l, const double *__restrict__ u,
+                                                       const double *__restrict__ c, const double *__restrict__ aty,
+                                                       const double *__restrict__ atyn, const double *__restrict__ dc,
+                                                       double eps_abs, const uint64_t *__restrict__ seeds,
+                                                       V *__restrict__ lh, V *__restrict__ uh, double *__restrict__ ch,
+                                                       V *__restrict__ x, double *__restrict__ w0,
+                                                       double *__restrict__ part, int ntile)
+{
+    const int4 tl = rn[blockIdx.x];
+    double v[1] = {0.0}; // columns off both bounds
+    if ((int)threadIdx.x < tl.z) {
+        const int j = tl.y + threadIdx.x;
+        if (active[tl.x]) {
+            const double xj = xk[j];
+            const bool at_lo = !is_inf_lo(l[j]) && xj - l[j] <= eps_abs;
+            const bool at_up = !is_inf_up(u[j]) && u[j] - xj <= eps_abs;
+            lh[j] = at_lo ? (V)0 : (V)-INFINITY;
+            uh[j] = at_up ? (V)0 : (V)INFINITY;
+            const double lam = c[j] - aty[j];
+            const double rj = (at_lo && at_up) ? 0.0 : at_lo ? fmin(lam, 0.0) : at_up ? fmax(lam, 0.0) : lam;
+            ch[j] = dc[j] * (c[j] - atyn[j] - rj);
+            const double uj = push_unit(seeds[tl.x], (int64_t)(j - coff[tl.x]));
+            w0[j] = (at_lo && at_up) ? 0.0 : (at_up ? -uj : uj);
+            x[j] = (V)0;
+            v[0] = (!at_lo && !at_up) ? 1.0 : 0.0;
+        } else {
+            w0[j] = 0.0;
+        }
+    }
+    block_reduce<1>(v, 0u);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v[0];
+        part[ntile + blockIdx.x] = 0.0;
+    }
+}
+
+// aw = A w0 (unscaled); an LP's first row is the first row of its first
+// reduction tile, its column count the difference of its column offsets.
+__global__ __launch_bounds__(kBlock) void kb_dpush_rhs(const int4 *__restrict__ rm, const int *__restrict__ rm_start,
+                                                      const int *__restrict__ coff, const int *__restrict__ active,
+                                                      const int8_t *__restrict__ sense, const double *__restrict__ dr,
+                                                      const double *__restrict__ ys, const double *__restrict__ aw,
+                                                      const uint64_t *__restrict__ seeds, double scale,
+                                                      double *__restrict__ bh, double *__restrict__ y)
+{
+    const int4 tl = rm[blockIdx.x];
+    if (!active[tl.x] || (int)threadIdx.x >= tl.z) return;
+    const int i = tl.y + threadIdx.x;
+    if (sense[i] == 'N') {
+        bh[i] = 0.0;
+        y[i] = 0.0;
+        return;
+    }
+    const int row0 = rm[rm_start[tl.x]].y;
+    const int64_t n_lp = coff[tl.x + 1] - coff[tl.x];
+    const double vi = push_unit(seeds[tl.x], n_lp + (i - row0));
+    const int8_t sn = sense[i];
+    const double g = sn == '>' ? aw[i] - vi : (sn == '<' ? aw[i] + vi : aw[i]);
+    bh[i] = dr[i] * (scale * g);
+    y[i] = ys[i];
+}
+
+// The pushed y: the push's candidate on the rows kept; the solve's y on the
+// dropped rows and on every row of an LP whose push made no check or did not run.
+__global__ __launch_bounds__(kBlock) void kb_dpush_final(const int4 *__restrict__ rm, const DevState *__restrict__ sts,
+                                                        const int *__restrict__ active, const int8_t *__restrict__ sense,
+                                                        const double *__restrict__ yu, double *__restrict__ ypush)
+{
+    const int4 tl = rm[blockIdx.x];
+    if ((int)threadIdx.x >= tl.z) return;
+    const int i = tl.y + threadIdx.x;
+    if (!active[tl.x] || sts[tl.x].checks == 0 || sense[i] == 'N') ypush[i] = yu[i];
+}
+
+// Needs batch_report() of (xk, yu) just before: s->ax holds A xk, s->aty A'yu.
+template <typename V>
+static hipError_t dual_push_setup_b(pdhg_batch *b, const double *xk, int64_t *cols_free, int64_t *rows_fixed)
+{
+    pdhg_solver *s = b->s;
+    hipStream_t st = s->stream;
+    double *pm = b->part, *pn = b->part + (size_t)(Q_COUNT + 1) * b->n_rm;
+    hipLaunchKernelGGL(kb_dpush_rows, dim3(b->n_rm), dim3(kBlock), 0, st, b->rm, b->active, s->sense0, s->b, s->ax,
+                       s->yu, s->p.eps_abs, s->sense, s->ypush, pm);
+    spmv<double, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, s->atv, s->ypush, s->zpush);
+    hipLaunchKernelGGL((kb_dpush_cols<V>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, b->d_coff, b->active, xk, s->l,
+                       s->u, s->c, s->aty, s->zpush, s->dc, s->p.eps_abs, b->seeds, (V *)s->lh, (V *)s->uh, s->ch,
+                       (V *)s->x, s->w0, pn, b->n_rn);
+    // A w0 into ax (read above, free now): the rows of LPs not taking part keep their bhat
+    spmv<double, double, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, s->av, s->w0, s->ax);
+    hipLaunchKernelGGL(kb_dpush_rhs, dim3(b->n_rm), dim3(kBlock), 0, st, b->rm, b->rm_start, b->d_coff, b->active,
+                       s->sense, s->dr, (const double *)s->ys, s->ax, b->seeds, s->p.push_obj_scale, (double *)s->bh,
+                       (double *)s->y);
+    hipLaunchKernelGGL(kb_push_final, dim3(b->count), dim3(kBlock), 0, st, pn, b->n_rn, pm, b->rm_start, b->rn_start,
+                       b->rep);
+    hipMemcpyAsync(b->rep_host, b->rep, sizeof(double) * R_COUNT * (size_t)b->count, hipMemcpyDeviceToHost, st);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < b->count; i++) {
+        cols_free[i] = (int64_t)b->rep_host[(size_t)i * R_COUNT + 0];
+        rows_fixed[i] = (int64_t)b->rep_host[(size_t)i * R_COUNT + 2];
+    }
+    return phase_begin_b<V>(b, false);
+}
+
+hipError_t batch_dual_push_setup(pdhg_batch *b, const uint64_t *seeds, const double *xk, int64_t *cols_free,
+                                 int64_t *rows_fixed)
+{
+    b->s->model_original = false;
+    hipError_t ec = batch_compact_tiles(b, true); // every LP taking part iterates again
+    if (ec != hipSuccess) return ec;
+    hipError_t e = hipMemcpyAsync(b->seeds, seeds, sizeof(uint64_t) * (size_t)b->count, hipMemcpyHostToDevice,
+                                  b->s->stream);
+    if (e != hipSuccess) return e;
+    return b->s->fp32 ? dual_push_setup_b<float>(b, xk, cols_free, rows_fixed)
+                      : dual_push_setup_b<double>(b, xk, cols_free, rows_fixed);
+}
+
+hipError_t batch_dual_push_finish(pdhg_batch *b)
+{
+    hipLaunchKernelGGL(kb_dpush_final, dim3(b->n_rm), dim3(kBlock), 0, b->s->stream, b->rm, b->sts, b->active,
+                       b->s->sense, b->s->yu, b->s->ypush);
     return hipGetLastError();
 }
 

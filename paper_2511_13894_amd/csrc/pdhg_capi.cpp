@@ -1245,7 +1245,8 @@ static int batch_push_common(pdhg_batch *b, const uint64_t *seeds, pdhg_push_res
                              double theta)
 {
     if (!b || !seeds || !results) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
-    if (!b->solved || b->pushed) return fail(PDHG_ERR_STATE, "corner push needs a batch solve first (and runs once)");
+    if (!b->solved || b->pushed || b->dual_pushed)
+        return fail(PDHG_ERR_STATE, "corner push needs a batch solve first (runs once, and not after a dual push)");
     const double t0 = now_s();
     try {
         pdhg_solver *s = b->s;
@@ -1335,10 +1336,77 @@ int pdhg_batch_corner_push_learned(pdhg_batch *b, pdhg_mlp *net, double theta, c
     return batch_push_common(b, seeds, results, net, theta);
 }
 
+// The dual corner push of every LP that reached the tolerance, each with its
+// own seed: the single-LP steps DP1-DP7 over the block-diagonal model, the
+// iterations in lockstep cycles.  After a batch corner push each LP's face is
+// that of its pushed xhat.
+int pdhg_batch_dual_push(pdhg_batch *b, const uint64_t *seeds, pdhg_dual_push_result *results)
+{
+    if (!b || !seeds || !results) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    if (!b->solved || b->dual_pushed)
+        return fail(PDHG_ERR_STATE, "dual push needs a batch solve first (and runs once)");
+    const double t0 = now_s();
+    try {
+        pdhg_solver *s = b->s;
+        hipStream_t st = s->stream;
+        const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
+        for (int i = 0; i < b->count; i++) std::memset(&results[i], 0, sizeof(pdhg_dual_push_result));
+        if (!s->ypush) dalloc(&s->ypush, (size_t)(s->m > 0 ? s->m : 1));
+        if (!s->zpush) dalloc(&s->zpush, (size_t)(s->n > 0 ? s->n : 1));
+        if (!s->w0) dalloc(&s->w0, (size_t)(s->n > 0 ? s->n : 1));
+        if (!b->pushed) { // DP1 (after the corner push the solve's answer is already in place)
+            HIPCHK(hipMemcpyAsync(s->xs, s->xp, vb * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(s->ys, s->yp, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
+            HIPCHK(unscale(s, s->xs, s->ys, s->xu, s->yu));
+        }
+        const double *xk = b->pushed ? s->xpush : s->xu;
+        std::vector<pdhg_kkt_report> before((size_t)b->count), after((size_t)b->count);
+        HIPCHK(batch_report(b, xk, s->yu, s->zsol, before.data()));
+        // the LPs that reached the tolerance take part (the solve's flags; an LP
+        // that did not keeps the solve's state and status)
+        const std::vector<int> act = b->active_host;
+        std::vector<int> solve_status((size_t)b->count);
+        for (int i = 0; i < b->count; i++) solve_status[i] = b->sts_host[i].status;
+        HIPCHK(hipMemcpy(b->active, act.data(), sizeof(int) * (size_t)b->count, hipMemcpyHostToDevice));
+        std::vector<int64_t> cols_free((size_t)b->count), rows_fixed((size_t)b->count);
+        HIPCHK(batch_dual_push_setup(b, seeds, xk, cols_free.data(), rows_fixed.data()));
+        b->t_host = 0;
+        b->next_check = s->p.push_min_iters;
+        const bool time_out = run_batch_phase(b, s->p.push_max_iter, 3, t0);
+        HIPCHK(unscale(s, nullptr, s->yp, nullptr, s->ypush));
+        HIPCHK(batch_dual_push_finish(b));
+        HIPCHK(batch_report(b, xk, s->ypush, s->zpush, after.data()));
+        const double secs = now_s() - t0;
+        for (int i = 0; i < b->count; i++) {
+            const DevState &d = b->sts_host[i];
+            pdhg_dual_push_result &r = results[i];
+            r.before = before[i];
+            r.after = after[i];
+            r.seconds = secs;
+            r.n_cols_free = cols_free[i];
+            r.n_rows_fixed = rows_fixed[i];
+            if (!act[i]) { // the solve did not reach the tolerance: no push
+                r.status = solve_status[i];
+                r.rel_d_push = NAN;
+                continue;
+            }
+            r.status = d.done ? d.status : (time_out ? PDHG_TIME_LIMIT : PDHG_ITER_LIMIT);
+            r.iters = d.done ? d.t : b->t_host;
+            r.restarts = d.restarts;
+            r.rel_d_push = d.checks > 0 ? d.rel_d : NAN;
+        }
+        b->dual_pushed = true;
+    } catch (const HipFailure &f) {
+        return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
+    }
+    return PDHG_OK;
+}
+
 int pdhg_batch_features(pdhg_batch *b, const uint64_t *seeds, float *out)
 {
     if (!b || !seeds) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
-    if (!b->solved || b->pushed) return fail(PDHG_ERR_STATE, "features describe a solved batch before its push");
+    if (!b->solved || b->pushed || b->dual_pushed)
+        return fail(PDHG_ERR_STATE, "features describe a solved batch before its push");
     try {
         pdhg_solver *s = b->s;
         batch_learned_buffers(b);
@@ -1363,9 +1431,11 @@ int pdhg_batch_get_solution(pdhg_batch *b, int32_t i, double *x, double *y, doub
         const size_t n0 = (size_t)b->coff[i], nn = (size_t)(b->coff[i + 1] - b->coff[i]);
         const size_t m0 = (size_t)b->roff[i], mm = (size_t)(b->roff[i + 1] - b->roff[i]);
         const double *cx = b->pushed ? s->xpush : s->xu;
+        const double *cy = b->dual_pushed ? s->ypush : s->yu;
+        const double *cz = b->dual_pushed ? s->zpush : s->zsol;
         if (x) HIPCHK(hipMemcpy(x, cx + n0, sizeof(double) * nn, hipMemcpyDeviceToHost));
-        if (y) HIPCHK(hipMemcpy(y, s->yu + m0, sizeof(double) * mm, hipMemcpyDeviceToHost));
-        if (z) HIPCHK(hipMemcpy(z, s->zsol + n0, sizeof(double) * nn, hipMemcpyDeviceToHost));
+        if (y) HIPCHK(hipMemcpy(y, cy + m0, sizeof(double) * mm, hipMemcpyDeviceToHost));
+        if (z) HIPCHK(hipMemcpy(z, cz + n0, sizeof(double) * nn, hipMemcpyDeviceToHost));
     } catch (const HipFailure &f) {
         return fail(PDHG_ERR_HIP, std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.err));
     }

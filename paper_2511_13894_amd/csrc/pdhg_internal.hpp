@@ -214,6 +214,7 @@ struct pdhg_batch {
     int graph_len = 0, graph_mode = -1;
     int64_t t_host = 0, next_check = 0;
     bool solved = false, pushed = false;
+    bool dual_pushed = false; // pdhg_batch_dual_push has run (y, z in the solver's ypush, zpush)
     double solve_seconds = 0.0, push_seconds = 0.0;
     double timed_bytes_primal = 0.0, timed_bytes_dual = 0.0; // algorithmic bytes of the timed launches
     int64_t solve_iters_max = 0, push_iters_max = 0;
@@ -287,6 +288,9 @@ hipError_t batch_iterations(pdhg_batch *b, int count, bool check_at_end, int mod
 hipError_t batch_capture_cycle(pdhg_batch *b, int len, int mode);
 hipError_t batch_report(pdhg_batch *b, const double *x, const double *y, double *z, pdhg_kkt_report *out);
 hipError_t batch_push_setup(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *out, double theta);
+hipError_t batch_dual_push_setup(pdhg_batch *b, const uint64_t *seeds, const double *xk, int64_t *cols_free,
+                                 int64_t *rows_fixed);
+hipError_t batch_dual_push_finish(pdhg_batch *b);
 hipError_t batch_keep_unpushed(pdhg_batch *b);
 
 // learned push (pdhg_learned.hip)

@@ -134,7 +134,7 @@ EXPORTS = ["pdhg_default_params", "pdhg_create", "pdhg_solve", "pdhg_iterate", "
            "pdhg_batch_features", "pdhg_batch_corner_push_learned",
            "pdhg_corner_push_learned", "pdhg_get_solution_device", "pdhg_set_start", "pdhg_state_size",
            "pdhg_get_state", "pdhg_set_state", "pdhg_get_solve_solution", "pdhg_batch_get_solve_solution",
-           "pdhg_dual_push"]
+           "pdhg_dual_push", "pdhg_batch_dual_push"]
 
 _lib = None
 
@@ -158,6 +158,7 @@ def load(path: Optional[Path] = None):
     lib.pdhg_iterate.argtypes = [C.c_void_p, C.c_int64, P(Result)]
     lib.pdhg_corner_push.argtypes = [C.c_void_p, C.c_uint64, P(PushResult)]
     lib.pdhg_dual_push.argtypes = [C.c_void_p, C.c_uint64, P(DualPushResult)]
+    lib.pdhg_batch_dual_push.argtypes = [C.c_void_p, P(C.c_uint64), P(DualPushResult)]
     lib.pdhg_kkt.argtypes = [C.c_void_p, dp, dp, P(KKTReport)]
     lib.pdhg_get_solution.argtypes = [C.c_void_p, dp, dp, dp]
     lib.pdhg_get_solve_solution.argtypes = [C.c_void_p, dp, dp, dp]
@@ -198,7 +199,8 @@ def load(path: Optional[Path] = None):
     lib.pdhg_last_error.restype = C.c_char_p
     lib.pdhg_struct_size.restype = C.c_int32
     lib.pdhg_struct_size.argtypes = [C.c_int32]
-    for fn in ("pdhg_create", "pdhg_solve", "pdhg_iterate", "pdhg_corner_push", "pdhg_dual_push", "pdhg_kkt",
+    for fn in ("pdhg_create", "pdhg_solve", "pdhg_iterate", "pdhg_corner_push", "pdhg_dual_push",
+               "pdhg_batch_dual_push", "pdhg_kkt",
                "pdhg_get_solution",
                "pdhg_get_iterate", "pdhg_get_scaling", "pdhg_get_timing", "pdhg_copy_probe", "pdhg_batch_create",
                "pdhg_batch_solve", "pdhg_batch_corner_push", "pdhg_batch_get_solution", "pdhg_batch_get_report",
@@ -435,6 +437,13 @@ class Batch:
         sd = (C.c_uint64 * self.count)(*[int(v) for v in seeds])
         r = (PushResult * self.count)()
         self._check(self.lib.pdhg_batch_corner_push(self.h, sd, r))
+        return list(r)
+
+    def dual_push(self, seeds):
+        """Dual corner push of every LP; afterwards get_solution(i) gives (x, yhat, zhat)."""
+        sd = (C.c_uint64 * self.count)(*[int(v) for v in seeds])
+        r = (DualPushResult * self.count)()
+        self._check(self.lib.pdhg_batch_dual_push(self.h, sd, r))
         return list(r)
 
     def corner_push_learned(self, net, theta: float, seeds):

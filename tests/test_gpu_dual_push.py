@@ -191,3 +191,68 @@ def test_dual_push_state_rules():
     g2.dual_push(1)
     with pytest.raises(pdhg.PdhgError):
         g2.dual_push(1)
+
+
+def _batch_lps():
+    lps = [lpgen.planted(120 + 20 * i, 300 + 50 * i, seed=60 + i, zero_frac=0.8, degen_frac=0.0, ineq_frac=0.3)
+           for i in range(4)]
+    lps += [lpgen.config3_instance(i, base_seed=5000, m_range=(40, 300)) for i in range(3)]
+    lps.append(lpgen.transportation(6, 9, seed=4))
+    lps.append(lpgen.tiny(207, m=40, n=120, with_free=True))
+    return lps
+
+
+def test_batch_dual_push_matches_the_oracle_lp_by_lp():
+    """The batch dual push (every LP's own seed and numbering, lockstep cycles
+    over the block-diagonal model) against the oracle's dual push of each LP."""
+    lps = _batch_lps()
+    seeds = [21 + i for i in range(len(lps))]
+    b = pdhg.Batch(lps, eps_rel=1e-8)
+    b.solve()
+    res = b.dual_push(seeds)
+    for i, lp in enumerate(lps):
+        o = OracleSolver(lp, eps_rel=1e-8)
+        o.solve()
+        po = o.dual_push(seeds[i])
+        r = res[i]
+        print(f"[dual push] batch LP {i} ({lp.m}x{lp.n}): {r.iters} iterations (oracle {po.iters}), est_dual "
+              f"{r.before.est_dual} -> {r.after.est_dual} (oracle {po.before.est_dual} -> {po.after.est_dual})",
+              flush=True)
+        assert (r.n_cols_free, r.n_rows_fixed) == (po.n_cols_free, po.n_rows_fixed), i
+        assert r.status == po.status == pdhg.PDHG_PUSH_DONE, i
+        assert abs(r.iters - po.iters) <= 128, (i, r.iters, po.iters)
+        assert r.rel_d_push <= 1e-8
+        x, y, _ = b.get_solution(i)
+        xo, yo, _ = o.solution()
+        assert rel_inf(x, xo) <= 1e-7, i
+        if r.iters == po.iters:
+            assert rel_inf(y, yo) <= 1e-7, i
+            assert r.after.est_dual == po.after.est_dual, i
+
+
+def test_batch_dual_push_after_the_batch_corner_push():
+    lps = _batch_lps()[:5]
+    seeds = [31 + i for i in range(len(lps))]
+    b = pdhg.Batch(lps, eps_rel=1e-8)
+    b.solve()
+    pr = b.corner_push(seeds)
+    xh = [b.get_solution(i)[0] for i in range(len(lps))]
+    dr = b.dual_push(seeds)
+    with pytest.raises(pdhg.PdhgError):
+        b.dual_push(seeds)
+    for i, lp in enumerate(lps):
+        o = OracleSolver(lp, eps_rel=1e-8)
+        o.solve()
+        po = o.corner_push(seeds[i])
+        do = o.dual_push(seeds[i])
+        x, y, _ = b.get_solution(i)
+        np.testing.assert_array_equal(x, xh[i])
+        assert dr[i].status == do.status == pdhg.PDHG_PUSH_DONE, i
+        if pr[i].iters == po.iters:
+            assert (dr[i].n_cols_free, dr[i].n_rows_fixed) == (do.n_cols_free, do.n_rows_fixed), i
+            assert abs(dr[i].iters - do.iters) <= 128, i
+    b2 = pdhg.Batch(lps, eps_rel=1e-8)
+    b2.solve()
+    b2.dual_push(seeds)
+    with pytest.raises(pdhg.PdhgError):
+        b2.corner_push(seeds)

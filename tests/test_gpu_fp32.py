@@ -39,7 +39,7 @@ def test_fp32_mixed_error_against_fp64_oracle(name, make):
     print(f"[fp32] {name}: iters fp32 {rg.iters} / fp64 oracle {ro.iters}; float64 KKT of the fp32 answer "
           f"{rg.rel_p:.2e}/{rg.rel_d:.2e}/{rg.rel_gap:.2e}; objective error {obj_err:.2e}; "
           f"|x - x_oracle| {_rel(xg, xo):.2e}, |y - y_oracle| {_rel(yg, yo):.2e}", flush=True)
-    # the answer is judged on the float64 original model
+    # the answer is evaluated on the float64 original model
     assert max(rg.rel_p, rg.rel_d, rg.rel_gap) <= 20 * eps
     assert obj_err <= 2e-5
     pg = g.corner_push(5)
