@@ -90,7 +90,7 @@ def cpu_baseline(lp, iters, cfg):
 
 
 def bench_batch(args, pdhg, copy_gbs):
-    """The batched family: one step = batch create + solve + corner push of all 256 LPs."""
+    """The batched family: one step = batch create + solve + corner push (or dual corner push) of all 256 LPs."""
     from paper_2511_13894_amd import lpgen
 
     lps = [lpgen.config3_instance(i) for i in range(256)]
@@ -103,7 +103,7 @@ def bench_batch(args, pdhg, copy_gbs):
         b = pdhg.Batch(lps, precision=args.precision, timing=timing, use_graph=0 if args.no_graph else 1,
                        push_compact=args.push_compact)
         res = b.solve()
-        push = b.corner_push(seeds)
+        push = b.corner_push(seeds) if args.push == "primal" else b.dual_push(seeds)
         rep = b.report()
         b.destroy()
         return res, push, rep
@@ -129,14 +129,20 @@ def bench_batch(args, pdhg, copy_gbs):
         status = {}
         for r in res:
             status[pdhg.STATUS[r.status]] = status.get(pdhg.STATUS[r.status], 0) + 1
-        details.append({"step_s": te - ts, "solve_s": rep.solve_seconds, "push_s": rep.push_seconds,
-                        "solve_lp_iters": si, "push_lp_iters": pi, "solve_lockstep": rep.solve_lockstep_iters,
-                        "push_lockstep": rep.push_lockstep_iters, "solve_status": status,
-                        "off_bound_before": sum(p.before.p_off for p in push),
-                        "off_bound_after": sum(p.after.p_off for p in push),
-                        "est_primal_before": sum(p.before.est_primal for p in push),
-                        "est_primal_after": sum(p.after.est_primal for p in push),
-                        "kernels": [rep.lanes_at, rep.lanes_a]})
+        d = {"step_s": te - ts, "solve_s": rep.solve_seconds, "solve_lp_iters": si, "push_lp_iters": pi,
+             "solve_lockstep": rep.solve_lockstep_iters, "solve_status": status, "kernels": [rep.lanes_at, rep.lanes_a]}
+        if args.push == "primal":
+            d.update({"push_s": rep.push_seconds, "push_lockstep": rep.push_lockstep_iters,
+                      "off_bound_before": sum(p.before.p_off for p in push),
+                      "off_bound_after": sum(p.after.p_off for p in push),
+                      "est_primal_before": sum(p.before.est_primal for p in push),
+                      "est_primal_after": sum(p.after.est_primal for p in push)})
+        else:
+            d.update({"push_s": push[0].seconds if push else 0.0, "push_lockstep": max(p.iters for p in push),
+                      "est_dual_before": sum(p.before.est_dual for p in push),
+                      "est_dual_after": sum(p.after.est_dual for p in push),
+                      "push_status": sorted({pdhg.STATUS[p.status] for p in push})})
+        details.append(d)
         print(f"[bench] step {k}: {te - ts:.3f}s, {si} solve + {pi} push LP-iterations, status {status}",
               file=sys.stderr, flush=True)
     elapsed = time.perf_counter() - t_start
@@ -152,9 +158,11 @@ def bench_batch(args, pdhg, copy_gbs):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64norms", "data": "synthetic",
-        "config": {"workload": f"c3: {WORKLOADS['c3']}; step = batch create + solve to 1e-6 relative KKT + corner "
-                               "push of every LP", "lps": len(lps), "m": tot_m, "n": tot_n, "nnz": tot_nz,
-                   "precision": args.precision, "eps_rel": 1e-6, "push_on_free_columns": bool(args.push_compact)},
+        "config": {"workload": f"c3: {WORKLOADS['c3']}; step = batch create + solve to 1e-6 relative KKT + "
+                               f"{'corner push' if args.push == 'primal' else 'dual corner push'} of every LP",
+                   "lps": len(lps), "m": tot_m, "n": tot_n, "nnz": tot_nz, "precision": args.precision,
+                   "eps_rel": 1e-6, "push_on_free_columns": bool(args.push_compact) and args.push == "primal",
+                   "push": args.push},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
                      "launch_us": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": int(nbytes),
@@ -220,9 +228,6 @@ def main():
     copy_gbs = pdhg.copy_probe(1 << 30, 20)
     print(f"[bench] copy probe 1 GiB: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     if args.config == "c3":
-        if args.push == "dual":
-            print("the dual push is a single-LP entry point; c3 is a batch", file=sys.stderr)
-            sys.exit(2)
         return bench_batch(args, pdhg, copy_gbs)
 
     if args.iters_only:
