@@ -40,6 +40,10 @@ WORKLOADS = {
 }
 
 
+PUSH_WORDS = {"primal": "corner push", "dual": "dual corner push",
+              "both": "corner push + dual corner push from its pushed x"}
+
+
 def make_lp(cfg):
     from paper_2511_13894_amd import lpgen
 
@@ -207,8 +211,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--push-compact", type=int, default=1, choices=[0, 1],
                     help="1 (default): the push iterates on its free columns; 0: on the full push model")
-    ap.add_argument("--push", default="primal", choices=["primal", "dual"],
-                    help="primal (default): the corner push of Algorithm 1; dual: the dual corner push")
+    ap.add_argument("--push", default="primal", choices=["primal", "dual", "both"],
+                    help="primal (default): the corner push of Algorithm 1; dual: the dual corner push; both: "
+                         "the corner push, then the dual push from its pushed x (single LP only)")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every cycle eagerly instead of replaying captured hipGraphs (profiler runs)")
     args = ap.parse_args()
@@ -228,6 +233,9 @@ def main():
     copy_gbs = pdhg.copy_probe(1 << 30, 20)
     print(f"[bench] copy probe 1 GiB: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     if args.config == "c3":
+        if args.push == "both":
+            print("--push both is a single-LP option", file=sys.stderr)
+            sys.exit(2)
         return bench_batch(args, pdhg, copy_gbs)
 
     if args.iters_only:
@@ -242,13 +250,14 @@ def main():
         s = pdhg.Solver(lp, precision=args.precision, timing=timing, use_graph=0 if args.no_graph else 1,
                         push_compact=args.push_compact)
         r = s.solve()
-        p = s.corner_push(args.seed) if args.push == "primal" else s.dual_push(args.seed)
+        p = s.corner_push(args.seed) if args.push != "dual" else s.dual_push(args.seed)
+        d = s.dual_push(args.seed) if args.push == "both" else None
         t = s.get_timing() if timing else None
         s.destroy()
-        return r, p, t
+        return r, p, t, d
 
     for w in range(args.warmup):
-        r, p, _ = step(0)
+        r, p, _, _ = step(0)
         print(f"[bench] warmup {w}: solve {r.iters} it ({pdhg.STATUS[r.status]}), push {p.iters} it "
               f"({pdhg.STATUS[p.status]})", file=sys.stderr, flush=True)
     iters = 0
@@ -259,16 +268,16 @@ def main():
     t_start = time.perf_counter()
     for k in range(args.steps):
         ts = time.perf_counter()
-        r, p, tim = step(1)
+        r, p, tim, dp = step(1)
         te = time.perf_counter()
-        iters += r.iters + p.iters
+        iters += r.iters + p.iters + (dp.iters if dp is not None else 0)
         prim_ms += tim.primal_ms * tim.samples
         dual_ms += tim.dual_ms * tim.samples
         samples += tim.samples
         d = {"solve_iters": r.iters, "solve_status": pdhg.STATUS[r.status], "push_iters": p.iters,
              "push_status": pdhg.STATUS[p.status], "step_s": te - ts,
              "rel_kkt": [r.rel_p, r.rel_d, r.rel_gap], "pobj": r.pobj}
-        if args.push == "primal":
+        if args.push != "dual":
             d.update({"off_bound_before": p.before.p_off, "off_bound_after": p.after.p_off,
                       "candidates_before": p.before.candidates, "candidates_after": p.after.candidates,
                       "est_primal_before": p.before.est_primal, "est_primal_after": p.after.est_primal,
@@ -278,8 +287,15 @@ def main():
                       "est_dual_before": p.before.est_dual, "est_dual_after": p.after.est_dual,
                       "cols_free": p.n_cols_free, "rows_fixed": p.n_rows_fixed,
                       "rel_d_push": p.rel_d_push, "push_s": p.seconds})
+        if dp is not None:
+            d.update({"dual_push_iters": dp.iters, "dual_push_status": pdhg.STATUS[dp.status],
+                      "dual_push_s": dp.seconds, "est_dual_before": dp.before.est_dual,
+                      "est_dual_after": dp.after.est_dual, "zero_rc_before": dp.before.d_zero,
+                      "zero_rc_after": dp.after.d_zero, "cols_free": dp.n_cols_free, "rows_fixed": dp.n_rows_fixed,
+                      "final_rel_kkt": [dp.after.rel_p, dp.after.rel_d, dp.after.rel_gap]})
         details.append(d)
-        print(f"[bench] step {k}: {te - ts:.3f}s solve {r.iters} push {p.iters}", file=sys.stderr, flush=True)
+        print(f"[bench] step {k}: {te - ts:.3f}s solve {r.iters} push {p.iters}"
+              + (f" dual push {dp.iters}" if dp is not None else ""), file=sys.stderr, flush=True)
     elapsed = time.perf_counter() - t_start
     value = iters / elapsed
     prim_ms /= max(samples, 1)
@@ -309,10 +325,10 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64norms", "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}; step = create + solve to 1e-6 relative "
-                               f"KKT + {'corner push' if args.push == 'primal' else 'dual corner push'}",
+                               f"KKT + {PUSH_WORDS[args.push]}",
                    "m": lp.m, "n": lp.n, "nnz": lp.nnz,
                    "precision": args.precision, "eps_rel": 1e-6, "push_seed": args.seed,
-                   "push_on_free_columns": bool(args.push_compact) and args.push == "primal",
+                   "push_on_free_columns": bool(args.push_compact) and args.push != "dual",
                    "push": args.push},
         "roofline": roof,
         "detail": {"steps": details, "time_to_corner_s": round(elapsed / args.steps, 4),
