@@ -147,6 +147,31 @@ def test_converged_dual_push_matches_highs_on_the_face(seed):
     np.testing.assert_allclose(y1, want, atol=1e-5 * (1 + np.abs(want).max()))
 
 
+@pytest.mark.parametrize("name,make", [
+    ("free_columns_10x30", lambda: lpgen.tiny(209, m=10, n=30, with_free=True)),
+    ("upper_bounds_ineq_14x40",
+     lambda: lpgen.planted(14, 40, seed=77, zero_frac=0.75, degen_frac=0.0, ineq_frac=0.4, upper_frac=0.3)),
+    ("transport_4x5", lambda: lpgen.transportation(4, 5, seed=6)),
+], ids=["free_columns_10x30", "upper_bounds_ineq_14x40", "transport_4x5"])
+def test_converged_dual_push_reaches_highs_optimum_on_the_face(name, make):
+    """Driven to convergence, the push attains HiGHS's optimal value of the
+    anchored objective over the face, and its reduced costs A'y are HiGHS's.
+    A transportation LP's face contains a line (dependent equality rows), so
+    its maximiser is unique only up to that line: the value and A'y are."""
+    lp = make()
+    s = OracleSolver(lp, eps_rel=1e-10, max_iter=400000, push_min_iters=60000)
+    s.solve()
+    x0 = s.solution()[0]
+    pr = s.dual_push(11)
+    assert pr.status == 3
+    y1 = s.solution()[1]
+    g = anchored_rhs(lp, x0, 11)
+    want = face_argmax(lp, x0, g)
+    a = lp.dense()
+    assert abs(g @ y1 - g @ want) <= 1e-6 * (1 + abs(g @ want)), (g @ y1, g @ want)
+    np.testing.assert_allclose(a.T @ y1, a.T @ want, atol=1e-5 * (1 + np.abs(a.T @ want).max()))
+
+
 @pytest.mark.parametrize("eps,max_after", [(1e-8, 0), (1e-6, None)])
 def test_dual_push_removes_dual_superbasics_on_planted_degenerate_lps(eps, max_after):
     """Planted optimum with 100 of 500 columns off their bounds and m = 200 rows:
