@@ -256,3 +256,35 @@ def test_batch_dual_push_after_the_batch_corner_push():
     b2.dual_push(seeds)
     with pytest.raises(pdhg.PdhgError):
         b2.corner_push(seeds)
+
+
+def _sweep():
+    cases = [(f"tiny_{3 + 4 * k}x{8 + 10 * k}", lambda k=k: lpgen.tiny(400 + k, m=3 + 4 * k, n=8 + 10 * k,
+                                                                        with_free=(k % 2 == 1)))
+             for k in range(10)]
+    cases += [(f"planted_ragged_{50 + 30 * k}x{150 + 60 * k}",
+               lambda k=k: lpgen.planted(50 + 30 * k, 150 + 60 * k, seed=90 + k, zero_frac=0.7 + 0.05 * k,
+                                         degen_frac=0.1 * (k % 2), ineq_frac=0.3, upper_frac=0.2, deg_range=(1, 7)))
+              for k in range(3)]
+    return cases
+
+
+@pytest.mark.parametrize("k,name,make", [(k, c[0], c[1]) for k, c in enumerate(_sweep())],
+                         ids=[c[0] for c in _sweep()])
+def test_dual_push_sweep_of_small_lps(k, name, make):
+    """Random senses, bounds, free columns and ragged degrees: the same face,
+    status and stop as the oracle, and the same pushed y when the stops agree."""
+    lp = make()
+    g = pdhg.Solver(lp, eps_rel=1e-8, max_iter=400000)
+    o = OracleSolver(lp, eps_rel=1e-8, max_iter=400000)
+    rg, ro = g.solve(), o.solve()
+    assert rg.status == ro.status == pdhg.PDHG_OPTIMAL and rg.iters == ro.iters
+    pg, po = g.dual_push(3 + k), o.dual_push(3 + k)
+    print(f"[dual push] sweep {name}: {pg.iters} / {po.iters} iterations, est_dual {pg.before.est_dual} -> "
+          f"{pg.after.est_dual}", flush=True)
+    assert (pg.n_cols_free, pg.n_rows_fixed) == (po.n_cols_free, po.n_rows_fixed)
+    assert pg.status == po.status == pdhg.PDHG_PUSH_DONE
+    assert abs(pg.iters - po.iters) <= 64
+    if pg.iters == po.iters:
+        assert rel_inf(g.get_solution()[1], o.solution()[1]) <= 1e-7
+        assert pg.after.est_dual == po.after.est_dual
