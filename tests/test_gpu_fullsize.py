@@ -109,6 +109,23 @@ def test_c1_setup_iterates_solve_and_push(c1):
     if p.iters == gp["iters"]:
         assert (p.after.p_off, p.after.candidates, p.after.est_primal) == \
             (gp["p_off_after"], gp["candidates_after"], gp["est_primal_after"])
+    # crossover's order: the dual push from the pushed x, against the oracle's continuation of its run
+    d = g.dual_push(1)
+    gd = gold["dual_push_after_push"]
+    x3, y3, _ = g.get_solution()
+    np.testing.assert_array_equal(x3, xp)
+    kd = o.kkt(x3, y3)
+    print(f"[full] c1 dual push after the push: {d.iters} iterations (oracle {gd['iters']}); est_dual "
+          f"{d.before.est_dual} -> {d.after.est_dual} (oracle's run {gd['est_dual_before']} -> {gd['est_dual_after']})",
+          flush=True)
+    assert d.status == gd["status"] == pdhg.PDHG_PUSH_DONE and d.rel_d_push <= 1e-6
+    assert (d.after.d_zero, d.after.est_dual) == (kd.d_zero, kd.est_dual)
+    if p.iters == gp["iters"]:
+        assert (d.n_cols_free, d.n_rows_fixed) == (gd["n_cols_free"], gd["n_rows_fixed"])
+        assert (d.before.d_zero, d.before.est_dual) == (gd["d_zero_before"], gd["est_dual_before"])
+        assert abs(d.iters - gd["iters"]) <= 64
+        if d.iters == gd["iters"]:
+            assert (d.after.d_zero, d.after.est_dual) == (gd["d_zero_after"], gd["est_dual_after"])
 
 
 def test_c5_solve_and_dual_push_against_the_oracle_full_run():
