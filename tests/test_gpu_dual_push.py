@@ -288,3 +288,28 @@ def test_dual_push_sweep_of_small_lps(k, name, make):
     if pg.iters == po.iters:
         assert rel_inf(g.get_solution()[1], o.solution()[1]) <= 1e-7
         assert pg.after.est_dual == po.after.est_dual
+
+
+def test_dual_push_stopped_before_its_first_check_keeps_the_solve_y():
+    """push_max_iter below push_min_iters: no check runs, the status is the
+    iteration limit and the answer's y is the solve's, on one LP and on every
+    LP of a batch; the oracle does the same."""
+    lp = lpgen.planted(200, 500, seed=1, zero_frac=0.8, degen_frac=0.0)
+    g = pdhg.Solver(lp, eps_rel=1e-8, max_iter=400000, push_max_iter=50)
+    o = OracleSolver(lp, eps_rel=1e-8, max_iter=400000, push_max_iter=50)
+    g.solve()
+    o.solve()
+    y0 = g.get_solution()[1]
+    pg, po = g.dual_push(5), o.dual_push(5)
+    assert pg.status == po.status == pdhg.PDHG_ITER_LIMIT and pg.iters == po.iters == 50
+    assert np.isnan(pg.rel_d_push)
+    np.testing.assert_array_equal(g.get_solution()[1], y0)
+    assert rel_inf(o.solution()[1], y0) <= 1e-8
+    lps = _batch_lps()[:3]
+    b = pdhg.Batch(lps, eps_rel=1e-8, push_max_iter=50)
+    b.solve()
+    ys = [b.get_solution(i)[1] for i in range(len(lps))]
+    res = b.dual_push([1, 2, 3])
+    for i in range(len(lps)):
+        assert res[i].status == pdhg.PDHG_ITER_LIMIT and res[i].iters == 50, i
+        np.testing.assert_array_equal(b.get_solution(i)[1], ys[i])
