@@ -313,3 +313,27 @@ def test_dual_push_stopped_before_its_first_check_keeps_the_solve_y():
     for i in range(len(lps)):
         assert res[i].status == pdhg.PDHG_ITER_LIMIT and res[i].iters == 50, i
         np.testing.assert_array_equal(b.get_solution(i)[1], ys[i])
+
+
+def test_dual_push_after_a_learned_corner_push():
+    """The learned corner push (fixes from the predictor, undone at checks)
+    leaves the handle ready for the dual push: the face is that of its xhat,
+    xhat is kept, and the dual test is met at the stop."""
+    lp = lpgen.config0(3)
+    net = pdhg.Mlp(1)
+    s = pdhg.Solver(lp, record_history=1, eps_rel=1e-7)
+    assert s.solve().status == pdhg.PDHG_OPTIMAL
+    p = s.corner_push_learned(net, 1e-4, 5)
+    assert p.status == pdhg.PDHG_PUSH_DONE
+    xh = s.get_solution()[0]
+    d = s.dual_push(5)
+    print(f"[dual push] after the learned push: {d.iters} iterations, est_dual {d.before.est_dual} -> "
+          f"{d.after.est_dual}", flush=True)
+    assert d.status == pdhg.PDHG_PUSH_DONE and d.rel_d_push <= 1e-7
+    x2, y2, _ = s.get_solution()
+    np.testing.assert_array_equal(x2, xh)
+    at_lo = np.isfinite(lp.l) & (xh - lp.l <= 1e-6)
+    at_up = np.isfinite(lp.u) & (lp.u - xh <= 1e-6)
+    assert d.n_cols_free == int(np.sum(~at_lo & ~at_up))
+    k = s.kkt(x2, y2)
+    assert k.rel_d <= 2e-7
