@@ -261,8 +261,9 @@ int pdhg_corner_push(pdhg_solver *s, uint64_t seed, pdhg_push_result *r);
  * the original model.  Runs once per solve, right after it or after
  * pdhg_corner_push (the primal phase first, as in crossover): then x is the
  * pushed xhat, ybar is still the solve's y, and the answer is (xhat, yhat,
- * zhat).  pdhg_corner_push is refused after it.  Single LP only; the push
- * runs on the full model (push_compact applies to pdhg_corner_push).
+ * zhat).  pdhg_corner_push is refused after it.  pdhg_batch_dual_push is the
+ * batch form.  The push runs on the full model (push_compact applies to
+ * pdhg_corner_push).
  * Errors: INVALID_ARG, STATE (no solve yet, or a second dual push), HIP. */
 int pdhg_dual_push(pdhg_solver *s, uint64_t seed, pdhg_dual_push_result *r);
 
