@@ -58,9 +58,13 @@ def make_lp(cfg):
     return lpgen.config0(0)
 
 
-def kernel_source_hash():
+KERNEL_FILES = ("pdhg_iter.hip", "pdhg_device.hpp", "pdhg_kernels.hpp", "pdhg_internal.hpp")
+BATCH_KERNEL_FILES = KERNEL_FILES + ("pdhg_batch.hip",)  # the batch engine's kernels (kb_*) as well
+
+
+def kernel_source_hash(files=KERNEL_FILES):
     h = hashlib.sha256()
-    for f in ("pdhg_iter.hip", "pdhg_device.hpp", "pdhg_kernels.hpp", "pdhg_internal.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2511_13894_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -75,7 +79,8 @@ def traffic_from_profile(cfg, kernel):
     txt = open(path).read()
     m = re.search(r"kernel_source_hash:\s*(\w+)", txt)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not t or m.group(1) != kernel_source_hash():
+    files = BATCH_KERNEL_FILES if kernel.startswith("kb_") else KERNEL_FILES
+    if not m or not t or m.group(1) != kernel_source_hash(files):
         return None
     return float(t.group(1))
 
@@ -168,7 +173,8 @@ def bench_batch(args, pdhg, copy_gbs):
                    "eps_rel": 1e-6, "push_on_free_columns": bool(args.push_compact) and args.push == "primal",
                    "push": args.push},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile("c3", kname),
+                     "kernel": kname,
                      "launch_us": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": int(nbytes),
                      "other_kernel": {"name": other[0], "launch_us": round(other[1] * 1e3, 2),
                                       "algorithmic_bytes_per_launch": int(other[2])},
