@@ -227,6 +227,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note, "
               "not a built path", file=sys.stderr)
         sys.exit(2)
+    if args.config == "c3" and args.push == "both":
+        print("--push both is a single-LP option; c3 is a batch", file=sys.stderr)
+        sys.exit(2)
 
     from paper_2511_13894_amd import pdhg
 
@@ -239,9 +242,6 @@ def main():
     copy_gbs = pdhg.copy_probe(1 << 30, 20)
     print(f"[bench] copy probe 1 GiB: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     if args.config == "c3":
-        if args.push == "both":
-            print("--push both is a single-LP option", file=sys.stderr)
-            sys.exit(2)
         return bench_batch(args, pdhg, copy_gbs)
 
     if args.iters_only:
