@@ -13,6 +13,10 @@ from .oracle import (  # noqa: F401
     build_oracle,
     num_threads,
     push_uniform,
+    restart_decision,
+    set_threads,
+    kkt_weighted,
+    weight_update,
     splitmix64,
     STATUS,
 )

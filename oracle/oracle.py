@@ -38,7 +38,7 @@ class OrParams(C.Structure):
         ("eta_safety", C.c_double), ("reflect_gamma", C.c_double), ("power_tol", C.c_double),
         ("push_min_iters", C.c_int32), ("pad_", C.c_int32),
         ("push_obj_scale", C.c_double), ("push_max_iter", C.c_int64),
-        ("push_gate", C.c_int32), ("pad2_", C.c_int32), ("push_gate_rows", C.c_double), ("push_gate_min", C.c_int64),
+        ("push_gate", C.c_int32), ("record_history", C.c_int32), ("push_gate_rows", C.c_double), ("push_gate_min", C.c_int64),
     ]
 
 
@@ -68,6 +68,7 @@ class OrPushResult(C.Structure):
         ("status", C.c_int32), ("pad_", C.c_int32), ("iters", C.c_int64), ("restarts", C.c_int64),
         ("n_fix_lower", C.c_int64), ("n_fix_upper", C.c_int64), ("n_rows_to_eq", C.c_int64),
         ("rel_p_push", C.c_double), ("before", OrKKT), ("after", OrKKT),
+        ("n_learned_fix", C.c_int64), ("n_learned_undo", C.c_int64),
     ]
 
 
@@ -98,6 +99,15 @@ def _load():
         lib.or_iterate.argtypes = [C.c_void_p, C.c_int64, P(OrResult)]
         lib.or_solve.argtypes = [C.c_void_p, P(OrResult)]
         lib.or_corner_push.argtypes = [C.c_void_p, C.c_uint64, P(OrPushResult)]
+        lib.or_corner_push_learned.argtypes = [C.c_void_p, P(C.c_float), C.c_double, C.c_uint64, P(OrPushResult)]
+        lib.or_features.argtypes = [C.c_void_p, C.c_uint64, dp]
+        lib.or_set_threads.argtypes = [C.c_int]
+        lib.or_kkt_weighted.restype = C.c_double
+        lib.or_kkt_weighted.argtypes = [C.c_double] * 4
+        lib.or_restart_decision.restype = C.c_int
+        lib.or_restart_decision.argtypes = [P(OrParams), C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int64]
+        lib.or_weight_update.restype = C.c_double
+        lib.or_weight_update.argtypes = [P(OrParams), C.c_double, C.c_double, C.c_double]
         lib.or_dual_push.argtypes = [C.c_void_p, C.c_uint64, P(OrDualPushResult)]
         lib.or_get_rhs_scaled.argtypes = [C.c_void_p, dp]
         lib.or_kkt_report.argtypes = [C.c_void_p, dp, dp, P(OrKKT)]
@@ -138,6 +148,28 @@ def num_threads() -> int:
 
 def push_uniform(seed: int, j: int) -> float:
     return float(_load().or_push_uniform(C.c_uint64(seed), C.c_int64(j)))
+
+
+def set_threads(k: int) -> None:
+    """Threads of the oracle's row-parallel products from now on."""
+    _load().or_set_threads(int(k))
+
+
+def kkt_weighted(omega: float, p2: float, d2: float, gap2: float) -> float:
+    """The weighted KKT measure the restart rule compares."""
+    return float(_load().or_kkt_weighted(omega, p2, d2, gap2))
+
+
+def restart_decision(kc: float, ka: float, kprev: float, k: int, t: int, **params) -> bool:
+    """The restart rule of a check, as the oracle's loop applies it."""
+    p = default_params(**params)
+    return bool(_load().or_restart_decision(C.byref(p), kc, ka, kprev, int(k), int(t)))
+
+
+def weight_update(omega: float, dx: float, dy: float, **params) -> float:
+    """The primal weight after a restart whose anchors moved by dx and dy."""
+    p = default_params(**params)
+    return float(_load().or_weight_update(C.byref(p), omega, dx, dy))
 
 
 def default_params(**kw) -> OrParams:
@@ -193,6 +225,28 @@ class OracleSolver:
         if st < 0:
             raise RuntimeError("corner push needs a prior solve")
         return r
+
+    def corner_push_learned(self, logits, theta: float, seed: int) -> OrPushResult:
+        """Corner push with the learned warm start from per-column logits
+        (float32, one per column)."""
+        lg = np.ascontiguousarray(logits, dtype=np.float32)
+        if lg.shape != (self.n,):
+            raise ValueError("one logit per column")
+        r = OrPushResult()
+        st = self.lib.or_corner_push_learned(self.h, lg.ctypes.data_as(C.POINTER(C.c_float)), float(theta),
+                                             C.c_uint64(seed), C.byref(r))
+        if st == -1:
+            raise ValueError("theta must lie in (0, 1)")
+        if st < 0:
+            raise RuntimeError("corner push needs a prior solve")
+        return r
+
+    def features(self, seed: int) -> np.ndarray:
+        """The 16 learned-warm-start features of every column (n x 16)."""
+        out = np.zeros((self.n, 16))
+        if self.lib.or_features(self.h, C.c_uint64(seed), _dp(out)) != 0:
+            raise RuntimeError("features need a solve and no push yet")
+        return out
 
     def dual_push(self, seed: int) -> OrDualPushResult:
         """Dual corner push; afterwards solution() gives (x, yhat, zhat)."""

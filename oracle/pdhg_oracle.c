@@ -117,7 +117,9 @@ typedef struct {
        solve's answer has at least max(push_gate_rows * m, push_gate_min)
        candidates (off bound with |z| < tol) */
     int32_t push_gate;
-    int32_t pad2_;
+    /* keep x and z of the solve's candidate at its last 4 restarts (float32
+       values), for the trend features of the learned warm start */
+    int32_t record_history;
     double push_gate_rows;
     int64_t push_gate_min;
 } or_params;
@@ -147,6 +149,8 @@ typedef struct {
     int64_t n_fix_lower, n_fix_upper, n_rows_to_eq;
     double rel_p_push; /* relative primal residual of the push model at stop */
     or_kkt before, after;
+    int64_t n_learned_fix;  /* learned warm start: columns fixed from the predictor */
+    int64_t n_learned_undo; /* learned fixes undone at push checks                  */
 } or_push_result;
 
 typedef struct {
@@ -194,6 +198,12 @@ typedef struct {
     double *xpush;         /* unscaled push result */
     double *ypush, *zpush; /* unscaled dual push result and its reduced costs */
     double *cpush;         /* unscaled objective of the dual push model        */
+    /* learned warm start: restart history of the solve (slot (r - 1) mod 4
+       holds the candidate of restart r, rounded to float32) and the fixes */
+    double *hx, *hz;
+    signed char *lfix; /* 0 none, 1 fixed at its lower bound, 2 at its upper */
+    int learned;       /* the push runs with learned fixes                    */
+    int64_t n_lfix, n_lundo;
     or_params p;
 } or_solver;
 
@@ -416,9 +426,32 @@ static void kkt_scaled_parts(or_solver *s, const double *x, const double *y, dou
     free(aty);
 }
 
-static double kkt_weighted(double omega, double p2, double d2, double gap2)
+/* KKT_omega = sqrt(omega^2 ||rP||^2 + ||rD||^2 / omega^2 + gap^2): the primal
+ * part weighted up and the dual part down by the primal weight omega. */
+double or_kkt_weighted(double omega, double p2, double d2, double gap2)
 {
     return sqrt(omega * omega * p2 + d2 / (omega * omega) + gap2);
+}
+
+/* Restart decision at a check from the weighted KKT of the candidate (kc),
+ * of the anchor (ka) and of the previous check's candidate (kprev), the
+ * iterations since the last restart (k) and in the phase (t): restart on
+ * sufficient decay, on necessary decay without progress since the last
+ * check, or when the inner run is long against the whole phase. */
+int or_restart_decision(const or_params *p, double kc, double ka, double kprev, int64_t k, int64_t t)
+{
+    return (kc <= p->restart_suff * ka) || (kc <= p->restart_nec * ka && kc > kprev) ||
+           ((double)k >= p->restart_art * (double)t);
+}
+
+/* Primal weight after a restart whose anchors moved by dx (primal) and dy
+ * (dual): log-space smoothing of dy/dx with the old weight,
+ * exp(th ln(dy/dx) + (1 - th) ln omega); kept when either move is below 1e-10. */
+double or_weight_update(const or_params *p, double omega, double dx, double dy)
+{
+    if (!(dx > 1e-10 && dy > 1e-10)) return omega;
+    double th = p->pw_smooth;
+    return exp(th * log(dy / dx) + (1.0 - th) * log(omega));
 }
 
 /* ------------------------------------------------------------------------ */
@@ -443,6 +476,7 @@ static void set_defaults(or_params *p)
     p->pad_ = 0;
     p->push_obj_scale = 1.0;
     p->push_gate = 0;
+    p->record_history = 0;
     p->push_gate_rows = 2.0;
     p->push_gate_min = 100000;
     p->push_max_iter = 1000000;
@@ -496,7 +530,8 @@ void or_destroy(or_solver *s)
     void *ptrs[] = {s->rp, s->ci, s->av, s->tp, s->ti, s->tpos, s->b, s->c, s->l, s->u, s->sense0,
                     s->ahat, s->ahat_t, s->dr, s->dc, s->bh, s->ch, s->lh, s->uh, s->sense, s->x,
                     s->y, s->xa, s->ya, s->xp, s->yp, s->xbar, s->g, s->hv, s->xs_hat, s->xsol,
-                    s->ysol, s->zsol, s->xpush, s->ys_hat, s->ypush, s->zpush, s->cpush};
+                    s->ysol, s->zsol, s->xpush, s->ys_hat, s->ypush, s->zpush, s->cpush,
+                    s->hx, s->hz, s->lfix};
     for (size_t q = 0; q < sizeof(ptrs) / sizeof(ptrs[0]); q++) free(ptrs[q]);
     free(s);
 }
@@ -602,7 +637,7 @@ static void reset_iteration(or_solver *s, int64_t first_check)
     s->restarts = 0;
     s->next_check = first_check;
     kkt_scaled_parts(s, s->x, s->y, &s->kkt_anchor_p2, &s->kkt_anchor_d2, &s->kkt_anchor_gap2);
-    s->kkt_prev = kkt_weighted(s->omega, s->kkt_anchor_p2, s->kkt_anchor_d2, s->kkt_anchor_gap2);
+    s->kkt_prev = or_kkt_weighted(s->omega, s->kkt_anchor_p2, s->kkt_anchor_d2, s->kkt_anchor_gap2);
 }
 
 or_solver *or_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
@@ -689,6 +724,11 @@ or_solver *or_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, 
     s->ypush = dalloc(m);
     s->zpush = dalloc(n);
     s->cpush = dalloc(n);
+    s->lfix = (signed char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (s->p.record_history) {
+        s->hx = dalloc(4 * (int64_t)n);
+        s->hz = dalloc(4 * (int64_t)n);
+    }
 
     scale_and_step(s);
     for (int i = 0; i < m; i++) {
@@ -743,27 +783,45 @@ static void unscale(const or_solver *s, const double *xh, const double *yh, doub
         for (int i = 0; i < s->m; i++) y[i] = s->dr[i] * yh[i];
 }
 
+/* zsplit: the part of the reduced cost lam that finite bounds absorb */
+static double zsplit(double lam, double lo, double hi)
+{
+    double zp = (!is_inf_lo(lo) && lam > 0.0) ? lam : 0.0;
+    double zm = (!is_inf_up(hi) && lam < 0.0) ? -lam : 0.0;
+    return zp - zm;
+}
+
+/* the solve's candidate (x+, y+) at restart number s->restarts, rounded to
+ * float32, into slot (restarts - 1) mod 4 of the history */
+static void record_history(or_solver *s)
+{
+    int n = s->n;
+    double *aty = dalloc(n);
+    mv_At(s, s->ahat_t, s->yp, aty);
+    int64_t slot = (s->restarts - 1) % 4;
+    for (int j = 0; j < n; j++) {
+        s->hx[slot * n + j] = (double)(float)s->xp[j];
+        s->hz[slot * n + j] = (double)(float)zsplit(s->ch[j] - aty[j], s->lh[j], s->uh[j]);
+    }
+    free(aty);
+}
+
 /* restart test and primal-weight update at a check; candidate = (xp, yp) */
 static void restart_check(or_solver *s)
 {
     double p2, d2, g2;
     kkt_scaled_parts(s, s->xp, s->yp, &p2, &d2, &g2);
-    double kc = kkt_weighted(s->omega, p2, d2, g2);
-    double ka = kkt_weighted(s->omega, s->kkt_anchor_p2, s->kkt_anchor_d2, s->kkt_anchor_gap2);
-    int do_restart = (kc <= s->p.restart_suff * ka) ||
-                     (kc <= s->p.restart_nec * ka && kc > s->kkt_prev) ||
-                     ((double)s->k >= s->p.restart_art * (double)s->t);
+    double kc = or_kkt_weighted(s->omega, p2, d2, g2);
+    double ka = or_kkt_weighted(s->omega, s->kkt_anchor_p2, s->kkt_anchor_d2, s->kkt_anchor_gap2);
+    int do_restart = or_restart_decision(&s->p, kc, ka, s->kkt_prev, s->k, s->t);
     s->kkt_prev = kc;
     if (!do_restart) return;
     csum sx = {0, 0}, sy = {0, 0};
     for (int j = 0; j < s->n; j++) cadd(&sx, (s->xp[j] - s->xa[j]) * (s->xp[j] - s->xa[j]));
     for (int i = 0; i < s->m; i++) cadd(&sy, (s->yp[i] - s->ya[i]) * (s->yp[i] - s->ya[i]));
-    double dx = sqrt(cval(&sx));
-    double dy = sqrt(cval(&sy));
-    if (dx > 1e-10 && dy > 1e-10) {
-        double th = s->p.pw_smooth;
-        s->omega = exp(th * log(dy / dx) + (1.0 - th) * log(s->omega));
-    }
+    s->omega = or_weight_update(&s->p, s->omega, sqrt(cval(&sx)), sqrt(cval(&sy)));
+    s->restarts++;
+    if (!s->in_push && s->p.record_history) record_history(s);
     memcpy(s->x, s->xp, sizeof(double) * (size_t)s->n);
     memcpy(s->xa, s->xp, sizeof(double) * (size_t)s->n);
     memcpy(s->y, s->yp, sizeof(double) * (size_t)s->m);
@@ -771,9 +829,27 @@ static void restart_check(or_solver *s)
     s->kkt_anchor_p2 = p2;
     s->kkt_anchor_d2 = d2;
     s->kkt_anchor_gap2 = g2;
-    s->kkt_prev = kkt_weighted(s->omega, p2, d2, g2);
+    s->kkt_prev = or_kkt_weighted(s->omega, p2, d2, g2);
     s->k = 0;
-    s->restarts++;
+}
+
+/* learned warm start, undo rule: a learned fix whose push-model reduced cost
+ * (unscaled: the push objective minus A'y of the check's candidate, aty
+ * unscaled) has the wrong sign beyond eps_abs goes back to the bounds the
+ * plain rule left it (the original ones) */
+static void learned_undo(or_solver *s, const double *aty)
+{
+    double ea = s->p.eps_abs;
+    for (int j = 0; j < s->n; j++) {
+        if (!s->lfix[j]) continue;
+        double lam = s->ch[j] / s->dc[j] - aty[j];
+        if ((s->lfix[j] == 1 && lam < -ea) || (s->lfix[j] == 2 && lam > ea)) {
+            s->lh[j] = s->l[j] / s->dc[j];
+            s->uh[j] = s->u[j] / s->dc[j];
+            s->lfix[j] = 0;
+            s->n_lundo++;
+        }
+    }
 }
 
 static int all_finite(const double *v, int64_t n)
@@ -830,10 +906,14 @@ static int run_phase(or_solver *s, int64_t iters, double *out_relp)
             if (out_relp) *out_relp = k.rel_p;
             if (k.rel_p <= s->p.eps_rel) {
                 status = OR_PUSH_DONE;
+                /* the check's tests saw the model the candidate came from;
+                   the undo follows them, at the terminating check too */
+                if (s->learned) learned_undo(s, aty);
                 break;
             }
         }
         restart_check(s);
+        if (s->in_push == 1 && s->learned) learned_undo(s, aty);
     }
     free(x);
     free(y);
@@ -894,8 +974,42 @@ static void reduced_costs(const or_solver *s, const double *x, const double *y, 
     free(aty);
 }
 
-/* Algorithm 1 with implicit slacks, modified in place, continued by PDHG */
-int or_corner_push(or_solver *s, uint64_t seed, or_push_result *r)
+/* learned warm start, fixes at the push start (after the plain rule): a
+ * column the plain rule leaves free (|z_j| <= eps_abs) whose logit is at
+ * least logit(theta) (the comparison in float32, the predictor's precision)
+ * is fixed at its nearer finite bound (distances to the scaled bounds, a tie
+ * going to the lower one) when the sign of z_j allows that bound (z_j >=
+ * -eps_abs at the lower, z_j <= eps_abs at the upper); the push starts with
+ * x_j at that bound.  A column with no finite bound is left free. */
+static void learned_fix(or_solver *s, const float *logits, double theta)
+{
+    const float tl = (float)log(theta / (1.0 - theta));
+    double ea = s->p.eps_abs;
+    s->n_lfix = 0;
+    s->n_lundo = 0;
+    for (int j = 0; j < s->n; j++) {
+        s->lfix[j] = 0;
+        if (fabs(s->zsol[j]) > ea || !(logits[j] >= tl)) continue;
+        double lo = s->l[j] / s->dc[j], hi = s->u[j] / s->dc[j], xv = s->xs_hat[j];
+        double dl = is_inf_lo(lo) ? INFINITY : xv - lo;
+        double du = is_inf_up(hi) ? INFINITY : hi - xv;
+        if (isinf(dl) && isinf(du)) continue;
+        if (dl <= du) {
+            if (s->zsol[j] < -ea) continue;
+            s->lh[j] = s->uh[j] = s->x[j] = lo;
+            s->lfix[j] = 1;
+        } else {
+            if (s->zsol[j] > ea) continue;
+            s->lh[j] = s->uh[j] = s->x[j] = hi;
+            s->lfix[j] = 2;
+        }
+        s->n_lfix++;
+    }
+}
+
+/* Algorithm 1 with implicit slacks, modified in place, continued by PDHG;
+ * with logits, the learned warm start on top of the plain rule */
+static int corner_push_impl(or_solver *s, uint64_t seed, or_push_result *r, const float *logits, double theta)
 {
     if (!s || !s->solved || s->in_push) return OR_ERR_STATE;
     int m = s->m, n = s->n;
@@ -933,6 +1047,8 @@ int or_corner_push(or_solver *s, uint64_t seed, or_push_result *r)
     /* CP5: start from (x, 0); keep scaling and eta; new weight and restart state */
     memcpy(s->x, s->xs_hat, sizeof(double) * (size_t)n);
     for (int i = 0; i < m; i++) s->y[i] = 0.0;
+    s->learned = logits != NULL;
+    if (logits) learned_fix(s, logits, theta);
     s->omega = initial_omega(s->ch, n, s->bh, m);
     s->in_push = 1;
     reset_iteration(s, s->p.push_min_iters);
@@ -948,9 +1064,90 @@ int or_corner_push(or_solver *s, uint64_t seed, or_push_result *r)
     double *z2 = dalloc(n);
     reduced_costs(s, s->xpush, s->ysol, z2, ax, &r->after);
     corner_counts(s, s->xpush, ax, s->ysol, s->zsol, &r->after);
+    r->n_learned_fix = s->learned ? s->n_lfix : 0;
+    r->n_learned_undo = s->learned ? s->n_lundo : 0;
+    s->learned = 0;
     free(z2);
     free(ax);
     return st;
+}
+
+int or_corner_push(or_solver *s, uint64_t seed, or_push_result *r)
+{
+    return corner_push_impl(s, seed, r, NULL, -1.0);
+}
+
+/* the corner push with the learned warm start from per-column logits (n
+ * float32 values: the predictor's output on the solve's state) */
+int or_corner_push_learned(or_solver *s, const float *logits, double theta, uint64_t seed, or_push_result *r)
+{
+    if (!logits || !(theta > 0.0 && theta < 1.0)) return OR_ERR_ARG;
+    return corner_push_impl(s, seed, r, logits, theta);
+}
+
+/* The 16 features of the learned warm start for every column of a solved LP
+ * (before its push), on the scaled model at the solve's last checked
+ * candidate (x+, y+), z = the bound-absorbed part of c - A'y+:
+ *   0..3   x_j, z_j, |c_j|, ||A_{:,j}||_2;
+ *   4..7   x_j at the last, second-last, ... 4th-last restart minus x_j (0
+ *          where fewer restarts happened or no history was kept);
+ *   8..11  the same for z_j;
+ *   12     the push objective coefficient of column j for the push seed;
+ *   13, 14 x_j - l_j and u_j - x_j (-1 where that bound is infinite);
+ *   15     (x_j - l_j) / (u_j - l_j) where both bounds are finite and
+ *          distinct, else -1;
+ * a non-finite value counts as 0.  Each feature v is then mapped to
+ * sign(v) ln(1 + |v| / s), s the root mean square of that feature over the
+ * LP's columns (1 if it is 0).  out is n x 16, row j = column j. */
+int or_features(or_solver *s, uint64_t seed, double *out)
+{
+    if (!s || !out) return OR_ERR_ARG;
+    if (!s->solved || s->in_push) return OR_ERR_STATE;
+    int n = s->n;
+    double *aty = dalloc(n);
+    mv_At(s, s->ahat_t, s->ys_hat, aty);
+    int64_t rest = s->restarts, have = rest < 4 ? rest : 4;
+    double sq[16];
+    for (int q = 0; q < 16; q++) sq[q] = 0.0;
+    for (int j = 0; j < n; j++) {
+        double v[16];
+        double xj = s->xs_hat[j];
+        double zj = zsplit(s->ch[j] - aty[j], s->lh[j], s->uh[j]);
+        double cn = 0.0;
+        for (int64_t e = s->tp[j]; e < s->tp[j + 1]; e++) cn += s->ahat_t[e] * s->ahat_t[e];
+        v[0] = xj;
+        v[1] = zj;
+        v[2] = fabs(s->ch[j]);
+        v[3] = sqrt(cn);
+        for (int k = 1; k <= 4; k++) {
+            int use = k <= have && s->hx;
+            int64_t slot = use ? (rest - k) % 4 : 0;
+            v[3 + k] = use ? s->hx[slot * n + j] - xj : 0.0;
+            v[7 + k] = use ? s->hz[slot * n + j] - zj : 0.0;
+        }
+        double lo = s->lh[j], hi = s->uh[j];
+        int flo = !is_inf_lo(lo), fhi = !is_inf_up(hi);
+        v[12] = s->dc[j] * (s->p.push_obj_scale * or_push_uniform(seed, j));
+        v[13] = flo ? xj - lo : -1.0;
+        v[14] = fhi ? hi - xj : -1.0;
+        v[15] = (flo && fhi && hi > lo) ? (xj - lo) / (hi - lo) : -1.0;
+        for (int q = 0; q < 16; q++) {
+            if (!isfinite(v[q])) v[q] = 0.0;
+            out[(int64_t)j * 16 + q] = v[q];
+            sq[q] += v[q] * v[q];
+        }
+    }
+    for (int q = 0; q < 16; q++) {
+        double rms = n > 0 ? sqrt(sq[q] / n) : 0.0;
+        double sc = rms > 0.0 ? rms : 1.0;
+        for (int j = 0; j < n; j++) {
+            double v = out[(int64_t)j * 16 + q];
+            double t = log1p(fabs(v) / sc);
+            out[(int64_t)j * 16 + q] = v < 0.0 ? -t : t;
+        }
+    }
+    free(aty);
+    return 0;
 }
 
 /* Dual corner push (reading in the file header).  Runs once, after the solve
@@ -1111,6 +1308,15 @@ int or_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+/* thread count of the row-parallel products (the CPU leg's 1-thread timing) */
+void or_set_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
 #endif
 }
 int or_params_size(void) { return (int)sizeof(or_params); }

@@ -88,3 +88,40 @@ def test_adam_lowers_the_loss_on_a_separable_problem():
     l1, _, z = M.loss_and_grad(p, f, y, 1.0)
     assert l1 < 0.5 * l0
     assert np.mean((z > 0) == (y > 0)) > 0.9
+
+
+def _one_param(v):
+    return {"w": np.array([v], dtype=np.float64)}
+
+
+def test_adam_first_step_is_lr_times_the_gradient_sign():
+    """Adam (Kingma and Ba 2015) with bias correction: after one step
+    m_hat = g and v_hat = g^2, so the move is lr g / (|g| + eps), which is
+    lr sign(g) when |g| >> eps.  Without the correction the move would be
+    lr * 0.1 g / (sqrt(0.001) |g|) = 3.16 lr."""
+    st = {}
+    p = M.adam_step(_one_param(0.5), {"w": np.array([2.0])}, st, lr=1e-3)
+    assert p["w"][0] == pytest.approx(np.float32(0.5 - 1e-3 * 2.0 / (2.0 + 1e-8)), rel=0, abs=1e-9)
+    st = {}
+    p = M.adam_step(_one_param(0.5), {"w": np.array([-3e-4])}, st, lr=1e-3)
+    assert p["w"][0] == pytest.approx(np.float32(0.5 + 1e-3 * 3e-4 / (3e-4 + 1e-8)), rel=0, abs=1e-9)
+
+
+def test_adam_second_step_closed_form():
+    """Step 2: m = 0.9 (0.1 g1) + 0.1 g2, v = 0.999 (0.001 g1^2) + 0.001 g2^2,
+    m_hat = m / (1 - 0.9^2) = m / 0.19, v_hat = v / (1 - 0.999^2) = v / 0.001999.
+    g2 = g1 = g: m_hat = g, v_hat = g^2, move lr sign(g) again.
+    g2 = -g1: m = -0.01 g1, m_hat = -g1 / 19, v_hat = g1^2, move -lr/19 sign(g1)."""
+    lr, g = 1e-3, 0.25
+    st = {}
+    p = M.adam_step(_one_param(1.0), {"w": np.array([g])}, st, lr=lr)
+    p = M.adam_step(p, {"w": np.array([g])}, st, lr=lr)
+    p1 = np.float32(1.0 - lr * g / (g + 1e-8))
+    assert p["w"][0] == pytest.approx(np.float32(p1 - lr * g / (g + 1e-8)), rel=0, abs=2e-9)
+    st = {}
+    p = M.adam_step(_one_param(1.0), {"w": np.array([g])}, st, lr=lr)
+    p = M.adam_step(p, {"w": np.array([-g])}, st, lr=lr)
+    m_hat = -g / 19.0
+    v_hat = g * g
+    assert p["w"][0] == pytest.approx(np.float32(p1 - lr * m_hat / (np.sqrt(v_hat) + 1e-8)), rel=0, abs=2e-9)
+    assert st["t"] == 2
