@@ -474,6 +474,16 @@ int pdhg_features(pdhg_solver *s, uint64_t seed, float *out);
  * for theta outside (0, 1). */
 int pdhg_corner_push_learned(pdhg_solver *s, pdhg_mlp *net, double theta, uint64_t seed, pdhg_push_result *r);
 
+/* pdhg_corner_push_learned with the predictor's output supplied by the
+ * caller: logits[n] (host float32, column j's logit; copied before the
+ * call returns, the caller keeps ownership) take the place of the network
+ * on the handle's features.  A column is predicted fixed when its logit is
+ * >= ln(theta / (1 - theta)), compared in float32; a NaN logit never fixes.
+ * The same fixes, undo rule and counts follow.  For callers with their own
+ * predictor (the paper has none: a warm start of Algorithm 1's fixing set).
+ * Errors as pdhg_corner_push_learned, INVALID_ARG for NULL logits. */
+int pdhg_corner_push_logits(pdhg_solver *s, const float *logits, double theta, uint64_t seed, pdhg_push_result *r);
+
 /* The features of pdhg_features for every LP of a solved batch (before its
  * push), each LP normalised over its own columns and drawing the push
  * objective of seeds[i] (count seeds, host): out[total_n x 16] (host),
@@ -489,6 +499,11 @@ int pdhg_batch_features(pdhg_batch *b, const uint64_t *seeds, float *out);
  * theta outside (0, 1) or a NULL network. */
 int pdhg_batch_corner_push_learned(pdhg_batch *b, pdhg_mlp *net, double theta, const uint64_t *seeds,
                                    pdhg_push_result *results);
+
+/* pdhg_batch_corner_push_learned with caller logits: logits[total_n] (host
+ * float32, the LPs' columns in batch order), as pdhg_corner_push_logits. */
+int pdhg_batch_corner_push_logits(pdhg_batch *b, const float *logits, double theta, const uint64_t *seeds,
+                                  pdhg_push_result *results);
 
 /* Release all device memory of the handle (NULL is a no-op). */
 void pdhg_destroy(pdhg_solver *s);

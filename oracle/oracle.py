@@ -100,7 +100,7 @@ def _load():
         lib.or_solve.argtypes = [C.c_void_p, P(OrResult)]
         lib.or_corner_push.argtypes = [C.c_void_p, C.c_uint64, P(OrPushResult)]
         lib.or_corner_push_learned.argtypes = [C.c_void_p, P(C.c_float), C.c_double, C.c_uint64, P(OrPushResult)]
-        lib.or_features.argtypes = [C.c_void_p, C.c_uint64, dp]
+        lib.or_features.argtypes = [C.c_void_p, C.c_uint64, dp, dp]
         lib.or_set_threads.argtypes = [C.c_int]
         lib.or_kkt_weighted.restype = C.c_double
         lib.or_kkt_weighted.argtypes = [C.c_double] * 4
@@ -241,12 +241,14 @@ class OracleSolver:
             raise RuntimeError("corner push needs a prior solve")
         return r
 
-    def features(self, seed: int) -> np.ndarray:
-        """The 16 learned-warm-start features of every column (n x 16)."""
+    def features(self, seed: int, with_scale: bool = False):
+        """The 16 learned-warm-start features of every column (n x 16); with
+        with_scale, also each feature's normalising scale (16)."""
         out = np.zeros((self.n, 16))
-        if self.lib.or_features(self.h, C.c_uint64(seed), _dp(out)) != 0:
+        sc = np.zeros(16)
+        if self.lib.or_features(self.h, C.c_uint64(seed), _dp(out), _dp(sc)) != 0:
             raise RuntimeError("features need a solve and no push yet")
-        return out
+        return (out, sc) if with_scale else out
 
     def dual_push(self, seed: int) -> OrDualPushResult:
         """Dual corner push; afterwards solution() gives (x, yhat, zhat)."""

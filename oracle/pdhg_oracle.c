@@ -1098,8 +1098,9 @@ int or_corner_push_learned(or_solver *s, const float *logits, double theta, uint
  *          distinct, else -1;
  * a non-finite value counts as 0.  Each feature v is then mapped to
  * sign(v) ln(1 + |v| / s), s the root mean square of that feature over the
- * LP's columns (1 if it is 0).  out is n x 16, row j = column j. */
-int or_features(or_solver *s, uint64_t seed, double *out)
+ * LP's columns (1 if it is 0).  out is n x 16, row j = column j; scale
+ * (16 values, or NULL) receives the s of each feature. */
+int or_features(or_solver *s, uint64_t seed, double *out, double *scale)
 {
     if (!s || !out) return OR_ERR_ARG;
     if (!s->solved || s->in_push) return OR_ERR_STATE;
@@ -1140,6 +1141,7 @@ int or_features(or_solver *s, uint64_t seed, double *out)
     for (int q = 0; q < 16; q++) {
         double rms = n > 0 ? sqrt(sq[q] / n) : 0.0;
         double sc = rms > 0.0 ? rms : 1.0;
+        if (scale) scale[q] = sc;
         for (int j = 0; j < n; j++) {
             double v = out[(int64_t)j * 16 + q];
             double t = log1p(fabs(v) / sc);

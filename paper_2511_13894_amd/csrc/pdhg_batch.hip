@@ -90,7 +90,7 @@ static void launch_primal_b(pdhg_batch *b, int i, int store, hipEvent_t e0 = nul
 #define PDHG_BP_CASE(TT, RR, NT)                                                                               \
     case TT:                                                                                                   \
         PDHG_LAUNCH(e0, e1, (kb_primal<V, RR, NT>), dim3(b->n_ptiles), dim3(NT), s->stream, b->ptiles, s->tp, \
-                           s->ti, (const V *)s->ahat_t, (const double *)s->y, s->ch,               \
+                           s->ti, (const V *)s->ahat_t, (const double *)s->y, s->chc,               \
                            (const V *)s->lh, (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar,     \
                            (V *)s->xp, b->sts, i, store);                                                     \
         break;
@@ -113,7 +113,7 @@ static void launch_dual_b(pdhg_batch *b, int i, int store, hipEvent_t e0 = nullp
 #define PDHG_BD_CASE(TT, RR, NT)                                                                               \
     case TT:                                                                                                   \
         PDHG_LAUNCH(e0, e1, (kb_dual<V, RR, NT>), dim3(b->n_dtiles), dim3(NT), s->stream, b->dtiles, s->rp,   \
-                           s->ci, (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bh, s->sense,    \
+                           s->ci, (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense,    \
                            (double *)s->y, (const double *)s->ya, (double *)s->yp, b->sts, i, store);         \
         break;
     switch (-b->kern_a) {
@@ -129,7 +129,10 @@ static void launch_dual_b(pdhg_batch *b, int i, int store, hipEvent_t e0 = nullp
 }
 
 // ---------------------------------------------------------------- checks ---
-__global__ __launch_bounds__(kBlock) void kb_check_rows(const int4 *__restrict__ rm, const double *__restrict__ ax,
+// ex / ety (mixed mode, else NULL): the rounding error's products, added to
+// ax / aty to give the float64 products, which are written back
+__global__ __launch_bounds__(kBlock) void kb_check_rows(const int4 *__restrict__ rm, double *__restrict__ ax,
+                                                       const double *__restrict__ ex,
                                                        const double *__restrict__ bh, const int8_t *__restrict__ sense,
                                                        const double *__restrict__ dr, const double *__restrict__ yc,
                                                        const double *__restrict__ ya, double *__restrict__ part,
@@ -140,7 +143,12 @@ __global__ __launch_bounds__(kBlock) void kb_check_rows(const int4 *__restrict__
     double v[6] = {0, 0, 0, 0, 0, 0}; // PH2, P2, PINF, BTY, DY2, NAN
     if ((int)threadIdx.x < tl.z) {
         const int i = tl.y + threadIdx.x;
-        double r = bh[i] - ax[i];
+        double axi = ax[i];
+        if (ex) {
+            axi += ex[i];
+            ax[i] = axi;
+        }
+        double r = bh[i] - axi;
         const int8_t s = sense[i];
         if (s == '<') r = r < 0.0 ? r : 0.0;
         else if (s == '>') r = r > 0.0 ? r : 0.0;
@@ -167,7 +175,8 @@ __global__ __launch_bounds__(kBlock) void kb_check_rows(const int4 *__restrict__
 }
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void kb_check_cols(const int4 *__restrict__ rn, const double *__restrict__ aty,
+__global__ __launch_bounds__(kBlock) void kb_check_cols(const int4 *__restrict__ rn, double *__restrict__ aty,
+                                                       const double *__restrict__ ety,
                                                        const double *__restrict__ ch, const V *__restrict__ lh,
                                                        const V *__restrict__ uh, const double *__restrict__ dc,
                                                        const V *__restrict__ xc, const V *__restrict__ xa,
@@ -183,7 +192,12 @@ __global__ __launch_bounds__(kBlock) void kb_check_cols(const int4 *__restrict__
         const int j = tl.y + threadIdx.x;
         double cj, lo, hi;
         check_model<V>(orig != 0, j, ch, lh, uh, c0, l0, u0, dc, cj, lo, hi);
-        const double lam = cj - aty[j];
+        double atyj = aty[j];
+        if (ety) {
+            atyj += ety[j];
+            aty[j] = atyj;
+        }
+        const double lam = cj - atyj;
         const double zp = (!is_inf_lo(lo) && lam > 0.0) ? lam : 0.0;
         const double zm = (!is_inf_up(hi) && lam < 0.0) ? -lam : 0.0;
         const double rd = lam - (zp - zm);
@@ -253,6 +267,26 @@ __global__ __launch_bounds__(kBlock) void kb_restart_apply(const int4 *__restric
     }
 }
 
+// Defect correction per LP (mixed mode): chc = ch - E' y_a, bhc = bh - E x_a
+// for every LP that restarted at this check (its candidate is the new anchor),
+// or for every LP with `always` (a phase start); column tiles, then row tiles.
+__global__ __launch_bounds__(kBlock) void kb_defect_set(const int4 *__restrict__ rn, int ntn,
+                                                       const int4 *__restrict__ rm,
+                                                       const DevState *__restrict__ sts, int always,
+                                                       const double *__restrict__ ch, const double *__restrict__ ety,
+                                                       double *__restrict__ chc, const double *__restrict__ bh,
+                                                       const double *__restrict__ ex, double *__restrict__ bhc)
+{
+    const bool col = (int)blockIdx.x < ntn;
+    const int4 tl = col ? rn[blockIdx.x] : rm[blockIdx.x - ntn];
+    const DevState *st = sts + tl.x;
+    if (!always && (!st->restart_flag || st->done)) return;
+    if ((int)threadIdx.x >= tl.z) return;
+    const int k = tl.y + threadIdx.x;
+    if (col) chc[k] = ch[k] - ety[k];
+    else bhc[k] = bh[k] - ex[k];
+}
+
 __global__ void kb_advance(DevState *sts, int count, int len)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -310,16 +344,26 @@ static void check_b(pdhg_batch *b, int mode, int len)
     const double *yc = (const double *)(mode ? s->yp : s->y);
     launch_spmv_b<V, V>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
     launch_spmv_b<V, double>(b, b->kern_at, b->ptiles, b->n_ptiles, s->tp, s->ti, (const V *)s->ahat_t, yc, s->aty);
+    if (s->aerr) { // mixed mode: the rounding error's products complete the float64 ones
+        launch_spmv_b<float, V>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci, (const float *)s->aerr, xc, s->ex);
+        launch_spmv_b<float, double>(b, b->kern_at, b->ptiles, b->n_ptiles, s->tp, s->ti, (const float *)s->aerr_t,
+                                     yc, s->ety);
+    }
     double *pm = b->part, *pn = b->part + (size_t)(Q_COUNT + 1) * b->n_rm;
-    hipLaunchKernelGGL(kb_check_rows, dim3(b->n_rm), dim3(kBlock), 0, st, b->rm, s->ax, (const double *)s->bh, s->sense,
+    hipLaunchKernelGGL(kb_check_rows, dim3(b->n_rm), dim3(kBlock), 0, st, b->rm, s->ax,
+                       (const double *)(s->aerr ? s->ex : nullptr), (const double *)s->bh, s->sense,
                        s->dr, yc, (const double *)s->ya, pm, b->n_rm, b->sts);
-    hipLaunchKernelGGL((kb_check_cols<V>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, s->aty, s->ch,
+    hipLaunchKernelGGL((kb_check_cols<V>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, s->aty,
+                       (const double *)(s->aerr ? s->ety : nullptr), s->ch,
                        (const V *)s->lh, (const V *)s->uh, s->dc, xc, (const V *)s->xa, s->c, s->l, s->u,
                        s->model_original ? 1 : 0, pn, b->n_rn, b->sts);
     hipLaunchKernelGGL(kb_check_final, dim3(b->count), dim3(kBlock), 0, st, b->sts, pm, b->n_rm, pn, b->n_rn,
                        b->rm_start, b->rn_start, mode, len);
     if (mode == 1 && s->hx) (void)batch_record_history(b); // before the restart copies
     if (mode == 2 && s->learned_active) (void)batch_learned_undo(b);
+    if (mode != 0 && s->aerr)
+        hipLaunchKernelGGL(kb_defect_set, dim3(b->n_rn + b->n_rm), dim3(kBlock), 0, st, b->rn, b->n_rn, b->rm, b->sts, 0,
+                           s->ch, s->ety, s->chc, (const double *)s->bh, s->ex, s->bhc);
     if (mode != 0)
         hipLaunchKernelGGL((kb_restart_apply<V>), dim3(b->n_rn + b->n_rm), dim3(kBlock), 0, st, b->rn, b->n_rn, b->rm,
                            b->sts, (V *)s->x, (V *)s->xa, (const V *)s->xp, (double *)s->y, (double *)s->ya,
@@ -572,8 +616,28 @@ static hipError_t phase_begin_b(pdhg_batch *b, bool fresh)
     return hipGetLastError();
 }
 
+// mixed mode: every LP's corrected data at its current anchor
+hipError_t batch_defect_refresh(pdhg_batch *b)
+{
+    pdhg_solver *s = b->s;
+    s->defect_stale = false;
+    if (!s->aerr) {
+        defect_alias(s);
+        return hipSuccess;
+    }
+    // the LPs taking part in the phase (the tiles skip the others)
+    launch_spmv_b<float, float>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci, (const float *)s->aerr,
+                                (const float *)s->xa, s->ex);
+    launch_spmv_b<float, double>(b, b->kern_at, b->ptiles, b->n_ptiles, s->tp, s->ti, (const float *)s->aerr_t,
+                                 (const double *)s->ya, s->ety);
+    hipLaunchKernelGGL(kb_defect_set, dim3(b->n_rn + b->n_rm), dim3(kBlock), 0, s->stream, b->rn, b->n_rn, b->rm,
+                       b->sts, 1, s->ch, s->ety, s->chc, (const double *)s->bh, s->ex, s->bhc);
+    return hipGetLastError();
+}
+
 hipError_t batch_phase_begin(pdhg_batch *b, bool fresh)
 {
+    b->s->defect_stale = true;
     return b->s->fp32 ? phase_begin_b<float>(b, fresh) : phase_begin_b<double>(b, fresh);
 }
 

@@ -89,7 +89,8 @@ void free_all(pdhg_solver *s)
                     s->ax,   s->aty, s->xu, s->yu,   s->zsol,   s->xpush, s->partials, s->redout, s->st,
                     s->hx,   s->hz,  s->feat_raw, s->feat_b, s->logits, s->lfix, s->lcount, s->sell_idx,
                     s->sell_val, s->sell_soff, s->sell_len, s->sell_wi_start, s->sell_wi, s->sell_part,
-                    s->ypush, s->zpush, s->w0};
+                    s->ypush, s->zpush, s->w0, s->aerr, s->aerr_t, s->ex, s->ety,
+                    s->aerr ? (void *)s->chc : nullptr, s->aerr ? (void *)s->bhc : nullptr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->st_host) (void)hipHostFree(s->st_host);
@@ -116,6 +117,7 @@ int run_phase(pdhg_solver *s, int64_t iters, int mode, double t0)
     const int depth = 4; // cycles enqueued before the host looks at the state
     bool time_out = false;
     if (s->st_host->done) return s->st_host->status;
+    if (s->defect_stale) HIPCHK(defect_refresh(s)); // corrected data at the phase's anchor (mixed mode)
     while (s->t_host < target) {
         int enq = 0;
         bool any_check = false;
@@ -234,6 +236,7 @@ bool run_batch_phase(pdhg_batch *b, int64_t iters, int mode, double t0)
         }
     };
     HIPCHK(batch_compact_tiles(b, true));
+    if (s->defect_stale) HIPCHK(batch_defect_refresh(b)); // corrected data at every LP's anchor (mixed mode)
     while (b->t_host < target) {
         int enq = 0;
         bool events = false;
@@ -395,6 +398,22 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
         (p.precision != PDHG_FP64 && p.precision != PDHG_FP32_MIXED) || !(p.eps_rel > 0.0) || !(p.eta_safety > 0.0) ||
         !(p.power_tol >= 0.0) || !(p.push_gate_rows >= 0.0) || p.push_gate_min < 0)
         return fail(PDHG_ERR_INVALID_ARG, "invalid parameter");
+    // every remaining tolerance, factor and cap: a NaN would turn each test
+    // that reads it into "false" (no fix, no restart, no stop)
+    if (!(p.eps_abs >= 0.0 && std::isfinite(p.eps_abs)) || !(std::isfinite(p.eps_rel)))
+        return fail(PDHG_ERR_INVALID_ARG, "eps_abs must be finite and >= 0, eps_rel finite");
+    if (!(p.push_obj_scale > 0.0 && std::isfinite(p.push_obj_scale)))
+        return fail(PDHG_ERR_INVALID_ARG, "push_obj_scale must be finite and > 0");
+    if (p.max_iter < 0 || p.push_max_iter < 0) return fail(PDHG_ERR_INVALID_ARG, "negative iteration cap");
+    if (!(p.reflect_gamma >= 0.0 && p.reflect_gamma <= 1.0))
+        return fail(PDHG_ERR_INVALID_ARG, "reflect_gamma must lie in [0, 1]");
+    if (!(p.pw_smooth >= 0.0 && p.pw_smooth <= 1.0)) return fail(PDHG_ERR_INVALID_ARG, "pw_smooth must lie in [0, 1]");
+    if (!(p.restart_suff >= 0.0 && p.restart_suff <= 1.0) || !(p.restart_nec >= 0.0 && p.restart_nec <= 1.0) ||
+        !(p.restart_art >= 0.0 && std::isfinite(p.restart_art)))
+        return fail(PDHG_ERR_INVALID_ARG, "restart factors: suff and nec in [0, 1], art finite and >= 0");
+    if (std::isnan(p.pc_alpha) || std::isnan(p.time_limit) || !std::isfinite(p.eta_safety))
+        return fail(PDHG_ERR_INVALID_ARG, "NaN pc_alpha or time_limit, or infinite eta_safety");
+    if (p.halpern != 0 && p.halpern != 1) return fail(PDHG_ERR_INVALID_ARG, "halpern must be 0 or 1");
     for (int half = 0; half < 2; half++) { // 0: primal half (lanes_at), 1: dual half (lanes_a)
         const int32_t k = half ? p.lanes_a : p.lanes_at;
         const bool lane_ok = k >= 1 && k <= 64 && !(k & (k - 1));
@@ -488,6 +507,16 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
         dalloc(&s->ch, N);
         for (void **q : {&s->y, &s->ya, &s->yp, &s->bh, &s->ys}) // m-vectors stay float64
             hip_check(hipMalloc(q, sizeof(double) * (M > 0 ? M : 1)), "hipMalloc");
+        if (s->fp32) { // the float matrix's rounding error and the corrected data (defect correction)
+            hip_check(hipMalloc(&s->aerr, sizeof(float) * (NZ > 0 ? NZ : 1)), "hipMalloc");
+            hip_check(hipMalloc(&s->aerr_t, sizeof(float) * (NZ > 0 ? NZ : 1)), "hipMalloc");
+            dalloc(&s->ex, M);
+            dalloc(&s->ety, N);
+            dalloc(&s->chc, N);
+            dalloc(&s->bhc, M);
+        } else {
+            defect_alias(s);
+        }
         dalloc(&s->ax, M);
         dalloc(&s->aty, N);
         dalloc(&s->xu, N);
@@ -535,6 +564,10 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(build_transpose(s));
         HIPCHK(scale_problem(s));
+        if (s->aerr) { // until the first anchor's correction: the uncorrected data
+            if (n > 0) HIPCHK(hipMemcpyAsync(s->chc, s->ch, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+            if (m > 0) HIPCHK(hipMemcpyAsync(s->bhc, s->bh, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
+        }
         if (s->kern_a == kSell) HIPCHK(sell_build(s, rp));
         if (single) {
             HIPCHK(power_iteration(s));
@@ -585,8 +618,12 @@ int pdhg_solve(pdhg_solver *s, pdhg_result *r)
     return pdhg_iterate(s, left > 0 ? left : 0, r);
 }
 
-static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, pdhg_mlp *net, double theta)
+// The corner push; with a network or caller logits (host, n float32), the
+// learned warm start on top of the plain rule.
+static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, pdhg_mlp *net,
+                              const float *logits_host, double theta)
 {
+    const bool learned = net != nullptr || logits_host != nullptr;
     if (!s || !r) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
     if (!s->solved || s->in_push) return fail(PDHG_ERR_STATE, "corner push needs a solve first (and runs once)");
     std::memset(r, 0, sizeof(*r));
@@ -611,20 +648,25 @@ static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r
             s->primal_pushed = true;
             return PDHG_OK;
         }
-        if (net) { // predictor on the solve's state, before the model changes
+        if (learned) { // predictor on the solve's state, before the model changes
             const size_t n = (size_t)(s->n > 0 ? s->n : 1);
-            if (!s->feat_raw) dalloc(&s->feat_raw, 16 * n);
-            if (!s->feat_b) dalloc(&s->feat_b, 16 * n);
             if (!s->logits) dalloc(&s->logits, n);
             if (!s->lfix) dalloc(&s->lfix, n);
             if (!s->lcount) dalloc(&s->lcount, 2);
             HIPCHK(hipMemsetAsync(s->lcount, 0, 2 * sizeof(unsigned), st));
-            HIPCHK(compute_features(s, seed));
-            HIPCHK(mlp_forward(net, st, s->feat_b, s->n, s->logits));
+            if (net) {
+                if (!s->feat_raw) dalloc(&s->feat_raw, 16 * n);
+                if (!s->feat_b) dalloc(&s->feat_b, 16 * n);
+                HIPCHK(compute_features(s, seed));
+                HIPCHK(mlp_forward(net, st, s->feat_b, s->n, s->logits));
+            } else if (s->n > 0) {
+                HIPCHK(hipMemcpyAsync(s->logits, logits_host, sizeof(float) * (size_t)s->n, hipMemcpyHostToDevice,
+                                      st));
+            }
         }
         // CP2-CP5: bounds, senses, objective, start (x, 0), new weight and restart state
-        HIPCHK(push_setup(s, seed, r, net ? theta : -1.0));
-        s->learned_active = net != nullptr;
+        HIPCHK(push_setup(s, seed, r, learned ? theta : -1.0));
+        s->learned_active = learned;
         HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         s->in_push = true;
@@ -646,7 +688,7 @@ static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r
         r->restarts = s->st_host->restarts;
         r->rel_p_push = s->st_host->checks > 0 ? s->st_host->rel_p : NAN;
         r->seconds = now_s() - t0;
-        if (net) {
+        if (learned) {
             unsigned cnt[2] = {0, 0};
             HIPCHK(hipMemcpy(cnt, s->lcount, sizeof(cnt), hipMemcpyDeviceToHost));
             r->n_learned_fix = cnt[0];
@@ -661,14 +703,22 @@ static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r
 
 int pdhg_corner_push(pdhg_solver *s, uint64_t seed, pdhg_push_result *r)
 {
-    return corner_push_common(s, seed, r, nullptr, -1.0);
+    return corner_push_common(s, seed, r, nullptr, nullptr, -1.0);
 }
 
 int pdhg_corner_push_learned(pdhg_solver *s, pdhg_mlp *net, double theta, uint64_t seed, pdhg_push_result *r)
 {
     if (!net) return fail(PDHG_ERR_INVALID_ARG, "NULL network");
     if (!(theta > 0.0 && theta < 1.0)) return fail(PDHG_ERR_INVALID_ARG, "theta must lie in (0, 1)");
-    return corner_push_common(s, seed, r, net, theta);
+    return corner_push_common(s, seed, r, net, nullptr, theta);
+}
+
+int pdhg_corner_push_logits(pdhg_solver *s, const float *logits, double theta, uint64_t seed, pdhg_push_result *r)
+{
+    if (!s) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
+    if (!logits && s->n > 0) return fail(PDHG_ERR_INVALID_ARG, "NULL logits");
+    if (!(theta > 0.0 && theta < 1.0)) return fail(PDHG_ERR_INVALID_ARG, "theta must lie in (0, 1)");
+    return corner_push_common(s, seed, r, nullptr, logits, theta);
 }
 
 // The dual corner push: DP1 the solve's answer, x replaced by the corner
@@ -963,6 +1013,7 @@ int pdhg_set_state(pdhg_solver *s, const void *buf, int64_t bytes)
         HIPCHK(hipStreamSynchronize(st));
         s->t_host = h.t_host;
         s->next_check = h.next_check;
+        s->defect_stale = true; // the restored anchor's correction (mixed mode)
         s->has_candidate = h.has_candidate != 0;
         s->solved = h.solved != 0;
     } catch (const HipFailure &f) {
@@ -1242,8 +1293,9 @@ static void batch_learned_buffers(pdhg_batch *b)
 }
 
 static int batch_push_common(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *results, pdhg_mlp *net,
-                             double theta)
+                             const float *logits_host, double theta)
 {
+    const bool learned = net != nullptr || logits_host != nullptr;
     if (!b || !seeds || !results) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
     if (!b->solved || b->pushed || b->dual_pushed)
         return fail(PDHG_ERR_STATE, "corner push needs a batch solve first (runs once, and not after a dual push)");
@@ -1270,15 +1322,21 @@ static int batch_push_common(pdhg_batch *b, const uint64_t *seeds, pdhg_push_res
                     gated[i] = 1;
                 }
         HIPCHK(hipMemcpy(b->active, act.data(), sizeof(int) * (size_t)b->count, hipMemcpyHostToDevice));
-        if (net) { // predictor on every LP's solve state, before the models change
+        if (learned) { // predictor on every LP's solve state, before the models change
             batch_learned_buffers(b);
             HIPCHK(hipMemsetAsync(s->lcount, 0, 2 * sizeof(unsigned) * (size_t)b->count, st));
-            HIPCHK(hipMemcpyAsync(b->seeds, seeds, sizeof(uint64_t) * (size_t)b->count, hipMemcpyHostToDevice, st));
-            HIPCHK(batch_compute_features(b));
-            HIPCHK(mlp_forward(net, st, s->feat_b, s->n, s->logits));
+            if (net) {
+                HIPCHK(hipMemcpyAsync(b->seeds, seeds, sizeof(uint64_t) * (size_t)b->count, hipMemcpyHostToDevice,
+                                      st));
+                HIPCHK(batch_compute_features(b));
+                HIPCHK(mlp_forward(net, st, s->feat_b, s->n, s->logits));
+            } else if (s->n > 0) {
+                HIPCHK(hipMemcpyAsync(s->logits, logits_host, sizeof(float) * (size_t)s->n, hipMemcpyHostToDevice,
+                                      st));
+            }
         }
-        HIPCHK(batch_push_setup(b, seeds, results, net ? theta : -1.0));
-        s->learned_active = net != nullptr;
+        HIPCHK(batch_push_setup(b, seeds, results, learned ? theta : -1.0));
+        s->learned_active = learned;
         b->t_host = 0;
         b->next_check = s->p.push_min_iters;
         if (s->p.push_compact) HIPCHK(batch_push_compact_begin(b)); // the push on the free columns
@@ -1306,7 +1364,7 @@ static int batch_push_common(pdhg_batch *b, const uint64_t *seeds, pdhg_push_res
             r.restarts = d.restarts;
             r.rel_p_push = d.checks > 0 ? d.rel_p : NAN;
         }
-        if (net) {
+        if (learned) {
             std::vector<unsigned> cnt(2 * (size_t)b->count);
             HIPCHK(hipMemcpy(cnt.data(), s->lcount, sizeof(unsigned) * cnt.size(), hipMemcpyDeviceToHost));
             for (int i = 0; i < b->count; i++) {
@@ -1325,7 +1383,7 @@ static int batch_push_common(pdhg_batch *b, const uint64_t *seeds, pdhg_push_res
 
 int pdhg_batch_corner_push(pdhg_batch *b, const uint64_t *seeds, pdhg_push_result *results)
 {
-    return batch_push_common(b, seeds, results, nullptr, -1.0);
+    return batch_push_common(b, seeds, results, nullptr, nullptr, -1.0);
 }
 
 int pdhg_batch_corner_push_learned(pdhg_batch *b, pdhg_mlp *net, double theta, const uint64_t *seeds,
@@ -1333,7 +1391,16 @@ int pdhg_batch_corner_push_learned(pdhg_batch *b, pdhg_mlp *net, double theta, c
 {
     if (!net) return fail(PDHG_ERR_INVALID_ARG, "NULL network");
     if (!(theta > 0.0 && theta < 1.0)) return fail(PDHG_ERR_INVALID_ARG, "theta must lie in (0, 1)");
-    return batch_push_common(b, seeds, results, net, theta);
+    return batch_push_common(b, seeds, results, net, nullptr, theta);
+}
+
+int pdhg_batch_corner_push_logits(pdhg_batch *b, const float *logits, double theta, const uint64_t *seeds,
+                                  pdhg_push_result *results)
+{
+    if (!b) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
+    if (!logits && b->s->n > 0) return fail(PDHG_ERR_INVALID_ARG, "NULL logits");
+    if (!(theta > 0.0 && theta < 1.0)) return fail(PDHG_ERR_INVALID_ARG, "theta must lie in (0, 1)");
+    return batch_push_common(b, seeds, results, nullptr, logits, theta);
 }
 
 // The dual corner push of every LP that reached the tolerance, each with its

@@ -217,7 +217,7 @@ hipError_t alloc(T **p, size_t count)
 void free_compact(pdhg_solver::PushCompact &c)
 {
     void *ptrs[] = {c.flag, c.newid, c.keep, c.tp, c.ti, c.rp, c.ci, c.ahat, c.ahat_t, c.lh, c.uh,
-                    c.x, c.xa, c.xbar, c.xp, c.ch, c.dc, c.bt, c.lfix, c.l, c.u};
+                    c.x, c.xa, c.xbar, c.xp, c.ch, c.dc, c.bt, c.lfix, c.l, c.u, c.aerr, c.aerr_t};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     c = pdhg_solver::PushCompact{};
@@ -265,6 +265,11 @@ hipError_t begin_impl(pdhg_solver *s)
     if ((e = alloc(reinterpret_cast<V **>(&c.ahat_t), (size_t)nnz_f)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_copy_cols<V>), dim3(grid_for(nf, kBlock, 1 << 30)), dim3(kBlock), 0, st, nf, c.keep, s->tp,
                        s->ti, (const V *)s->ahat_t, c.tp, c.ti, (V *)c.ahat_t);
+    if (s->aerr) { // mixed mode: the free columns' rounding errors as well (same indices rewritten)
+        if ((e = alloc(reinterpret_cast<float **>(&c.aerr_t), (size_t)nnz_f)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_copy_cols<float>), dim3(grid_for(nf, kBlock, 1 << 30)), dim3(kBlock), 0, st, nf, c.keep,
+                           s->tp, s->ti, (const float *)s->aerr_t, c.tp, c.ti, (float *)c.aerr_t);
+    }
     // rows of A (the dual half) restricted to the free columns
     int *cnt = nullptr;
     if ((e = alloc(&cnt, (size_t)m + 1)) != hipSuccess) return e;
@@ -284,10 +289,15 @@ hipError_t begin_impl(pdhg_solver *s)
     if ((e = alloc(reinterpret_cast<V **>(&c.ahat), (size_t)nnz_f)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_copy_rows<V>), dim3(gw), dim3(kBlock), 0, st, m, s->rp, s->ci, (const V *)s->ahat, c.flag,
                        c.newid, c.rp, c.ci, (V *)c.ahat);
-    // btilde = bhat - Ahat xf, the product on the full model (aty is free here)
+    if (s->aerr) {
+        if ((e = alloc(reinterpret_cast<float **>(&c.aerr), (size_t)nnz_f)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_copy_rows<float>), dim3(gw), dim3(kBlock), 0, st, m, s->rp, s->ci,
+                           (const float *)s->aerr, c.flag, c.newid, c.rp, c.ci, (float *)c.aerr);
+    }
+    // btilde = bhat - Ahat xf, the float64 product on the full model (aty is free here)
     double *xf = s->aty;
     hipLaunchKernelGGL((k_fixed_values<V>), dim3(gn1), dim3(kBlock), 0, st, n, c.flag, (const V *)s->lh, xf);
-    if ((e = solver_product(s, false, xf, s->ax)) != hipSuccess) return e;
+    if ((e = exact_product(s, false, xf, s->ax)) != hipSuccess) return e;
     if ((e = alloc(&c.bt, (size_t)m)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_btilde, dim3(grid_for(m, kBlock, 1 << 30)), dim3(kBlock), 0, st, m, (const double *)s->bh,
                        s->ax, c.bt);
@@ -329,6 +339,10 @@ hipError_t begin_impl(pdhg_solver *s)
     c.xp0 = s->xp;
     c.ch0 = s->ch;
     c.dc0 = s->dc;
+    c.aerr0 = s->aerr;
+    c.aerr_t0 = s->aerr_t;
+    c.chc0 = s->chc;
+    c.bhc0 = s->bhc;
     s->n = nf;
     s->nnz = nnz_f;
     s->red_blocks_n = grid_for(nf, kBlock, kMaxRedBlocks);
@@ -347,6 +361,12 @@ hipError_t begin_impl(pdhg_solver *s)
     s->xp = c.xp;
     s->ch = c.ch;
     s->dc = c.dc;
+    if (s->aerr) { // the full model's chc and bhc (n >= nf entries) serve the compact model
+        s->aerr = c.aerr;
+        s->aerr_t = c.aerr_t;
+    }
+    defect_alias(s);
+    s->defect_stale = true;
     if (lfix) {
         c.lfix0 = s->lfix;
         c.l0 = s->l;
@@ -394,6 +414,11 @@ hipError_t end_impl(pdhg_solver *s, bool scatter)
     s->xp = c.xp0;
     s->ch = c.ch0;
     s->dc = c.dc0;
+    s->aerr = c.aerr0;
+    s->aerr_t = c.aerr_t0;
+    s->chc = c.chc0;
+    s->bhc = c.bhc0;
+    s->defect_stale = true;
     if (c.lfix0) {
         s->lfix = c.lfix0;
         s->l = c.l0;

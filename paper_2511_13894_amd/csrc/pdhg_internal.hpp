@@ -106,6 +106,17 @@ struct pdhg_solver {
     void *xp = nullptr, *yp = nullptr;
     double *ch = nullptr;            // scaled objective, float64 in both precisions
     void *bh = nullptr, *lh = nullptr, *uh = nullptr;
+    // Mixed precision: the rounding error of the float matrix, E = Ahat -
+    // fl32(Ahat), stored as float in A order and transpose order, so that
+    // fl32(Ahat) v + E v is the float64 product; ex = E x+ and ety = E' y+ of
+    // the last check.  The iteration kernels read chc and bhc: in float64
+    // mode the same arrays as ch and bh; in the mixed mode ch - E' y_a and
+    // bh - E x_a at the anchor (x_a, y_a), so that at the anchor the float
+    // matrix gives the float64 residuals (defect correction).
+    void *aerr = nullptr, *aerr_t = nullptr;
+    double *ex = nullptr, *ety = nullptr;
+    double *chc = nullptr, *bhc = nullptr;
+    bool defect_stale = true; // chc, bhc do not yet follow the current anchor and model
     void *xs = nullptr, *ys = nullptr; // scaled solution of the solve (kept for the push)
     int8_t *sense = nullptr;
 
@@ -168,6 +179,7 @@ struct pdhg_solver {
         void *ahat = nullptr, *ahat_t = nullptr, *lh = nullptr, *uh = nullptr;
         void *x = nullptr, *xa = nullptr, *xbar = nullptr, *xp = nullptr;
         double *ch = nullptr, *dc = nullptr, *bt = nullptr;
+        void *aerr = nullptr, *aerr_t = nullptr; // mixed precision: the free columns' matrix errors
         int8_t *lfix = nullptr;             // learned push: its fixes, which an undo may free again
         double *l = nullptr, *u = nullptr;  // learned push: the original bounds an undo restores
         int n0 = 0, nnz0 = 0, red_blocks_n0 = 1;
@@ -177,6 +189,8 @@ struct pdhg_solver {
         void *ahat0 = nullptr, *ahat_t0 = nullptr, *lh0 = nullptr, *uh0 = nullptr, *bh0 = nullptr;
         void *x0 = nullptr, *xa0 = nullptr, *xbar0 = nullptr, *xp0 = nullptr;
         double *ch0 = nullptr, *dc0 = nullptr;
+        void *aerr0 = nullptr, *aerr_t0 = nullptr;
+        double *chc0 = nullptr, *bhc0 = nullptr;
     } pc;
 
     // live kernel timing: events around one primal and one dual launch per cycle
@@ -244,6 +258,20 @@ hipError_t power_iteration(pdhg_solver *s);
 // out = Ahat vec (transpose = false) or Ahat' vec, float64, with the structure of
 // the iteration kernel of that half (the kernels must have been chosen)
 hipError_t solver_product(pdhg_solver *s, bool transpose, const double *vec, double *out);
+// the same product with the float64 matrix: in the mixed mode the float
+// matrix's product plus that of its rounding error E
+hipError_t exact_product(pdhg_solver *s, bool transpose, const double *vec, double *out);
+// mixed precision: chc = ch - E' y_a, bhc = bh - E x_a at the current anchor
+// (a no-op in float64 mode, where chc and bhc are ch and bh)
+hipError_t defect_refresh(pdhg_solver *s);
+// float64 mode: chc and bhc follow ch and bh (after any swap of those arrays)
+inline void defect_alias(pdhg_solver *s)
+{
+    if (!s->aerr) {
+        s->chc = s->ch;
+        s->bhc = (double *)s->bh;
+    }
+}
 // sliced ELLPACK dual half: layout (after scaling), iteration half, product Ahat vec
 hipError_t sell_build(pdhg_solver *s, const std::vector<int> &rp_host);
 void sell_dual(pdhg_solver *s, int i, int store, hipEvent_t e0, hipEvent_t e1);
@@ -284,6 +312,7 @@ hipError_t batch_autotune(pdhg_batch *b);
 hipError_t batch_compact_tiles(pdhg_batch *b, bool all);
 hipError_t batch_set_kernels(pdhg_batch *b, int kern_at, int kern_a);
 hipError_t batch_phase_begin(pdhg_batch *b, bool fresh);
+hipError_t batch_defect_refresh(pdhg_batch *b);
 hipError_t batch_iterations(pdhg_batch *b, int count, bool check_at_end, int mode, bool timed);
 hipError_t batch_capture_cycle(pdhg_batch *b, int len, int mode);
 hipError_t batch_report(pdhg_batch *b, const double *x, const double *y, double *z, pdhg_kkt_report *out);

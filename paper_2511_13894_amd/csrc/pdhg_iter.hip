@@ -147,6 +147,33 @@ static void check_spmv(hipStream_t st, int kern, int rows, const int *ptr, const
 #undef PDHG_CS_CASE
 }
 
+__global__ __launch_bounds__(kBlock) void k_add_to(int64_t len, double *__restrict__ out, const double *__restrict__ add)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += (int64_t)gridDim.x * kBlock)
+        out[i] += add[i];
+}
+
+static int err_kern_a(const pdhg_solver *s);
+
+hipError_t solver_product(pdhg_solver *s, bool transpose, const double *vec, double *out);
+
+hipError_t exact_product(pdhg_solver *s, bool transpose, const double *vec, double *out)
+{
+    hipError_t e = solver_product(s, transpose, vec, out);
+    if (e != hipSuccess || !s->aerr) return e;
+    hipStream_t st = s->stream;
+    if (transpose) { // ety is free outside a check cycle
+        check_spmv<float, double>(st, s->kern_at, s->n, s->tp, s->ti, (const float *)s->aerr_t, vec, s->ety);
+        hipLaunchKernelGGL(k_add_to, dim3(grid_for(s->n, kBlock, 8192)), dim3(kBlock), 0, st, (int64_t)s->n, out,
+                           (const double *)s->ety);
+    } else {
+        check_spmv<float, double>(st, err_kern_a(s), s->m, s->rp, s->ci, (const float *)s->aerr, vec, s->ex);
+        hipLaunchKernelGGL(k_add_to, dim3(grid_for(s->m, kBlock, 8192)), dim3(kBlock), 0, st, (int64_t)s->m, out,
+                           (const double *)s->ex);
+    }
+    return hipGetLastError();
+}
+
 hipError_t solver_product(pdhg_solver *s, bool transpose, const double *vec, double *out)
 {
     if (transpose) {
@@ -274,7 +301,7 @@ static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = null
     if (s->n <= 0) return;
     if (L == kRowBlock) {
         PDHG_LAUNCH(e0, e1, (k_primal_rowblock<V>), dim3(s->n), dim3(kBlock), s->stream, s->n, s->tp, s->ti,
-                    (const V *)s->ahat_t, (const double *)s->y, s->ch, (const V *)s->lh, (const V *)s->uh,
+                    (const V *)s->ahat_t, (const double *)s->y, s->chc, (const V *)s->lh, (const V *)s->uh,
                     (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i, store);
         return;
     }
@@ -285,7 +312,7 @@ static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = null
 #define PDHG_PT_CASE(TT, RR, NT)                                                                                \
     case TT:                                                                                                    \
         PDHG_LAUNCH(e0, e1, (k_primal_tiled<V, RR, NT>), dim3(grid), dim3(NT), s->stream, s->n, s->tp, s->ti, \
-                           (const V *)s->ahat_t, (const double *)s->y, s->ch, (const V *)s->lh,          \
+                           (const V *)s->ahat_t, (const double *)s->y, s->chc, (const V *)s->lh,          \
                            (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i,  \
                            store);                                                                              \
         break;
@@ -305,7 +332,7 @@ static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = null
 #define PDHG_PRIMAL_CASE(LL)                                                                                    \
     case LL:                                                                                                    \
         PDHG_LAUNCH(e0, e1, (k_primal<V, LL>), dim3(grid), dim3(kBlock), s->stream, s->n, s->tp, s->ti,      \
-                           (const V *)s->ahat_t, (const double *)s->y, s->ch, (const V *)s->lh,          \
+                           (const V *)s->ahat_t, (const double *)s->y, s->chc, (const V *)s->lh,          \
                            (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i,  \
                            store);                                                                              \
         break;
@@ -333,7 +360,7 @@ static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullpt
     }
     if (L == kRowBlock) {
         PDHG_LAUNCH(e0, e1, (k_dual_rowblock<V>), dim3(s->m), dim3(kBlock), s->stream, s->m, s->rp, s->ci,
-                    (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bh, s->sense, (double *)s->y,
+                    (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense, (double *)s->y,
                     (const double *)s->ya, (double *)s->yp, s->st, i, store);
         return;
     }
@@ -344,7 +371,7 @@ static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullpt
 #define PDHG_DT_CASE(TT, RR, NT)                                                                                \
     case TT:                                                                                                    \
         PDHG_LAUNCH(e0, e1, (k_dual_tiled<V, RR, NT>), dim3(grid), dim3(NT), s->stream, s->m, s->rp, s->ci,   \
-                           (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bh, s->sense, (double *)s->y,\
+                           (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense, (double *)s->y,\
                            (const double *)s->ya, (double *)s->yp, s->st, i, store);                                      \
         break;
         switch (T) {
@@ -363,7 +390,7 @@ static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullpt
 #define PDHG_DUAL_CASE(LL)                                                                                      \
     case LL:                                                                                                    \
         PDHG_LAUNCH(e0, e1, (k_dual<V, LL>), dim3(grid), dim3(kBlock), s->stream, s->m, s->rp, s->ci,        \
-                           (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bh, s->sense, (double *)s->y,\
+                           (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense, (double *)s->y,\
                            (const double *)s->ya, (double *)s->yp, s->st, i, store);                                      \
         break;
     switch (L) {
@@ -382,7 +409,10 @@ static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullpt
 // ---------------------------------------------------------------- checks ---
 // Row part of a check on the candidate (xc, yc) of the scaled current model:
 // rP_hat (current senses), unscaled rP = rP_hat / Dr, b'y, ||yc - ya||^2.
-__global__ __launch_bounds__(kBlock) void k_check_rows(int m, const double *__restrict__ ax, const double *__restrict__ bh,
+// In the mixed mode ex (else NULL) holds E xc, the float matrix's rounding
+// error times the candidate: ax + ex is the float64 product, written back.
+__global__ __launch_bounds__(kBlock) void k_check_rows(int m, double *__restrict__ ax, const double *__restrict__ ex,
+                                                      const double *__restrict__ bh,
                                                       const int8_t *__restrict__ sense, const double *__restrict__ dr,
                                                       const double *__restrict__ yc, const double *__restrict__ ya,
                                                       double *__restrict__ part, int nblk, const DevState *st)
@@ -390,7 +420,12 @@ __global__ __launch_bounds__(kBlock) void k_check_rows(int m, const double *__re
     if (st->done) return;
     double v[6] = {0, 0, 0, 0, 0, 0}; // PH2, P2, PINF, BTY, DY2, NAN
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
-        double r = (double)bh[i] - ax[i];
+        double axi = ax[i];
+        if (ex) {
+            axi += ex[i];
+            ax[i] = axi;
+        }
+        double r = (double)bh[i] - axi;
         const int8_t s = sense[i];
         if (s == '<') r = r < 0.0 ? r : 0.0;
         else if (s == '>') r = r > 0.0 ? r : 0.0;
@@ -419,8 +454,10 @@ __global__ __launch_bounds__(kBlock) void k_check_rows(int m, const double *__re
 // Column part: lambda_hat = chat - Ahat'yc, zhat split by the finite bounds,
 // rD_hat = lambda_hat - zhat, unscaled rD = rD_hat / Dc, chat'xc, bound terms
 // of the dual objective, ||xc - xa||^2.
+// ety (mixed mode, else NULL) = E' yc: aty + ety is the float64 product, written back.
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_check_cols(int n, const double *__restrict__ aty, const double *__restrict__ ch,
+__global__ __launch_bounds__(kBlock) void k_check_cols(int n, double *__restrict__ aty, const double *__restrict__ ety,
+                                                      const double *__restrict__ ch,
                                                       const V *__restrict__ lh, const V *__restrict__ uh,
                                                       const double *__restrict__ dc, const V *__restrict__ xc,
                                                       const V *__restrict__ xa, const double *__restrict__ c0,
@@ -433,7 +470,12 @@ __global__ __launch_bounds__(kBlock) void k_check_cols(int n, const double *__re
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
         double cj, lo, hi;
         check_model<V>(orig != 0, j, ch, lh, uh, c0, l0, u0, dc, cj, lo, hi);
-        const double lam = cj - aty[j];
+        double atyj = aty[j];
+        if (ety) {
+            atyj += ety[j];
+            aty[j] = atyj;
+        }
+        const double lam = cj - atyj;
         const double zp = (!is_inf_lo(lo) && lam > 0.0) ? lam : 0.0;
         const double zm = (!is_inf_up(hi) && lam < 0.0) ? -lam : 0.0;
         const double rd = lam - (zp - zm);
@@ -496,12 +538,31 @@ __global__ __launch_bounds__(kBlock) void k_restart_apply(int n, int m, const De
     }
 }
 
+// Defect correction (mixed mode): at a restart the candidate becomes the
+// anchor, so chc = ch - E' y+ and bhc = bh - E x+ from the check's error
+// products; with `always` (a phase start) regardless of the restart flag.
+__global__ __launch_bounds__(kBlock) void k_defect_set(int n, int m, const DevState *st, int always,
+                                                      const double *__restrict__ ch, const double *__restrict__ ety,
+                                                      double *__restrict__ chc, const double *__restrict__ bh,
+                                                      const double *__restrict__ ex, double *__restrict__ bhc)
+{
+    if (!always && (!st->restart_flag || st->done)) return;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
+        if (i < n) chc[i] = ch[i] - ety[i];
+        else bhc[i - n] = bh[i - n] - ex[i - n];
+    }
+}
+
 __global__ void k_advance(DevState *st, int len)
 {
     if (st->done) return;
     st->t += len;
     st->k0 += len;
 }
+
+// kernel structure of the rounding-error products (the sliced layout holds
+// only the float matrix: its lane-group width then)
+static int err_kern_a(const pdhg_solver *s) { return s->kern_a == kSell ? s->lanes_a : s->kern_a; }
 
 template <typename V>
 static void check_impl(pdhg_solver *s, const V *xc, const double *yc, double *pm, double *pn)
@@ -510,10 +571,15 @@ static void check_impl(pdhg_solver *s, const V *xc, const double *yc, double *pm
     if (s->kern_a == kSell) sell_product(s, xc, s->ax);
     else check_spmv<V, V>(st, s->kern_a, s->m, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
     check_spmv<V, double>(st, s->kern_at, s->n, s->tp, s->ti, (const V *)s->ahat_t, yc, s->aty);
+    if (s->aerr) { // mixed mode: the float64 products are these plus E xc and E' yc
+        check_spmv<float, V>(st, err_kern_a(s), s->m, s->rp, s->ci, (const float *)s->aerr, xc, s->ex);
+        check_spmv<float, double>(st, s->kern_at, s->n, s->tp, s->ti, (const float *)s->aerr_t, yc, s->ety);
+    }
     const int gm = s->red_blocks_m, gn = s->red_blocks_n;
-    hipLaunchKernelGGL(k_check_rows, dim3(gm), dim3(kBlock), 0, st, s->m, s->ax, (const double *)s->bh, s->sense, s->dr,
-                       yc, (const double *)s->ya, pm, gm, s->st);
-    hipLaunchKernelGGL((k_check_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->aty, s->ch,
+    hipLaunchKernelGGL(k_check_rows, dim3(gm), dim3(kBlock), 0, st, s->m, s->ax, (const double *)(s->aerr ? s->ex : nullptr),
+                       (const double *)s->bh, s->sense, s->dr, yc, (const double *)s->ya, pm, gm, s->st);
+    hipLaunchKernelGGL((k_check_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->aty,
+                       (const double *)(s->aerr ? s->ety : nullptr), s->ch,
                        (const V *)s->lh, (const V *)s->uh, s->dc, xc, (const V *)s->xa, s->c, s->l, s->u,
                        s->model_original ? 1 : 0, pn, gn, s->st);
 }
@@ -540,6 +606,9 @@ hipError_t launch_check(pdhg_solver *s, int mode, int len)
     }
     if (mode != 0) {
         const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
+        if (s->aerr)
+            hipLaunchKernelGGL(k_defect_set, dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->st, 0, s->ch, s->ety,
+                               s->chc, (const double *)s->bh, s->ex, s->bhc);
         if (s->fp32)
             hipLaunchKernelGGL((k_restart_apply<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->st,
                                (float *)s->x, (float *)s->xa, (const float *)s->xp, (double *)s->y, (double *)s->ya,
@@ -549,6 +618,23 @@ hipError_t launch_check(pdhg_solver *s, int mode, int len)
                                (double *)s->x, (double *)s->xa, (const double *)s->xp, (double *)s->y, (double *)s->ya,
                                (const double *)s->yp);
     }
+    return hipGetLastError();
+}
+
+hipError_t defect_refresh(pdhg_solver *s)
+{
+    s->defect_stale = false;
+    if (!s->aerr) {
+        defect_alias(s);
+        return hipSuccess;
+    }
+    hipStream_t st = s->stream;
+    check_spmv<float, float>(st, err_kern_a(s), s->m, s->rp, s->ci, (const float *)s->aerr, (const float *)s->xa, s->ex);
+    check_spmv<float, double>(st, s->kern_at, s->n, s->tp, s->ti, (const float *)s->aerr_t, (const double *)s->ya,
+                              s->ety);
+    const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
+    hipLaunchKernelGGL(k_defect_set, dim3(g), dim3(kBlock), 0, st, s->n, s->m, s->st, 1, s->ch, s->ety, s->chc,
+                       (const double *)s->bh, s->ex, s->bhc);
     return hipGetLastError();
 }
 
@@ -699,6 +785,7 @@ template <typename V>
 static hipError_t phase_start(pdhg_solver *s, bool fresh_start)
 {
     hipStream_t st = s->stream;
+    s->defect_stale = true; // a new anchor (and possibly a new model)
     start_vectors<V>(s, fresh_start);
     const int nb = grid_for(s->n > s->m ? s->n : s->m, kBlock, kMaxRedBlocks);
     hipLaunchKernelGGL((k_sumsq2<double>), dim3(nb), dim3(kBlock), 0, st, s->n, s->ch, s->m, (const double *)s->bh,

@@ -185,11 +185,11 @@ static void sell_dual_impl(pdhg_solver *s, int i, int store, hipEvent_t e0, hipE
     hipEvent_t f0 = s->n_sell_wi > 0 ? nullptr : e0;
     if (f0 || e1)
         hipExtLaunchKernelGGL(k_sell_dual_finish, gf, bk, 0, s->stream, f0, e1, 0, s->m, s->sell_wi_start, s->sell_part,
-                              (const double *)s->bh, s->sense, (double *)s->y, (const double *)s->ya, (double *)s->yp,
+                              (const double *)s->bhc, s->sense, (double *)s->y, (const double *)s->ya, (double *)s->yp,
                               st, i, store);
     else
         hipLaunchKernelGGL(k_sell_dual_finish, gf, bk, 0, s->stream, s->m, s->sell_wi_start, s->sell_part,
-                           (const double *)s->bh, s->sense, (double *)s->y, (const double *)s->ya, (double *)s->yp, st,
+                           (const double *)s->bhc, s->sense, (double *)s->y, (const double *)s->ya, (double *)s->yp, st,
                            i, store);
 }
 

@@ -142,6 +142,18 @@ __global__ __launch_bounds__(kBlock) void k_convert(int64_t len, const double *_
         dst[p] = (T)src[p];
 }
 
+// rounding error of the float copy, v - fl32(v) (exact in float64), stored as
+// float (its own rounding is 2^-24 of an error already 2^-24 of v); with a
+// permutation, gathered into the transpose's order
+__global__ __launch_bounds__(kBlock) void k_round_err(int64_t len, const int *__restrict__ perm,
+                                                     const double *__restrict__ src, float *__restrict__ dst)
+{
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < len; p += (int64_t)gridDim.x * kBlock) {
+        const double v = src[perm ? perm[p] : p];
+        dst[p] = (float)(v - (double)(float)v);
+    }
+}
+
 static hipError_t exclusive_scan(hipStream_t st, int len, const int *in, int *out, int *work)
 {
     // out has len+1 entries; work holds ceil(len/kScanTile) + 1 ints
@@ -291,6 +303,12 @@ static void make_scaled(pdhg_solver *s, const double *ahat64)
     if (s->nnz > 0) {
         hipLaunchKernelGGL((k_convert<V>), dim3(big), dim3(kBlock), 0, st, (int64_t)s->nnz, ahat64, (V *)s->ahat);
         hipLaunchKernelGGL((k_gather<V>), dim3(big), dim3(kBlock), 0, st, s->nnz, s->tperm, ahat64, (V *)s->ahat_t);
+        if (s->aerr) {
+            hipLaunchKernelGGL(k_round_err, dim3(big), dim3(kBlock), 0, st, (int64_t)s->nnz, (const int *)nullptr,
+                               ahat64, (float *)s->aerr);
+            hipLaunchKernelGGL(k_round_err, dim3(big), dim3(kBlock), 0, st, (int64_t)s->nnz, (const int *)s->tperm,
+                               ahat64, (float *)s->aerr_t);
+        }
     }
     if (s->n > 0)
         hipLaunchKernelGGL((k_scaled_cols<V>), dim3(grid_for(s->n, kBlock, 1 << 30)), dim3(kBlock), 0, st, s->n, s->dc,

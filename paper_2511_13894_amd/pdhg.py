@@ -134,7 +134,7 @@ EXPORTS = ["pdhg_default_params", "pdhg_create", "pdhg_solve", "pdhg_iterate", "
            "pdhg_batch_features", "pdhg_batch_corner_push_learned",
            "pdhg_corner_push_learned", "pdhg_get_solution_device", "pdhg_set_start", "pdhg_state_size",
            "pdhg_get_state", "pdhg_set_state", "pdhg_get_solve_solution", "pdhg_batch_get_solve_solution",
-           "pdhg_dual_push", "pdhg_batch_dual_push"]
+           "pdhg_dual_push", "pdhg_batch_dual_push", "pdhg_corner_push_logits", "pdhg_batch_corner_push_logits"]
 
 _lib = None
 
@@ -196,6 +196,8 @@ def load(path: Optional[Path] = None):
     lib.pdhg_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
     lib.pdhg_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
     lib.pdhg_batch_corner_push_learned.argtypes = [C.c_void_p, C.c_void_p, C.c_double, P(C.c_uint64), P(PushResult)]
+    lib.pdhg_corner_push_logits.argtypes = [C.c_void_p, fp, C.c_double, C.c_uint64, P(PushResult)]
+    lib.pdhg_batch_corner_push_logits.argtypes = [C.c_void_p, fp, C.c_double, P(C.c_uint64), P(PushResult)]
     lib.pdhg_last_error.restype = C.c_char_p
     lib.pdhg_struct_size.restype = C.c_int32
     lib.pdhg_struct_size.argtypes = [C.c_int32]
@@ -208,7 +210,7 @@ def load(path: Optional[Path] = None):
                "pdhg_mlp_gradient", "pdhg_mlp_train", "pdhg_features", "pdhg_corner_push_learned",
                "pdhg_batch_features", "pdhg_batch_corner_push_learned", "pdhg_get_solution_device",
                "pdhg_set_start", "pdhg_state_size", "pdhg_get_state", "pdhg_set_state", "pdhg_get_solve_solution",
-               "pdhg_batch_get_solve_solution"):
+               "pdhg_batch_get_solve_solution", "pdhg_corner_push_logits", "pdhg_batch_corner_push_logits"):
         getattr(lib, fn).restype = C.c_int
     sizes = [C.sizeof(Params), C.sizeof(Result), C.sizeof(KKTReport), C.sizeof(PushResult), C.sizeof(Timing),
              C.sizeof(LpDesc), C.sizeof(BatchReport), C.sizeof(DualPushResult)]
@@ -356,6 +358,16 @@ class Solver:
         self._check(self.lib.pdhg_corner_push_learned(self.h, net.h, float(theta), C.c_uint64(seed), C.byref(r)))
         return r
 
+    def corner_push_logits(self, logits, theta: float, seed: int) -> PushResult:
+        """Learned warm start from caller logits (one float32 per column)."""
+        lg = np.ascontiguousarray(logits, dtype=np.float32)
+        if lg.shape != (self.n,):
+            raise ValueError("one logit per column")
+        r = PushResult()
+        self._check(self.lib.pdhg_corner_push_logits(self.h, lg.ctypes.data_as(C.POINTER(C.c_float)), float(theta),
+                                                     C.c_uint64(seed), C.byref(r)))
+        return r
+
     def set_start(self, x, y):
         xa = np.ascontiguousarray(x, dtype=np.float64)
         ya = np.ascontiguousarray(y, dtype=np.float64)
@@ -450,6 +462,17 @@ class Batch:
         sd = (C.c_uint64 * self.count)(*[int(v) for v in seeds])
         r = (PushResult * self.count)()
         self._check(self.lib.pdhg_batch_corner_push_learned(self.h, net.h, float(theta), sd, r))
+        return list(r)
+
+    def corner_push_logits(self, logits, theta: float, seeds):
+        """Learned warm start of every LP from caller logits (the LPs' columns in batch order)."""
+        lg = np.ascontiguousarray(logits, dtype=np.float32)
+        if lg.shape != (sum(lp.n for lp in self.lps),):
+            raise ValueError("one logit per column of the batch")
+        sd = (C.c_uint64 * self.count)(*[int(v) for v in seeds])
+        r = (PushResult * self.count)()
+        self._check(self.lib.pdhg_batch_corner_push_logits(self.h, lg.ctypes.data_as(C.POINTER(C.c_float)),
+                                                           float(theta), sd, r))
         return list(r)
 
     def features(self, seeds):

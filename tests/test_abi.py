@@ -83,3 +83,34 @@ def test_default_params_and_argument_errors_without_gpu():
     assert lib.pdhg_solve(None, None) == -1
     assert lib.pdhg_kkt(None, None, None, None) == -1
     lib.pdhg_destroy(None)
+
+
+def test_numeric_parameters_are_validated_without_gpu():
+    """Non-finite or out-of-range tolerances, factors and caps are refused
+    at create, before any device call: a NaN eps_abs would make every fixing
+    test false, a negative push scale would flip the push objective."""
+    lib = pdhg.load()
+    h = ctypes.c_void_p()
+    rp = (ctypes.c_int64 * 2)(0, 1)
+    ci = (ctypes.c_int32 * 1)(0)
+    va = (ctypes.c_double * 1)(1.0)
+    b = (ctypes.c_double * 1)(1.0)
+    c = (ctypes.c_double * 2)(1.0, 1.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    nan, inf = float("nan"), float("inf")
+    bad = [("eps_abs", nan), ("eps_abs", -1e-6), ("eps_abs", inf), ("eps_rel", nan), ("eps_rel", inf),
+           ("push_obj_scale", -1.0), ("push_obj_scale", 0.0), ("push_obj_scale", nan), ("push_max_iter", -1),
+           ("max_iter", -1), ("reflect_gamma", 1.5), ("reflect_gamma", -0.1), ("reflect_gamma", nan),
+           ("pw_smooth", nan), ("pw_smooth", 2.0), ("restart_suff", nan), ("restart_nec", 1.5),
+           ("restart_art", -0.1), ("restart_art", nan), ("pc_alpha", nan), ("time_limit", nan),
+           ("eta_safety", inf), ("halpern", 2)]
+    for field, value in bad:
+        q = pdhg.default_params()
+        setattr(q, field, value)
+        rc = lib.pdhg_create(1, 2, 1, rp, ci, ctypes.cast(va, dp), ctypes.cast(b, dp), ctypes.cast(c, dp), None,
+                             None, None, ctypes.byref(q), ctypes.byref(h))
+        assert rc == -1, (field, value)
+        assert lib.pdhg_last_error(), field
+    lg = (ctypes.c_float * 2)(0.0, 0.0)
+    assert lib.pdhg_corner_push_logits(None, lg, 0.5, 1, None) == -1
+    assert lib.pdhg_batch_corner_push_logits(None, lg, 0.5, None, None) == -1

@@ -105,10 +105,9 @@ def test_c1_setup_iterates_solve_and_push(c1):
     assert abs(r.pobj - gs["pobj"]) <= 1e-9 * abs(gs["pobj"])
     assert (p.n_fix_lower, p.n_fix_upper, p.n_rows_to_eq) == (gp["n_fix_lower"], gp["n_fix_upper"], gp["n_rows_to_eq"])
     assert (p.before.p_off, p.before.candidates) == (gp["p_off_before"], gp["candidates_before"])
-    assert p.status == gp["status"] and abs(p.iters - gp["iters"]) <= 64
-    if p.iters == gp["iters"]:
-        assert (p.after.p_off, p.after.candidates, p.after.est_primal) == \
-            (gp["p_off_after"], gp["candidates_after"], gp["est_primal_after"])
+    assert p.status == gp["status"] and p.iters == gp["iters"]
+    assert (p.after.p_off, p.after.candidates, p.after.est_primal) == \
+        (gp["p_off_after"], gp["candidates_after"], gp["est_primal_after"])
     # crossover's order: the dual push from the pushed x, against the oracle's continuation of its run
     d = g.dual_push(1)
     gd = gold["dual_push_after_push"]
@@ -120,12 +119,10 @@ def test_c1_setup_iterates_solve_and_push(c1):
           flush=True)
     assert d.status == gd["status"] == pdhg.PDHG_PUSH_DONE and d.rel_d_push <= 1e-6
     assert (d.after.d_zero, d.after.est_dual) == (kd.d_zero, kd.est_dual)
-    if p.iters == gp["iters"]:
-        assert (d.n_cols_free, d.n_rows_fixed) == (gd["n_cols_free"], gd["n_rows_fixed"])
-        assert (d.before.d_zero, d.before.est_dual) == (gd["d_zero_before"], gd["est_dual_before"])
-        assert abs(d.iters - gd["iters"]) <= 64
-        if d.iters == gd["iters"]:
-            assert (d.after.d_zero, d.after.est_dual) == (gd["d_zero_after"], gd["est_dual_after"])
+    assert (d.n_cols_free, d.n_rows_fixed) == (gd["n_cols_free"], gd["n_rows_fixed"])
+    assert (d.before.d_zero, d.before.est_dual) == (gd["d_zero_before"], gd["est_dual_before"])
+    assert d.iters == gd["iters"]
+    assert (d.after.d_zero, d.after.est_dual) == (gd["d_zero_after"], gd["est_dual_after"])
 
 
 def test_c5_solve_and_dual_push_against_the_oracle_full_run():
@@ -165,9 +162,8 @@ def test_c5_solve_and_dual_push_against_the_oracle_full_run():
     assert (p.after.d_zero, p.after.est_dual) == (ka.d_zero, ka.est_dual)
     assert ka.rel_d <= 2e-6
     assert p.before.est_dual == gd["est_dual_before"]
-    assert abs(p.iters - gd["iters"]) <= 64
-    if p.iters == gd["iters"]:
-        assert p.after.est_dual == gd["est_dual_after"]
+    assert p.iters == gd["iters"]
+    assert p.after.est_dual == gd["est_dual_after"]
 
 
 def test_c2_setup_iterates_and_solve(c2):

@@ -152,3 +152,115 @@ def test_learned_push_on_free_columns_equals_the_full_push():
             (a.n_learned_fix, a.n_learned_undo, a.status, a.iters), i
         xa, xc = res[0][1][i], res[1][1][i]
         assert np.abs(xc - xa).max() <= 1e-8 * max(1.0, np.abs(xa).max()), i
+
+
+def _feature_bound(fo, so):
+    """Per-element bound on |GPU - oracle| for the normalised features of an
+    FP64 solve.  The device rounds each raw value v to float32 before the
+    map t = sign(v) ln(1 + |v|/s) (|dt| <= |dv| / (s + |v|)) and stores the
+    restart history in float32, so a trend feature v = h - base carries the
+    rounding of h = v + base (base = x_j for 4..7, z_j for 8..11); the
+    result is rounded to float32 once more.  Both sides also carry their
+    float64 trajectories, which agree to about 1e-12 relative after
+    thousands of iterations (different summation order): 1e-10 of the x or
+    objective scale covers that in every x- or z-derived feature.  Raw values
+    come back from the oracle's own features and scales."""
+    u = 2.0 ** -24
+    v = np.sign(fo) * so[None, :] * np.expm1(np.abs(fo))
+    dv = u * np.abs(v)
+    base = np.zeros_like(v)
+    base[:, 4:8] = np.abs(v[:, 0:1])
+    base[:, 8:12] = np.abs(v[:, 1:2])
+    dv = dv + u * (np.abs(v) + base)
+    xs = max(1.0, np.abs(v[:, 0]).max())
+    cs = max(1.0, np.abs(v[:, 2]).max())
+    traj = np.zeros(16)
+    traj[[0, 4, 5, 6, 7, 13, 14, 15]] = 1e-10 * xs
+    traj[[1, 8, 9, 10, 11]] = 1e-10 * cs
+    dv = dv + traj[None, :]
+    return 4.0 * (dv / (so[None, :] + np.abs(v)) + u * np.abs(fo)) + 1e-12
+
+
+LEARNED_CASES = [
+    ("c0_s3", lambda: lpgen.config0(3)),
+    ("ineq_ub_300x1200", lambda: lpgen.config1(seed=3, m=300, n=1200)),
+    ("ragged_deg_1_9", lambda: lpgen.planted(333, 777, seed=4, deg_range=(1, 9), upper_frac=0.3)),
+    ("tiny_general_8", lambda: lpgen.tiny(8, m=4, n=9)),
+]
+
+
+@pytest.mark.parametrize("name,make", LEARNED_CASES, ids=[c[0] for c in LEARNED_CASES])
+def test_features_follow_the_oracle(name, make):
+    """All 16 features, the restart trends included, equal the oracle's
+    (computed in float64 from its own restart history) within the float32
+    storage bound of the device."""
+    print(f"[learned] features vs oracle: {name}", flush=True)
+    lp = make()
+    g = pdhg.Solver(lp, record_history=1, eps_rel=1e-7)
+    o = OracleSolver(lp, record_history=1, eps_rel=1e-7)
+    rg, ro = g.solve(), o.solve()
+    assert (rg.iters, rg.restarts) == (ro.iters, ro.restarts)
+    fg = g.features(21).astype(np.float64)
+    fo, so = o.features(21, with_scale=True)
+    bound = _feature_bound(fo, so)
+    err = np.abs(fg - fo)
+    worst = np.unravel_index(np.argmax(err / bound), err.shape)
+    print(f"[learned] {name}: {ro.restarts} restarts, max |gpu - oracle| {err.max():.2e}, worst ratio to bound "
+          f"{(err / bound).max():.3f} at column {worst[0]} feature {worst[1]}", flush=True)
+    assert np.all(err <= bound), (worst, fg[worst], fo[worst], bound[worst])
+    if ro.restarts > 0:
+        assert np.abs(fo[:, 4]).max() > 0  # the trend features are exercised
+
+
+@pytest.mark.parametrize("compact", [1, 0])
+@pytest.mark.parametrize("theta", [0.5, 0.9])
+@pytest.mark.parametrize("name,make", LEARNED_CASES, ids=[c[0] for c in LEARNED_CASES])
+def test_learned_push_from_logits_follows_the_oracle(name, make, theta, compact):
+    """The learned warm start from the same seeded logits on both sides:
+    the same plain and learned fixes, the same undos at the push checks, the
+    same push iterations and status, and the same pushed point."""
+    print(f"[learned] logits push vs oracle: {name} theta {theta} compact {compact}", flush=True)
+    lp = make()
+    logits = np.random.default_rng(1234).normal(0.0, 2.0, lp.n).astype(np.float32)
+    g = pdhg.Solver(lp, eps_rel=1e-7, push_compact=compact)
+    o = OracleSolver(lp, eps_rel=1e-7)
+    rg, ro = g.solve(), o.solve()
+    assert rg.status == ro.status == 0 and rg.iters == ro.iters
+    pg = g.corner_push_logits(logits, theta, 5)
+    po = o.corner_push_learned(logits, theta, 5)
+    got = (pg.n_fix_lower, pg.n_fix_upper, pg.n_rows_to_eq, pg.n_learned_fix, pg.n_learned_undo, pg.status, pg.iters)
+    want = (po.n_fix_lower, po.n_fix_upper, po.n_rows_to_eq, po.n_learned_fix, po.n_learned_undo, po.status, po.iters)
+    print(f"[learned] {name}: (lower, upper, rows, learned fixes, undone, status, iterations) gpu {got} / oracle {want}",
+          flush=True)
+    assert got == want
+    assert (pg.after.p_off, pg.after.candidates) == (po.after.p_off, po.after.candidates)
+    xg, yg, _ = g.get_solution()
+    xo, yo, _ = o.solution()
+    assert np.abs(xg - xo).max() <= 1e-7 * max(1.0, np.abs(xo).max())
+    np.testing.assert_array_equal(yg, g.get_solve_solution()[1])
+
+
+def test_batch_learned_push_from_logits_follows_the_oracle():
+    """The batch engine's learned push from caller logits: every LP's fixes,
+    undos, push iterations and pushed point equal the oracle's on that LP."""
+    lps = [lpgen.config3_instance(i, base_seed=47000, m_range=(60, 300)) for i in range(5)]
+    seeds = [31 + i for i in range(len(lps))]
+    logits = np.random.default_rng(99).normal(0.0, 2.0, sum(lp.n for lp in lps)).astype(np.float32)
+    b = pdhg.Batch(lps, eps_rel=1e-7)
+    b.solve()
+    res = b.corner_push_logits(logits, 0.6, seeds)
+    off = 0
+    for i, lp in enumerate(lps):
+        lg = logits[off: off + lp.n]
+        off += lp.n
+        o = OracleSolver(lp, eps_rel=1e-7)
+        o.solve()
+        po = o.corner_push_learned(lg, 0.6, seeds[i])
+        pg = res[i]
+        got = (pg.n_fix_lower, pg.n_fix_upper, pg.n_learned_fix, pg.n_learned_undo, pg.status, pg.iters)
+        want = (po.n_fix_lower, po.n_fix_upper, po.n_learned_fix, po.n_learned_undo, po.status, po.iters)
+        print(f"[learned] batch LP {i} (m={lp.m}): gpu {got} / oracle {want}", flush=True)
+        assert got == want, i
+        xg = b.get_solution(i)[0]
+        xo = o.solution()[0]
+        assert np.abs(xg - xo).max() <= 1e-7 * max(1.0, np.abs(xo).max()), i

@@ -1,6 +1,9 @@
 """BF16 MFMA fix-predictor kernels vs the CPU reference (same rounding
-points; the hardware's float32 accumulation order is the only difference,
-so a hidden activation can land one bfloat16 step away: tolerances below)."""
+points; the hardware's float32 accumulation order is the only difference).
+On these seeded inputs no hidden activation lands on the other side of a
+bfloat16 rounding boundary, so what remains is float32 accumulation order:
+a few ulps of float32 on a sum of 64 products (measured 5e-7 on the logits,
+1.3e-7 relative on the gradient); the bounds below allow 1e-5."""
 import numpy as np
 import pytest
 
@@ -30,8 +33,7 @@ def test_forward_matches_reference():
     zo, _ = M.forward(M.unflat(net.get_params()), f.astype(np.float64))
     err = np.abs(zg - zo)
     print(f"[mlp] forward: max |dz| {err.max():.2e}, mean {err.mean():.2e}", flush=True)
-    assert err.mean() <= 2e-3
-    assert np.all(err <= 3e-2 * (1 + np.abs(zo)))
+    assert np.all(err <= 1e-5 * (1 + np.abs(zo)))
 
 
 def test_gradient_matches_reference():
@@ -43,14 +45,16 @@ def test_gradient_matches_reference():
     g, loss = net.gradient(f, y, 2.0)
     lo, go, _ = M.loss_and_grad(q, f.astype(np.float64), y.astype(np.float64), 2.0)
     go = M.flat(go)
-    assert loss == pytest.approx(lo, rel=2e-3)
+    assert loss == pytest.approx(lo, rel=1e-5)
     rel = np.linalg.norm(g - go) / np.linalg.norm(go)
     print(f"[mlp] gradient: relative l2 error {rel:.2e}, loss gpu {loss:.6f} ref {lo:.6f}", flush=True)
-    assert rel <= 1e-2
+    assert rel <= 1e-5
     # each block of parameters separately
-    for k, sl in (("w1", slice(0, 1024)), ("w2", slice(1088, 5184)), ("w3", slice(5248, 5312))):
+    for k, sl in (("w1", slice(0, 1024)), ("b1", slice(1024, 1088)), ("w2", slice(1088, 5184)),
+                  ("b2", slice(5184, 5248)), ("w3", slice(5248, 5312)), ("b3", slice(5312, 5313))):
         r = np.linalg.norm(g[sl] - go[sl]) / max(np.linalg.norm(go[sl]), 1e-30)
-        assert r <= 2e-2, (k, r)
+        print(f"[mlp] gradient block {k}: relative l2 error {r:.2e}", flush=True)
+        assert r <= 1e-5, (k, r)
     assert np.all(g[0:1024].reshape(64, 16)[:, 12:] == 0)
 
 
@@ -79,8 +83,13 @@ def test_one_adam_step_matches_reference():
     q2 = M.adam_step(q, go, {}, lr=1e-3)
     moved_g = net.get_params() - M.flat(q)
     moved_o = M.flat(q2) - M.flat(q)
-    mask = np.abs(moved_o) > 1e-5
-    agree = np.mean(np.sign(moved_g[mask]) == np.sign(moved_o[mask]))
-    print(f"[mlp] adam step: sign agreement {agree:.4f} over {mask.sum()} parameters", flush=True)
-    assert agree > 0.97
-    np.testing.assert_allclose(moved_g[mask], moved_o[mask], rtol=0.2, atol=2e-4)
+    # the first Adam step moves a parameter by lr g / (|g| + eps): about lr
+    # sign(g) where |g| >> eps, and a sensitive function of g near eps, so
+    # the comparison takes the parameters whose gradient is well above eps
+    mask = np.abs(M.flat(go)) > 1e-6
+    dev = np.abs(moved_g[mask] - moved_o[mask])
+    print(f"[mlp] adam step: max deviation {dev.max():.2e} over {mask.sum()} parameters", flush=True)
+    assert mask.sum() > 4000
+    # both sides round the new float32 weight (|w| < 0.62 after the
+    # Kaiming-uniform init, one ulp <= 6e-8): two ulps of absolute slack
+    np.testing.assert_allclose(moved_g[mask], moved_o[mask], rtol=1e-4, atol=1.2e-7)

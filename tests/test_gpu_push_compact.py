@@ -55,17 +55,15 @@ def test_compact_push_matches_full_push_and_oracle(name, make):
         assert (p.n_fix_lower, p.n_fix_upper, p.n_rows_to_eq) == (po.n_fix_lower, po.n_fix_upper, po.n_rows_to_eq)
         assert p.status == po.status
         assert p.before.p_off == po.before.p_off
-    assert abs(p1.iters - p0.iters) <= 64 and abs(p1.iters - po.iters) <= 64
+    assert p1.iters == p0.iters and p1.iters == po.iters
     np.testing.assert_array_equal(y1, y0)  # the solve's y, returned by both
     if p1.status == pdhg.PDHG_PUSH_DONE:
         assert p1.after.rel_p <= eps * 1.0000001
-    if p1.iters == p0.iters:
-        assert rel_inf(x1, x0) <= 1e-8
-        assert (p1.after.p_off, p1.after.candidates) == (p0.after.p_off, p0.after.candidates)
-        # the last iterate too: fixed columns at their bound, free ones as in the full push
-        assert rel_inf(xi1, xi0) <= 1e-8 and rel_inf(yi1, yi0) <= 1e-8
-    if p1.iters == po.iters:
-        assert rel_inf(x1, xo) <= 1e-7
+    assert rel_inf(x1, x0) <= 1e-8
+    assert (p1.after.p_off, p1.after.candidates) == (p0.after.p_off, p0.after.candidates)
+    # the last iterate too: fixed columns at their bound, free ones as in the full push
+    assert rel_inf(xi1, xi0) <= 1e-8 and rel_inf(yi1, yi0) <= 1e-8
+    assert rel_inf(x1, xo) <= 1e-7
 
 
 def test_compact_push_fp32_and_timing_bytes():
@@ -85,7 +83,9 @@ def test_compact_push_fp32_and_timing_bytes():
           f"{ta1.bytes_primal} (compact) / {ta0.bytes_primal} (full)", flush=True)
     assert p1.status == p0.status
     assert (p1.n_fix_lower, p1.n_fix_upper) == (p0.n_fix_lower, p0.n_fix_upper)
-    assert abs(p1.iters - p0.iters) <= 64
+    # float32 rounds the two models differently (see the batch test below)
+    assert abs(p1.iters - p0.iters) <= max(256, p0.iters // 4)
+    assert p1.after.rel_p <= 1.0000001e-6 and p0.after.rel_p <= 1.0000001e-6
     assert ts1.bytes_primal == ts0.bytes_primal  # the solve is the same
     if p1.n_fix_lower + p1.n_fix_upper > 0 and ta1.samples > ts1.samples:
         assert ta1.bytes_primal < ta0.bytes_primal
@@ -118,7 +118,7 @@ def test_compact_batch_push_matches_full_batch_push_and_oracle():
             (po.n_fix_lower, po.n_fix_upper, po.n_rows_to_eq), i
         assert r1[i].status == r0[i].status == po.status, i
         assert r1[i].iters == r0[i].iters, (i, r1[i].iters, r0[i].iters)
-        assert abs(r1[i].iters - po.iters) <= 128, (i, r1[i].iters, po.iters)
+        assert r1[i].iters == po.iters, (i, r1[i].iters, po.iters)
         assert rel_inf(x1[i], x0[i]) <= 1e-8, i
         assert (r1[i].after.p_off, r1[i].after.candidates) == (r0[i].after.p_off, r0[i].after.candidates), i
 
@@ -170,9 +170,16 @@ def test_compact_batch_push_fp32():
         b = pdhg.Batch(lps, precision="fp32", eps_rel=1e-6, push_compact=compact)
         b.solve()
         res[compact] = (b.corner_push(seeds), [b.get_solution(i)[0] for i in range(len(lps))])
+    # In float32 the two models round differently: the full push multiplies
+    # the fixed columns by the float matrix every iteration (its defect
+    # correction refreshed at restarts), the compact push has them in btilde
+    # in float64 once.  The trajectories agree to float32 rounding, and a
+    # check's decision can fall either way: counts may differ by a few checks.
     for i in range(len(lps)):
         a, c = res[0][0][i], res[1][0][i]
+        print(f"[compact] fp32 batch LP {i}: push iterations {c.iters} (compact) / {a.iters} (full)", flush=True)
         assert (c.status, c.n_fix_lower, c.n_fix_upper) == (a.status, a.n_fix_lower, a.n_fix_upper), i
-        assert abs(c.iters - a.iters) <= 64, (i, c.iters, a.iters)
+        assert abs(c.iters - a.iters) <= max(256, a.iters // 4), (i, c.iters, a.iters)
+        assert c.after.rel_p <= 1.0000001e-6 and a.after.rel_p <= 1.0000001e-6, i
         if c.iters == a.iters:
             assert rel_inf(res[1][1][i], res[0][1][i]) <= 1e-5, i
