@@ -1,14 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark: one step = the whole hot path on one synthetic LP, on one GPU:
-pdhg_create (transpose, scaling, step size), pdhg_solve to the relative KKT
-tolerance, pdhg_corner_push (Algorithm 1 and its early stop).
+pdhg_create_device (ingest from HBM, transpose, scaling, step size),
+pdhg_solve to the relative KKT tolerance, pdhg_corner_push (Algorithm 1 and
+its early stop).  The default workload is the 2,000 x 5,000 transportation
+LP (10M columns) in the FP32-mixed mode.
 
 Prints ONE JSON line.  `value` is PDHG iterations per second over the timed
-steps (solve + push iterations / wall time, inputs already on the device side
-of pdhg_create's copies is NOT assumed: pdhg_create's host-to-device copy is
-inside the step).  The roofline object covers the dominant iteration kernel:
-algorithmic bytes per launch / mean launch duration measured live with HIP
-events on the solver's stream during the timed steps.
+steps (solve + push iterations / wall time), with the LP already in device
+memory when a step starts (it is copied there once, before the warm-up).
+The roofline object covers the dominant iteration kernel: algorithmic bytes
+per launch / mean launch duration measured live with HIP events on the
+solver's stream during the timed steps.  Outside the timed region: the
+learned-vs-plain comparison of the corner push and the CPU oracle's rate.
 """
 import argparse
 import hashlib
@@ -40,6 +43,10 @@ WORKLOADS = {
 }
 
 
+# oracle iterations timed for the CPU baseline (all cores, one thread): about
+# 10-20 s each on a 16-thread host (c2 and c4 hold 10M and 3.2M columns)
+CPU_ITERS = {"c0": (20000, 5000), "c1": (2000, 200), "c2": (200, 30), "c4": (400, 60), "c5": (2000, 200)}
+
 PUSH_WORDS = {"primal": "corner push", "dual": "dual corner push",
               "both": "corner push + dual corner push from its pushed x"}
 
@@ -58,11 +65,12 @@ def make_lp(cfg):
     return lpgen.config0(0)
 
 
-KERNEL_FILES = ("pdhg_iter.hip", "pdhg_device.hpp", "pdhg_kernels.hpp", "pdhg_internal.hpp")
-BATCH_KERNEL_FILES = KERNEL_FILES + ("pdhg_batch.hip",)  # the batch engine's kernels (kb_*) as well
+# Everything that shapes a profiled run: every library source and the input
+# generator.  A counter summary counts only while this hash is unchanged.
+SOURCE_FILES = tuple(sorted(os.listdir(os.path.join(ROOT, "paper_2511_13894_amd", "csrc")))) + ("../lpgen.py",)
 
 
-def kernel_source_hash(files=KERNEL_FILES):
+def kernel_source_hash(files=SOURCE_FILES):
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, "paper_2511_13894_amd", "csrc", f), "rb") as fh:
@@ -70,32 +78,74 @@ def kernel_source_hash(files=KERNEL_FILES):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(cfg, kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{cfg}_counters.txt")
+def traffic_from_profile(cfg, kernel, precision, push, push_compact):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this workload (config, precision, push mode, push on free columns), if
+    it was taken on the current sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{cfg}_{precision}_counters.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    m = re.search(r"kernel_source_hash:\s*(\w+)", txt)
-    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    files = BATCH_KERNEL_FILES if kernel.startswith("kb_") else KERNEL_FILES
-    if not m or not t or m.group(1) != kernel_source_hash(files):
+    fields = dict(re.findall(r"^(\w+):\s*(\S+)", txt, flags=re.M))
+    want = {"kernel_source_hash": kernel_source_hash(), "precision": precision, "push": push,
+            "push_compact": str(int(push_compact))}
+    if any(fields.get(k) != v for k, v in want.items()) or "hbm_bytes_per_launch" not in fields:
         return None
-    return float(t.group(1))
+    return float(fields["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(lp, iters, cfg):
-    """The CPU oracle as it stands, timed on this host: setup excluded,
-    `iters` PDHG iterations of the same LP in float64."""
-    from oracle import OracleSolver, num_threads
+def cpu_baseline(lp, iters, iters_one, cfg):
+    """The CPU oracle as it stands, timed on this host after its setup: `iters`
+    float64 PDHG iterations of the same LP on every core it uses, then
+    `iters_one` on one thread."""
+    from oracle import OracleSolver, num_threads, set_threads
 
     o = OracleSolver(lp, eps_rel=1e-30)
+    cores = num_threads()
     t0 = time.perf_counter()
     o.iterate(iters)
     dt = time.perf_counter() - t0
-    return {"value": iters / dt, "unit": "iter/s", "cores": num_threads(), "kind": "oracle",
-            "sample": f"{cfg}, {iters} float64 PDHG iterations after setup ({dt:.1f} s)"}
+    set_threads(1)
+    t1 = time.perf_counter()
+    o.iterate(iters_one)
+    dt1 = time.perf_counter() - t1
+    set_threads(cores)
+    return {"value": iters / dt, "unit": "iter/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cfg}, {iters} float64 PDHG iterations after setup on {cores} threads ({dt:.1f} s)",
+            "single_thread": {"value": iters_one / dt1, "unit": "iter/s", "cores": 1,
+                              "sample": f"the next {iters_one} iterations on 1 thread ({dt1:.1f} s)"}}
+
+
+PREDICTOR = os.path.join(ROOT, "paper_2511_13894_amd", "predictor.json")
+
+
+def learned_vs_plain(path):
+    """Outside the timed region: the corner push with the committed learned
+    warm start against the plain push, on the multicommodity evaluation LP
+    (single LP) and on 64 held-out LPs of the batched family (learned+batched
+    against plain batched), both FP32-mixed.  Each arm's time to the corner is
+    create + solve + push; max(p - m, 0) and the candidate count are the
+    pushed point's."""
+    from paper_2511_13894_amd import learned, lpgen
+
+    net, theta, meta = learned.load_predictor(path)
+    keys = ("seconds", "push_iters", "push_lockstep", "push_lp_iters", "est_primal_after", "candidates_after",
+            "off_bound_after", "learned_fix", "learned_undo", "push_status", "push_done", "optimal")
+    pick = lambda d: None if d is None else {k: d[k] for k in keys if k in d}  # noqa: E731
+    out = {"predictor": os.path.relpath(path, ROOT), "theta": theta, "trained_by": meta.get("command")}
+    lp = lpgen.config4()
+    print("[bench] learned vs plain: multicommodity LP", file=sys.stderr, flush=True)
+    plain = learned.time_to_corner(lp, 4100, "fp32")
+    lrn = learned.time_to_corner(lp, 4100, "fp32", net, theta)
+    out["c4"] = {"workload": WORKLOADS["c4"], "plain": pick(plain), "learned": pick(lrn)}
+    m_range = tuple(meta.get("val_lps", [0, 0, [500, 20000]])[2])
+    ev = [lpgen.config3_instance(i, base_seed=43000, m_range=m_range) for i in range(64)]
+    seeds = [500 + i for i in range(len(ev))]
+    print("[bench] learned vs plain: 64 held-out LPs, batched", file=sys.stderr, flush=True)
+    out["batched_64"] = {"workload": f"64 held-out LPs of the batched family (seeds 43000+i, m in {list(m_range)})",
+                         "plain": pick(learned.batch_time_to_corner(ev, seeds, "fp32")),
+                         "learned": pick(learned.batch_time_to_corner(ev, seeds, "fp32", net, theta))}
+    return out
 
 
 def bench_batch(args, pdhg, copy_gbs):
@@ -173,7 +223,8 @@ def bench_batch(args, pdhg, copy_gbs):
                    "eps_rel": 1e-6, "push_on_free_columns": bool(args.push_compact) and args.push == "primal",
                    "push": args.push},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile("c3", kname),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile("c3", kname, args.precision, args.push,
+                                                                    args.push_compact),
                      "kernel": kname,
                      "launch_us": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": int(nbytes),
                      "other_kernel": {"name": other[0], "launch_us": round(other[1] * 1e3, 2),
@@ -190,7 +241,7 @@ def bench_batch(args, pdhg, copy_gbs):
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         from oracle import OracleSolver, num_threads
 
-        sample, it_each, dt = lps[:32], 2 * args.cpu_iters, 0.0
+        sample, it_each, dt = lps[:32], 2 * (args.cpu_iters or 2000), 0.0
         for lp in sample:
             o = OracleSolver(lp, eps_rel=1e-30)
             t0 = time.perf_counter()
@@ -208,10 +259,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c1", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"],
+                    help="fp32: FP32-mixed (float matrix and n-vectors, float64 checks, defect correction); fp64")
+    ap.add_argument("--learned", default=PREDICTOR,
+                    help="predictor file for the learned-vs-plain comparison outside the timed region ('' skips it)")
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--cpu-iters", type=int, default=2000)
+    ap.add_argument("--cpu-iters", type=int, default=0,
+                    help="oracle iterations for the CPU baseline (0: the workload's default)")
     ap.add_argument("--iters-only", type=int, default=0,
                     help="profiling runs: create + this many iterations per step, no push, no JSON roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -246,14 +301,18 @@ def main():
 
     if args.iters_only:
         for k in range(args.steps):
-            s = pdhg.Solver(lp, precision=args.precision, use_graph=0 if args.no_graph else 1)
+            s = pdhg.Solver(pdhg.DeviceLP(lp), precision=args.precision, use_graph=0 if args.no_graph else 1)
             r = s.iterate(args.iters_only)
             s.destroy()
             print(f"[bench] profiling step {k}: {r.iters} iterations", file=sys.stderr, flush=True)
         return
 
+    # the inputs are copied to HBM once, before any timed step: a step starts
+    # from the LP in device memory (pdhg_create_device), as the metric asks
+    dlp = pdhg.DeviceLP(lp)
+
     def step(timing):
-        s = pdhg.Solver(lp, precision=args.precision, timing=timing, use_graph=0 if args.no_graph else 1,
+        s = pdhg.Solver(dlp, precision=args.precision, timing=timing, use_graph=0 if args.no_graph else 1,
                         push_compact=args.push_compact)
         r = s.solve()
         p = s.corner_push(args.seed) if args.push != "dual" else s.dual_push(args.seed)
@@ -313,7 +372,8 @@ def main():
         kname, ms, nbytes = "k_dual", dual_ms, tim.bytes_dual
     achieved = nbytes / (ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(args.config, kname),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profile(args.config, kname, args.precision, args.push, args.push_compact),
             "kernel": kname, "launch_us": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": int(nbytes),
             "other_kernel": {"name": "k_dual" if kname == "k_primal" else "k_primal",
                              "launch_us": round((dual_ms if kname == "k_primal" else prim_ms) * 1e3, 2),
@@ -340,9 +400,14 @@ def main():
         "detail": {"steps": details, "time_to_corner_s": round(elapsed / args.steps, 4),
                    "lanes_at": tim.lanes_at, "lanes_a": tim.lanes_a},
     }
+    if args.learned and os.path.exists(args.learned):
+        out["learned_vs_plain"] = learned_vs_plain(args.learned)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(lp, args.cpu_iters, f"{args.config} at full size")
+        n_all, n_one = CPU_ITERS.get(args.config, (2000, 200))
+        if args.cpu_iters:
+            n_all, n_one = args.cpu_iters, max(1, args.cpu_iters // 10)
+        out["cpu_baseline"] = cpu_baseline(lp, n_all, n_one, f"{args.config} at full size")
     print(json.dumps(out), flush=True)
 
 

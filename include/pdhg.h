@@ -225,6 +225,20 @@ int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const
                 const double *val, const double *b, const double *c, const double *l, const double *u,
                 const char *sense, const pdhg_params *p, pdhg_solver **out);
 
+/* pdhg_create on a model already in device memory (the same meaning and
+ * layout; every pointer is a device address on the current device): the
+ * inputs stay where they are and are copied device to device, so a caller
+ * whose data lives in HBM never crosses PCIe.  The device checks the model:
+ * row_ptr as above, columns in range and strictly ascending within each row
+ * (this entry point does not sort or merge duplicates), finite val, b and c,
+ * bounds not NaN with l <= u, senses '=', '<' or '>' (l, u, sense may be
+ * NULL: 0, +infinity, all '=').  The caller keeps ownership and may free its
+ * arrays once this returns.  Errors: as pdhg_create (INVALID_ARG names the
+ * first failed check), OOM, HIP. */
+int pdhg_create_device(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                       const double *val, const double *b, const double *c, const double *l, const double *u,
+                       const char *sense, const pdhg_params *p, pdhg_solver **out);
+
 /* Iterate until the relative tests hold (PDHG_OPTIMAL), max_iter, the time
  * limit or a non-finite value.  Re-callable: continues from the current
  * state.  *r may be NULL.  Errors: INVALID_ARG, STATE (after a push), HIP. */

@@ -361,37 +361,9 @@ int32_t pdhg_struct_size(int32_t which)
     }
 }
 
-// Validate, canonicalise and upload one model, build its transpose and scale
-// it.  With `single` the step size, norms and start point of a lone LP are
-// set up as well; a batch does those per LP (pdhg_batch.hip).
-static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
-                        const double *val, const double *b, const double *c, const double *l, const double *u,
-                        const char *sense, const pdhg_params *params, bool single, pdhg_solver **out)
+// Validate the parameters (NULL: the defaults) into p; returns PDHG_OK or the error.
+static int check_params(const pdhg_params *params, pdhg_params &p)
 {
-    if (!out) return fail(PDHG_ERR_INVALID_ARG, "out is NULL");
-    *out = nullptr;
-    if (m < 0 || n < 0 || nnz < 0) return fail(PDHG_ERR_INVALID_ARG, "negative dimension");
-    if (!row_ptr || (nnz > 0 && (!col_idx || !val)) || (m > 0 && !b) || (n > 0 && !c))
-        return fail(PDHG_ERR_INVALID_ARG, "NULL array");
-    if (nnz >= (int64_t)1 << 31) return fail(PDHG_ERR_INVALID_ARG, "nnz must stay below 2^31");
-    if (row_ptr[0] != 0 || row_ptr[m] != nnz) return fail(PDHG_ERR_INVALID_ARG, "row_ptr[0] != 0 or row_ptr[m] != nnz");
-    for (int i = 0; i < m; i++)
-        if (row_ptr[i + 1] < row_ptr[i]) return fail(PDHG_ERR_INVALID_ARG, "row_ptr not non-decreasing");
-    for (int64_t e = 0; e < nnz; e++) {
-        if (col_idx[e] < 0 || col_idx[e] >= n) return fail(PDHG_ERR_INVALID_ARG, "column index out of range");
-        if (!std::isfinite(val[e])) return fail(PDHG_ERR_INVALID_ARG, "non-finite matrix value");
-    }
-    for (int i = 0; i < m; i++) {
-        if (!std::isfinite(b[i])) return fail(PDHG_ERR_INVALID_ARG, "non-finite b");
-        if (sense && sense[i] != '=' && sense[i] != '<' && sense[i] != '>')
-            return fail(PDHG_ERR_INVALID_ARG, "sense must be '=', '<' or '>'");
-    }
-    for (int j = 0; j < n; j++) {
-        const double lo = l ? l[j] : 0.0, hi = u ? u[j] : INFINITY;
-        if (!std::isfinite(c[j])) return fail(PDHG_ERR_INVALID_ARG, "non-finite c");
-        if (std::isnan(lo) || std::isnan(hi) || lo > hi) return fail(PDHG_ERR_INVALID_ARG, "bad bounds (NaN or l > u)");
-    }
-    pdhg_params p;
     if (params) p = *params;
     else pdhg_default_params(&p);
     if (p.check_every < 1 || p.ruiz_iters < 0 || p.power_iters < 0 || p.push_min_iters < 1 ||
@@ -424,43 +396,25 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
                                               "-32/-64/-128/-256/-1032/-1064/-2256, or -3032 (lanes_a only)");
     }
 
-    // canonical rows (ascending columns, duplicates summed), host side ingest
-    std::vector<int> rp((size_t)m + 1);
-    std::vector<int> ci;
-    std::vector<double> av;
-    if (row_sorted_unique(row_ptr, col_idx, m)) {
-        for (int i = 0; i <= m; i++) rp[i] = (int)row_ptr[i];
-        ci.assign(col_idx, col_idx + nnz);
-        av.assign(val, val + nnz);
-    } else {
-        ci.reserve((size_t)nnz);
-        av.reserve((size_t)nnz);
-        std::vector<std::pair<int, double>> row;
-        rp[0] = 0;
-        for (int i = 0; i < m; i++) {
-            row.clear();
-            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) row.emplace_back(col_idx[e], val[e]);
-            std::stable_sort(row.begin(), row.end(), [](auto &a, auto &b2) { return a.first < b2.first; });
-            for (size_t q = 0; q < row.size(); q++) {
-                if (!ci.empty() && (int)ci.size() > rp[i] && ci.back() == row[q].first) av.back() += row[q].second;
-                else {
-                    ci.push_back(row[q].first);
-                    av.push_back(row[q].second);
-                }
-            }
-            rp[i + 1] = (int)ci.size();
-        }
-    }
-    const int nz = rp[m];
-    std::vector<double> lv((size_t)n), uv((size_t)n);
-    std::vector<int8_t> sv((size_t)m);
-    for (int j = 0; j < n; j++) {
-        const double lo = l ? l[j] : 0.0, hi = u ? u[j] : INFINITY;
-        lv[j] = lo <= -1e20 ? -INFINITY : lo;
-        uv[j] = hi >= 1e20 ? INFINITY : hi;
-    }
-    for (int i = 0; i < m; i++) sv[i] = (int8_t)(sense ? sense[i] : '=');
+    return PDHG_OK;
+}
 
+// Where a model's arrays come from: canonical host arrays (rows sorted and
+// unique, bounds with infinities, senses filled in), or the caller's device
+// arrays, which the device checks and converts (pdhg_create_device).
+struct ModelSource {
+    const int *rp = nullptr, *ci = nullptr;
+    const double *av = nullptr, *b = nullptr, *c = nullptr, *l = nullptr, *u = nullptr;
+    const int8_t *sense = nullptr;
+    const DeviceModel *dev = nullptr;
+};
+
+// Upload (or take over on the device) one model, build its transpose and
+// scale it.  With `single` the step size, norms and start point of a lone LP
+// are set up as well; a batch does those per LP (pdhg_batch.hip).
+static int build_solver(int m, int n, int nz, const pdhg_params &p, const ModelSource &src, bool single,
+                        pdhg_solver **out)
+{
     pdhg_solver *s = new (std::nothrow) pdhg_solver();
     if (!s) return fail(PDHG_ERR_OOM, "host allocation failed");
     try {
@@ -536,19 +490,35 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
         HIPCHK(hipHostMalloc((void **)&s->cnt_host, sizeof(int64_t) * 16, hipHostMallocDefault));
 
         hipStream_t st = s->stream;
-        HIPCHK(hipMemcpyAsync(s->rp, rp.data(), sizeof(int) * (M + 1), hipMemcpyHostToDevice, st));
-        if (nz > 0) {
-            HIPCHK(hipMemcpyAsync(s->ci, ci.data(), sizeof(int) * NZ, hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(s->av, av.data(), sizeof(double) * NZ, hipMemcpyHostToDevice, st));
-        }
-        if (m > 0) {
-            HIPCHK(hipMemcpyAsync(s->b, b, sizeof(double) * M, hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(s->sense0, sv.data(), M, hipMemcpyHostToDevice, st));
-        }
-        if (n > 0) {
-            HIPCHK(hipMemcpyAsync(s->c, c, sizeof(double) * N, hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(s->l, lv.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(s->u, uv.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+        std::vector<int> rp_host;
+        if (src.dev) { // the caller's device arrays: checked and converted on the device
+            unsigned bad = 0;
+            HIPCHK(ingest_device(s, *src.dev, &bad));
+            if (bad) {
+                free_all(s);
+                delete s;
+                return fail(PDHG_ERR_INVALID_ARG, ingest_error(bad));
+            }
+            if (s->kern_a == kSell) { // the sliced layout is planned on the host
+                rp_host.resize(M + 1);
+                HIPCHK(hipMemcpy(rp_host.data(), s->rp, sizeof(int) * (M + 1), hipMemcpyDeviceToHost));
+            }
+        } else {
+            HIPCHK(hipMemcpyAsync(s->rp, src.rp, sizeof(int) * (M + 1), hipMemcpyHostToDevice, st));
+            if (nz > 0) {
+                HIPCHK(hipMemcpyAsync(s->ci, src.ci, sizeof(int) * NZ, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(s->av, src.av, sizeof(double) * NZ, hipMemcpyHostToDevice, st));
+            }
+            if (m > 0) {
+                HIPCHK(hipMemcpyAsync(s->b, src.b, sizeof(double) * M, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(s->sense0, src.sense, M, hipMemcpyHostToDevice, st));
+            }
+            if (n > 0) {
+                HIPCHK(hipMemcpyAsync(s->c, src.c, sizeof(double) * N, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(s->l, src.l, sizeof(double) * N, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(s->u, src.u, sizeof(double) * N, hipMemcpyHostToDevice, st));
+            }
+            rp_host.assign(src.rp, src.rp + M + 1);
         }
         DevState hs{};
         hs.gamma = p.reflect_gamma;
@@ -568,7 +538,7 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
             if (n > 0) HIPCHK(hipMemcpyAsync(s->chc, s->ch, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
             if (m > 0) HIPCHK(hipMemcpyAsync(s->bhc, s->bh, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
         }
-        if (s->kern_a == kSell) HIPCHK(sell_build(s, rp));
+        if (s->kern_a == kSell) HIPCHK(sell_build(s, rp_host));
         if (single) {
             HIPCHK(power_iteration(s));
             HIPCHK(init_norms(s));
@@ -589,6 +559,105 @@ static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_pt
     *out = s;
     set_error("");
     return PDHG_OK;
+}
+
+// Validate and canonicalise a host model (rows sorted, duplicates summed),
+// then build the solver on it (build_solver).
+static int create_model(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                        const double *val, const double *b, const double *c, const double *l, const double *u,
+                        const char *sense, const pdhg_params *params, bool single, pdhg_solver **out)
+{
+    if (!out) return fail(PDHG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (m < 0 || n < 0 || nnz < 0) return fail(PDHG_ERR_INVALID_ARG, "negative dimension");
+    if (!row_ptr || (nnz > 0 && (!col_idx || !val)) || (m > 0 && !b) || (n > 0 && !c))
+        return fail(PDHG_ERR_INVALID_ARG, "NULL array");
+    if (nnz >= (int64_t)1 << 31) return fail(PDHG_ERR_INVALID_ARG, "nnz must stay below 2^31");
+    if (row_ptr[0] != 0 || row_ptr[m] != nnz) return fail(PDHG_ERR_INVALID_ARG, "row_ptr[0] != 0 or row_ptr[m] != nnz");
+    for (int i = 0; i < m; i++)
+        if (row_ptr[i + 1] < row_ptr[i]) return fail(PDHG_ERR_INVALID_ARG, "row_ptr not non-decreasing");
+    for (int64_t e = 0; e < nnz; e++) {
+        if (col_idx[e] < 0 || col_idx[e] >= n) return fail(PDHG_ERR_INVALID_ARG, "column index out of range");
+        if (!std::isfinite(val[e])) return fail(PDHG_ERR_INVALID_ARG, "non-finite matrix value");
+    }
+    for (int i = 0; i < m; i++) {
+        if (!std::isfinite(b[i])) return fail(PDHG_ERR_INVALID_ARG, "non-finite b");
+        if (sense && sense[i] != '=' && sense[i] != '<' && sense[i] != '>')
+            return fail(PDHG_ERR_INVALID_ARG, "sense must be '=', '<' or '>'");
+    }
+    for (int j = 0; j < n; j++) {
+        const double lo = l ? l[j] : 0.0, hi = u ? u[j] : INFINITY;
+        if (!std::isfinite(c[j])) return fail(PDHG_ERR_INVALID_ARG, "non-finite c");
+        if (std::isnan(lo) || std::isnan(hi) || lo > hi) return fail(PDHG_ERR_INVALID_ARG, "bad bounds (NaN or l > u)");
+    }
+    pdhg_params p;
+    if (int rc = check_params(params, p)) return rc;
+
+    // canonical rows (ascending columns, duplicates summed), host side ingest
+    std::vector<int> rp((size_t)m + 1);
+    std::vector<int> ci;
+    std::vector<double> av;
+    if (row_sorted_unique(row_ptr, col_idx, m)) {
+        for (int i = 0; i <= m; i++) rp[i] = (int)row_ptr[i];
+        ci.assign(col_idx, col_idx + nnz);
+        av.assign(val, val + nnz);
+    } else {
+        ci.reserve((size_t)nnz);
+        av.reserve((size_t)nnz);
+        std::vector<std::pair<int, double>> row;
+        rp[0] = 0;
+        for (int i = 0; i < m; i++) {
+            row.clear();
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) row.emplace_back(col_idx[e], val[e]);
+            std::stable_sort(row.begin(), row.end(), [](auto &a, auto &b2) { return a.first < b2.first; });
+            for (size_t q = 0; q < row.size(); q++) {
+                if (!ci.empty() && (int)ci.size() > rp[i] && ci.back() == row[q].first) av.back() += row[q].second;
+                else {
+                    ci.push_back(row[q].first);
+                    av.push_back(row[q].second);
+                }
+            }
+            rp[i + 1] = (int)ci.size();
+        }
+    }
+    const int nz = rp[m];
+    std::vector<double> lv((size_t)n), uv((size_t)n);
+    std::vector<int8_t> sv((size_t)m);
+    for (int j = 0; j < n; j++) {
+        const double lo = l ? l[j] : 0.0, hi = u ? u[j] : INFINITY;
+        lv[j] = lo <= -1e20 ? -INFINITY : lo;
+        uv[j] = hi >= 1e20 ? INFINITY : hi;
+    }
+    for (int i = 0; i < m; i++) sv[i] = (int8_t)(sense ? sense[i] : '=');
+
+    ModelSource src;
+    src.rp = rp.data();
+    src.ci = ci.data();
+    src.av = av.data();
+    src.b = b;
+    src.c = c;
+    src.l = lv.data();
+    src.u = uv.data();
+    src.sense = sv.data();
+    return build_solver(m, n, nz, p, src, single, out);
+}
+
+int pdhg_create_device(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                       const double *val, const double *b, const double *c, const double *l, const double *u,
+                       const char *sense, const pdhg_params *params, pdhg_solver **out)
+{
+    if (!out) return fail(PDHG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (m < 0 || n < 0 || nnz < 0) return fail(PDHG_ERR_INVALID_ARG, "negative dimension");
+    if (!row_ptr || (nnz > 0 && (!col_idx || !val)) || (m > 0 && !b) || (n > 0 && !c))
+        return fail(PDHG_ERR_INVALID_ARG, "NULL array");
+    if (nnz >= (int64_t)1 << 31) return fail(PDHG_ERR_INVALID_ARG, "nnz must stay below 2^31");
+    pdhg_params p;
+    if (int rc = check_params(params, p)) return rc;
+    DeviceModel dm{m, n, nnz, row_ptr, col_idx, val, b, c, l, u, sense};
+    ModelSource src;
+    src.dev = &dm;
+    return build_solver(m, n, (int)nnz, p, src, true, out);
 }
 
 int pdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx, const double *val,

@@ -251,7 +251,27 @@ namespace pdhg {
 void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
 
+// a caller's model in device memory (pdhg_create_device)
+struct DeviceModel {
+    int m, n;
+    int64_t nnz;
+    const int64_t *row_ptr;
+    const int32_t *col_idx;
+    const double *val, *b, *c, *l, *u; // l, u may be NULL (0 and +infinity)
+    const char *sense;                 // may be NULL (all '=')
+};
+// ingest bits: what the device found wrong with a DeviceModel
+enum IngestBad : unsigned {
+    BAD_ROWPTR = 1u, BAD_COL = 2u, BAD_ORDER = 4u, BAD_VAL = 8u, BAD_B = 16u, BAD_C = 32u, BAD_BOUND = 64u,
+    BAD_SENSE = 128u
+};
+
 // setup kernels (pdhg_setup.hip)
+// check a device model and copy it into the solver's arrays (row pointers
+// to int32, infinite bounds for |v| >= 1e20, defaults for NULL l, u, sense);
+// *bad receives the IngestBad bits (0: accepted)
+hipError_t ingest_device(pdhg_solver *s, const DeviceModel &dm, unsigned *bad);
+const char *ingest_error(unsigned bad);
 hipError_t build_transpose(pdhg_solver *s);
 hipError_t scale_problem(pdhg_solver *s);
 hipError_t power_iteration(pdhg_solver *s);

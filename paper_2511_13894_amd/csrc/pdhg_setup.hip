@@ -142,6 +142,8 @@ __global__ __launch_bounds__(kBlock) void k_convert(int64_t len, const double *_
         dst[p] = (T)src[p];
 }
 
+__global__ void k_fill_u32(unsigned *p, unsigned v) { *p = v; }
+
 // rounding error of the float copy, v - fl32(v) (exact in float64), stored as
 // float (its own rounding is 2^-24 of an error already 2^-24 of v); with a
 // permutation, gathered into the transpose's order
@@ -167,6 +169,108 @@ static hipError_t exclusive_scan(hipStream_t st, int len, const int *in, int *ou
         hipMemsetAsync(out, 0, sizeof(int), st);
     }
     return hipGetLastError();
+}
+
+// ------------------------------------------------------ device ingest ---
+// Rows: row_ptr[0] = 0, row_ptr[m] = nnz, non-decreasing; within a row the
+// columns in range and strictly ascending (the canonical form: a device
+// model is not re-sorted), values finite.  One wave per row (the lanes
+// stride its entries; each compares its column with the previous entry's).
+__global__ __launch_bounds__(kBlock) void k_ingest_rows(int m, int n, int64_t nnz, const int64_t *__restrict__ rp64,
+                                                       const int32_t *__restrict__ ci_in,
+                                                       const double *__restrict__ av_in, const double *__restrict__ b_in,
+                                                       const char *__restrict__ sense_in, int *__restrict__ rp,
+                                                       int *__restrict__ ci, double *__restrict__ av,
+                                                       double *__restrict__ b, int8_t *__restrict__ sense0,
+                                                       unsigned *__restrict__ bad)
+{
+    const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / 64;
+    const int lane = (int)(threadIdx.x & 63);
+    if (i > m) return;
+    unsigned flags = 0;
+    const int64_t p0 = rp64[i];
+    const bool p0_ok = p0 >= 0 && p0 <= nnz;
+    if (lane == 0) rp[i] = (int)(p0_ok ? p0 : 0);
+    if ((i == 0 && p0 != 0) || !p0_ok) flags |= BAD_ROWPTR;
+    if (i == m) {
+        if (p0 != nnz) flags |= BAD_ROWPTR;
+    } else {
+        const int64_t p1 = rp64[i + 1];
+        if (p1 < p0 || p1 > nnz || !p0_ok) {
+            flags |= BAD_ROWPTR;
+        } else {
+            for (int64_t e = p0 + lane; e < p1; e += 64) {
+                const int col = ci_in[e];
+                const double v = av_in[e];
+                if (col < 0 || col >= n) flags |= BAD_COL;
+                else if (e > p0 && col <= ci_in[e - 1]) flags |= BAD_ORDER;
+                if (!isfinite(v)) flags |= BAD_VAL;
+                ci[e] = col;
+                av[e] = v;
+            }
+        }
+        if (lane == 0) {
+            const double bi = b_in[i];
+            if (!isfinite(bi)) flags |= BAD_B;
+            b[i] = bi;
+            const char sn = sense_in ? sense_in[i] : '=';
+            if (sn != '=' && sn != '<' && sn != '>') flags |= BAD_SENSE;
+            sense0[i] = (int8_t)sn;
+        }
+    }
+    if (flags) atomicOr(bad, flags);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ingest_cols(int n, const double *__restrict__ c_in,
+                                                       const double *__restrict__ l_in,
+                                                       const double *__restrict__ u_in, double *__restrict__ c,
+                                                       double *__restrict__ l, double *__restrict__ u,
+                                                       unsigned *__restrict__ bad)
+{
+    unsigned flags = 0;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        const double cj = c_in[j];
+        const double lo = l_in ? l_in[j] : 0.0, hi = u_in ? u_in[j] : INFINITY;
+        if (!isfinite(cj)) flags |= BAD_C;
+        if (isnan(lo) || isnan(hi) || lo > hi) flags |= BAD_BOUND;
+        c[j] = cj;
+        l[j] = lo <= -1e20 ? -INFINITY : lo;
+        u[j] = hi >= 1e20 ? INFINITY : hi;
+    }
+    if (flags) atomicOr(bad, flags);
+}
+
+hipError_t ingest_device(pdhg_solver *s, const DeviceModel &dm, unsigned *bad)
+{
+    hipStream_t st = s->stream;
+    unsigned *d_bad = nullptr;
+    hipError_t e = hipMalloc(&d_bad, sizeof(unsigned));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, st, d_bad, 0u);
+    hipLaunchKernelGGL(k_ingest_rows, dim3(grid_for(((int64_t)dm.m + 1) * 64, kBlock, 1 << 30)), dim3(kBlock), 0, st, dm.m,
+                       dm.n, dm.nnz, dm.row_ptr, dm.col_idx, dm.val, dm.b, dm.sense, s->rp, s->ci, s->av, s->b,
+                       s->sense0, d_bad);
+    if (dm.n > 0)
+        hipLaunchKernelGGL(k_ingest_cols, dim3(grid_for(dm.n, kBlock, 1 << 20)), dim3(kBlock), 0, st, dm.n, dm.c, dm.l,
+                           dm.u, s->c, s->l, s->u, d_bad);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(bad, d_bad, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d_bad);
+    return e;
+}
+
+const char *ingest_error(unsigned bad)
+{
+    if (bad & BAD_ROWPTR) return "row_ptr[0] != 0, row_ptr[m] != nnz or row_ptr not non-decreasing";
+    if (bad & BAD_COL) return "column index out of range";
+    if (bad & BAD_ORDER) return "a device model's rows need ascending, unique column indices";
+    if (bad & BAD_VAL) return "non-finite matrix value";
+    if (bad & BAD_B) return "non-finite b";
+    if (bad & BAD_C) return "non-finite c";
+    if (bad & BAD_BOUND) return "bad bounds (NaN or l > u)";
+    if (bad & BAD_SENSE) return "sense must be '=', '<' or '>'";
+    return "invalid model";
 }
 
 hipError_t build_transpose(pdhg_solver *s)

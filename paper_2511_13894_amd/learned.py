@@ -144,6 +144,27 @@ def time_to_corner(lp, seed, precision="fp64", net=None, theta=0.9, eps=1e-6):
             "rel_p_after": p.after.rel_p, "learned_fix": p.n_learned_fix, "learned_undo": p.n_learned_undo}
 
 
+def save_predictor(path, net, theta, meta):
+    """The trained network's float32 parameters, its theta and how it was
+    made, as JSON."""
+    out = dict(meta)
+    out.update({"theta": theta, "n_params": pdhg.MLP_NPARAMS,
+                "params": [float(v) for v in np.asarray(net.get_params(), dtype=np.float32)]})
+    with open(path, "w") as fh:
+        json.dump(out, fh)
+
+
+def load_predictor(path):
+    """(network, theta, metadata) from a file written by save_predictor."""
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("n_params") != pdhg.MLP_NPARAMS or len(d.get("params", [])) != pdhg.MLP_NPARAMS:
+        raise ValueError(f"{path}: not a predictor of {pdhg.MLP_NPARAMS} parameters")
+    net = pdhg.Mlp(seed=0)
+    net.set_params(np.asarray(d.pop("params"), dtype=np.float32))
+    return net, d["theta"], d
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=200)
@@ -162,6 +183,7 @@ def main(argv=None):
                     help="with --batched: choose theta by the validation batch's measured time to the corner")
     ap.add_argument("--batched", action="store_true",
                     help="training data from the batch engine, and learned+batched vs plain batched push")
+    ap.add_argument("--save", default="", help="write the trained network and its theta to this JSON file")
     args = ap.parse_args(argv)
     global USE_GRAPH
     USE_GRAPH = 0 if args.no_graph else 1
@@ -187,6 +209,15 @@ def main(argv=None):
     for th, prec, frac in rows:
         log(f"[learned] validation theta {th}: precision {prec:.4f}, fixes {frac:.4f} of free columns")
     theta = choose_theta(rows, args.min_precision)
+    if args.save:
+        cmd = "python -m paper_2511_13894_amd.learned " + " ".join(argv if argv is not None else sys.argv[1:])
+        save_predictor(args.save, net, theta,
+                       {"command": cmd, "train_columns": int(f.shape[0]), "val_columns": int(fv.shape[0]),
+                        "train_loss": [rep.loss_first, rep.loss_last], "theta_table": rows,
+                        "min_precision": args.min_precision,
+                        "train_lps": [args.train, "base seed 40000", [args.m_lo, args.m_hi]],
+                        "val_lps": [args.val, "base seed 42000", [args.m_lo, args.m_hi]]})
+        log(f"[learned] saved the network and theta {theta} to {args.save}")
     if args.batched and args.theta_by_time:
         sd = [91 + i for i in range(len(va))]
         base = batch_time_to_corner(va, sd, args.precision)
@@ -202,10 +233,10 @@ def main(argv=None):
     out = {"train_columns": int(f.shape[0]), "val_columns": int(fv.shape[0]), "theta": theta,
            "theta_table": rows, "train_loss": [rep.loss_first, rep.loss_last], "train_seconds": rep.seconds,
            "train_samples_per_s": rep.samples_per_s, "eval": []}
-    if theta is None:
+    if theta is None or (not ev and not args.mcf):
         print(json.dumps(out))
         return
-    if args.batched:
+    if args.batched and ev:
         sd = [500 + i for i in range(len(ev))]
         plain = batch_time_to_corner(ev, sd, args.precision)
         lrn = batch_time_to_corner(ev, sd, args.precision, net, theta)

@@ -134,7 +134,8 @@ EXPORTS = ["pdhg_default_params", "pdhg_create", "pdhg_solve", "pdhg_iterate", "
            "pdhg_batch_features", "pdhg_batch_corner_push_learned",
            "pdhg_corner_push_learned", "pdhg_get_solution_device", "pdhg_set_start", "pdhg_state_size",
            "pdhg_get_state", "pdhg_set_state", "pdhg_get_solve_solution", "pdhg_batch_get_solve_solution",
-           "pdhg_dual_push", "pdhg_batch_dual_push", "pdhg_corner_push_logits", "pdhg_batch_corner_push_logits"]
+           "pdhg_dual_push", "pdhg_batch_dual_push", "pdhg_corner_push_logits", "pdhg_batch_corner_push_logits",
+           "pdhg_create_device"]
 
 _lib = None
 
@@ -154,6 +155,9 @@ def load(path: Optional[Path] = None):
     lib.pdhg_default_params.restype = None
     lib.pdhg_create.argtypes = [C.c_int32, C.c_int32, C.c_int64, P(C.c_int64), P(C.c_int32), dp, dp, dp, dp, dp,
                                 C.c_char_p, P(Params), P(C.c_void_p)]
+    vp = C.c_void_p
+    lib.pdhg_create_device.argtypes = [C.c_int32, C.c_int32, C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, P(Params),
+                                       P(C.c_void_p)]
     lib.pdhg_solve.argtypes = [C.c_void_p, P(Result)]
     lib.pdhg_iterate.argtypes = [C.c_void_p, C.c_int64, P(Result)]
     lib.pdhg_corner_push.argtypes = [C.c_void_p, C.c_uint64, P(PushResult)]
@@ -210,7 +214,8 @@ def load(path: Optional[Path] = None):
                "pdhg_mlp_gradient", "pdhg_mlp_train", "pdhg_features", "pdhg_corner_push_learned",
                "pdhg_batch_features", "pdhg_batch_corner_push_learned", "pdhg_get_solution_device",
                "pdhg_set_start", "pdhg_state_size", "pdhg_get_state", "pdhg_set_state", "pdhg_get_solve_solution",
-               "pdhg_batch_get_solve_solution", "pdhg_corner_push_logits", "pdhg_batch_corner_push_logits"):
+               "pdhg_batch_get_solve_solution", "pdhg_corner_push_logits", "pdhg_batch_corner_push_logits",
+               "pdhg_create_device"):
         getattr(lib, fn).restype = C.c_int
     sizes = [C.sizeof(Params), C.sizeof(Result), C.sizeof(KKTReport), C.sizeof(PushResult), C.sizeof(Timing),
              C.sizeof(LpDesc), C.sizeof(BatchReport), C.sizeof(DualPushResult)]
@@ -266,8 +271,60 @@ def _refuse_second_runtime():
             pass
 
 
+_hip = None
+
+
+def _hip_runtime():
+    """The HIP runtime the library links (device memory for DeviceLP)."""
+    global _hip
+    if _hip is None:
+        load()
+        h = C.CDLL("libamdhip64.so.7")
+        h.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+        h.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        h.hipFree.argtypes = [C.c_void_p]
+        for f in ("hipMalloc", "hipMemcpy", "hipFree"):
+            getattr(h, f).restype = C.c_int
+        _hip = h
+    return _hip
+
+
+class DeviceLP:
+    """An LP's arrays copied once into device memory (the inputs of
+    pdhg_create_device): rows must be sorted with unique columns."""
+
+    FIELDS = (("row_ptr", np.int64), ("col", np.int32), ("val", np.float64), ("b", np.float64),
+              ("c", np.float64), ("l", np.float64), ("u", np.float64), ("sense", np.uint8))
+
+    def __init__(self, lp):
+        _refuse_second_runtime()
+        hip = _hip_runtime()
+        self.m, self.n, self.nnz = int(lp.m), int(lp.n), int(lp.nnz)
+        self.ptr = {}
+        for name, dt in self.FIELDS:
+            a = np.ascontiguousarray(getattr(lp, name), dtype=dt)
+            p = C.c_void_p()
+            if hip.hipMalloc(C.byref(p), max(a.nbytes, 8)) != 0:
+                self.free()
+                raise PdhgError(-3, f"hipMalloc of {name} failed")
+            self.ptr[name] = p
+            if a.nbytes and hip.hipMemcpy(p, a.ctypes.data_as(C.c_void_p), a.nbytes, 1) != 0:
+                self.free()
+                raise PdhgError(-4, f"copy of {name} to the device failed")
+
+    def free(self):
+        for p in self.ptr.values():
+            _hip_runtime().hipFree(p)
+        self.ptr = {}
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            self.free()
+
+
 class Solver:
-    """One LP on the GPU (pdhg_create ... pdhg_destroy)."""
+    """One LP on the GPU (pdhg_create ... pdhg_destroy); a DeviceLP goes
+    through pdhg_create_device."""
 
     def __init__(self, lp, stream=None, **params):
         _refuse_second_runtime()
@@ -275,6 +332,14 @@ class Solver:
         self.m, self.n = int(lp.m), int(lp.n)
         self.params = default_params(**params)
         self.params.stream = stream.value if isinstance(stream, C.c_void_p) else stream
+        if isinstance(lp, DeviceLP):
+            d = lp.ptr
+            h = C.c_void_p()
+            rc = self.lib.pdhg_create_device(self.m, self.n, lp.nnz, d["row_ptr"], d["col"], d["val"], d["b"], d["c"],
+                                             d["l"], d["u"], d["sense"], C.byref(self.params), C.byref(h))
+            self._check(rc)
+            self.h = h
+            return
         rp = np.ascontiguousarray(lp.row_ptr, dtype=np.int64)
         ci = np.ascontiguousarray(lp.col, dtype=np.int32)
         va = np.ascontiguousarray(lp.val, dtype=np.float64)

@@ -94,3 +94,48 @@ def test_solution_into_device_buffers():
     finally:
         for p in bufs:
             hip.hipFree(p)
+
+
+def test_create_from_device_memory_equals_host_create():
+    """pdhg_create_device on the same (row-sorted) LP gives the same solve and
+    push, bit for bit, as pdhg_create; invalid device models are refused by
+    the device's own checks."""
+    import copy
+
+    for prec in ("fp64", "fp32"):
+        lp = lpgen.config1(seed=3, m=300, n=1200)
+        a = pdhg.Solver(lp, precision=prec, eps_rel=1e-6)
+        d = pdhg.DeviceLP(lp)
+        b = pdhg.Solver(d, precision=prec, eps_rel=1e-6)
+        d.free()  # the library holds its own copy
+        ra, rb = a.solve(), b.solve()
+        assert (ra.status, ra.iters, ra.restarts) == (rb.status, rb.iters, rb.restarts)
+        pa, pb = a.corner_push(5), b.corner_push(5)
+        assert (pa.status, pa.iters, pa.n_fix_lower, pa.n_fix_upper) == (pb.status, pb.iters, pb.n_fix_lower, pb.n_fix_upper)
+        for va, vb in zip(a.get_solution(), b.get_solution()):
+            np.testing.assert_array_equal(va, vb)
+    lp = lpgen.config0(1)
+    bad_cases = []
+    x = copy.deepcopy(lp)
+    x.col = x.col.copy()
+    x.col[x.row_ptr[3]] = lp.n  # a column out of range
+    bad_cases.append((x, b"column index out of range"))
+    x = copy.deepcopy(lp)
+    x.col = x.col.copy()
+    r0 = int(x.row_ptr[5])
+    x.col[r0], x.col[r0 + 1] = x.col[r0 + 1], x.col[r0]  # unsorted row
+    bad_cases.append((x, b"ascending"))
+    x = copy.deepcopy(lp)
+    x.val = x.val.copy()
+    x.val[7] = np.nan
+    bad_cases.append((x, b"non-finite matrix value"))
+    x = copy.deepcopy(lp)
+    x.u = x.u.copy()
+    x.u[4] = -1.0  # l > u
+    bad_cases.append((x, b"bounds"))
+    for x, msg in bad_cases:
+        d = pdhg.DeviceLP(x)
+        with pytest.raises(pdhg.PdhgError) as e:
+            pdhg.Solver(d)
+        assert msg.decode() in str(e.value), str(e.value)
+        d.free()
