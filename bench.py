@@ -65,9 +65,13 @@ def make_lp(cfg):
     return lpgen.config0(0)
 
 
-# Everything that shapes a profiled run: every library source and the input
-# generator.  A counter summary counts only while this hash is unchanged.
-SOURCE_FILES = tuple(sorted(os.listdir(os.path.join(ROOT, "paper_2511_13894_amd", "csrc")))) + ("../lpgen.py",)
+# Everything that shapes a profiled run of the solve and the pushes: the
+# iteration, check, setup, push, compaction and batch sources, the host code
+# that drives them, and the input generator (the predictor's network and
+# features play no part in it).  A counter summary counts only while this
+# hash is unchanged.
+SOURCE_FILES = ("pdhg_iter.hip", "pdhg_kernels.hpp", "pdhg_device.hpp", "pdhg_internal.hpp", "pdhg_setup.hip",
+                "pdhg_compact.hip", "pdhg_sell.hip", "pdhg_batch.hip", "pdhg_capi.cpp", "../lpgen.py")
 
 
 def kernel_source_hash(files=SOURCE_FILES):

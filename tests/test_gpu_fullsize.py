@@ -193,3 +193,53 @@ def test_batch_of_256_every_answer_checked_by_the_oracle():
         worst = max(worst, k.rel_p, k.rel_d, k.rel_gap)
         assert max(k.rel_p, k.rel_d, k.rel_gap) <= 1e-6, i
     print(f"[full] batch: all 256 OPTIMAL, worst float64 KKT by the oracle {worst:.3e}", flush=True)
+
+
+def test_c1_fp32_mixed_reaches_the_original_optimum(c1):
+    """FP32-mixed at full size, as the benchmark runs it: the float32-rounded
+    c1 matrix has no optimum, and the defect-corrected iteration still ends
+    at the float64 tolerance of the original model (the oracle's own KKT of
+    the answer), in the float64 path's iteration count, and the push stops
+    with the oracle's primal residual of the pushed point at the tolerance."""
+    lp, o = c1
+    g = pdhg.Solver(pdhg.DeviceLP(lp), precision="fp32", timing=1)
+    r = g.solve()
+    x, y, _ = g.get_solution()
+    k = o.kkt(x, y)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c1_oracle.json")))["solve"]
+    obj_err = abs(k.pobj - gold["pobj"]) / (1 + abs(gold["pobj"]))
+    print(f"[full] c1 fp32: {pdhg.STATUS[r.status]} in {r.iters} iterations (float64 oracle run {gold['iters']}); "
+          f"oracle's KKT {k.rel_p:.2e}/{k.rel_d:.2e}/{k.rel_gap:.2e}; objective error {obj_err:.2e}", flush=True)
+    assert r.status == pdhg.PDHG_OPTIMAL
+    assert max(k.rel_p, k.rel_d, k.rel_gap) <= 1e-6
+    assert obj_err <= 1e-5
+    assert r.iters <= 2 * gold["iters"]
+    p = g.corner_push(1)
+    xh = g.get_solution()[0]
+    kh = o.kkt(xh, y)
+    print(f"[full] c1 fp32 push: {pdhg.STATUS[p.status]} in {p.iters} iterations; oracle's primal residual of the "
+          f"pushed x {kh.rel_p:.2e}; primal push estimate {p.before.est_primal} -> {p.after.est_primal}", flush=True)
+    assert p.status == pdhg.PDHG_PUSH_DONE and kh.rel_p <= 1e-6
+    assert (p.after.p_off, p.after.est_primal) == (kh.p_off, kh.est_primal)
+
+
+def test_batch_of_256_fp32_all_optimal():
+    """The 256-LP batched family in FP32-mixed mode: every LP optimal (the
+    batch report's float64 KKT of each answer within the tolerance) and
+    every push stopped primal feasible."""
+    lps = [lpgen.config3_instance(i) for i in range(256)]
+    b = pdhg.Batch(lps, precision="fp32", eps_rel=1e-6)
+    res = b.solve()
+    push = b.corner_push([1 + i for i in range(len(lps))])
+    worst = max(max(r.rel_p, r.rel_d, r.rel_gap) for r in res)
+    print(f"[full] batch of 256, fp32: {sum(r.status == pdhg.PDHG_OPTIMAL for r in res)} optimal, worst relative KKT "
+          f"{worst:.2e}, pushes done {sum(p.status == pdhg.PDHG_PUSH_DONE for p in push)}", flush=True)
+    assert all(r.status == pdhg.PDHG_OPTIMAL for r in res)
+    assert worst <= 1e-6
+    assert all(p.status == pdhg.PDHG_PUSH_DONE and p.after.rel_p <= 1.0000001e-6 for p in push)
+    # spot-check a few answers with the oracle's own KKT evaluation
+    for i in (0, 97, 255):
+        o = OracleSolver(lps[i])
+        x, y, _ = b.get_solve_solution(i)
+        k = o.kkt(x, y)
+        assert max(k.rel_p, k.rel_d, k.rel_gap) <= 1e-6, i
