@@ -453,6 +453,17 @@ int pdhg_mlp_set_params(pdhg_mlp *net, const float *params);
 int pdhg_mlp_get_params(pdhg_mlp *net, float *params);
 /* logits[n] of features[n x 16] (host arrays). */
 int pdhg_mlp_forward(pdhg_mlp *net, const float *features, int64_t n, float *logits);
+/* pdhg_mlp_forward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops): features[n x 16] and
+ * logits[n] are the caller's device buffers, on the device the network was
+ * created on; the work is enqueued on `stream` (a hipStream_t, NULL: the
+ * network's own stream) and the call returns without waiting.  The bfloat16
+ * staging copy of the features lives in a fixed 2 MiB device array per GPU,
+ * so n is at most 65536 per call (INVALID_ARG beyond); no allocation, no
+ * synchronisation.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * ordered by the caller.  Errors: INVALID_ARG, HIP. */
+int pdhg_mlp_forward_noalloc(pdhg_mlp *net, const float *features, int64_t n, float *logits, void *stream);
 /* Gradient of the mean weighted binary cross-entropy over n <= 65536
  * samples (labels 0/1) into grad[PDHG_MLP_NPARAMS]; *loss = the mean loss. */
 int pdhg_mlp_gradient(pdhg_mlp *net, const float *features, const float *labels, int64_t n, double pos_weight,

@@ -11,6 +11,8 @@
 // variables) need the activations with the variable index as K; those tiles
 // go through LDS.
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "pdhg_device.hpp"
 #include "pdhg_internal.hpp"
@@ -433,3 +435,66 @@ hipError_t mlp_adam(pdhg_mlp *net, float lr, float beta1, float beta2, float eps
 }
 
 } // namespace pdhg
+
+// ------------------------------------------------- forward without allocation
+// For callers that cannot allocate (graph capture, serving loops): the
+// bfloat16 staging copy of the features lives in this file-scope device
+// array instead of a buffer allocated per call.  Every GPU the library runs
+// on holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in symbol): the
+// device address comes from hipGetSymbolAddress, once per device with that
+// device current, and is kept per device.
+namespace pdhg {
+namespace {
+
+constexpr int64_t kNoAllocMaxRows = 65536;     // variables per call
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) short scratch[16 * kNoAllocMaxRows]; // 2 MiB
+short *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// the current device's address of `scratch` (looked up on first use)
+hipError_t scratch_for_current_device(short **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (short *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+} // namespace
+
+hipError_t mlp_scratch_setup() // at pdhg_mlp_create, on the device the network lives on
+{
+    short *p = nullptr;
+    return scratch_for_current_device(&p);
+}
+
+} // namespace pdhg
+
+extern "C" int pdhg_mlp_forward_noalloc(pdhg_mlp *net, const float *features, int64_t n, float *logits, void *stream)
+{
+    using namespace pdhg;
+    if (!net || n < 0 || (n > 0 && (!features || !logits)))
+        return fail(PDHG_ERR_INVALID_ARG, "bad arguments (NULL network or device pointer, or n < 0)");
+    if (n > kNoAllocMaxRows)
+        return fail(PDHG_ERR_INVALID_ARG, "pdhg_mlp_forward_noalloc takes at most 65536 variables per call");
+    if (n == 0) return PDHG_OK;
+    short *fb = nullptr;
+    hipError_t e = scratch_for_current_device(&fb);
+    if (e != hipSuccess) return fail(PDHG_ERR_HIP, std::string("HIP error in hipGetSymbolAddress: ") + hipGetErrorString(e));
+    hipStream_t st = stream ? (hipStream_t)stream : net->stream;
+    e = mlp_features_to_bf16(st, features, fb, n); // every staged row is overwritten: nothing to clear
+    if (e == hipSuccess) e = mlp_forward(net, st, fb, n, logits);
+    if (e != hipSuccess) return fail(PDHG_ERR_HIP, std::string("HIP error in the forward launch: ") + hipGetErrorString(e));
+    return PDHG_OK;
+}

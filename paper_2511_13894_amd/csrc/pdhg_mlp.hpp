@@ -26,4 +26,7 @@ hipError_t mlp_features_to_bf16(hipStream_t st, const float *src, short *dst, in
 hipError_t mlp_forward(const pdhg_mlp *net, hipStream_t st, const short *F, int64_t N, float *logits);
 hipError_t mlp_grad(pdhg_mlp *net, const short *F, const float *Y, const int *idx, int64_t b0, int bsz, float pw);
 hipError_t mlp_adam(pdhg_mlp *net, float lr, float beta1, float beta2, float eps, int64_t t);
+// device address of the no-allocation forward's staging array on the current
+// device (looked up once per device)
+hipError_t mlp_scratch_setup();
 } // namespace pdhg

@@ -97,6 +97,7 @@ int pdhg_mlp_create(uint64_t seed, pdhg_mlp **out)
         CHK(hipMalloc(&net->lossp, sizeof(float) * (size_t)net->max_waves));
         CHK(hipMalloc(&net->loss_acc, sizeof(double)));
         CHK(mlp_init(net, seed));
+        CHK(mlp_scratch_setup()); // the no-allocation forward's staging array on this device
         CHK(hipStreamSynchronize(net->stream));
     } catch (const HipFail &f) {
         pdhg_mlp_destroy(net);

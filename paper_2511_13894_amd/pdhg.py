@@ -135,7 +135,7 @@ EXPORTS = ["pdhg_default_params", "pdhg_create", "pdhg_solve", "pdhg_iterate", "
            "pdhg_corner_push_learned", "pdhg_get_solution_device", "pdhg_set_start", "pdhg_state_size",
            "pdhg_get_state", "pdhg_set_state", "pdhg_get_solve_solution", "pdhg_batch_get_solve_solution",
            "pdhg_dual_push", "pdhg_batch_dual_push", "pdhg_corner_push_logits", "pdhg_batch_corner_push_logits",
-           "pdhg_create_device"]
+           "pdhg_create_device", "pdhg_mlp_forward_noalloc"]
 
 _lib = None
 
@@ -187,6 +187,8 @@ def load(path: Optional[Path] = None):
     lib.pdhg_mlp_set_params.argtypes = [C.c_void_p, fp]
     lib.pdhg_mlp_get_params.argtypes = [C.c_void_p, fp]
     lib.pdhg_mlp_forward.argtypes = [C.c_void_p, fp, C.c_int64, fp]
+    lib.pdhg_mlp_forward_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+    lib.pdhg_mlp_forward_noalloc.restype = C.c_int
     lib.pdhg_mlp_gradient.argtypes = [C.c_void_p, fp, fp, C.c_int64, C.c_double, fp, P(C.c_double)]
     lib.pdhg_default_train_params.argtypes = [P(TrainParams)]
     lib.pdhg_default_train_params.restype = None
@@ -283,7 +285,8 @@ def _hip_runtime():
         h.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
         h.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
         h.hipFree.argtypes = [C.c_void_p]
-        for f in ("hipMalloc", "hipMemcpy", "hipFree"):
+        h.hipDeviceSynchronize.argtypes = []
+        for f in ("hipMalloc", "hipMemcpy", "hipFree", "hipDeviceSynchronize"):
             getattr(h, f).restype = C.c_int
         _hip = h
     return _hip
@@ -606,6 +609,10 @@ class Mlp:
         a = np.zeros(MLP_NPARAMS, dtype=np.float32)
         self._check(self.lib.pdhg_mlp_get_params(self.h, _fp(a)))
         return a
+
+    def forward_noalloc(self, features_dev, n: int, logits_dev, stream=None):
+        """pdhg_mlp_forward_noalloc on device pointers (enqueued, not waited for)."""
+        self._check(self.lib.pdhg_mlp_forward_noalloc(self.h, features_dev, int(n), logits_dev, stream))
 
     def forward(self, features):
         f = np.ascontiguousarray(features, dtype=np.float32).reshape(-1, MLP_FEATURES)
