@@ -19,16 +19,19 @@ __global__ __launch_bounds__(kBlock) void k_primal(int n, const int *__restrict_
                                                   const V *__restrict__ xa, V *__restrict__ xbar, V *__restrict__ xp,
                                                   const DevState *__restrict__ st, int i, int store_cand)
 {
-    if (st->done) return;
     const int64_t gi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int64_t j = gi / L;
     const int lane = (int)(gi % L);
     if (j >= n) return;
+    // the epilogue's operands are loaded by every lane of the group (one
+    // request per group) before the product, and the stop flag after them,
+    // so their latencies overlap
+    const double xj = (double)x[j], cj = (double)ch[j], lo = (double)lh[j], hi = (double)uh[j], aj = (double)xa[j];
+    if (st->done) return;
     double acc = lane_dot<L, double>(tp[j], tp[j + 1], lane, ti, atv, y);
     acc = group_sum<L>(acc);
     if (lane != 0) return;
-    primal_update<V>(j, acc, (double)x[j], (double)ch[j], (double)lh[j], (double)uh[j], (double)xa[j], x, xbar, xp,
-                     st, i, store_cand);
+    primal_update<V>(j, acc, xj, cj, lo, hi, aj, x, xbar, xp, st, i, store_cand);
 }
 
 // Dual half, one row of A per group of L lanes:  h = Ahat xbar.
@@ -40,15 +43,17 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
                                                 double *__restrict__ yp, const DevState *__restrict__ st, int i,
                                                 int store_cand)
 {
-    if (st->done) return;
     const int64_t gi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int64_t r = gi / L;
     const int lane = (int)(gi % L);
     if (r >= m) return;
+    const double yr = y[r], br = bh[r], ar = ya[r]; // loaded before the product (see k_primal)
+    const int8_t sn = sense[r];
+    if (st->done) return;
     double acc = lane_dot<L, double>(rp[r], rp[r + 1], lane, ci, av, xbar);
     acc = group_sum<L>(acc);
     if (lane != 0) return;
-    dual_update(r, acc, y[r], bh[r], ya[r], sense[r], y, yp, st, i, store_cand);
+    dual_update(r, acc, yr, br, ar, sn, y, yp, st, i, store_cand);
 }
 
 // ------------------------------------------------------- long rows ---
@@ -245,20 +250,19 @@ __global__ __launch_bounds__(NT) void k_primal_tiled(int n, const int *__restric
     __shared__ int s_ptr[T + 1];
     __shared__ double s_prod[kTileU * NT];
     __shared__ double s_sum[T];
-    if (st->done) return;
     const int r0 = xcd_block(blockIdx.x, gridDim.x) * T;
-    const int rows = n - r0 < T ? n - r0 : T;
+    const int rows = n - r0 < T ? n - r0 : T; // >= 1: the grid covers n
     const int tid = threadIdx.x;
     const bool mine = tid < rows;
     const int j = r0 + tid;
-    double xj = 0, cj = 0, lo = 0, hi = 0, aj = 0;
-    if (mine) { // epilogue operands, independent of the product
-        xj = (double)x[j];
-        cj = (double)ch[j];
-        lo = (double)lh[j];
-        hi = (double)uh[j];
-        aj = (double)xa[j];
-    }
+    // Epilogue operands, independent of the product: every thread loads
+    // (threads past the tile reload its first row), so no load waits on a
+    // branch, and the stop flag is read after them so its latency overlaps
+    // theirs.  The flag is uniform: the whole workgroup leaves together.
+    const int jc = mine ? j : r0;
+    const double xj = (double)x[jc], cj = (double)ch[jc], lo = (double)lh[jc], hi = (double)uh[jc],
+                 aj = (double)xa[jc];
+    if (st->done) return;
     tile_row_sums<V, double, T, NT>(r0, rows, tp, ti, atv, y, s_ptr, s_prod, s_sum);
     if (!mine) return;
     primal_update<V>(j, s_sum[tid], xj, cj, lo, hi, aj, x, xbar, xp, st, i, store_cand);
@@ -275,20 +279,15 @@ __global__ __launch_bounds__(NT) void k_dual_tiled(int m, const int *__restrict_
     __shared__ int s_ptr[T + 1];
     __shared__ double s_prod[kTileU * NT];
     __shared__ double s_sum[T];
-    if (st->done) return;
     const int r0 = xcd_block(blockIdx.x, gridDim.x) * T;
-    const int rows = m - r0 < T ? m - r0 : T;
+    const int rows = m - r0 < T ? m - r0 : T; // >= 1: the grid covers m
     const int tid = threadIdx.x;
     const bool mine = tid < rows;
     const int r = r0 + tid;
-    double yr = 0, br = 0, ar = 0;
-    int8_t sn = '=';
-    if (mine) {
-        yr = y[r];
-        br = bh[r];
-        ar = ya[r];
-        sn = sense[r];
-    }
+    const int rc = mine ? r : r0; // as in k_primal_tiled: unconditional loads, then the stop flag
+    const double yr = y[rc], br = bh[rc], ar = ya[rc];
+    const int8_t sn = sense[rc];
+    if (st->done) return;
     tile_row_sums<V, V, T, NT>(r0, rows, rp, ci, av, xbar, s_ptr, s_prod, s_sum);
     if (!mine) return;
     dual_update(r, s_sum[tid], yr, br, ar, sn, y, yp, st, i, store_cand);
