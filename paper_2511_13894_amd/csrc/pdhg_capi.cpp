@@ -533,6 +533,7 @@ static int build_solver(int m, int n, int nz, const pdhg_params &p, const ModelS
         HIPCHK(hipMemcpyAsync(s->st, s->st_host, sizeof(DevState), hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(build_transpose(s));
+        HIPCHK(detect_uniform_columns(s));
         HIPCHK(scale_problem(s));
         if (s->aerr) { // until the first anchor's correction: the uncorrected data
             if (n > 0) HIPCHK(hipMemcpyAsync(s->chc, s->ch, sizeof(double) * N, hipMemcpyDeviceToDevice, st));

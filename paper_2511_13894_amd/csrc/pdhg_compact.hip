@@ -323,6 +323,7 @@ hipError_t begin_impl(pdhg_solver *s)
     // put the compact model in place
     c.n0 = s->n;
     c.nnz0 = s->nnz;
+    c.udeg_at0 = s->udeg_at;
     c.red_blocks_n0 = s->red_blocks_n;
     c.tp0 = s->tp;
     c.ti0 = s->ti;
@@ -381,7 +382,7 @@ hipError_t begin_impl(pdhg_solver *s)
         s->graph_exec = nullptr;
         s->graph_mode = -1;
     }
-    return hipSuccess;
+    return detect_uniform_columns(s); // of the compact model (on failure the caller restores the full one)
 }
 
 template <typename V>
@@ -398,6 +399,7 @@ hipError_t end_impl(pdhg_solver *s, bool scatter)
     if (e == hipSuccess) e = e2;
     s->n = c.n0;
     s->nnz = c.nnz0;
+    s->udeg_at = c.udeg_at0;
     s->red_blocks_n = c.red_blocks_n0;
     s->tp = c.tp0;
     s->ti = c.ti0;

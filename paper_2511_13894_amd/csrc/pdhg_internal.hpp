@@ -134,6 +134,7 @@ struct pdhg_solver {
     int64_t *cnt_host = nullptr;       // pinned integer counts
 
     int lanes_at = 1, lanes_a = 1; // lane-group width of setup / check products
+    int udeg_at = 0;               // every column holds this many entries (1..3), else 0
     int kern_at = 1, kern_a = 1;   // iteration kernels: > 0 lane-group width, < 0 LDS tile of -k rows
     int64_t t_host = 0;      // iterations of the current phase (mirror of st->t)
     int64_t power_steps = 0; // power-iteration steps taken at create
@@ -182,7 +183,7 @@ struct pdhg_solver {
         void *aerr = nullptr, *aerr_t = nullptr; // mixed precision: the free columns' matrix errors
         int8_t *lfix = nullptr;             // learned push: its fixes, which an undo may free again
         double *l = nullptr, *u = nullptr;  // learned push: the original bounds an undo restores
-        int n0 = 0, nnz0 = 0, red_blocks_n0 = 1;
+        int n0 = 0, nnz0 = 0, red_blocks_n0 = 1, udeg_at0 = 0;
         int8_t *lfix0 = nullptr;
         double *l0 = nullptr, *u0 = nullptr;
         int *tp0 = nullptr, *ti0 = nullptr, *rp0 = nullptr, *ci0 = nullptr;
@@ -284,6 +285,8 @@ hipError_t exact_product(pdhg_solver *s, bool transpose, const double *vec, doub
 // mixed precision: chc = ch - E' y_a, bhc = bh - E x_a at the current anchor
 // (a no-op in float64 mode, where chc and bhc are ch and bh)
 hipError_t defect_refresh(pdhg_solver *s);
+// udeg_at: the common entry count of every column (1..3) of the current model, or 0
+hipError_t detect_uniform_columns(pdhg_solver *s);
 // float64 mode: chc and bhc follow ch and bh (after any swap of those arrays)
 inline void defect_alias(pdhg_solver *s)
 {

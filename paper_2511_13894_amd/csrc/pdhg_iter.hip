@@ -293,11 +293,69 @@ __global__ __launch_bounds__(NT) void k_dual_tiled(int m, const int *__restrict_
     dual_update(r, s_sum[tid], yr, br, ar, sn, y, yp, st, i, store_cand);
 }
 
+// Primal half when every column of A has the same D <= 3 entries (every
+// transpose row starts at j*D: network and transportation LPs, and their
+// push models on the free columns): one thread per column, with no
+// row-pointer loads, so the column's index and value loads go out with the
+// epilogue's in the first round and the gathers in the second.  The products
+// are rounded before they are summed in entry order, as the 256-row LDS
+// tiles (one thread per row) sum them: the two give the same bits.
+template <typename V, int D>
+__global__ __launch_bounds__(kBlock) void k_primal_udeg(int n, const int *__restrict__ ti, const V *__restrict__ atv,
+                                                       const double *__restrict__ y, const double *__restrict__ ch,
+                                                       const V *__restrict__ lh, const V *__restrict__ uh,
+                                                       V *__restrict__ x, const V *__restrict__ xa,
+                                                       V *__restrict__ xbar, V *__restrict__ xp,
+                                                       const DevState *__restrict__ st, int i, int store_cand)
+{
+    const int64_t j = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (j >= n) return;
+    int id[D];
+    double v[D];
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        id[d] = ti[j * D + d];
+        v[d] = (double)atv[j * D + d];
+    }
+    const double xj = (double)x[j], cj = (double)ch[j], lo = (double)lh[j], hi = (double)uh[j], aj = (double)xa[j];
+    if (st->done) return;
+    double g[D];
+#pragma unroll
+    for (int d = 0; d < D; d++) g[d] = y[id[d]];
+    double acc = 0.0;
+    {
+#pragma clang fp contract(off)
+        // separate roundings of each product and each sum, as the tiles' LDS products
+#pragma unroll
+        for (int d = 0; d < D; d++) acc = acc + v[d] * g[d];
+    }
+    primal_update<V>(j, acc, xj, cj, lo, hi, aj, x, xbar, xp, st, i, store_cand);
+}
+
 template <typename V>
 static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     const int L = s->kern_at;
     if (s->n <= 0) return;
+    // uniform columns, kernel chosen by the library: the 256-row tiles' sums with fewer loads
+    // (an explicit lanes_at = -256 keeps the tiles)
+    if (L == -256 && s->p.lanes_at == 0 && s->udeg_at >= 1 && s->udeg_at <= 3) {
+        const int grid = (s->n + kBlock - 1) / kBlock;
+#define PDHG_UD_CASE(DD)                                                                                       \
+    case DD:                                                                                                   \
+        PDHG_LAUNCH(e0, e1, (k_primal_udeg<V, DD>), dim3(grid), dim3(kBlock), s->stream, s->n, s->ti,        \
+                    (const V *)s->ahat_t, (const double *)s->y, s->chc, (const V *)s->lh, (const V *)s->uh,    \
+                    (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i, store);                   \
+        break;
+        switch (s->udeg_at) {
+            PDHG_UD_CASE(1)
+            PDHG_UD_CASE(2)
+        default:
+            PDHG_UD_CASE(3)
+        }
+#undef PDHG_UD_CASE
+        return;
+    }
     if (L == kRowBlock) {
         PDHG_LAUNCH(e0, e1, (k_primal_rowblock<V>), dim3(s->n), dim3(kBlock), s->stream, s->n, s->tp, s->ti,
                     (const V *)s->ahat_t, (const double *)s->y, s->chc, (const V *)s->lh, (const V *)s->uh,
@@ -618,6 +676,36 @@ hipError_t launch_check(pdhg_solver *s, int mode, int len)
                                (const double *)s->yp);
     }
     return hipGetLastError();
+}
+
+// bad |= 1 if some row of `ptr` (rows + 1 entries) does not hold exactly D entries
+__global__ __launch_bounds__(kBlock) void k_uniform_rows(int rows, const int *__restrict__ ptr, int D,
+                                                        unsigned *__restrict__ bad)
+{
+    for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r <= rows; r += (int64_t)gridDim.x * kBlock)
+        if (ptr[r] != (int)(r * D)) {
+            atomicOr(bad, 1u);
+            return;
+        }
+}
+
+__global__ void k_zero_u32(unsigned *p) { *p = 0u; }
+
+hipError_t detect_uniform_columns(pdhg_solver *s)
+{
+    s->udeg_at = 0;
+    if (s->n <= 0 || s->nnz % s->n != 0) return hipSuccess;
+    const int D = s->nnz / s->n;
+    if (D < 1 || D > 3) return hipSuccess;
+    unsigned *d_bad = (unsigned *)s->redout; // small scratch of the handle, free outside a check
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s->stream, d_bad);
+    hipLaunchKernelGGL(k_uniform_rows, dim3(grid_for((int64_t)s->n + 1, kBlock, 4096)), dim3(kBlock), 0, s->stream,
+                       s->n, s->tp, D, d_bad);
+    unsigned bad = 1;
+    hipError_t e = hipMemcpyAsync(&bad, d_bad, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess && bad == 0) s->udeg_at = D;
+    return e;
 }
 
 hipError_t defect_refresh(pdhg_solver *s)

@@ -247,3 +247,28 @@ def test_sliced_ellpack_dual_follows_the_oracle(name, make):
     if rg.status == pdhg.PDHG_OPTIMAL:
         pg, po = g.corner_push(7), o.corner_push(7)
         assert (pg.iters, pg.n_fix_lower, pg.n_fix_upper) == (po.iters, po.n_fix_lower, po.n_fix_upper)
+
+
+@pytest.mark.parametrize("name,make,prec", [
+    ("transport_60x150", lambda: lpgen.transportation(60, 150, seed=7), "fp64"),
+    ("transport_60x150_fp32", lambda: lpgen.transportation(60, 150, seed=7), "fp32"),
+    ("multicommodity", lambda: lpgen.multicommodity(300, 2400, 4, seed=11, walks=40, max_len=8), "fp64"),
+])
+def test_uniform_column_kernel_equals_the_tiles(name, make, prec):
+    """Columns of 2 (transportation) or 3 (multicommodity) entries: the
+    library's choice, the one-thread-per-column kernel without row pointers,
+    gives the 256-row tiles' iterates bit for bit, through the solve and the
+    push on the free columns (whose model is uniform too)."""
+    lp = make()
+    out = []
+    for lanes_at in (0, -256):
+        g = pdhg.Solver(lp, precision=prec, lanes_at=lanes_at, eps_rel=1e-7)
+        assert g.get_timing().lanes_at == -256
+        r = g.solve()
+        p = g.corner_push(3)
+        out.append((r.iters, p.iters, g.get_solution()[0], g.get_iterate()))
+    print(f"[uniform] {name}: solve {out[0][0]} / {out[1][0]}, push {out[0][1]} / {out[1][1]}", flush=True)
+    assert out[0][:2] == out[1][:2]
+    np.testing.assert_array_equal(out[0][2], out[1][2])
+    np.testing.assert_array_equal(out[0][3][0], out[1][3][0])
+    np.testing.assert_array_equal(out[0][3][1], out[1][3][1])
