@@ -89,7 +89,19 @@ __device__ __forceinline__ ACC lane_dot(int beg, int end, int lane, const int *_
         acc += v2 * g2;
         acc += v3 * g3;
     }
-    for (; e < end; e += L) acc += (ACC)val[e] * (ACC)x[idx[e]];
+    // the last up to three terms of the lane: their loads go out together too
+    // (positions past the end reload the lane's first one, whose term is not
+    // added), summed in the same order as a sequential tail
+    if (e < end) {
+        const int e1 = e + L, e2 = e + 2 * L;
+        const int c1 = e1 < end ? e1 : e, c2 = e2 < end ? e2 : e;
+        const int i0 = idx[e], i1 = idx[c1], i2 = idx[c2];
+        const ACC v0 = (ACC)val[e], v1 = (ACC)val[c1], v2 = (ACC)val[c2];
+        const ACC g0 = (ACC)x[i0], g1 = (ACC)x[i1], g2 = (ACC)x[i2];
+        acc += v0 * g0;
+        if (e1 < end) acc += v1 * g1;
+        if (e2 < end) acc += v2 * g2;
+    }
     return acc;
 }
 
