@@ -23,10 +23,10 @@ constexpr int kRedRows = kBlock; // rows per reduction tile (one per thread)
 template <typename V, int T, int NT>
 __global__ __launch_bounds__(NT) void kb_primal(const int4 *__restrict__ tiles, const int *__restrict__ tp,
                                                const int *__restrict__ ti, const V *__restrict__ atv,
-                                               const double *__restrict__ y, const double *__restrict__ ch,
+                                               const V *__restrict__ y, const double *__restrict__ ch,
                                                const V *__restrict__ lh, const V *__restrict__ uh,
-                                               V *__restrict__ x, const V *__restrict__ xa, V *__restrict__ xbar,
-                                               V *__restrict__ xp, const DevState *__restrict__ sts, int i,
+                                               V *__restrict__ x, const double *__restrict__ xa, V *__restrict__ xbar,
+                                               double *__restrict__ xp, const DevState *__restrict__ sts, int i,
                                                int store_cand)
 {
     __shared__ int s_ptr[T + 1];
@@ -41,13 +41,13 @@ __global__ __launch_bounds__(NT) void kb_primal(const int4 *__restrict__ tiles, 
     const int j = r0 + tid;
     double xj = 0, cj = 0, lo = 0, hi = 0, aj = 0;
     if (mine) {
-        xj = (double)x[j];
-        cj = (double)ch[j];
+        aj = xa[j];
+        xj = iterate_value<V>(x[j], aj);
+        cj = ch[j];
         lo = (double)lh[j];
         hi = (double)uh[j];
-        aj = (double)xa[j];
     }
-    tile_row_sums<V, double, T, NT>(r0, rows, tp, ti, atv, y, s_ptr, s_prod, s_sum);
+    tile_row_sums<V, V, T, NT>(r0, rows, tp, ti, atv, y, s_ptr, s_prod, s_sum);
     if (!mine) return;
     primal_update<V>(j, s_sum[tid], xj, cj, lo, hi, aj, x, xbar, xp, st, i, store_cand);
 }
@@ -58,7 +58,8 @@ __global__ __launch_bounds__(NT) void kb_dual(const int4 *__restrict__ tiles, co
                                              const V *__restrict__ xbar, const double *__restrict__ bh,
                                              const int8_t *__restrict__ sense, double *__restrict__ y,
                                              const double *__restrict__ ya, double *__restrict__ yp,
-                                             const DevState *__restrict__ sts, int i, int store_cand)
+                                             float *__restrict__ dy, const DevState *__restrict__ sts, int i,
+                                             int store_cand)
 {
     __shared__ int s_ptr[T + 1];
     __shared__ double s_prod[kTileU * NT];
@@ -80,19 +81,20 @@ __global__ __launch_bounds__(NT) void kb_dual(const int4 *__restrict__ tiles, co
     }
     tile_row_sums<V, V, T, NT>(r0, rows, rp, ci, av, xbar, s_ptr, s_prod, s_sum);
     if (!mine) return;
-    dual_update(r, s_sum[tid], yr, br, ar, sn, y, yp, st, i, store_cand);
+    dual_update(r, s_sum[tid], yr, br, ar, sn, y, yp, dy, st, i, store_cand);
 }
 
 template <typename V>
 static void launch_primal_b(pdhg_batch *b, int i, int store, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     pdhg_solver *s = b->s;
+    const void *yg = s->fp32 ? (const void *)s->dy : s->y; // the dual vector the products gather
 #define PDHG_BP_CASE(TT, RR, NT)                                                                               \
     case TT:                                                                                                   \
         PDHG_LAUNCH(e0, e1, (kb_primal<V, RR, NT>), dim3(b->n_ptiles), dim3(NT), s->stream, b->ptiles, s->tp, \
-                           s->ti, (const V *)s->ahat_t, (const double *)s->y, s->chc,               \
-                           (const V *)s->lh, (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar,     \
-                           (V *)s->xp, b->sts, i, store);                                                     \
+                           s->ti, (const V *)s->ahat_t, (const V *)yg, s->chc,                                 \
+                           (const V *)s->lh, (const V *)s->uh, (V *)s->x, (const double *)s->xa, (V *)s->xbar,\
+                           (double *)s->xp, b->sts, i, store);                                                \
         break;
     switch (-b->kern_at) {
         PDHG_BP_CASE(32, 32, 256)
@@ -114,7 +116,7 @@ static void launch_dual_b(pdhg_batch *b, int i, int store, hipEvent_t e0 = nullp
     case TT:                                                                                                   \
         PDHG_LAUNCH(e0, e1, (kb_dual<V, RR, NT>), dim3(b->n_dtiles), dim3(NT), s->stream, b->dtiles, s->rp,   \
                            s->ci, (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense,    \
-                           (double *)s->y, (const double *)s->ya, (double *)s->yp, b->sts, i, store);         \
+                           (double *)s->y, (const double *)s->ya, (double *)s->yp, s->dy, b->sts, i, store);  \
         break;
     switch (-b->kern_a) {
         PDHG_BD_CASE(32, 32, 256)
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void kb_check_cols(const int4 *__restrict__
                                                        const double *__restrict__ ety,
                                                        const double *__restrict__ ch, const V *__restrict__ lh,
                                                        const V *__restrict__ uh, const double *__restrict__ dc,
-                                                       const V *__restrict__ xc, const V *__restrict__ xa,
+                                                       const double *__restrict__ xc, const double *__restrict__ xa,
                                                        const double *__restrict__ c0, const double *__restrict__ l0,
                                                        const double *__restrict__ u0, int orig,
                                                        double *__restrict__ part, int ntile,
@@ -202,8 +204,8 @@ __global__ __launch_bounds__(kBlock) void kb_check_cols(const int4 *__restrict__
         const double zm = (!is_inf_up(hi) && lam < 0.0) ? -lam : 0.0;
         const double rd = lam - (zp - zm);
         const double rdu = rd / dc[j];
-        const double xj = (double)xc[j];
-        const double dx = xj - (double)xa[j];
+        const double xj = xc[j];
+        const double dx = xj - xa[j];
         v[0] = rd * rd;
         v[1] = rdu * rdu;
         v[2] = fabs(rdu);
@@ -241,15 +243,17 @@ __global__ __launch_bounds__(kBlock) void kb_check_final(DevState *__restrict__ 
     if (threadIdx.x == 0) check_decide(st, v, mode, len);
 }
 
-// restart copies per tile: column tiles first, then row tiles
+// restart copies per tile: column tiles first, then row tiles (mixed mode:
+// the stored differences x - x_a and dy become 0)
 template <typename V>
 __global__ __launch_bounds__(kBlock) void kb_restart_apply(const int4 *__restrict__ rn, int ntn,
                                                           const int4 *__restrict__ rm,
                                                           const DevState *__restrict__ sts, V *__restrict__ x,
-                                                          V *__restrict__ xa, const V *__restrict__ xp,
+                                                          double *__restrict__ xa, const double *__restrict__ xp,
                                                           double *__restrict__ y, double *__restrict__ ya,
-                                                          const double *__restrict__ yp)
+                                                          const double *__restrict__ yp, float *__restrict__ dy)
 {
+    constexpr bool delta = sizeof(V) == sizeof(float);
     const bool col = (int)blockIdx.x < ntn;
     const int4 tl = col ? rn[blockIdx.x] : rm[blockIdx.x - ntn];
     const DevState *st = sts + tl.x;
@@ -257,25 +261,29 @@ __global__ __launch_bounds__(kBlock) void kb_restart_apply(const int4 *__restric
     if ((int)threadIdx.x >= tl.z) return;
     const int k = tl.y + threadIdx.x;
     if (col) {
-        const V v = xp[k];
-        x[k] = v;
+        const double v = xp[k];
+        x[k] = delta ? (V)0 : (V)v;
         xa[k] = v;
     } else {
         const double v = yp[k];
         y[k] = v;
         ya[k] = v;
+        if (dy) dy[k] = 0.0f;
     }
 }
 
-// Defect correction per LP (mixed mode): chc = ch - E' y_a, bhc = bh - E x_a
-// for every LP that restarted at this check (its candidate is the new anchor),
-// or for every LP with `always` (a phase start); column tiles, then row tiles.
+// Anchored objective and right-hand side per LP (mixed mode): chc = ch -
+// (pa + pb), bhc = bh - (qa + qb) with pa + pb = Ahat' y_a and qa + qb =
+// Ahat x_a in float64 (pb, qb may be NULL; pa, qa may be the outputs), for
+// every LP that restarted at this check (the check left its candidate's
+// float64 products in aty and ax), or for every LP with `always` (a phase
+// start); column tiles, then row tiles.
 __global__ __launch_bounds__(kBlock) void kb_defect_set(const int4 *__restrict__ rn, int ntn,
                                                        const int4 *__restrict__ rm,
                                                        const DevState *__restrict__ sts, int always,
-                                                       const double *__restrict__ ch, const double *__restrict__ ety,
-                                                       double *__restrict__ chc, const double *__restrict__ bh,
-                                                       const double *__restrict__ ex, double *__restrict__ bhc)
+                                                       const double *ch, const double *pa, const double *pb,
+                                                       double *chc, const double *bh, const double *qa,
+                                                       const double *qb, double *bhc)
 {
     const bool col = (int)blockIdx.x < ntn;
     const int4 tl = col ? rn[blockIdx.x] : rm[blockIdx.x - ntn];
@@ -283,8 +291,8 @@ __global__ __launch_bounds__(kBlock) void kb_defect_set(const int4 *__restrict__
     if (!always && (!st->restart_flag || st->done)) return;
     if ((int)threadIdx.x >= tl.z) return;
     const int k = tl.y + threadIdx.x;
-    if (col) chc[k] = ch[k] - ety[k];
-    else bhc[k] = bh[k] - ex[k];
+    if (col) chc[k] = ch[k] - (pb ? pa[k] + pb[k] : pa[k]);
+    else bhc[k] = bh[k] - (qb ? qa[k] + qb[k] : qa[k]);
 }
 
 __global__ void kb_advance(DevState *sts, int count, int len)
@@ -340,12 +348,15 @@ static void check_b(pdhg_batch *b, int mode, int len)
 {
     pdhg_solver *s = b->s;
     hipStream_t st = s->stream;
-    const V *xc = (const V *)(mode ? s->xp : s->x);
+    // mode 0 checks the iterate at a phase start, where it is the anchor
+    // (in the mixed mode x holds its difference from x_a, which is 0 there)
+    const double *xc = (const double *)(mode ? s->xp : (s->fp32 ? s->xa : s->x));
     const double *yc = (const double *)(mode ? s->yp : s->y);
-    launch_spmv_b<V, V>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
+    launch_spmv_b<V, double>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
     launch_spmv_b<V, double>(b, b->kern_at, b->ptiles, b->n_ptiles, s->tp, s->ti, (const V *)s->ahat_t, yc, s->aty);
     if (s->aerr) { // mixed mode: the rounding error's products complete the float64 ones
-        launch_spmv_b<float, V>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci, (const float *)s->aerr, xc, s->ex);
+        launch_spmv_b<float, double>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci, (const float *)s->aerr, xc,
+                                     s->ex);
         launch_spmv_b<float, double>(b, b->kern_at, b->ptiles, b->n_ptiles, s->tp, s->ti, (const float *)s->aerr_t,
                                      yc, s->ety);
     }
@@ -355,19 +366,20 @@ static void check_b(pdhg_batch *b, int mode, int len)
                        s->dr, yc, (const double *)s->ya, pm, b->n_rm, b->sts);
     hipLaunchKernelGGL((kb_check_cols<V>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, s->aty,
                        (const double *)(s->aerr ? s->ety : nullptr), s->ch,
-                       (const V *)s->lh, (const V *)s->uh, s->dc, xc, (const V *)s->xa, s->c, s->l, s->u,
+                       (const V *)s->lh, (const V *)s->uh, s->dc, xc, (const double *)s->xa, s->c, s->l, s->u,
                        s->model_original ? 1 : 0, pn, b->n_rn, b->sts);
     hipLaunchKernelGGL(kb_check_final, dim3(b->count), dim3(kBlock), 0, st, b->sts, pm, b->n_rm, pn, b->n_rn,
                        b->rm_start, b->rn_start, mode, len);
     if (mode == 1 && s->hx) (void)batch_record_history(b); // before the restart copies
     if (mode == 2 && s->learned_active) (void)batch_learned_undo(b);
-    if (mode != 0 && s->aerr)
+    if (mode != 0 && s->aerr) // the check left Ahat x+ and Ahat' y+ (float64) in ax and aty
         hipLaunchKernelGGL(kb_defect_set, dim3(b->n_rn + b->n_rm), dim3(kBlock), 0, st, b->rn, b->n_rn, b->rm, b->sts, 0,
-                           s->ch, s->ety, s->chc, (const double *)s->bh, s->ex, s->bhc);
+                           s->ch, (const double *)s->aty, (const double *)nullptr, s->chc, (const double *)s->bh,
+                           (const double *)s->ax, (const double *)nullptr, s->bhc);
     if (mode != 0)
         hipLaunchKernelGGL((kb_restart_apply<V>), dim3(b->n_rn + b->n_rm), dim3(kBlock), 0, st, b->rn, b->n_rn, b->rm,
-                           b->sts, (V *)s->x, (V *)s->xa, (const V *)s->xp, (double *)s->y, (double *)s->ya,
-                           (const double *)s->yp);
+                           b->sts, (V *)s->x, (double *)s->xa, (const double *)s->xp, (double *)s->y, (double *)s->ya,
+                           (const double *)s->yp, s->dy);
 }
 
 hipError_t batch_iterations(pdhg_batch *b, int count, bool check_at_end, int mode, bool timed_launch)
@@ -625,13 +637,19 @@ hipError_t batch_defect_refresh(pdhg_batch *b)
         defect_alias(s);
         return hipSuccess;
     }
-    // the LPs taking part in the phase (the tiles skip the others)
-    launch_spmv_b<float, float>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci, (const float *)s->aerr,
-                                (const float *)s->xa, s->ex);
-    launch_spmv_b<float, double>(b, b->kern_at, b->ptiles, b->n_ptiles, s->tp, s->ti, (const float *)s->aerr_t,
-                                 (const double *)s->ya, s->ety);
+    // the LPs taking part in the phase (the tiles skip the others): fl32(Ahat)
+    // x_a and fl32(Ahat)' y_a into bhc and chc, E x_a and E' y_a into ex and ety
+    const double *xa = (const double *)s->xa, *ya = (const double *)s->ya;
+    launch_spmv_b<float, double>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci, (const float *)s->ahat, xa,
+                                 s->bhc);
+    launch_spmv_b<float, double>(b, b->kern_at, b->ptiles, b->n_ptiles, s->tp, s->ti, (const float *)s->ahat_t, ya,
+                                 s->chc);
+    launch_spmv_b<float, double>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci, (const float *)s->aerr, xa, s->ex);
+    launch_spmv_b<float, double>(b, b->kern_at, b->ptiles, b->n_ptiles, s->tp, s->ti, (const float *)s->aerr_t, ya,
+                                 s->ety);
     hipLaunchKernelGGL(kb_defect_set, dim3(b->n_rn + b->n_rm), dim3(kBlock), 0, s->stream, b->rn, b->n_rn, b->rm,
-                       b->sts, 1, s->ch, s->ety, s->chc, (const double *)s->bh, s->ex, s->bhc);
+                       b->sts, 1, s->ch, (const double *)s->chc, (const double *)s->ety, s->chc,
+                       (const double *)s->bh, (const double *)s->bhc, (const double *)s->ex, s->bhc);
     return hipGetLastError();
 }
 
@@ -786,26 +804,27 @@ hipError_t batch_report(pdhg_batch *b, const double *x, const double *y, double 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void kb_push_cols(const int4 *__restrict__ rn, const int *__restrict__ coff,
                                                       const int *__restrict__ active, const double *__restrict__ z,
-                                                      const V *__restrict__ xs, const double *__restrict__ dc,
+                                                      const double *__restrict__ xs, const double *__restrict__ dc,
                                                       double eps_abs, const uint64_t *__restrict__ seeds, double scale,
                                                       V *__restrict__ lh, V *__restrict__ uh, double *__restrict__ ch,
-                                                      V *__restrict__ x, double *__restrict__ part, int ntile)
+                                                      V *__restrict__ x, double *__restrict__ xa,
+                                                      double *__restrict__ part, int ntile)
 {
     const int4 tl = rn[blockIdx.x];
     double v[2] = {0.0, 0.0};
     if (active[tl.x] && (int)threadIdx.x < tl.z) {
         const int j = tl.y + threadIdx.x;
         const int64_t jl = j - coff[tl.x]; // column number inside its LP
-        const V xv = xs[j];
+        const double xv = xs[j];
         if (z[j] > eps_abs) {
-            uh[j] = xv;
+            uh[j] = (V)xv;
             v[1] = 1.0;
         } else if (z[j] < -eps_abs) {
-            lh[j] = xv;
+            lh[j] = (V)xv;
             v[0] = 1.0;
         }
         ch[j] = dc[j] * (scale * push_unit(seeds[tl.x], jl));
-        x[j] = xv;
+        set_iterate<V>(j, xv, x, xa); // the solve's x
     }
     block_reduce<2>(v, 0u);
     if (threadIdx.x == 0) {
@@ -856,8 +875,8 @@ static hipError_t push_setup_b(pdhg_batch *b, pdhg_push_result *out, double thet
     hipStream_t st = s->stream;
     double *pm = b->part, *pn = b->part + (size_t)(Q_COUNT + 1) * b->n_rm;
     hipLaunchKernelGGL((kb_push_cols<V>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, b->d_coff, b->active, s->zsol,
-                       (const V *)s->xs, s->dc, s->p.eps_abs, b->seeds, s->p.push_obj_scale, (V *)s->lh, (V *)s->uh,
-                       s->ch, (V *)s->x, pn, b->n_rn);
+                       (const double *)s->xs, s->dc, s->p.eps_abs, b->seeds, s->p.push_obj_scale, (V *)s->lh,
+                       (V *)s->uh, s->ch, (V *)s->x, (double *)s->xa, pn, b->n_rn);
     hipLaunchKernelGGL(kb_push_rows, dim3(b->n_rm), dim3(kBlock), 0, st, b->rm, b->active, s->yu, s->p.eps_abs,
                        s->sense, (double *)s->y, pm);
     if (theta > 0.0) { // learned warm start on the columns the plain rule leaves free
@@ -946,8 +965,8 @@ __global__ __launch_bounds__(kBlock) void kb_dpush_cols(const int4 *__restrict__
                                                        const double *__restrict__ atyn, const double *__restrict__ dc,
                                                        double eps_abs, const uint64_t *__restrict__ seeds,
                                                        V *__restrict__ lh, V *__restrict__ uh, double *__restrict__ ch,
-                                                       V *__restrict__ x, double *__restrict__ w0,
-                                                       double *__restrict__ part, int ntile)
+                                                       V *__restrict__ x, double *__restrict__ xa,
+                                                       double *__restrict__ w0, double *__restrict__ part, int ntile)
 {
     const int4 tl = rn[blockIdx.x];
     double v[1] = {0.0}; // columns off both bounds
@@ -965,6 +984,7 @@ __global__ __launch_bounds__(kBlock) void kb_dpush_cols(const int4 *__restrict__
             const double uj = push_unit(seeds[tl.x], (int64_t)(j - coff[tl.x]));
             w0[j] = (at_lo && at_up) ? 0.0 : (at_up ? -uj : uj);
             x[j] = (V)0;
+            xa[j] = 0.0;
             v[0] = (!at_lo && !at_up) ? 1.0 : 0.0;
         } else {
             w0[j] = 0.0;
@@ -1027,7 +1047,7 @@ static hipError_t dual_push_setup_b(pdhg_batch *b, const double *xk, int64_t *co
     spmv<double, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, s->atv, s->ypush, s->zpush);
     hipLaunchKernelGGL((kb_dpush_cols<V>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, b->d_coff, b->active, xk, s->l,
                        s->u, s->c, s->aty, s->zpush, s->dc, s->p.eps_abs, b->seeds, (V *)s->lh, (V *)s->uh, s->ch,
-                       (V *)s->x, s->w0, pn, b->n_rn);
+                       (V *)s->x, (double *)s->xa, s->w0, pn, b->n_rn);
     // A w0 into ax (read above, free now): the rows of LPs not taking part keep their bhat
     spmv<double, double, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, s->av, s->w0, s->ax);
     hipLaunchKernelGGL(kb_dpush_rhs, dim3(b->n_rm), dim3(kBlock), 0, st, b->rm, b->rm_start, b->d_coff, b->active,
@@ -1266,12 +1286,16 @@ hipError_t batch_autotune(pdhg_batch *b)
     pdhg_solver *s = b->s;
     const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
     void *sx = nullptr, *sxbar = nullptr, *sxp = nullptr, *sy = nullptr, *syp = nullptr;
+    float *sdy = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipMalloc(&sx, vb * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sxbar, vb * (size_t)(s->n > 0 ? s->n : 1));
-    if (e == hipSuccess) e = hipMalloc(&sxp, vb * (size_t)(s->n > 0 ? s->n : 1));
+    if (e == hipSuccess) e = hipMalloc(&sxp, sizeof(double) * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sy, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
     if (e == hipSuccess) e = hipMalloc(&syp, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
+    if (e == hipSuccess && s->dy) e = hipMalloc(&sdy, sizeof(float) * (size_t)(s->m > 0 ? s->m : 1));
+    if (e == hipSuccess && s->dy)
+        e = hipMemcpyAsync(sdy, s->dy, sizeof(float) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
     if (e == hipSuccess) e = hipMemcpyAsync(sx, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
@@ -1279,11 +1303,13 @@ hipError_t batch_autotune(pdhg_batch *b)
     if (e == hipSuccess) e = hipMemcpyAsync(sy, s->y, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
     const int cands[] = {-32, -64, -128, -256, -1032, -1064};
     void *keep[5] = {s->x, s->xbar, s->xp, s->y, s->yp};
+    float *keep_dy = s->dy;
     s->x = sx;
     s->xbar = sxbar;
     s->xp = sxp;
     s->y = sy;
     s->yp = syp;
+    s->dy = sdy;
     int best_at = b->kern_at, best_a = b->kern_a;
     for (int half = 0; half < 2 && e == hipSuccess; half++) {
         float best = 1e30f;
@@ -1317,9 +1343,10 @@ hipError_t batch_autotune(pdhg_batch *b)
     s->xp = keep[2];
     s->y = keep[3];
     s->yp = keep[4];
+    s->dy = keep_dy;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    for (void *q : {sx, sxbar, sxp, sy, syp})
+    for (void *q : {sx, sxbar, sxp, sy, syp, (void *)sdy})
         if (q) (void)hipFree(q);
     if (e != hipSuccess) return e;
     return batch_set_kernels(b, best_at, best_a);

@@ -37,18 +37,19 @@ double gate_threshold(const pdhg_params &p, int64_t m)
     return a > b ? a : b;
 }
 
-// byte model of the two kernels: v = bytes per matrix value and n-vector
-// entry (4 in the mixed mode, 8 otherwise), m-vectors are float64, 4 bytes
-// per index
+// byte model of the two kernels: v = bytes per matrix value and per entry of
+// lhat, uhat, x, xbar (4 in the mixed mode, 8 otherwise); chat, the anchors
+// and the m-vectors are float64; 4 bytes per index
 void model_bytes(const pdhg_solver *s, int64_t *bytes_primal, int64_t *bytes_dual)
 {
     const int64_t v = s->fp32 ? 4 : 8, m = s->m, n = s->n, nz = s->nnz;
-    // primal: row pointers, indices + values, y gathered once, reads x, chat,
-    // x_anchor, lhat, uhat, writes x, xbar
-    *bytes_primal = 4 * (n + 1) + (4 + v) * nz + 8 * m + 6 * v * n + 8 * n;
+    const int64_t gy = s->fp32 ? 4 : 8; // the gathered dual vector: dy (float) or y
+    // primal: row pointers (none for uniform columns), indices + values, the
+    // dual vector gathered once, reads x, chat, x_anchor, lhat, uhat, writes x, xbar
+    *bytes_primal = (uses_uniform_kernel(s) ? 0 : 4 * (n + 1)) + (4 + v) * nz + gy * m + (5 * v + 16) * n;
     // dual: row pointers, indices + values, xbar gathered once, reads y, bhat,
-    // y_anchor, sense byte, writes y
-    *bytes_dual = 4 * (m + 1) + (4 + v) * nz + v * n + 4 * 8 * m + m;
+    // y_anchor, sense byte, writes y (and dy in the mixed mode)
+    *bytes_dual = 4 * (m + 1) + (4 + v) * nz + v * n + 4 * 8 * m + m + (s->fp32 ? 4 * m : 0);
 }
 } // namespace pdhg
 
@@ -90,7 +91,7 @@ void free_all(pdhg_solver *s)
                     s->hx,   s->hz,  s->feat_raw, s->feat_b, s->logits, s->lfix, s->lcount, s->sell_idx,
                     s->sell_val, s->sell_soff, s->sell_len, s->sell_wi_start, s->sell_wi, s->sell_part,
                     s->ypush, s->zpush, s->w0, s->aerr, s->aerr_t, s->ex, s->ety,
-                    s->aerr ? (void *)s->chc : nullptr, s->aerr ? (void *)s->bhc : nullptr};
+                    s->aerr ? (void *)s->chc : nullptr, s->aerr ? (void *)s->bhc : nullptr, s->dy};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->st_host) (void)hipHostFree(s->st_host);
@@ -179,7 +180,7 @@ int run_phase(pdhg_solver *s, int64_t iters, int mode, double t0)
 void solution_report(pdhg_solver *s, pdhg_kkt_report *k)
 {
     if (!s->has_candidate) HIPCHK(candidate_from_iterate(s));
-    HIPCHK(unscale(s, s->xp, s->yp, s->xu, s->yu));
+    HIPCHK(unscale(s, (const double *)s->xp, (const double *)s->yp, s->xu, s->yu));
     HIPCHK(report(s, s->xu, s->yu, s->zsol, k));
 }
 
@@ -224,15 +225,16 @@ bool run_batch_phase(pdhg_batch *b, int64_t iters, int mode, double t0)
     bool time_out = false;
     // algorithmic bytes of one primal / dual launch over the LPs that have not
     // stopped (tiles of stopped LPs exit at once), from the last host view
-    const int64_t vbytes = s->fp32 ? 4 : 8;
+    // (the single-LP byte model, per LP)
+    const double vbytes = s->fp32 ? 4.0 : 8.0, gy = s->fp32 ? 4.0 : 8.0, dyw = s->fp32 ? 4.0 : 0.0;
     auto active_bytes = [&](double &bp, double &bd) {
         bp = bd = 0.0;
         for (int i = 0; i < b->count; i++) {
             if (b->sts_host[i].done) continue;
-            const int64_t mi = b->roff[i + 1] - b->roff[i], ni = b->coff[i + 1] - b->coff[i];
+            const double mi = (double)(b->roff[i + 1] - b->roff[i]), ni = (double)(b->coff[i + 1] - b->coff[i]);
             const double nz = (double)b->nnz_of[i];
-            bp += 4.0 * (ni + 1) + (4.0 + vbytes) * nz + 8.0 * mi + 6.0 * vbytes * ni + 8.0 * ni;
-            bd += 4.0 * (mi + 1) + (4.0 + vbytes) * nz + (double)vbytes * ni + 33.0 * mi;
+            bp += 4.0 * (ni + 1) + (4.0 + vbytes) * nz + gy * mi + (5.0 * vbytes + 16.0) * ni;
+            bd += 4.0 * (mi + 1) + (4.0 + vbytes) * nz + vbytes * ni + (33.0 + dyw) * mi;
         }
     };
     HIPCHK(batch_compact_tiles(b, true));
@@ -457,7 +459,9 @@ static int build_solver(int m, int n, int nz, const pdhg_params &p, const ModelS
         auto vall = [&](void **ptr, size_t cnt) { hip_check(hipMalloc(ptr, vb * (cnt > 0 ? cnt : 1)), "hipMalloc"); };
         vall(&s->ahat, NZ);
         vall(&s->ahat_t, NZ);
-        for (void **q : {&s->x, &s->xa, &s->xbar, &s->xp, &s->lh, &s->uh, &s->xs}) vall(q, N);
+        for (void **q : {&s->x, &s->xbar, &s->lh, &s->uh}) vall(q, N);
+        for (void **q : {&s->xa, &s->xp, &s->xs}) // anchor, candidate, solution: float64
+            hip_check(hipMalloc(q, sizeof(double) * (N > 0 ? N : 1)), "hipMalloc");
         dalloc(&s->ch, N);
         for (void **q : {&s->y, &s->ya, &s->yp, &s->bh, &s->ys}) // m-vectors stay float64
             hip_check(hipMalloc(q, sizeof(double) * (M > 0 ? M : 1)), "hipMalloc");
@@ -468,6 +472,7 @@ static int build_solver(int m, int n, int nz, const pdhg_params &p, const ModelS
             dalloc(&s->ety, N);
             dalloc(&s->chc, N);
             dalloc(&s->bhc, M);
+            dalloc(&s->dy, M);
         } else {
             defect_alias(s);
         }
@@ -700,11 +705,10 @@ static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r
     const double t0 = now_s();
     try {
         hipStream_t st = s->stream;
-        const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
         // CP1: the solve's candidate (x, y) and z on the original model
-        HIPCHK(hipMemcpyAsync(s->xs, s->xp, vb * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(s->xs, s->xp, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(s->ys, s->yp, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
-        HIPCHK(unscale(s, s->xs, s->ys, s->xu, s->yu));
+        HIPCHK(unscale(s, (const double *)s->xs, (const double *)s->ys, s->xu, s->yu));
         HIPCHK(report(s, s->xu, s->yu, s->zsol, &r->before));
         if (s->p.push_gate && (double)r->before.candidates < gate_threshold(s->p, s->m)) {
             // section 4.2's selection rule: too few candidates to be worth a push
@@ -750,7 +754,7 @@ static int corner_push_common(pdhg_solver *s, uint64_t seed, pdhg_push_result *r
         int status = run_phase(s, s->p.push_max_iter, 2, t0);
         HIPCHK(push_compact_end(s, true));
         // CP7: (xhat, y, z)
-        if (s->has_candidate) HIPCHK(unscale(s, s->xp, nullptr, s->xpush, nullptr));
+        if (s->has_candidate) HIPCHK(unscale(s, (const double *)s->xp, nullptr, s->xpush, nullptr));
         else HIPCHK(hipMemcpyAsync(s->xpush, s->xu, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
         HIPCHK(report(s, s->xpush, s->yu, nullptr, &r->after));
         r->status = status;
@@ -805,14 +809,13 @@ int pdhg_dual_push(pdhg_solver *s, uint64_t seed, pdhg_dual_push_result *r)
     const double t0 = now_s();
     try {
         hipStream_t st = s->stream;
-        const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
         if (!s->ypush) dalloc(&s->ypush, (size_t)(s->m > 0 ? s->m : 1));
         if (!s->zpush) dalloc(&s->zpush, (size_t)(s->n > 0 ? s->n : 1));
         // DP1 (after the corner push, xs, ys, xu, yu already hold the solve's answer)
         if (!s->primal_pushed) {
-            HIPCHK(hipMemcpyAsync(s->xs, s->xp, vb * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(s->xs, s->xp, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
             HIPCHK(hipMemcpyAsync(s->ys, s->yp, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
-            HIPCHK(unscale(s, s->xs, s->ys, s->xu, s->yu));
+            HIPCHK(unscale(s, (const double *)s->xs, (const double *)s->ys, s->xu, s->yu));
         }
         const double *xk = cur_x(s);
         HIPCHK(report(s, xk, s->yu, s->zsol, &r->before));
@@ -831,7 +834,7 @@ int pdhg_dual_push(pdhg_solver *s, uint64_t seed, pdhg_dual_push_result *r)
         int status = run_phase(s, s->p.push_max_iter, 3, t0);
         // DP7
         if (s->has_candidate) {
-            HIPCHK(unscale(s, nullptr, s->yp, nullptr, s->ypush));
+            HIPCHK(unscale(s, nullptr, (const double *)s->yp, nullptr, s->ypush));
             HIPCHK(dual_push_finish(s)); // the solve's y on the dropped rows
         } else {
             HIPCHK(hipMemcpyAsync(s->ypush, s->yu, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
@@ -1003,8 +1006,9 @@ constexpr char kCkptMagic[8] = {'P', 'D', 'H', 'G', 'C', 'K', 'P', 'T'};
 
 int64_t ckpt_bytes(const pdhg_solver *s)
 {
+    // x in the working precision (mixed mode: its difference from x_a), x_a and x+ in float64, y, y_a, y+
     const int64_t vb = s->fp32 ? 4 : 8;
-    return (int64_t)sizeof(CkptHeader) + (int64_t)sizeof(DevState) + 3 * vb * s->n + 3 * 8 * (int64_t)s->m;
+    return (int64_t)sizeof(CkptHeader) + (int64_t)sizeof(DevState) + (vb + 16) * s->n + 3 * 8 * (int64_t)s->m;
 }
 } // namespace
 
@@ -1025,7 +1029,7 @@ int pdhg_get_state(pdhg_solver *s, void *buf, int64_t bytes)
         char *p = (char *)buf;
         CkptHeader h{};
         std::memcpy(h.magic, kCkptMagic, 8);
-        h.version = 1;
+        h.version = 2;
         h.m = s->m;
         h.n = s->n;
         h.fp32 = s->fp32 ? 1 : 0;
@@ -1038,10 +1042,11 @@ int pdhg_get_state(pdhg_solver *s, void *buf, int64_t bytes)
         p += sizeof(h);
         HIPCHK(hipMemcpyAsync(p, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
         p += sizeof(DevState);
-        const size_t xb = (size_t)(s->fp32 ? 4 : 8) * (size_t)s->n, yb = 8 * (size_t)s->m;
+        const size_t vb = (size_t)(s->fp32 ? 4 : 8) * (size_t)s->n, xb = 8 * (size_t)s->n, yb = 8 * (size_t)s->m;
         for (const void *src : {(const void *)s->x, (const void *)s->xa, (const void *)s->xp}) {
-            HIPCHK(hipMemcpyAsync(p, src, xb, hipMemcpyDeviceToHost, st));
-            p += xb;
+            const size_t nb = src == s->x ? vb : xb;
+            HIPCHK(hipMemcpyAsync(p, src, nb, hipMemcpyDeviceToHost, st));
+            p += nb;
         }
         for (const void *src : {(const void *)s->y, (const void *)s->ya, (const void *)s->yp}) {
             HIPCHK(hipMemcpyAsync(p, src, yb, hipMemcpyDeviceToHost, st));
@@ -1061,7 +1066,7 @@ int pdhg_set_state(pdhg_solver *s, const void *buf, int64_t bytes)
     CkptHeader h;
     if (bytes < (int64_t)sizeof(h)) return fail(PDHG_ERR_INVALID_ARG, "state buffer too small");
     std::memcpy(&h, buf, sizeof(h));
-    if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+    if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 2)
         return fail(PDHG_ERR_INVALID_ARG, "not a checkpoint of this library");
     if (h.m != s->m || h.n != s->n || h.fp32 != (s->fp32 ? 1 : 0) || h.bytes != ckpt_bytes(s) || bytes < h.bytes)
         return fail(PDHG_ERR_INVALID_ARG, "checkpoint of another LP size or precision");
@@ -1070,15 +1075,17 @@ int pdhg_set_state(pdhg_solver *s, const void *buf, int64_t bytes)
         const char *p = (const char *)buf + sizeof(h);
         HIPCHK(hipMemcpyAsync(s->st, p, sizeof(DevState), hipMemcpyHostToDevice, st));
         p += sizeof(DevState);
-        const size_t xb = (size_t)(s->fp32 ? 4 : 8) * (size_t)s->n, yb = 8 * (size_t)s->m;
+        const size_t vb = (size_t)(s->fp32 ? 4 : 8) * (size_t)s->n, xb = 8 * (size_t)s->n, yb = 8 * (size_t)s->m;
         for (void *dst : {(void *)s->x, (void *)s->xa, (void *)s->xp}) {
-            HIPCHK(hipMemcpyAsync(dst, p, xb, hipMemcpyHostToDevice, st));
-            p += xb;
+            const size_t nb = dst == s->x ? vb : xb;
+            HIPCHK(hipMemcpyAsync(dst, p, nb, hipMemcpyHostToDevice, st));
+            p += nb;
         }
         for (void *dst : {(void *)s->y, (void *)s->ya, (void *)s->yp}) {
             HIPCHK(hipMemcpyAsync(dst, p, yb, hipMemcpyHostToDevice, st));
             p += yb;
         }
+        HIPCHK(restore_dy(s)); // mixed mode: dy = y - y_a, as the dual half wrote it
         HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         s->t_host = h.t_host;
@@ -1100,7 +1107,7 @@ int pdhg_get_iterate(pdhg_solver *s, double *x, double *y)
         double *dx = nullptr, *dy = nullptr;
         dalloc(&dx, (size_t)s->n);
         dalloc(&dy, (size_t)s->m);
-        HIPCHK(unscale(s, s->x, s->y, dx, dy));
+        HIPCHK(unscale_iterate(s, dx, dy));
         if (x) HIPCHK(hipMemcpyAsync(x, dx, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost, st));
         if (y) HIPCHK(hipMemcpyAsync(y, dy, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToHost, st));
         hipError_t e = hipStreamSynchronize(st);
@@ -1321,7 +1328,7 @@ int pdhg_batch_solve(pdhg_batch *b, pdhg_result *results)
         pdhg_solver *s = b->s;
         const bool time_out = run_batch_phase(b, s->p.max_iter, 1, t0);
         if (b->t_host < s->p.check_every) HIPCHK(candidate_from_iterate(s));
-        HIPCHK(unscale(s, s->xp, s->yp, s->xu, s->yu));
+        HIPCHK(unscale(s, (const double *)s->xp, (const double *)s->yp, s->xu, s->yu));
         std::vector<pdhg_kkt_report> k((size_t)b->count);
         HIPCHK(batch_report(b, s->xu, s->yu, s->zsol, k.data()));
         b->solve_seconds = now_s() - t0;
@@ -1373,11 +1380,10 @@ static int batch_push_common(pdhg_batch *b, const uint64_t *seeds, pdhg_push_res
     try {
         pdhg_solver *s = b->s;
         hipStream_t st = s->stream;
-        const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
         for (int i = 0; i < b->count; i++) std::memset(&results[i], 0, sizeof(pdhg_push_result));
-        HIPCHK(hipMemcpyAsync(s->xs, s->xp, vb * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(s->xs, s->xp, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(s->ys, s->yp, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
-        HIPCHK(unscale(s, s->xs, s->ys, s->xu, s->yu));
+        HIPCHK(unscale(s, (const double *)s->xs, (const double *)s->ys, s->xu, s->yu));
         std::vector<pdhg_kkt_report> before((size_t)b->count), after((size_t)b->count);
         HIPCHK(batch_report(b, s->xu, s->yu, s->zsol, before.data()));
         std::vector<int> solve_status((size_t)b->count);
@@ -1412,7 +1418,7 @@ static int batch_push_common(pdhg_batch *b, const uint64_t *seeds, pdhg_push_res
         if (s->p.push_compact) HIPCHK(batch_push_compact_begin(b)); // the push on the free columns
         const bool time_out = run_batch_phase(b, s->p.push_max_iter, 2, t0);
         HIPCHK(batch_push_compact_end(b, true));
-        HIPCHK(unscale(s, s->xp, nullptr, s->xpush, nullptr));
+        HIPCHK(unscale(s, (const double *)s->xp, nullptr, s->xpush, nullptr));
         HIPCHK(batch_keep_unpushed(b));
         HIPCHK(batch_report(b, s->xpush, s->yu, nullptr, after.data()));
         b->push_seconds = now_s() - t0;
@@ -1486,15 +1492,14 @@ int pdhg_batch_dual_push(pdhg_batch *b, const uint64_t *seeds, pdhg_dual_push_re
     try {
         pdhg_solver *s = b->s;
         hipStream_t st = s->stream;
-        const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
         for (int i = 0; i < b->count; i++) std::memset(&results[i], 0, sizeof(pdhg_dual_push_result));
         if (!s->ypush) dalloc(&s->ypush, (size_t)(s->m > 0 ? s->m : 1));
         if (!s->zpush) dalloc(&s->zpush, (size_t)(s->n > 0 ? s->n : 1));
         if (!s->w0) dalloc(&s->w0, (size_t)(s->n > 0 ? s->n : 1));
         if (!b->pushed) { // DP1 (after the corner push the solve's answer is already in place)
-            HIPCHK(hipMemcpyAsync(s->xs, s->xp, vb * (size_t)s->n, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(s->xs, s->xp, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToDevice, st));
             HIPCHK(hipMemcpyAsync(s->ys, s->yp, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, st));
-            HIPCHK(unscale(s, s->xs, s->ys, s->xu, s->yu));
+            HIPCHK(unscale(s, (const double *)s->xs, (const double *)s->ys, s->xu, s->yu));
         }
         const double *xk = b->pushed ? s->xpush : s->xu;
         std::vector<pdhg_kkt_report> before((size_t)b->count), after((size_t)b->count);
@@ -1510,7 +1515,7 @@ int pdhg_batch_dual_push(pdhg_batch *b, const uint64_t *seeds, pdhg_dual_push_re
         b->t_host = 0;
         b->next_check = s->p.push_min_iters;
         const bool time_out = run_batch_phase(b, s->p.push_max_iter, 3, t0);
-        HIPCHK(unscale(s, nullptr, s->yp, nullptr, s->ypush));
+        HIPCHK(unscale(s, nullptr, (const double *)s->yp, nullptr, s->ypush));
         HIPCHK(batch_dual_push_finish(b));
         HIPCHK(batch_report(b, xk, s->ypush, s->zpush, after.data()));
         const double secs = now_s() - t0;

@@ -145,10 +145,10 @@ template <typename V>
 __global__ __launch_bounds__(kBlock) void k_gather_free(int nf, const int *__restrict__ keep, const double *__restrict__ ch,
                                                        const double *__restrict__ dc, const V *__restrict__ lh,
                                                        const V *__restrict__ uh, const V *__restrict__ x,
-                                                       const V *__restrict__ xa, const V *__restrict__ xp,
+                                                       const double *__restrict__ xa, const double *__restrict__ xp,
                                                        double *__restrict__ chc, double *__restrict__ dcc,
                                                        V *__restrict__ lhc, V *__restrict__ uhc, V *__restrict__ xc,
-                                                       V *__restrict__ xac, V *__restrict__ xpc)
+                                                       double *__restrict__ xac, double *__restrict__ xpc)
 {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= nf) return;
@@ -163,13 +163,15 @@ __global__ __launch_bounds__(kBlock) void k_gather_free(int nf, const int *__res
 }
 
 // back to the full vectors: free columns from the compact ones, fixed
-// columns at their bound (their x+ at every push iteration)
+// columns at their bound (their x+ at every push iteration; in the mixed
+// mode as the anchor, stored difference 0)
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_expand(int n, const int *__restrict__ flag, const int *__restrict__ newid,
                                                   const V *__restrict__ lh, const V *__restrict__ xc,
-                                                  const V *__restrict__ xac, const V *__restrict__ xpc,
-                                                  V *__restrict__ x, V *__restrict__ xa, V *__restrict__ xp)
+                                                  const double *__restrict__ xac, const double *__restrict__ xpc,
+                                                  V *__restrict__ x, double *__restrict__ xa, double *__restrict__ xp)
 {
+    constexpr bool delta = sizeof(V) == sizeof(float);
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
     if (flag[j]) {
@@ -178,9 +180,10 @@ __global__ __launch_bounds__(kBlock) void k_expand(int n, const int *__restrict_
         xa[j] = xac[k];
         xp[j] = xpc[k];
     } else {
-        x[j] = lh[j];
-        xa[j] = lh[j];
-        xp[j] = lh[j];
+        const double v = (double)lh[j];
+        x[j] = delta ? (V)0 : lh[j];
+        xa[j] = v;
+        xp[j] = v;
     }
 }
 
@@ -305,12 +308,15 @@ hipError_t begin_impl(pdhg_solver *s)
     if ((e = alloc(&c.ch, (size_t)nf)) != hipSuccess) return e;
     if ((e = alloc(&c.dc, (size_t)nf)) != hipSuccess) return e;
     V **vecs[] = {reinterpret_cast<V **>(&c.lh), reinterpret_cast<V **>(&c.uh), reinterpret_cast<V **>(&c.x),
-                  reinterpret_cast<V **>(&c.xa), reinterpret_cast<V **>(&c.xbar), reinterpret_cast<V **>(&c.xp)};
+                  reinterpret_cast<V **>(&c.xbar)};
     for (V **q : vecs)
         if ((e = alloc(q, (size_t)nf)) != hipSuccess) return e;
+    for (double **q : {reinterpret_cast<double **>(&c.xa), reinterpret_cast<double **>(&c.xp)}) // float64 anchor, candidate
+        if ((e = alloc(q, (size_t)nf)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_gather_free<V>), dim3(grid_for(nf, kBlock, 1 << 30)), dim3(kBlock), 0, st, nf, c.keep,
-                       s->ch, s->dc, (const V *)s->lh, (const V *)s->uh, (const V *)s->x, (const V *)s->xa,
-                       (const V *)s->xp, c.ch, c.dc, (V *)c.lh, (V *)c.uh, (V *)c.x, (V *)c.xa, (V *)c.xp);
+                       s->ch, s->dc, (const V *)s->lh, (const V *)s->uh, (const V *)s->x, (const double *)s->xa,
+                       (const double *)s->xp, c.ch, c.dc, (V *)c.lh, (V *)c.uh, (V *)c.x, (double *)c.xa,
+                       (double *)c.xp);
     if (lfix) {
         if ((e = alloc(&c.lfix, (size_t)nf)) != hipSuccess) return e;
         if ((e = alloc(&c.l, (size_t)nf)) != hipSuccess) return e;
@@ -392,8 +398,8 @@ hipError_t end_impl(pdhg_solver *s, bool scatter)
     hipError_t e = hipSuccess;
     if (scatter)
         hipLaunchKernelGGL((k_expand<V>), dim3(grid_for(c.n0, kBlock, 1 << 30)), dim3(kBlock), 0, s->stream, c.n0,
-                           c.flag, c.newid, (const V *)c.lh0, (const V *)c.x, (const V *)c.xa, (const V *)c.xp,
-                           (V *)c.x0, (V *)c.xa0, (V *)c.xp0);
+                           c.flag, c.newid, (const V *)c.lh0, (const V *)c.x, (const double *)c.xa,
+                           (const double *)c.xp, (V *)c.x0, (double *)c.xa0, (double *)c.xp0);
     e = hipGetLastError();
     const hipError_t e2 = hipStreamSynchronize(s->stream); // the compact arrays are freed below
     if (e == hipSuccess) e = e2;

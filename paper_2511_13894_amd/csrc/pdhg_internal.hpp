@@ -100,19 +100,24 @@ struct pdhg_solver {
     // scaling
     double *dr = nullptr, *dc = nullptr;
 
-    // iteration arrays in the working precision (float or double)
+    // iteration arrays: the matrix, lhat, uhat, x and xbar in the working
+    // precision (float or double); in the mixed mode x and xbar hold the
+    // differences x - x_a and xbar - x_a from the float64 anchor.  The anchors,
+    // the candidate (xp, yp), the solve's solution (xs, ys) and every m-vector
+    // are float64 in both precisions.
     void *ahat = nullptr, *ahat_t = nullptr;
     void *x = nullptr, *y = nullptr, *xa = nullptr, *ya = nullptr, *xbar = nullptr;
     void *xp = nullptr, *yp = nullptr;
-    double *ch = nullptr;            // scaled objective, float64 in both precisions
+    float *dy = nullptr;             // mixed mode: y - y_a, the vector the primal half gathers
+    double *ch = nullptr;            // scaled objective
     void *bh = nullptr, *lh = nullptr, *uh = nullptr;
     // Mixed precision: the rounding error of the float matrix, E = Ahat -
     // fl32(Ahat), stored as float in A order and transpose order, so that
-    // fl32(Ahat) v + E v is the float64 product; ex = E x+ and ety = E' y+ of
-    // the last check.  The iteration kernels read chc and bhc: in float64
-    // mode the same arrays as ch and bh; in the mixed mode ch - E' y_a and
-    // bh - E x_a at the anchor (x_a, y_a), so that at the anchor the float
-    // matrix gives the float64 residuals (defect correction).
+    // fl32(Ahat) v + E v is the float64 product (ex, ety: the error parts of
+    // a product).  The iteration kernels read chc and bhc: in float64 mode
+    // the same arrays as ch and bh; in the mixed mode ch - Ahat' y_a and
+    // bh - Ahat x_a at the anchor (x_a, y_a) in float64, which the float
+    // products of the differences complete.
     void *aerr = nullptr, *aerr_t = nullptr;
     double *ex = nullptr, *ety = nullptr;
     double *chc = nullptr, *bhc = nullptr;
@@ -287,6 +292,12 @@ hipError_t exact_product(pdhg_solver *s, bool transpose, const double *vec, doub
 hipError_t defect_refresh(pdhg_solver *s);
 // udeg_at: the common entry count of every column (1..3) of the current model, or 0
 hipError_t detect_uniform_columns(pdhg_solver *s);
+// the primal half runs the uniform-column kernel: columns of 1-3 entries each,
+// 256-row tiles chosen by the library (an explicit lanes_at keeps the tiles)
+inline bool uses_uniform_kernel(const pdhg_solver *s)
+{
+    return s->kern_at == -256 && s->p.lanes_at == 0 && s->udeg_at >= 1 && s->udeg_at <= 3;
+}
 // float64 mode: chc and bhc follow ch and bh (after any swap of those arrays)
 inline void defect_alias(pdhg_solver *s)
 {
@@ -310,7 +321,9 @@ hipError_t launch_check(pdhg_solver *s, int mode, int len);
 hipError_t launch_advance(pdhg_solver *s, int len);
 hipError_t candidate_from_iterate(pdhg_solver *s);
 hipError_t launch_start_vectors(pdhg_solver *s, bool fresh_start);
-hipError_t unscale(pdhg_solver *s, const void *xh, const void *yh, double *xo, double *yo);
+hipError_t unscale(pdhg_solver *s, const double *xh, const double *yh, double *xo, double *yo);
+hipError_t unscale_iterate(pdhg_solver *s, double *xo, double *yo); // the current iterate (x, y), unscaled
+hipError_t restore_dy(pdhg_solver *s); // mixed mode: dy = y - y_a (nothing in float64 mode)
 hipError_t report(pdhg_solver *s, const double *x, const double *y, double *z, pdhg_kkt_report *k);
 hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, double theta);
 hipError_t dual_push_setup(pdhg_solver *s, uint64_t seed, const double *xk, double *w0, double *yn, double *atyn,

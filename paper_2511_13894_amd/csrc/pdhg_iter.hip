@@ -13,11 +13,12 @@ namespace pdhg {
 // ------------------------------------------------------------ iteration ---
 template <typename V, int L>
 __global__ __launch_bounds__(kBlock) void k_primal(int n, const int *__restrict__ tp, const int *__restrict__ ti,
-                                                  const V *__restrict__ atv, const double *__restrict__ y,
+                                                  const V *__restrict__ atv, const V *__restrict__ y,
                                                   const double *__restrict__ ch, const V *__restrict__ lh,
                                                   const V *__restrict__ uh, V *__restrict__ x,
-                                                  const V *__restrict__ xa, V *__restrict__ xbar, V *__restrict__ xp,
-                                                  const DevState *__restrict__ st, int i, int store_cand)
+                                                  const double *__restrict__ xa, V *__restrict__ xbar,
+                                                  double *__restrict__ xp, const DevState *__restrict__ st, int i,
+                                                  int store_cand)
 {
     const int64_t gi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int64_t j = gi / L;
@@ -26,7 +27,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(int n, const int *__restrict_
     // the epilogue's operands are loaded by every lane of the group (one
     // request per group) before the product, and the stop flag after them,
     // so their latencies overlap
-    const double xj = (double)x[j], cj = (double)ch[j], lo = (double)lh[j], hi = (double)uh[j], aj = (double)xa[j];
+    const double aj = xa[j], xj = iterate_value<V>(x[j], aj), cj = ch[j], lo = (double)lh[j], hi = (double)uh[j];
     if (st->done) return;
     double acc = lane_dot<L, double>(tp[j], tp[j + 1], lane, ti, atv, y);
     acc = group_sum<L>(acc);
@@ -40,8 +41,8 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
                                                 const V *__restrict__ av, const V *__restrict__ xbar,
                                                 const double *__restrict__ bh, const int8_t *__restrict__ sense,
                                                 double *__restrict__ y, const double *__restrict__ ya,
-                                                double *__restrict__ yp, const DevState *__restrict__ st, int i,
-                                                int store_cand)
+                                                double *__restrict__ yp, float *__restrict__ dy,
+                                                const DevState *__restrict__ st, int i, int store_cand)
 {
     const int64_t gi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int64_t r = gi / L;
@@ -53,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
     double acc = lane_dot<L, double>(rp[r], rp[r + 1], lane, ci, av, xbar);
     acc = group_sum<L>(acc);
     if (lane != 0) return;
-    dual_update(r, acc, yr, br, ar, sn, y, yp, st, i, store_cand);
+    dual_update(r, acc, yr, br, ar, sn, y, yp, dy, st, i, store_cand);
 }
 
 // ------------------------------------------------------- long rows ---
@@ -196,23 +197,23 @@ hipError_t solver_product(pdhg_solver *s, bool transpose, const double *vec, dou
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_primal_rowblock(int n, const int *__restrict__ tp,
                                                            const int *__restrict__ ti, const V *__restrict__ atv,
-                                                           const double *__restrict__ y, const double *__restrict__ ch,
+                                                           const V *__restrict__ y, const double *__restrict__ ch,
                                                            const V *__restrict__ lh, const V *__restrict__ uh,
-                                                           V *__restrict__ x, const V *__restrict__ xa,
-                                                           V *__restrict__ xbar, V *__restrict__ xp,
+                                                           V *__restrict__ x, const double *__restrict__ xa,
+                                                           V *__restrict__ xbar, double *__restrict__ xp,
                                                            const DevState *__restrict__ st, int i, int store_cand)
 {
     if (st->done) return;
     const int j = xcd_block(blockIdx.x, gridDim.x);
     double xj = 0, cj = 0, lo = 0, hi = 0, aj = 0;
     if (threadIdx.x == 0) {
-        xj = (double)x[j];
+        aj = xa[j];
+        xj = iterate_value<V>(x[j], aj);
         cj = ch[j];
         lo = (double)lh[j];
         hi = (double)uh[j];
-        aj = (double)xa[j];
     }
-    const double g = row_block_sum<V, double>(tp[j], tp[j + 1], ti, atv, y);
+    const double g = row_block_sum<V, V>(tp[j], tp[j + 1], ti, atv, y);
     if (threadIdx.x == 0) primal_update<V>(j, g, xj, cj, lo, hi, aj, x, xbar, xp, st, i, store_cand);
 }
 
@@ -222,7 +223,8 @@ __global__ __launch_bounds__(kBlock) void k_dual_rowblock(int m, const int *__re
                                                          const double *__restrict__ bh,
                                                          const int8_t *__restrict__ sense, double *__restrict__ y,
                                                          const double *__restrict__ ya, double *__restrict__ yp,
-                                                         const DevState *__restrict__ st, int i, int store_cand)
+                                                         float *__restrict__ dy, const DevState *__restrict__ st, int i,
+                                                         int store_cand)
 {
     if (st->done) return;
     const int r = xcd_block(blockIdx.x, gridDim.x);
@@ -235,16 +237,16 @@ __global__ __launch_bounds__(kBlock) void k_dual_rowblock(int m, const int *__re
         sn = sense[r];
     }
     const double h = row_block_sum<V, V>(rp[r], rp[r + 1], ci, av, xbar);
-    if (threadIdx.x == 0) dual_update(r, h, yr, br, ar, sn, y, yp, st, i, store_cand);
+    if (threadIdx.x == 0) dual_update(r, h, yr, br, ar, sn, y, yp, dy, st, i, store_cand);
 }
 
 template <typename V, int T, int NT>
 __global__ __launch_bounds__(NT) void k_primal_tiled(int n, const int *__restrict__ tp, const int *__restrict__ ti,
-                                                    const V *__restrict__ atv, const double *__restrict__ y,
+                                                    const V *__restrict__ atv, const V *__restrict__ y,
                                                     const double *__restrict__ ch, const V *__restrict__ lh,
                                                     const V *__restrict__ uh, V *__restrict__ x,
-                                                    const V *__restrict__ xa, V *__restrict__ xbar,
-                                                    V *__restrict__ xp, const DevState *__restrict__ st, int i,
+                                                    const double *__restrict__ xa, V *__restrict__ xbar,
+                                                    double *__restrict__ xp, const DevState *__restrict__ st, int i,
                                                     int store_cand)
 {
     __shared__ int s_ptr[T + 1];
@@ -260,10 +262,10 @@ __global__ __launch_bounds__(NT) void k_primal_tiled(int n, const int *__restric
     // branch, and the stop flag is read after them so its latency overlaps
     // theirs.  The flag is uniform: the whole workgroup leaves together.
     const int jc = mine ? j : r0;
-    const double xj = (double)x[jc], cj = (double)ch[jc], lo = (double)lh[jc], hi = (double)uh[jc],
-                 aj = (double)xa[jc];
+    const double aj = xa[jc], xj = iterate_value<V>(x[jc], aj), cj = ch[jc], lo = (double)lh[jc],
+                 hi = (double)uh[jc];
     if (st->done) return;
-    tile_row_sums<V, double, T, NT>(r0, rows, tp, ti, atv, y, s_ptr, s_prod, s_sum);
+    tile_row_sums<V, V, T, NT>(r0, rows, tp, ti, atv, y, s_ptr, s_prod, s_sum);
     if (!mine) return;
     primal_update<V>(j, s_sum[tid], xj, cj, lo, hi, aj, x, xbar, xp, st, i, store_cand);
 }
@@ -273,8 +275,8 @@ __global__ __launch_bounds__(NT) void k_dual_tiled(int m, const int *__restrict_
                                                   const V *__restrict__ av, const V *__restrict__ xbar,
                                                   const double *__restrict__ bh, const int8_t *__restrict__ sense,
                                                   double *__restrict__ y, const double *__restrict__ ya,
-                                                  double *__restrict__ yp, const DevState *__restrict__ st, int i,
-                                                  int store_cand)
+                                                  double *__restrict__ yp, float *__restrict__ dy,
+                                                  const DevState *__restrict__ st, int i, int store_cand)
 {
     __shared__ int s_ptr[T + 1];
     __shared__ double s_prod[kTileU * NT];
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(NT) void k_dual_tiled(int m, const int *__restrict_
     if (st->done) return;
     tile_row_sums<V, V, T, NT>(r0, rows, rp, ci, av, xbar, s_ptr, s_prod, s_sum);
     if (!mine) return;
-    dual_update(r, s_sum[tid], yr, br, ar, sn, y, yp, st, i, store_cand);
+    dual_update(r, s_sum[tid], yr, br, ar, sn, y, yp, dy, st, i, store_cand);
 }
 
 // Primal half when every column of A has the same D <= 3 entries (every
@@ -302,10 +304,10 @@ __global__ __launch_bounds__(NT) void k_dual_tiled(int m, const int *__restrict_
 // tiles (one thread per row) sum them: the two give the same bits.
 template <typename V, int D>
 __global__ __launch_bounds__(kBlock) void k_primal_udeg(int n, const int *__restrict__ ti, const V *__restrict__ atv,
-                                                       const double *__restrict__ y, const double *__restrict__ ch,
+                                                       const V *__restrict__ y, const double *__restrict__ ch,
                                                        const V *__restrict__ lh, const V *__restrict__ uh,
-                                                       V *__restrict__ x, const V *__restrict__ xa,
-                                                       V *__restrict__ xbar, V *__restrict__ xp,
+                                                       V *__restrict__ x, const double *__restrict__ xa,
+                                                       V *__restrict__ xbar, double *__restrict__ xp,
                                                        const DevState *__restrict__ st, int i, int store_cand)
 {
     const int64_t j = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
@@ -317,11 +319,11 @@ __global__ __launch_bounds__(kBlock) void k_primal_udeg(int n, const int *__rest
         id[d] = ti[j * D + d];
         v[d] = (double)atv[j * D + d];
     }
-    const double xj = (double)x[j], cj = (double)ch[j], lo = (double)lh[j], hi = (double)uh[j], aj = (double)xa[j];
+    const double aj = xa[j], xj = iterate_value<V>(x[j], aj), cj = ch[j], lo = (double)lh[j], hi = (double)uh[j];
     if (st->done) return;
     double g[D];
 #pragma unroll
-    for (int d = 0; d < D; d++) g[d] = y[id[d]];
+    for (int d = 0; d < D; d++) g[d] = (double)y[id[d]];
     double acc = 0.0;
     {
 #pragma clang fp contract(off)
@@ -337,15 +339,16 @@ static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = null
 {
     const int L = s->kern_at;
     if (s->n <= 0) return;
+    const void *yg = s->fp32 ? (const void *)s->dy : s->y; // the dual vector the products gather
     // uniform columns, kernel chosen by the library: the 256-row tiles' sums with fewer loads
     // (an explicit lanes_at = -256 keeps the tiles)
-    if (L == -256 && s->p.lanes_at == 0 && s->udeg_at >= 1 && s->udeg_at <= 3) {
+    if (uses_uniform_kernel(s)) {
         const int grid = (s->n + kBlock - 1) / kBlock;
 #define PDHG_UD_CASE(DD)                                                                                       \
     case DD:                                                                                                   \
         PDHG_LAUNCH(e0, e1, (k_primal_udeg<V, DD>), dim3(grid), dim3(kBlock), s->stream, s->n, s->ti,        \
-                    (const V *)s->ahat_t, (const double *)s->y, s->chc, (const V *)s->lh, (const V *)s->uh,    \
-                    (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i, store);                   \
+                    (const V *)s->ahat_t, (const V *)yg, s->chc, (const V *)s->lh, (const V *)s->uh,    \
+                    (V *)s->x, (const double *)s->xa, (V *)s->xbar, (double *)s->xp, s->st, i, store);                   \
         break;
         switch (s->udeg_at) {
             PDHG_UD_CASE(1)
@@ -358,8 +361,8 @@ static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = null
     }
     if (L == kRowBlock) {
         PDHG_LAUNCH(e0, e1, (k_primal_rowblock<V>), dim3(s->n), dim3(kBlock), s->stream, s->n, s->tp, s->ti,
-                    (const V *)s->ahat_t, (const double *)s->y, s->chc, (const V *)s->lh, (const V *)s->uh,
-                    (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i, store);
+                    (const V *)s->ahat_t, (const V *)yg, s->chc, (const V *)s->lh, (const V *)s->uh,
+                    (V *)s->x, (const double *)s->xa, (V *)s->xbar, (double *)s->xp, s->st, i, store);
         return;
     }
     if (L < 0) { // LDS-tiled kernel: -T (256 threads) or -(1000 + T) (64 threads)
@@ -369,8 +372,8 @@ static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = null
 #define PDHG_PT_CASE(TT, RR, NT)                                                                                \
     case TT:                                                                                                    \
         PDHG_LAUNCH(e0, e1, (k_primal_tiled<V, RR, NT>), dim3(grid), dim3(NT), s->stream, s->n, s->tp, s->ti, \
-                           (const V *)s->ahat_t, (const double *)s->y, s->chc, (const V *)s->lh,          \
-                           (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i,  \
+                           (const V *)s->ahat_t, (const V *)yg, s->chc, (const V *)s->lh,          \
+                           (const V *)s->uh, (V *)s->x, (const double *)s->xa, (V *)s->xbar, (double *)s->xp, s->st, i,  \
                            store);                                                                              \
         break;
         switch (T) {
@@ -389,8 +392,8 @@ static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = null
 #define PDHG_PRIMAL_CASE(LL)                                                                                    \
     case LL:                                                                                                    \
         PDHG_LAUNCH(e0, e1, (k_primal<V, LL>), dim3(grid), dim3(kBlock), s->stream, s->n, s->tp, s->ti,      \
-                           (const V *)s->ahat_t, (const double *)s->y, s->chc, (const V *)s->lh,          \
-                           (const V *)s->uh, (V *)s->x, (const V *)s->xa, (V *)s->xbar, (V *)s->xp, s->st, i,  \
+                           (const V *)s->ahat_t, (const V *)yg, s->chc, (const V *)s->lh,          \
+                           (const V *)s->uh, (V *)s->x, (const double *)s->xa, (V *)s->xbar, (double *)s->xp, s->st, i,  \
                            store);                                                                              \
         break;
     switch (L) {
@@ -418,7 +421,7 @@ static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullpt
     if (L == kRowBlock) {
         PDHG_LAUNCH(e0, e1, (k_dual_rowblock<V>), dim3(s->m), dim3(kBlock), s->stream, s->m, s->rp, s->ci,
                     (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense, (double *)s->y,
-                    (const double *)s->ya, (double *)s->yp, s->st, i, store);
+                    (const double *)s->ya, (double *)s->yp, s->dy, s->st, i, store);
         return;
     }
     if (L < 0) {
@@ -429,7 +432,7 @@ static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullpt
     case TT:                                                                                                    \
         PDHG_LAUNCH(e0, e1, (k_dual_tiled<V, RR, NT>), dim3(grid), dim3(NT), s->stream, s->m, s->rp, s->ci,   \
                            (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense, (double *)s->y,\
-                           (const double *)s->ya, (double *)s->yp, s->st, i, store);                                      \
+                           (const double *)s->ya, (double *)s->yp, s->dy, s->st, i, store);                                      \
         break;
         switch (T) {
             PDHG_DT_CASE(32, 32, 256)
@@ -448,7 +451,7 @@ static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullpt
     case LL:                                                                                                    \
         PDHG_LAUNCH(e0, e1, (k_dual<V, LL>), dim3(grid), dim3(kBlock), s->stream, s->m, s->rp, s->ci,        \
                            (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense, (double *)s->y,\
-                           (const double *)s->ya, (double *)s->yp, s->st, i, store);                                      \
+                           (const double *)s->ya, (double *)s->yp, s->dy, s->st, i, store);                                      \
         break;
     switch (L) {
         PDHG_DUAL_CASE(1)
@@ -516,8 +519,8 @@ template <typename V>
 __global__ __launch_bounds__(kBlock) void k_check_cols(int n, double *__restrict__ aty, const double *__restrict__ ety,
                                                       const double *__restrict__ ch,
                                                       const V *__restrict__ lh, const V *__restrict__ uh,
-                                                      const double *__restrict__ dc, const V *__restrict__ xc,
-                                                      const V *__restrict__ xa, const double *__restrict__ c0,
+                                                      const double *__restrict__ dc, const double *__restrict__ xc,
+                                                      const double *__restrict__ xa, const double *__restrict__ c0,
                                                       const double *__restrict__ l0, const double *__restrict__ u0,
                                                       int orig, double *__restrict__ part, int nblk,
                                                       const DevState *st)
@@ -537,8 +540,8 @@ __global__ __launch_bounds__(kBlock) void k_check_cols(int n, double *__restrict
         const double zm = (!is_inf_up(hi) && lam < 0.0) ? -lam : 0.0;
         const double rd = lam - (zp - zm);
         const double rdu = rd / dc[j];
-        const double xj = (double)xc[j];
-        const double dx = xj - (double)xa[j];
+        const double xj = xc[j];
+        const double dx = xj - xa[j];
         v[0] += rd * rd;
         v[1] += rdu * rdu;
         v[2] = fmax(v[2], fabs(rdu));
@@ -573,40 +576,50 @@ __global__ __launch_bounds__(kBlock) void k_check_final(DevState *st, const doub
     if (threadIdx.x == 0) check_decide(st, v, mode, len);
 }
 
-// On restart: x = x_anchor = x+, y = y_anchor = y+ (candidate of the check).
+// On restart: x = x_anchor = x+, y = y_anchor = y+ (candidate of the check);
+// in the mixed mode the stored differences x - x_a and dy = y - y_a become 0.
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_restart_apply(int n, int m, const DevState *st, V *__restrict__ x,
-                                                         V *__restrict__ xa, const V *__restrict__ xp,
+                                                         double *__restrict__ xa, const double *__restrict__ xp,
                                                          double *__restrict__ y, double *__restrict__ ya,
-                                                         const double *__restrict__ yp)
+                                                         const double *__restrict__ yp, float *__restrict__ dy)
 {
+    constexpr bool delta = sizeof(V) == sizeof(float);
     if (!st->restart_flag || st->done) return;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
         if (i < n) {
-            const V v = xp[i];
-            x[i] = v;
+            const double v = xp[i];
+            x[i] = delta ? (V)0 : (V)v;
             xa[i] = v;
         } else {
             const int64_t r = i - n;
             const double v = yp[r];
             y[r] = v;
             ya[r] = v;
+            if (dy) dy[r] = 0.0f;
         }
     }
 }
 
-// Defect correction (mixed mode): at a restart the candidate becomes the
-// anchor, so chc = ch - E' y+ and bhc = bh - E x+ from the check's error
-// products; with `always` (a phase start) regardless of the restart flag.
+// Anchored objective and right-hand side (mixed mode): chc = ch - (pa + pb)
+// and bhc = bh - (qa + qb), where pa + pb = Ahat' y_a and qa + qb = Ahat x_a
+// in float64 (pb, qb may be NULL; pa, qa may be the outputs themselves).  At
+// a restart the candidate becomes the anchor and the check has just left its
+// float64 products in aty and ax; with `always` (a phase start) regardless
+// of the restart flag.
 __global__ __launch_bounds__(kBlock) void k_defect_set(int n, int m, const DevState *st, int always,
-                                                      const double *__restrict__ ch, const double *__restrict__ ety,
-                                                      double *__restrict__ chc, const double *__restrict__ bh,
-                                                      const double *__restrict__ ex, double *__restrict__ bhc)
+                                                      const double *ch, const double *pa, const double *pb,
+                                                      double *chc, const double *bh, const double *qa,
+                                                      const double *qb, double *bhc)
 {
     if (!always && (!st->restart_flag || st->done)) return;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
-        if (i < n) chc[i] = ch[i] - ety[i];
-        else bhc[i - n] = bh[i - n] - ex[i - n];
+        if (i < n) {
+            chc[i] = ch[i] - (pb ? pa[i] + pb[i] : pa[i]);
+        } else {
+            const int64_t r = i - n;
+            bhc[r] = bh[r] - (qb ? qa[r] + qb[r] : qa[r]);
+        }
     }
 }
 
@@ -622,14 +635,14 @@ __global__ void k_advance(DevState *st, int len)
 static int err_kern_a(const pdhg_solver *s) { return s->kern_a == kSell ? s->lanes_a : s->kern_a; }
 
 template <typename V>
-static void check_impl(pdhg_solver *s, const V *xc, const double *yc, double *pm, double *pn)
+static void check_impl(pdhg_solver *s, const double *xc, const double *yc, double *pm, double *pn)
 {
     hipStream_t st = s->stream;
     if (s->kern_a == kSell) sell_product(s, xc, s->ax);
-    else check_spmv<V, V>(st, s->kern_a, s->m, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
+    else check_spmv<V, double>(st, s->kern_a, s->m, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
     check_spmv<V, double>(st, s->kern_at, s->n, s->tp, s->ti, (const V *)s->ahat_t, yc, s->aty);
     if (s->aerr) { // mixed mode: the float64 products are these plus E xc and E' yc
-        check_spmv<float, V>(st, err_kern_a(s), s->m, s->rp, s->ci, (const float *)s->aerr, xc, s->ex);
+        check_spmv<float, double>(st, err_kern_a(s), s->m, s->rp, s->ci, (const float *)s->aerr, xc, s->ex);
         check_spmv<float, double>(st, s->kern_at, s->n, s->tp, s->ti, (const float *)s->aerr_t, yc, s->ety);
     }
     const int gm = s->red_blocks_m, gn = s->red_blocks_n;
@@ -637,7 +650,7 @@ static void check_impl(pdhg_solver *s, const V *xc, const double *yc, double *pm
                        (const double *)s->bh, s->sense, s->dr, yc, (const double *)s->ya, pm, gm, s->st);
     hipLaunchKernelGGL((k_check_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->aty,
                        (const double *)(s->aerr ? s->ety : nullptr), s->ch,
-                       (const V *)s->lh, (const V *)s->uh, s->dc, xc, (const V *)s->xa, s->c, s->l, s->u,
+                       (const V *)s->lh, (const V *)s->uh, s->dc, xc, (const double *)s->xa, s->c, s->l, s->u,
                        s->model_original ? 1 : 0, pn, gn, s->st);
 }
 
@@ -647,11 +660,11 @@ hipError_t launch_check(pdhg_solver *s, int mode, int len)
     const int gm = s->red_blocks_m, gn = s->red_blocks_n;
     double *pm = s->partials;
     double *pn = s->partials + (size_t)(Q_COUNT + 1) * gm;
-    if (s->fp32)
-        check_impl<float>(s, (const float *)(use_cand ? s->xp : s->x), (const double *)(use_cand ? s->yp : s->y), pm, pn);
-    else
-        check_impl<double>(s, (const double *)(use_cand ? s->xp : s->x), (const double *)(use_cand ? s->yp : s->y), pm,
-                           pn);
+    // mode 0 checks the iterate at a phase start, where it is the anchor
+    // (in the mixed mode x holds its difference from x_a, which is 0 there)
+    const double *xc = (const double *)(use_cand ? s->xp : (s->fp32 ? s->xa : s->x));
+    if (s->fp32) check_impl<float>(s, xc, (const double *)(use_cand ? s->yp : s->y), pm, pn);
+    else check_impl<double>(s, xc, (const double *)(use_cand ? s->yp : s->y), pm, pn);
     hipLaunchKernelGGL(k_check_final, dim3(1), dim3(kBlock), 0, s->stream, s->st, pm, gm, pn, gn, mode, len);
     if (mode == 1 && s->hx) { // restart history for the learned push (before the restart copies)
         hipError_t e = launch_record_history(s);
@@ -663,17 +676,18 @@ hipError_t launch_check(pdhg_solver *s, int mode, int len)
     }
     if (mode != 0) {
         const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
-        if (s->aerr)
-            hipLaunchKernelGGL(k_defect_set, dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->st, 0, s->ch, s->ety,
-                               s->chc, (const double *)s->bh, s->ex, s->bhc);
+        if (s->aerr) // the check left Ahat x+ and Ahat' y+ (float64) in ax and aty
+            hipLaunchKernelGGL(k_defect_set, dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->st, 0, s->ch,
+                               (const double *)s->aty, (const double *)nullptr, s->chc, (const double *)s->bh,
+                               (const double *)s->ax, (const double *)nullptr, s->bhc);
         if (s->fp32)
             hipLaunchKernelGGL((k_restart_apply<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->st,
-                               (float *)s->x, (float *)s->xa, (const float *)s->xp, (double *)s->y, (double *)s->ya,
-                               (const double *)s->yp);
+                               (float *)s->x, (double *)s->xa, (const double *)s->xp, (double *)s->y, (double *)s->ya,
+                               (const double *)s->yp, s->dy);
         else
             hipLaunchKernelGGL((k_restart_apply<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->st,
                                (double *)s->x, (double *)s->xa, (const double *)s->xp, (double *)s->y, (double *)s->ya,
-                               (const double *)s->yp);
+                               (const double *)s->yp, (float *)nullptr);
     }
     return hipGetLastError();
 }
@@ -716,12 +730,17 @@ hipError_t defect_refresh(pdhg_solver *s)
         return hipSuccess;
     }
     hipStream_t st = s->stream;
-    check_spmv<float, float>(st, err_kern_a(s), s->m, s->rp, s->ci, (const float *)s->aerr, (const float *)s->xa, s->ex);
-    check_spmv<float, double>(st, s->kern_at, s->n, s->tp, s->ti, (const float *)s->aerr_t, (const double *)s->ya,
-                              s->ety);
+    const double *xa = (const double *)s->xa, *ya = (const double *)s->ya;
+    // fl32(Ahat) x_a and fl32(Ahat)' y_a into bhc and chc, E x_a and E' y_a into ex and ety
+    if (s->kern_a == kSell) sell_product(s, xa, s->bhc);
+    else check_spmv<float, double>(st, s->kern_a, s->m, s->rp, s->ci, (const float *)s->ahat, xa, s->bhc);
+    check_spmv<float, double>(st, s->kern_at, s->n, s->tp, s->ti, (const float *)s->ahat_t, ya, s->chc);
+    check_spmv<float, double>(st, err_kern_a(s), s->m, s->rp, s->ci, (const float *)s->aerr, xa, s->ex);
+    check_spmv<float, double>(st, s->kern_at, s->n, s->tp, s->ti, (const float *)s->aerr_t, ya, s->ety);
     const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
-    hipLaunchKernelGGL(k_defect_set, dim3(g), dim3(kBlock), 0, st, s->n, s->m, s->st, 1, s->ch, s->ety, s->chc,
-                       (const double *)s->bh, s->ex, s->bhc);
+    hipLaunchKernelGGL(k_defect_set, dim3(g), dim3(kBlock), 0, st, s->n, s->m, s->st, 1, s->ch,
+                       (const double *)s->chc, (const double *)s->ety, s->chc, (const double *)s->bh,
+                       (const double *)s->bhc, (const double *)s->ex, s->bhc);
     return hipGetLastError();
 }
 
@@ -817,33 +836,50 @@ __global__ __launch_bounds__(kBlock) void k_phase_start(DevState *st, const doub
     st->checks = 0;
 }
 
-// x = clamp(0, lhat, uhat), y = 0, anchors = (x, y)
+// x = clamp(0, lhat, uhat), y = 0, anchors = (x, y) (mixed mode: x_a = that
+// point, stored differences x - x_a and dy = 0)
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_start_point(int n, int m, const V *__restrict__ lh, const V *__restrict__ uh,
-                                                       V *__restrict__ x, V *__restrict__ xa, double *__restrict__ y,
-                                                       double *__restrict__ ya)
+                                                       V *__restrict__ x, double *__restrict__ xa,
+                                                       double *__restrict__ y, double *__restrict__ ya,
+                                                       float *__restrict__ dy)
 {
+    constexpr bool delta = sizeof(V) == sizeof(float);
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
         if (i < n) {
             V v = (V)0;
             v = v < lh[i] ? lh[i] : v;
             v = v > uh[i] ? uh[i] : v;
-            x[i] = v;
-            xa[i] = v;
+            x[i] = delta ? (V)0 : v;
+            xa[i] = (double)v;
         } else {
             y[i - n] = 0.0;
             ya[i - n] = 0.0;
+            if (dy) dy[i - n] = 0.0f;
         }
     }
 }
 
+// anchors = the current iterate (mixed mode: x_a += x - x_a, then the
+// differences are 0)
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_copy_anchor(int n, int m, const V *__restrict__ x, V *__restrict__ xa,
-                                                       const double *__restrict__ y, double *__restrict__ ya)
+__global__ __launch_bounds__(kBlock) void k_copy_anchor(int n, int m, V *__restrict__ x, double *__restrict__ xa,
+                                                       const double *__restrict__ y, double *__restrict__ ya,
+                                                       float *__restrict__ dy)
 {
+    constexpr bool delta = sizeof(V) == sizeof(float);
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
-        if (i < n) xa[i] = x[i];
-        else ya[i - n] = y[i - n];
+        if (i < n) {
+            if (delta) {
+                xa[i] += (double)x[i];
+                x[i] = (V)0;
+            } else {
+                xa[i] = (double)x[i];
+            }
+        } else {
+            ya[i - n] = y[i - n];
+            if (dy) dy[i - n] = 0.0f;
+        }
     }
 }
 
@@ -854,10 +890,10 @@ static void start_vectors(pdhg_solver *s, bool fresh_start)
     const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
     if (fresh_start)
         hipLaunchKernelGGL((k_start_point<V>), dim3(g), dim3(kBlock), 0, st, s->n, s->m, (const V *)s->lh,
-                           (const V *)s->uh, (V *)s->x, (V *)s->xa, (double *)s->y, (double *)s->ya);
+                           (const V *)s->uh, (V *)s->x, (double *)s->xa, (double *)s->y, (double *)s->ya, s->dy);
     else
-        hipLaunchKernelGGL((k_copy_anchor<V>), dim3(g), dim3(kBlock), 0, st, s->n, s->m, (const V *)s->x, (V *)s->xa,
-                           (const double *)s->y, (double *)s->ya);
+        hipLaunchKernelGGL((k_copy_anchor<V>), dim3(g), dim3(kBlock), 0, st, s->n, s->m, (V *)s->x, (double *)s->xa,
+                           (const double *)s->y, (double *)s->ya, s->dy);
 }
 
 // x = clamp(0, lhat, uhat), y = 0 (fresh) or anchors = current (x, y)
@@ -911,18 +947,25 @@ hipError_t init_iteration(pdhg_solver *s)
 }
 
 // caller's start point (xu, yu unscaled) -> x = clamp(x / Dc, lhat, uhat),
-// y = y / Dr projected on the sign of its row (the projections of the method)
+// y = y / Dr projected on the sign of its row (the projections of the method);
+// mixed mode: x_a = that x in float64 and the stored difference 0
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_set_start(int n, int m, const double *__restrict__ xu,
                                                      const double *__restrict__ yu, const double *__restrict__ dc,
                                                      const double *__restrict__ dr, const V *__restrict__ lh,
                                                      const V *__restrict__ uh, const int8_t *__restrict__ sense,
-                                                     V *__restrict__ x, double *__restrict__ y)
+                                                     V *__restrict__ x, double *__restrict__ xa, double *__restrict__ y)
 {
+    constexpr bool delta = sizeof(V) == sizeof(float);
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
         if (i < n) {
             const double v = fmin(fmax(xu[i] / dc[i], (double)lh[i]), (double)uh[i]);
-            x[i] = (V)v;
+            if (delta) {
+                xa[i] = v;
+                x[i] = (V)0;
+            } else {
+                x[i] = (V)v;
+            }
         } else {
             const int64_t r = i - n;
             double v = yu[r] / dr[r];
@@ -938,61 +981,90 @@ hipError_t set_start(pdhg_solver *s)
     const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
     if (s->fp32) {
         hipLaunchKernelGGL((k_set_start<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->xu, s->yu, s->dc,
-                           s->dr, (const float *)s->lh, (const float *)s->uh, s->sense, (float *)s->x, (double *)s->y);
+                           s->dr, (const float *)s->lh, (const float *)s->uh, s->sense, (float *)s->x, (double *)s->xa,
+                           (double *)s->y);
         return phase_start<float>(s, false);
     }
     hipLaunchKernelGGL((k_set_start<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->xu, s->yu, s->dc,
-                       s->dr, (const double *)s->lh, (const double *)s->uh, s->sense, (double *)s->x, (double *)s->y);
+                       s->dr, (const double *)s->lh, (const double *)s->uh, s->sense, (double *)s->x, (double *)s->xa,
+                       (double *)s->y);
     return phase_start<double>(s, false);
 }
 
+// (xp, yp) <- (x, y): the candidate of a phase that has not reached a check
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_copy2(int n, int m, const V *__restrict__ a, V *__restrict__ ac,
-                                                 const double *__restrict__ b, double *__restrict__ bc)
+__global__ __launch_bounds__(kBlock) void k_candidate_from_iterate(int n, int m, const V *__restrict__ x,
+                                                                  const double *__restrict__ xa,
+                                                                  double *__restrict__ xp, const double *__restrict__ y,
+                                                                  double *__restrict__ yp)
 {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
-        if (i < n) ac[i] = a[i];
-        else bc[i - n] = b[i - n];
+        if (i < n) xp[i] = iterate_value<V>(x[i], xa[i]);
+        else yp[i - n] = y[i - n];
     }
 }
 
-// (xp, yp) <- (x, y): the candidate of a phase that has not reached a check
 hipError_t candidate_from_iterate(pdhg_solver *s)
 {
     const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
     if (s->fp32)
-        hipLaunchKernelGGL((k_copy2<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, (const float *)s->x,
-                           (float *)s->xp, (const double *)s->y, (double *)s->yp);
+        hipLaunchKernelGGL((k_candidate_from_iterate<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m,
+                           (const float *)s->x, (const double *)s->xa, (double *)s->xp, (const double *)s->y,
+                           (double *)s->yp);
     else
-        hipLaunchKernelGGL((k_copy2<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, (const double *)s->x,
-                           (double *)s->xp, (const double *)s->y, (double *)s->yp);
+        hipLaunchKernelGGL((k_candidate_from_iterate<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m,
+                           (const double *)s->x, (const double *)s->xa, (double *)s->xp, (const double *)s->y,
+                           (double *)s->yp);
     return hipGetLastError();
 }
 
-template <typename V>
+// xo = Dc (xh + xd) (xd: an optional float difference), yo = Dr yh
 __global__ __launch_bounds__(kBlock) void k_unscale(int n, int m, const double *__restrict__ dc,
-                                                   const double *__restrict__ dr, const V *__restrict__ xh,
-                                                   const double *__restrict__ yh, double *__restrict__ xo,
-                                                   double *__restrict__ yo)
+                                                   const double *__restrict__ dr, const double *__restrict__ xh,
+                                                   const float *__restrict__ xd, const double *__restrict__ yh,
+                                                   double *__restrict__ xo, double *__restrict__ yo)
 {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
         if (i < n) {
-            if (xo) xo[i] = dc[i] * (double)xh[i];
+            if (xo) xo[i] = dc[i] * (xd ? xh[i] + (double)xd[i] : xh[i]);
         } else {
-            if (yo) yo[i - n] = dr[i - n] * (double)yh[i - n];
+            if (yo) yo[i - n] = dr[i - n] * yh[i - n];
         }
     }
 }
 
-hipError_t unscale(pdhg_solver *s, const void *xh, const void *yh, double *xo, double *yo)
+hipError_t unscale(pdhg_solver *s, const double *xh, const double *yh, double *xo, double *yo)
+{
+    const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
+    hipLaunchKernelGGL(k_unscale, dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->dc, s->dr, xh,
+                       (const float *)nullptr, yh, xo, yo);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_restore_dy(int m, const double *__restrict__ y,
+                                                      const double *__restrict__ ya, float *__restrict__ dy)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock)
+        dy[i] = (float)(y[i] - ya[i]);
+}
+
+hipError_t restore_dy(pdhg_solver *s)
+{
+    if (!s->dy || s->m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_restore_dy, dim3(grid_for(s->m, kBlock, 8192)), dim3(kBlock), 0, s->stream, s->m,
+                       (const double *)s->y, (const double *)s->ya, s->dy);
+    return hipGetLastError();
+}
+
+hipError_t unscale_iterate(pdhg_solver *s, double *xo, double *yo)
 {
     const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
     if (s->fp32)
-        hipLaunchKernelGGL((k_unscale<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->dc, s->dr,
-                           (const float *)xh, (const double *)yh, xo, yo);
+        hipLaunchKernelGGL(k_unscale, dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->dc, s->dr,
+                           (const double *)s->xa, (const float *)s->x, (const double *)s->y, xo, yo);
     else
-        hipLaunchKernelGGL((k_unscale<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->dc, s->dr,
-                           (const double *)xh, (const double *)yh, xo, yo);
+        hipLaunchKernelGGL(k_unscale, dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->dc, s->dr,
+                           (const double *)s->x, (const float *)nullptr, (const double *)s->y, xo, yo);
     return hipGetLastError();
 }
 
@@ -1127,24 +1199,26 @@ hipError_t report(pdhg_solver *s, const double *x, const double *y, double *z, p
 // z_j < -eps_abs (bounds stored scaled: the scaled solve candidate itself),
 // objective Uniform[0,1) scaled like c, start x at the solve's x.
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_push_cols(int n, const double *__restrict__ z, const V *__restrict__ xs,
+__global__ __launch_bounds__(kBlock) void k_push_cols(int n, const double *__restrict__ z, const double *__restrict__ xs,
                                                      const double *__restrict__ dc, double eps_abs, uint64_t seed,
                                                      double scale, V *__restrict__ lh, V *__restrict__ uh,
-                                                     double *__restrict__ ch, V *__restrict__ x, double *__restrict__ part,
-                                                     int nblk)
+                                                     double *__restrict__ ch, V *__restrict__ x, double *__restrict__ xa,
+                                                     double *__restrict__ part, int nblk)
 {
+    constexpr bool delta = sizeof(V) == sizeof(float);
     double v[2] = {0.0, 0.0}; // fixes at the lower, upper side
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
-        const V xv = xs[j];
+        const double xv = xs[j];
         if (z[j] > eps_abs) {
-            uh[j] = xv;
+            uh[j] = (V)xv;
             v[1] += 1.0;
         } else if (z[j] < -eps_abs) {
-            lh[j] = xv;
+            lh[j] = (V)xv;
             v[0] += 1.0;
         }
         ch[j] = dc[j] * (scale * push_unit(seed, j));
-        x[j] = xv;
+        x[j] = delta ? (V)0 : (V)xv; // the iterate starts at the solve's x (mixed mode: as the anchor)
+        xa[j] = xv;
     }
     block_reduce<2>(v, 0u);
     if (threadIdx.x == 0) {
@@ -1193,9 +1267,9 @@ static hipError_t push_setup_impl(pdhg_solver *s, uint64_t seed, pdhg_push_resul
     hipStream_t st = s->stream;
     const int gn = s->red_blocks_n, gm = s->red_blocks_m;
     double *pcnt = s->partials + (size_t)(Q_COUNT + 1) * (gm + gn); // past the check slots
-    hipLaunchKernelGGL((k_push_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->zsol, (const V *)s->xs, s->dc,
-                       s->p.eps_abs, seed, s->p.push_obj_scale, (V *)s->lh, (V *)s->uh, s->ch, (V *)s->x, pcnt,
-                       gn);
+    hipLaunchKernelGGL((k_push_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, s->zsol, (const double *)s->xs, s->dc,
+                       s->p.eps_abs, seed, s->p.push_obj_scale, (V *)s->lh, (V *)s->uh, s->ch, (V *)s->x,
+                       (double *)s->xa, pcnt, gn);
     hipLaunchKernelGGL(k_push_rows, dim3(gm), dim3(kBlock), 0, st, s->m, s->yu, s->p.eps_abs, s->sense, (double *)s->y,
                        pcnt + 2 * gn);
     hipLaunchKernelGGL(k_sum3, dim3(1), dim3(kBlock), 0, st, pcnt, gn, gm, s->redout);
@@ -1255,8 +1329,8 @@ __global__ __launch_bounds__(kBlock) void k_dpush_cols(int n, const double *__re
                                                       const double *__restrict__ aty, const double *__restrict__ atyn,
                                                       const double *__restrict__ dc, double eps_abs, uint64_t seed,
                                                       V *__restrict__ lh, V *__restrict__ uh, double *__restrict__ ch,
-                                                      V *__restrict__ x, double *__restrict__ w0,
-                                                      double *__restrict__ part, int nblk)
+                                                      V *__restrict__ x, double *__restrict__ xa,
+                                                      double *__restrict__ w0, double *__restrict__ part, int nblk)
 {
     double v[1] = {0.0}; // columns off both bounds
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
@@ -1271,6 +1345,7 @@ __global__ __launch_bounds__(kBlock) void k_dpush_cols(int n, const double *__re
         const double uj = push_unit(seed, j);
         w0[j] = (at_lo && at_up) ? 0.0 : (at_up ? -uj : uj);
         x[j] = (V)0;
+        xa[j] = 0.0;
         v[0] += (!at_lo && !at_up) ? 1.0 : 0.0;
     }
     block_reduce<1>(v, 0u);
@@ -1326,7 +1401,8 @@ static hipError_t dual_push_setup_impl(pdhg_solver *s, uint64_t seed, const doub
                        s->sense, yn, pcnt + 2 * gn);
     spmv<double, double, double, double>(st, s->lanes_at, s->n, s->tp, s->ti, s->atv, yn, atyn);
     hipLaunchKernelGGL((k_dpush_cols<V>), dim3(gn), dim3(kBlock), 0, st, s->n, xk, s->l, s->u, s->c, s->aty, atyn,
-                       s->dc, s->p.eps_abs, seed, (V *)s->lh, (V *)s->uh, s->ch, (V *)s->x, w0, pcnt, gn);
+                       s->dc, s->p.eps_abs, seed, (V *)s->lh, (V *)s->uh, s->ch, (V *)s->x, (double *)s->xa, w0,
+                       pcnt, gn);
     spmv<double, double, double, double>(st, s->lanes_a, s->m, s->rp, s->ci, s->av, w0, (double *)s->bh);
     hipLaunchKernelGGL(k_dpush_rhs, dim3(gm), dim3(kBlock), 0, st, s->m, s->n, s->sense, s->dr, (const double *)s->ys,
                        seed, s->p.push_obj_scale, (double *)s->bh, (double *)s->y);
@@ -1379,12 +1455,16 @@ hipError_t autotune(pdhg_solver *s)
 {
     const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
     void *sx = nullptr, *sxbar = nullptr, *sxp = nullptr, *sy = nullptr, *syp = nullptr;
+    float *sdy = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipMalloc(&sx, vb * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sxbar, vb * (size_t)(s->n > 0 ? s->n : 1));
-    if (e == hipSuccess) e = hipMalloc(&sxp, vb * (size_t)(s->n > 0 ? s->n : 1));
+    if (e == hipSuccess) e = hipMalloc(&sxp, sizeof(double) * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sy, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
     if (e == hipSuccess) e = hipMalloc(&syp, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
+    if (e == hipSuccess && s->dy) e = hipMalloc(&sdy, sizeof(float) * (size_t)(s->m > 0 ? s->m : 1));
+    if (e == hipSuccess && s->dy)
+        e = hipMemcpyAsync(sdy, s->dy, sizeof(float) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
     if (e == hipSuccess) e = hipMemcpyAsync(sx, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
@@ -1392,11 +1472,13 @@ hipError_t autotune(pdhg_solver *s)
     if (e == hipSuccess) e = hipMemcpyAsync(sy, s->y, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
     const int cands[] = {-32, -64, -128, -256, -1032, -1064, 1, 2, 4, 8, 16, 32, 64, kRowBlock, kSell};
     void *keep[5] = {s->x, s->xbar, s->xp, s->y, s->yp};
+    float *keep_dy = s->dy;
     s->x = sx;
     s->xbar = sxbar;
     s->xp = sxp;
     s->y = sy;
     s->yp = syp;
+    s->dy = sdy;
     for (int half = 0; half < 2 && e == hipSuccess; half++) {
         float best = 1e30f;
         int best_k = half == 0 ? s->kern_at : s->kern_a;
@@ -1432,9 +1514,10 @@ hipError_t autotune(pdhg_solver *s)
     s->xp = keep[2];
     s->y = keep[3];
     s->yp = keep[4];
+    s->dy = keep_dy;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    for (void *q : {sx, sxbar, sxp, sy, syp})
+    for (void *q : {sx, sxbar, sxp, sy, syp, (void *)sdy})
         if (q) (void)hipFree(q);
     return e;
 }

@@ -21,41 +21,74 @@ __device__ __forceinline__ void halpern_weights(const DevState *st, int i, doubl
     g = st->gamma;
 }
 
-// Storage: the matrix values and every n-vector (x, x_anchor, xbar, x+, chat,
-// lhat, uhat) are V (float in the mixed mode, double otherwise); every
-// m-vector (y, y_anchor, y+, bhat) is double.  All arithmetic — products,
-// sums, projections, Halpern averages — is double in registers; only the
-// stores round to V.  (With y in float the reduced cost chat - Ahat'y loses
-// its low bits and the large primal step tau = eta/omega amplifies that
-// rounding into x; keeping the short m-vectors in double removes it.)
+// Storage.  Float64 mode: every vector is double.  Mixed mode (V = float):
+// the matrix values, the bounds lhat, uhat and two n-vectors are float, and
+// the iterate x and the extrapolation xbar are stored as float DIFFERENCES
+// from the float64 anchor x_a (x - x_a, xbar - x_a); the anchor, the
+// candidate x+ and every m-vector (y, y_anchor, y+) are double, and the dual
+// half also writes dy = y - y_a as float for the primal half to gather.  The
+// float rounding of a difference shrinks as the restart cycle converges, so
+// the iteration keeps float64 accuracy near the optimum (rounding x itself to
+// float stalls primal-degenerate LPs, where the rows cancel).  The matching
+// objective and right-hand side are chat - Ahat'y_a and bhat - Ahat x_a in
+// float64, refreshed at every anchor:
+//   chat - Ahat'y = (chat - Ahat'y_a) - Ahat'(y - y_a),
+//   bhat - Ahat xbar = (bhat - Ahat x_a) - Ahat (xbar - x_a).
+// All arithmetic — products, sums, projections, Halpern averages — is double
+// in registers; only the stores round to V.
 
 // Primal half, one row of the transpose (= one column j of A) per group of L
-// lanes:  g = Ahat' y;  x+ = clamp(x - tau (chat - g), lhat, uhat);
-// xbar = 2 x+ - x;  x <- w ((1+gamma) x+ - gamma x) + wa x_anchor.
+// lanes:  g = Ahat' y (mixed: Ahat'(y - y_a));  x+ = clamp(x - tau (chat - g),
+// lhat, uhat);  xbar = 2 x+ - x;  x <- w ((1+gamma) x+ - gamma x) + wa x_a.
+// xj is the iterate itself (mixed: x_a + stored difference), aj the anchor.
 // At the last iteration before a check the candidate x+ is stored as well.
 template <typename V>
 __device__ __forceinline__ void primal_update(int64_t j, double g, double xj, double cj, double lo, double hi,
                                               double aj, V *__restrict__ x, V *__restrict__ xbar,
-                                              V *__restrict__ xp, const DevState *__restrict__ st, int i,
+                                              double *__restrict__ xp, const DevState *__restrict__ st, int i,
                                               int store_cand)
 {
+    constexpr bool delta = sizeof(V) == sizeof(float);
     double xn = xj - st->tau * (cj - g);
     xn = xn < lo ? lo : xn;
     xn = xn > hi ? hi : xn;
-    xbar[j] = (V)(2.0 * xn - xj);
-    if (store_cand) xp[j] = (V)xn;
+    const double xb = 2.0 * xn - xj;
+    xbar[j] = (V)(delta ? xb - aj : xb);
+    if (store_cand) xp[j] = xn;
+    double xnew = xn;
     if (st->halpern) {
         double w, wa, gm;
         halpern_weights(st, i, w, wa, gm);
-        x[j] = (V)(w * ((1.0 + gm) * xn - gm * xj) + wa * aj);
+        xnew = w * ((1.0 + gm) * xn - gm * xj) + wa * aj;
+    }
+    x[j] = (V)(delta ? xnew - aj : xnew);
+}
+
+// set the iterate of column j to v (mixed mode: as the anchor, difference 0;
+// a phase start that follows makes the anchor the iterate in either mode)
+template <typename V>
+__device__ __forceinline__ void set_iterate(int64_t j, double v, V *__restrict__ x, double *__restrict__ xa)
+{
+    if (sizeof(V) == sizeof(float)) {
+        xa[j] = v;
+        x[j] = (V)0;
     } else {
-        x[j] = (V)xn;
+        x[j] = (V)v;
+        xa[j] = v;
     }
 }
 
-// Dual half:  y+ = proj_Y(y + sigma (bhat - h));  y <- w ((1+gamma) y+ - gamma y) + wa y_anchor.
+// the iterate from its stored form
+template <typename V>
+__device__ __forceinline__ double iterate_value(V stored, double anchor)
+{
+    return sizeof(V) == sizeof(float) ? anchor + (double)stored : (double)stored;
+}
+
+// Dual half:  y+ = proj_Y(y + sigma (bhat - h));  y <- w ((1+gamma) y+ - gamma y) + wa y_anchor;
+// with dy (mixed mode) dy = y - y_anchor in float for the primal half's gathers.
 __device__ __forceinline__ void dual_update(int64_t r, double h, double yr, double br, double ar, int8_t sn,
-                                            double *__restrict__ y, double *__restrict__ yp,
+                                            double *__restrict__ y, double *__restrict__ yp, float *__restrict__ dy,
                                             const DevState *__restrict__ st, int i, int store_cand)
 {
     double yn = yr + st->sigma * (br - h);
@@ -63,13 +96,14 @@ __device__ __forceinline__ void dual_update(int64_t r, double h, double yr, doub
     else if (sn == '>') yn = yn > 0.0 ? yn : 0.0;
     else if (sn == 'N') yn = 0.0; // a row the dual push drops: y_i = 0
     if (store_cand) yp[r] = yn;
+    double ynew = yn;
     if (st->halpern) {
         double w, wa, gm;
         halpern_weights(st, i, w, wa, gm);
-        y[r] = w * ((1.0 + gm) * yn - gm * yr) + wa * ar;
-    } else {
-        y[r] = yn;
+        ynew = w * ((1.0 + gm) * yn - gm * yr) + wa * ar;
     }
+    y[r] = ynew;
+    if (dy) dy[r] = (float)(ynew - ar);
 }
 
 // ------------------------------------------------- LDS-tiled short rows ---

@@ -43,7 +43,7 @@ __device__ __forceinline__ double zsplit(double lam, double lo, double hi)
 // at a restart of the solve: slot (restarts - 1) mod 4 <- candidate x, z
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_record_history(int n, const DevState *__restrict__ st,
-                                                          const V *__restrict__ xp, const double *__restrict__ ch,
+                                                          const double *__restrict__ xp, const double *__restrict__ ch,
                                                           const V *__restrict__ lh, const V *__restrict__ uh,
                                                           const double *__restrict__ aty, float *__restrict__ hx,
                                                           float *__restrict__ hz)
@@ -61,7 +61,7 @@ hipError_t launch_record_history(pdhg_solver *s)
     const int g = grid_for(s->n, kBlock, 8192);
     if (s->fp32)
         hipLaunchKernelGGL((k_record_history<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->st,
-                           (const float *)s->xp, s->ch, (const float *)s->lh, (const float *)s->uh,
+                           (const double *)s->xp, s->ch, (const float *)s->lh, (const float *)s->uh,
                            s->aty, s->hx, s->hz);
     else
         hipLaunchKernelGGL((k_record_history<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->st,
@@ -74,7 +74,7 @@ hipError_t launch_record_history(pdhg_solver *s)
 // n the stride of the history arrays; rest the LP's restart count)
 template <typename V>
 __device__ __forceinline__ void column_features(int64_t j, int64_t jl, int64_t n, int64_t rest,
-                                                const V *__restrict__ xp, const double *__restrict__ ch,
+                                                const double *__restrict__ xp, const double *__restrict__ ch,
                                                 const V *__restrict__ lh, const V *__restrict__ uh,
                                                 const double *__restrict__ aty, const int *__restrict__ tp,
                                                 const V *__restrict__ atv, const float *__restrict__ hx,
@@ -109,7 +109,7 @@ __device__ __forceinline__ void column_features(int64_t j, int64_t jl, int64_t n
 
 // raw features into f (n x 16, float) and per-block sums of their squares
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_feat_raw(int n, const DevState *__restrict__ st, const V *__restrict__ xp,
+__global__ __launch_bounds__(kBlock) void k_feat_raw(int n, const DevState *__restrict__ st, const double *__restrict__ xp,
                                                     const double *__restrict__ ch, const V *__restrict__ lh,
                                                     const V *__restrict__ uh, const double *__restrict__ aty,
                                                     const int *__restrict__ tp, const V *__restrict__ atv,
@@ -192,7 +192,7 @@ hipError_t compute_features(pdhg_solver *s, uint64_t seed)
     const int nb = s->red_blocks_n;
     double *scale = s->redout + 16;
     if (s->fp32)
-        hipLaunchKernelGGL((k_feat_raw<float>), dim3(nb), dim3(kBlock), 0, st, s->n, s->st, (const float *)s->xp,
+        hipLaunchKernelGGL((k_feat_raw<float>), dim3(nb), dim3(kBlock), 0, st, s->n, s->st, (const double *)s->xp,
                            s->ch, (const float *)s->lh, (const float *)s->uh, s->aty, s->tp,
                            (const float *)s->ahat_t, s->hx, s->hz, s->dc, seed, s->p.push_obj_scale, s->feat_raw,
                            s->partials, nb);
@@ -213,8 +213,9 @@ template <typename V>
 __device__ __forceinline__ int learned_fix_one(int64_t j, const float *__restrict__ logits, float theta_logit,
                                                const double *__restrict__ z, double eps_abs,
                                                const double *__restrict__ l, const double *__restrict__ u,
-                                               const double *__restrict__ dc, const V *__restrict__ xs,
-                                               V *__restrict__ lh, V *__restrict__ uh, V *__restrict__ x)
+                                               const double *__restrict__ dc, const double *__restrict__ xs,
+                                               V *__restrict__ lh, V *__restrict__ uh, V *__restrict__ x,
+                                               double *__restrict__ xa)
 {
     if (fabs(z[j]) > eps_abs || logits[j] < theta_logit) return 0; // plain-fixed, or not predicted
     const double lo = l[j] / dc[j], hi = u[j] / dc[j], xv = (double)xs[j];
@@ -223,11 +224,13 @@ __device__ __forceinline__ int learned_fix_one(int64_t j, const float *__restric
     if (!(dl < INFINITY) && !(du < INFINITY)) return 0; // free column
     if (dl <= du) {
         if (z[j] < -eps_abs) return 0;
-        lh[j] = uh[j] = x[j] = (V)lo;
+        lh[j] = uh[j] = (V)lo;
+        set_iterate<V>(j, (double)(V)lo, x, xa);
         return 1;
     }
     if (z[j] > eps_abs) return 0;
-    lh[j] = uh[j] = x[j] = (V)hi;
+    lh[j] = uh[j] = (V)hi;
+    set_iterate<V>(j, (double)(V)hi, x, xa);
     return 2;
 }
 
@@ -235,12 +238,13 @@ template <typename V>
 __global__ __launch_bounds__(kBlock) void k_learned_fix(int n, const float *__restrict__ logits, float theta_logit,
                                                        const double *__restrict__ z, double eps_abs,
                                                        const double *__restrict__ l, const double *__restrict__ u,
-                                                       const double *__restrict__ dc, const V *__restrict__ xs,
+                                                       const double *__restrict__ dc, const double *__restrict__ xs,
                                                        V *__restrict__ lh, V *__restrict__ uh, V *__restrict__ x,
+                                                       double *__restrict__ xa,
                                                        int8_t *__restrict__ lfix, unsigned *__restrict__ count)
 {
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
-        const int f = learned_fix_one<V>(j, logits, theta_logit, z, eps_abs, l, u, dc, xs, lh, uh, x);
+        const int f = learned_fix_one<V>(j, logits, theta_logit, z, eps_abs, l, u, dc, xs, lh, uh, x, xa);
         lfix[j] = (int8_t)f;
         if (f) atomicAdd(&count[0], 1u);
     }
@@ -252,12 +256,12 @@ hipError_t launch_learned_fix(pdhg_solver *s, double theta)
     const int g = grid_for(s->n, kBlock, 8192);
     if (s->fp32)
         hipLaunchKernelGGL((k_learned_fix<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->logits, tl, s->zsol,
-                           s->p.eps_abs, s->l, s->u, s->dc, (const float *)s->xs, (float *)s->lh, (float *)s->uh,
-                           (float *)s->x, s->lfix, s->lcount);
+                           s->p.eps_abs, s->l, s->u, s->dc, (const double *)s->xs, (float *)s->lh, (float *)s->uh,
+                           (float *)s->x, (double *)s->xa, s->lfix, s->lcount);
     else
         hipLaunchKernelGGL((k_learned_fix<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->logits, tl, s->zsol,
                            s->p.eps_abs, s->l, s->u, s->dc, (const double *)s->xs, (double *)s->lh, (double *)s->uh,
-                           (double *)s->x, s->lfix, s->lcount);
+                           (double *)s->x, (double *)s->xa, s->lfix, s->lcount);
     return hipGetLastError();
 }
 
@@ -311,7 +315,7 @@ hipError_t launch_learned_undo(pdhg_solver *s)
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void kb_record_history(const int4 *__restrict__ rn, int n,
-                                                           const DevState *__restrict__ sts, const V *__restrict__ xp,
+                                                           const DevState *__restrict__ sts, const double *__restrict__ xp,
                                                            const double *__restrict__ ch, const V *__restrict__ lh,
                                                            const V *__restrict__ uh, const double *__restrict__ aty,
                                                            float *__restrict__ hx, float *__restrict__ hz)
@@ -326,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void kb_record_history(const int4 *__restri
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void kb_feat_raw(const int4 *__restrict__ rn, int n, const int *__restrict__ coff,
-                                                     const DevState *__restrict__ sts, const V *__restrict__ xp,
+                                                     const DevState *__restrict__ sts, const double *__restrict__ xp,
                                                      const double *__restrict__ ch, const V *__restrict__ lh,
                                                      const V *__restrict__ uh, const double *__restrict__ aty,
                                                      const int *__restrict__ tp, const V *__restrict__ atv,
@@ -399,14 +403,15 @@ __global__ __launch_bounds__(kBlock) void kb_learned_fix(const int4 *__restrict_
                                                         const float *__restrict__ logits, float theta_logit,
                                                         const double *__restrict__ z, double eps_abs,
                                                         const double *__restrict__ l, const double *__restrict__ u,
-                                                        const double *__restrict__ dc, const V *__restrict__ xs,
+                                                        const double *__restrict__ dc, const double *__restrict__ xs,
                                                         V *__restrict__ lh, V *__restrict__ uh, V *__restrict__ x,
+                                                        double *__restrict__ xa,
                                                         int8_t *__restrict__ lfix, unsigned *__restrict__ count)
 {
     const int4 tl = rn[blockIdx.x];
     if ((int)threadIdx.x >= tl.z) return;
     const int64_t j = tl.y + threadIdx.x;
-    const int f = active[tl.x] ? learned_fix_one<V>(j, logits, theta_logit, z, eps_abs, l, u, dc, xs, lh, uh, x) : 0;
+    const int f = active[tl.x] ? learned_fix_one<V>(j, logits, theta_logit, z, eps_abs, l, u, dc, xs, lh, uh, x, xa) : 0;
     lfix[j] = (int8_t)f;
     if (f) atomicAdd(&count[2 * tl.x], 1u);
 }
@@ -430,7 +435,7 @@ hipError_t batch_record_history(pdhg_batch *b)
     pdhg_solver *s = b->s;
     if (s->fp32)
         hipLaunchKernelGGL((kb_record_history<float>), dim3(b->n_rn), dim3(kBlock), 0, s->stream, b->rn, s->n, b->sts,
-                           (const float *)s->xp, s->ch, (const float *)s->lh, (const float *)s->uh, s->aty, s->hx,
+                           (const double *)s->xp, s->ch, (const float *)s->lh, (const float *)s->uh, s->aty, s->hx,
                            s->hz);
     else
         hipLaunchKernelGGL((kb_record_history<double>), dim3(b->n_rn), dim3(kBlock), 0, s->stream, b->rn, s->n,
@@ -452,7 +457,7 @@ hipError_t batch_compute_features(pdhg_batch *b)
                                              (const double *)s->yp, s->aty);
     if (s->fp32)
         hipLaunchKernelGGL((kb_feat_raw<float>), dim3(b->n_rn), dim3(kBlock), 0, st, b->rn, s->n, b->d_coff, b->sts,
-                           (const float *)s->xp, s->ch, (const float *)s->lh, (const float *)s->uh, s->aty, s->tp,
+                           (const double *)s->xp, s->ch, (const float *)s->lh, (const float *)s->uh, s->aty, s->tp,
                            (const float *)s->ahat_t, s->hx, s->hz, s->dc, b->seeds, s->p.push_obj_scale, s->feat_raw,
                            b->fpart, b->n_rn);
     else
@@ -472,12 +477,12 @@ hipError_t batch_learned_fix(pdhg_batch *b, double theta)
     const float tl = (float)log(theta / (1.0 - theta)); // probability >= theta <=> logit >= tl
     if (s->fp32)
         hipLaunchKernelGGL((kb_learned_fix<float>), dim3(b->n_rn), dim3(kBlock), 0, s->stream, b->rn, b->active,
-                           s->logits, tl, s->zsol, s->p.eps_abs, s->l, s->u, s->dc, (const float *)s->xs,
-                           (float *)s->lh, (float *)s->uh, (float *)s->x, s->lfix, s->lcount);
+                           s->logits, tl, s->zsol, s->p.eps_abs, s->l, s->u, s->dc, (const double *)s->xs,
+                           (float *)s->lh, (float *)s->uh, (float *)s->x, (double *)s->xa, s->lfix, s->lcount);
     else
         hipLaunchKernelGGL((kb_learned_fix<double>), dim3(b->n_rn), dim3(kBlock), 0, s->stream, b->rn, b->active,
                            s->logits, tl, s->zsol, s->p.eps_abs, s->l, s->u, s->dc, (const double *)s->xs,
-                           (double *)s->lh, (double *)s->uh, (double *)s->x, s->lfix, s->lcount);
+                           (double *)s->lh, (double *)s->uh, (double *)s->x, (double *)s->xa, s->lfix, s->lcount);
     return hipGetLastError();
 }
 
