@@ -316,8 +316,10 @@ def main():
     dlp = pdhg.DeviceLP(lp)
 
     def step(timing):
+        t0 = time.perf_counter()
         s = pdhg.Solver(dlp, precision=args.precision, timing=timing, use_graph=0 if args.no_graph else 1,
                         push_compact=args.push_compact)
+        step.create_s = time.perf_counter() - t0
         r = s.solve()
         p = s.corner_push(args.seed) if args.push != "dual" else s.dual_push(args.seed)
         d = s.dual_push(args.seed) if args.push == "both" else None
@@ -344,7 +346,8 @@ def main():
         dual_ms += tim.dual_ms * tim.samples
         samples += tim.samples
         d = {"solve_iters": r.iters, "solve_status": pdhg.STATUS[r.status], "push_iters": p.iters,
-             "push_status": pdhg.STATUS[p.status], "step_s": te - ts,
+             "push_status": pdhg.STATUS[p.status], "step_s": te - ts, "create_s": step.create_s,
+             "solve_s": r.seconds, "push_s": p.seconds,
              "rel_kkt": [r.rel_p, r.rel_d, r.rel_gap], "pobj": r.pobj}
         if args.push != "dual":
             d.update({"off_bound_before": p.before.p_off, "off_bound_after": p.after.p_off,
@@ -355,7 +358,7 @@ def main():
             d.update({"zero_rc_before": p.before.d_zero, "zero_rc_after": p.after.d_zero,
                       "est_dual_before": p.before.est_dual, "est_dual_after": p.after.est_dual,
                       "cols_free": p.n_cols_free, "rows_fixed": p.n_rows_fixed,
-                      "rel_d_push": p.rel_d_push, "push_s": p.seconds})
+                      "rel_d_push": p.rel_d_push})
         if dp is not None:
             d.update({"dual_push_iters": dp.iters, "dual_push_status": pdhg.STATUS[dp.status],
                       "dual_push_s": dp.seconds, "est_dual_before": dp.before.est_dual,
