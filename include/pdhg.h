@@ -70,8 +70,11 @@ enum pdhg_error {
 
 enum pdhg_precision {
     PDHG_FP64 = 0,      /* matrix, vectors and updates in float64                         */
-    PDHG_FP32_MIXED = 1 /* matrix, vectors and updates in float32; residual norms, restart
-                           test, termination and the push fixing test in float64         */
+    PDHG_FP32_MIXED = 1 /* matrix, bounds and the streamed vectors in float32: x and xbar as
+                           differences from the float64 restart anchor, y - y_anchor for the
+                           primal products; anchors, objective, dual vector, arithmetic,
+                           residual norms, restart test, termination and the push fixing
+                           test in float64                                                */
 };
 
 /* Parameters.  Every constant the paper leaves open lives here. */
@@ -319,8 +322,8 @@ int pdhg_set_start(pdhg_solver *s, const double *x, const double *y);
  * caller's host buffer; pdhg_set_state loads such a buffer into a handle
  * created from the same LP and parameters, after which pdhg_iterate /
  * pdhg_solve continue exactly as the checkpointed run would have.  Errors:
- * INVALID_ARG (NULL, buffer too small, not a checkpoint, another size or
- * precision), STATE during a push. */
+ * INVALID_ARG (NULL, buffer too small, not a checkpoint of this layout,
+ * another size or precision), STATE during a push. */
 int pdhg_state_size(pdhg_solver *s, int64_t *bytes);
 int pdhg_get_state(pdhg_solver *s, void *buf, int64_t bytes);
 int pdhg_set_state(pdhg_solver *s, const void *buf, int64_t bytes);

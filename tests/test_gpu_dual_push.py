@@ -117,17 +117,22 @@ def test_dual_push_graph_replay_equals_eager_launches():
     np.testing.assert_array_equal(out[0][1], out[1][1])
 
 
-def test_dual_push_fp32_mixed():
-    """FP32 matrix and x-vectors (y and the checks stay float64): the same face,
-    and the push cuts the dual superbasic estimate as the float64 one does."""
-    lp = lpgen.planted(400, 1000, seed=3, zero_frac=0.8, degen_frac=0.0, deg_range=(1, 9))
+@pytest.mark.parametrize("name,make", [
+    ("planted_400x1000", lambda: lpgen.planted(400, 1000, seed=3, zero_frac=0.8, degen_frac=0.0, deg_range=(1, 9))),
+    ("c5_family_m1000", lambda: lpgen.config5(seed=5, m=1000, n=4000)),
+], ids=["planted_400x1000", "c5_family_m1000"])
+def test_dual_push_fp32_mixed(name, make):
+    """FP32 matrix and x-vector differences (y and the checks stay float64):
+    the same face, and the push cuts the dual superbasic estimate as the
+    float64 one does, also on the primal-degenerate family."""
+    lp = make()
     res = {}
     for prec in ("fp64", "fp32"):
         g = pdhg.Solver(lp, precision=prec, eps_rel=1e-6, max_iter=400000)
         assert g.solve().status == pdhg.PDHG_OPTIMAL
         res[prec] = g.dual_push(4)
     a, b = res["fp64"], res["fp32"]
-    print(f"[dual push] fp32: est_dual {b.before.est_dual} -> {b.after.est_dual}, {b.iters} iterations "
+    print(f"[dual push] {name} fp32: est_dual {b.before.est_dual} -> {b.after.est_dual}, {b.iters} iterations "
           f"(fp64 {a.before.est_dual} -> {a.after.est_dual}, {a.iters})", flush=True)
     assert b.status == pdhg.PDHG_PUSH_DONE
     assert b.rel_d_push <= 1e-6

@@ -1,15 +1,15 @@
 """FP32-mixed mode against the FP64 oracle: the error is stated, not bitwise.
 
-The mixed mode streams the matrix and the n-vectors in FP32 and keeps every
-check in float64.  Rounding the matrix changes the LP (on the c1 family the
-rounded LP has no optimum at all), so the iteration runs on corrected data:
-at every anchor (x_a, y_a) the objective and right-hand side are shifted by
-the rounding error's products, chat - E'y_a and bhat - E x_a (E = Ahat -
-fl32(Ahat)), which makes the anchor's float32 residuals equal its float64
-ones.  The fixed point of a restart cycle is then the original LP's up to
-E (x - x_a), and it moves closer at every restart (defect correction).  Every
-check evaluates the float64 products fl32(Ahat) v + E v, so a reported
-OPTIMAL is an optimum of the original model at the tolerance.
+The mixed mode streams the matrix, the bounds and two n-vectors in FP32 and
+keeps every check in float64.  The n-vectors are stored as float differences
+from a float64 anchor: x - x_a and xbar - x_a, and the primal half gathers
+dy = y - y_a in float.  The kernels read the anchored objective and
+right-hand side chat - Ahat'y_a and bhat - Ahat x_a, computed in float64 at
+every anchor (restart or phase start), so the float products only see the
+differences.  Their rounding shrinks as the restart cycle converges, and the
+matrix's own rounding error E = Ahat - fl32(Ahat) enters only as E times a
+difference.  Every check evaluates the float64 products fl32(Ahat) v + E v,
+so a reported OPTIMAL is an optimum of the original model at the tolerance.
 """
 import numpy as np
 import pytest
@@ -39,15 +39,20 @@ CASES = [
     ("batched_1", lambda: lpgen.config3_instance(1)),
     ("batched_20", lambda: lpgen.config3_instance(20)),
     ("batched_100", lambda: lpgen.config3_instance(100)),
+    # the primal-degenerate family: its rows cancel near the optimum, where
+    # float32 iterates (not differences) stalled the solve
+    ("c5_family_m500", lambda: lpgen.config5(seed=5, m=500, n=2000)),
+    ("c5_family_m1000", lambda: lpgen.config5(seed=5, m=1000, n=4000)),
 ]
 
 
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
 def test_fp32_mixed_solves_the_original_lp(name, make):
     """The mixed path reaches the oracle's status at the float64 tolerance of
-    the original model, in about as many iterations as float64 (the corrected
-    iteration's fixed point is the original LP's), and the push stops with
-    the float64 primal residual at the tolerance."""
+    the original model, in about as many iterations as float64 (the anchored
+    iteration's fixed point is the original LP's; the matrix rounding may move
+    a restart by a check), and the push stops with the float64 primal
+    residual at the tolerance."""
     print(f"[fp32] {name}", flush=True)
     lp = make()
     g = pdhg.Solver(lp, precision="fp32", eps_rel=EPS, max_iter=200000)
@@ -64,8 +69,8 @@ def test_fp32_mixed_solves_the_original_lp(name, make):
     assert rg.status == pdhg.PDHG_OPTIMAL, pdhg.STATUS[rg.status]
     assert max(ko.rel_p, ko.rel_d, ko.rel_gap) <= EPS
     assert abs(ko.rel_p - rg.rel_p) <= 1e-12 and abs(ko.rel_gap - rg.rel_gap) <= 1e-12
-    assert obj_err <= 1e-5
-    assert rg.iters <= 2 * ro.iters + 640
+    assert obj_err <= 1e-7
+    assert rg.iters <= 1.25 * ro.iters + 128
     pg = g.corner_push(5)
     xh = g.get_solution()[0]
     kh = o.kkt(xh, yg)
