@@ -70,11 +70,10 @@ enum pdhg_error {
 
 enum pdhg_precision {
     PDHG_FP64 = 0,      /* matrix, vectors and updates in float64                         */
-    PDHG_FP32_MIXED = 1 /* matrix, bounds and the streamed vectors in float32: x and xbar as
-                           differences from the float64 restart anchor, y - y_anchor for the
-                           primal products; anchors, objective, dual vector, arithmetic,
-                           residual norms, restart test, termination and the push fixing
-                           test in float64                                                */
+    PDHG_FP32_MIXED = 1 /* matrix, bounds, x and xbar in float32, x and xbar stored as
+                           differences from the float64 restart anchor; anchors, objective,
+                           dual vectors, arithmetic, residual norms, restart test,
+                           termination and the push fixing test in float64                */
 };
 
 /* Parameters.  Every constant the paper leaves open lives here. */

@@ -23,7 +23,7 @@ constexpr int kRedRows = kBlock; // rows per reduction tile (one per thread)
 template <typename V, int T, int NT>
 __global__ __launch_bounds__(NT) void kb_primal(const int4 *__restrict__ tiles, const int *__restrict__ tp,
                                                const int *__restrict__ ti, const V *__restrict__ atv,
-                                               const V *__restrict__ y, const double *__restrict__ ch,
+                                               const double *__restrict__ y, const double *__restrict__ ch,
                                                const V *__restrict__ lh, const V *__restrict__ uh,
                                                V *__restrict__ x, const double *__restrict__ xa, V *__restrict__ xbar,
                                                double *__restrict__ xp, const DevState *__restrict__ sts, int i,
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(NT) void kb_primal(const int4 *__restrict__ tiles, 
         lo = (double)lh[j];
         hi = (double)uh[j];
     }
-    tile_row_sums<V, V, T, NT>(r0, rows, tp, ti, atv, y, s_ptr, s_prod, s_sum);
+    tile_row_sums<V, double, T, NT>(r0, rows, tp, ti, atv, y, s_ptr, s_prod, s_sum);
     if (!mine) return;
     primal_update<V>(j, s_sum[tid], xj, cj, lo, hi, aj, x, xbar, xp, st, i, store_cand);
 }
@@ -58,8 +58,7 @@ __global__ __launch_bounds__(NT) void kb_dual(const int4 *__restrict__ tiles, co
                                              const V *__restrict__ xbar, const double *__restrict__ bh,
                                              const int8_t *__restrict__ sense, double *__restrict__ y,
                                              const double *__restrict__ ya, double *__restrict__ yp,
-                                             float *__restrict__ dy, const DevState *__restrict__ sts, int i,
-                                             int store_cand)
+                                             const DevState *__restrict__ sts, int i, int store_cand)
 {
     __shared__ int s_ptr[T + 1];
     __shared__ double s_prod[kTileU * NT];
@@ -81,18 +80,17 @@ __global__ __launch_bounds__(NT) void kb_dual(const int4 *__restrict__ tiles, co
     }
     tile_row_sums<V, V, T, NT>(r0, rows, rp, ci, av, xbar, s_ptr, s_prod, s_sum);
     if (!mine) return;
-    dual_update(r, s_sum[tid], yr, br, ar, sn, y, yp, dy, st, i, store_cand);
+    dual_update(r, s_sum[tid], yr, br, ar, sn, y, yp, st, i, store_cand);
 }
 
 template <typename V>
 static void launch_primal_b(pdhg_batch *b, int i, int store, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     pdhg_solver *s = b->s;
-    const void *yg = s->fp32 ? (const void *)s->dy : s->y; // the dual vector the products gather
 #define PDHG_BP_CASE(TT, RR, NT)                                                                               \
     case TT:                                                                                                   \
         PDHG_LAUNCH(e0, e1, (kb_primal<V, RR, NT>), dim3(b->n_ptiles), dim3(NT), s->stream, b->ptiles, s->tp, \
-                           s->ti, (const V *)s->ahat_t, (const V *)yg, s->chc,                                 \
+                           s->ti, (const V *)s->ahat_t, (const double *)s->y, s->chc,                         \
                            (const V *)s->lh, (const V *)s->uh, (V *)s->x, (const double *)s->xa, (V *)s->xbar,\
                            (double *)s->xp, b->sts, i, store);                                                \
         break;
@@ -116,7 +114,7 @@ static void launch_dual_b(pdhg_batch *b, int i, int store, hipEvent_t e0 = nullp
     case TT:                                                                                                   \
         PDHG_LAUNCH(e0, e1, (kb_dual<V, RR, NT>), dim3(b->n_dtiles), dim3(NT), s->stream, b->dtiles, s->rp,   \
                            s->ci, (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense,    \
-                           (double *)s->y, (const double *)s->ya, (double *)s->yp, s->dy, b->sts, i, store);  \
+                           (double *)s->y, (const double *)s->ya, (double *)s->yp, b->sts, i, store);         \
         break;
     switch (-b->kern_a) {
         PDHG_BD_CASE(32, 32, 256)
@@ -244,14 +242,14 @@ __global__ __launch_bounds__(kBlock) void kb_check_final(DevState *__restrict__ 
 }
 
 // restart copies per tile: column tiles first, then row tiles (mixed mode:
-// the stored differences x - x_a and dy become 0)
+// the stored difference x - x_a becomes 0)
 template <typename V>
 __global__ __launch_bounds__(kBlock) void kb_restart_apply(const int4 *__restrict__ rn, int ntn,
                                                           const int4 *__restrict__ rm,
                                                           const DevState *__restrict__ sts, V *__restrict__ x,
                                                           double *__restrict__ xa, const double *__restrict__ xp,
                                                           double *__restrict__ y, double *__restrict__ ya,
-                                                          const double *__restrict__ yp, float *__restrict__ dy)
+                                                          const double *__restrict__ yp)
 {
     constexpr bool delta = sizeof(V) == sizeof(float);
     const bool col = (int)blockIdx.x < ntn;
@@ -268,16 +266,15 @@ __global__ __launch_bounds__(kBlock) void kb_restart_apply(const int4 *__restric
         const double v = yp[k];
         y[k] = v;
         ya[k] = v;
-        if (dy) dy[k] = 0.0f;
     }
 }
 
 // Anchored objective and right-hand side per LP (mixed mode): chc = ch -
-// (pa + pb), bhc = bh - (qa + qb) with pa + pb = Ahat' y_a and qa + qb =
-// Ahat x_a in float64 (pb, qb may be NULL; pa, qa may be the outputs), for
-// every LP that restarted at this check (the check left its candidate's
-// float64 products in aty and ax), or for every LP with `always` (a phase
-// start); column tiles, then row tiles.
+// (pa + pb), bhc = bh - (qa + qb) with pa + pb = E' y_a and qa + qb = Ahat
+// x_a in float64 (pb, qb may be NULL; qa may be the output), for every LP
+// that restarted at this check (the check left E' y+ in ety and the float64
+// Ahat x+ in ax), or for every LP with `always` (a phase start); column
+// tiles, then row tiles.
 __global__ __launch_bounds__(kBlock) void kb_defect_set(const int4 *__restrict__ rn, int ntn,
                                                        const int4 *__restrict__ rm,
                                                        const DevState *__restrict__ sts, int always,
@@ -372,14 +369,14 @@ static void check_b(pdhg_batch *b, int mode, int len)
                        b->rm_start, b->rn_start, mode, len);
     if (mode == 1 && s->hx) (void)batch_record_history(b); // before the restart copies
     if (mode == 2 && s->learned_active) (void)batch_learned_undo(b);
-    if (mode != 0 && s->aerr) // the check left Ahat x+ and Ahat' y+ (float64) in ax and aty
+    if (mode != 0 && s->aerr) // the check left E' y+ in ety and Ahat x+ (float64) in ax
         hipLaunchKernelGGL(kb_defect_set, dim3(b->n_rn + b->n_rm), dim3(kBlock), 0, st, b->rn, b->n_rn, b->rm, b->sts, 0,
-                           s->ch, (const double *)s->aty, (const double *)nullptr, s->chc, (const double *)s->bh,
+                           s->ch, (const double *)s->ety, (const double *)nullptr, s->chc, (const double *)s->bh,
                            (const double *)s->ax, (const double *)nullptr, s->bhc);
     if (mode != 0)
         hipLaunchKernelGGL((kb_restart_apply<V>), dim3(b->n_rn + b->n_rm), dim3(kBlock), 0, st, b->rn, b->n_rn, b->rm,
                            b->sts, (V *)s->x, (double *)s->xa, (const double *)s->xp, (double *)s->y, (double *)s->ya,
-                           (const double *)s->yp, s->dy);
+                           (const double *)s->yp);
 }
 
 hipError_t batch_iterations(pdhg_batch *b, int count, bool check_at_end, int mode, bool timed_launch)
@@ -638,17 +635,15 @@ hipError_t batch_defect_refresh(pdhg_batch *b)
         return hipSuccess;
     }
     // the LPs taking part in the phase (the tiles skip the others): fl32(Ahat)
-    // x_a and fl32(Ahat)' y_a into bhc and chc, E x_a and E' y_a into ex and ety
+    // x_a into bhc, E x_a into ex, E' y_a into ety
     const double *xa = (const double *)s->xa, *ya = (const double *)s->ya;
     launch_spmv_b<float, double>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci, (const float *)s->ahat, xa,
                                  s->bhc);
-    launch_spmv_b<float, double>(b, b->kern_at, b->ptiles, b->n_ptiles, s->tp, s->ti, (const float *)s->ahat_t, ya,
-                                 s->chc);
     launch_spmv_b<float, double>(b, b->kern_a, b->dtiles, b->n_dtiles, s->rp, s->ci, (const float *)s->aerr, xa, s->ex);
     launch_spmv_b<float, double>(b, b->kern_at, b->ptiles, b->n_ptiles, s->tp, s->ti, (const float *)s->aerr_t, ya,
                                  s->ety);
     hipLaunchKernelGGL(kb_defect_set, dim3(b->n_rn + b->n_rm), dim3(kBlock), 0, s->stream, b->rn, b->n_rn, b->rm,
-                       b->sts, 1, s->ch, (const double *)s->chc, (const double *)s->ety, s->chc,
+                       b->sts, 1, s->ch, (const double *)s->ety, (const double *)nullptr, s->chc,
                        (const double *)s->bh, (const double *)s->bhc, (const double *)s->ex, s->bhc);
     return hipGetLastError();
 }
@@ -1286,16 +1281,12 @@ hipError_t batch_autotune(pdhg_batch *b)
     pdhg_solver *s = b->s;
     const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
     void *sx = nullptr, *sxbar = nullptr, *sxp = nullptr, *sy = nullptr, *syp = nullptr;
-    float *sdy = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipMalloc(&sx, vb * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sxbar, vb * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sxp, sizeof(double) * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sy, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
     if (e == hipSuccess) e = hipMalloc(&syp, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
-    if (e == hipSuccess && s->dy) e = hipMalloc(&sdy, sizeof(float) * (size_t)(s->m > 0 ? s->m : 1));
-    if (e == hipSuccess && s->dy)
-        e = hipMemcpyAsync(sdy, s->dy, sizeof(float) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
     if (e == hipSuccess) e = hipMemcpyAsync(sx, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
@@ -1303,13 +1294,11 @@ hipError_t batch_autotune(pdhg_batch *b)
     if (e == hipSuccess) e = hipMemcpyAsync(sy, s->y, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
     const int cands[] = {-32, -64, -128, -256, -1032, -1064};
     void *keep[5] = {s->x, s->xbar, s->xp, s->y, s->yp};
-    float *keep_dy = s->dy;
     s->x = sx;
     s->xbar = sxbar;
     s->xp = sxp;
     s->y = sy;
     s->yp = syp;
-    s->dy = sdy;
     int best_at = b->kern_at, best_a = b->kern_a;
     for (int half = 0; half < 2 && e == hipSuccess; half++) {
         float best = 1e30f;
@@ -1343,10 +1332,9 @@ hipError_t batch_autotune(pdhg_batch *b)
     s->xp = keep[2];
     s->y = keep[3];
     s->yp = keep[4];
-    s->dy = keep_dy;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    for (void *q : {sx, sxbar, sxp, sy, syp, (void *)sdy})
+    for (void *q : {sx, sxbar, sxp, sy, syp})
         if (q) (void)hipFree(q);
     if (e != hipSuccess) return e;
     return batch_set_kernels(b, best_at, best_a);

@@ -43,13 +43,12 @@ double gate_threshold(const pdhg_params &p, int64_t m)
 void model_bytes(const pdhg_solver *s, int64_t *bytes_primal, int64_t *bytes_dual)
 {
     const int64_t v = s->fp32 ? 4 : 8, m = s->m, n = s->n, nz = s->nnz;
-    const int64_t gy = s->fp32 ? 4 : 8; // the gathered dual vector: dy (float) or y
-    // primal: row pointers (none for uniform columns), indices + values, the
-    // dual vector gathered once, reads x, chat, x_anchor, lhat, uhat, writes x, xbar
-    *bytes_primal = (uses_uniform_kernel(s) ? 0 : 4 * (n + 1)) + (4 + v) * nz + gy * m + (5 * v + 16) * n;
+    // primal: row pointers (none for uniform columns), indices + values, y
+    // gathered once, reads x, chat, x_anchor, lhat, uhat, writes x, xbar
+    *bytes_primal = (uses_uniform_kernel(s) ? 0 : 4 * (n + 1)) + (4 + v) * nz + 8 * m + (5 * v + 16) * n;
     // dual: row pointers, indices + values, xbar gathered once, reads y, bhat,
-    // y_anchor, sense byte, writes y (and dy in the mixed mode)
-    *bytes_dual = 4 * (m + 1) + (4 + v) * nz + v * n + 4 * 8 * m + m + (s->fp32 ? 4 * m : 0);
+    // y_anchor, sense byte, writes y
+    *bytes_dual = 4 * (m + 1) + (4 + v) * nz + v * n + 4 * 8 * m + m;
 }
 } // namespace pdhg
 
@@ -91,7 +90,7 @@ void free_all(pdhg_solver *s)
                     s->hx,   s->hz,  s->feat_raw, s->feat_b, s->logits, s->lfix, s->lcount, s->sell_idx,
                     s->sell_val, s->sell_soff, s->sell_len, s->sell_wi_start, s->sell_wi, s->sell_part,
                     s->ypush, s->zpush, s->w0, s->aerr, s->aerr_t, s->ex, s->ety,
-                    s->aerr ? (void *)s->chc : nullptr, s->aerr ? (void *)s->bhc : nullptr, s->dy};
+                    s->aerr ? (void *)s->chc : nullptr, s->aerr ? (void *)s->bhc : nullptr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->st_host) (void)hipHostFree(s->st_host);
@@ -226,15 +225,15 @@ bool run_batch_phase(pdhg_batch *b, int64_t iters, int mode, double t0)
     // algorithmic bytes of one primal / dual launch over the LPs that have not
     // stopped (tiles of stopped LPs exit at once), from the last host view
     // (the single-LP byte model, per LP)
-    const double vbytes = s->fp32 ? 4.0 : 8.0, gy = s->fp32 ? 4.0 : 8.0, dyw = s->fp32 ? 4.0 : 0.0;
+    const double vbytes = s->fp32 ? 4.0 : 8.0;
     auto active_bytes = [&](double &bp, double &bd) {
         bp = bd = 0.0;
         for (int i = 0; i < b->count; i++) {
             if (b->sts_host[i].done) continue;
             const double mi = (double)(b->roff[i + 1] - b->roff[i]), ni = (double)(b->coff[i + 1] - b->coff[i]);
             const double nz = (double)b->nnz_of[i];
-            bp += 4.0 * (ni + 1) + (4.0 + vbytes) * nz + gy * mi + (5.0 * vbytes + 16.0) * ni;
-            bd += 4.0 * (mi + 1) + (4.0 + vbytes) * nz + vbytes * ni + (33.0 + dyw) * mi;
+            bp += 4.0 * (ni + 1) + (4.0 + vbytes) * nz + 8.0 * mi + (5.0 * vbytes + 16.0) * ni;
+            bd += 4.0 * (mi + 1) + (4.0 + vbytes) * nz + vbytes * ni + 33.0 * mi;
         }
     };
     HIPCHK(batch_compact_tiles(b, true));
@@ -472,7 +471,6 @@ static int build_solver(int m, int n, int nz, const pdhg_params &p, const ModelS
             dalloc(&s->ety, N);
             dalloc(&s->chc, N);
             dalloc(&s->bhc, M);
-            dalloc(&s->dy, M);
         } else {
             defect_alias(s);
         }
@@ -1085,7 +1083,6 @@ int pdhg_set_state(pdhg_solver *s, const void *buf, int64_t bytes)
             HIPCHK(hipMemcpyAsync(dst, p, yb, hipMemcpyHostToDevice, st));
             p += yb;
         }
-        HIPCHK(restore_dy(s)); // mixed mode: dy = y - y_a, as the dual half wrote it
         HIPCHK(hipMemcpyAsync(s->st_host, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         s->t_host = h.t_host;

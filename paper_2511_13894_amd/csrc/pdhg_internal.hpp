@@ -108,16 +108,15 @@ struct pdhg_solver {
     void *ahat = nullptr, *ahat_t = nullptr;
     void *x = nullptr, *y = nullptr, *xa = nullptr, *ya = nullptr, *xbar = nullptr;
     void *xp = nullptr, *yp = nullptr;
-    float *dy = nullptr;             // mixed mode: y - y_a, the vector the primal half gathers
     double *ch = nullptr;            // scaled objective
     void *bh = nullptr, *lh = nullptr, *uh = nullptr;
     // Mixed precision: the rounding error of the float matrix, E = Ahat -
     // fl32(Ahat), stored as float in A order and transpose order, so that
     // fl32(Ahat) v + E v is the float64 product (ex, ety: the error parts of
     // a product).  The iteration kernels read chc and bhc: in float64 mode
-    // the same arrays as ch and bh; in the mixed mode ch - Ahat' y_a and
+    // the same arrays as ch and bh; in the mixed mode ch - E' y_a and
     // bh - Ahat x_a at the anchor (x_a, y_a) in float64, which the float
-    // products of the differences complete.
+    // products of y and of the differences xbar - x_a complete.
     void *aerr = nullptr, *aerr_t = nullptr;
     double *ex = nullptr, *ety = nullptr;
     double *chc = nullptr, *bhc = nullptr;
@@ -323,7 +322,6 @@ hipError_t candidate_from_iterate(pdhg_solver *s);
 hipError_t launch_start_vectors(pdhg_solver *s, bool fresh_start);
 hipError_t unscale(pdhg_solver *s, const double *xh, const double *yh, double *xo, double *yo);
 hipError_t unscale_iterate(pdhg_solver *s, double *xo, double *yo); // the current iterate (x, y), unscaled
-hipError_t restore_dy(pdhg_solver *s); // mixed mode: dy = y - y_a (nothing in float64 mode)
 hipError_t report(pdhg_solver *s, const double *x, const double *y, double *z, pdhg_kkt_report *k);
 hipError_t push_setup(pdhg_solver *s, uint64_t seed, pdhg_push_result *r, double theta);
 hipError_t dual_push_setup(pdhg_solver *s, uint64_t seed, const double *xk, double *w0, double *yn, double *atyn,

@@ -13,7 +13,7 @@ namespace pdhg {
 // ------------------------------------------------------------ iteration ---
 template <typename V, int L>
 __global__ __launch_bounds__(kBlock) void k_primal(int n, const int *__restrict__ tp, const int *__restrict__ ti,
-                                                  const V *__restrict__ atv, const V *__restrict__ y,
+                                                  const V *__restrict__ atv, const double *__restrict__ y,
                                                   const double *__restrict__ ch, const V *__restrict__ lh,
                                                   const V *__restrict__ uh, V *__restrict__ x,
                                                   const double *__restrict__ xa, V *__restrict__ xbar,
@@ -41,8 +41,8 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
                                                 const V *__restrict__ av, const V *__restrict__ xbar,
                                                 const double *__restrict__ bh, const int8_t *__restrict__ sense,
                                                 double *__restrict__ y, const double *__restrict__ ya,
-                                                double *__restrict__ yp, float *__restrict__ dy,
-                                                const DevState *__restrict__ st, int i, int store_cand)
+                                                double *__restrict__ yp, const DevState *__restrict__ st, int i,
+                                                int store_cand)
 {
     const int64_t gi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int64_t r = gi / L;
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
     double acc = lane_dot<L, double>(rp[r], rp[r + 1], lane, ci, av, xbar);
     acc = group_sum<L>(acc);
     if (lane != 0) return;
-    dual_update(r, acc, yr, br, ar, sn, y, yp, dy, st, i, store_cand);
+    dual_update(r, acc, yr, br, ar, sn, y, yp, st, i, store_cand);
 }
 
 // ------------------------------------------------------- long rows ---
@@ -197,7 +197,7 @@ hipError_t solver_product(pdhg_solver *s, bool transpose, const double *vec, dou
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_primal_rowblock(int n, const int *__restrict__ tp,
                                                            const int *__restrict__ ti, const V *__restrict__ atv,
-                                                           const V *__restrict__ y, const double *__restrict__ ch,
+                                                           const double *__restrict__ y, const double *__restrict__ ch,
                                                            const V *__restrict__ lh, const V *__restrict__ uh,
                                                            V *__restrict__ x, const double *__restrict__ xa,
                                                            V *__restrict__ xbar, double *__restrict__ xp,
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_primal_rowblock(int n, const int *__
         lo = (double)lh[j];
         hi = (double)uh[j];
     }
-    const double g = row_block_sum<V, V>(tp[j], tp[j + 1], ti, atv, y);
+    const double g = row_block_sum<V, double>(tp[j], tp[j + 1], ti, atv, y);
     if (threadIdx.x == 0) primal_update<V>(j, g, xj, cj, lo, hi, aj, x, xbar, xp, st, i, store_cand);
 }
 
@@ -223,8 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_dual_rowblock(int m, const int *__re
                                                          const double *__restrict__ bh,
                                                          const int8_t *__restrict__ sense, double *__restrict__ y,
                                                          const double *__restrict__ ya, double *__restrict__ yp,
-                                                         float *__restrict__ dy, const DevState *__restrict__ st, int i,
-                                                         int store_cand)
+                                                         const DevState *__restrict__ st, int i, int store_cand)
 {
     if (st->done) return;
     const int r = xcd_block(blockIdx.x, gridDim.x);
@@ -237,12 +236,12 @@ __global__ __launch_bounds__(kBlock) void k_dual_rowblock(int m, const int *__re
         sn = sense[r];
     }
     const double h = row_block_sum<V, V>(rp[r], rp[r + 1], ci, av, xbar);
-    if (threadIdx.x == 0) dual_update(r, h, yr, br, ar, sn, y, yp, dy, st, i, store_cand);
+    if (threadIdx.x == 0) dual_update(r, h, yr, br, ar, sn, y, yp, st, i, store_cand);
 }
 
 template <typename V, int T, int NT>
 __global__ __launch_bounds__(NT) void k_primal_tiled(int n, const int *__restrict__ tp, const int *__restrict__ ti,
-                                                    const V *__restrict__ atv, const V *__restrict__ y,
+                                                    const V *__restrict__ atv, const double *__restrict__ y,
                                                     const double *__restrict__ ch, const V *__restrict__ lh,
                                                     const V *__restrict__ uh, V *__restrict__ x,
                                                     const double *__restrict__ xa, V *__restrict__ xbar,
@@ -265,7 +264,7 @@ __global__ __launch_bounds__(NT) void k_primal_tiled(int n, const int *__restric
     const double aj = xa[jc], xj = iterate_value<V>(x[jc], aj), cj = ch[jc], lo = (double)lh[jc],
                  hi = (double)uh[jc];
     if (st->done) return;
-    tile_row_sums<V, V, T, NT>(r0, rows, tp, ti, atv, y, s_ptr, s_prod, s_sum);
+    tile_row_sums<V, double, T, NT>(r0, rows, tp, ti, atv, y, s_ptr, s_prod, s_sum);
     if (!mine) return;
     primal_update<V>(j, s_sum[tid], xj, cj, lo, hi, aj, x, xbar, xp, st, i, store_cand);
 }
@@ -275,8 +274,8 @@ __global__ __launch_bounds__(NT) void k_dual_tiled(int m, const int *__restrict_
                                                   const V *__restrict__ av, const V *__restrict__ xbar,
                                                   const double *__restrict__ bh, const int8_t *__restrict__ sense,
                                                   double *__restrict__ y, const double *__restrict__ ya,
-                                                  double *__restrict__ yp, float *__restrict__ dy,
-                                                  const DevState *__restrict__ st, int i, int store_cand)
+                                                  double *__restrict__ yp, const DevState *__restrict__ st, int i,
+                                                  int store_cand)
 {
     __shared__ int s_ptr[T + 1];
     __shared__ double s_prod[kTileU * NT];
@@ -292,7 +291,7 @@ __global__ __launch_bounds__(NT) void k_dual_tiled(int m, const int *__restrict_
     if (st->done) return;
     tile_row_sums<V, V, T, NT>(r0, rows, rp, ci, av, xbar, s_ptr, s_prod, s_sum);
     if (!mine) return;
-    dual_update(r, s_sum[tid], yr, br, ar, sn, y, yp, dy, st, i, store_cand);
+    dual_update(r, s_sum[tid], yr, br, ar, sn, y, yp, st, i, store_cand);
 }
 
 // Primal half when every column of A has the same D <= 3 entries (every
@@ -304,7 +303,7 @@ __global__ __launch_bounds__(NT) void k_dual_tiled(int m, const int *__restrict_
 // tiles (one thread per row) sum them: the two give the same bits.
 template <typename V, int D>
 __global__ __launch_bounds__(kBlock) void k_primal_udeg(int n, const int *__restrict__ ti, const V *__restrict__ atv,
-                                                       const V *__restrict__ y, const double *__restrict__ ch,
+                                                       const double *__restrict__ y, const double *__restrict__ ch,
                                                        const V *__restrict__ lh, const V *__restrict__ uh,
                                                        V *__restrict__ x, const double *__restrict__ xa,
                                                        V *__restrict__ xbar, double *__restrict__ xp,
@@ -323,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_primal_udeg(int n, const int *__rest
     if (st->done) return;
     double g[D];
 #pragma unroll
-    for (int d = 0; d < D; d++) g[d] = (double)y[id[d]];
+    for (int d = 0; d < D; d++) g[d] = y[id[d]];
     double acc = 0.0;
     {
 #pragma clang fp contract(off)
@@ -339,7 +338,6 @@ static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = null
 {
     const int L = s->kern_at;
     if (s->n <= 0) return;
-    const void *yg = s->fp32 ? (const void *)s->dy : s->y; // the dual vector the products gather
     // uniform columns, kernel chosen by the library: the 256-row tiles' sums with fewer loads
     // (an explicit lanes_at = -256 keeps the tiles)
     if (uses_uniform_kernel(s)) {
@@ -347,7 +345,7 @@ static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = null
 #define PDHG_UD_CASE(DD)                                                                                       \
     case DD:                                                                                                   \
         PDHG_LAUNCH(e0, e1, (k_primal_udeg<V, DD>), dim3(grid), dim3(kBlock), s->stream, s->n, s->ti,        \
-                    (const V *)s->ahat_t, (const V *)yg, s->chc, (const V *)s->lh, (const V *)s->uh,    \
+                    (const V *)s->ahat_t, (const double *)s->y, s->chc, (const V *)s->lh, (const V *)s->uh,    \
                     (V *)s->x, (const double *)s->xa, (V *)s->xbar, (double *)s->xp, s->st, i, store);                   \
         break;
         switch (s->udeg_at) {
@@ -361,7 +359,7 @@ static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = null
     }
     if (L == kRowBlock) {
         PDHG_LAUNCH(e0, e1, (k_primal_rowblock<V>), dim3(s->n), dim3(kBlock), s->stream, s->n, s->tp, s->ti,
-                    (const V *)s->ahat_t, (const V *)yg, s->chc, (const V *)s->lh, (const V *)s->uh,
+                    (const V *)s->ahat_t, (const double *)s->y, s->chc, (const V *)s->lh, (const V *)s->uh,
                     (V *)s->x, (const double *)s->xa, (V *)s->xbar, (double *)s->xp, s->st, i, store);
         return;
     }
@@ -372,7 +370,7 @@ static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = null
 #define PDHG_PT_CASE(TT, RR, NT)                                                                                \
     case TT:                                                                                                    \
         PDHG_LAUNCH(e0, e1, (k_primal_tiled<V, RR, NT>), dim3(grid), dim3(NT), s->stream, s->n, s->tp, s->ti, \
-                           (const V *)s->ahat_t, (const V *)yg, s->chc, (const V *)s->lh,          \
+                           (const V *)s->ahat_t, (const double *)s->y, s->chc, (const V *)s->lh,          \
                            (const V *)s->uh, (V *)s->x, (const double *)s->xa, (V *)s->xbar, (double *)s->xp, s->st, i,  \
                            store);                                                                              \
         break;
@@ -392,7 +390,7 @@ static void launch_primal(pdhg_solver *s, int i, int store, hipEvent_t e0 = null
 #define PDHG_PRIMAL_CASE(LL)                                                                                    \
     case LL:                                                                                                    \
         PDHG_LAUNCH(e0, e1, (k_primal<V, LL>), dim3(grid), dim3(kBlock), s->stream, s->n, s->tp, s->ti,      \
-                           (const V *)s->ahat_t, (const V *)yg, s->chc, (const V *)s->lh,          \
+                           (const V *)s->ahat_t, (const double *)s->y, s->chc, (const V *)s->lh,          \
                            (const V *)s->uh, (V *)s->x, (const double *)s->xa, (V *)s->xbar, (double *)s->xp, s->st, i,  \
                            store);                                                                              \
         break;
@@ -421,7 +419,7 @@ static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullpt
     if (L == kRowBlock) {
         PDHG_LAUNCH(e0, e1, (k_dual_rowblock<V>), dim3(s->m), dim3(kBlock), s->stream, s->m, s->rp, s->ci,
                     (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense, (double *)s->y,
-                    (const double *)s->ya, (double *)s->yp, s->dy, s->st, i, store);
+                    (const double *)s->ya, (double *)s->yp, s->st, i, store);
         return;
     }
     if (L < 0) {
@@ -432,7 +430,7 @@ static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullpt
     case TT:                                                                                                    \
         PDHG_LAUNCH(e0, e1, (k_dual_tiled<V, RR, NT>), dim3(grid), dim3(NT), s->stream, s->m, s->rp, s->ci,   \
                            (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense, (double *)s->y,\
-                           (const double *)s->ya, (double *)s->yp, s->dy, s->st, i, store);                                      \
+                           (const double *)s->ya, (double *)s->yp, s->st, i, store);                                      \
         break;
         switch (T) {
             PDHG_DT_CASE(32, 32, 256)
@@ -451,7 +449,7 @@ static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullpt
     case LL:                                                                                                    \
         PDHG_LAUNCH(e0, e1, (k_dual<V, LL>), dim3(grid), dim3(kBlock), s->stream, s->m, s->rp, s->ci,        \
                            (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense, (double *)s->y,\
-                           (const double *)s->ya, (double *)s->yp, s->dy, s->st, i, store);                                      \
+                           (const double *)s->ya, (double *)s->yp, s->st, i, store);                                      \
         break;
     switch (L) {
         PDHG_DUAL_CASE(1)
@@ -577,12 +575,12 @@ __global__ __launch_bounds__(kBlock) void k_check_final(DevState *st, const doub
 }
 
 // On restart: x = x_anchor = x+, y = y_anchor = y+ (candidate of the check);
-// in the mixed mode the stored differences x - x_a and dy = y - y_a become 0.
+// in the mixed mode the stored difference x - x_a becomes 0.
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_restart_apply(int n, int m, const DevState *st, V *__restrict__ x,
                                                          double *__restrict__ xa, const double *__restrict__ xp,
                                                          double *__restrict__ y, double *__restrict__ ya,
-                                                         const double *__restrict__ yp, float *__restrict__ dy)
+                                                         const double *__restrict__ yp)
 {
     constexpr bool delta = sizeof(V) == sizeof(float);
     if (!st->restart_flag || st->done) return;
@@ -596,17 +594,16 @@ __global__ __launch_bounds__(kBlock) void k_restart_apply(int n, int m, const De
             const double v = yp[r];
             y[r] = v;
             ya[r] = v;
-            if (dy) dy[r] = 0.0f;
         }
     }
 }
 
 // Anchored objective and right-hand side (mixed mode): chc = ch - (pa + pb)
-// and bhc = bh - (qa + qb), where pa + pb = Ahat' y_a and qa + qb = Ahat x_a
-// in float64 (pb, qb may be NULL; pa, qa may be the outputs themselves).  At
-// a restart the candidate becomes the anchor and the check has just left its
-// float64 products in aty and ax; with `always` (a phase start) regardless
-// of the restart flag.
+// and bhc = bh - (qa + qb), where pa + pb = E' y_a and qa + qb = Ahat x_a in
+// float64 (pb, qb may be NULL; qa may be the output itself).  At a restart the
+// candidate becomes the anchor and the check has just left E' y+ in ety and
+// the float64 product Ahat x+ in ax; with `always` (a phase start)
+// regardless of the restart flag.
 __global__ __launch_bounds__(kBlock) void k_defect_set(int n, int m, const DevState *st, int always,
                                                       const double *ch, const double *pa, const double *pb,
                                                       double *chc, const double *bh, const double *qa,
@@ -676,18 +673,18 @@ hipError_t launch_check(pdhg_solver *s, int mode, int len)
     }
     if (mode != 0) {
         const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
-        if (s->aerr) // the check left Ahat x+ and Ahat' y+ (float64) in ax and aty
+        if (s->aerr) // the check left E' y+ in ety and Ahat x+ (float64) in ax
             hipLaunchKernelGGL(k_defect_set, dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->st, 0, s->ch,
-                               (const double *)s->aty, (const double *)nullptr, s->chc, (const double *)s->bh,
+                               (const double *)s->ety, (const double *)nullptr, s->chc, (const double *)s->bh,
                                (const double *)s->ax, (const double *)nullptr, s->bhc);
         if (s->fp32)
             hipLaunchKernelGGL((k_restart_apply<float>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->st,
                                (float *)s->x, (double *)s->xa, (const double *)s->xp, (double *)s->y, (double *)s->ya,
-                               (const double *)s->yp, s->dy);
+                               (const double *)s->yp);
         else
             hipLaunchKernelGGL((k_restart_apply<double>), dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->st,
                                (double *)s->x, (double *)s->xa, (const double *)s->xp, (double *)s->y, (double *)s->ya,
-                               (const double *)s->yp, (float *)nullptr);
+                               (const double *)s->yp);
     }
     return hipGetLastError();
 }
@@ -731,15 +728,14 @@ hipError_t defect_refresh(pdhg_solver *s)
     }
     hipStream_t st = s->stream;
     const double *xa = (const double *)s->xa, *ya = (const double *)s->ya;
-    // fl32(Ahat) x_a and fl32(Ahat)' y_a into bhc and chc, E x_a and E' y_a into ex and ety
+    // fl32(Ahat) x_a into bhc, E x_a into ex, E' y_a into ety
     if (s->kern_a == kSell) sell_product(s, xa, s->bhc);
     else check_spmv<float, double>(st, s->kern_a, s->m, s->rp, s->ci, (const float *)s->ahat, xa, s->bhc);
-    check_spmv<float, double>(st, s->kern_at, s->n, s->tp, s->ti, (const float *)s->ahat_t, ya, s->chc);
     check_spmv<float, double>(st, err_kern_a(s), s->m, s->rp, s->ci, (const float *)s->aerr, xa, s->ex);
     check_spmv<float, double>(st, s->kern_at, s->n, s->tp, s->ti, (const float *)s->aerr_t, ya, s->ety);
     const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
     hipLaunchKernelGGL(k_defect_set, dim3(g), dim3(kBlock), 0, st, s->n, s->m, s->st, 1, s->ch,
-                       (const double *)s->chc, (const double *)s->ety, s->chc, (const double *)s->bh,
+                       (const double *)s->ety, (const double *)nullptr, s->chc, (const double *)s->bh,
                        (const double *)s->bhc, (const double *)s->ex, s->bhc);
     return hipGetLastError();
 }
@@ -837,12 +833,11 @@ __global__ __launch_bounds__(kBlock) void k_phase_start(DevState *st, const doub
 }
 
 // x = clamp(0, lhat, uhat), y = 0, anchors = (x, y) (mixed mode: x_a = that
-// point, stored differences x - x_a and dy = 0)
+// point, stored difference x - x_a = 0)
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_start_point(int n, int m, const V *__restrict__ lh, const V *__restrict__ uh,
                                                        V *__restrict__ x, double *__restrict__ xa,
-                                                       double *__restrict__ y, double *__restrict__ ya,
-                                                       float *__restrict__ dy)
+                                                       double *__restrict__ y, double *__restrict__ ya)
 {
     constexpr bool delta = sizeof(V) == sizeof(float);
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
@@ -855,7 +850,6 @@ __global__ __launch_bounds__(kBlock) void k_start_point(int n, int m, const V *_
         } else {
             y[i - n] = 0.0;
             ya[i - n] = 0.0;
-            if (dy) dy[i - n] = 0.0f;
         }
     }
 }
@@ -864,8 +858,7 @@ __global__ __launch_bounds__(kBlock) void k_start_point(int n, int m, const V *_
 // differences are 0)
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_copy_anchor(int n, int m, V *__restrict__ x, double *__restrict__ xa,
-                                                       const double *__restrict__ y, double *__restrict__ ya,
-                                                       float *__restrict__ dy)
+                                                       const double *__restrict__ y, double *__restrict__ ya)
 {
     constexpr bool delta = sizeof(V) == sizeof(float);
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += (int64_t)gridDim.x * kBlock) {
@@ -878,7 +871,6 @@ __global__ __launch_bounds__(kBlock) void k_copy_anchor(int n, int m, V *__restr
             }
         } else {
             ya[i - n] = y[i - n];
-            if (dy) dy[i - n] = 0.0f;
         }
     }
 }
@@ -890,10 +882,10 @@ static void start_vectors(pdhg_solver *s, bool fresh_start)
     const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
     if (fresh_start)
         hipLaunchKernelGGL((k_start_point<V>), dim3(g), dim3(kBlock), 0, st, s->n, s->m, (const V *)s->lh,
-                           (const V *)s->uh, (V *)s->x, (double *)s->xa, (double *)s->y, (double *)s->ya, s->dy);
+                           (const V *)s->uh, (V *)s->x, (double *)s->xa, (double *)s->y, (double *)s->ya);
     else
         hipLaunchKernelGGL((k_copy_anchor<V>), dim3(g), dim3(kBlock), 0, st, s->n, s->m, (V *)s->x, (double *)s->xa,
-                           (const double *)s->y, (double *)s->ya, s->dy);
+                           (const double *)s->y, (double *)s->ya);
 }
 
 // x = clamp(0, lhat, uhat), y = 0 (fresh) or anchors = current (x, y)
@@ -1038,21 +1030,6 @@ hipError_t unscale(pdhg_solver *s, const double *xh, const double *yh, double *x
     const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
     hipLaunchKernelGGL(k_unscale, dim3(g), dim3(kBlock), 0, s->stream, s->n, s->m, s->dc, s->dr, xh,
                        (const float *)nullptr, yh, xo, yo);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(kBlock) void k_restore_dy(int m, const double *__restrict__ y,
-                                                      const double *__restrict__ ya, float *__restrict__ dy)
-{
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock)
-        dy[i] = (float)(y[i] - ya[i]);
-}
-
-hipError_t restore_dy(pdhg_solver *s)
-{
-    if (!s->dy || s->m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_restore_dy, dim3(grid_for(s->m, kBlock, 8192)), dim3(kBlock), 0, s->stream, s->m,
-                       (const double *)s->y, (const double *)s->ya, s->dy);
     return hipGetLastError();
 }
 
@@ -1455,16 +1432,12 @@ hipError_t autotune(pdhg_solver *s)
 {
     const size_t vb = s->fp32 ? sizeof(float) : sizeof(double);
     void *sx = nullptr, *sxbar = nullptr, *sxp = nullptr, *sy = nullptr, *syp = nullptr;
-    float *sdy = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipMalloc(&sx, vb * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sxbar, vb * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sxp, sizeof(double) * (size_t)(s->n > 0 ? s->n : 1));
     if (e == hipSuccess) e = hipMalloc(&sy, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
     if (e == hipSuccess) e = hipMalloc(&syp, sizeof(double) * (size_t)(s->m > 0 ? s->m : 1));
-    if (e == hipSuccess && s->dy) e = hipMalloc(&sdy, sizeof(float) * (size_t)(s->m > 0 ? s->m : 1));
-    if (e == hipSuccess && s->dy)
-        e = hipMemcpyAsync(sdy, s->dy, sizeof(float) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
     if (e == hipSuccess) e = hipMemcpyAsync(sx, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
@@ -1472,13 +1445,11 @@ hipError_t autotune(pdhg_solver *s)
     if (e == hipSuccess) e = hipMemcpyAsync(sy, s->y, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
     const int cands[] = {-32, -64, -128, -256, -1032, -1064, 1, 2, 4, 8, 16, 32, 64, kRowBlock, kSell};
     void *keep[5] = {s->x, s->xbar, s->xp, s->y, s->yp};
-    float *keep_dy = s->dy;
     s->x = sx;
     s->xbar = sxbar;
     s->xp = sxp;
     s->y = sy;
     s->yp = syp;
-    s->dy = sdy;
     for (int half = 0; half < 2 && e == hipSuccess; half++) {
         float best = 1e30f;
         int best_k = half == 0 ? s->kern_at : s->kern_a;
@@ -1514,10 +1485,9 @@ hipError_t autotune(pdhg_solver *s)
     s->xp = keep[2];
     s->y = keep[3];
     s->yp = keep[4];
-    s->dy = keep_dy;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    for (void *q : {sx, sxbar, sxp, sy, syp, (void *)sdy})
+    for (void *q : {sx, sxbar, sxp, sy, syp})
         if (q) (void)hipFree(q);
     return e;
 }

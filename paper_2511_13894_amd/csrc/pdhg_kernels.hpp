@@ -25,20 +25,20 @@ __device__ __forceinline__ void halpern_weights(const DevState *st, int i, doubl
 // the matrix values, the bounds lhat, uhat and two n-vectors are float, and
 // the iterate x and the extrapolation xbar are stored as float DIFFERENCES
 // from the float64 anchor x_a (x - x_a, xbar - x_a); the anchor, the
-// candidate x+ and every m-vector (y, y_anchor, y+) are double, and the dual
-// half also writes dy = y - y_a as float for the primal half to gather.  The
-// float rounding of a difference shrinks as the restart cycle converges, so
-// the iteration keeps float64 accuracy near the optimum (rounding x itself to
-// float stalls primal-degenerate LPs, where the rows cancel).  The matching
-// objective and right-hand side are chat - Ahat'y_a and bhat - Ahat x_a in
-// float64, refreshed at every anchor:
-//   chat - Ahat'y = (chat - Ahat'y_a) - Ahat'(y - y_a),
-//   bhat - Ahat xbar = (bhat - Ahat x_a) - Ahat (xbar - x_a).
-// All arithmetic — products, sums, projections, Halpern averages — is double
-// in registers; only the stores round to V.
+// candidate x+ and every m-vector (y, y_anchor, y+) are double.  The float
+// rounding of a difference shrinks as the restart cycle converges, so the
+// iteration keeps float64 accuracy near the optimum (rounding x itself to
+// float stalls primal-degenerate LPs, where the rows cancel).  With the float
+// matrix fl32(Ahat) = Ahat - E, the kernels read a float64 objective and
+// right-hand side fixed at every anchor:
+//   bhat - Ahat xbar = (bhat - Ahat x_a) - fl32(Ahat)(xbar - x_a) - E (xbar - x_a),
+//   chat - Ahat'y    = (chat - E'y_a) - fl32(Ahat)'y - E'(y - y_a),
+// so the only errors are E times a difference (and the differences' own
+// rounding).  All arithmetic — products, sums, projections, Halpern averages —
+// is double in registers; only the stores round to V.
 
 // Primal half, one row of the transpose (= one column j of A) per group of L
-// lanes:  g = Ahat' y (mixed: Ahat'(y - y_a));  x+ = clamp(x - tau (chat - g),
+// lanes:  g = Ahat' y;  x+ = clamp(x - tau (chat - g),
 // lhat, uhat);  xbar = 2 x+ - x;  x <- w ((1+gamma) x+ - gamma x) + wa x_a.
 // xj is the iterate itself (mixed: x_a + stored difference), aj the anchor.
 // At the last iteration before a check the candidate x+ is stored as well.
@@ -85,10 +85,9 @@ __device__ __forceinline__ double iterate_value(V stored, double anchor)
     return sizeof(V) == sizeof(float) ? anchor + (double)stored : (double)stored;
 }
 
-// Dual half:  y+ = proj_Y(y + sigma (bhat - h));  y <- w ((1+gamma) y+ - gamma y) + wa y_anchor;
-// with dy (mixed mode) dy = y - y_anchor in float for the primal half's gathers.
+// Dual half:  y+ = proj_Y(y + sigma (bhat - h));  y <- w ((1+gamma) y+ - gamma y) + wa y_anchor.
 __device__ __forceinline__ void dual_update(int64_t r, double h, double yr, double br, double ar, int8_t sn,
-                                            double *__restrict__ y, double *__restrict__ yp, float *__restrict__ dy,
+                                            double *__restrict__ y, double *__restrict__ yp,
                                             const DevState *__restrict__ st, int i, int store_cand)
 {
     double yn = yr + st->sigma * (br - h);
@@ -103,7 +102,6 @@ __device__ __forceinline__ void dual_update(int64_t r, double h, double yr, doub
         ynew = w * ((1.0 + gm) * yn - gm * yr) + wa * ar;
     }
     y[r] = ynew;
-    if (dy) dy[r] = (float)(ynew - ar);
 }
 
 // ------------------------------------------------- LDS-tiled short rows ---

@@ -74,8 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_dual_finish(int m, const int *_
                                                             const double *__restrict__ bh,
                                                             const int8_t *__restrict__ sense, double *__restrict__ y,
                                                             const double *__restrict__ ya, double *__restrict__ yp,
-                                                            float *__restrict__ dy, const DevState *__restrict__ st,
-                                                            int i, int store_cand)
+                                                            const DevState *__restrict__ st, int i, int store_cand)
 {
     if (st->done) return;
     const int r = blockIdx.x * kBlock + threadIdx.x;
@@ -83,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_dual_finish(int m, const int *_
     const int s = r / kSellC, lane = r % kSellC;
     double h = 0.0;
     for (int w = wi_start[s]; w < wi_start[s + 1]; w++) h += part[(size_t)w * kSellC + lane];
-    dual_update(r, h, y[r], bh[r], ya[r], sense[r], y, yp, dy, st, i, store_cand);
+    dual_update(r, h, y[r], bh[r], ya[r], sense[r], y, yp, st, i, store_cand);
 }
 
 __global__ __launch_bounds__(kBlock) void k_sell_product_finish(int m, const int *__restrict__ wi_start,
@@ -187,11 +186,11 @@ static void sell_dual_impl(pdhg_solver *s, int i, int store, hipEvent_t e0, hipE
     if (f0 || e1)
         hipExtLaunchKernelGGL(k_sell_dual_finish, gf, bk, 0, s->stream, f0, e1, 0, s->m, s->sell_wi_start, s->sell_part,
                               (const double *)s->bhc, s->sense, (double *)s->y, (const double *)s->ya, (double *)s->yp,
-                              s->dy, st, i, store);
+                              st, i, store);
     else
         hipLaunchKernelGGL(k_sell_dual_finish, gf, bk, 0, s->stream, s->m, s->sell_wi_start, s->sell_part,
                            (const double *)s->bhc, s->sense, (double *)s->y, (const double *)s->ya, (double *)s->yp,
-                           s->dy, st, i, store);
+                           st, i, store);
 }
 
 void sell_dual(pdhg_solver *s, int i, int store, hipEvent_t e0, hipEvent_t e1)

@@ -1,15 +1,15 @@
 """FP32-mixed mode against the FP64 oracle: the error is stated, not bitwise.
 
 The mixed mode streams the matrix, the bounds and two n-vectors in FP32 and
-keeps every check in float64.  The n-vectors are stored as float differences
-from a float64 anchor: x - x_a and xbar - x_a, and the primal half gathers
-dy = y - y_a in float.  The kernels read the anchored objective and
-right-hand side chat - Ahat'y_a and bhat - Ahat x_a, computed in float64 at
-every anchor (restart or phase start), so the float products only see the
-differences.  Their rounding shrinks as the restart cycle converges, and the
-matrix's own rounding error E = Ahat - fl32(Ahat) enters only as E times a
-difference.  Every check evaluates the float64 products fl32(Ahat) v + E v,
-so a reported OPTIMAL is an optimum of the original model at the tolerance.
+keeps y and every check in float64.  The n-vectors are stored as float
+differences from a float64 anchor: x - x_a and xbar - x_a.  With the
+matrix's rounding error E = Ahat - fl32(Ahat), the kernels read the anchored
+right-hand side bhat - Ahat x_a and the corrected objective chat - E'y_a,
+computed in float64 at every anchor (restart or phase start), so the only
+errors are E times a difference (x - x_a or y - y_a) and the differences'
+own rounding, which shrink as the restart cycle converges.  Every check
+evaluates the float64 products fl32(Ahat) v + E v, so a reported OPTIMAL is
+an optimum of the original model at the tolerance.
 """
 import numpy as np
 import pytest
@@ -69,7 +69,7 @@ def test_fp32_mixed_solves_the_original_lp(name, make):
     assert rg.status == pdhg.PDHG_OPTIMAL, pdhg.STATUS[rg.status]
     assert max(ko.rel_p, ko.rel_d, ko.rel_gap) <= EPS
     assert abs(ko.rel_p - rg.rel_p) <= 1e-12 and abs(ko.rel_gap - rg.rel_gap) <= 1e-12
-    assert obj_err <= 1e-7
+    assert obj_err <= 2 * EPS  # both answers meet the relative gap test at EPS
     assert rg.iters <= 1.25 * ro.iters + 128
     pg = g.corner_push(5)
     xh = g.get_solution()[0]
