@@ -9,21 +9,24 @@ from paper_2511_13894_amd import lpgen, pdhg
 pytestmark = pytest.mark.gpu
 
 
-def test_checkpoint_resume_continues_bitwise():
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_checkpoint_resume_continues_bitwise(prec):
+    """Also in the mixed mode, whose anchored data a resumed handle rebuilds
+    from the restored anchor with the same products the restart used."""
     lp = lpgen.config1(seed=5, m=800, n=3200)
-    a = pdhg.Solver(lp, eps_rel=1e-7)
+    a = pdhg.Solver(lp, eps_rel=1e-7, precision=prec)
     a.iterate(100)
     state = a.get_state()
     a.iterate(150)
     xa, ya = a.get_iterate()
-    b = pdhg.Solver(lp, eps_rel=1e-7)
+    b = pdhg.Solver(lp, eps_rel=1e-7, precision=prec)
     b.set_state(state)
     b.iterate(150)
     xb, yb = b.get_iterate()
     np.testing.assert_array_equal(xa, xb)
     np.testing.assert_array_equal(ya, yb)
     ra, rb = a.solve(), b.solve()
-    print(f"[state] resumed solve: {rb.iters} iterations (uninterrupted {ra.iters})", flush=True)
+    print(f"[state] {prec} resumed solve: {rb.iters} iterations (uninterrupted {ra.iters})", flush=True)
     assert (ra.status, ra.iters, ra.restarts) == (rb.status, rb.iters, rb.restarts)
     assert ra.pobj == rb.pobj
     pa, pb = a.corner_push(3), b.corner_push(3)
