@@ -7,9 +7,16 @@
 // a lane holds A[row = lane % 16][k = 4 (lane / 16) + i], B[k = 4 (lane / 16)
 // + i][col = lane % 16] and D[row = 4 (lane / 16) + i][col = lane % 16], so the
 // D block of one layer is already the B operand of the next layer's K block
-// and the layers chain in registers.  The weight gradients (sums over
-// variables) need the activations with the variable index as K; those tiles
-// go through LDS.
+// and the layers chain in registers.  The 64-wide layer-2 contractions use
+// gfx950's v_mfma_f32_16x16x32_bf16, two K = 32 steps instead of four K = 16
+// ones: there a lane holds A[lane % 16][k = 8 (lane / 16) + i] and B[k = 8
+// (lane / 16) + i][lane % 16], i < 8, and the same D layout.  A lane's 8 B
+// values are its D values of two consecutive 16-row blocks, so within a K = 32
+// step the hidden unit of slot (lane / 16, i) is 16 (2p + i / 4) + 4 (lane /
+// 16) + i % 4; the weights are loaded in that order, and the contraction is
+// the same sum over all 64 units.  The weight gradients (sums over variables)
+// need the activations with the variable index as K; those tiles go through
+// LDS.
 #include <cmath>
 #include <mutex>
 #include <string>
@@ -21,6 +28,8 @@
 namespace pdhg {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ short f2bf(float f)
@@ -37,6 +46,21 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                                  0, 0, 0);
+}
+
+// hidden unit of K = 32 step p, slot (lane group lg, element i)
+__device__ __forceinline__ int k32_unit(int p, int lg, int i) { return 16 * (2 * p + (i >> 2)) + 4 * lg + (i & 3); }
+
+// the B operand of K = 32 step p: the D values of 16-row blocks 2p and 2p + 1
+__device__ __forceinline__ bf16x8 k32_pair(const bf16x4 &lo, const bf16x4 &hi)
+{
+    return bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
 // parameter offsets in the flat vector: w1 (64x16), b1, w2 (64x64), b2, w3, b3
 constexpr int OFF_W1 = 0, OFF_B1 = 1024, OFF_W2 = 1088, OFF_B2 = 5184, OFF_W3 = 5248, OFF_B3 = 5312;
 
@@ -50,15 +74,16 @@ __global__ __launch_bounds__(kBlock) void k_mlp_forward(const short *__restrict_
                                                        float *__restrict__ logits)
 {
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-    bf16x4 w1a[4], w2a[4][4];
+    bf16x4 w1a[4];
+    bf16x8 w2a[4][2];
 #pragma unroll
     for (int mb = 0; mb < 4; mb++) {
 #pragma unroll
         for (int i = 0; i < 4; i++) w1a[mb][i] = w.w1b[(16 * mb + lr) * 16 + 4 * lg + i];
 #pragma unroll
-        for (int kb = 0; kb < 4; kb++)
+        for (int p = 0; p < 2; p++)
 #pragma unroll
-            for (int i = 0; i < 4; i++) w2a[mb][kb][i] = w.w2b[(16 * mb + lr) * 64 + 16 * kb + 4 * lg + i];
+            for (int i = 0; i < 8; i++) w2a[mb][p][i] = w.w2b[(16 * mb + lr) * 64 + k32_unit(p, lg, i)];
     }
     const float b3 = w.p[OFF_B3];
     const int64_t ntiles = (N + 15) / 16;
@@ -81,11 +106,12 @@ __global__ __launch_bounds__(kBlock) void k_mlp_forward(const short *__restrict_
             }
         }
         float part = 0.0f;
+        const bf16x8 h1p[2] = {k32_pair(h1b[0], h1b[1]), k32_pair(h1b[2], h1b[3])};
 #pragma unroll
         for (int mb = 0; mb < 4; mb++) {
             f32x4 a = {0, 0, 0, 0};
 #pragma unroll
-            for (int kb = 0; kb < 4; kb++) a = mfma16(w2a[mb][kb], h1b[kb], a);
+            for (int p = 0; p < 2; p++) a = mfma32(w2a[mb][p], h1p[p], a);
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int h = 16 * mb + 4 * lg + r;
@@ -116,17 +142,18 @@ __global__ __launch_bounds__(kBlock) void k_mlp_grad(const short *__restrict__ F
     __shared__ short sF[kBlock / 64][16 * 16];
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wid = threadIdx.x >> 6;
     const int gw = blockIdx.x * (kBlock / 64) + wid; // global wave number
-    bf16x4 w1a[4], w2a[4][4], w2t[4][4];
+    bf16x4 w1a[4];
+    bf16x8 w2a[4][2], w2t[4][2];
 #pragma unroll
     for (int mb = 0; mb < 4; mb++) {
 #pragma unroll
         for (int i = 0; i < 4; i++) w1a[mb][i] = w.w1b[(16 * mb + lr) * 16 + 4 * lg + i];
 #pragma unroll
-        for (int kb = 0; kb < 4; kb++)
+        for (int p = 0; p < 2; p++)
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                w2a[mb][kb][i] = w.w2b[(16 * mb + lr) * 64 + 16 * kb + 4 * lg + i];
-                w2t[mb][kb][i] = w.w2b[(16 * kb + 4 * lg + i) * 64 + 16 * mb + lr]; // W2^T
+            for (int i = 0; i < 8; i++) {
+                w2a[mb][p][i] = w.w2b[(16 * mb + lr) * 64 + k32_unit(p, lg, i)];
+                w2t[mb][p][i] = w.w2b[k32_unit(p, lg, i) * 64 + 16 * mb + lr]; // W2^T
             }
     }
     const float b3 = w.p[OFF_B3];
@@ -167,11 +194,12 @@ __global__ __launch_bounds__(kBlock) void k_mlp_grad(const short *__restrict__ F
             }
         }
         float z = 0.0f;
+        const bf16x8 h1p[2] = {k32_pair(h1b[0], h1b[1]), k32_pair(h1b[2], h1b[3])};
 #pragma unroll
         for (int mb = 0; mb < 4; mb++) {
             f32x4 a = {0, 0, 0, 0};
 #pragma unroll
-            for (int kb = 0; kb < 4; kb++) a = mfma16(w2a[mb][kb], h1b[kb], a);
+            for (int p = 0; p < 2; p++) a = mfma32(w2a[mb][p], h1p[p], a);
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int h = 16 * mb + 4 * lg + r;
@@ -207,11 +235,12 @@ __global__ __launch_bounds__(kBlock) void k_mlp_grad(const short *__restrict__ F
             }
         // dH1^T = W2^T dH2^T, masked by relu
         bf16x4 dh1b[4];
+        const bf16x8 dh2p[2] = {k32_pair(dh2b[0], dh2b[1]), k32_pair(dh2b[2], dh2b[3])};
 #pragma unroll
         for (int mb = 0; mb < 4; mb++) {
             f32x4 a = {0, 0, 0, 0};
 #pragma unroll
-            for (int kb = 0; kb < 4; kb++) a = mfma16(w2t[mb][kb], dh2b[kb], a);
+            for (int p = 0; p < 2; p++) a = mfma32(w2t[mb][p], dh2p[p], a);
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const float d = h1[mb][r] > 0.0f ? a[r] : 0.0f;
