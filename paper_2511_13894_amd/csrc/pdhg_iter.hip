@@ -25,8 +25,9 @@ __global__ __launch_bounds__(kBlock) void k_primal(int n, const int *__restrict_
     const int lane = (int)(gi % L);
     if (j >= n) return;
     // the epilogue's operands are loaded by every lane of the group (one
-    // request per group) before the product, and the stop flag after them,
-    // so their latencies overlap
+    // request per group), none behind a divergent branch; the stop flag is
+    // uniform, and the compiler reads it first (its latency measured as off
+    // the critical path: dropping the test does not shorten the launch)
     const double aj = xa[j], xj = iterate_value<V>(x[j], aj), cj = ch[j], lo = (double)lh[j], hi = (double)uh[j];
     if (st->done) return;
     double acc = lane_dot<L, double>(tp[j], tp[j + 1], lane, ti, atv, y);
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
     const int64_t r = gi / L;
     const int lane = (int)(gi % L);
     if (r >= m) return;
-    const double yr = y[r], br = bh[r], ar = ya[r]; // loaded before the product (see k_primal)
+    const double yr = y[r], br = bh[r], ar = ya[r]; // epilogue operands (see k_primal)
     const int8_t sn = sense[r];
     if (st->done) return;
     double acc = lane_dot<L, double>(rp[r], rp[r + 1], lane, ci, av, xbar);
@@ -258,8 +259,8 @@ __global__ __launch_bounds__(NT) void k_primal_tiled(int n, const int *__restric
     const int j = r0 + tid;
     // Epilogue operands, independent of the product: every thread loads
     // (threads past the tile reload its first row), so no load waits on a
-    // branch, and the stop flag is read after them so its latency overlaps
-    // theirs.  The flag is uniform: the whole workgroup leaves together.
+    // divergent branch.  The stop flag is uniform: the whole workgroup
+    // leaves together.
     const int jc = mine ? j : r0;
     const double aj = xa[jc], xj = iterate_value<V>(x[jc], aj), cj = ch[jc], lo = (double)lh[jc],
                  hi = (double)uh[jc];
@@ -285,7 +286,7 @@ __global__ __launch_bounds__(NT) void k_dual_tiled(int m, const int *__restrict_
     const int tid = threadIdx.x;
     const bool mine = tid < rows;
     const int r = r0 + tid;
-    const int rc = mine ? r : r0; // as in k_primal_tiled: unconditional loads, then the stop flag
+    const int rc = mine ? r : r0; // as in k_primal_tiled: unconditional epilogue loads
     const double yr = y[rc], br = bh[rc], ar = ya[rc];
     const int8_t sn = sense[rc];
     if (st->done) return;
