@@ -264,3 +264,33 @@ def test_batch_learned_push_from_logits_follows_the_oracle():
         xg = b.get_solution(i)[0]
         xo = o.solution()[0]
         assert np.abs(xg - xo).max() <= 1e-7 * max(1.0, np.abs(xo).max()), i
+
+
+@pytest.mark.parametrize("compact", [1, 0])
+@pytest.mark.parametrize("name,make", LEARNED_CASES[:3], ids=[c[0] for c in LEARNED_CASES[:3]])
+def test_learned_push_fp32_mixed(name, make, compact):
+    """The learned warm start in the mixed mode, where a learned fix sets the
+    float64 anchor (the stored difference 0): the push ends primal feasible on
+    the original model as the oracle evaluates it, and the learned fixes and
+    undos stay within a few columns of the float64 oracle's from the same
+    logits (the float32 solve's answer moves reduced costs near eps_abs)."""
+    print(f"[learned] fp32 logits push: {name} compact {compact}", flush=True)
+    lp = make()
+    logits = np.random.default_rng(1234).normal(0.0, 2.0, lp.n).astype(np.float32)
+    g = pdhg.Solver(lp, eps_rel=1e-6, precision="fp32", push_compact=compact)
+    o = OracleSolver(lp, eps_rel=1e-6)
+    rg, ro = g.solve(), o.solve()
+    assert rg.status == ro.status == 0
+    y_solve = g.get_solution()[1]
+    pg = g.corner_push_logits(logits, 0.6, 5)
+    po = o.corner_push_learned(logits, 0.6, 5)
+    xg = g.get_solution()[0]
+    k = o.kkt(xg, y_solve)
+    print(f"[learned] {name} fp32: status {pdhg.STATUS[pg.status]} in {pg.iters} iterations (oracle {po.iters}); "
+          f"learned fixes {pg.n_learned_fix} (oracle {po.n_learned_fix}), undone {pg.n_learned_undo} "
+          f"(oracle {po.n_learned_undo}); oracle's primal residual of the pushed x {k.rel_p:.2e}", flush=True)
+    assert pg.status == pdhg.PDHG_PUSH_DONE
+    assert k.rel_p <= 1e-6
+    assert pg.n_learned_fix > 0
+    assert abs(pg.n_learned_fix - po.n_learned_fix) <= max(2, po.n_learned_fix // 50)
+    assert abs(pg.n_learned_undo - po.n_learned_undo) <= max(2, po.n_learned_undo // 20)
