@@ -151,17 +151,25 @@ def test_rerun_is_bitwise_deterministic():
     np.testing.assert_array_equal(outs[0][2], outs[1][2])
 
 
-def test_edge_cases_empty_rows_columns_and_single_row():
-    print("[gpu] edge cases", flush=True)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_edge_cases_empty_rows_columns_and_single_row(prec):
+    """Float64: the oracle's iterations and objective.  FP32-mixed: optimal at
+    the same tolerance with the oracle's objective (its anchored storage keeps
+    float64 accuracy on these LPs)."""
+    print(f"[gpu] edge cases {prec}", flush=True)
     a = np.array([[1.0, 1.0, 0.0], [0.0, 0.0, 0.0]])
     lp = lpgen.from_dense(a, [2.0, 0.0], [1.0, 2.0, -1.0], [0, 0, 0], [np.inf, np.inf, 4.0], "==")
     for make in (lambda: lp, lambda: lpgen.from_dense([[1.0, 1.0, 1.0, 1.0]], [2.0], [0.0, 0.0, 0.0, 1.0],
                                                        [0, 0, 0, 0], [1, 1, 1, 1], "=")):
         q = make()
-        g = pdhg.Solver(q, eps_rel=1e-10)
+        g = pdhg.Solver(q, eps_rel=1e-10, precision=prec)
         o = OracleSolver(q, eps_rel=1e-10)
         rg, ro = g.solve(), o.solve()
-        assert rg.status == ro.status == 0 and rg.iters == ro.iters
+        print(f"[gpu] edge {q.name} {prec}: {rg.iters} iterations (oracle {ro.iters}), pobj {rg.pobj!r} "
+              f"(oracle {ro.pobj!r})", flush=True)
+        assert rg.status == ro.status == 0
+        if prec == "fp64":
+            assert rg.iters == ro.iters
         assert abs(rg.pobj - ro.pobj) <= 1e-8
 
 

@@ -51,15 +51,18 @@ def test_checkpoint_errors():
         a.get_state()
 
 
-def test_warm_start_from_an_optimal_point_stops_at_the_first_check():
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_warm_start_from_an_optimal_point_stops_at_the_first_check(prec):
+    """Also in the mixed mode, where the start point becomes the float64
+    anchor with a zero stored difference."""
     lp = lpgen.config0(4)
     a = pdhg.Solver(lp, eps_rel=1e-8)
     ra = a.solve()
     x, y, _ = a.get_solution()
-    b = pdhg.Solver(lp, eps_rel=1e-6)
+    b = pdhg.Solver(lp, eps_rel=1e-6, precision=prec)
     b.set_start(x, y)
     rb = b.solve()
-    print(f"[state] cold solve {ra.iters} iterations; warm start from its answer {rb.iters}", flush=True)
+    print(f"[state] cold solve {ra.iters} iterations; {prec} warm start from its answer {rb.iters}", flush=True)
     assert rb.status == pdhg.PDHG_OPTIMAL and rb.iters <= 128 < ra.iters
     bad = x.copy()
     bad[0] = np.nan
