@@ -385,6 +385,16 @@ typedef struct pdhg_batch_report {
  * 32-bit indices), OOM, HIP. */
 int pdhg_batch_create(int32_t count, const pdhg_lp_desc *lps, const pdhg_params *p, pdhg_batch **out);
 
+/* pdhg_batch_create on LPs already in device memory: the descriptors are a
+ * host array (count <= 65535), every array they point to is device memory
+ * of this GPU, owned by the caller and only read (it may be freed once the
+ * call returns).  The block-diagonal model is assembled and checked on the
+ * device as pdhg_create_device checks one LP, rows needing ascending,
+ * unique column indices; each LP's row_ptr must start at 0 and end at its
+ * nnz, and its column indices stay below its own n.  Errors: INVALID_ARG
+ * (bad sizes or pointers, an invalid LP), OOM, HIP. */
+int pdhg_batch_create_device(int32_t count, const pdhg_lp_desc *lps, const pdhg_params *p, pdhg_batch **out);
+
 /* Solve every LP (results[count]); STATE if called twice. */
 int pdhg_batch_solve(pdhg_batch *b, pdhg_result *results);
 

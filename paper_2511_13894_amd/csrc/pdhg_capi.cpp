@@ -1176,6 +1176,9 @@ void pdhg_destroy(pdhg_solver *s)
     delete s;
 }
 
+static int batch_finish(pdhg_solver *s, int count, const std::vector<int> &roff, const std::vector<int> &coff,
+                        const std::vector<int64_t> &nnz_of, const pdhg_params &p, pdhg_batch **out);
+
 int pdhg_batch_create(int32_t count, const pdhg_lp_desc *lps, const pdhg_params *params, pdhg_batch **out)
 {
     if (!out) return fail(PDHG_ERR_INVALID_ARG, "out is NULL");
@@ -1233,6 +1236,19 @@ int pdhg_batch_create(int32_t count, const pdhg_lp_desc *lps, const pdhg_params 
     int rc = create_model(M, N, nz_total, rp.data(), ci.data(), va.data(), bb.data(), cc.data(), ll.data(), uu.data(),
                           sn.data(), &p, false, &s);
     if (rc != PDHG_OK) return rc;
+    std::vector<int64_t> nnz_of;
+    for (int i = 0; i < count; i++) nnz_of.push_back(lps[i].nnz);
+    return batch_finish(s, count, roff, coff, nnz_of, p, out);
+}
+
+// The batch around a solver already built on the block-diagonal model: tiles,
+// per-LP state, kernel choice, setup and the first phase start.
+static int batch_finish(pdhg_solver *s, int count, const std::vector<int> &roff, const std::vector<int> &coff,
+                        const std::vector<int64_t> &nnz_of, const pdhg_params &p, pdhg_batch **out)
+{
+    const int M = roff.back(), N = coff.back();
+    int64_t nz_total = 0;
+    for (int64_t v : nnz_of) nz_total += v;
     pdhg_batch *b = new (std::nothrow) pdhg_batch();
     if (!b) {
         pdhg_destroy(s);
@@ -1242,7 +1258,7 @@ int pdhg_batch_create(int32_t count, const pdhg_lp_desc *lps, const pdhg_params 
     b->count = count;
     b->roff = roff;
     b->coff = coff;
-    for (int i = 0; i < count; i++) b->nnz_of.push_back(lps[i].nnz);
+    b->nnz_of = nnz_of;
     try {
         hipStream_t st = s->stream;
         std::vector<int4> rn, rm;
@@ -1314,6 +1330,67 @@ int pdhg_batch_create(int32_t count, const pdhg_lp_desc *lps, const pdhg_params 
     *out = b;
     set_error("");
     return PDHG_OK;
+}
+
+int pdhg_batch_create_device(int32_t count, const pdhg_lp_desc *lps, const pdhg_params *params, pdhg_batch **out)
+{
+    if (!out) return fail(PDHG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !lps) return fail(PDHG_ERR_INVALID_ARG, "count must be >= 1 with a descriptor array");
+    if (count > 65535) return fail(PDHG_ERR_INVALID_ARG, "a batch from device arrays takes at most 65535 LPs");
+    pdhg_params p;
+    if (int rc = check_params(params, p)) return rc;
+    for (int32_t k : {p.lanes_a, p.lanes_at})
+        if (k > 0 || k == kRowBlock || k == kSell)
+            return fail(PDHG_ERR_INVALID_ARG, "the batch engine runs tiled kernels only (lanes -32/-64/-128/-256/-1032/-1064)");
+    std::vector<int> roff(1, 0), coff(1, 0);
+    std::vector<int64_t> nnz_of;
+    std::vector<BatchPart> parts;
+    int64_t nz_total = 0;
+    for (int i = 0; i < count; i++) {
+        const pdhg_lp_desc &d = lps[i];
+        if (d.m < 1 || d.n < 1 || d.nnz < 0 || !d.row_ptr || !d.b || !d.c || (d.nnz > 0 && (!d.col_idx || !d.val)))
+            return fail(PDHG_ERR_INVALID_ARG, "LP " + std::to_string(i) + ": bad dimensions or NULL arrays");
+        if ((int64_t)roff.back() + d.m >= (int64_t)1 << 31 || (int64_t)coff.back() + d.n >= (int64_t)1 << 31)
+            return fail(PDHG_ERR_INVALID_ARG, "batch too large for 32-bit indices");
+        parts.push_back(BatchPart{d.row_ptr, d.col_idx, d.val, d.b, d.c, d.l, d.u, d.sense, d.m, d.n, d.nnz,
+                                  roff.back(), coff.back(), nz_total});
+        roff.push_back(roff.back() + d.m);
+        coff.push_back(coff.back() + d.n);
+        nz_total += d.nnz;
+        nnz_of.push_back(d.nnz);
+    }
+    if (nz_total >= (int64_t)1 << 31) return fail(PDHG_ERR_INVALID_ARG, "batch nnz must stay below 2^31");
+    const int M = roff.back(), N = coff.back();
+    // the block-diagonal model assembled on the device, then ingested as pdhg_create_device does
+    hipStream_t st = nullptr;
+    std::vector<void *> temps;
+    auto release = [&]() {
+        for (void *q : temps) (void)hipFree(q);
+        temps.clear();
+        if (st) (void)hipStreamDestroy(st);
+        st = nullptr;
+    };
+    DeviceModel dm{};
+    unsigned bad = 0;
+    hipError_t e = hipStreamCreate(&st);
+    if (e == hipSuccess) e = batch_assemble_device(st, parts, M, N, nz_total, &dm, temps, &bad);
+    if (e != hipSuccess) {
+        release();
+        return fail(e == hipErrorOutOfMemory ? PDHG_ERR_OOM : PDHG_ERR_HIP,
+                    std::string("HIP error assembling the batch: ") + hipGetErrorString(e));
+    }
+    if (bad) {
+        release();
+        return fail(PDHG_ERR_INVALID_ARG, ingest_error(bad));
+    }
+    ModelSource src;
+    src.dev = &dm;
+    pdhg_solver *s = nullptr;
+    const int rc = build_solver(M, N, (int)nz_total, p, src, false, &s);
+    release(); // the solver holds its own copies
+    if (rc != PDHG_OK) return rc;
+    return batch_finish(s, count, roff, coff, nnz_of, p, out);
 }
 
 int pdhg_batch_solve(pdhg_batch *b, pdhg_result *results)

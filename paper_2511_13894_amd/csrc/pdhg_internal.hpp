@@ -277,6 +277,25 @@ enum IngestBad : unsigned {
 // *bad receives the IngestBad bits (0: accepted)
 hipError_t ingest_device(pdhg_solver *s, const DeviceModel &dm, unsigned *bad);
 const char *ingest_error(unsigned bad);
+// one LP of a batch created from device arrays: its caller-owned arrays and
+// its place in the block-diagonal model
+struct BatchPart {
+    const int64_t *row_ptr;
+    const int32_t *col_idx;
+    const double *val, *b, *c, *l, *u; // l, u may be NULL (0 and +infinity)
+    const char *sense;                 // may be NULL (all '=')
+    int m, n;
+    int64_t nnz;
+    int roff, coff; // first row and column in the block
+    int64_t nzoff;  // first entry in the block
+};
+// Assemble the block-diagonal model of `parts` in new device arrays (kept in
+// temps, freed by the caller after the solver has copied them): row pointers
+// and column indices shifted by each LP's offsets, every LP's row pointers
+// checked at both ends and its column indices against its own n (bad gets
+// BAD_ROWPTR / BAD_COL); the rest is checked by ingest_device.
+hipError_t batch_assemble_device(hipStream_t st, const std::vector<BatchPart> &parts, int M, int N, int64_t NZ,
+                                 DeviceModel *dm, std::vector<void *> &temps, unsigned *bad);
 hipError_t build_transpose(pdhg_solver *s);
 hipError_t scale_problem(pdhg_solver *s);
 hipError_t power_iteration(pdhg_solver *s);

@@ -260,6 +260,104 @@ hipError_t ingest_device(pdhg_solver *s, const DeviceModel &dm, unsigned *bad)
     return e;
 }
 
+// ------------------------------------------------ batch from device arrays
+// blockIdx.y is the LP; x-blocks stride over its rows (r = m checks the end
+// pointer, and the last LP writes the block's final one)
+__global__ __launch_bounds__(kBlock) void k_batch_rows(const BatchPart *__restrict__ parts, int count,
+                                                      int64_t *__restrict__ rp, double *__restrict__ b,
+                                                      char *__restrict__ sense, unsigned *__restrict__ bad)
+{
+    const BatchPart q = parts[blockIdx.y];
+    unsigned flags = 0;
+    for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r <= q.m; r += (int64_t)gridDim.x * kBlock) {
+        const int64_t v = q.row_ptr[r];
+        const bool ok = v >= 0 && v <= q.nnz;
+        if (!ok || (r == 0 && v != 0) || (r == q.m && v != q.nnz)) flags |= BAD_ROWPTR;
+        if (r < q.m) {
+            rp[q.roff + r] = q.nzoff + (ok ? v : 0);
+            b[q.roff + r] = q.b[r];
+            sense[q.roff + r] = q.sense ? q.sense[r] : '=';
+        } else if ((int)blockIdx.y == count - 1) {
+            rp[q.roff + r] = q.nzoff + (ok ? v : 0);
+        }
+    }
+    if (flags) atomicOr(bad, flags);
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_entries(const BatchPart *__restrict__ parts,
+                                                         int32_t *__restrict__ ci, double *__restrict__ val,
+                                                         unsigned *__restrict__ bad)
+{
+    const BatchPart q = parts[blockIdx.y];
+    unsigned flags = 0;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < q.nnz; e += (int64_t)gridDim.x * kBlock) {
+        const int32_t col = q.col_idx[e];
+        if (col < 0 || col >= q.n) flags |= BAD_COL;
+        ci[q.nzoff + e] = (col < 0 || col >= q.n) ? q.coff : q.coff + col;
+        val[q.nzoff + e] = q.val[e];
+    }
+    if (flags) atomicOr(bad, flags);
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_cols(const BatchPart *__restrict__ parts, double *__restrict__ c,
+                                                      double *__restrict__ l, double *__restrict__ u)
+{
+    const BatchPart q = parts[blockIdx.y];
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < q.n; j += (int64_t)gridDim.x * kBlock) {
+        c[q.coff + j] = q.c[j];
+        l[q.coff + j] = q.l ? q.l[j] : 0.0;
+        u[q.coff + j] = q.u ? q.u[j] : INFINITY;
+    }
+}
+
+hipError_t batch_assemble_device(hipStream_t st, const std::vector<BatchPart> &parts, int M, int N, int64_t NZ,
+                                 DeviceModel *dm, std::vector<void *> &temps, unsigned *bad)
+{
+    const int count = (int)parts.size();
+    int64_t max_m = 0, max_n = 0, max_nz = 0;
+    for (const BatchPart &q : parts) {
+        max_m = q.m > max_m ? q.m : max_m;
+        max_n = q.n > max_n ? q.n : max_n;
+        max_nz = q.nnz > max_nz ? q.nnz : max_nz;
+    }
+    auto get = [&](void **ptr, size_t bytes) {
+        hipError_t e = hipMalloc(ptr, bytes > 0 ? bytes : 1);
+        if (e == hipSuccess) temps.push_back(*ptr);
+        return e;
+    };
+    void *rp = nullptr, *ci = nullptr, *val = nullptr, *b = nullptr, *c = nullptr, *l = nullptr, *u = nullptr,
+         *sense = nullptr, *d_parts = nullptr, *d_bad = nullptr;
+    hipError_t e = get(&rp, sizeof(int64_t) * ((size_t)M + 1));
+    if (e == hipSuccess) e = get(&ci, sizeof(int32_t) * (size_t)NZ);
+    if (e == hipSuccess) e = get(&val, sizeof(double) * (size_t)NZ);
+    if (e == hipSuccess) e = get(&b, sizeof(double) * (size_t)M);
+    if (e == hipSuccess) e = get(&sense, (size_t)M);
+    if (e == hipSuccess) e = get(&c, sizeof(double) * (size_t)N);
+    if (e == hipSuccess) e = get(&l, sizeof(double) * (size_t)N);
+    if (e == hipSuccess) e = get(&u, sizeof(double) * (size_t)N);
+    if (e == hipSuccess) e = get(&d_parts, sizeof(BatchPart) * (size_t)count);
+    if (e == hipSuccess) e = get(&d_bad, sizeof(unsigned));
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(d_parts, parts.data(), sizeof(BatchPart) * (size_t)count, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, st, (unsigned *)d_bad, 0u);
+    const BatchPart *pp = (const BatchPart *)d_parts;
+    hipLaunchKernelGGL(k_batch_rows, dim3(grid_for(max_m + 1, kBlock, 256), count), dim3(kBlock), 0, st, pp, count,
+                       (int64_t *)rp, (double *)b, (char *)sense, (unsigned *)d_bad);
+    if (max_nz > 0)
+        hipLaunchKernelGGL(k_batch_entries, dim3(grid_for(max_nz, kBlock, 1024), count), dim3(kBlock), 0, st, pp,
+                           (int32_t *)ci, (double *)val, (unsigned *)d_bad);
+    hipLaunchKernelGGL(k_batch_cols, dim3(grid_for(max_n, kBlock, 256), count), dim3(kBlock), 0, st, pp, (double *)c,
+                       (double *)l, (double *)u);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(bad, d_bad, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    *dm = DeviceModel{M, N, NZ, (const int64_t *)rp, (const int32_t *)ci, (const double *)val, (const double *)b,
+                      (const double *)c, (const double *)l, (const double *)u, (const char *)sense};
+    return hipSuccess;
+}
+
 const char *ingest_error(unsigned bad)
 {
     if (bad & BAD_ROWPTR) return "row_ptr[0] != 0, row_ptr[m] != nnz or row_ptr not non-decreasing";

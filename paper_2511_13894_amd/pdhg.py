@@ -135,7 +135,7 @@ EXPORTS = ["pdhg_default_params", "pdhg_create", "pdhg_solve", "pdhg_iterate", "
            "pdhg_corner_push_learned", "pdhg_get_solution_device", "pdhg_set_start", "pdhg_state_size",
            "pdhg_get_state", "pdhg_set_state", "pdhg_get_solve_solution", "pdhg_batch_get_solve_solution",
            "pdhg_dual_push", "pdhg_batch_dual_push", "pdhg_corner_push_logits", "pdhg_batch_corner_push_logits",
-           "pdhg_create_device", "pdhg_mlp_forward_noalloc"]
+           "pdhg_create_device", "pdhg_mlp_forward_noalloc", "pdhg_batch_create_device"]
 
 _lib = None
 
@@ -173,6 +173,7 @@ def load(path: Optional[Path] = None):
     lib.pdhg_destroy.argtypes = [C.c_void_p]
     lib.pdhg_destroy.restype = None
     lib.pdhg_batch_create.argtypes = [C.c_int32, P(LpDesc), P(Params), P(C.c_void_p)]
+    lib.pdhg_batch_create_device.argtypes = [C.c_int32, P(LpDesc), P(Params), P(C.c_void_p)]
     lib.pdhg_batch_solve.argtypes = [C.c_void_p, P(Result)]
     lib.pdhg_batch_corner_push.argtypes = [C.c_void_p, P(C.c_uint64), P(PushResult)]
     lib.pdhg_batch_get_solution.argtypes = [C.c_void_p, C.c_int32, dp, dp, dp]
@@ -464,18 +465,44 @@ class Solver:
                 "power_steps": int(s5[4])}
 
 
+class DeviceBatch:
+    """Many LPs' arrays copied once into device memory (the inputs of
+    pdhg_batch_create_device): rows must be sorted with unique columns."""
+
+    def __init__(self, lps):
+        self.lps = list(lps)
+        self.dev = [DeviceLP(lp) for lp in self.lps]
+
+
 class Batch:
-    """Many LPs solved and corner-pushed together (pdhg_batch_*)."""
+    """Many LPs solved and corner-pushed together (pdhg_batch_*); a
+    DeviceBatch goes through pdhg_batch_create_device."""
 
     def __init__(self, lps, **params):
         _refuse_second_runtime()
         self.lib = load()
-        self.lps = list(lps)
+        device = isinstance(lps, DeviceBatch)
+        self.lps = list(lps.lps) if device else list(lps)
         self.count = len(self.lps)
         self.params = default_params(**params)
         self.params.stream = None
         descs = (LpDesc * self.count)()
         self._keep = []
+        if device:
+            for d, dl in zip(descs, lps.dev):
+                q = dl.ptr
+                d.m, d.n, d.nnz = dl.m, dl.n, dl.nnz
+                d.row_ptr = C.cast(q["row_ptr"], C.POINTER(C.c_int64))
+                d.col_idx = C.cast(q["col"], C.POINTER(C.c_int32))
+                d.val, d.b, d.c, d.l, d.u = (C.cast(q[k], C.POINTER(C.c_double)) for k in ("val", "b", "c", "l", "u"))
+                d.sense = C.cast(q["sense"], C.c_char_p)
+            self._keep.append(lps)
+            h = C.c_void_p()
+            rc = self.lib.pdhg_batch_create_device(self.count, descs, C.byref(self.params), C.byref(h))
+            if rc != 0:
+                raise PdhgError(rc, self.lib.pdhg_last_error().decode())
+            self.h = h
+            return
         for d, lp in zip(descs, self.lps):
             arrs = [np.ascontiguousarray(lp.row_ptr, dtype=np.int64), np.ascontiguousarray(lp.col, dtype=np.int32),
                     np.ascontiguousarray(lp.val, dtype=np.float64), np.ascontiguousarray(lp.b, dtype=np.float64),

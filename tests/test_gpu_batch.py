@@ -82,3 +82,43 @@ def test_batch_state_errors():
         bt.corner_push([1, 2])
     with pytest.raises(pdhg.PdhgError):
         pdhg.Batch(lps, lanes_at=8)
+
+
+def test_batch_from_device_memory_equals_host_create():
+    """pdhg_batch_create_device on the same (row-sorted) LPs gives the same
+    solves and pushes, bit for bit, as pdhg_batch_create; an LP whose column
+    index passes the block's range but not its own n, or whose row pointers
+    do not start at 0, is refused by the device checks."""
+    import copy
+
+    for prec in ("fp64", "fp32"):
+        lps = _family(7, 5200)
+        lps.append(lpgen.transportation(6, 9, seed=4))
+        a = pdhg.Batch(lps, precision=prec, eps_rel=1e-6)
+        db = pdhg.DeviceBatch(lps)
+        b = pdhg.Batch(db, precision=prec, eps_rel=1e-6)
+        for d in db.dev:
+            d.free()  # the library holds its own copy
+        ra, rb = a.solve(), b.solve()
+        assert [(r.status, r.iters, r.restarts) for r in ra] == [(r.status, r.iters, r.restarts) for r in rb]
+        seeds = [3 + i for i in range(len(lps))]
+        pa, pb = a.corner_push(seeds), b.corner_push(seeds)
+        assert [(r.status, r.iters) for r in pa] == [(r.status, r.iters) for r in pb]
+        for i in range(len(lps)):
+            for va, vb in zip(a.get_solution(i), b.get_solution(i)):
+                np.testing.assert_array_equal(va, vb)
+        print(f"[batch] {prec}: device create equals host create on {len(lps)} LPs "
+              f"(solve iterations {[r.iters for r in rb]})", flush=True)
+    base = _family(3, 5300)
+    x = copy.deepcopy(base[1])
+    x.col = x.col.copy()
+    x.col[x.row_ptr[2]] = x.n  # inside the block (LP 2 follows) but past this LP's columns
+    y = copy.deepcopy(base[1])
+    y.row_ptr = y.row_ptr.copy()
+    y.row_ptr[0] = 1  # row pointers not starting at 0
+    for bad, msg in ((x, "column index out of range"), (y, "row_ptr")):
+        db = pdhg.DeviceBatch([base[0], bad, base[2]])
+        with pytest.raises(pdhg.PdhgError) as e:
+            pdhg.Batch(db)
+        print(f"[batch] refused: {e.value}", flush=True)
+        assert msg in str(e.value)
