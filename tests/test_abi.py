@@ -114,3 +114,27 @@ def test_numeric_parameters_are_validated_without_gpu():
     lg = (ctypes.c_float * 2)(0.0, 0.0)
     assert lib.pdhg_corner_push_logits(None, lg, 0.5, 1, None) == -1
     assert lib.pdhg_batch_corner_push_logits(None, lg, 0.5, None, None) == -1
+
+
+def test_batch_create_device_argument_errors_without_gpu():
+    """pdhg_batch_create_device refuses bad counts, NULL arrays, lane
+    choices outside the tiled kernels and invalid parameters before it
+    touches the device or any LP array."""
+    lib = pdhg.load()
+    p = pdhg.default_params()
+    h = ctypes.c_void_p()
+    descs = (pdhg.LpDesc * 1)()
+    assert lib.pdhg_batch_create_device(0, descs, ctypes.byref(p), ctypes.byref(h)) == -1
+    assert lib.pdhg_batch_create_device(70000, descs, ctypes.byref(p), ctypes.byref(h)) == -1
+    assert b"65535" in lib.pdhg_last_error()
+    assert lib.pdhg_batch_create_device(1, descs, ctypes.byref(p), None) == -1
+    descs[0].m, descs[0].n, descs[0].nnz = 2, 3, 4  # NULL arrays
+    assert lib.pdhg_batch_create_device(1, descs, ctypes.byref(p), ctypes.byref(h)) == -1
+    assert b"NULL" in lib.pdhg_last_error()
+    q = pdhg.default_params()
+    q.lanes_a = 8  # a lane-group kernel: the batch runs tiles only
+    assert lib.pdhg_batch_create_device(1, descs, ctypes.byref(q), ctypes.byref(h)) == -1
+    q = pdhg.default_params()
+    q.eps_rel = float("nan")
+    assert lib.pdhg_batch_create_device(1, descs, ctypes.byref(q), ctypes.byref(h)) == -1
+    assert b"invalid parameter" in lib.pdhg_last_error()
