@@ -101,7 +101,7 @@ typedef struct pdhg_params {
     int64_t push_max_iter; /* iteration cap of a push; default 1e6                      */
     double time_limit;     /* seconds per solve / push call; <= 0: none (default)       */
     void *stream;          /* hipStream_t; NULL: library-owned stream                   */
-    int32_t verbosity;     /* 0 silent (default)                                        */
+    int32_t verbosity;     /* 0 silent (default); > 0: kernel plans on stderr          */
     int32_t lanes_at;      /* primal-half kernel: 1..64 (power of 2) lanes per row;
                               -32/-64/-128/-256: LDS tile of that many rows, 256
                               threads; -1032/-1064: tile of 32/64 rows, 64 threads;
@@ -109,6 +109,10 @@ typedef struct pdhg_params {
                               -3032 (lanes_a only): sliced ELLPACK, 32-row slices with
                               interleaved entries (long rows whose columns advance
                               together, e.g. the sinks of a transportation model);
+                              -4000 (lanes_a only): row segments, runs of rows whose
+                              columns are contiguous or spread out, each with its own
+                              lane-group width (the default for rows of more than 48
+                              entries; a batch takes tiled kernels only);
                               0 = chosen from the mean row length                      */
     int32_t lanes_a;       /* dual-half kernel, same encoding                           */
     int32_t use_graph;     /* 1: replay check cycles from a captured hipGraph (default) */

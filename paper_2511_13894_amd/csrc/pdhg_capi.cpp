@@ -391,10 +391,10 @@ static int check_params(const pdhg_params *params, pdhg_params &p)
         const int32_t k = half ? p.lanes_a : p.lanes_at;
         const bool lane_ok = k >= 1 && k <= 64 && !(k & (k - 1));
         const bool tile_ok = k == -32 || k == -64 || k == -128 || k == -256 || k == -1032 || k == -1064 ||
-                             k == kRowBlock || (half == 1 && k == kSell);
+                             k == kRowBlock || (half == 1 && (k == kSell || k == kRowSegs));
         if (k != 0 && !lane_ok && !tile_ok)
             return fail(PDHG_ERR_INVALID_ARG, "lanes must be 0, a power of two in 1..64, one of "
-                                              "-32/-64/-128/-256/-1032/-1064/-2256, or -3032 (lanes_a only)");
+                                              "-32/-64/-128/-256/-1032/-1064/-2256, or -3032/-4000 (lanes_a only)");
     }
 
     return PDHG_OK;
@@ -464,7 +464,7 @@ static int build_solver(int m, int n, int nz, const pdhg_params &p, const ModelS
         dalloc(&s->ch, N);
         for (void **q : {&s->y, &s->ya, &s->yp, &s->bh, &s->ys}) // m-vectors stay float64
             hip_check(hipMalloc(q, sizeof(double) * (M > 0 ? M : 1)), "hipMalloc");
-        if (s->fp32) { // the float matrix's rounding error and the corrected data (defect correction)
+        if (s->fp32) { // the float matrix's rounding error, its products and the anchored data
             hip_check(hipMalloc(&s->aerr, sizeof(float) * (NZ > 0 ? NZ : 1)), "hipMalloc");
             hip_check(hipMalloc(&s->aerr_t, sizeof(float) * (NZ > 0 ? NZ : 1)), "hipMalloc");
             dalloc(&s->ex, M);
@@ -542,6 +542,7 @@ static int build_solver(int m, int n, int nz, const pdhg_params &p, const ModelS
             if (n > 0) HIPCHK(hipMemcpyAsync(s->chc, s->ch, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
             if (m > 0) HIPCHK(hipMemcpyAsync(s->bhc, s->bh, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
         }
+        if (s->kern_a == kRowSegs || (single && p.autotune)) HIPCHK(plan_row_segments(s));
         if (s->kern_a == kSell) HIPCHK(sell_build(s, rp_host));
         if (single) {
             HIPCHK(power_iteration(s));
@@ -1188,7 +1189,7 @@ int pdhg_batch_create(int32_t count, const pdhg_lp_desc *lps, const pdhg_params 
     if (params) p = *params;
     else pdhg_default_params(&p);
     for (int32_t k : {p.lanes_a, p.lanes_at})
-        if (k > 0 || k == kRowBlock || k == kSell)
+        if (k > 0 || k == kRowBlock || k == kSell || k == kRowSegs)
             return fail(PDHG_ERR_INVALID_ARG, "the batch engine runs tiled kernels only (lanes -32/-64/-128/-256/-1032/-1064)");
     // one block-diagonal model with global column indices
     std::vector<int> roff(1, 0), coff(1, 0);
@@ -1341,7 +1342,7 @@ int pdhg_batch_create_device(int32_t count, const pdhg_lp_desc *lps, const pdhg_
     pdhg_params p;
     if (int rc = check_params(params, p)) return rc;
     for (int32_t k : {p.lanes_a, p.lanes_at})
-        if (k > 0 || k == kRowBlock || k == kSell)
+        if (k > 0 || k == kRowBlock || k == kSell || k == kRowSegs)
             return fail(PDHG_ERR_INVALID_ARG, "the batch engine runs tiled kernels only (lanes -32/-64/-128/-256/-1032/-1064)");
     std::vector<int> roff(1, 0), coff(1, 0);
     std::vector<int64_t> nnz_of;

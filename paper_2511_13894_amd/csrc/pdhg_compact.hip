@@ -350,6 +350,7 @@ hipError_t begin_impl(pdhg_solver *s)
     c.aerr_t0 = s->aerr_t;
     c.chc0 = s->chc;
     c.bhc0 = s->bhc;
+    c.segs0 = s->segs;
     s->n = nf;
     s->nnz = nnz_f;
     s->red_blocks_n = grid_for(nf, kBlock, kMaxRedBlocks);
@@ -388,6 +389,7 @@ hipError_t begin_impl(pdhg_solver *s)
         s->graph_exec = nullptr;
         s->graph_mode = -1;
     }
+    if (s->kern_a == kRowSegs && (e = plan_row_segments(s)) != hipSuccess) return e; // of the compact rows
     return detect_uniform_columns(s); // of the compact model (on failure the caller restores the full one)
 }
 
@@ -426,6 +428,7 @@ hipError_t end_impl(pdhg_solver *s, bool scatter)
     s->aerr_t = c.aerr_t0;
     s->chc = c.chc0;
     s->bhc = c.bhc0;
+    s->segs = c.segs0;
     s->defect_stale = true;
     if (c.lfix0) {
         s->lfix = c.lfix0;

@@ -25,7 +25,20 @@ namespace pdhg {
 constexpr int kBlock = 256;         // threads per workgroup (4 wave64)
 constexpr int kRowBlock = -2256; // kernel code: one row per workgroup of kBlock threads
 constexpr int kSell = -3032;     // kernel code (dual half): sliced ELLPACK, 32-row slices
+constexpr int kRowSegs = -4000;  // kernel code (dual half): row segments, each with its own lane-group width
 constexpr int kMaxRedBlocks = 1024; // cap on per-block partials of a reduction
+constexpr int kMaxSegs = 4;         // row segments of the kRowSegs dual half
+
+// Row segments of A for the dual half (kernel code kRowSegs): rows
+// [row0[k], row0[k+1]) run in lane groups of lanes[k], on workgroups
+// [blk0[k], blk0[k+1]) of one launch.  Every segment's workgroup count is a
+// multiple of 8, so a segment spreads over the 8 XCDs as its own launch would.
+struct RowSegs {
+    int count = 0;
+    int row0[kMaxSegs + 1] = {};
+    int blk0[kMaxSegs + 1] = {};
+    int lanes[kMaxSegs] = {};
+};
 
 // Quantities reduced at a check (block partials, then one fixed-order pass).
 enum CheckQ {
@@ -140,6 +153,7 @@ struct pdhg_solver {
     int lanes_at = 1, lanes_a = 1; // lane-group width of setup / check products
     int udeg_at = 0;               // every column holds this many entries (1..3), else 0
     int kern_at = 1, kern_a = 1;   // iteration kernels: > 0 lane-group width, < 0 LDS tile of -k rows
+    pdhg::RowSegs segs;            // the dual half's row segments (kern_a == kRowSegs)
     int64_t t_host = 0;      // iterations of the current phase (mirror of st->t)
     int64_t power_steps = 0; // power-iteration steps taken at create
     int64_t next_check = 0;  // phase iteration count of the next check
@@ -196,6 +210,7 @@ struct pdhg_solver {
         double *ch0 = nullptr, *dc0 = nullptr;
         void *aerr0 = nullptr, *aerr_t0 = nullptr;
         double *chc0 = nullptr, *bhc0 = nullptr;
+        pdhg::RowSegs segs0;
     } pc;
 
     // live kernel timing: events around one primal and one dual launch per cycle
@@ -332,6 +347,8 @@ void sell_product(pdhg_solver *s, const float *vec, double *out);
 
 // iteration, checks, push and reports (pdhg_iter.hip)
 hipError_t init_iteration(pdhg_solver *s);
+// the dual half's row segments of the current model (kern_a == kRowSegs)
+hipError_t plan_row_segments(pdhg_solver *s);
 // restart the solve phase from the start point staged (unscaled) in xu, yu
 hipError_t set_start(pdhg_solver *s);
 hipError_t launch_iterations(pdhg_solver *s, int count, bool check_at_end, int mode, bool timed_launch);

@@ -3,6 +3,8 @@
 // weighted KKT, restart and primal-weight update, termination), the corner
 // push setup of Algorithm 1, and float64 KKT reports on the original model.
 #include <cmath>
+#include <cstdio>
+#include <vector>
 
 #include "pdhg_device.hpp"
 #include "pdhg_internal.hpp"
@@ -26,14 +28,37 @@ __global__ __launch_bounds__(kBlock) void k_primal(int n, const int *__restrict_
     if (j >= n) return;
     // the epilogue's operands are loaded by every lane of the group (one
     // request per group), none behind a divergent branch; the stop flag is
-    // uniform, and the compiler reads it first (its latency measured as off
-    // the critical path: dropping the test does not shorten the launch)
+    // uniform (issuing the product's loads before the test, or testing only
+    // after the product, measured no faster)
     const double aj = xa[j], xj = iterate_value<V>(x[j], aj), cj = ch[j], lo = (double)lh[j], hi = (double)uh[j];
     if (st->done) return;
     double acc = lane_dot<L, double>(tp[j], tp[j + 1], lane, ti, atv, y);
     acc = group_sum<L>(acc);
     if (lane != 0) return;
     primal_update<V>(j, acc, xj, cj, lo, hi, aj, x, xbar, xp, st, i, store_cand);
+}
+
+// Dual half on rows [row0, row1), one row of A per group of L lanes, for the
+// workgroup that takes logical block lb:  h = Ahat xbar, then the update.
+template <typename V, int L>
+__device__ __forceinline__ void dual_rows(int row0, int row1, int lb, const int *__restrict__ rp,
+                                          const int *__restrict__ ci, const V *__restrict__ av,
+                                          const V *__restrict__ xbar, const double *__restrict__ bh,
+                                          const int8_t *__restrict__ sense, double *__restrict__ y,
+                                          const double *__restrict__ ya, double *__restrict__ yp,
+                                          const DevState *__restrict__ st, int i, int store_cand)
+{
+    const int64_t gi = (int64_t)lb * kBlock + threadIdx.x;
+    const int64_t r = row0 + gi / L;
+    const int lane = (int)(gi % L);
+    if (r >= row1) return;
+    const double yr = y[r], br = bh[r], ar = ya[r]; // epilogue operands (see k_primal)
+    const int8_t sn = sense[r];
+    if (st->done) return;
+    double acc = lane_dot<L, double>(rp[r], rp[r + 1], lane, ci, av, xbar);
+    acc = group_sum<L>(acc);
+    if (lane != 0) return;
+    dual_update(r, acc, yr, br, ar, sn, y, yp, st, i, store_cand);
 }
 
 // Dual half, one row of A per group of L lanes:  h = Ahat xbar.
@@ -45,17 +70,109 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
                                                 double *__restrict__ yp, const DevState *__restrict__ st, int i,
                                                 int store_cand)
 {
-    const int64_t gi = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const int64_t r = gi / L;
+    dual_rows<V, L>(0, m, xcd_block(blockIdx.x, gridDim.x), rp, ci, av, xbar, bh, sense, y, ya, yp, st, i,
+                    store_cand);
+}
+
+// ------------------------------------------------------- row segments ---
+// Rows of one kind share a lane-group width.  A row whose entries sit in
+// consecutive columns (a source row of a transportation model) streams its
+// share of xbar: many lanes finish it in few rounds of loads.  A row whose
+// columns are spread out (a sink row, one column per source) gathers one
+// cache line per entry, and the next rows gather the same lines: narrower
+// groups put more such rows in a workgroup, whose shared L1 then serves them.
+// Each segment has its own workgroups in one launch; a workgroup finds its
+// segment from its index (a uniform branch) and maps itself onto the
+// segment's XCD ranges.
+__device__ __forceinline__ int seg_of(const RowSegs &sg, int b)
+{
+    int k = 0;
+    while (k + 1 < sg.count && b >= sg.blk0[k + 1]) k++;
+    return k;
+}
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_dual_segs(RowSegs sg, const int *__restrict__ rp,
+                                                     const int *__restrict__ ci, const V *__restrict__ av,
+                                                     const V *__restrict__ xbar, const double *__restrict__ bh,
+                                                     const int8_t *__restrict__ sense, double *__restrict__ y,
+                                                     const double *__restrict__ ya, double *__restrict__ yp,
+                                                     const DevState *__restrict__ st, int i, int store_cand)
+{
+    const int k = seg_of(sg, blockIdx.x);
+    const int lb = xcd_block(blockIdx.x - sg.blk0[k], sg.blk0[k + 1] - sg.blk0[k]);
+    const int r0 = sg.row0[k], r1 = sg.row0[k + 1];
+#define PDHG_SEG_CASE(LL)                                                                                       \
+    case LL:                                                                                                    \
+        dual_rows<V, LL>(r0, r1, lb, rp, ci, av, xbar, bh, sense, y, ya, yp, st, i, store_cand);               \
+        break;
+    switch (sg.lanes[k]) {
+        PDHG_SEG_CASE(1)
+        PDHG_SEG_CASE(2)
+        PDHG_SEG_CASE(4)
+        PDHG_SEG_CASE(8)
+        PDHG_SEG_CASE(16)
+        PDHG_SEG_CASE(32)
+    default:
+        PDHG_SEG_CASE(64)
+    }
+#undef PDHG_SEG_CASE
+}
+
+// out = M vec on the same segments (the check products of this dual half)
+template <typename VM, typename VV, int L>
+__device__ __forceinline__ void spmv_rows(int row0, int row1, int lb, const int *__restrict__ ptr,
+                                          const int *__restrict__ idx, const VM *__restrict__ val,
+                                          const VV *__restrict__ vec, double *__restrict__ out)
+{
+    const int64_t gi = (int64_t)lb * kBlock + threadIdx.x;
+    const int64_t r = row0 + gi / L;
     const int lane = (int)(gi % L);
-    if (r >= m) return;
-    const double yr = y[r], br = bh[r], ar = ya[r]; // epilogue operands (see k_primal)
-    const int8_t sn = sense[r];
-    if (st->done) return;
-    double acc = lane_dot<L, double>(rp[r], rp[r + 1], lane, ci, av, xbar);
+    if (r >= row1) return;
+    double acc = lane_dot<L, double>(ptr[r], ptr[r + 1], lane, idx, val, vec);
     acc = group_sum<L>(acc);
-    if (lane != 0) return;
-    dual_update(r, acc, yr, br, ar, sn, y, yp, st, i, store_cand);
+    if (lane == 0) out[r] = acc;
+}
+
+template <typename VM, typename VV>
+__global__ __launch_bounds__(kBlock) void k_spmv_segs(RowSegs sg, const int *__restrict__ ptr,
+                                                     const int *__restrict__ idx, const VM *__restrict__ val,
+                                                     const VV *__restrict__ vec, double *__restrict__ out)
+{
+    const int k = seg_of(sg, blockIdx.x);
+    const int lb = xcd_block(blockIdx.x - sg.blk0[k], sg.blk0[k + 1] - sg.blk0[k]);
+    const int r0 = sg.row0[k], r1 = sg.row0[k + 1];
+#define PDHG_SEG_CASE(LL)                                                                                       \
+    case LL:                                                                                                    \
+        spmv_rows<VM, VV, LL>(r0, r1, lb, ptr, idx, val, vec, out);                                            \
+        break;
+    switch (sg.lanes[k]) {
+        PDHG_SEG_CASE(1)
+        PDHG_SEG_CASE(2)
+        PDHG_SEG_CASE(4)
+        PDHG_SEG_CASE(8)
+        PDHG_SEG_CASE(16)
+        PDHG_SEG_CASE(32)
+    default:
+        PDHG_SEG_CASE(64)
+    }
+#undef PDHG_SEG_CASE
+}
+
+// adj[r] = entries of row r whose next entry lies in the next column
+// (columns are sorted within a row); one wave per row
+__global__ __launch_bounds__(kBlock) void k_row_adjacent(int m, const int *__restrict__ rp,
+                                                        const int *__restrict__ ci, int *__restrict__ adj)
+{
+    const int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w >= m) return;
+    const int beg = rp[w], end = rp[w + 1];
+    int c = 0;
+    for (int e = beg + lane; e + 1 < end; e += 64) c += ci[e + 1] == ci[e] + 1 ? 1 : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0) adj[w] = c;
 }
 
 // ------------------------------------------------------- long rows ---
@@ -160,7 +277,21 @@ __global__ __launch_bounds__(kBlock) void k_add_to(int64_t len, double *__restri
         out[i] += add[i];
 }
 
-static int err_kern_a(const pdhg_solver *s);
+// out = M vec for a matrix with A's rows (Ahat, or its float rounding error
+// in mixed mode) in the dual half's kernel structure; the sliced layout
+// holds only the float matrix, so with it the products use lane groups
+template <typename VM, typename VV>
+static void row_product(const pdhg_solver *s, const VM *val, const VV *vec, double *out)
+{
+    if (s->m <= 0) return;
+    if (s->kern_a == kRowSegs) {
+        const RowSegs &sg = s->segs;
+        hipLaunchKernelGGL((k_spmv_segs<VM, VV>), dim3(sg.blk0[sg.count]), dim3(kBlock), 0, s->stream, sg, s->rp,
+                           s->ci, val, vec, out);
+        return;
+    }
+    check_spmv<VM, VV>(s->stream, s->kern_a == kSell ? s->lanes_a : s->kern_a, s->m, s->rp, s->ci, val, vec, out);
+}
 
 hipError_t solver_product(pdhg_solver *s, bool transpose, const double *vec, double *out);
 
@@ -174,7 +305,7 @@ hipError_t exact_product(pdhg_solver *s, bool transpose, const double *vec, doub
         hipLaunchKernelGGL(k_add_to, dim3(grid_for(s->n, kBlock, 8192)), dim3(kBlock), 0, st, (int64_t)s->n, out,
                            (const double *)s->ety);
     } else {
-        check_spmv<float, double>(st, err_kern_a(s), s->m, s->rp, s->ci, (const float *)s->aerr, vec, s->ex);
+        row_product<float, double>(s, (const float *)s->aerr, vec, s->ex);
         hipLaunchKernelGGL(k_add_to, dim3(grid_for(s->m, kBlock, 8192)), dim3(kBlock), 0, st, (int64_t)s->m, out,
                            (const double *)s->ex);
     }
@@ -189,8 +320,8 @@ hipError_t solver_product(pdhg_solver *s, bool transpose, const double *vec, dou
     } else if (s->kern_a == kSell) {
         sell_product(s, vec, out);
     } else {
-        if (s->fp32) check_spmv<float, double>(s->stream, s->kern_a, s->m, s->rp, s->ci, (const float *)s->ahat, vec, out);
-        else check_spmv<double, double>(s->stream, s->kern_a, s->m, s->rp, s->ci, (const double *)s->ahat, vec, out);
+        if (s->fp32) row_product<float, double>(s, (const float *)s->ahat, vec, out);
+        else row_product<double, double>(s, (const double *)s->ahat, vec, out);
     }
     return hipGetLastError();
 }
@@ -417,6 +548,13 @@ static void launch_dual(pdhg_solver *s, int i, int store, hipEvent_t e0 = nullpt
         sell_dual(s, i, store, e0, e1);
         return;
     }
+    if (L == kRowSegs) {
+        const RowSegs &sg = s->segs;
+        PDHG_LAUNCH(e0, e1, (k_dual_segs<V>), dim3(sg.blk0[sg.count]), dim3(kBlock), s->stream, sg, s->rp, s->ci,
+                    (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense, (double *)s->y,
+                    (const double *)s->ya, (double *)s->yp, s->st, i, store);
+        return;
+    }
     if (L == kRowBlock) {
         PDHG_LAUNCH(e0, e1, (k_dual_rowblock<V>), dim3(s->m), dim3(kBlock), s->stream, s->m, s->rp, s->ci,
                     (const V *)s->ahat, (const V *)s->xbar, (const double *)s->bhc, s->sense, (double *)s->y,
@@ -628,19 +766,15 @@ __global__ void k_advance(DevState *st, int len)
     st->k0 += len;
 }
 
-// kernel structure of the rounding-error products (the sliced layout holds
-// only the float matrix: its lane-group width then)
-static int err_kern_a(const pdhg_solver *s) { return s->kern_a == kSell ? s->lanes_a : s->kern_a; }
-
 template <typename V>
 static void check_impl(pdhg_solver *s, const double *xc, const double *yc, double *pm, double *pn)
 {
     hipStream_t st = s->stream;
     if (s->kern_a == kSell) sell_product(s, xc, s->ax);
-    else check_spmv<V, double>(st, s->kern_a, s->m, s->rp, s->ci, (const V *)s->ahat, xc, s->ax);
+    else row_product<V, double>(s, (const V *)s->ahat, xc, s->ax);
     check_spmv<V, double>(st, s->kern_at, s->n, s->tp, s->ti, (const V *)s->ahat_t, yc, s->aty);
     if (s->aerr) { // mixed mode: the float64 products are these plus E xc and E' yc
-        check_spmv<float, double>(st, err_kern_a(s), s->m, s->rp, s->ci, (const float *)s->aerr, xc, s->ex);
+        row_product<float, double>(s, (const float *)s->aerr, xc, s->ex);
         check_spmv<float, double>(st, s->kern_at, s->n, s->tp, s->ti, (const float *)s->aerr_t, yc, s->ety);
     }
     const int gm = s->red_blocks_m, gn = s->red_blocks_n;
@@ -731,8 +865,8 @@ hipError_t defect_refresh(pdhg_solver *s)
     const double *xa = (const double *)s->xa, *ya = (const double *)s->ya;
     // fl32(Ahat) x_a into bhc, E x_a into ex, E' y_a into ety
     if (s->kern_a == kSell) sell_product(s, xa, s->bhc);
-    else check_spmv<float, double>(st, s->kern_a, s->m, s->rp, s->ci, (const float *)s->ahat, xa, s->bhc);
-    check_spmv<float, double>(st, err_kern_a(s), s->m, s->rp, s->ci, (const float *)s->aerr, xa, s->ex);
+    else row_product<float, double>(s, (const float *)s->ahat, xa, s->bhc);
+    row_product<float, double>(s, (const float *)s->aerr, xa, s->ex);
     check_spmv<float, double>(st, s->kern_at, s->n, s->tp, s->ti, (const float *)s->aerr_t, ya, s->ety);
     const int g = grid_for((int64_t)s->n + s->m, kBlock, 8192);
     hipLaunchKernelGGL(k_defect_set, dim3(g), dim3(kBlock), 0, st, s->n, s->m, s->st, 1, s->ch,
@@ -1417,14 +1551,84 @@ hipError_t dual_push_finish(pdhg_solver *s)
 // ELLPACK layout, which stay available as explicit or autotuned choices).
 int choose_kernel(double mean_row, bool dual_half)
 {
-    (void)dual_half;
     if (mean_row <= 3.0) return -256; // 2-3 entries per row: 256-row tiles match or beat one lane per row
     if (mean_row <= 16.0) return -64; // measured best for 6 and 15 entries per row
     if (mean_row <= 48.0) return -32; // 24 entries per row
-    // long rows: a lane group per row; with four terms in flight per lane, 32
-    // lanes beat 64 on rows of thousands of entries
+    // long rows: a lane group per row; the dual half picks the width per
+    // segment of rows of one kind (plan_row_segments)
+    if (dual_half) return kRowSegs;
     const int l = lanes_for_mean(mean_row);
     return l > 32 ? 32 : l;
+}
+
+// Segments from the rows' column pattern: a row is contiguous when at least
+// half of its entries continue in the next column; runs of rows of one kind
+// (rows of fewer than two entries join the current run) become segments.
+// Each segment spreads over all 8 XCDs, so every XCD gets its share of each
+// kind of row.  Lane-group width per segment from its mean row length l: the
+// smallest power of two w >= l/4 (about one round of four loads per lane), at
+// most 32; spread-out rows take 16 once l >= 512, where sharing each gathered
+// line among more rows of a workgroup outweighs the extra rounds (sink rows of
+// 2,000 entries at stride 5,000: 16 lanes beat 8 and 32; sink rows of 90
+// entries: 32 beat 16).  More runs than kMaxSegs give one segment of 32.
+static RowSegs row_segments(const std::vector<int> &rp, const std::vector<int> &adj)
+{
+    const int m = (int)adj.size();
+    std::vector<int> start, cls;
+    for (int r = 0; r < m; r++) {
+        const int len = rp[r + 1] - rp[r];
+        int c = cls.empty() ? 0 : cls.back();
+        if (len >= 2) c = 2 * adj[r] >= len - 1 ? 1 : 0;
+        if (cls.empty() || c != cls.back()) {
+            start.push_back(r);
+            cls.push_back(c);
+        }
+    }
+    RowSegs sg;
+    if (m <= 0) return sg;
+    const bool one = (int)start.size() > kMaxSegs;
+    sg.count = one ? 1 : (int)start.size();
+    for (int k = 0; k < sg.count; k++) {
+        const int r0 = one ? 0 : start[k], r1 = one || k + 1 == sg.count ? m : start[k + 1];
+        const double mean = (double)(rp[r1] - rp[r0]) / (r1 - r0);
+        int w = 1;
+        while (w < 32 && 4 * w < mean) w <<= 1;
+        if (one) w = 32;
+        else if (cls[k] == 0 && mean >= 512.0) w = 16;
+        sg.row0[k] = r0;
+        sg.lanes[k] = w;
+        const int64_t blocks = ((int64_t)(r1 - r0) * w + kBlock - 1) / kBlock;
+        sg.blk0[k + 1] = sg.blk0[k] + (int)((blocks + 7) / 8 * 8);
+    }
+    sg.row0[sg.count] = m;
+    return sg;
+}
+
+hipError_t plan_row_segments(pdhg_solver *s)
+{
+    const int m = s->m;
+    s->segs = RowSegs{};
+    if (m <= 0) return hipSuccess;
+    std::vector<int> rp((size_t)m + 1), adj((size_t)m);
+    int *d_adj = nullptr;
+    hipError_t e = hipMalloc(&d_adj, sizeof(int) * (size_t)m);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_row_adjacent, dim3(grid_for((int64_t)m * 64, kBlock, 1 << 30)), dim3(kBlock), 0,
+                           s->stream, m, s->rp, s->ci, d_adj);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(adj.data(), d_adj, sizeof(int) * (size_t)m, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(rp.data(), s->rp, sizeof(int) * ((size_t)m + 1), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream); // the host vectors die on return
+    if (d_adj) (void)hipFree(d_adj);
+    if (e != hipSuccess) return e;
+    s->segs = row_segments(rp, adj);
+    if (s->p.verbosity > 0)
+        for (int k = 0; k < s->segs.count; k++)
+            fprintf(stderr, "[pdhg] dual row segment %d: rows %d..%d, %d lanes, %d workgroups\n", k, s->segs.row0[k],
+                    s->segs.row0[k + 1] - 1, s->segs.lanes[k], s->segs.blk0[k + 1] - s->segs.blk0[k]);
+    return hipSuccess;
 }
 
 // Time every candidate of each half on scratch output vectors (3 launches
@@ -1444,7 +1648,7 @@ hipError_t autotune(pdhg_solver *s)
     if (e == hipSuccess) e = hipMemcpyAsync(sx, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sxbar, s->x, vb * (size_t)s->n, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sy, s->y, sizeof(double) * (size_t)s->m, hipMemcpyDeviceToDevice, s->stream);
-    const int cands[] = {-32, -64, -128, -256, -1032, -1064, 1, 2, 4, 8, 16, 32, 64, kRowBlock, kSell};
+    const int cands[] = {-32, -64, -128, -256, -1032, -1064, 1, 2, 4, 8, 16, 32, 64, kRowBlock, kSell, kRowSegs};
     void *keep[5] = {s->x, s->xbar, s->xp, s->y, s->yp};
     s->x = sx;
     s->xbar = sxbar;
@@ -1456,6 +1660,7 @@ hipError_t autotune(pdhg_solver *s)
         int best_k = half == 0 ? s->kern_at : s->kern_a;
         for (int c : cands) {
             if (c == kSell && (half == 0 || !s->sell_idx)) continue; // dual half, layout built
+            if (c == kRowSegs && (half == 0 || s->segs.count == 0)) continue; // dual half, segments planned
             if (half == 0) s->kern_at = c;
             else s->kern_a = c;
             for (int rep = 0; rep < 4; rep++) {

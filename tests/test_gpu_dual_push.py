@@ -87,10 +87,10 @@ def test_dual_push_reaches_the_closed_form_vertex():
         assert pg.before.est_dual == 1 and pg.after.est_dual == 0 and pg.status == po.status
 
 
-@pytest.mark.parametrize("lanes_a", [-3032, -32, 4])
+@pytest.mark.parametrize("lanes_a", [-3032, -4000, -32, 4])
 def test_dual_push_on_every_dual_half_kernel(lanes_a):
     """The dropped rows ('N', y = 0) go through every dual-half kernel: sliced
-    ELLPACK, LDS tiles and lane groups give the oracle's push."""
+    ELLPACK, row segments, LDS tiles and lane groups give the oracle's push."""
     lp = lpgen.planted(300, 900, seed=2, zero_frac=0.85, degen_frac=0.0, ineq_frac=0.3, upper_frac=0.2)
     g = pdhg.Solver(lp, eps_rel=1e-8, max_iter=400000, lanes_a=lanes_a)
     o = OracleSolver(lp, eps_rel=1e-8, max_iter=400000)

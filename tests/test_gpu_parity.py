@@ -257,6 +257,87 @@ def test_sliced_ellpack_dual_follows_the_oracle(name, make):
         assert (pg.iters, pg.n_fix_lower, pg.n_fix_upper) == (po.iters, po.n_fix_lower, po.n_fix_upper)
 
 
+def _rows_permuted(lp, order):
+    """The same LP with its rows in the given order."""
+    order = np.asarray(order)
+    lens = np.diff(lp.row_ptr)[order]
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.concatenate([lp.col[lp.row_ptr[r]:lp.row_ptr[r + 1]] for r in order])
+    val = np.concatenate([lp.val[lp.row_ptr[r]:lp.row_ptr[r + 1]] for r in order])
+    return lpgen.LP(lp.m, lp.n, rp, col, val, lp.b[order], lp.c, lp.l, lp.u, lp.sense[order], name=lp.name + "_perm")
+
+
+def _alternating_transport():
+    """Source and sink rows interleaved in runs of 5: more runs of one kind
+    than the dual half has segments."""
+    lp = lpgen.transportation(30, 80, seed=2)
+    src, snk = list(range(30)), list(range(30, 110))
+    order = []
+    while src or snk:
+        order += src[:5] + snk[:5]
+        src, snk = src[5:], snk[5:]
+    return _rows_permuted(lp, order)
+
+
+def _seg_cases():
+    a = np.array([[1.0, 1.0, 0.0], [0.0, 0.0, 0.0]])
+    return [
+        # sources of 100 contiguous entries (32 lanes), sinks of 40 spread ones (16)
+        ("transport_40x100", lambda: lpgen.transportation(40, 100, seed=5)),
+        # sinks of 600 spread entries: past 512, 16 lanes; sources of 90 contiguous ones (32)
+        ("transport_600x90", lambda: lpgen.transportation(600, 90, seed=8)),
+        ("alternating_runs", _alternating_transport),
+        ("ragged_deg_1_9", lambda: lpgen.planted(333, 777, seed=4, deg_range=(1, 9))),
+        ("empty_row", lambda: lpgen.from_dense(a, [2.0, 0.0], [1.0, 2.0, -1.0], [0, 0, 0], [np.inf, np.inf, 4.0],
+                                                "==")),
+    ]
+
+
+@pytest.mark.parametrize("name,make", _seg_cases(), ids=[c[0] for c in _seg_cases()])
+def test_row_segment_dual_follows_the_oracle(name, make):
+    """The dual half on row segments (forced), each run of contiguous or
+    spread-out rows with its own lane-group width: first 50 iterates within
+    1e-10, then the oracle's solve and push, the push on the free columns
+    planning segments of its own rows."""
+    print(f"[gpu] row-segment dual: {name}", flush=True)
+    lp = make()
+    g = pdhg.Solver(lp, lanes_a=-4000, eps_rel=1e-8)
+    o = OracleSolver(lp, eps_rel=1e-8)
+    assert g.get_timing().lanes_a == -4000
+    for t in range(1, 51):
+        g.iterate(1)
+        o.iterate(1)
+        xg, yg = g.get_iterate()
+        xo, yo = o.iterate_state()
+        assert rel_inf(xg, xo) <= 1e-10 and rel_inf(yg, yo) <= 1e-10, t
+    rg, ro = g.solve(), o.solve()
+    assert rg.status == ro.status and rg.iters == ro.iters
+    assert abs(rg.pobj - ro.pobj) <= 1e-9 * max(1.0, abs(ro.pobj))
+    if rg.status == pdhg.PDHG_OPTIMAL:
+        pg, po = g.corner_push(7), o.corner_push(7)
+        assert (pg.iters, pg.n_fix_lower, pg.n_fix_upper) == (po.iters, po.n_fix_lower, po.n_fix_upper)
+        assert rel_inf(g.get_solution()[0], o.solution()[0]) <= 1e-8
+
+
+def test_row_segments_are_the_default_for_long_rows_and_one_segment_equals_its_lane_kernel():
+    """Rows of more than 48 entries get the row-segment dual by default.  With
+    more runs than segments the rows form one segment of 32 lanes, whose
+    iterates equal the 32-lane kernel's bit for bit."""
+    lp = lpgen.transportation(40, 100, seed=5)
+    assert pdhg.Solver(lp).get_timing().lanes_a == -4000
+    lp = _alternating_transport()
+    out = []
+    for la in (-4000, 32):
+        for graph in (0, 1):
+            g = pdhg.Solver(lp, lanes_a=la, use_graph=graph)
+            r = g.solve()
+            out.append((r.iters, g.get_iterate()))
+    for it, (x, y) in out[1:]:
+        assert it == out[0][0]
+        np.testing.assert_array_equal(x, out[0][1][0])
+        np.testing.assert_array_equal(y, out[0][1][1])
+
+
 @pytest.mark.parametrize("name,make,prec", [
     ("transport_60x150", lambda: lpgen.transportation(60, 150, seed=7), "fp64"),
     ("transport_60x150_fp32", lambda: lpgen.transportation(60, 150, seed=7), "fp32"),
