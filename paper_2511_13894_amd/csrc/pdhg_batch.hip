@@ -32,7 +32,7 @@ __global__ __launch_bounds__(NT) void kb_primal(const int4 *__restrict__ tiles, 
     __shared__ int s_ptr[T + 1];
     __shared__ double s_prod[kTileU * NT];
     __shared__ double s_sum[T];
-    const int4 tl = tiles[xcd_block(blockIdx.x, gridDim.x)];
+    const int4 tl = tiles[xcd_range_block(blockIdx.x, gridDim.x)];
     const DevState *st = sts + tl.x;
     if (st->done) return;
     const int r0 = tl.y, rows = tl.z;
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(NT) void kb_dual(const int4 *__restrict__ tiles, co
     __shared__ int s_ptr[T + 1];
     __shared__ double s_prod[kTileU * NT];
     __shared__ double s_sum[T];
-    const int4 tl = tiles[xcd_block(blockIdx.x, gridDim.x)];
+    const int4 tl = tiles[xcd_range_block(blockIdx.x, gridDim.x)];
     const DevState *st = sts + tl.x;
     if (st->done) return;
     const int r0 = tl.y, rows = tl.z;
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(NT) void kb_spmv(const int4 *__restrict__ tiles, co
     __shared__ int s_ptr[T + 1];
     __shared__ double s_prod[kTileU * NT];
     __shared__ double s_sum[T];
-    const int4 tl = tiles[xcd_block(blockIdx.x, gridDim.x)];
+    const int4 tl = tiles[xcd_range_block(blockIdx.x, gridDim.x)];
     if (sts ? sts[tl.x].done != 0 : skip[tl.x] != 0.0) return; // uniform over the workgroup
     tile_row_sums<VM, VV, T, NT>(tl.y, tl.z, ptr, idx, val, vec, s_ptr, s_prod, s_sum);
     if ((int)threadIdx.x < tl.z) out[tl.y + threadIdx.x] = s_sum[threadIdx.x];

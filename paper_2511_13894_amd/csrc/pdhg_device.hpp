@@ -63,11 +63,33 @@ __device__ __forceinline__ void block_reduce(double (&v)[NQ], unsigned is_max_ma
 // Workgroups are dispatched round-robin over the 8 XCDs (bid % 8).  Map them
 // so that every XCD works on one contiguous range of logical blocks: rows
 // that gather the same cache lines then meet in the same L2.
-__device__ __forceinline__ int xcd_block(int bid, int nblk)
+__device__ __forceinline__ int xcd_range_block(int bid, int nblk)
 {
     const int x = bid & 7, q = nblk >> 3, r = nblk & 7;
     const int base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
     return base + (bid >> 3);
+}
+
+// The mapping of a single LP's launches.  Up to kXcdChunkMin workgroups
+// (a launch whose workgroups are resident together) take the contiguous
+// ranges above.  A larger launch runs in many rounds, and with ranges each
+// XCD would own one region of the matrix: where the rows change kind along
+// the matrix (the node-balance, then the capacity rows of a multicommodity
+// LP) the XCDs get unequal work.  There chunks of kXcdChunk logical blocks
+// are dealt round-robin to the XCDs instead: neighbouring rows still share an
+// L2 within a chunk, and every region spreads over all 8 XCDs.  A tail of
+// fewer than 8 chunks keeps the dispatch order.  (The batch engine keeps the
+// ranges: one LP's tiles then stay in one L2.)
+constexpr int kXcdChunk = 16;
+constexpr int kXcdChunkMin = 8192;
+
+__device__ __forceinline__ int xcd_block(int bid, int nblk)
+{
+    if (nblk < kXcdChunkMin) return xcd_range_block(bid, nblk);
+    const int full = nblk / (8 * kXcdChunk) * (8 * kXcdChunk);
+    if (bid >= full) return bid;
+    const int x = bid & 7, k = bid >> 3;
+    return ((k / kXcdChunk) * 8 + x) * kXcdChunk + k % kXcdChunk;
 }
 
 // One lane's share of a row's product: the terms e = beg+lane, beg+lane+L, ...
