@@ -269,7 +269,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"],
-                    help="fp32: FP32-mixed (float matrix and n-vectors, float64 checks, defect correction); fp64")
+                    help="fp32: FP32-mixed (float matrix, n-vectors as float differences from float64 anchors, float64 checks); fp64")
     ap.add_argument("--learned", default=PREDICTOR,
                     help="predictor file for the learned-vs-plain comparison outside the timed region ('' skips it)")
     ap.add_argument("--seed", type=int, default=1)
