@@ -1545,10 +1545,12 @@ hipError_t dual_push_finish(pdhg_solver *s)
 // ------------------------------------------------------- kernel choice ---
 // From measured sweeps on the 100k x 400k, 7k x 10M and 800k x 3.2M LPs:
 // LDS tiles up to 48 entries per row (256-row tiles for 2-3 entries: 56 against
-// 63 us for one lane per row on the multicommodity primal), lane groups sized
-// to the mean beyond, at most 32 (on the dual half's 1,400 to
-// 2,800-entry rows 32 lanes beat 64, one workgroup per row and the sliced
-// ELLPACK layout, which stay available as explicit or autotuned choices).
+// 63 us for one lane per row on the multicommodity primal); beyond, lane
+// groups: for the primal half sized to the mean, at most 32; for the dual
+// half per row segment (on the 7k x 10M dual, row segments of 32 and 16
+// lanes beat one 32-lane group per row, 64 lanes, one workgroup per row and
+// the sliced ELLPACK layout, which stay available as explicit or autotuned
+// choices).
 int choose_kernel(double mean_row, bool dual_half)
 {
     if (mean_row <= 3.0) return -256; // 2-3 entries per row: 256-row tiles match or beat one lane per row
