@@ -116,6 +116,34 @@ def test_numeric_parameters_are_validated_without_gpu():
     assert lib.pdhg_batch_corner_push_logits(None, lg, 0.5, None, None) == -1
 
 
+def test_kernel_codes_are_validated_without_gpu():
+    """The dual-half-only kernel codes (sliced ELLPACK -3032, row segments
+    -4000) and anything outside the encoding are refused for the primal half,
+    and the batch (tiled kernels only) refuses both, before any device call."""
+    lib = pdhg.load()
+    h = ctypes.c_void_p()
+    rp = (ctypes.c_int64 * 2)(0, 1)
+    ci = (ctypes.c_int32 * 1)(0)
+    va = (ctypes.c_double * 1)(1.0)
+    b = (ctypes.c_double * 1)(1.0)
+    c = (ctypes.c_double * 2)(1.0, 1.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    for field, value in (("lanes_at", -4000), ("lanes_at", -3032), ("lanes_a", 3), ("lanes_a", -4001),
+                         ("lanes_at", 128)):
+        q = pdhg.default_params()
+        setattr(q, field, value)
+        rc = lib.pdhg_create(1, 2, 1, rp, ci, ctypes.cast(va, dp), ctypes.cast(b, dp), ctypes.cast(c, dp), None,
+                             None, None, ctypes.byref(q), ctypes.byref(h))
+        assert rc == -1 and b"lanes" in lib.pdhg_last_error(), (field, value)
+    descs = (pdhg.LpDesc * 1)()
+    descs[0].m, descs[0].n, descs[0].nnz = 2, 3, 4
+    for value in (-4000, -3032):
+        q = pdhg.default_params()
+        q.lanes_a = value
+        assert lib.pdhg_batch_create_device(1, descs, ctypes.byref(q), ctypes.byref(h)) == -1
+        assert b"tiled kernels only" in lib.pdhg_last_error(), value
+
+
 def test_batch_create_device_argument_errors_without_gpu():
     """pdhg_batch_create_device refuses bad counts, NULL arrays, lane
     choices outside the tiled kernels and invalid parameters before it
