@@ -53,7 +53,11 @@ __device__ __forceinline__ void primal_update(int64_t j, double g, double xj, do
     xn = xn < lo ? lo : xn;
     xn = xn > hi ? hi : xn;
     const double xb = 2.0 * xn - xj;
-    xbar[j] = (V)(delta ? xb - aj : xb);
+    // x and xbar go out as non-temporal stores: only the next launch reads
+    // them (the dual half xbar, the next primal half x), from beyond this
+    // XCD's L2 in any case, and lines left dirty in the L2 are written back
+    // before the launch can end (c2 push: 5.8 -> 5.4 us per launch)
+    __builtin_nontemporal_store((V)(delta ? xb - aj : xb), &xbar[j]);
     if (store_cand) xp[j] = xn;
     double xnew = xn;
     if (st->halpern) {
@@ -61,7 +65,7 @@ __device__ __forceinline__ void primal_update(int64_t j, double g, double xj, do
         halpern_weights(st, i, w, wa, gm);
         xnew = w * ((1.0 + gm) * xn - gm * xj) + wa * aj;
     }
-    x[j] = (V)(delta ? xnew - aj : xnew);
+    __builtin_nontemporal_store((V)(delta ? xnew - aj : xnew), &x[j]);
 }
 
 // set the iterate of column j to v (mixed mode: as the anchor, difference 0;
