@@ -1,9 +1,10 @@
 """Parity at full size, in the launch configuration the benchmark uses (default
 parameters: kernels chosen from the mean row length, graph-replayed cycles,
-event timing on).  The oracle cannot finish these solves, so the checks are
-on what it can compute at any size: the setup (scaling, step size), the first
-iterates, the float64 KKT of the GPU's answer evaluated by the oracle's own
-code, and the push's fixing decisions recounted from that answer."""
+event timing on).  Checked at any size: the setup (scaling, step size), the
+first iterates, the float64 KKT of the GPU's answer evaluated by the oracle's
+own code, and the push's fixing decisions recounted from that answer.  The
+oracle's own full runs of c1, c2 and c5, made once by the scripts under
+tests/golden/, pin the iteration, restart, fix and corner counts."""
 import json
 import os
 
@@ -178,6 +179,41 @@ def test_c2_setup_iterates_and_solve(c2):
     assert r.status == pdhg.PDHG_OPTIMAL
     assert max(k.rel_p, k.rel_d, k.rel_gap) <= 1e-6
     assert abs(r.pobj - k.pobj) <= 1e-12 * max(1.0, abs(k.pobj))
+
+
+def test_c2_solve_and_push_against_the_oracle_full_run(c2):
+    """The default workload's path in float64: the GPU's solve and corner push
+    (the push on its free columns) against the oracle's own full run on the
+    full push model (tests/golden/make_c2_oracle.py): iteration and restart
+    counts, fixes, the corner counts after the push; the fixing decisions
+    recounted from the GPU's answer and the pushed point's corner counts
+    evaluated by the oracle's code."""
+    lp, o = c2
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_oracle.json")))
+    gs, gp = gold["solve"], gold["push"]
+    g = pdhg.Solver(lp, timing=1)
+    r = g.solve()
+    x, y, z = g.get_solution()
+    assert r.status == pdhg.PDHG_OPTIMAL == gs["status"]
+    assert r.iters == gs["iters"] and r.restarts == gs["restarts"]
+    assert abs(r.pobj - gs["pobj"]) <= 1e-9 * abs(gs["pobj"])
+    zr = _z_of(lp, y)
+    np.testing.assert_allclose(z, zr, rtol=0, atol=1e-12 * max(1.0, np.abs(zr).max()))
+    p = g.corner_push(1)
+    xp, yp, _ = g.get_solution()
+    ka = o.kkt(xp, yp)
+    print(f"[full] c2 vs the oracle's full run: solve {r.iters}/{gs['iters']} iterations, push {p.iters}/{gp['iters']}, "
+          f"fixes {p.n_fix_lower + p.n_fix_upper}/{gp['n_fix_lower'] + gp['n_fix_upper']}, off-bound after "
+          f"{p.after.p_off}/{gp['p_off_after']} (oracle's evaluation of the GPU's point {ka.p_off})", flush=True)
+    assert p.n_fix_upper == int(np.sum(zr > 1e-6)) and p.n_fix_lower == int(np.sum(zr < -1e-6))
+    assert (p.after.p_off, p.after.candidates, p.after.est_primal) == (ka.p_off, ka.candidates, ka.est_primal)
+    assert (p.n_fix_lower, p.n_fix_upper, p.n_rows_to_eq) == (gp["n_fix_lower"], gp["n_fix_upper"], gp["n_rows_to_eq"])
+    assert (p.before.p_off, p.before.candidates, p.before.est_primal) == \
+        (gp["p_off_before"], gp["candidates_before"], gp["est_primal_before"])
+    assert p.status == gp["status"] and p.iters == gp["iters"]
+    assert (p.after.p_off, p.after.candidates, p.after.est_primal) == \
+        (gp["p_off_after"], gp["candidates_after"], gp["est_primal_after"])
+    assert abs(p.after.pobj - gp["pobj_after"]) <= 1e-9 * abs(gp["pobj_after"])
 
 
 def test_batch_of_256_every_answer_checked_by_the_oracle():
