@@ -233,10 +233,11 @@ def test_batch_of_256_every_answer_checked_by_the_oracle():
 
 def test_c1_fp32_mixed_reaches_the_original_optimum(c1):
     """FP32-mixed at full size, as the benchmark runs it: the float32-rounded
-    c1 matrix has no optimum, and the defect-corrected iteration still ends
-    at the float64 tolerance of the original model (the oracle's own KKT of
-    the answer), in the float64 path's iteration count, and the push stops
-    with the oracle's primal residual of the pushed point at the tolerance."""
+    c1 matrix has no optimum, and the iteration on float differences from its
+    float64 anchors still ends at the float64 tolerance of the original model
+    (the oracle's own KKT of the answer), in the float64 path's iteration
+    count, and the push stops with the oracle's primal residual of the pushed
+    point at the tolerance."""
     lp, o = c1
     g = pdhg.Solver(pdhg.DeviceLP(lp), precision="fp32", timing=1)
     r = g.solve()
@@ -257,6 +258,42 @@ def test_c1_fp32_mixed_reaches_the_original_optimum(c1):
           f"pushed x {kh.rel_p:.2e}; primal push estimate {p.before.est_primal} -> {p.after.est_primal}", flush=True)
     assert p.status == pdhg.PDHG_PUSH_DONE and kh.rel_p <= 1e-6
     assert (p.after.p_off, p.after.est_primal) == (kh.p_off, kh.est_primal)
+
+
+def test_c2_fp32_mixed_against_the_oracle_full_run(c2):
+    """The benchmark's default run itself (FP32-mixed, the LP in HBM, the push
+    on its free columns) against the oracle's float64 full run: the answer
+    meets the tolerance of the original model as the oracle evaluates it, the
+    fixes are those the answer's float64 reduced costs call for, and the
+    solve, the push and the corner they reach stay within a restart check of
+    the oracle's (a float32 run may take another rounding path)."""
+    lp, o = c2
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_oracle.json")))
+    gs, gp = gold["solve"], gold["push"]
+    g = pdhg.Solver(pdhg.DeviceLP(lp), precision="fp32", timing=1)
+    r = g.solve()
+    x, y, _ = g.get_solution()
+    k = o.kkt(x, y)
+    obj_err = abs(k.pobj - gs["pobj"]) / (1 + abs(gs["pobj"]))
+    print(f"[full] c2 fp32: {pdhg.STATUS[r.status]} in {r.iters} iterations (oracle {gs['iters']}); oracle's KKT "
+          f"{k.rel_p:.2e}/{k.rel_d:.2e}/{k.rel_gap:.2e}; objective error {obj_err:.2e}", flush=True)
+    assert r.status == pdhg.PDHG_OPTIMAL
+    assert max(k.rel_p, k.rel_d, k.rel_gap) <= 1e-6
+    assert obj_err <= 2e-6  # both answers meet the relative gap test at 1e-6
+    assert r.iters <= 1.25 * gs["iters"] + 128
+    zr = _z_of(lp, y)
+    p = g.corner_push(1)
+    xh = g.get_solution()[0]
+    kh = o.kkt(xh, y)
+    print(f"[full] c2 fp32 push: {pdhg.STATUS[p.status]} in {p.iters} iterations (oracle {gp['iters']}); oracle's "
+          f"primal residual of the pushed x {kh.rel_p:.2e}; off-bound {p.after.p_off} (oracle's run "
+          f"{gp['p_off_after']}), primal push estimate {p.after.est_primal} (oracle's run {gp['est_primal_after']})",
+          flush=True)
+    assert p.n_fix_upper == int(np.sum(zr > 1e-6)) and p.n_fix_lower == int(np.sum(zr < -1e-6))
+    assert p.status == pdhg.PDHG_PUSH_DONE and kh.rel_p <= 1e-6
+    assert (p.after.p_off, p.after.candidates, p.after.est_primal) == (kh.p_off, kh.candidates, kh.est_primal)
+    assert p.iters <= 1.25 * gp["iters"] + 128
+    assert p.after.est_primal <= 1.25 * gp["est_primal_after"] + 128
 
 
 def test_batch_of_256_fp32_all_optimal():
