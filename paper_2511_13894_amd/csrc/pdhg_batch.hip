@@ -625,7 +625,7 @@ static hipError_t phase_begin_b(pdhg_batch *b, bool fresh)
     return hipGetLastError();
 }
 
-// mixed mode: every LP's corrected data at its current anchor
+// mixed mode: every LP's anchored data at its current anchor
 hipError_t batch_defect_refresh(pdhg_batch *b)
 {
     pdhg_solver *s = b->s;

@@ -117,7 +117,7 @@ int run_phase(pdhg_solver *s, int64_t iters, int mode, double t0)
     const int depth = 4; // cycles enqueued before the host looks at the state
     bool time_out = false;
     if (s->st_host->done) return s->st_host->status;
-    if (s->defect_stale) HIPCHK(defect_refresh(s)); // corrected data at the phase's anchor (mixed mode)
+    if (s->defect_stale) HIPCHK(defect_refresh(s)); // anchored data at the phase's anchor (mixed mode)
     while (s->t_host < target) {
         int enq = 0;
         bool any_check = false;
@@ -237,7 +237,7 @@ bool run_batch_phase(pdhg_batch *b, int64_t iters, int mode, double t0)
         }
     };
     HIPCHK(batch_compact_tiles(b, true));
-    if (s->defect_stale) HIPCHK(batch_defect_refresh(b)); // corrected data at every LP's anchor (mixed mode)
+    if (s->defect_stale) HIPCHK(batch_defect_refresh(b)); // anchored data at every LP's anchor (mixed mode)
     while (b->t_host < target) {
         int enq = 0;
         bool events = false;
@@ -538,7 +538,7 @@ static int build_solver(int m, int n, int nz, const pdhg_params &p, const ModelS
         HIPCHK(build_transpose(s));
         HIPCHK(detect_uniform_columns(s));
         HIPCHK(scale_problem(s));
-        if (s->aerr) { // until the first anchor's correction: the uncorrected data
+        if (s->aerr) { // until the first anchor: the data themselves (anchor 0)
             if (n > 0) HIPCHK(hipMemcpyAsync(s->chc, s->ch, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
             if (m > 0) HIPCHK(hipMemcpyAsync(s->bhc, s->bh, sizeof(double) * M, hipMemcpyDeviceToDevice, st));
         }

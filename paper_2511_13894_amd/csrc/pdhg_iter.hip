@@ -82,8 +82,8 @@ __global__ __launch_bounds__(kBlock) void k_dual(int m, const int *__restrict__ 
 // cache line per entry, and the next rows gather the same lines: narrower
 // groups put more such rows in a workgroup, whose shared L1 then serves them.
 // Each segment has its own workgroups in one launch; a workgroup finds its
-// segment from its index (a uniform branch) and maps itself onto the
-// segment's XCD ranges.
+// segment from its index (a uniform branch) and maps itself onto the XCDs
+// as a launch of the segment alone would.
 __device__ __forceinline__ int seg_of(const RowSegs &sg, int b)
 {
     int k = 0;

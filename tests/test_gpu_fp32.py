@@ -115,7 +115,7 @@ def test_fp32_status_is_backed_by_float64_kkt(i):
 
 
 def test_fp32_batch_solves_every_lp():
-    """The batch engine in the mixed mode (per-LP defect correction): every
+    """The batch engine in the mixed mode (per-LP anchored data): every
     LP optimal at the float64 tolerance, each confirmed by the oracle, and
     every push stopped primal feasible."""
     lps = [lpgen.config3_instance(i, base_seed=48000, m_range=(100, 3000)) for i in range(8)]
